@@ -1,0 +1,186 @@
+/*
+ * gsc.h -- C ABI of the MI355X (gfx950) Gaussian-splat colorization library.
+ *
+ * The library maps 2D images (colours, features, masks) back onto a fixed
+ * scene of 3D Gaussian splats as described in "Instant Colorization of
+ * Gaussian Splats" (arXiv 2604.17155): every view is tile-rasterised front to
+ * back to obtain each Gaussian's blending weight w = alpha*T per pixel (the
+ * pixel visibility of eq. 4); per Gaussian the weighted normal equations
+ *   A_g = sum_{j,p} w phi_gj phi_gj^T,  B_g = sum_{j,p} w phi_gj y_p^T,
+ *   w_g = sum_{j,p} w                                         (eqs. 10-13)
+ * are accumulated, where phi_gj are the real spherical harmonics of the view
+ * direction camera -> Gaussian (eq. 3, eq. 9), and the Tikhonov-regularised
+ * systems (A_g + w_g Lambda) c_g = B_g (eq. 14, Algorithm 1 steps 1-6) are
+ * solved for the SH coefficients c_g.
+ *
+ * Conventions
+ *   - Every array argument is a DEVICE pointer owned by the caller unless it
+ *     is marked "host".  The library never frees or retains caller memory.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream).
+ *     Calls that size their scratch from data (colorize, render and their
+ *     adjoints) read one 4-byte count back from the device and therefore
+ *     synchronise `stream` once per call.
+ *   - Return value: GSC_OK or a negative gsc_status.  On failure
+ *     gsc_last_error() returns a message for the calling thread.  Invalid
+ *     arguments are rejected before any device work is enqueued.
+ *   - A gsc_ctx owns reusable device scratch and is not thread-safe; use one
+ *     context per host thread.  Calls on one context must not overlap.
+ *
+ * Geometry and pixel conventions
+ *   - Cameras: world -> camera x_cam = R x + t, R row-major, OpenCV axes
+ *     (x right, y down, z forward).  Pinhole projection
+ *     u = fx*x/z + cx, v = fy*y/z + cy; the centre of pixel (x, y) is at
+ *     (x + 0.5, y + 0.5).
+ *   - Gaussians: means [N,3]; scales [N,3] are linear standard deviations;
+ *     quats [N,4] are (w, x, y, z), normalised inside; opacities [N] in (0,1)
+ *     are already activated.  Sigma = R(q) diag(scale^2) R(q)^T.
+ *   - Projection: EWA splatting Sigma_2D = J R Sigma R^T J^T + dilation*I.
+ *   - Depth order: key = camera-space z of the mean computed in binary32 as
+ *     fmaf(R[6],mx, fmaf(R[7],my, fmaf(R[8],mz, t[2]))); ascending, ties by
+ *     lower Gaussian index.  key <= znear culls the Gaussian in that view.
+ *   - Per pixel, front to back: q = d^T Sigma_2D^{-1} d with d = pixel centre
+ *     minus projected mean; candidates need q <= sigma_cut^2;
+ *     alpha = min(alpha_max, o*exp(-q/2)); alpha < alpha_min is skipped;
+ *     if T*(1-alpha) < t_min the pixel stops (that Gaussian is not used);
+ *     otherwise w = alpha*T and T <- T*(1-alpha).  Background is zero.
+ *   - SH basis: real orthonormal spherical harmonics, flat index l*l+l+m,
+ *     Y_{l,0} = K P_l, Y_{l,m>0} = sqrt2 K P_l^m cos(m phi),
+ *     Y_{l,m<0} = sqrt2 K P_l^|m| sin(|m| phi) (no Condon-Shortley phase),
+ *     evaluated at the unit direction from the camera centre -R^T t to the
+ *     Gaussian mean.  Y_0 = 1/sqrt(4 pi).
+ *   - targets / images: [sum_j H_j W_j, C] row-major, channel-last; camera
+ *     j's pixel (x, y) is row cams[j].pixel_offset + y*W_j + x.
+ *   - coeffs: [N, (L+1)^2, C] float32.
+ *   - lambda (host): n_lambda = 1 (one value), L+1 (one per band) or
+ *     (L+1)^2 (one per coefficient); all >= 0.
+ */
+#ifndef GSC_H
+#define GSC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gsc_ctx gsc_ctx;
+typedef void* gsc_stream_t; /* hipStream_t */
+
+typedef enum {
+    GSC_OK = 0,
+    GSC_ERR_INVALID_ARG = -1,
+    GSC_ERR_HIP = -2,
+    GSC_ERR_CAPACITY = -3,
+    GSC_ERR_UNSUPPORTED = -4
+} gsc_status;
+
+typedef enum { GSC_F32 = 0, GSC_BF16 = 1 } gsc_dtype;
+
+/* Per-Gaussian status bits written by gsc_colorize. */
+enum {
+    GSC_G_UNOBSERVED = 1, /* w_g = 0: coefficients set to zero */
+    GSC_G_ILL_COND = 2,   /* Cholesky-diagonal estimate of kappa exceeded kappa_max */
+    GSC_G_FAILED = 4      /* factorisation failed (not positive definite); coefficients zero */
+};
+
+/* Option flags. */
+enum {
+    GSC_FLAG_VALIDATE_ONLY = 1, /* check the arguments and return; enqueue nothing */
+    GSC_FLAG_PROFILE = 2        /* time each pipeline stage with events on the call's stream */
+};
+
+/* Pipeline stages timed under GSC_FLAG_PROFILE (indices of gsc_stats.stage_ms). */
+enum {
+    GSC_STAGE_PROJECT = 0,    /* covariance, projection, footprint, depth key */
+    GSC_STAGE_DEPTH_SORT = 1, /* stable radix sort of (view, Gaussian) items by depth */
+    GSC_STAGE_SCAN = 2,       /* tile counts in depth order and their exclusive scan */
+    GSC_STAGE_EMIT = 3,       /* (tile, item) pair emission */
+    GSC_STAGE_TILE_SORT = 4,  /* stable radix sort of pairs by tile, tile ranges */
+    GSC_STAGE_BLEND = 5,      /* fused blend + accumulate (colorize) or blend + render */
+    GSC_STAGE_SOLVE = 6,      /* fold into normal equations + Cholesky solve */
+    GSC_N_STAGES = 8
+};
+
+typedef struct {
+    float R[9];
+    float t[3];
+    float fx, fy, cx, cy;
+    int32_t width, height;
+    int64_t pixel_offset; /* first target row of this camera */
+} gsc_camera;
+
+typedef struct {
+    float alpha_min; /* 1/255 */
+    float alpha_max; /* 0.99 */
+    float t_min;     /* 1e-4; 0 disables the early stop */
+    float sigma_cut; /* 3 */
+    float dilation;  /* 0.3 px^2 */
+    float znear;     /* 0.01 */
+    float kappa_max; /* 1e6: threshold for the GSC_G_ILL_COND bit */
+    int32_t flags;
+} gsc_options;
+
+typedef struct {
+    uint64_t contributions; /* accepted (Gaussian, view, pixel) triples of the last call */
+    uint64_t pairs;         /* (tile, Gaussian) list entries of the last call */
+    uint64_t items;         /* (view, Gaussian) projections of the last call */
+    uint32_t view_batches;  /* view batches the last call was split into */
+    uint32_t ill_conditioned; /* Gaussians flagged GSC_G_ILL_COND by the last colorize */
+    /* GSC_FLAG_PROFILE: device time and kernel launches per stage, summed over
+     * every call since the previous gsc_get_stats (up to 8192 stage records). */
+    float stage_ms[GSC_N_STAGES];
+    uint32_t stage_launches[GSC_N_STAGES];
+} gsc_stats;
+
+/* Fill `out` (host) with the default options listed above. */
+gsc_status gsc_default_options(gsc_options* out);
+
+/* Create a context.  `opt` (host) may be NULL for the defaults.  No device
+ * work happens here; device scratch is allocated on first use. */
+gsc_status gsc_ctx_create(gsc_ctx** ctx, const gsc_options* opt);
+void gsc_ctx_destroy(gsc_ctx* ctx);
+
+/* Replace the context's options (host pointer). */
+gsc_status gsc_ctx_set_options(gsc_ctx* ctx, const gsc_options* opt);
+
+/*
+ * Colorize (Algorithm 1, steps 1-6; eqs. 2-14).
+ *   means, scales, quats, opacities: device float32 arrays described above.
+ *   cams: host array of n_cams cameras (n_cams >= 0).
+ *   targets: device [rows, C], float32 (tdtype GSC_F32) or bfloat16
+ *            (GSC_BF16), rows >= max_j(pixel_offset_j + H_j W_j).
+ *   C: 1..64 channels.  sh_deg: 0..3.
+ *   lambda: host, n_lambda values (see above).
+ *   coeffs: device output [N, (L+1)^2, C] float32, fully overwritten.
+ *   status: device output [N] uint8 (GSC_G_* bits) or NULL.
+ * Unobserved Gaussians (w_g = 0) get zero coefficients.
+ */
+gsc_status gsc_colorize(gsc_ctx* ctx, const float* means, const float* scales, const float* quats,
+                        const float* opacities, int64_t N, const gsc_camera* cams, int32_t n_cams,
+                        const void* targets, int32_t tdtype, int32_t C, int32_t sh_deg,
+                        const float* lambda, int32_t n_lambda, float* coeffs, uint8_t* status,
+                        gsc_stream_t stream);
+
+/*
+ * Render (eqs. 1-3): images[p] = sum_g w_gp * c_g^T phi_gj over the same
+ * front-to-back blend, background zero.
+ *   coeffs: device [N, (L+1)^2, C] float32; images: device output
+ *   [sum_j H_j W_j, C] float32 (rows of every camera overwritten).
+ */
+gsc_status gsc_render(gsc_ctx* ctx, const float* means, const float* scales, const float* quats,
+                      const float* opacities, int64_t N, const gsc_camera* cams, int32_t n_cams,
+                      const float* coeffs, int32_t C, int32_t sh_deg, float* images,
+                      gsc_stream_t stream);
+
+/* Statistics of the last call on `ctx` (host output).  Synchronises with the
+ * device work of that call. */
+gsc_status gsc_get_stats(gsc_ctx* ctx, gsc_stats* out);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* gsc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSC_H */

@@ -1,0 +1,565 @@
+// C ABI: argument validation, context and scratch management, and the
+// per-call pipeline  project -> depth sort -> scan -> emit -> tile sort ->
+// tile ranges -> accumulate (per view batch) -> fold + solve.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "gsc_internal.h"
+
+using namespace gsc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+gsc_status fail(gsc_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define GSC_HIP(call)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(GSC_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));       \
+    } while (0)
+
+#define GSC_LAUNCHED(what)                                                                  \
+    do {                                                                                    \
+        hipError_t e_ = hipGetLastError();                                                  \
+        if (e_ != hipSuccess)                                                               \
+            return fail(GSC_ERR_HIP, "%s launch failed: %s", what, hipGetErrorString(e_)); \
+    } while (0)
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t bytes) {
+        if (bytes <= cap && p) return hipSuccess;
+        if (p) {
+            hipError_t e = hipFree(p);
+            if (e != hipSuccess) return e;
+            p = nullptr;
+            cap = 0;
+        }
+        size_t want = std::max<size_t>(bytes + bytes / 8, 4096);
+        hipError_t e = hipMalloc(&p, want);
+        if (e == hipSuccess) cap = want;
+        return e;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    template <typename T>
+    T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+// Upper bound on (view, Gaussian) items per batch.
+constexpr uint64_t kMaxItemsPerBatch = 1ull << 26;
+// Upper bound on (tile, item) pairs per batch (uint32 offsets).
+constexpr uint64_t kMaxPairsPerBatch = 1ull << 31;
+
+}  // namespace
+
+struct gsc_ctx {
+    gsc_options opt;
+    // device scratch
+    DevBuf views, views_all, cov, keys, vals, keys_alt, vals_alt, counts, counts_sorted, offsets, rec0, rec1,
+        rects, sort_scratch, pkeys, pvals, pkeys_alt, pvals_alt, ranges, vs, gamma, misc;
+    // host staging
+    ViewInfo* h_views = nullptr;  // staging of one batch's table
+    size_t h_views_cap = 0;
+    ViewInfo* h_all = nullptr;    // staging of the full camera table
+    size_t h_all_cap = 0;
+    uint32_t* h_total = nullptr;
+    gsc_stats stats;
+    bool stats_pending = false;
+    // GSC_FLAG_PROFILE: event pairs recorded during the last call
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    struct Mark { int stage; hipEvent_t a, b; uint32_t launches; };
+    std::vector<Mark> marks;
+    ~gsc_ctx() {
+        DevBuf* all[] = {&views, &views_all, &cov, &keys, &vals, &keys_alt, &vals_alt, &counts, &counts_sorted,
+                         &offsets, &rec0, &rec1, &rects, &sort_scratch, &pkeys, &pvals, &pkeys_alt,
+                         &pvals_alt, &ranges, &vs, &gamma, &misc};
+        for (DevBuf* b : all) b->release();
+        if (h_views) (void)hipHostFree(h_views);
+        if (h_all) (void)hipHostFree(h_all);
+        if (h_total) (void)hipHostFree(h_total);
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+constexpr size_t kMaxEvents = 1 << 14;
+// Records an event pair around a stage when profiling is on.  Pairs pile up
+// until gsc_get_stats() sums them.
+struct StageTimer {
+    gsc_ctx* ctx;
+    hipStream_t s;
+    int stage;
+    uint32_t launches;
+    hipEvent_t a = nullptr;
+    StageTimer(gsc_ctx* c, hipStream_t st, int stg, uint32_t n = 1) : ctx(c), s(st), stage(stg), launches(n) {
+        if (!(ctx->opt.flags & GSC_FLAG_PROFILE)) return;
+        a = take();
+        if (a) (void)hipEventRecord(a, s);
+    }
+    hipEvent_t take() {
+        if (ctx->ev_used >= kMaxEvents) return nullptr;  // stats not drained: stop recording
+        if (ctx->ev_used == ctx->ev_pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            ctx->ev_pool.push_back(e);
+        }
+        return ctx->ev_pool[ctx->ev_used++];
+    }
+    ~StageTimer() {
+        if (!a) return;
+        hipEvent_t b = take();
+        if (!b) return;
+        (void)hipEventRecord(b, s);
+        ctx->marks.push_back({stage, a, b, launches});
+    }
+};
+}  // namespace
+
+// misc buffer layout (device): [0] u64 contributions, [8] u32 pair total, [12] u32 ill count,
+// [16] u64 pair total (overflow check)
+namespace {
+constexpr size_t kMiscBytes = 64;
+// bin_views result asking the caller to retry with fewer views per batch
+constexpr gsc_status kSplit = (gsc_status)1;
+
+gsc_status validate_options(const gsc_options* o) {
+    if (!(o->alpha_min >= 0.0f && o->alpha_min < 1.0f)) return fail(GSC_ERR_INVALID_ARG, "alpha_min must be in [0,1)");
+    if (!(o->alpha_max > 0.0f && o->alpha_max < 1.0f)) return fail(GSC_ERR_INVALID_ARG, "alpha_max must be in (0,1)");
+    if (!(o->t_min >= 0.0f && o->t_min < 1.0f)) return fail(GSC_ERR_INVALID_ARG, "t_min must be in [0,1)");
+    if (!(o->sigma_cut > 0.0f && o->sigma_cut < 16.0f)) return fail(GSC_ERR_INVALID_ARG, "sigma_cut must be in (0,16)");
+    if (!(o->dilation >= 0.0f)) return fail(GSC_ERR_INVALID_ARG, "dilation must be >= 0");
+    if (!(o->znear > 0.0f)) return fail(GSC_ERR_INVALID_ARG, "znear must be > 0");
+    if (!(o->kappa_max > 0.0f)) return fail(GSC_ERR_INVALID_ARG, "kappa_max must be > 0");
+    return GSC_OK;
+}
+
+gsc_status validate_geometry(const float* means, const float* scales, const float* quats,
+                             const float* opac, int64_t N, const gsc_camera* cams, int32_t n_cams,
+                             int64_t* rows_needed) {
+    if (N < 0) return fail(GSC_ERR_INVALID_ARG, "N must be >= 0 (got %lld)", (long long)N);
+    if (N > (int64_t)0x7fffffff) return fail(GSC_ERR_INVALID_ARG, "N must be < 2^31");
+    if (N > 0 && (!means || !scales || !quats || !opac))
+        return fail(GSC_ERR_INVALID_ARG, "null Gaussian array with N > 0");
+    if (n_cams < 0) return fail(GSC_ERR_INVALID_ARG, "n_cams must be >= 0");
+    if (n_cams > 0 && !cams) return fail(GSC_ERR_INVALID_ARG, "cams is null with n_cams > 0");
+    int64_t rows = 0;
+    for (int j = 0; j < n_cams; ++j) {
+        const gsc_camera& c = cams[j];
+        if (c.width <= 0 || c.height <= 0 || c.width > 32768 || c.height > 32768)
+            return fail(GSC_ERR_INVALID_ARG, "camera %d: size %dx%d out of range", j, c.width, c.height);
+        if (c.pixel_offset < 0) return fail(GSC_ERR_INVALID_ARG, "camera %d: negative pixel_offset", j);
+        if (!(c.fx > 0.0f && c.fy > 0.0f) || !isfinite(c.cx) || !isfinite(c.cy))
+            return fail(GSC_ERR_INVALID_ARG, "camera %d: bad intrinsics", j);
+        for (int k = 0; k < 9; ++k)
+            if (!isfinite(c.R[k])) return fail(GSC_ERR_INVALID_ARG, "camera %d: non-finite R", j);
+        for (int k = 0; k < 3; ++k)
+            if (!isfinite(c.t[k])) return fail(GSC_ERR_INVALID_ARG, "camera %d: non-finite t", j);
+        rows = std::max<int64_t>(rows, c.pixel_offset + (int64_t)c.width * c.height);
+    }
+    *rows_needed = rows;
+    return GSC_OK;
+}
+
+gsc_status validate_channels(int32_t C, int32_t sh_deg) {
+    if (C < 1 || C > kMaxC) return fail(GSC_ERR_INVALID_ARG, "C must be in [1,64] (got %d)", C);
+    if (sh_deg < 0 || sh_deg > 3) return fail(GSC_ERR_INVALID_ARG, "sh_deg must be in [0,3] (got %d)", sh_deg);
+    return GSC_OK;
+}
+
+gsc_status expand_lambda(const float* lambda, int32_t n_lambda, int sh_deg, double* out) {
+    int nb = (sh_deg + 1) * (sh_deg + 1);
+    if (!lambda) return fail(GSC_ERR_INVALID_ARG, "lambda is null");
+    if (!(n_lambda == 1 || n_lambda == sh_deg + 1 || n_lambda == nb))
+        return fail(GSC_ERR_INVALID_ARG, "n_lambda must be 1, L+1 or (L+1)^2 (got %d)", n_lambda);
+    for (int i = 0; i < n_lambda; ++i)
+        if (!(lambda[i] >= 0.0f) || !isfinite(lambda[i]))
+            return fail(GSC_ERR_INVALID_ARG, "lambda[%d] must be finite and >= 0", i);
+    for (int l = 0; l <= sh_deg; ++l)
+        for (int m = -l; m <= l; ++m) {
+            int i = l * l + l + m;
+            out[i] = n_lambda == 1 ? lambda[0] : (n_lambda == sh_deg + 1 ? lambda[l] : lambda[i]);
+        }
+    return GSC_OK;
+}
+
+BlendParams blend_params(const gsc_options& o) {
+    BlendParams bp;
+    bp.alpha_min = o.alpha_min;
+    bp.alpha_max = o.alpha_max;
+    bp.t_min = o.t_min;
+    bp.cut2 = o.sigma_cut * o.sigma_cut;
+    bp.dilation = o.dilation;
+    bp.znear = o.znear;
+    return bp;
+}
+
+ViewInfo make_view(const gsc_camera& c) {
+    ViewInfo v;
+    memset(&v, 0, sizeof(v));
+    memcpy(v.R, c.R, sizeof(v.R));
+    memcpy(v.t, c.t, sizeof(v.t));
+    v.fx = c.fx; v.fy = c.fy; v.cx = c.cx; v.cy = c.cy;
+    for (int i = 0; i < 3; ++i)
+        v.centre[i] = -((double)c.R[i] * c.t[0] + (double)c.R[3 + i] * c.t[1] + (double)c.R[6 + i] * c.t[2]);
+    v.width = c.width;
+    v.height = c.height;
+    v.tiles_x = (c.width + kTile - 1) / kTile;
+    v.tiles_y = (c.height + kTile - 1) / kTile;
+    v.pixel_offset = c.pixel_offset;
+    return v;
+}
+
+int bits_for(uint64_t n) {
+    int b = 0;
+    while (b < 32 && (1ull << b) < n) ++b;
+    return b;
+}
+
+// Result of binning one view batch.
+struct Binned {
+    uint32_t n_tiles = 0;
+    uint32_t n_pairs = 0;
+    uint64_t n_items = 0;
+};
+
+// Project, depth-sort, emit and tile-sort the views [v0, v0+nv) of `all`.
+// The batch's ViewInfo table is uploaded to ctx->views (tile_base local to
+// the batch).  Synchronises `s` once to read the pair count.
+gsc_status bin_views(gsc_ctx* ctx, const std::vector<ViewInfo>& all, int v0, int nv,
+                     const float* means, const float* opac, int64_t N, const BlendParams& bp,
+                     hipStream_t s, Binned* out) {
+    // tile numbering local to the batch
+    if ((size_t)nv > ctx->h_views_cap) {
+        if (ctx->h_views) GSC_HIP(hipHostFree(ctx->h_views));
+        ctx->h_views = nullptr;
+        GSC_HIP(hipHostMalloc((void**)&ctx->h_views, sizeof(ViewInfo) * (size_t)nv));
+        ctx->h_views_cap = (size_t)nv;
+    }
+    uint64_t tiles = 0;
+    for (int k = 0; k < nv; ++k) {
+        ViewInfo v = all[v0 + k];
+        v.tile_base = (uint32_t)tiles;
+        tiles += (uint64_t)v.tiles_x * v.tiles_y;
+        ctx->h_views[k] = v;
+    }
+    if (tiles >= 0xffffffffull) return fail(GSC_ERR_CAPACITY, "too many tiles in one batch");
+    GSC_HIP(ctx->views.ensure(sizeof(ViewInfo) * (size_t)nv));
+    GSC_HIP(hipMemcpyAsync(ctx->views.p, ctx->h_views, sizeof(ViewInfo) * (size_t)nv,
+                           hipMemcpyHostToDevice, s));
+    const uint64_t items = (uint64_t)nv * (uint64_t)N;
+    out->n_items = items;
+    out->n_tiles = (uint32_t)tiles;
+    const uint32_t ni = (uint32_t)items;
+    GSC_HIP(ctx->keys.ensure(4 * items + 4));
+    GSC_HIP(ctx->vals.ensure(4 * items + 4));
+    GSC_HIP(ctx->keys_alt.ensure(4 * items + 4));
+    GSC_HIP(ctx->vals_alt.ensure(4 * items + 4));
+    GSC_HIP(ctx->counts.ensure(4 * items + 4));
+    GSC_HIP(ctx->counts_sorted.ensure(4 * items + 4));
+    GSC_HIP(ctx->offsets.ensure(4 * items + 4));
+    GSC_HIP(ctx->rec0.ensure(16 * items + 16));
+    GSC_HIP(ctx->rec1.ensure(16 * items + 16));
+    GSC_HIP(ctx->rects.ensure(sizeof(Rect) * items + 16));
+    GSC_HIP(ctx->ranges.ensure(sizeof(uint2) * (tiles + 1)));
+    const ViewInfo* dviews = ctx->views.as<ViewInfo>();
+    {
+        StageTimer t(ctx, s, GSC_STAGE_PROJECT);
+        launch_project(dviews, nv, means, ctx->cov.as<float>(), opac, N, bp, ctx->keys.as<uint32_t>(),
+                       ctx->vals.as<uint32_t>(), ctx->counts.as<uint32_t>(), ctx->rec0.as<float4>(),
+                       ctx->rec1.as<float4>(), ctx->rects.as<Rect>(), s);
+        GSC_LAUNCHED("project");
+    }
+    size_t scr = std::max(radix_scratch_words(ni), scan_scratch_words(ni));
+    GSC_HIP(ctx->sort_scratch.ensure(4 * scr + 256));
+    {
+        StageTimer t(ctx, s, GSC_STAGE_DEPTH_SORT);
+        radix_sort(ctx->keys.as<uint32_t>(), ctx->vals.as<uint32_t>(), ctx->keys_alt.as<uint32_t>(),
+                   ctx->vals_alt.as<uint32_t>(), ni, 32, ctx->sort_scratch.as<uint32_t>(), s);
+        GSC_LAUNCHED("depth sort");
+    }
+    StageTimer* scan_t = new StageTimer(ctx, s, GSC_STAGE_SCAN);
+    launch_gather_counts(ctx->vals.as<uint32_t>(), ctx->counts.as<uint32_t>(),
+                         ctx->counts_sorted.as<uint32_t>(), ni, s);
+    uint32_t* d_total = reinterpret_cast<uint32_t*>(ctx->misc.as<char>() + 8);
+    unsigned long long* d_total64 = reinterpret_cast<unsigned long long*>(ctx->misc.as<char>() + 16);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(d_total64), 0u, 2, s);
+    launch_sum_u64(ctx->counts.as<uint32_t>(), ni, d_total64, s);
+    launch_scan(ctx->counts_sorted.as<uint32_t>(), ctx->offsets.as<uint32_t>(), ni, d_total,
+                ctx->sort_scratch.as<uint32_t>(), s);
+    delete scan_t;
+    GSC_LAUNCHED("count scan");
+    GSC_HIP(hipMemcpyAsync(ctx->h_total, ctx->misc.as<char>() + 8, 16, hipMemcpyDeviceToHost, s));
+    GSC_HIP(hipStreamSynchronize(s));
+    uint64_t pairs64 = 0;
+    memcpy(&pairs64, reinterpret_cast<const char*>(ctx->h_total) + 8, 8);
+    if (pairs64 >= kMaxPairsPerBatch) {
+        if (nv > 1) return kSplit;
+        return fail(GSC_ERR_CAPACITY, "one view produces %llu tile pairs (limit %llu)",
+                    (unsigned long long)pairs64, (unsigned long long)kMaxPairsPerBatch);
+    }
+    const uint64_t pairs = pairs64;
+    if (pairs != *ctx->h_total) return fail(GSC_ERR_HIP, "pair count mismatch");
+    out->n_pairs = (uint32_t)pairs;
+    GSC_HIP(ctx->pkeys.ensure(4 * pairs + 4));
+    GSC_HIP(ctx->pvals.ensure(4 * pairs + 4));
+    GSC_HIP(ctx->pkeys_alt.ensure(4 * pairs + 4));
+    GSC_HIP(ctx->pvals_alt.ensure(4 * pairs + 4));
+    {
+        StageTimer t(ctx, s, GSC_STAGE_EMIT);
+        launch_emit(dviews, ctx->vals.as<uint32_t>(), ctx->offsets.as<uint32_t>(),
+                    ctx->counts.as<uint32_t>(), ctx->rects.as<Rect>(), ni, N,
+                    ctx->pkeys.as<uint32_t>(), ctx->pvals.as<uint32_t>(), s);
+        GSC_LAUNCHED("emit");
+    }
+    size_t pscr = radix_scratch_words((uint32_t)pairs);
+    GSC_HIP(ctx->sort_scratch.ensure(4 * std::max(pscr, scr) + 256));
+    {
+        StageTimer t(ctx, s, GSC_STAGE_TILE_SORT);
+        radix_sort(ctx->pkeys.as<uint32_t>(), ctx->pvals.as<uint32_t>(), ctx->pkeys_alt.as<uint32_t>(),
+                   ctx->pvals_alt.as<uint32_t>(), (uint32_t)pairs, bits_for(tiles),
+                   ctx->sort_scratch.as<uint32_t>(), s);
+        GSC_LAUNCHED("tile sort");
+        launch_fill_u32(ctx->ranges.as<uint32_t>(), 0u, (uint64_t)2 * tiles, s);
+        launch_tile_ranges(ctx->pkeys.as<uint32_t>(), (uint32_t)pairs, ctx->ranges.as<uint2>(), s);
+        GSC_LAUNCHED("tile ranges");
+    }
+    return GSC_OK;
+}
+
+// Run `body(v0, nv, binned)` over consecutive view batches.  A batch holds at
+// most kMaxItemsPerBatch items; a batch whose tile pairs overflow is halved.
+template <typename Body>
+gsc_status for_view_batches(gsc_ctx* ctx, const std::vector<ViewInfo>& all, int n_cams,
+                            const float* means, const float* opac, int64_t N, const BlendParams& bp,
+                            hipStream_t s, Body body) {
+    int per = (int)std::max<int64_t>(1, (int64_t)(kMaxItemsPerBatch / (uint64_t)std::max<int64_t>(N, 1)));
+    int v = 0;
+    while (v < n_cams) {
+        int nv = std::min(per, n_cams - v);
+        Binned bn;
+        gsc_status st = bin_views(ctx, all, v, nv, means, opac, N, bp, s, &bn);
+        if (st == kSplit) {
+            per = std::max(1, nv / 2);
+            continue;
+        }
+        if (st != GSC_OK) return st;
+        if ((st = body(v, nv, bn)) != GSC_OK) return st;
+        ctx->stats.pairs += bn.n_pairs;
+        ctx->stats.items += bn.n_items;
+        ctx->stats.view_batches += 1;
+        v += nv;
+    }
+    return GSC_OK;
+}
+
+gsc_status ensure_common(gsc_ctx* ctx, const float* scales, const float* quats, int64_t N,
+                         hipStream_t s) {
+    GSC_HIP(ctx->misc.ensure(kMiscBytes));
+    if (!ctx->h_total) GSC_HIP(hipHostMalloc((void**)&ctx->h_total, 64));
+    GSC_HIP(ctx->cov.ensure(sizeof(float) * 6 * (size_t)std::max<int64_t>(N, 1)));
+    launch_fill_u32(ctx->misc.as<uint32_t>(), 0u, kMiscBytes / 4, s);
+    launch_cov3d(scales, quats, ctx->cov.as<float>(), N, s);
+    GSC_LAUNCHED("cov3d");
+    return GSC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gsc_status gsc_default_options(gsc_options* out) {
+    if (!out) return fail(GSC_ERR_INVALID_ARG, "null options");
+    out->alpha_min = 1.0f / 255.0f;
+    out->alpha_max = 0.99f;
+    out->t_min = 1e-4f;
+    out->sigma_cut = 3.0f;
+    out->dilation = 0.3f;
+    out->znear = 0.01f;
+    out->kappa_max = 1e6f;
+    out->flags = 0;
+    return GSC_OK;
+}
+
+gsc_status gsc_ctx_create(gsc_ctx** ctx, const gsc_options* opt) {
+    if (!ctx) return fail(GSC_ERR_INVALID_ARG, "null ctx pointer");
+    *ctx = nullptr;
+    gsc_options o;
+    gsc_default_options(&o);
+    if (opt) o = *opt;
+    gsc_status st = validate_options(&o);
+    if (st != GSC_OK) return st;
+    gsc_ctx* c = new (std::nothrow) gsc_ctx();
+    if (!c) return fail(GSC_ERR_HIP, "out of host memory");
+    c->opt = o;
+    memset(&c->stats, 0, sizeof(c->stats));
+    *ctx = c;
+    return GSC_OK;
+}
+
+void gsc_ctx_destroy(gsc_ctx* ctx) { delete ctx; }
+
+gsc_status gsc_ctx_set_options(gsc_ctx* ctx, const gsc_options* opt) {
+    if (!ctx || !opt) return fail(GSC_ERR_INVALID_ARG, "null ctx or options");
+    gsc_status st = validate_options(opt);
+    if (st != GSC_OK) return st;
+    ctx->opt = *opt;
+    return GSC_OK;
+}
+
+gsc_status gsc_colorize(gsc_ctx* ctx, const float* means, const float* scales, const float* quats,
+                        const float* opacities, int64_t N, const gsc_camera* cams, int32_t n_cams,
+                        const void* targets, int32_t tdtype, int32_t C, int32_t sh_deg,
+                        const float* lambda, int32_t n_lambda, float* coeffs, uint8_t* status,
+                        gsc_stream_t stream) {
+    if (!ctx) return fail(GSC_ERR_INVALID_ARG, "null ctx");
+    int64_t rows = 0;
+    gsc_status st = validate_geometry(means, scales, quats, opacities, N, cams, n_cams, &rows);
+    if (st != GSC_OK) return st;
+    if ((st = validate_channels(C, sh_deg)) != GSC_OK) return st;
+    if (tdtype != GSC_F32 && tdtype != GSC_BF16) return fail(GSC_ERR_INVALID_ARG, "tdtype must be GSC_F32 or GSC_BF16");
+    if (rows > 0 && !targets) return fail(GSC_ERR_INVALID_ARG, "targets is null");
+    if (N > 0 && !coeffs) return fail(GSC_ERR_INVALID_ARG, "coeffs is null");
+    double lam[kMaxNb];
+    if ((st = expand_lambda(lambda, n_lambda, sh_deg, lam)) != GSC_OK) return st;
+    if (ctx->opt.flags & GSC_FLAG_VALIDATE_ONLY) return GSC_OK;
+
+    hipStream_t s = (hipStream_t)stream;
+    memset(&ctx->stats, 0, sizeof(ctx->stats));
+    if (N == 0) return GSC_OK;
+    const int nb = (sh_deg + 1) * (sh_deg + 1);
+    BlendParams bp = blend_params(ctx->opt);
+    if ((st = ensure_common(ctx, scales, quats, N, s)) != GSC_OK) return st;
+    std::vector<ViewInfo> all(n_cams);
+    for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j]);
+    const bool per_view = sh_deg > 0;
+    const uint64_t vs_words = (uint64_t)(per_view ? std::max(n_cams, 1) : 1) * (uint64_t)N * (uint64_t)(C + 1);
+    GSC_HIP(ctx->vs.ensure(4 * vs_words));
+    launch_fill_u32(ctx->vs.as<uint32_t>(), 0u, vs_words, s);
+    unsigned long long* d_counter = reinterpret_cast<unsigned long long*>(ctx->misc.p);
+    st = for_view_batches(ctx, all, n_cams, means, opacities, N, bp, s,
+                          [&](int v0, int nv, const Binned& bn) -> gsc_status {
+        StageTimer t(ctx, s, GSC_STAGE_BLEND, (uint32_t)((C + accumulate_chunk(C) - 1) / accumulate_chunk(C)));
+        launch_accumulate(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
+                          ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(),
+                          targets, tdtype, C, N, v0, per_view, bp, ctx->vs.as<float>(), d_counter, s);
+        GSC_LAUNCHED("accumulate");
+        return GSC_OK;
+    });
+    if (st != GSC_OK) return st;
+    // fold + solve needs the full camera table (only the camera centres are used)
+    if (per_view && n_cams > 0) {
+        if ((size_t)n_cams > ctx->h_all_cap) {
+            if (ctx->h_all) GSC_HIP(hipHostFree(ctx->h_all));
+            ctx->h_all = nullptr;
+            GSC_HIP(hipHostMalloc((void**)&ctx->h_all, sizeof(ViewInfo) * (size_t)n_cams));
+            ctx->h_all_cap = (size_t)n_cams;
+        }
+        for (int j = 0; j < n_cams; ++j) ctx->h_all[j] = all[j];
+        GSC_HIP(ctx->views_all.ensure(sizeof(ViewInfo) * (size_t)n_cams));
+        GSC_HIP(hipMemcpyAsync(ctx->views_all.p, ctx->h_all, sizeof(ViewInfo) * (size_t)n_cams,
+                               hipMemcpyHostToDevice, s));
+    }
+    unsigned int* d_ill = reinterpret_cast<unsigned int*>(ctx->misc.as<char>() + 12);
+    StageTimer t_solve(ctx, s, GSC_STAGE_SOLVE);
+    launch_fold_solve(ctx->views_all.as<ViewInfo>(), per_view ? n_cams : 0, means, ctx->vs.as<float>(), N, C, sh_deg,
+                      lam, ctx->opt.kappa_max, coeffs, status, d_ill, s);
+    GSC_LAUNCHED("fold/solve");
+    (void)nb;
+    ctx->stats_pending = true;
+    return GSC_OK;
+}
+
+gsc_status gsc_render(gsc_ctx* ctx, const float* means, const float* scales, const float* quats,
+                      const float* opacities, int64_t N, const gsc_camera* cams, int32_t n_cams,
+                      const float* coeffs, int32_t C, int32_t sh_deg, float* images,
+                      gsc_stream_t stream) {
+    if (!ctx) return fail(GSC_ERR_INVALID_ARG, "null ctx");
+    int64_t rows = 0;
+    gsc_status st = validate_geometry(means, scales, quats, opacities, N, cams, n_cams, &rows);
+    if (st != GSC_OK) return st;
+    if ((st = validate_channels(C, sh_deg)) != GSC_OK) return st;
+    if (rows > 0 && !images) return fail(GSC_ERR_INVALID_ARG, "images is null");
+    if (N > 0 && !coeffs) return fail(GSC_ERR_INVALID_ARG, "coeffs is null");
+    if (ctx->opt.flags & GSC_FLAG_VALIDATE_ONLY) return GSC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    memset(&ctx->stats, 0, sizeof(ctx->stats));
+    if (n_cams == 0) return GSC_OK;
+    BlendParams bp = blend_params(ctx->opt);
+    if ((st = ensure_common(ctx, scales, quats, N, s)) != GSC_OK) return st;
+    std::vector<ViewInfo> all(n_cams);
+    for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j]);
+    unsigned long long* d_counter = reinterpret_cast<unsigned long long*>(ctx->misc.p);
+    st = for_view_batches(ctx, all, n_cams, means, opacities, N, bp, s,
+                          [&](int v0, int nv, const Binned& bn) -> gsc_status {
+        (void)v0;
+        StageTimer t(ctx, s, GSC_STAGE_BLEND, 1 + (uint32_t)((C + 3) / 4));
+        GSC_HIP(ctx->gamma.ensure(4 * (size_t)nv * (size_t)std::max<int64_t>(N, 1) * (size_t)C));
+        launch_view_colors(ctx->views.as<ViewInfo>(), nv, means, coeffs, N, C, sh_deg,
+                           ctx->gamma.as<float>(), s);
+        GSC_LAUNCHED("view colors");
+        launch_render(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
+                      ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(),
+                      ctx->gamma.as<float>(), C, N, bp, images, d_counter, s);
+        GSC_LAUNCHED("render");
+        return GSC_OK;
+    });
+    if (st != GSC_OK) return st;
+    ctx->stats_pending = true;
+    return GSC_OK;
+}
+
+gsc_status gsc_get_stats(gsc_ctx* ctx, gsc_stats* out) {
+    if (!ctx || !out) return fail(GSC_ERR_INVALID_ARG, "null ctx or output");
+    if (ctx->stats_pending && ctx->misc.p) {
+        uint64_t buf[2] = {0, 0};
+        GSC_HIP(hipDeviceSynchronize());
+        GSC_HIP(hipMemcpy(buf, ctx->misc.p, 16, hipMemcpyDeviceToHost));
+        ctx->stats.contributions = buf[0];
+        ctx->stats.ill_conditioned = (uint32_t)(buf[1] >> 32);
+        ctx->stats_pending = false;
+    }
+    if (!ctx->marks.empty()) {
+        GSC_HIP(hipDeviceSynchronize());
+        for (int i = 0; i < GSC_N_STAGES; ++i) {
+            ctx->stats.stage_ms[i] = 0.0f;
+            ctx->stats.stage_launches[i] = 0;
+        }
+        for (const auto& m : ctx->marks) {
+            float ms = 0.0f;
+            GSC_HIP(hipEventElapsedTime(&ms, m.a, m.b));
+            ctx->stats.stage_ms[m.stage] += ms;
+            ctx->stats.stage_launches[m.stage] += m.launches;
+        }
+        ctx->marks.clear();
+        ctx->ev_used = 0;
+    }
+    *out = ctx->stats;
+    return GSC_OK;
+}
+
+const char* gsc_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

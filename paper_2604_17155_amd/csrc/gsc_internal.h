@@ -1,0 +1,99 @@
+// Internal declarations shared by the HIP translation units of libgsc.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gsc.h"
+
+namespace gsc {
+
+constexpr int kTile = 16;           // tile edge in pixels (16x16 = one wave, 4 pixels per lane)
+constexpr int kTileShift = 4;
+constexpr int kMaxNb = 16;          // (L+1)^2 for L <= 3
+constexpr int kMaxC = 64;
+
+// One view as the kernels see it.
+struct ViewInfo {
+    float R[9];
+    float t[3];
+    float fx, fy, cx, cy;
+    double centre[3];      // camera centre -R^T t, for the SH view direction
+    int32_t width, height;
+    int32_t tiles_x, tiles_y;
+    uint32_t tile_base;    // first global tile id of this view within its batch
+    uint32_t pad;
+    int64_t pixel_offset;  // first target row
+};
+
+// Blend constants in the form the kernels use.
+struct BlendParams {
+    float alpha_min, alpha_max, t_min, cut2, dilation, znear;
+};
+
+// Splat record of one (view, Gaussian) item, two float4:
+//   r0 = (u, v, opacity, depth key)   r1 = (conic_xx, conic_xy, conic_yy, bits of g)
+struct Rect {
+    uint16_t tx0, ty0, tx1, ty1;
+};
+
+// ---- kernels launched from gsc_api.hip ----------------------------------
+void launch_cov3d(const float* scales, const float* quats, float* cov, int64_t N, hipStream_t s);
+
+void launch_project(const ViewInfo* views, int n_views, const float* means, const float* cov,
+                    const float* opac, int64_t N, BlendParams bp, uint32_t* keys, uint32_t* vals,
+                    uint32_t* counts, float4* rec0, float4* rec1, Rect* rects, hipStream_t s);
+
+void launch_gather_counts(const uint32_t* sorted_vals, const uint32_t* counts, uint32_t* out,
+                          uint32_t n, hipStream_t s);
+
+void launch_emit(const ViewInfo* views, const uint32_t* sorted_vals, const uint32_t* offsets,
+                 const uint32_t* counts, const Rect* rects, uint32_t n_items, int64_t N,
+                 uint32_t* pair_keys, uint32_t* pair_vals, hipStream_t s);
+
+// Sum of n uint32 counts into *out (u64, must be zeroed).
+void launch_sum_u64(const uint32_t* counts, uint32_t n, unsigned long long* out, hipStream_t s);
+
+void launch_tile_ranges(const uint32_t* sorted_keys, uint32_t n_pairs, uint2* ranges, hipStream_t s);
+
+void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
+
+// Exclusive scan of n uint32 values; total written to *total (device). Scratch
+// must hold scan_scratch_words(n) words.
+size_t scan_scratch_words(uint64_t n);
+void launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total, uint32_t* scratch,
+                 hipStream_t s);
+
+// Stable LSD radix sort of (key, val) on the low `bits` bits of key. The
+// result ends in (keys, vals); alt buffers are scratch of the same size.
+size_t radix_scratch_words(uint32_t n);
+void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
+                uint32_t n, int bits, uint32_t* scratch, hipStream_t s);
+
+// Channels per accumulate launch for C channels (launches = ceil(C / chunk)).
+int accumulate_chunk(int C);
+
+// Accumulate V_gj and S_gj (per view when per_view, else summed over views).
+void launch_accumulate(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
+                       const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
+                       const void* targets, int tdtype, int C, int64_t N, int view_first,
+                       bool per_view, BlendParams bp, float* VS, unsigned long long* counter,
+                       hipStream_t s);
+
+// Per-view colour gamma[v][g][c] = sum_m coeffs[g][m][c] phi_m(dir_gv).
+void launch_view_colors(const ViewInfo* views, int n_views, const float* means,
+                        const float* coeffs, int64_t N, int C, int sh_deg, float* gamma,
+                        hipStream_t s);
+
+void launch_render(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
+                   const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
+                   const float* gamma, int C, int64_t N, BlendParams bp, float* images,
+                   unsigned long long* counter, hipStream_t s);
+
+// Fold the per-view sums into the regularised normal equations and solve.
+void launch_fold_solve(const ViewInfo* views, int n_views, const float* means, const float* VS,
+                       int64_t N, int C, int sh_deg, const double* lam_nb /*host, nb*/,
+                       float kappa_max, float* coeffs, uint8_t* status,
+                       unsigned int* ill_count, hipStream_t s);
+
+}  // namespace gsc

@@ -1,0 +1,370 @@
+// Fused per-tile blend + accumulate (the hot loop), and render.
+//
+// One wave64 owns one 16x16 tile; lane l handles the four pixels
+// (l%16, l/16 + 4k), k = 0..3.  The tile's Gaussians arrive in front-to-back
+// order (eq. 2).  Each lane blends its pixels in FP32; per Gaussian the wave
+// reduces sum_p w and sum_p w*y_p over the tile (the per-view visibility V_gj
+// of eq. 5 and the numerator of eq. 6) with DPP row reductions, and one
+// atomic per value adds the tile's share to the (view, Gaussian) slot.
+// Splat records for the next 64 list entries are loaded one per lane and
+// broadcast with v_readlane, so the loop needs no LDS and no barriers.
+#include "gsc_internal.h"
+#include "sh.h"
+
+namespace gsc {
+
+namespace {
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Sum over the 64 lanes; the result is uniform.  All lanes must be active.
+__device__ __forceinline__ float wave_sum(float v) {
+    v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_mov<0x141>(v);  // row_half_mirror
+    v += dpp_mov<0x140>(v);  // row_mirror: every lane holds its row's sum
+    float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return (r0 + r1) + (r2 + r3);
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 0) + (uint32_t)__builtin_amdgcn_readlane((int)v, 16) +
+           (uint32_t)__builtin_amdgcn_readlane((int)v, 32) + (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+}
+
+__device__ __forceinline__ float bcast(float v, uint32_t lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), (int)lane));
+}
+__device__ __forceinline__ uint32_t bcast_u(uint32_t v, uint32_t lane) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)lane);
+}
+
+__device__ __forceinline__ int find_view(const ViewInfo* __restrict__ views, int n_views, uint32_t tile) {
+    int lo = 0, hi = n_views - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (views[mid].tile_base <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <bool BF16>
+__device__ __forceinline__ float load_target(const void* __restrict__ t, int64_t idx) {
+    if constexpr (BF16) {
+        uint32_t b = ((const uint16_t*)t)[idx];
+        return __uint_as_float(b << 16);
+    } else {
+        return ((const float*)t)[idx];
+    }
+}
+
+}  // namespace
+
+// CC: channels handled by this launch (chunk [c_off, c_off + CC) of C).
+template <int CC, bool BF16>
+__global__ __launch_bounds__(256) void k_accumulate(
+    const ViewInfo* __restrict__ views, int n_views, uint32_t n_tiles, const uint2* __restrict__ ranges,
+    const uint32_t* __restrict__ pair_vals, const float4* __restrict__ rec0,
+    const float4* __restrict__ rec1, const void* __restrict__ targets, int C, int c_off, int64_t N,
+    int view_first, int per_view, BlendParams bp, float* __restrict__ VS,
+    unsigned long long* __restrict__ counter) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tile >= n_tiles) return;  // whole wave
+    const int vloc = find_view(views, n_views, tile);
+    const ViewInfo& V = views[vloc];
+    const uint32_t local = tile - V.tile_base;
+    const int tx = (int)(local % (uint32_t)V.tiles_x), ty = (int)(local / (uint32_t)V.tiles_x);
+    const int ix = tx * kTile + (int)(lane & 15);
+    const int iy0 = ty * kTile + (int)(lane >> 4);
+    const float px = (float)ix + 0.5f;
+    const int stride = C + 1;
+
+    float T[4];
+    bool live[4];
+    float y[4][CC];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int iy = iy0 + 4 * k;
+        live[k] = ix < V.width && iy < V.height;
+        T[k] = 1.0f;
+        int64_t row = V.pixel_offset + (int64_t)iy * V.width + ix;
+#pragma unroll
+        for (int c = 0; c < CC; ++c)
+            y[k][c] = (live[k] && c_off + c < C) ? load_target<BF16>(targets, row * C + c_off + c) : 0.0f;
+    }
+    const uint2 rg = ranges[tile];
+    uint32_t cnt = 0;
+    bool wave_live = __ballot(live[0] || live[1] || live[2] || live[3]) != 0;
+    const int64_t vs_view = per_view ? (int64_t)(view_first + vloc) * N : 0;
+    const bool first_chunk = c_off == 0;
+
+    for (uint32_t b = rg.x; b < rg.y && wave_live; b += 64) {
+        const uint32_t nb = min(64u, rg.y - b);
+        const uint32_t it = lane < nb ? pair_vals[b + lane] : 0u;
+        float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0;
+        if (lane < nb) {
+            a0 = rec0[it];
+            a1 = rec1[it];
+        }
+        for (uint32_t j = 0; j < nb; ++j) {
+            const float u = bcast(a0.x, j), v = bcast(a0.y, j), o = bcast(a0.z, j);
+            const float ca = bcast(a1.x, j), cb = bcast(a1.y, j), cc = bcast(a1.z, j);
+            const int g = (int)bcast_u(__float_as_uint(a1.w), j);
+            float sv = 0.0f;
+            float ss[CC];
+#pragma unroll
+            for (int c = 0; c < CC; ++c) ss[c] = 0.0f;
+            bool hit = false;
+            const float dx = px - u;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (!live[k]) continue;
+                const float dy = (float)(iy0 + 4 * k) + 0.5f - v;
+                const float q = ca * dx * dx + 2.0f * cb * dx * dy + cc * dy * dy;
+                if (q > bp.cut2) continue;
+                const float al = fminf(bp.alpha_max, o * __expf(-0.5f * q));
+                if (al < bp.alpha_min) continue;
+                const float test = T[k] * (1.0f - al);
+                if (test < bp.t_min) {
+                    live[k] = false;
+                    continue;
+                }
+                const float w = al * T[k];
+                T[k] = test;
+                sv += w;
+#pragma unroll
+                for (int c = 0; c < CC; ++c) ss[c] += w * y[k][c];
+                ++cnt;
+                hit = true;
+            }
+            if (__ballot(hit) != 0) {
+                const float tv = wave_sum(sv);
+                float mine = tv;
+#pragma unroll
+                for (int c = 0; c < CC; ++c) {
+                    const float ts = wave_sum(ss[c]);
+                    if (lane == (uint32_t)(c + 1)) mine = ts;
+                }
+                float* slot = VS + (vs_view + g) * (int64_t)stride;
+                if (lane == 0) {
+                    if (first_chunk) unsafeAtomicAdd(slot, mine);
+                } else if (lane <= (uint32_t)CC && c_off + (int)lane - 1 < C) {
+                    unsafeAtomicAdd(slot + c_off + lane, mine);
+                }
+            }
+            if (__ballot(live[0] || live[1] || live[2] || live[3]) == 0) {
+                wave_live = false;
+                break;
+            }
+        }
+    }
+    if (first_chunk) {
+        const uint32_t tot = wave_sum_u32(cnt);
+        if (lane == 0 && tot) atomicAdd(counter, (unsigned long long)tot);
+    }
+}
+
+template <int CC>
+static void launch_acc_cc(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
+                          const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
+                          const void* targets, int tdtype, int C, int64_t N, int view_first,
+                          bool per_view, BlendParams bp, float* VS, unsigned long long* counter,
+                          hipStream_t s) {
+    dim3 grid((n_tiles + 3) / 4), block(256);
+    for (int c_off = 0; c_off < C; c_off += CC) {
+        if (tdtype == GSC_BF16)
+            hipLaunchKernelGGL((k_accumulate<CC, true>), grid, block, 0, s, views, n_views, n_tiles,
+                               ranges, pair_vals, rec0, rec1, targets, C, c_off, N, view_first,
+                               (int)per_view, bp, VS, counter);
+        else
+            hipLaunchKernelGGL((k_accumulate<CC, false>), grid, block, 0, s, views, n_views, n_tiles,
+                               ranges, pair_vals, rec0, rec1, targets, C, c_off, N, view_first,
+                               (int)per_view, bp, VS, counter);
+    }
+}
+
+int accumulate_chunk(int C) { return C <= 3 ? C : (C <= 4 ? 4 : (C <= 8 ? 8 : 16)); }
+
+void launch_accumulate(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
+                       const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
+                       const void* targets, int tdtype, int C, int64_t N, int view_first,
+                       bool per_view, BlendParams bp, float* VS, unsigned long long* counter,
+                       hipStream_t s) {
+    if (n_tiles == 0) return;
+    if (C == 1)
+        launch_acc_cc<1>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, targets, tdtype, C,
+                         N, view_first, per_view, bp, VS, counter, s);
+    else if (C == 2)
+        launch_acc_cc<2>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, targets, tdtype, C,
+                         N, view_first, per_view, bp, VS, counter, s);
+    else if (C == 3)
+        launch_acc_cc<3>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, targets, tdtype, C,
+                         N, view_first, per_view, bp, VS, counter, s);
+    else if (C <= 4)
+        launch_acc_cc<4>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, targets, tdtype, C,
+                         N, view_first, per_view, bp, VS, counter, s);
+    else if (C <= 8)
+        launch_acc_cc<8>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, targets, tdtype, C,
+                         N, view_first, per_view, bp, VS, counter, s);
+    else
+        launch_acc_cc<16>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, targets, tdtype, C,
+                          N, view_first, per_view, bp, VS, counter, s);
+}
+
+// ---- render ----------------------------------------------------------------
+
+// gamma[(v*N + g)*C + c] = sum_m coeffs[g][m][c] * phi_m(dir_gv)
+template <int L>
+__global__ void k_view_colors(const ViewInfo* __restrict__ views, const float* __restrict__ means,
+                              const float* __restrict__ coeffs, int64_t N, int C,
+                              float* __restrict__ gamma) {
+    constexpr int NB = (L + 1) * (L + 1);
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int v = blockIdx.y;
+    if (g >= N) return;
+    const ViewInfo& V = views[v];
+    double dx = (double)means[3 * g] - V.centre[0];
+    double dy = (double)means[3 * g + 1] - V.centre[1];
+    double dz = (double)means[3 * g + 2] - V.centre[2];
+    double inv = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+    float phi[NB];
+    sh_eval<float, L>((float)(dx * inv), (float)(dy * inv), (float)(dz * inv), phi);
+    const float* cg = coeffs + g * NB * C;
+    float* out = gamma + ((int64_t)v * N + g) * C;
+    for (int c = 0; c < C; ++c) {
+        float a = 0.0f;
+#pragma unroll
+        for (int m = 0; m < NB; ++m) a += cg[m * C + c] * phi[m];
+        out[c] = a;
+    }
+}
+
+void launch_view_colors(const ViewInfo* views, int n_views, const float* means, const float* coeffs,
+                        int64_t N, int C, int sh_deg, float* gamma, hipStream_t s) {
+    if (N <= 0 || n_views <= 0) return;
+    dim3 grid((unsigned)((N + 255) / 256), (unsigned)n_views);
+    switch (sh_deg) {
+        case 0: hipLaunchKernelGGL(k_view_colors<0>, grid, dim3(256), 0, s, views, means, coeffs, N, C, gamma); break;
+        case 1: hipLaunchKernelGGL(k_view_colors<1>, grid, dim3(256), 0, s, views, means, coeffs, N, C, gamma); break;
+        case 2: hipLaunchKernelGGL(k_view_colors<2>, grid, dim3(256), 0, s, views, means, coeffs, N, C, gamma); break;
+        default: hipLaunchKernelGGL(k_view_colors<3>, grid, dim3(256), 0, s, views, means, coeffs, N, C, gamma); break;
+    }
+}
+
+// images[row][c] = sum_g w_gp * gamma_gv[c]; every pixel of every tile is written.
+template <int CC>
+__global__ __launch_bounds__(256) void k_render(
+    const ViewInfo* __restrict__ views, int n_views, uint32_t n_tiles, const uint2* __restrict__ ranges,
+    const uint32_t* __restrict__ pair_vals, const float4* __restrict__ rec0,
+    const float4* __restrict__ rec1, const float* __restrict__ gamma, int C, int c_off, int64_t N,
+    BlendParams bp, float* __restrict__ images, unsigned long long* __restrict__ counter) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tile >= n_tiles) return;
+    const int vloc = find_view(views, n_views, tile);
+    const ViewInfo& V = views[vloc];
+    const uint32_t local = tile - V.tile_base;
+    const int tx = (int)(local % (uint32_t)V.tiles_x), ty = (int)(local / (uint32_t)V.tiles_x);
+    const int ix = tx * kTile + (int)(lane & 15);
+    const int iy0 = ty * kTile + (int)(lane >> 4);
+    const float px = (float)ix + 0.5f;
+    float T[4];
+    bool live[4], inside[4];
+    float img[4][CC];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        inside[k] = ix < V.width && iy0 + 4 * k < V.height;
+        live[k] = inside[k];
+        T[k] = 1.0f;
+#pragma unroll
+        for (int c = 0; c < CC; ++c) img[k][c] = 0.0f;
+    }
+    const uint2 rg = ranges[tile];
+    uint32_t cnt = 0;
+    bool wave_live = __ballot(live[0] || live[1] || live[2] || live[3]) != 0;
+    for (uint32_t b = rg.x; b < rg.y && wave_live; b += 64) {
+        const uint32_t nb = min(64u, rg.y - b);
+        const uint32_t it = lane < nb ? pair_vals[b + lane] : 0u;
+        float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0;
+        if (lane < nb) {
+            a0 = rec0[it];
+            a1 = rec1[it];
+        }
+        for (uint32_t j = 0; j < nb; ++j) {
+            const float u = bcast(a0.x, j), v = bcast(a0.y, j), o = bcast(a0.z, j);
+            const float ca = bcast(a1.x, j), cb = bcast(a1.y, j), cc = bcast(a1.z, j);
+            const uint32_t item = bcast_u(it, j);
+            float col[CC];
+            const float* gp = gamma + (int64_t)item * C + c_off;
+#pragma unroll
+            for (int c = 0; c < CC; ++c) col[c] = (c_off + c < C) ? gp[c] : 0.0f;
+            const float dx = px - u;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (!live[k]) continue;
+                const float dy = (float)(iy0 + 4 * k) + 0.5f - v;
+                const float q = ca * dx * dx + 2.0f * cb * dx * dy + cc * dy * dy;
+                if (q > bp.cut2) continue;
+                const float al = fminf(bp.alpha_max, o * __expf(-0.5f * q));
+                if (al < bp.alpha_min) continue;
+                const float test = T[k] * (1.0f - al);
+                if (test < bp.t_min) {
+                    live[k] = false;
+                    continue;
+                }
+                const float w = al * T[k];
+                T[k] = test;
+#pragma unroll
+                for (int c = 0; c < CC; ++c) img[k][c] += w * col[c];
+                ++cnt;
+            }
+            if (__ballot(live[0] || live[1] || live[2] || live[3]) == 0) {
+                wave_live = false;
+                break;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (!inside[k]) continue;
+        int64_t row = V.pixel_offset + (int64_t)(iy0 + 4 * k) * V.width + ix;
+#pragma unroll
+        for (int c = 0; c < CC; ++c)
+            if (c_off + c < C) images[row * C + c_off + c] = img[k][c];
+    }
+    if (c_off == 0) {
+        const uint32_t tot = wave_sum_u32(cnt);
+        if (lane == 0 && tot) atomicAdd(counter, (unsigned long long)tot);
+    }
+}
+
+void launch_render(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
+                   const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
+                   const float* gamma, int C, int64_t N, BlendParams bp, float* images,
+                   unsigned long long* counter, hipStream_t s) {
+    if (n_tiles == 0) return;
+    dim3 grid((n_tiles + 3) / 4), block(256);
+    for (int c_off = 0; c_off < C; c_off += 4) {
+        if (C <= 3 && c_off == 0) {
+            hipLaunchKernelGGL(k_render<3>, grid, block, 0, s, views, n_views, n_tiles, ranges,
+                               pair_vals, rec0, rec1, gamma, C, c_off, N, bp, images, counter);
+        } else {
+            hipLaunchKernelGGL(k_render<4>, grid, block, 0, s, views, n_views, n_tiles, ranges,
+                               pair_vals, rec0, rec1, gamma, C, c_off, N, bp, images, counter);
+        }
+    }
+}
+
+}  // namespace gsc

@@ -1,0 +1,196 @@
+// Projection, binning and tile ranges (per view x Gaussian).
+//
+// Gaussian geometry follows the 3DGS renderer the paper builds on (Sec. 3,
+// "Differentiable renderer"): Sigma = R(q) diag(s^2) R(q)^T, EWA projection
+// Sigma_2D = J W Sigma W^T J^T + dilation*I, a 3-sigma footprint, and the
+// front-to-back order of eq. 2 keyed on the camera-space depth of the mean.
+#include "gsc_internal.h"
+
+namespace gsc {
+
+// a1: 3D covariance, 6 floats per Gaussian (xx xy xz yy yz zz).
+__global__ void k_cov3d(const float* __restrict__ scales, const float* __restrict__ quats,
+                        float* __restrict__ cov, int64_t N) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= N) return;
+    float w = quats[4 * g], x = quats[4 * g + 1], y = quats[4 * g + 2], z = quats[4 * g + 3];
+    float inv = rsqrtf(w * w + x * x + y * y + z * z);
+    w *= inv; x *= inv; y *= inv; z *= inv;
+    float R[3][3] = {{1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y)},
+                     {2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x)},
+                     {2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)}};
+    float s0 = scales[3 * g], s1 = scales[3 * g + 1], s2 = scales[3 * g + 2];
+    float d[3] = {s0 * s0, s1 * s1, s2 * s2};
+    float S[6];
+    int k = 0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = i; j < 3; ++j) {
+            S[k++] = R[i][0] * d[0] * R[j][0] + R[i][1] * d[1] * R[j][1] + R[i][2] * d[2] * R[j][2];
+        }
+    for (int i = 0; i < 6; ++i) cov[6 * g + i] = S[i];
+}
+
+void launch_cov3d(const float* scales, const float* quats, float* cov, int64_t N, hipStream_t s) {
+    if (N <= 0) return;
+    hipLaunchKernelGGL(k_cov3d, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, scales, quats,
+                       cov, N);
+}
+
+// a2: one thread per (view, Gaussian).  Item index i = v * N + g.
+__global__ __launch_bounds__(256) void k_project(const ViewInfo* __restrict__ views,
+                                                 const float* __restrict__ means,
+                                                 const float* __restrict__ cov,
+                                                 const float* __restrict__ opac, int64_t N,
+                                                 BlendParams bp, uint32_t* __restrict__ keys,
+                                                 uint32_t* __restrict__ vals,
+                                                 uint32_t* __restrict__ counts,
+                                                 float4* __restrict__ rec0, float4* __restrict__ rec1,
+                                                 Rect* __restrict__ rects) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int v = blockIdx.y;
+    if (g >= N) return;
+    const ViewInfo& V = views[v];
+    uint32_t i = (uint32_t)((int64_t)v * N + g);
+    float mx = means[3 * g], my = means[3 * g + 1], mz = means[3 * g + 2];
+    float key = __fmaf_rn(V.R[6], mx, __fmaf_rn(V.R[7], my, __fmaf_rn(V.R[8], mz, V.t[2])));
+    uint32_t kb = 0xFFFFFFFFu, cnt = 0;
+    float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
+    Rect rc = {0, 0, 0, 0};
+    if (key > bp.znear) {
+        float tx = __fmaf_rn(V.R[0], mx, __fmaf_rn(V.R[1], my, __fmaf_rn(V.R[2], mz, V.t[0])));
+        float ty = __fmaf_rn(V.R[3], mx, __fmaf_rn(V.R[4], my, __fmaf_rn(V.R[5], mz, V.t[1])));
+        float iz = 1.0f / key;
+        float j00 = V.fx * iz, j02 = -V.fx * tx * iz * iz;
+        float j11 = V.fy * iz, j12 = -V.fy * ty * iz * iz;
+        const float* c = cov + 6 * g;
+        float S[3][3] = {{c[0], c[1], c[2]}, {c[1], c[3], c[4]}, {c[2], c[4], c[5]}};
+        // Sc = W S W^T
+        float M[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                M[a][b] = V.R[3 * a] * S[0][b] + V.R[3 * a + 1] * S[1][b] + V.R[3 * a + 2] * S[2][b];
+        float Sc[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int b = a; b < 3; ++b)
+                Sc[a][b] = M[a][0] * V.R[3 * b] + M[a][1] * V.R[3 * b + 1] + M[a][2] * V.R[3 * b + 2];
+        float sxx = j00 * j00 * Sc[0][0] + 2.f * j00 * j02 * Sc[0][2] + j02 * j02 * Sc[2][2] + bp.dilation;
+        float sxy = j00 * j11 * Sc[0][1] + j00 * j12 * Sc[0][2] + j02 * j11 * Sc[1][2] + j02 * j12 * Sc[2][2];
+        float syy = j11 * j11 * Sc[1][1] + 2.f * j11 * j12 * Sc[1][2] + j12 * j12 * Sc[2][2] + bp.dilation;
+        float det = sxx * syy - sxy * sxy;
+        float u = V.fx * tx * iz + V.cx;
+        float vv = V.fy * ty * iz + V.cy;
+        float cut = sqrtf(bp.cut2);
+        float rx = cut * sqrtf(sxx), ry = cut * sqrtf(syy);
+        // pixel centres x+0.5 with |x+0.5-u| <= rx, widened by half a pixel
+        float fx0 = fmaxf(floorf(u - rx - 1.0f), 0.0f);
+        float fx1 = fminf(ceilf(u + rx), (float)(V.width - 1));
+        float fy0 = fmaxf(floorf(vv - ry - 1.0f), 0.0f);
+        float fy1 = fminf(ceilf(vv + ry), (float)(V.height - 1));
+        if (det > 0.0f && fx0 <= fx1 && fy0 <= fy1) {
+            float inv = 1.0f / det;
+            int x0 = (int)fx0, x1 = (int)fx1, y0 = (int)fy0, y1 = (int)fy1;
+            rc.tx0 = (uint16_t)(x0 >> kTileShift);
+            rc.tx1 = (uint16_t)(x1 >> kTileShift);
+            rc.ty0 = (uint16_t)(y0 >> kTileShift);
+            rc.ty1 = (uint16_t)(y1 >> kTileShift);
+            cnt = (uint32_t)(rc.tx1 - rc.tx0 + 1) * (uint32_t)(rc.ty1 - rc.ty0 + 1);
+            kb = __float_as_uint(key);
+            r0 = make_float4(u, vv, opac[g], key);
+            r1 = make_float4(syy * inv, -sxy * inv, sxx * inv, __int_as_float((int)g));
+        }
+    }
+    keys[i] = kb;
+    vals[i] = i;
+    counts[i] = cnt;
+    rec0[i] = r0;
+    rec1[i] = r1;
+    rects[i] = rc;
+}
+
+void launch_project(const ViewInfo* views, int n_views, const float* means, const float* cov,
+                    const float* opac, int64_t N, BlendParams bp, uint32_t* keys, uint32_t* vals,
+                    uint32_t* counts, float4* rec0, float4* rec1, Rect* rects, hipStream_t s) {
+    if (N <= 0 || n_views <= 0) return;
+    hipLaunchKernelGGL(k_project, dim3((unsigned)((N + 255) / 256), (unsigned)n_views), dim3(256), 0,
+                       s, views, means, cov, opac, N, bp, keys, vals, counts, rec0, rec1, rects);
+}
+
+__global__ void k_gather_counts(const uint32_t* __restrict__ sorted_vals,
+                                const uint32_t* __restrict__ counts, uint32_t* __restrict__ out,
+                                uint32_t n) {
+    uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) out[k] = counts[sorted_vals[k]];
+}
+
+void launch_gather_counts(const uint32_t* sorted_vals, const uint32_t* counts, uint32_t* out,
+                          uint32_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_gather_counts, dim3((n + 255) / 256), dim3(256), 0, s, sorted_vals, counts,
+                       out, n);
+}
+
+// a3: emit (global tile id, item) pairs in depth order; a stable sort by tile
+// id then yields every tile's list in front-to-back order.
+__global__ void k_emit(const ViewInfo* __restrict__ views, const uint32_t* __restrict__ sorted_vals,
+                       const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ counts,
+                       const Rect* __restrict__ rects, uint32_t n_items, int64_t N,
+                       uint32_t* __restrict__ pair_keys, uint32_t* __restrict__ pair_vals) {
+    uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_items) return;
+    uint32_t i = sorted_vals[k];
+    if (counts[i] == 0) return;
+    int v = (int)((int64_t)i / N);
+    const ViewInfo& V = views[v];
+    Rect rc = rects[i];
+    uint32_t off = offsets[k];
+    for (uint32_t ty = rc.ty0; ty <= rc.ty1; ++ty)
+        for (uint32_t tx = rc.tx0; tx <= rc.tx1; ++tx) {
+            pair_keys[off] = V.tile_base + ty * (uint32_t)V.tiles_x + tx;
+            pair_vals[off] = i;
+            ++off;
+        }
+}
+
+void launch_emit(const ViewInfo* views, const uint32_t* sorted_vals, const uint32_t* offsets,
+                 const uint32_t* counts, const Rect* rects, uint32_t n_items, int64_t N,
+                 uint32_t* pair_keys, uint32_t* pair_vals, hipStream_t s) {
+    if (n_items == 0) return;
+    hipLaunchKernelGGL(k_emit, dim3((n_items + 255) / 256), dim3(256), 0, s, views, sorted_vals,
+                       offsets, counts, rects, n_items, N, pair_keys, pair_vals);
+}
+
+__global__ __launch_bounds__(256) void k_sum_u64(const uint32_t* __restrict__ counts, uint32_t n,
+                                                unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long part[4];
+    unsigned long long acc = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        acc += counts[i];
+    for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(out, part[0] + part[1] + part[2] + part[3]);
+}
+
+void launch_sum_u64(const uint32_t* counts, uint32_t n, unsigned long long* out, hipStream_t s) {
+    if (n == 0) return;
+    uint32_t blocks = (n + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(k_sum_u64, dim3(blocks), dim3(256), 0, s, counts, n, out);
+}
+
+__global__ void k_tile_ranges(const uint32_t* __restrict__ keys, uint32_t n, uint2* __restrict__ ranges) {
+    uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    uint32_t t = keys[k];
+    if (k == 0 || keys[k - 1] != t) ranges[t].x = k;
+    if (k == n - 1 || keys[k + 1] != t) ranges[t].y = k + 1;
+}
+
+void launch_tile_ranges(const uint32_t* sorted_keys, uint32_t n_pairs, uint2* ranges, hipStream_t s) {
+    if (n_pairs == 0) return;
+    hipLaunchKernelGGL(k_tile_ranges, dim3((n_pairs + 255) / 256), dim3(256), 0, s, sorted_keys,
+                       n_pairs, ranges);
+}
+
+}  // namespace gsc

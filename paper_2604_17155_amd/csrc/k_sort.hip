@@ -1,0 +1,241 @@
+// Device-wide exclusive scan and stable LSD radix sort (8-bit digits).
+//
+// The sort orders the (view, Gaussian) items by depth and then the emitted
+// (tile, item) pairs by tile.  Stability of every pass is what carries the
+// depth order (and the index tie-break) into each tile's list.
+#include "gsc_internal.h"
+
+namespace gsc {
+
+namespace {
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanBlock = kScanThreads * kScanItems;  // 2048
+
+constexpr int kRsThreads = 256;
+constexpr int kRsItems = 16;
+constexpr int kRsTile = kRsThreads * kRsItems;  // 4096
+constexpr int kRsWaves = kRsThreads / 64;
+
+__device__ inline uint32_t wave_inclusive_scan(uint32_t v) {
+    int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+// Exclusive scan over the 256 threads of a block; returns the block total in *total.
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* wsum, uint32_t* total) {
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t inc = wave_inclusive_scan(v);
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    uint32_t off = 0, all = 0;
+#pragma unroll
+    for (int k = 0; k < kScanThreads / 64; ++k) {
+        uint32_t s = wsum[k];
+        if (k < w) off += s;
+        all += s;
+    }
+    *total = all;
+    __syncthreads();
+    return off + inc - v;
+}
+}  // namespace
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __restrict__ in,
+                                                              uint32_t n, uint32_t* __restrict__ bsums) {
+    __shared__ uint32_t wsum[kScanThreads / 64];
+    uint64_t base = (uint64_t)blockIdx.x * kScanBlock + (uint64_t)threadIdx.x * kScanItems;
+    uint32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        uint64_t idx = base + j;
+        if (idx < n) s += in[idx];
+    }
+    uint32_t tot;
+    block_exclusive_scan(s, wsum, &tot);
+    if (threadIdx.x == 0) bsums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* in, uint32_t* out,
+                                                            uint32_t n, const uint32_t* bsums,
+                                                            uint32_t* total) {
+    __shared__ uint32_t wsum[kScanThreads / 64];
+    uint64_t base = (uint64_t)blockIdx.x * kScanBlock + (uint64_t)threadIdx.x * kScanItems;
+    uint32_t x[kScanItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        uint64_t idx = base + j;
+        x[j] = idx < n ? in[idx] : 0u;
+        s += x[j];
+    }
+    uint32_t tot;
+    uint32_t pre = block_exclusive_scan(s, wsum, &tot);
+    uint32_t off = bsums ? bsums[blockIdx.x] : 0u;
+    pre += off;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        uint64_t idx = base + j;
+        if (idx < n) out[idx] = pre;
+        pre += x[j];
+    }
+    if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = off + tot;
+}
+
+size_t scan_scratch_words(uint64_t n) {
+    size_t w = 0;
+    while (n > (uint64_t)kScanBlock) {
+        n = (n + kScanBlock - 1) / kScanBlock;
+        w += (size_t)((n + 63) / 64) * 64;
+    }
+    return w + 64;
+}
+
+void launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total, uint32_t* scratch,
+                 hipStream_t s) {
+    if (n == 0) {
+        if (total) launch_fill_u32(total, 0u, 1, s);
+        return;
+    }
+    if (n <= (uint32_t)kScanBlock) {
+        hipLaunchKernelGGL(k_scan_down, dim3(1), dim3(kScanThreads), 0, s, in, out, n,
+                           (const uint32_t*)nullptr, total);
+        return;
+    }
+    uint32_t nb = (n + kScanBlock - 1) / kScanBlock;
+    uint32_t* bs = scratch;
+    uint32_t* rest = scratch + ((nb + 63) / 64) * 64;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, s, in, n, bs);
+    launch_scan(bs, bs, nb, nullptr, rest, s);
+    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kScanThreads), 0, s, in, out, n,
+                       (const uint32_t*)bs, total);
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, uint64_t n) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t step = (uint64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += step) p[i] = v;
+}
+
+// Fill with a kernel rather than hipMemsetAsync so that the work stays
+// ordinary kernel nodes if a caller captures the stream into a graph.
+void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
+    if (n == 0) return;
+    uint64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, v, n);
+}
+
+// ---- radix sort ----------------------------------------------------------
+
+// Digit histogram of one 4096-key tile, written digit-major: hist[d * nblocks + b].
+__global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint32_t* __restrict__ keys, uint32_t n,
+                                                        int shift, uint32_t* __restrict__ hist,
+                                                        uint32_t nblocks) {
+    __shared__ uint32_t h[kRsWaves][256];
+    int w = threadIdx.x >> 6;
+    for (int k = threadIdx.x; k < kRsWaves * 256; k += kRsThreads) (&h[0][0])[k] = 0;
+    __syncthreads();
+    uint64_t base = (uint64_t)blockIdx.x * kRsTile;
+#pragma unroll 4
+    for (int it = 0; it < kRsItems; ++it) {
+        uint64_t idx = base + (uint64_t)it * kRsThreads + threadIdx.x;
+        if (idx < n) atomicAdd(&h[w][(keys[idx] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    uint32_t d = threadIdx.x;
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kRsWaves; ++k) sum += h[k][d];
+    hist[(uint64_t)d * nblocks + blockIdx.x] = sum;
+}
+
+// Stable scatter: ranks within the tile follow the original order
+// (iteration, wave, lane), offset by the scanned digit-major histogram.
+__global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* __restrict__ keys_in,
+                                                           const uint32_t* __restrict__ vals_in,
+                                                           uint32_t* __restrict__ keys_out,
+                                                           uint32_t* __restrict__ vals_out,
+                                                           uint32_t n, int shift,
+                                                           const uint32_t* __restrict__ offs,
+                                                           uint32_t nblocks) {
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t wc[kRsWaves][256];
+    int w = threadIdx.x >> 6;
+    base[threadIdx.x] = offs[(uint64_t)threadIdx.x * nblocks + blockIdx.x];
+    uint64_t tile0 = (uint64_t)blockIdx.x * kRsTile;
+    for (int it = 0; it < kRsItems; ++it) {
+        for (int k = threadIdx.x; k < kRsWaves * 256; k += kRsThreads) (&wc[0][0])[k] = 0;
+        __syncthreads();
+        uint64_t idx = tile0 + (uint64_t)it * kRsThreads + threadIdx.x;
+        bool valid = idx < n;
+        uint32_t key = valid ? keys_in[idx] : 0u;
+        uint32_t val = valid ? vals_in[idx] : 0u;
+        uint32_t d = (key >> shift) & 255u;
+        uint64_t m = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            uint64_t bb = __ballot((d >> b) & 1u);
+            m &= ((d >> b) & 1u) ? bb : ~bb;
+        }
+        uint32_t pre = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if (valid && pre == 0) wc[w][d] = (uint32_t)__popcll(m);
+        __syncthreads();
+        {
+            uint32_t t = threadIdx.x;
+            uint32_t run = base[t];
+#pragma unroll
+            for (int k = 0; k < kRsWaves; ++k) {
+                uint32_t c = wc[k][t];
+                wc[k][t] = run;
+                run += c;
+            }
+            base[t] = run;
+        }
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = wc[w][d] + pre;
+            keys_out[pos] = key;
+            vals_out[pos] = val;
+        }
+        __syncthreads();
+    }
+}
+
+size_t radix_scratch_words(uint32_t n) {
+    uint64_t nb = (n + kRsTile - 1) / kRsTile;
+    uint64_t h = 256 * (nb > 0 ? nb : 1);
+    return (size_t)(((h + 63) / 64) * 64 + scan_scratch_words(h));
+}
+
+void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, uint32_t n,
+                int bits, uint32_t* scratch, hipStream_t s) {
+    if (n <= 1 || bits <= 0) return;
+    uint32_t nb = (n + kRsTile - 1) / kRsTile;
+    uint32_t* hist = scratch;
+    uint32_t* sscr = scratch + ((256ull * nb + 63) / 64) * 64;
+    int passes = (bits + 7) / 8;
+    uint32_t *sk = keys, *sv = vals, *dk = keys_alt, *dv = vals_alt;
+    for (int p = 0; p < passes; ++p) {
+        int shift = 8 * p;
+        hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kRsThreads), 0, s, sk, n, shift, hist, nb);
+        launch_scan(hist, hist, 256u * nb, nullptr, sscr, s);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kRsThreads), 0, s, sk, sv, dk, dv, n, shift,
+                           hist, nb);
+        uint32_t* t;
+        t = sk; sk = dk; dk = t;
+        t = sv; sv = dv; dv = t;
+    }
+    if (sk != keys) {
+        (void)hipMemcpyAsync(keys, sk, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s);
+        (void)hipMemcpyAsync(vals, sv, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s);
+    }
+}
+
+}  // namespace gsc

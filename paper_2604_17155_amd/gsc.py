@@ -1,0 +1,226 @@
+"""Python binding of libgsc (ctypes).  Argument marshalling only: every step
+of colorize and render runs in the HIP library.  PyTorch supplies device
+memory and the current stream.
+
+Importing this module does not need a GPU; calling into the library does.
+If libgsc.so has not been built the loader raises instead of falling back to
+anything else.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgsc.so")
+
+GSC_OK = 0
+GSC_ERR_INVALID_ARG = -1
+GSC_ERR_HIP = -2
+GSC_ERR_CAPACITY = -3
+GSC_ERR_UNSUPPORTED = -4
+GSC_F32 = 0
+GSC_BF16 = 1
+GSC_G_UNOBSERVED = 1
+GSC_G_ILL_COND = 2
+GSC_G_FAILED = 4
+GSC_FLAG_VALIDATE_ONLY = 1
+
+
+class GscCamera(ct.Structure):
+    _fields_ = [("R", ct.c_float * 9), ("t", ct.c_float * 3), ("fx", ct.c_float),
+                ("fy", ct.c_float), ("cx", ct.c_float), ("cy", ct.c_float),
+                ("width", ct.c_int32), ("height", ct.c_int32), ("pixel_offset", ct.c_int64)]
+
+
+class GscOptions(ct.Structure):
+    _fields_ = [("alpha_min", ct.c_float), ("alpha_max", ct.c_float), ("t_min", ct.c_float),
+                ("sigma_cut", ct.c_float), ("dilation", ct.c_float), ("znear", ct.c_float),
+                ("kappa_max", ct.c_float), ("flags", ct.c_int32)]
+
+
+GSC_FLAG_PROFILE = 2
+STAGES = ["project", "depth_sort", "scan", "emit", "tile_sort", "blend", "solve", "reserved"]
+
+
+class GscStats(ct.Structure):
+    _fields_ = [("contributions", ct.c_uint64), ("pairs", ct.c_uint64), ("items", ct.c_uint64),
+                ("view_batches", ct.c_uint32), ("ill_conditioned", ct.c_uint32),
+                ("stage_ms", ct.c_float * 8), ("stage_launches", ct.c_uint32 * 8)]
+
+    def stage_dict(self):
+        return {n: float(self.stage_ms[i]) for i, n in enumerate(STAGES[:7])}
+
+
+class GscError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"gsc error {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: Optional[str] = None):
+    """Load libgsc.so; raises if it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise ImportError(f"libgsc.so not found at {p}; build it with __graft_entry__.build()")
+    lib = ct.CDLL(p)
+    P, i64, i32 = ct.c_void_p, ct.c_int64, ct.c_int32
+    lib.gsc_default_options.argtypes = [ct.POINTER(GscOptions)]
+    lib.gsc_default_options.restype = ct.c_int
+    lib.gsc_ctx_create.argtypes = [ct.POINTER(P), ct.POINTER(GscOptions)]
+    lib.gsc_ctx_create.restype = ct.c_int
+    lib.gsc_ctx_destroy.argtypes = [P]
+    lib.gsc_ctx_destroy.restype = None
+    lib.gsc_ctx_set_options.argtypes = [P, ct.POINTER(GscOptions)]
+    lib.gsc_ctx_set_options.restype = ct.c_int
+    lib.gsc_colorize.argtypes = [P, P, P, P, P, i64, P, i32, P, i32, i32, i32, P, i32, P, P, P]
+    lib.gsc_colorize.restype = ct.c_int
+    lib.gsc_render.argtypes = [P, P, P, P, P, i64, P, i32, P, i32, i32, P, P]
+    lib.gsc_render.restype = ct.c_int
+    lib.gsc_get_stats.argtypes = [P, ct.POINTER(GscStats)]
+    lib.gsc_get_stats.restype = ct.c_int
+    lib.gsc_last_error.argtypes = []
+    lib.gsc_last_error.restype = ct.c_char_p
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(lib, st: int):
+    if st != GSC_OK:
+        raise GscError(st, lib.gsc_last_error().decode())
+
+
+def default_options() -> GscOptions:
+    lib = load()
+    o = GscOptions()
+    _check(lib, lib.gsc_default_options(ct.byref(o)))
+    return o
+
+
+def make_cameras(cams: Sequence, offsets: Optional[Sequence[int]] = None):
+    """ctypes array of gsc_camera from objects with R, t, fx, fy, cx, cy,
+    width, height.  Pixel offsets default to the cameras' cumulative sizes."""
+    arr = (GscCamera * max(1, len(cams)))()
+    off = 0
+    for i, c in enumerate(cams):
+        arr[i].R[:] = [float(v) for v in np.asarray(c.R, dtype=np.float32).reshape(-1)]
+        arr[i].t[:] = [float(v) for v in c.t]
+        arr[i].fx, arr[i].fy, arr[i].cx, arr[i].cy = float(c.fx), float(c.fy), float(c.cx), float(c.cy)
+        arr[i].width, arr[i].height = int(c.width), int(c.height)
+        arr[i].pixel_offset = off if offsets is None else int(offsets[i])
+        off += int(c.width) * int(c.height)
+    return arr
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Context:
+    """Owns a gsc_ctx (device scratch reused across calls)."""
+
+    def __init__(self, options: Optional[GscOptions] = None, **overrides):
+        self.lib = load()
+        o = options or default_options()
+        for k, v in overrides.items():
+            setattr(o, k, v)
+        h = ct.c_void_p()
+        _check(self.lib, self.lib.gsc_ctx_create(ct.byref(h), ct.byref(o)))
+        self.handle = h
+        self.options = o
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.gsc_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_options(self, **overrides):
+        for k, v in overrides.items():
+            setattr(self.options, k, v)
+        _check(self.lib, self.lib.gsc_ctx_set_options(self.handle, ct.byref(self.options)))
+
+    def stats(self) -> GscStats:
+        out = GscStats()
+        _check(self.lib, self.lib.gsc_get_stats(self.handle, ct.byref(out)))
+        return out
+
+    def colorize(self, means, scales, quats, opacities, cams, targets, sh_deg: int, lam,
+                 coeffs=None, status=None, offsets=None, stream=None, with_status: bool = True):
+        """Solve the per-Gaussian regularised normal equations.  Returns
+        (coeffs [N,(L+1)^2,C] float32, status [N] uint8 or None)."""
+        import torch
+        N = int(means.shape[0])
+        C = int(targets.shape[1]) if targets.dim() == 2 else 1
+        nb = (sh_deg + 1) ** 2
+        if targets.dtype == torch.float32:
+            td = GSC_F32
+        elif targets.dtype == torch.bfloat16:
+            td = GSC_BF16
+        else:
+            raise ValueError("targets must be float32 or bfloat16")
+        dev = means.device
+        if coeffs is None:
+            coeffs = torch.empty((N, nb, C), dtype=torch.float32, device=dev)
+        if status is None and with_status:
+            status = torch.empty((N,), dtype=torch.uint8, device=dev)
+        lam_a = (ct.c_float * len(lam))(*[float(v) for v in lam])
+        cam_arr = make_cameras(cams, offsets)
+        st = self.lib.gsc_colorize(self.handle, _ptr(means), _ptr(scales), _ptr(quats),
+                                   _ptr(opacities), N, cam_arr, len(cams), _ptr(targets), td, C,
+                                   sh_deg, lam_a, len(lam), _ptr(coeffs), _ptr(status),
+                                   _stream_ptr(stream))
+        _check(self.lib, st)
+        return coeffs, status
+
+    def render(self, means, scales, quats, opacities, cams, coeffs, images=None, offsets=None,
+               stream=None):
+        """Render coefficients [N,(L+1)^2,C] to images [sum HW, C] float32."""
+        import torch
+        N = int(means.shape[0])
+        nb, C = int(coeffs.shape[1]), int(coeffs.shape[2])
+        sh_deg = int(round(nb ** 0.5)) - 1
+        rows = sum(int(c.width) * int(c.height) for c in cams) if offsets is None else \
+            max(int(o) + int(c.width) * int(c.height) for o, c in zip(offsets, cams))
+        if images is None:
+            images = torch.empty((rows, C), dtype=torch.float32, device=means.device)
+        cam_arr = make_cameras(cams, offsets)
+        st = self.lib.gsc_render(self.handle, _ptr(means), _ptr(scales), _ptr(quats),
+                                 _ptr(opacities), N, cam_arr, len(cams), _ptr(coeffs), C, sh_deg,
+                                 _ptr(images), _stream_ptr(stream))
+        _check(self.lib, st)
+        return images
+
+
+def scene_tensors(scene, device="cuda"):
+    """Device tensors (means, scales, quats, opacities) of a synthetic scene."""
+    import torch
+    f = lambda a: torch.from_numpy(a).to(device).contiguous()
+    return f(scene.means), f(scene.scales), f(scene.quats), f(scene.opacities)

@@ -1,0 +1,135 @@
+"""Host-side checks of the C ABI (no GPU needed): every symbol declared in
+include/gsc.h is exported, and argument validation rejects bad input before
+any device work (GSC_FLAG_VALIDATE_ONLY makes valid calls return without
+touching the GPU)."""
+import ctypes as ct
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2604_17155_amd import gsc, synthetic as syn
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gsc.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(gsc.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return gsc.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:gsc_status|void|const char\*)\s+(gsc_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for required in ["gsc_colorize", "gsc_render", "gsc_ctx_create", "gsc_ctx_destroy",
+                     "gsc_get_stats", "gsc_last_error", "gsc_default_options"]:
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def _vctx(**over):
+    o = gsc.default_options()
+    o.flags = gsc.GSC_FLAG_VALIDATE_ONLY
+    for k, v in over.items():
+        setattr(o, k, v)
+    return gsc.Context(o)
+
+
+FAKE = 4096  # never dereferenced in validate-only mode
+
+
+def _call(ctx, N=10, cams=None, tdtype=0, C=3, sh_deg=0, lam=(1e-4,), means=FAKE, coeffs=FAKE,
+          targets=FAKE):
+    cams = cams if cams is not None else syn.circle_cams(2, 3.0, 16, 16)
+    arr = gsc.make_cameras(cams)
+    lam_a = (ct.c_float * max(1, len(lam)))(*lam)
+    return ctx.lib.gsc_colorize(ctx.handle, means, FAKE, FAKE, FAKE, N, arr, len(cams), targets,
+                                tdtype, C, sh_deg, lam_a, len(lam), coeffs, None, None)
+
+
+def test_validate_only_accepts_valid(lib):
+    ctx = _vctx()
+    assert _call(ctx) == gsc.GSC_OK
+    assert _call(ctx, sh_deg=3, lam=(1e-5, 1e-4, 1e-3, 1e-2)) == gsc.GSC_OK
+    assert _call(ctx, sh_deg=3, lam=tuple([1e-3] * 16)) == gsc.GSC_OK
+    assert _call(ctx, C=64, tdtype=1) == gsc.GSC_OK
+    assert _call(ctx, N=0, means=None, coeffs=None) == gsc.GSC_OK
+    assert _call(ctx, cams=[], targets=None) == gsc.GSC_OK
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(N=-1), "N must be"),
+    (dict(C=0), "C must be"),
+    (dict(C=65), "C must be"),
+    (dict(sh_deg=4), "sh_deg"),
+    (dict(sh_deg=-1), "sh_deg"),
+    (dict(sh_deg=3, lam=(1e-4, 1e-4)), "n_lambda"),
+    (dict(lam=(-1.0,)), "lambda[0]"),
+    (dict(lam=(float("nan"),)), "lambda[0]"),
+    (dict(tdtype=7), "tdtype"),
+    (dict(means=None), "null Gaussian"),
+    (dict(coeffs=None), "coeffs is null"),
+    (dict(targets=None), "targets is null"),
+])
+def test_validate_rejects(lib, kw, needle):
+    ctx = _vctx()
+    st = _call(ctx, **kw)
+    assert st == gsc.GSC_ERR_INVALID_ARG
+    assert needle in lib.gsc_last_error().decode()
+
+
+def test_bad_camera_rejected(lib):
+    ctx = _vctx()
+    cams = syn.circle_cams(2, 3.0, 16, 16)
+    cams[1].width = 0
+    assert _call(ctx, cams=cams) == gsc.GSC_ERR_INVALID_ARG
+    assert "camera 1" in lib.gsc_last_error().decode()
+    cams = syn.circle_cams(2, 3.0, 16, 16)
+    cams[0].fx = -1.0
+    assert _call(ctx, cams=cams) == gsc.GSC_ERR_INVALID_ARG
+
+
+def test_bad_options_rejected(lib):
+    for over in [dict(alpha_max=1.5), dict(t_min=-1.0), dict(znear=0.0), dict(sigma_cut=0.0)]:
+        o = gsc.default_options()
+        for k, v in over.items():
+            setattr(o, k, v)
+        h = ct.c_void_p()
+        st = lib.gsc_ctx_create(ct.byref(h), ct.byref(o))
+        assert st == gsc.GSC_ERR_INVALID_ARG
+
+
+def test_default_options_values(lib):
+    o = gsc.default_options()
+    assert o.alpha_min == np.float32(1 / 255)
+    assert o.alpha_max == np.float32(0.99)
+    assert o.t_min == np.float32(1e-4)
+    assert o.sigma_cut == 3.0 and o.dilation == np.float32(0.3)
+
+
+def test_render_validation(lib):
+    ctx = _vctx()
+    cams = syn.circle_cams(2, 3.0, 16, 16)
+    arr = gsc.make_cameras(cams)
+    st = lib.gsc_render(ctx.handle, FAKE, FAKE, FAKE, FAKE, 10, arr, 2, FAKE, 0, 0, FAKE, None)
+    assert st == gsc.GSC_ERR_INVALID_ARG
+    st = lib.gsc_render(ctx.handle, FAKE, FAKE, FAKE, FAKE, 10, arr, 2, FAKE, 3, 0, FAKE, None)
+    assert st == gsc.GSC_OK
+
+
+def test_binding_has_no_fallback(tmp_path):
+    with pytest.raises(ImportError):
+        gsc.load(str(tmp_path / "missing.so"))

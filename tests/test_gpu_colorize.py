@@ -1,0 +1,168 @@
+"""GPU parity of gsc_colorize / gsc_render against the FP64 oracle.
+
+Inputs are the seeded synthetic workloads at sizes the oracle finishes in
+seconds (several tiles, ragged image edges), plus the full 100k-Gaussian
+relighting workload compared on a random sample of Gaussians.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_17155_amd import synthetic as syn
+from tests import parity, tiny
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gsc_mod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2604_17155_amd import gsc
+    import __graft_entry__
+    __graft_entry__._ensure_built()
+    gsc.load()
+    return gsc
+
+
+@pytest.fixture(scope="module")
+def ctx(gsc_mod):
+    return gsc_mod.Context()
+
+
+def run_gpu(ctx, sc, y, lam=None):
+    import torch
+    from paper_2604_17155_amd import gsc
+    m, s, q, o = gsc.scene_tensors(sc)
+    lam = list(sc.lam if lam is None else lam)
+    coeffs, status = ctx.colorize(m, s, q, o, sc.cams, parity.to_device_targets(y), sc.sh_deg, lam)
+    torch.cuda.synchronize()
+    return coeffs.cpu().numpy(), status.cpu().numpy(), ctx.stats()
+
+
+def _case(ctx, sc, y, label, want=None):
+    print(f"[case] {label}: N={sc.N} cams={len(sc.cams)} L={sc.sh_deg} C={sc.C} dtype={y.dtype}", flush=True)
+    ref = oracle.colorize(sc, y, want=want)
+    c, st, stats = run_gpu(ctx, sc, y)
+    msg = parity.check_colorize(c, st, ref, want=want,
+                                count_gpu=None if want is not None else stats.contributions,
+                                label=label)
+    print(msg, f"| contributions gpu={stats.contributions} oracle={ref['count']} events={ref['events']}",
+          flush=True)
+    return c, st, stats, ref
+
+
+def test_plain_workload(ctx):
+    sc = syn.make_plain()
+    y = oracle.make_targets(sc)
+    _case(ctx, sc, y, "plain 2k L0 C3")
+
+
+def test_relight_reduced(ctx):
+    sc = syn.make_relight(n=20000, n_cams=16, res=256)
+    y = oracle.make_targets(sc)
+    _case(ctx, sc, y, "relight 20k L3 C3 256^2")
+
+
+def test_ragged_sizes_and_channel_chunks(ctx):
+    rng = np.random.Generator(np.random.PCG64(7))
+    sc = syn.make_relight(n=4000, n_cams=6, res=64, sh_deg=2,
+                          lam=rng.uniform(1e-4, 1e-2, 9).astype(np.float32))
+    sc.cams = syn.hemisphere_cams(6, 3.0, 200, 120)
+    sc.C = 5
+    sc.gt = [np.concatenate([sc.gt[0], sc.gt[0][:, :, :2] * 0.5], axis=2)]
+    y = oracle.make_targets(sc)
+    _case(ctx, sc, y, "ragged 200x120 L2 C5 per-coefficient lambda")
+
+
+def test_bf16_targets_l1(ctx):
+    sc = syn.make_relight(n=3000, n_cams=6, res=96, sh_deg=1)
+    sc.cams = syn.hemisphere_cams(6, 3.0, 96, 80)
+    sc.target_dtype = "bf16"
+    y = oracle.make_targets(sc)
+    assert y.dtype == np.uint16
+    _case(ctx, sc, y, "bf16 L1 C3 96x80")
+
+
+def test_feature_channels_bf16(ctx):
+    sc = syn.make_features(n=20000, n_cams=8, width=240, height=136, C=64)
+    y = oracle.make_targets(sc)
+    _case(ctx, sc, y, "features 20k L0 C64 bf16")
+
+
+def test_segment_like_c16(ctx):
+    sc = syn.make_segment_scene(0, n_override=8000, cams_override=10)
+    sc.cams = syn.hemisphere_cams(10, 3.0, 160, 120)
+    y = oracle.make_targets(sc)
+    _case(ctx, sc, y, "segment 8k L0 C16 bf16")
+
+
+def test_degenerate_inputs(ctx, gsc_mod):
+    import torch
+    # no Gaussians
+    sc = tiny.random_scene(1, n=0, n_cams=2, res=16, sh_deg=1, C=2)
+    y = np.zeros((sc.n_pixels, 2), np.float32)
+    m = torch.zeros((0, 3), device="cuda")
+    coeffs, st = ctx.colorize(m, m, torch.zeros((0, 4), device="cuda"), torch.zeros(0, device="cuda"),
+                              sc.cams, parity.to_device_targets(y), 1, [1e-4, 1e-3])
+    assert coeffs.shape == (0, 4, 2)
+    # no cameras: everything unobserved
+    sc = tiny.random_scene(2, n=50, n_cams=0, sh_deg=3, C=3)
+    c, st, _ = run_gpu(ctx, sc, np.zeros((1, 3), np.float32))
+    assert np.all(st == gsc_mod.GSC_G_UNOBSERVED) and np.all(c == 0)
+    # Gaussians behind the camera or outside every view
+    cam = tiny.axis_camera(32, 32, z=-4.0)
+    sc = tiny.scene([[0, 0, 0], [0, 0, -6.0], [8.0, 0, 0], [0.05, 0.02, 0.3]], np.full((4, 3), 0.05),
+                    tiny.identity_quats(4), [0.5, 0.5, 0.5, 0.7], [cam], sh_deg=1, C=1,
+                    lam=[1e-4, 1e-3])
+    y = np.random.default_rng(0).uniform(0, 1, (sc.n_pixels, 1)).astype(np.float32)
+    ref = oracle.colorize(sc, y)
+    c, st, stats = run_gpu(ctx, sc, y)
+    assert list(st & 1) == list(ref["status"] & 1) == [0, 1, 1, 0]
+    parity.check_colorize(c, st, ref, count_gpu=stats.contributions, label="tiny")
+
+
+def test_render_matches_oracle(ctx, gsc_mod):
+    import torch
+    sc = syn.make_relight(n=20000, n_cams=8, res=200)
+    coeffs = sc.gt[0]
+    m, s, q, o = gsc_mod.scene_tensors(sc)
+    img = ctx.render(m, s, q, o, sc.cams, torch.from_numpy(coeffs.astype(np.float32)).cuda())
+    torch.cuda.synchronize()
+    img = img.cpu().numpy()
+    # the oracle renders the float32-rounded coefficients the GPU sees
+    ref32 = oracle.render(sc, coeffs.astype(np.float32).astype(np.float64))
+    err = np.abs(img - ref32).max(axis=1)
+    stats = ctx.stats()
+    ref_full = oracle.colorize(sc, np.zeros((sc.n_pixels, 3), np.float32))
+    # every near-threshold decision changes at most one pixel
+    bad = int((err > 1e-4).sum())
+    print(f"render: max err {err.max():.2e}, pixels >1e-4: {bad}, events {ref_full['events']}", flush=True)
+    assert bad <= ref_full["events"]
+    assert np.median(err) < 1e-6
+    assert abs(int(stats.contributions) - ref_full["count"]) <= ref_full["events"]
+
+
+def test_repeat_and_context_reuse(ctx):
+    sc_big = syn.make_relight(n=20000, n_cams=10, res=160)
+    y_big = oracle.make_targets(sc_big)
+    sc_small = syn.make_plain()
+    y_small = oracle.make_targets(sc_small)
+    a1, _, s1 = run_gpu(ctx, sc_big, y_big)
+    b, _, _ = run_gpu(ctx, sc_small, y_small)
+    a2, _, s2 = run_gpu(ctx, sc_big, y_big)
+    assert s1.contributions == s2.contributions
+    e, obs = parity.rel_errors(a2, dict(coeffs=a1.astype(np.float64), status=np.zeros(len(a1), np.uint8)))
+    assert e.max() < 1e-5  # only the order of float atomics differs
+    ref = oracle.colorize(sc_small, y_small)
+    e, obs = parity.rel_errors(b, ref)
+    assert e[obs & ~parity.flagged(ref)].max() <= parity.TOL_F32
+
+
+def test_relight_full_size(ctx):
+    """The 100k-Gaussian, 50 x 512^2, L=3 workload in the benchmark's launch
+    configuration, compared on every Gaussian."""
+    sc = syn.make_relight()
+    y = oracle.make_targets(sc)
+    _case(ctx, sc, y, "relight full 100k L3 50x512^2")
