@@ -161,6 +161,23 @@ gsc_status gsc_colorize(gsc_ctx* ctx, const float* means, const float* scales, c
                         const float* lambda, int32_t n_lambda, float* coeffs, uint8_t* status,
                         gsc_stream_t stream);
 
+/* Optional extra outputs of gsc_colorize_ex (each device pointer may be NULL). */
+typedef struct {
+    float* view_sums;    /* [n_cams, N, C+1] float32: per view j and Gaussian g the
+                            visibility V_gj = sum_p w (eq. 5) followed by the C
+                            weighted target sums S_gj = sum_p w y_p (numerator of eq. 6) */
+    float* visibility;   /* [N] float32: total visibility w_g = sum_j V_gj (eq. 14) */
+    uint32_t* counts;    /* [N]: accepted (view, pixel) contributions per Gaussian */
+} gsc_extras;
+
+/* gsc_colorize plus the optional outputs in `extras` (host struct, may be NULL). */
+gsc_status gsc_colorize_ex(gsc_ctx* ctx, const float* means, const float* scales,
+                           const float* quats, const float* opacities, int64_t N,
+                           const gsc_camera* cams, int32_t n_cams, const void* targets,
+                           int32_t tdtype, int32_t C, int32_t sh_deg, const float* lambda,
+                           int32_t n_lambda, float* coeffs, uint8_t* status,
+                           const gsc_extras* extras, gsc_stream_t stream);
+
 /*
  * Render (eqs. 1-3): images[p] = sum_g w_gp * c_g^T phi_gj over the same
  * front-to-back blend, background zero.

@@ -139,7 +139,8 @@ def _threads(n):
 def colorize(scene, targets, want: Optional[np.ndarray] = None, opts: Optional[Options] = None,
              lam=None, with_kappa: bool = False, threads=None):
     """Oracle colorization (Algorithm 1, steps 1-6).  Returns a dict with
-    coeffs [N,nb,C], status, A (regularised), B, w, sens, kappa, cnt,
+    coeffs [N,nb,C], status, A (regularised), B, w, flip (bound on the
+    coefficient change near-threshold decisions could cause), kappa, cnt,
     count (accepted contributions) and events."""
     lib = load()
     opts = opts or Options()
@@ -153,7 +154,7 @@ def colorize(scene, targets, want: Optional[np.ndarray] = None, opts: Optional[O
     A = np.zeros((N, nb, nb), np.float64)
     B = np.zeros((N, nb, C), np.float64)
     w = np.zeros(N, np.float64)
-    sens = np.zeros(N, np.float64)
+    flip = np.zeros(N, np.float64)
     kappa = np.zeros(N, np.float64) if with_kappa else None
     cnt = np.zeros(N, np.int64)
     stats = np.zeros(2, np.int64)
@@ -164,11 +165,11 @@ def colorize(scene, targets, want: Optional[np.ndarray] = None, opts: Optional[O
     rc = lib.oc_colorize(_f(m), _f(s), _f(q), _f(o), N, ct.cast(cams, ct.c_void_p),
                          len(scene.cams), _f(t), td, C, scene.sh_deg, _f(lam), lam.size,
                          ct.byref(oo), None if wp is None else _f(wp), _f(coeffs), _f(status),
-                         _f(A), _f(B), _f(w), _f(sens), None if kappa is None else _f(kappa),
+                         _f(A), _f(B), _f(w), _f(flip), None if kappa is None else _f(kappa),
                          _f(cnt), _f(stats), _threads(threads))
     if rc != 0:
         raise ValueError("oracle colorize rejected its arguments")
-    return dict(coeffs=coeffs, status=status, A=A, B=B, w=w, sens=sens, kappa=kappa, cnt=cnt,
+    return dict(coeffs=coeffs, status=status, A=A, B=B, w=w, flip=flip, kappa=kappa, cnt=cnt,
                 count=int(stats[0]), events=int(stats[1]))
 
 

@@ -30,10 +30,12 @@
  *
  * Pixel decisions (footprint q <= sigma_cut^2, alpha >= alpha_min, early stop
  * when T*(1-alpha) < T_min) are discontinuous.  Whenever such a decision falls
- * within a relative margin of its threshold the oracle records an "event" and
- * adds the weight that the other outcome could move to a per-Gaussian
- * sensitivity mass; callers exclude Gaussians whose mass is not negligible
- * from element-wise comparison.
+ * within a relative margin of its threshold the oracle records an "event":
+ * the weight that the other outcome could add, remove or rescale.  After the
+ * solve it bounds, per Gaussian, the coefficient change those events could
+ * cause (first order); callers exclude Gaussians whose bound is not
+ * negligible from element-wise comparison, since there several results are
+ * correct.
  *
  * Build: gcc -O2 -std=c99 -fopenmp -ffp-contract=off -fPIC -shared
  */
@@ -262,6 +264,32 @@ static void push(elist_t* L, entry_t en) {
     L->e[L->n++] = en;
 }
 
+/* A near-threshold decision: the weight `m` of Gaussian g at pixel (x, y)
+ * may appear, vanish or be rescaled in an implementation that decides the
+ * other way within rounding. */
+typedef struct {
+    int32_t g, x, y;
+    double m;
+} event_t;
+
+typedef struct {
+    event_t* e;
+    int64_t n, cap;
+} evlist_t;
+
+static void push_ev(evlist_t* L, int64_t g, int x, int y, double m) {
+    if (!L) return;
+    if (L->n == L->cap) {
+        L->cap = L->cap ? 2 * L->cap : 256;
+        L->e = (event_t*)realloc(L->e, sizeof(event_t) * (size_t)L->cap);
+    }
+    L->e[L->n].g = (int32_t)g;
+    L->e[L->n].x = x;
+    L->e[L->n].y = y;
+    L->e[L->n].m = m;
+    L->n++;
+}
+
 static const proj_t* g_sort_P;
 static int cmp_key(const void* a, const void* b) {
     int64_t ia = *(const int64_t*)a, ib = *(const int64_t*)b;
@@ -302,10 +330,16 @@ typedef struct {
  * Blend one view.  Appends every accepted contribution (pixel, Gaussian,
  * weight) to `out` in front-to-back order per pixel (rows ascending).
  * pix_mask (H*W bytes, may be NULL) restricts the pixels evaluated.
- * sens (N doubles, may be NULL) receives the sensitivity mass.
+ * ev (may be NULL) receives the near-threshold events:
+ *   - footprint or alpha-floor decision within eps of its threshold: the
+ *     Gaussian's own weight there, and every later weight at that pixel
+ *     rescaled by (1 - alpha) (tracked as the pixel's pending alpha mass);
+ *   - stop decision within (eps_t + pending alpha mass) of T_min: the weight
+ *     of the deciding Gaussian and of the next candidates at that pixel,
+ *     which an implementation that decides the other way would (not) accept.
  */
 static void blend_view(const scene_t* sc, const oc_camera* cam, const oc_options* o,
-                       const uint8_t* pix_mask, proj_t* P, elist_t* out, double* sens,
+                       const uint8_t* pix_mask, proj_t* P, elist_t* out, evlist_t* ev,
                        vstats_t* st) {
     int64_t N = sc->N;
     int W = cam->width, H = cam->height;
@@ -333,7 +367,7 @@ static void blend_view(const scene_t* sc, const oc_camera* cam, const oc_options
     double* T = (double*)malloc(sizeof(double) * (size_t)W);
     double* pend = (double*)malloc(sizeof(double) * (size_t)W);
     uint8_t* done = (uint8_t*)malloc((size_t)W);
-    uint8_t* shadow = (uint8_t*)malloc((size_t)W);
+    uint8_t* unsure = (uint8_t*)malloc((size_t)W); /* candidates left to mark after a near stop */
     double s2 = (double)o->sigma_cut * (double)o->sigma_cut;
     double amin = o->alpha_min, amax = o->alpha_max, tmin = o->t_min;
     for (int y = 0; y < H; ++y) {
@@ -348,7 +382,7 @@ static void blend_view(const scene_t* sc, const oc_camera* cam, const oc_options
             T[x] = 1.0;
             pend[x] = 0.0;
             done[x] = mrow ? (mrow[x] ? 0 : 1) : 0;
-            shadow[x] = 0;
+            unsure[x] = 0;
         }
         double py = y + 0.5;
         for (int64_t k = rcount[y]; k < rcount[y + 1]; ++k) {
@@ -357,40 +391,35 @@ static void blend_view(const scene_t* sc, const oc_camera* cam, const oc_options
             int xs = p->x0 > xlo ? p->x0 : xlo, xe = p->x1 < xhi ? p->x1 : xhi;
             double o_g = sc->opac[g];
             for (int x = xs; x <= xe; ++x) {
-                if (done[x] && !shadow[x]) continue;
+                if (done[x] && !unsure[x]) continue;
                 double dx = x + 0.5 - p->u, dy = py - p->v;
                 double q = p->ca * dx * dx + 2.0 * p->cb * dx * dy + p->cc * dy * dy;
                 double G = exp(-0.5 * q);
                 double araw = o_g * G;
                 double alpha = araw < amax ? araw : amax;
-                if (shadow[x]) {
-                    /* The stop just before was within rounding of T_min; a
-                     * renderer that did not stop would accept this one. */
-                    if (q <= s2 * (1.0 + o->eps_q) && araw >= amin * (1.0 - o->eps_a)) {
-                        if (sens) sens[g] += alpha * T[x];
-                        shadow[x] = 0;
-                    }
-                    continue;
+                int may_pass = q <= s2 * (1.0 + o->eps_q) && araw >= amin * (1.0 - o->eps_a);
+                if (unsure[x] && may_pass) {
+                    push_ev(ev, g, x, y, alpha * T[x]);
+                    unsure[x]--;
                 }
-                if (fabs(q - s2) <= o->eps_q * s2) {
+                if (done[x]) continue;
+                if (fabs(q - s2) <= o->eps_q * s2 && araw >= amin * (1.0 - o->eps_a)) {
                     st->events++;
-                    if (araw >= amin * (1.0 - o->eps_a)) {
-                        if (sens) sens[g] += alpha * T[x];
-                        pend[x] += alpha;
-                    }
+                    push_ev(ev, g, x, y, alpha * T[x]);
+                    pend[x] += alpha;
                 }
                 if (q > s2) continue;
                 if (fabs(araw - amin) <= o->eps_a * amin) {
                     st->events++;
-                    if (sens) sens[g] += alpha * T[x];
+                    push_ev(ev, g, x, y, alpha * T[x]);
                     pend[x] += alpha;
                 }
                 if (alpha < amin) continue;
                 double test = T[x] * (1.0 - alpha);
-                if (fabs(test - tmin) <= o->eps_t * tmin) {
+                if (fabs(test - tmin) <= (o->eps_t + pend[x]) * tmin) {
                     st->events++;
-                    if (sens) sens[g] += alpha * T[x];
-                    if (test < tmin) shadow[x] = 1;
+                    push_ev(ev, g, x, y, alpha * T[x]);
+                    unsure[x] = 2;
                 }
                 if (test < tmin) {
                     done[x] = 1;
@@ -403,7 +432,7 @@ static void blend_view(const scene_t* sc, const oc_camera* cam, const oc_options
                 en.alpha = alpha;
                 en.G = G;
                 en.clamped = araw >= amax;
-                if (sens && pend[x] > 0.0) sens[g] += pend[x] * en.w;
+                if (pend[x] > 0.0) push_ev(ev, g, x, y, pend[x] * en.w);
                 push(out, en);
                 st->count++;
                 T[x] = test;
@@ -417,7 +446,7 @@ static void blend_view(const scene_t* sc, const oc_camera* cam, const oc_options
         sentinel.g = -1;
         push(out, sentinel);
     }
-    free(T); free(pend); free(done); free(shadow);
+    free(T); free(pend); free(done); free(unsure);
     free(order); free(tmp); free(rcount); free(rlist); free(fill);
 }
 
@@ -559,15 +588,19 @@ static uint8_t* wanted_mask(const scene_t* sc, const oc_camera* cam, const oc_op
  * Outputs (each may be NULL except coeffs):
  *   coeffs [N][nb][C]; status [N] (bit0 unobserved, bit2 factorisation failed);
  *   A_out [N][nb][nb] regularised normal matrix; B_out [N][nb][C]; w_out [N];
- *   sens_out [N] sensitivity mass; kappa_out [N]; cnt_out [N] accepted
- *   contributions per Gaussian; stats[0] total accepted contributions of the
- *   wanted Gaussians, stats[1] near-threshold events.
+ *   flip_out [N]: first-order bound on ||dc_g||_F from every near-threshold
+ *   event touching g, sum_e m_e ||(A_g + w_g Lambda)^{-1} (phi (y_p - c^T phi)^T
+ *   - Lambda c)||_F (a weight m added at pixel p changes B by m phi y^T and
+ *   A + w Lambda by m (phi phi^T + Lambda));
+ *   kappa_out [N]; cnt_out [N] accepted contributions per Gaussian;
+ *   stats[0] total accepted contributions of the wanted Gaussians,
+ *   stats[1] near-threshold events.
  */
 int oc_colorize(const float* means, const float* scales, const float* quats, const float* opac,
                 int64_t N, const oc_camera* cams, int n_cams, const void* targets, int tdtype,
                 int C, int L, const float* lam, int n_lambda, const oc_options* o,
                 const uint8_t* want, double* coeffs, uint8_t* status, double* A_out, double* B_out,
-                double* w_out, double* sens_out, double* kappa_out, int64_t* cnt_out,
+                double* w_out, double* flip_out, double* kappa_out, int64_t* cnt_out,
                 int64_t* stats, int n_threads) {
     if (check_common(N, n_cams, C, L)) return -1;
     if (!(n_lambda == 1 || n_lambda == L + 1 || n_lambda == (L + 1) * (L + 1))) return -1;
@@ -580,8 +613,9 @@ int oc_colorize(const float* means, const float* scales, const float* quats, con
     int64_t* kidx = (int64_t*)malloc(sizeof(int64_t) * (size_t)(N > 0 ? N : 1));
     int64_t K = 0;
     for (int64_t g = 0; g < N; ++g) kidx[g] = (!want || want[g]) ? K++ : -1;
-    int stride = C + 3; /* V, S[C], sens, count */
+    int stride = C + 2; /* V, S[C], count */
     double* per_view = (double*)calloc((size_t)(K > 0 ? K : 1) * (size_t)(n_cams > 0 ? n_cams : 1) * stride, sizeof(double));
+    evlist_t* evs = (evlist_t*)calloc((size_t)(n_cams > 0 ? n_cams : 1), sizeof(evlist_t));
     int64_t tot_events = 0;
     if (n_threads > 0) {
 #ifdef _OPENMP
@@ -591,24 +625,21 @@ int oc_colorize(const float* means, const float* scales, const float* quats, con
 #pragma omp parallel reduction(+ : tot_events)
     {
         proj_t* P = (proj_t*)malloc(sizeof(proj_t) * (size_t)(N > 0 ? N : 1));
-        double* sens = (double*)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
         elist_t lst = {0, 0, 0};
 #pragma omp for schedule(dynamic, 1)
         for (int j = 0; j < n_cams; ++j) {
             const oc_camera* cam = &cams[j];
             uint8_t* mask = want ? wanted_mask(&sc, cam, o, want, P) : NULL;
-            memset(sens, 0, sizeof(double) * (size_t)N);
             lst.n = 0;
             vstats_t st = {0, 0};
-            blend_view(&sc, cam, o, mask, P, &lst, sens, &st);
+            blend_view(&sc, cam, o, mask, P, &lst, &evs[j], &st);
             tot_events += st.events;
             double* pv = per_view + (size_t)j * (size_t)K * stride;
-            int y = 0;
             /* entries of a row come before that row's sentinel */
             int64_t row_start = 0;
             for (int64_t i = 0; i < lst.n; ++i) {
                 if (lst.e[i].g >= 0) continue;
-                y = lst.e[i].x;
+                int y = lst.e[i].x;
                 for (int64_t r = row_start; r < i; ++r) {
                     const entry_t* en = &lst.e[r];
                     int64_t k = kidx[en->g];
@@ -617,20 +648,39 @@ int oc_colorize(const float* means, const float* scales, const float* quats, con
                     double* a = pv + (size_t)k * stride;
                     a[0] += en->w;
                     for (int c = 0; c < C; ++c) a[1 + c] += en->w * target_at(targets, tdtype, row, C, c);
-                    a[C + 2] += 1.0;
+                    a[C + 1] += 1.0;
                 }
                 row_start = i + 1;
             }
-            for (int64_t g = 0; g < N; ++g)
-                if (kidx[g] >= 0) pv[(size_t)kidx[g] * stride + C + 1] = sens[g];
             free(mask);
         }
-        free(P); free(sens); free(lst.e);
+        free(P); free(lst.e);
+    }
+    /* Events grouped by Gaussian (view order kept). */
+    int64_t* ev_start = (int64_t*)calloc((size_t)(N > 0 ? N : 1) + 1, sizeof(int64_t));
+    for (int j = 0; j < n_cams; ++j)
+        for (int64_t i = 0; i < evs[j].n; ++i)
+            if (kidx[evs[j].e[i].g] >= 0) ev_start[evs[j].e[i].g + 1]++;
+    for (int64_t g = 0; g < N; ++g) ev_start[g + 1] += ev_start[g];
+    int64_t n_ev = ev_start[N > 0 ? N : 0];
+    event_t* ev_all = (event_t*)malloc(sizeof(event_t) * (size_t)(n_ev > 0 ? n_ev : 1));
+    int32_t* ev_view = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_ev > 0 ? n_ev : 1));
+    {
+        int64_t* fillp = (int64_t*)malloc(sizeof(int64_t) * (size_t)(N > 0 ? N : 1));
+        for (int64_t g = 0; g < N; ++g) fillp[g] = ev_start[g];
+        for (int j = 0; j < n_cams; ++j)
+            for (int64_t i = 0; i < evs[j].n; ++i) {
+                const event_t* e = &evs[j].e[i];
+                if (kidx[e->g] < 0) continue;
+                ev_all[fillp[e->g]] = *e;
+                ev_view[fillp[e->g]] = j;
+                fillp[e->g]++;
+            }
+        free(fillp);
     }
     /* Fold over views in view order (eq. 11-13), then regularise and solve. */
     int64_t tot_count = 0;
-    int fail = 0;
-#pragma omp parallel for schedule(static) reduction(+ : tot_count)
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : tot_count)
     for (int64_t g = 0; g < N; ++g) {
         int64_t k = kidx[g];
         if (k < 0) continue;
@@ -638,12 +688,11 @@ int oc_colorize(const float* means, const float* scales, const float* quats, con
         double phi[OC_MAX_NB];
         memset(A, 0, sizeof(A));
         memset(B, 0, sizeof(B));
-        double w = 0.0, sens = 0.0;
+        double w = 0.0;
         int64_t cnt = 0;
         for (int j = 0; j < n_cams; ++j) {
             const double* a = per_view + ((size_t)j * (size_t)K + (size_t)k) * stride;
-            sens += a[C + 1];
-            cnt += (int64_t)a[C + 2];
+            cnt += (int64_t)a[C + 1];
             if (a[0] == 0.0) continue;
             double d[3];
             view_dir(&cams[j], means + 3 * g, d);
@@ -659,10 +708,10 @@ int oc_colorize(const float* means, const float* scales, const float* quats, con
         if (A_out) memcpy(A_out + (size_t)g * nb * nb, A, sizeof(double) * (size_t)(nb * nb));
         if (B_out) memcpy(B_out + (size_t)g * nb * C, B, sizeof(double) * (size_t)(nb * C));
         if (w_out) w_out[g] = w;
-        if (sens_out) sens_out[g] = sens;
         if (cnt_out) cnt_out[g] = cnt;
         uint8_t stt = 0;
         double* cg = coeffs + (size_t)g * nb * C;
+        double flip = 0.0;
         if (w == 0.0) {
             stt |= 1;
             memset(cg, 0, sizeof(double) * (size_t)(nb * C));
@@ -677,13 +726,42 @@ int oc_colorize(const float* means, const float* scales, const float* quats, con
             }
             if (kappa_out) kappa_out[g] = jacobi_cond(nb, A);
         }
+        if (flip_out && ev_start[g + 1] > ev_start[g]) {
+            /* an event on a Gaussian the oracle sees as unobserved: its weight
+             * alone would make it observed; report an unbounded effect */
+            if (w == 0.0 || (stt & 4)) {
+                flip = INFINITY;
+            } else {
+                double M[OC_MAX_NB * 64];
+                for (int64_t i = ev_start[g]; i < ev_start[g + 1]; ++i) {
+                    const event_t* e = &ev_all[i];
+                    const oc_camera* cam = &cams[ev_view[i]];
+                    int64_t row = cam->pixel_offset + (int64_t)e->y * cam->width + e->x;
+                    double d[3];
+                    view_dir(cam, means + 3 * g, d);
+                    sh_basis(L, d, phi);
+                    for (int c = 0; c < C; ++c) {
+                        double gam = 0.0;
+                        for (int r = 0; r < nb; ++r) gam += phi[r] * cg[r * C + c];
+                        double yv = target_at(targets, tdtype, row, C, c);
+                        for (int r = 0; r < nb; ++r) M[r * C + c] = phi[r] * (yv - gam) - lamx[r] * cg[r * C + c];
+                    }
+                    chol_solve(nb, C, Lm, M);
+                    double mn = 0.0;
+                    for (int i2 = 0; i2 < nb * C; ++i2) mn += M[i2] * M[i2];
+                    flip += e->m * sqrt(mn);
+                }
+            }
+        }
+        if (flip_out) flip_out[g] = flip;
         if (status) status[g] = stt;
     }
-    (void)fail;
     if (stats) {
         stats[0] = tot_count;
         stats[1] = tot_events;
     }
+    for (int j = 0; j < n_cams; ++j) free(evs[j].e);
+    free(evs); free(ev_start); free(ev_all); free(ev_view);
     free(per_view); free(kidx); free(sc.cov3);
     return 0;
 }

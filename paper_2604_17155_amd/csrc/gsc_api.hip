@@ -429,11 +429,12 @@ gsc_status gsc_ctx_set_options(gsc_ctx* ctx, const gsc_options* opt) {
     return GSC_OK;
 }
 
-gsc_status gsc_colorize(gsc_ctx* ctx, const float* means, const float* scales, const float* quats,
-                        const float* opacities, int64_t N, const gsc_camera* cams, int32_t n_cams,
-                        const void* targets, int32_t tdtype, int32_t C, int32_t sh_deg,
-                        const float* lambda, int32_t n_lambda, float* coeffs, uint8_t* status,
-                        gsc_stream_t stream) {
+gsc_status gsc_colorize_ex(gsc_ctx* ctx, const float* means, const float* scales,
+                           const float* quats, const float* opacities, int64_t N,
+                           const gsc_camera* cams, int32_t n_cams, const void* targets,
+                           int32_t tdtype, int32_t C, int32_t sh_deg, const float* lambda,
+                           int32_t n_lambda, float* coeffs, uint8_t* status,
+                           const gsc_extras* extras, gsc_stream_t stream) {
     if (!ctx) return fail(GSC_ERR_INVALID_ARG, "null ctx");
     int64_t rows = 0;
     gsc_status st = validate_geometry(means, scales, quats, opacities, N, cams, n_cams, &rows);
@@ -449,26 +450,32 @@ gsc_status gsc_colorize(gsc_ctx* ctx, const float* means, const float* scales, c
     hipStream_t s = (hipStream_t)stream;
     memset(&ctx->stats, 0, sizeof(ctx->stats));
     if (N == 0) return GSC_OK;
-    const int nb = (sh_deg + 1) * (sh_deg + 1);
+    float* x_sums = extras ? extras->view_sums : nullptr;
+    float* x_vis = extras ? extras->visibility : nullptr;
+    uint32_t* x_cnt = extras ? extras->counts : nullptr;
     BlendParams bp = blend_params(ctx->opt);
     if ((st = ensure_common(ctx, scales, quats, N, s)) != GSC_OK) return st;
     std::vector<ViewInfo> all(n_cams);
     for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j]);
-    const bool per_view = sh_deg > 0;
+    const bool per_view = sh_deg > 0 || x_sums != nullptr;
     const uint64_t vs_words = (uint64_t)(per_view ? std::max(n_cams, 1) : 1) * (uint64_t)N * (uint64_t)(C + 1);
     GSC_HIP(ctx->vs.ensure(4 * vs_words));
     launch_fill_u32(ctx->vs.as<uint32_t>(), 0u, vs_words, s);
+    if (x_cnt) launch_fill_u32(x_cnt, 0u, (uint64_t)N, s);
     unsigned long long* d_counter = reinterpret_cast<unsigned long long*>(ctx->misc.p);
     st = for_view_batches(ctx, all, n_cams, means, opacities, N, bp, s,
                           [&](int v0, int nv, const Binned& bn) -> gsc_status {
         StageTimer t(ctx, s, GSC_STAGE_BLEND, (uint32_t)((C + accumulate_chunk(C) - 1) / accumulate_chunk(C)));
         launch_accumulate(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
                           ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(),
-                          targets, tdtype, C, N, v0, per_view, bp, ctx->vs.as<float>(), d_counter, s);
+                          targets, tdtype, C, N, v0, per_view, bp, ctx->vs.as<float>(), d_counter,
+                          x_cnt, s);
         GSC_LAUNCHED("accumulate");
         return GSC_OK;
     });
     if (st != GSC_OK) return st;
+    if (x_sums && n_cams > 0)
+        GSC_HIP(hipMemcpyAsync(x_sums, ctx->vs.p, 4 * vs_words, hipMemcpyDeviceToDevice, s));
     // fold + solve needs the full camera table (only the camera centres are used)
     if (per_view && n_cams > 0) {
         if ((size_t)n_cams > ctx->h_all_cap) {
@@ -482,14 +489,28 @@ gsc_status gsc_colorize(gsc_ctx* ctx, const float* means, const float* scales, c
         GSC_HIP(hipMemcpyAsync(ctx->views_all.p, ctx->h_all, sizeof(ViewInfo) * (size_t)n_cams,
                                hipMemcpyHostToDevice, s));
     }
+    float* dc_scratch = nullptr;
+    if (sh_deg == 0 && per_view) {
+        GSC_HIP(ctx->gamma.ensure(4 * (size_t)N * (size_t)(C + 1)));
+        dc_scratch = ctx->gamma.as<float>();
+    }
     unsigned int* d_ill = reinterpret_cast<unsigned int*>(ctx->misc.as<char>() + 12);
     StageTimer t_solve(ctx, s, GSC_STAGE_SOLVE);
-    launch_fold_solve(ctx->views_all.as<ViewInfo>(), per_view ? n_cams : 0, means, ctx->vs.as<float>(), N, C, sh_deg,
-                      lam, ctx->opt.kappa_max, coeffs, status, d_ill, s);
+    launch_fold_solve(ctx->views_all.as<ViewInfo>(), per_view ? n_cams : 0, means, ctx->vs.as<float>(),
+                      per_view, N, C, sh_deg, lam, ctx->opt.kappa_max, coeffs, status, x_vis,
+                      dc_scratch, d_ill, s);
     GSC_LAUNCHED("fold/solve");
-    (void)nb;
     ctx->stats_pending = true;
     return GSC_OK;
+}
+
+gsc_status gsc_colorize(gsc_ctx* ctx, const float* means, const float* scales, const float* quats,
+                        const float* opacities, int64_t N, const gsc_camera* cams, int32_t n_cams,
+                        const void* targets, int32_t tdtype, int32_t C, int32_t sh_deg,
+                        const float* lambda, int32_t n_lambda, float* coeffs, uint8_t* status,
+                        gsc_stream_t stream) {
+    return gsc_colorize_ex(ctx, means, scales, quats, opacities, N, cams, n_cams, targets, tdtype,
+                           C, sh_deg, lambda, n_lambda, coeffs, status, nullptr, stream);
 }
 
 gsc_status gsc_render(gsc_ctx* ctx, const float* means, const float* scales, const float* quats,

@@ -78,7 +78,7 @@ void launch_accumulate(const ViewInfo* views, int n_views, uint32_t n_tiles, con
                        const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
                        const void* targets, int tdtype, int C, int64_t N, int view_first,
                        bool per_view, BlendParams bp, float* VS, unsigned long long* counter,
-                       hipStream_t s);
+                       uint32_t* gcount, hipStream_t s);
 
 // Per-view colour gamma[v][g][c] = sum_m coeffs[g][m][c] phi_m(dir_gv).
 void launch_view_colors(const ViewInfo* views, int n_views, const float* means,
@@ -91,9 +91,12 @@ void launch_render(const ViewInfo* views, int n_views, uint32_t n_tiles, const u
                    unsigned long long* counter, hipStream_t s);
 
 // Fold the per-view sums into the regularised normal equations and solve.
+// per_view: VS holds [n_views][N][C+1] (else [N][C+1] summed over views).
+// wout (optional): w_g = sum_j V_gj.  dc_scratch: N*(C+1) floats, used when
+// sh_deg == 0 and per_view.
 void launch_fold_solve(const ViewInfo* views, int n_views, const float* means, const float* VS,
-                       int64_t N, int C, int sh_deg, const double* lam_nb /*host, nb*/,
-                       float kappa_max, float* coeffs, uint8_t* status,
-                       unsigned int* ill_count, hipStream_t s);
+                       bool per_view, int64_t N, int C, int sh_deg, const double* lam_nb /*host, nb*/,
+                       float kappa_max, float* coeffs, uint8_t* status, float* wout,
+                       float* dc_scratch, unsigned int* ill_count, hipStream_t s);
 
 }  // namespace gsc

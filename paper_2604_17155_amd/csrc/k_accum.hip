@@ -78,7 +78,7 @@ __global__ __launch_bounds__(256) void k_accumulate(
     const uint32_t* __restrict__ pair_vals, const float4* __restrict__ rec0,
     const float4* __restrict__ rec1, const void* __restrict__ targets, int C, int c_off, int64_t N,
     int view_first, int per_view, BlendParams bp, float* __restrict__ VS,
-    unsigned long long* __restrict__ counter) {
+    unsigned long long* __restrict__ counter, uint32_t* __restrict__ gcount) {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t tile = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (tile >= n_tiles) return;  // whole wave
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(256) void k_accumulate(
             float ss[CC];
 #pragma unroll
             for (int c = 0; c < CC; ++c) ss[c] = 0.0f;
-            bool hit = false;
+            uint32_t nh = 0;
             const float dx = px - u;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -146,10 +146,14 @@ __global__ __launch_bounds__(256) void k_accumulate(
                 sv += w;
 #pragma unroll
                 for (int c = 0; c < CC; ++c) ss[c] += w * y[k][c];
-                ++cnt;
-                hit = true;
+                ++nh;
             }
-            if (__ballot(hit) != 0) {
+            cnt += nh;
+            if (__ballot(nh != 0) != 0) {
+                if (gcount != nullptr && first_chunk) {
+                    const uint32_t tn = wave_sum_u32(nh);
+                    if (lane == 0) atomicAdd(gcount + g, tn);
+                }
                 const float tv = wave_sum(sv);
                 float mine = tv;
 #pragma unroll
@@ -181,17 +185,17 @@ static void launch_acc_cc(const ViewInfo* views, int n_views, uint32_t n_tiles, 
                           const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
                           const void* targets, int tdtype, int C, int64_t N, int view_first,
                           bool per_view, BlendParams bp, float* VS, unsigned long long* counter,
-                          hipStream_t s) {
+                          uint32_t* gcount, hipStream_t s) {
     dim3 grid((n_tiles + 3) / 4), block(256);
     for (int c_off = 0; c_off < C; c_off += CC) {
         if (tdtype == GSC_BF16)
             hipLaunchKernelGGL((k_accumulate<CC, true>), grid, block, 0, s, views, n_views, n_tiles,
                                ranges, pair_vals, rec0, rec1, targets, C, c_off, N, view_first,
-                               (int)per_view, bp, VS, counter);
+                               (int)per_view, bp, VS, counter, gcount);
         else
             hipLaunchKernelGGL((k_accumulate<CC, false>), grid, block, 0, s, views, n_views, n_tiles,
                                ranges, pair_vals, rec0, rec1, targets, C, c_off, N, view_first,
-                               (int)per_view, bp, VS, counter);
+                               (int)per_view, bp, VS, counter, gcount);
     }
 }
 
@@ -201,26 +205,26 @@ void launch_accumulate(const ViewInfo* views, int n_views, uint32_t n_tiles, con
                        const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
                        const void* targets, int tdtype, int C, int64_t N, int view_first,
                        bool per_view, BlendParams bp, float* VS, unsigned long long* counter,
-                       hipStream_t s) {
+                       uint32_t* gcount, hipStream_t s) {
     if (n_tiles == 0) return;
     if (C == 1)
         launch_acc_cc<1>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, targets, tdtype, C,
-                         N, view_first, per_view, bp, VS, counter, s);
+                         N, view_first, per_view, bp, VS, counter, gcount, s);
     else if (C == 2)
         launch_acc_cc<2>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, targets, tdtype, C,
-                         N, view_first, per_view, bp, VS, counter, s);
+                         N, view_first, per_view, bp, VS, counter, gcount, s);
     else if (C == 3)
         launch_acc_cc<3>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, targets, tdtype, C,
-                         N, view_first, per_view, bp, VS, counter, s);
+                         N, view_first, per_view, bp, VS, counter, gcount, s);
     else if (C <= 4)
         launch_acc_cc<4>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, targets, tdtype, C,
-                         N, view_first, per_view, bp, VS, counter, s);
+                         N, view_first, per_view, bp, VS, counter, gcount, s);
     else if (C <= 8)
         launch_acc_cc<8>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, targets, tdtype, C,
-                         N, view_first, per_view, bp, VS, counter, s);
+                         N, view_first, per_view, bp, VS, counter, gcount, s);
     else
         launch_acc_cc<16>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, targets, tdtype, C,
-                          N, view_first, per_view, bp, VS, counter, s);
+                          N, view_first, per_view, bp, VS, counter, gcount, s);
 }
 
 // ---- render ----------------------------------------------------------------

@@ -22,11 +22,13 @@ struct LamNB {
 constexpr double kY0 = 0.28209479177387814;
 
 __global__ void k_solve_dc(const float* __restrict__ VS, int64_t N, int C, double lam0,
-                           float* __restrict__ coeffs, uint8_t* __restrict__ status) {
+                           float* __restrict__ coeffs, uint8_t* __restrict__ status,
+                           float* __restrict__ wout) {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= N) return;
     const float* s = VS + g * (int64_t)(C + 1);
     double w = s[0];
+    if (wout) wout[g] = (float)w;
     float* out = coeffs + g * C;
     if (w == 0.0) {
         for (int c = 0; c < C; ++c) out[c] = 0.0f;
@@ -38,6 +40,17 @@ __global__ void k_solve_dc(const float* __restrict__ VS, int64_t N, int C, doubl
     if (status) status[g] = 0;
 }
 
+// Sum the per-view slots of every Gaussian over the views (L = 0 with
+// per-view sums kept for the caller).
+__global__ void k_sum_views(const float* __restrict__ VS, int n_views, int64_t N, int stride,
+                            float* __restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N * stride) return;
+    float a = 0.0f;
+    for (int v = 0; v < n_views; ++v) a += VS[(int64_t)v * N * stride + i];
+    out[i] = a;
+}
+
 template <int L>
 __global__ __launch_bounds__(64) void k_fold_solve(const ViewInfo* __restrict__ views, int n_views,
                                                    const float* __restrict__ means,
@@ -45,6 +58,7 @@ __global__ __launch_bounds__(64) void k_fold_solve(const ViewInfo* __restrict__ 
                                                    LamNB lam, float kappa_max,
                                                    float* __restrict__ coeffs,
                                                    uint8_t* __restrict__ status,
+                                                   float* __restrict__ wout,
                                                    unsigned int* __restrict__ ill_count) {
     constexpr int NB = (L + 1) * (L + 1);
     constexpr int RPL = (NB + 3) / 4;  // rows per lane
@@ -175,6 +189,7 @@ __global__ __launch_bounds__(64) void k_fold_solve(const ViewInfo* __restrict__ 
         __syncthreads();
     }
     if (valid && r == 0) {
+        if (wout) wout[g] = (float)wsum;
         uint8_t st = 0;
         if (wsum == 0.0) {
             st = GSC_G_UNOBSERVED;
@@ -198,12 +213,20 @@ __global__ __launch_bounds__(64) void k_fold_solve(const ViewInfo* __restrict__ 
 }
 
 void launch_fold_solve(const ViewInfo* views, int n_views, const float* means, const float* VS,
-                       int64_t N, int C, int sh_deg, const double* lam_nb, float kappa_max,
-                       float* coeffs, uint8_t* status, unsigned int* ill_count, hipStream_t s) {
+                       bool per_view, int64_t N, int C, int sh_deg, const double* lam_nb,
+                       float kappa_max, float* coeffs, uint8_t* status, float* wout,
+                       float* dc_scratch, unsigned int* ill_count, hipStream_t s) {
     if (N <= 0) return;
     if (sh_deg == 0) {
-        hipLaunchKernelGGL(k_solve_dc, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, VS, N, C,
-                           lam_nb[0], coeffs, status);
+        const float* src = VS;
+        if (per_view) {
+            int64_t n = N * (int64_t)(C + 1);
+            hipLaunchKernelGGL(k_sum_views, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, VS,
+                               n_views, N, C + 1, dc_scratch);
+            src = dc_scratch;
+        }
+        hipLaunchKernelGGL(k_solve_dc, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, src, N, C,
+                           lam_nb[0], coeffs, status, wout);
         return;
     }
     LamNB lam;
@@ -212,9 +235,9 @@ void launch_fold_solve(const ViewInfo* views, int n_views, const float* means, c
     for (int i = 0; i < nb; ++i) lam.v[i] = lam_nb[i];
     dim3 grid((unsigned)((N + 15) / 16)), block(64);
     switch (sh_deg) {
-        case 1: hipLaunchKernelGGL(k_fold_solve<1>, grid, block, 0, s, views, n_views, means, VS, N, C, lam, kappa_max, coeffs, status, ill_count); break;
-        case 2: hipLaunchKernelGGL(k_fold_solve<2>, grid, block, 0, s, views, n_views, means, VS, N, C, lam, kappa_max, coeffs, status, ill_count); break;
-        default: hipLaunchKernelGGL(k_fold_solve<3>, grid, block, 0, s, views, n_views, means, VS, N, C, lam, kappa_max, coeffs, status, ill_count); break;
+        case 1: hipLaunchKernelGGL(k_fold_solve<1>, grid, block, 0, s, views, n_views, means, VS, N, C, lam, kappa_max, coeffs, status, wout, ill_count); break;
+        case 2: hipLaunchKernelGGL(k_fold_solve<2>, grid, block, 0, s, views, n_views, means, VS, N, C, lam, kappa_max, coeffs, status, wout, ill_count); break;
+        default: hipLaunchKernelGGL(k_fold_solve<3>, grid, block, 0, s, views, n_views, means, VS, N, C, lam, kappa_max, coeffs, status, wout, ill_count); break;
     }
 }
 

@@ -55,6 +55,10 @@ class GscStats(ct.Structure):
         return {n: float(self.stage_ms[i]) for i, n in enumerate(STAGES[:7])}
 
 
+class GscExtras(ct.Structure):
+    _fields_ = [("view_sums", ct.c_void_p), ("visibility", ct.c_void_p), ("counts", ct.c_void_p)]
+
+
 class GscError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"gsc error {status}: {msg}")
@@ -84,6 +88,9 @@ def load(path: Optional[str] = None):
     lib.gsc_ctx_set_options.restype = ct.c_int
     lib.gsc_colorize.argtypes = [P, P, P, P, P, i64, P, i32, P, i32, i32, i32, P, i32, P, P, P]
     lib.gsc_colorize.restype = ct.c_int
+    lib.gsc_colorize_ex.argtypes = [P, P, P, P, P, i64, P, i32, P, i32, i32, i32, P, i32, P, P,
+                                    ct.POINTER(GscExtras), P]
+    lib.gsc_colorize_ex.restype = ct.c_int
     lib.gsc_render.argtypes = [P, P, P, P, P, i64, P, i32, P, i32, i32, P, P]
     lib.gsc_render.restype = ct.c_int
     lib.gsc_get_stats.argtypes = [P, ct.POINTER(GscStats)]
@@ -173,9 +180,14 @@ class Context:
         return out
 
     def colorize(self, means, scales, quats, opacities, cams, targets, sh_deg: int, lam,
-                 coeffs=None, status=None, offsets=None, stream=None, with_status: bool = True):
+                 coeffs=None, status=None, offsets=None, stream=None, with_status: bool = True,
+                 extras=None):
         """Solve the per-Gaussian regularised normal equations.  Returns
-        (coeffs [N,(L+1)^2,C] float32, status [N] uint8 or None)."""
+        (coeffs [N,(L+1)^2,C] float32, status [N] uint8 or None).
+
+        extras: optional set of names among {"view_sums", "visibility",
+        "counts"}; when given, a third element is returned: a dict of device
+        tensors (view_sums [n_cams,N,C+1], visibility [N], counts [N] int32)."""
         import torch
         N = int(means.shape[0])
         C = int(targets.shape[1]) if targets.dim() == 2 else 1
@@ -193,11 +205,25 @@ class Context:
             status = torch.empty((N,), dtype=torch.uint8, device=dev)
         lam_a = (ct.c_float * len(lam))(*[float(v) for v in lam])
         cam_arr = make_cameras(cams, offsets)
-        st = self.lib.gsc_colorize(self.handle, _ptr(means), _ptr(scales), _ptr(quats),
-                                   _ptr(opacities), N, cam_arr, len(cams), _ptr(targets), td, C,
-                                   sh_deg, lam_a, len(lam), _ptr(coeffs), _ptr(status),
-                                   _stream_ptr(stream))
+        xd = None
+        xs = None
+        if extras:
+            xd = {}
+            if "view_sums" in extras:
+                xd["view_sums"] = torch.zeros((len(cams), N, C + 1), dtype=torch.float32, device=dev)
+            if "visibility" in extras:
+                xd["visibility"] = torch.zeros((N,), dtype=torch.float32, device=dev)
+            if "counts" in extras:
+                xd["counts"] = torch.zeros((N,), dtype=torch.int32, device=dev)
+            xs = GscExtras(_ptr(xd.get("view_sums")), _ptr(xd.get("visibility")),
+                           _ptr(xd.get("counts")))
+        st = self.lib.gsc_colorize_ex(self.handle, _ptr(means), _ptr(scales), _ptr(quats),
+                                      _ptr(opacities), N, cam_arr, len(cams), _ptr(targets), td, C,
+                                      sh_deg, lam_a, len(lam), _ptr(coeffs), _ptr(status),
+                                      None if xs is None else ct.byref(xs), _stream_ptr(stream))
         _check(self.lib, st)
+        if xd is not None:
+            return coeffs, status, xd
         return coeffs, status
 
     def render(self, means, scales, quats, opacities, cams, coeffs, images=None, offsets=None,
