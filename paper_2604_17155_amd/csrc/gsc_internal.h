@@ -31,8 +31,9 @@ struct BlendParams {
     float alpha_min, alpha_max, t_min, cut2, dilation, znear;
 };
 
-// Splat record of one (view, Gaussian) item, two float4:
-//   r0 = (u, v, opacity, depth key)   r1 = (conic_xx, conic_xy, conic_yy, bits of g)
+// Splat record of one (view, Gaussian) item i = v * N + g, two float4:
+//   r0 = (u_hi, v_hi, u_lo, v_lo)   projected mean as FP32 hi/lo pairs
+//   r1 = (conic_xx, conic_xy, conic_yy, opacity)
 struct Rect {
     uint16_t tx0, ty0, tx1, ty1;
 };

@@ -108,6 +108,7 @@ __global__ __launch_bounds__(256) void k_accumulate(
     uint32_t cnt = 0;
     bool wave_live = __ballot(live[0] || live[1] || live[2] || live[3]) != 0;
     const int64_t vs_view = per_view ? (int64_t)(view_first + vloc) * N : 0;
+    const int64_t item_base = (int64_t)vloc * N;  // item = vloc * N + g
     const bool first_chunk = c_off == 0;
 
     for (uint32_t b = rg.x; b < rg.y && wave_live; b += 64) {
@@ -119,19 +120,21 @@ __global__ __launch_bounds__(256) void k_accumulate(
             a1 = rec1[it];
         }
         for (uint32_t j = 0; j < nb; ++j) {
-            const float u = bcast(a0.x, j), v = bcast(a0.y, j), o = bcast(a0.z, j);
+            const float uh = bcast(a0.x, j), vh = bcast(a0.y, j);
+            const float ul = bcast(a0.z, j), vl = bcast(a0.w, j);
             const float ca = bcast(a1.x, j), cb = bcast(a1.y, j), cc = bcast(a1.z, j);
-            const int g = (int)bcast_u(__float_as_uint(a1.w), j);
+            const float o = bcast(a1.w, j);
+            const int64_t g = (int64_t)bcast_u(it, j) - item_base;
             float sv = 0.0f;
             float ss[CC];
 #pragma unroll
             for (int c = 0; c < CC; ++c) ss[c] = 0.0f;
             uint32_t nh = 0;
-            const float dx = px - u;
+            const float dx = (px - uh) - ul;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (!live[k]) continue;
-                const float dy = (float)(iy0 + 4 * k) + 0.5f - v;
+                const float dy = ((float)(iy0 + 4 * k) + 0.5f - vh) - vl;
                 const float q = ca * dx * dx + 2.0f * cb * dx * dy + cc * dy * dy;
                 if (q > bp.cut2) continue;
                 const float al = fminf(bp.alpha_max, o * __expf(-0.5f * q));
@@ -307,18 +310,20 @@ __global__ __launch_bounds__(256) void k_render(
             a1 = rec1[it];
         }
         for (uint32_t j = 0; j < nb; ++j) {
-            const float u = bcast(a0.x, j), v = bcast(a0.y, j), o = bcast(a0.z, j);
+            const float uh = bcast(a0.x, j), vh = bcast(a0.y, j);
+            const float ul = bcast(a0.z, j), vl = bcast(a0.w, j);
             const float ca = bcast(a1.x, j), cb = bcast(a1.y, j), cc = bcast(a1.z, j);
+            const float o = bcast(a1.w, j);
             const uint32_t item = bcast_u(it, j);
             float col[CC];
             const float* gp = gamma + (int64_t)item * C + c_off;
 #pragma unroll
             for (int c = 0; c < CC; ++c) col[c] = (c_off + c < C) ? gp[c] : 0.0f;
-            const float dx = px - u;
+            const float dx = (px - uh) - ul;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (!live[k]) continue;
-                const float dy = (float)(iy0 + 4 * k) + 0.5f - v;
+                const float dy = ((float)(iy0 + 4 * k) + 0.5f - vh) - vl;
                 const float q = ca * dx * dx + 2.0f * cb * dx * dy + cc * dy * dy;
                 if (q > bp.cut2) continue;
                 const float al = fminf(bp.alpha_max, o * __expf(-0.5f * q));

@@ -37,6 +37,11 @@ void launch_cov3d(const float* scales, const float* quats, float* cov, int64_t N
 }
 
 // a2: one thread per (view, Gaussian).  Item index i = v * N + g.
+// The projection is evaluated in FP64 (a few dozen operations per item) and
+// the pixel position is stored as an FP32 hi/lo pair, so that the blend can
+// form pixel offsets d = (p - u_hi) - u_lo exactly to one FP32 ulp of d; a
+// single FP32 coordinate of a 512-pixel image is only good to ~3e-5 pixel,
+// enough to move alpha by ~1e-4 relative at the footprint edge.
 __global__ __launch_bounds__(256) void k_project(const ViewInfo* __restrict__ views,
                                                  const float* __restrict__ means,
                                                  const float* __restrict__ cov,
@@ -57,46 +62,53 @@ __global__ __launch_bounds__(256) void k_project(const ViewInfo* __restrict__ vi
     float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
     Rect rc = {0, 0, 0, 0};
     if (key > bp.znear) {
-        float tx = __fmaf_rn(V.R[0], mx, __fmaf_rn(V.R[1], my, __fmaf_rn(V.R[2], mz, V.t[0])));
-        float ty = __fmaf_rn(V.R[3], mx, __fmaf_rn(V.R[4], my, __fmaf_rn(V.R[5], mz, V.t[1])));
-        float iz = 1.0f / key;
-        float j00 = V.fx * iz, j02 = -V.fx * tx * iz * iz;
-        float j11 = V.fy * iz, j12 = -V.fy * ty * iz * iz;
+        double R[9];
+        for (int k = 0; k < 9; ++k) R[k] = V.R[k];
+        const double dmx = mx, dmy = my, dmz = mz;
+        const double tx = R[0] * dmx + R[1] * dmy + R[2] * dmz + (double)V.t[0];
+        const double ty = R[3] * dmx + R[4] * dmy + R[5] * dmz + (double)V.t[1];
+        const double tz = R[6] * dmx + R[7] * dmy + R[8] * dmz + (double)V.t[2];
+        const double iz = 1.0 / tz;
+        const double fx = V.fx, fy = V.fy;
+        const double j00 = fx * iz, j02 = -fx * tx * iz * iz;
+        const double j11 = fy * iz, j12 = -fy * ty * iz * iz;
         const float* c = cov + 6 * g;
-        float S[3][3] = {{c[0], c[1], c[2]}, {c[1], c[3], c[4]}, {c[2], c[4], c[5]}};
+        const double S[3][3] = {{c[0], c[1], c[2]}, {c[1], c[3], c[4]}, {c[2], c[4], c[5]}};
         // Sc = W S W^T
-        float M[3][3];
+        double M[3][3];
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b)
-                M[a][b] = V.R[3 * a] * S[0][b] + V.R[3 * a + 1] * S[1][b] + V.R[3 * a + 2] * S[2][b];
-        float Sc[3][3];
+                M[a][b] = R[3 * a] * S[0][b] + R[3 * a + 1] * S[1][b] + R[3 * a + 2] * S[2][b];
+        double Sc[3][3];
         for (int a = 0; a < 3; ++a)
             for (int b = a; b < 3; ++b)
-                Sc[a][b] = M[a][0] * V.R[3 * b] + M[a][1] * V.R[3 * b + 1] + M[a][2] * V.R[3 * b + 2];
-        float sxx = j00 * j00 * Sc[0][0] + 2.f * j00 * j02 * Sc[0][2] + j02 * j02 * Sc[2][2] + bp.dilation;
-        float sxy = j00 * j11 * Sc[0][1] + j00 * j12 * Sc[0][2] + j02 * j11 * Sc[1][2] + j02 * j12 * Sc[2][2];
-        float syy = j11 * j11 * Sc[1][1] + 2.f * j11 * j12 * Sc[1][2] + j12 * j12 * Sc[2][2] + bp.dilation;
-        float det = sxx * syy - sxy * sxy;
-        float u = V.fx * tx * iz + V.cx;
-        float vv = V.fy * ty * iz + V.cy;
-        float cut = sqrtf(bp.cut2);
-        float rx = cut * sqrtf(sxx), ry = cut * sqrtf(syy);
+                Sc[a][b] = M[a][0] * R[3 * b] + M[a][1] * R[3 * b + 1] + M[a][2] * R[3 * b + 2];
+        const double dil = bp.dilation;
+        const double sxx = j00 * j00 * Sc[0][0] + 2.0 * j00 * j02 * Sc[0][2] + j02 * j02 * Sc[2][2] + dil;
+        const double sxy = j00 * j11 * Sc[0][1] + j00 * j12 * Sc[0][2] + j02 * j11 * Sc[1][2] + j02 * j12 * Sc[2][2];
+        const double syy = j11 * j11 * Sc[1][1] + 2.0 * j11 * j12 * Sc[1][2] + j12 * j12 * Sc[2][2] + dil;
+        const double det = sxx * syy - sxy * sxy;
+        const double u = fx * tx * iz + (double)V.cx;
+        const double vv = fy * ty * iz + (double)V.cy;
+        const double cut = sqrt((double)bp.cut2);
+        const double rx = cut * sqrt(sxx), ry = cut * sqrt(syy);
         // pixel centres x+0.5 with |x+0.5-u| <= rx, widened by half a pixel
-        float fx0 = fmaxf(floorf(u - rx - 1.0f), 0.0f);
-        float fx1 = fminf(ceilf(u + rx), (float)(V.width - 1));
-        float fy0 = fmaxf(floorf(vv - ry - 1.0f), 0.0f);
-        float fy1 = fminf(ceilf(vv + ry), (float)(V.height - 1));
-        if (det > 0.0f && fx0 <= fx1 && fy0 <= fy1) {
-            float inv = 1.0f / det;
-            int x0 = (int)fx0, x1 = (int)fx1, y0 = (int)fy0, y1 = (int)fy1;
+        const double fx0 = fmax(floor(u - rx - 1.0), 0.0);
+        const double fx1 = fmin(ceil(u + rx), (double)(V.width - 1));
+        const double fy0 = fmax(floor(vv - ry - 1.0), 0.0);
+        const double fy1 = fmin(ceil(vv + ry), (double)(V.height - 1));
+        if (det > 0.0 && fx0 <= fx1 && fy0 <= fy1) {
+            const double inv = 1.0 / det;
+            const int x0 = (int)fx0, x1 = (int)fx1, y0 = (int)fy0, y1 = (int)fy1;
             rc.tx0 = (uint16_t)(x0 >> kTileShift);
             rc.tx1 = (uint16_t)(x1 >> kTileShift);
             rc.ty0 = (uint16_t)(y0 >> kTileShift);
             rc.ty1 = (uint16_t)(y1 >> kTileShift);
             cnt = (uint32_t)(rc.tx1 - rc.tx0 + 1) * (uint32_t)(rc.ty1 - rc.ty0 + 1);
             kb = __float_as_uint(key);
-            r0 = make_float4(u, vv, opac[g], key);
-            r1 = make_float4(syy * inv, -sxy * inv, sxx * inv, __int_as_float((int)g));
+            const float uh = (float)u, vh = (float)vv;
+            r0 = make_float4(uh, vh, (float)(u - (double)uh), (float)(vv - (double)vh));
+            r1 = make_float4((float)(syy * inv), (float)(-sxy * inv), (float)(sxx * inv), opac[g]);
         }
     }
     keys[i] = kb;
