@@ -78,7 +78,7 @@ struct gsc_ctx {
     gsc_options opt;
     // device scratch
     DevBuf views, views_all, cov, keys, vals, keys_alt, vals_alt, counts, counts_sorted, offsets, rec0, rec1,
-        rects, sort_scratch, pkeys, pvals, pkeys_alt, pvals_alt, ranges, vs, gamma, misc;
+        sort_scratch, pkeys, pvals, pkeys_alt, pvals_alt, ranges, vs, gamma, misc;
     // host staging
     ViewInfo* h_views = nullptr;  // staging of one batch's table
     size_t h_views_cap = 0;
@@ -94,7 +94,7 @@ struct gsc_ctx {
     std::vector<Mark> marks;
     ~gsc_ctx() {
         DevBuf* all[] = {&views, &views_all, &cov, &keys, &vals, &keys_alt, &vals_alt, &counts, &counts_sorted,
-                         &offsets, &rec0, &rec1, &rects, &sort_scratch, &pkeys, &pvals, &pkeys_alt,
+                         &offsets, &rec0, &rec1, &sort_scratch, &pkeys, &pvals, &pkeys_alt,
                          &pvals_alt, &ranges, &vs, &gamma, &misc};
         for (DevBuf* b : all) b->release();
         if (h_views) (void)hipHostFree(h_views);
@@ -160,7 +160,7 @@ gsc_status validate_geometry(const float* means, const float* scales, const floa
                              const float* opac, int64_t N, const gsc_camera* cams, int32_t n_cams,
                              int64_t* rows_needed) {
     if (N < 0) return fail(GSC_ERR_INVALID_ARG, "N must be >= 0 (got %lld)", (long long)N);
-    if (N > (int64_t)0x7fffffff) return fail(GSC_ERR_INVALID_ARG, "N must be < 2^31");
+    if (N > (int64_t)kItemMask) return fail(GSC_ERR_UNSUPPORTED, "N must be < 2^26 (got %lld)", (long long)N);
     if (N > 0 && (!means || !scales || !quats || !opac))
         return fail(GSC_ERR_INVALID_ARG, "null Gaussian array with N > 0");
     if (n_cams < 0) return fail(GSC_ERR_INVALID_ARG, "n_cams must be >= 0");
@@ -282,14 +282,13 @@ gsc_status bin_views(gsc_ctx* ctx, const std::vector<ViewInfo>& all, int v0, int
     GSC_HIP(ctx->offsets.ensure(4 * items + 4));
     GSC_HIP(ctx->rec0.ensure(16 * items + 16));
     GSC_HIP(ctx->rec1.ensure(16 * items + 16));
-    GSC_HIP(ctx->rects.ensure(sizeof(Rect) * items + 16));
     GSC_HIP(ctx->ranges.ensure(sizeof(uint2) * (tiles + 1)));
     const ViewInfo* dviews = ctx->views.as<ViewInfo>();
     {
         StageTimer t(ctx, s, GSC_STAGE_PROJECT);
         launch_project(dviews, nv, means, ctx->cov.as<float>(), opac, N, bp, ctx->keys.as<uint32_t>(),
                        ctx->vals.as<uint32_t>(), ctx->counts.as<uint32_t>(), ctx->rec0.as<float4>(),
-                       ctx->rec1.as<float4>(), ctx->rects.as<Rect>(), s);
+                       ctx->rec1.as<float4>(), s);
         GSC_LAUNCHED("project");
     }
     size_t scr = std::max(radix_scratch_words(ni), scan_scratch_words(ni));
@@ -330,8 +329,9 @@ gsc_status bin_views(gsc_ctx* ctx, const std::vector<ViewInfo>& all, int v0, int
     {
         StageTimer t(ctx, s, GSC_STAGE_EMIT);
         launch_emit(dviews, ctx->vals.as<uint32_t>(), ctx->offsets.as<uint32_t>(),
-                    ctx->counts.as<uint32_t>(), ctx->rects.as<Rect>(), ni, N,
-                    ctx->pkeys.as<uint32_t>(), ctx->pvals.as<uint32_t>(), s);
+                    ctx->counts.as<uint32_t>(), ctx->rec0.as<float4>(),
+                    ctx->rec1.as<float4>(), bp, ni, N, (uint32_t)tiles, ctx->pkeys.as<uint32_t>(),
+                    ctx->pvals.as<uint32_t>(), s);
         GSC_LAUNCHED("emit");
     }
     size_t pscr = radix_scratch_words((uint32_t)pairs);
@@ -339,11 +339,12 @@ gsc_status bin_views(gsc_ctx* ctx, const std::vector<ViewInfo>& all, int v0, int
     {
         StageTimer t(ctx, s, GSC_STAGE_TILE_SORT);
         radix_sort(ctx->pkeys.as<uint32_t>(), ctx->pvals.as<uint32_t>(), ctx->pkeys_alt.as<uint32_t>(),
-                   ctx->pvals_alt.as<uint32_t>(), (uint32_t)pairs, bits_for(tiles),
+                   ctx->pvals_alt.as<uint32_t>(), (uint32_t)pairs, bits_for(tiles + 1),
                    ctx->sort_scratch.as<uint32_t>(), s);
         GSC_LAUNCHED("tile sort");
         launch_fill_u32(ctx->ranges.as<uint32_t>(), 0u, (uint64_t)2 * tiles, s);
-        launch_tile_ranges(ctx->pkeys.as<uint32_t>(), (uint32_t)pairs, ctx->ranges.as<uint2>(), s);
+        launch_tile_ranges(ctx->pkeys.as<uint32_t>(), (uint32_t)pairs, (uint32_t)tiles,
+                           ctx->ranges.as<uint2>(), s);
         GSC_LAUNCHED("tile ranges");
     }
     return GSC_OK;

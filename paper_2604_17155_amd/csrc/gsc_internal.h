@@ -33,29 +33,37 @@ struct BlendParams {
 
 // Splat record of one (view, Gaussian) item i = v * N + g, two float4:
 //   r0 = (u_hi, v_hi, u_lo, v_lo)   projected mean as FP32 hi/lo pairs
-//   r1 = (conic_xx, conic_xy, conic_yy, opacity)
-struct Rect {
-    uint16_t tx0, ty0, tx1, ty1;
-};
+//   r1 = (K*cxx, 2*K*cxy, K*cyy, opacity) with the conic (cxx, cxy, cyy) =
+//        Sigma_2D^{-1} pre-scaled by K = -log2(e)/2, so that
+//        q2 = K*q = r1.x dx^2 + r1.y dx dy + r1.z dy^2 and exp(-q/2) = exp2(q2).
+constexpr double kExp2Scale = -0.72134752044448170368;  // -0.5 * log2(e)
+
+// Tile pairs carry the item index in the low 26 bits and, in the top 4 bits,
+// which 16x4 pixel bands (rows 4k..4k+3 of the tile) the footprint reaches.
+constexpr uint32_t kItemBits = 26;
+constexpr uint32_t kItemMask = (1u << kItemBits) - 1u;
 
 // ---- kernels launched from gsc_api.hip ----------------------------------
 void launch_cov3d(const float* scales, const float* quats, float* cov, int64_t N, hipStream_t s);
 
 void launch_project(const ViewInfo* views, int n_views, const float* means, const float* cov,
                     const float* opac, int64_t N, BlendParams bp, uint32_t* keys, uint32_t* vals,
-                    uint32_t* counts, float4* rec0, float4* rec1, Rect* rects, hipStream_t s);
+                    uint32_t* counts, float4* rec0, float4* rec1, hipStream_t s);
 
 void launch_gather_counts(const uint32_t* sorted_vals, const uint32_t* counts, uint32_t* out,
                           uint32_t n, hipStream_t s);
 
 void launch_emit(const ViewInfo* views, const uint32_t* sorted_vals, const uint32_t* offsets,
-                 const uint32_t* counts, const Rect* rects, uint32_t n_items, int64_t N,
-                 uint32_t* pair_keys, uint32_t* pair_vals, hipStream_t s);
+                 const uint32_t* counts, const float4* rec0, const float4* rec1, BlendParams bp,
+                 uint32_t n_items, int64_t N, uint32_t n_tiles, uint32_t* pair_keys,
+                 uint32_t* pair_vals, hipStream_t s);
 
 // Sum of n uint32 counts into *out (u64, must be zeroed).
 void launch_sum_u64(const uint32_t* counts, uint32_t n, unsigned long long* out, hipStream_t s);
 
-void launch_tile_ranges(const uint32_t* sorted_keys, uint32_t n_pairs, uint2* ranges, hipStream_t s);
+// Pairs whose key is >= n_tiles are ignored.
+void launch_tile_ranges(const uint32_t* sorted_keys, uint32_t n_pairs, uint32_t n_tiles,
+                        uint2* ranges, hipStream_t s);
 
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 

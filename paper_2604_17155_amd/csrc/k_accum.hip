@@ -33,6 +33,23 @@ __device__ __forceinline__ float wave_sum(float v) {
     return (r0 + r1) + (r2 + r3);
 }
 
+// Sums four per-lane values over the wave at once.  Quad exchanges split the
+// four values between lanes (lane bit 0 picks the pair, bit 1 the member),
+// rotations sum the four quads of a row, and two shuffles sum the rows.
+// On return lane L < 4 holds the total of value 2*(L&1) + (L>>1).
+__device__ __forceinline__ float wave_sum4_transposed(float v0, float v1, float v2, float v3,
+                                                      uint32_t lane) {
+    const bool b0 = lane & 1u, b1 = lane & 2u;
+    const float x0 = (b0 ? v2 : v0) + dpp_mov<0xB1>(b0 ? v0 : v2);
+    const float x1 = (b0 ? v3 : v1) + dpp_mov<0xB1>(b0 ? v1 : v3);
+    float y = (b1 ? x1 : x0) + dpp_mov<0x4E>(b1 ? x0 : x1);
+    y += dpp_mov<0x124>(y);  // row_ror:4
+    y += dpp_mov<0x128>(y);  // row_ror:8
+    y += __shfl_xor(y, 16, 64);
+    y += __shfl_xor(y, 32, 64);
+    return y;
+}
+
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
     v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
     v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
@@ -111,45 +128,52 @@ __global__ __launch_bounds__(256) void k_accumulate(
     const int64_t item_base = (int64_t)vloc * N;  // item = vloc * N + g
     const bool first_chunk = c_off == 0;
 
+    const float qlim = (float)(kExp2Scale * (double)bp.cut2);  // q <= cut2  <=>  q2 >= qlim
+    float pyk[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pyk[k] = (float)(iy0 + 4 * k) + 0.5f;
+
     for (uint32_t b = rg.x; b < rg.y && wave_live; b += 64) {
         const uint32_t nb = min(64u, rg.y - b);
-        const uint32_t it = lane < nb ? pair_vals[b + lane] : 0u;
-        float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0;
-        if (lane < nb) {
-            a0 = rec0[it];
-            a1 = rec1[it];
-        }
+        const uint32_t pv = lane < nb ? pair_vals[b + lane] : 0u;
+        // records are fetched with uniform addresses one entry ahead
+        uint32_t pn = bcast_u(pv, 0);
+        float4 n0 = rec0[pn & kItemMask], n1 = rec1[pn & kItemMask];
         for (uint32_t j = 0; j < nb; ++j) {
-            const float uh = bcast(a0.x, j), vh = bcast(a0.y, j);
-            const float ul = bcast(a0.z, j), vl = bcast(a0.w, j);
-            const float ca = bcast(a1.x, j), cb = bcast(a1.y, j), cc = bcast(a1.z, j);
-            const float o = bcast(a1.w, j);
-            const int64_t g = (int64_t)bcast_u(it, j) - item_base;
+            const uint32_t pc = pn;
+            const float4 c0 = n0, c1 = n1;
+            if (j + 1 < nb) {
+                pn = bcast_u(pv, j + 1);
+                n0 = rec0[pn & kItemMask];
+                n1 = rec1[pn & kItemMask];
+            }
+            const uint32_t bands = pc >> kItemBits;
+            const int64_t g = (int64_t)(pc & kItemMask) - item_base;
+            const float dx = (px - c0.x) - c0.z;
+            const float a0 = c1.x * dx * dx;
+            const float b0 = c1.y * dx;
             float sv = 0.0f;
             float ss[CC];
 #pragma unroll
             for (int c = 0; c < CC; ++c) ss[c] = 0.0f;
             uint32_t nh = 0;
-            const float dx = (px - uh) - ul;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                if (!live[k]) continue;
-                const float dy = ((float)(iy0 + 4 * k) + 0.5f - vh) - vl;
-                const float q = ca * dx * dx + 2.0f * cb * dx * dy + cc * dy * dy;
-                if (q > bp.cut2) continue;
-                const float al = fminf(bp.alpha_max, o * __expf(-0.5f * q));
-                if (al < bp.alpha_min) continue;
-                const float test = T[k] * (1.0f - al);
-                if (test < bp.t_min) {
-                    live[k] = false;
-                    continue;
-                }
-                const float w = al * T[k];
-                T[k] = test;
+                if (!((bands >> k) & 1u)) continue;  // uniform: footprint misses band k
+                const float dy = (pyk[k] - c0.y) - c0.w;
+                const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
+                const float al = fminf(bp.alpha_max, c1.w * __builtin_amdgcn_exp2f(q2));
+                const float test = fmaf(-T[k], al, T[k]);
+                const bool cand = live[k] && q2 >= qlim && al >= bp.alpha_min;
+                const bool stop = cand && test < bp.t_min;
+                const bool take = cand && !stop;
+                live[k] = live[k] && !stop;
+                const float w = take ? al * T[k] : 0.0f;
+                T[k] = take ? test : T[k];
                 sv += w;
 #pragma unroll
-                for (int c = 0; c < CC; ++c) ss[c] += w * y[k][c];
-                ++nh;
+                for (int c = 0; c < CC; ++c) ss[c] = fmaf(w, y[k][c], ss[c]);
+                nh += take ? 1u : 0u;
             }
             cnt += nh;
             if (__ballot(nh != 0) != 0) {
@@ -157,18 +181,32 @@ __global__ __launch_bounds__(256) void k_accumulate(
                     const uint32_t tn = wave_sum_u32(nh);
                     if (lane == 0) atomicAdd(gcount + g, tn);
                 }
-                const float tv = wave_sum(sv);
-                float mine = tv;
-#pragma unroll
-                for (int c = 0; c < CC; ++c) {
-                    const float ts = wave_sum(ss[c]);
-                    if (lane == (uint32_t)(c + 1)) mine = ts;
-                }
                 float* slot = VS + (vs_view + g) * (int64_t)stride;
-                if (lane == 0) {
-                    if (first_chunk) unsafeAtomicAdd(slot, mine);
-                } else if (lane <= (uint32_t)CC && c_off + (int)lane - 1 < C) {
-                    unsafeAtomicAdd(slot + c_off + lane, mine);
+                if constexpr (CC <= 3) {
+                    const float t = wave_sum4_transposed(sv, CC > 0 ? ss[0] : 0.0f,
+                                                         CC > 1 ? ss[CC > 1 ? 1 : 0] : 0.0f,
+                                                         CC > 2 ? ss[CC > 2 ? 2 : 0] : 0.0f, lane);
+                    if (lane < 4u) {
+                        const int idx = (int)(2u * (lane & 1u) + (lane >> 1));
+                        if (idx == 0) {
+                            if (first_chunk) unsafeAtomicAdd(slot, t);
+                        } else if (idx <= CC && c_off + idx - 1 < C) {
+                            unsafeAtomicAdd(slot + c_off + idx, t);
+                        }
+                    }
+                } else {
+                    const float tv = wave_sum(sv);
+                    float mine = tv;
+#pragma unroll
+                    for (int c = 0; c < CC; ++c) {
+                        const float ts = wave_sum(ss[c]);
+                        if (lane == (uint32_t)(c + 1)) mine = ts;
+                    }
+                    if (lane == 0) {
+                        if (first_chunk) unsafeAtomicAdd(slot, mine);
+                    } else if (lane <= (uint32_t)CC && c_off + (int)lane - 1 < C) {
+                        unsafeAtomicAdd(slot + c_off + lane, mine);
+                    }
                 }
             }
             if (__ballot(live[0] || live[1] || live[2] || live[3]) == 0) {
@@ -301,34 +339,42 @@ __global__ __launch_bounds__(256) void k_render(
     const uint2 rg = ranges[tile];
     uint32_t cnt = 0;
     bool wave_live = __ballot(live[0] || live[1] || live[2] || live[3]) != 0;
+    const float qlim = (float)(kExp2Scale * (double)bp.cut2);
+    float pyk[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pyk[k] = (float)(iy0 + 4 * k) + 0.5f;
     for (uint32_t b = rg.x; b < rg.y && wave_live; b += 64) {
         const uint32_t nb = min(64u, rg.y - b);
-        const uint32_t it = lane < nb ? pair_vals[b + lane] : 0u;
-        float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0;
-        if (lane < nb) {
-            a0 = rec0[it];
-            a1 = rec1[it];
-        }
+        const uint32_t pv = lane < nb ? pair_vals[b + lane] : 0u;
+        uint32_t pn = bcast_u(pv, 0);
+        float4 n0 = rec0[pn & kItemMask], n1 = rec1[pn & kItemMask];
         for (uint32_t j = 0; j < nb; ++j) {
-            const float uh = bcast(a0.x, j), vh = bcast(a0.y, j);
-            const float ul = bcast(a0.z, j), vl = bcast(a0.w, j);
-            const float ca = bcast(a1.x, j), cb = bcast(a1.y, j), cc = bcast(a1.z, j);
-            const float o = bcast(a1.w, j);
-            const uint32_t item = bcast_u(it, j);
+            const uint32_t pc = pn;
+            const float4 c0 = n0, c1 = n1;
+            if (j + 1 < nb) {
+                pn = bcast_u(pv, j + 1);
+                n0 = rec0[pn & kItemMask];
+                n1 = rec1[pn & kItemMask];
+            }
+            const uint32_t bands = pc >> kItemBits;
+            const uint32_t item = pc & kItemMask;
             float col[CC];
             const float* gp = gamma + (int64_t)item * C + c_off;
 #pragma unroll
             for (int c = 0; c < CC; ++c) col[c] = (c_off + c < C) ? gp[c] : 0.0f;
-            const float dx = (px - uh) - ul;
+            const float dx = (px - c0.x) - c0.z;
+            const float a0 = c1.x * dx * dx;
+            const float b0 = c1.y * dx;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
+                if (!((bands >> k) & 1u)) continue;
                 if (!live[k]) continue;
-                const float dy = ((float)(iy0 + 4 * k) + 0.5f - vh) - vl;
-                const float q = ca * dx * dx + 2.0f * cb * dx * dy + cc * dy * dy;
-                if (q > bp.cut2) continue;
-                const float al = fminf(bp.alpha_max, o * __expf(-0.5f * q));
+                const float dy = (pyk[k] - c0.y) - c0.w;
+                const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
+                if (q2 < qlim) continue;
+                const float al = fminf(bp.alpha_max, c1.w * __builtin_amdgcn_exp2f(q2));
                 if (al < bp.alpha_min) continue;
-                const float test = T[k] * (1.0f - al);
+                const float test = fmaf(-T[k], al, T[k]);
                 if (test < bp.t_min) {
                     live[k] = false;
                     continue;
@@ -336,7 +382,7 @@ __global__ __launch_bounds__(256) void k_render(
                 const float w = al * T[k];
                 T[k] = test;
 #pragma unroll
-                for (int c = 0; c < CC; ++c) img[k][c] += w * col[c];
+                for (int c = 0; c < CC; ++c) img[k][c] = fmaf(w, col[c], img[k][c]);
                 ++cnt;
             }
             if (__ballot(live[0] || live[1] || live[2] || live[3]) == 0) {

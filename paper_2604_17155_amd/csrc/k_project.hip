@@ -36,12 +36,79 @@ void launch_cov3d(const float* scales, const float* quats, float* cov, int64_t N
                        cov, N);
 }
 
+// Largest q at which a pixel can still pass both the footprint test
+// (q <= cut2) and the alpha floor (o exp(-q/2) >= alpha_min), with a margin
+// covering the FP32 evaluation in the blend; negative when nothing passes.
+__device__ inline float reach_q(float o, const BlendParams& bp) {
+    if (!(o >= bp.alpha_min)) return -1.0f;
+    const float qa = 2.0f * __logf(o / bp.alpha_min);
+    const float q = fminf(bp.cut2, qa);
+    return q * (1.0f + 1e-4f) + 1e-3f;
+}
+
+// Walks the pixel rows of a record's footprint {q <= qmax} and calls
+// visit(ty, lo, hi) once per tile row, where [lo[k], hi[k]] is the range of
+// tile columns holding a pixel centre of band k (rows 4k..4k+3 of the tile)
+// inside the footprint (lo > hi: none).  Row intervals are widened by 0.01
+// pixel, so the walk is conservative with respect to the blend's FP32 test.
+// Used identically for counting and emitting.
+template <typename Visit>
+__device__ inline void footprint_rows(float4 r0, float4 r1, float qmax, int W, int H,
+                                      Visit&& visit) {
+    constexpr float kInvK = (float)(1.0 / kExp2Scale);
+    const float a = r1.x * kInvK, b = 0.5f * r1.y * kInvK, c = r1.z * kInvK;
+    const float det = a * c - b * b;
+    if (!(a > 0.0f && det > 0.0f && qmax > 0.0f)) return;
+    const float ia = 1.0f / a, cq = det * ia;  // q = a (dx + b dy / a)^2 + cq dy^2
+    const float ry = sqrtf(qmax / cq) * 1.0001f + 0.01f;
+    const float vc = r0.y - 0.5f + r0.w;  // row index whose centre is the mean
+    const float fy0 = fmaxf(ceilf(vc - ry), 0.0f);
+    const float fy1 = fminf(floorf(vc + ry), (float)(H - 1));
+    if (!(fy0 <= fy1)) return;
+    const int y0 = (int)fy0, y1 = (int)fy1;
+    int lo[4], hi[4];
+    int cur = y0 >> kTileShift;
+    for (int k = 0; k < 4; ++k) { lo[k] = 1 << 30; hi[k] = -1; }
+    for (int y = y0; y <= y1; ++y) {
+        const int ty = y >> kTileShift;
+        if (ty != cur) {
+            visit(cur, lo, hi);
+            for (int k = 0; k < 4; ++k) { lo[k] = 1 << 30; hi[k] = -1; }
+            cur = ty;
+        }
+        const float dy = ((float)y + 0.5f - r0.y) - r0.w;
+        const float disc = qmax - cq * dy * dy;
+        if (disc < 0.0f) continue;
+        const float half = sqrtf(disc * ia) * 1.0001f + 0.01f;
+        const float mid = (r0.x - 0.5f + r0.z) - b * dy * ia;  // column index of the centre
+        const float xf = fmaxf(ceilf(mid - half), 0.0f);
+        const float xl = fminf(floorf(mid + half), (float)(W - 1));
+        if (!(xf <= xl)) continue;
+        const int band = (y >> 2) & 3;
+        const int t0 = (int)xf >> kTileShift, t1 = (int)xl >> kTileShift;
+        for (int k = 0; k < 4; ++k)
+            if (k == band) {
+                lo[k] = min(lo[k], t0);
+                hi[k] = max(hi[k], t1);
+            }
+    }
+    visit(cur, lo, hi);
+}
+
+__device__ inline uint32_t band_bits(const int* lo, const int* hi, int t) {
+    uint32_t m = 0;
+    for (int k = 0; k < 4; ++k) m |= (lo[k] <= t && t <= hi[k]) ? (1u << k) : 0u;
+    return m;
+}
+
 // a2: one thread per (view, Gaussian).  Item index i = v * N + g.
 // The projection is evaluated in FP64 (a few dozen operations per item) and
 // the pixel position is stored as an FP32 hi/lo pair, so that the blend can
 // form pixel offsets d = (p - u_hi) - u_lo exactly to one FP32 ulp of d; a
 // single FP32 coordinate of a 512-pixel image is only good to ~3e-5 pixel,
 // enough to move alpha by ~1e-4 relative at the footprint edge.
+// A tile is binned only if its pixel centres come within the footprint
+// reach (3-sigma ellipse, shrunk by the alpha floor for faint splats).
 __global__ __launch_bounds__(256) void k_project(const ViewInfo* __restrict__ views,
                                                  const float* __restrict__ means,
                                                  const float* __restrict__ cov,
@@ -49,8 +116,7 @@ __global__ __launch_bounds__(256) void k_project(const ViewInfo* __restrict__ vi
                                                  BlendParams bp, uint32_t* __restrict__ keys,
                                                  uint32_t* __restrict__ vals,
                                                  uint32_t* __restrict__ counts,
-                                                 float4* __restrict__ rec0, float4* __restrict__ rec1,
-                                                 Rect* __restrict__ rects) {
+                                                 float4* __restrict__ rec0, float4* __restrict__ rec1) {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int v = blockIdx.y;
     if (g >= N) return;
@@ -60,8 +126,9 @@ __global__ __launch_bounds__(256) void k_project(const ViewInfo* __restrict__ vi
     float key = __fmaf_rn(V.R[6], mx, __fmaf_rn(V.R[7], my, __fmaf_rn(V.R[8], mz, V.t[2])));
     uint32_t kb = 0xFFFFFFFFu, cnt = 0;
     float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
-    Rect rc = {0, 0, 0, 0};
-    if (key > bp.znear) {
+    const float og = opac[g];
+    const float qmax = reach_q(og, bp);
+    if (key > bp.znear && qmax > 0.0f) {
         double R[9];
         for (int k = 0; k < 9; ++k) R[k] = V.R[k];
         const double dmx = mx, dmy = my, dmz = mz;
@@ -90,25 +157,21 @@ __global__ __launch_bounds__(256) void k_project(const ViewInfo* __restrict__ vi
         const double det = sxx * syy - sxy * sxy;
         const double u = fx * tx * iz + (double)V.cx;
         const double vv = fy * ty * iz + (double)V.cy;
-        const double cut = sqrt((double)bp.cut2);
-        const double rx = cut * sqrt(sxx), ry = cut * sqrt(syy);
-        // pixel centres x+0.5 with |x+0.5-u| <= rx, widened by half a pixel
-        const double fx0 = fmax(floor(u - rx - 1.0), 0.0);
-        const double fx1 = fmin(ceil(u + rx), (double)(V.width - 1));
-        const double fy0 = fmax(floor(vv - ry - 1.0), 0.0);
-        const double fy1 = fmin(ceil(vv + ry), (double)(V.height - 1));
-        if (det > 0.0 && fx0 <= fx1 && fy0 <= fy1) {
+        if (det > 0.0 && isfinite(u) && isfinite(vv)) {
             const double inv = 1.0 / det;
-            const int x0 = (int)fx0, x1 = (int)fx1, y0 = (int)fy0, y1 = (int)fy1;
-            rc.tx0 = (uint16_t)(x0 >> kTileShift);
-            rc.tx1 = (uint16_t)(x1 >> kTileShift);
-            rc.ty0 = (uint16_t)(y0 >> kTileShift);
-            rc.ty1 = (uint16_t)(y1 >> kTileShift);
-            cnt = (uint32_t)(rc.tx1 - rc.tx0 + 1) * (uint32_t)(rc.ty1 - rc.ty0 + 1);
-            kb = __float_as_uint(key);
             const float uh = (float)u, vh = (float)vv;
             r0 = make_float4(uh, vh, (float)(u - (double)uh), (float)(vv - (double)vh));
-            r1 = make_float4((float)(syy * inv), (float)(-sxy * inv), (float)(sxx * inv), opac[g]);
+            r1 = make_float4((float)(kExp2Scale * syy * inv), (float)(-2.0 * kExp2Scale * sxy * inv),
+                             (float)(kExp2Scale * sxx * inv), og);
+            footprint_rows(r0, r1, qmax, V.width, V.height, [&](int, const int* lo, const int* hi) {
+                int t0 = 1 << 30, t1 = -1;
+                for (int k = 0; k < 4; ++k) {
+                    t0 = min(t0, lo[k]);
+                    t1 = max(t1, hi[k]);
+                }
+                for (int t = t0; t <= t1; ++t) cnt += band_bits(lo, hi, t) != 0u;
+            });
+            if (cnt > 0) kb = __float_as_uint(key);
         }
     }
     keys[i] = kb;
@@ -116,15 +179,14 @@ __global__ __launch_bounds__(256) void k_project(const ViewInfo* __restrict__ vi
     counts[i] = cnt;
     rec0[i] = r0;
     rec1[i] = r1;
-    rects[i] = rc;
 }
 
 void launch_project(const ViewInfo* views, int n_views, const float* means, const float* cov,
                     const float* opac, int64_t N, BlendParams bp, uint32_t* keys, uint32_t* vals,
-                    uint32_t* counts, float4* rec0, float4* rec1, Rect* rects, hipStream_t s) {
+                    uint32_t* counts, float4* rec0, float4* rec1, hipStream_t s) {
     if (N <= 0 || n_views <= 0) return;
     hipLaunchKernelGGL(k_project, dim3((unsigned)((N + 255) / 256), (unsigned)n_views), dim3(256), 0,
-                       s, views, means, cov, opac, N, bp, keys, vals, counts, rec0, rec1, rects);
+                       s, views, means, cov, opac, N, bp, keys, vals, counts, rec0, rec1);
 }
 
 __global__ void k_gather_counts(const uint32_t* __restrict__ sorted_vals,
@@ -145,7 +207,8 @@ void launch_gather_counts(const uint32_t* sorted_vals, const uint32_t* counts, u
 // id then yields every tile's list in front-to-back order.
 __global__ void k_emit(const ViewInfo* __restrict__ views, const uint32_t* __restrict__ sorted_vals,
                        const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ counts,
-                       const Rect* __restrict__ rects, uint32_t n_items, int64_t N,
+                       const float4* __restrict__ rec0, const float4* __restrict__ rec1,
+                       BlendParams bp, uint32_t n_items, int64_t N, uint32_t sentinel,
                        uint32_t* __restrict__ pair_keys, uint32_t* __restrict__ pair_vals) {
     uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_items) return;
@@ -153,22 +216,40 @@ __global__ void k_emit(const ViewInfo* __restrict__ views, const uint32_t* __res
     if (counts[i] == 0) return;
     int v = (int)((int64_t)i / N);
     const ViewInfo& V = views[v];
-    Rect rc = rects[i];
+    const float4 r0 = rec0[i], r1 = rec1[i];
     uint32_t off = offsets[k];
-    for (uint32_t ty = rc.ty0; ty <= rc.ty1; ++ty)
-        for (uint32_t tx = rc.tx0; tx <= rc.tx1; ++tx) {
-            pair_keys[off] = V.tile_base + ty * (uint32_t)V.tiles_x + tx;
-            pair_vals[off] = i;
+    const uint32_t end = off + counts[i];
+    footprint_rows(r0, r1, reach_q(r1.w, bp), V.width, V.height,
+                   [&](int ty, const int* lo, const int* hi) {
+        int t0 = 1 << 30, t1 = -1;
+        for (int b = 0; b < 4; ++b) {
+            t0 = min(t0, lo[b]);
+            t1 = max(t1, hi[b]);
+        }
+        for (int t = t0; t <= t1; ++t) {
+            const uint32_t m = band_bits(lo, hi, t);
+            if (m == 0u || off >= end) continue;
+            pair_keys[off] = V.tile_base + (uint32_t)ty * (uint32_t)V.tiles_x + (uint32_t)t;
+            pair_vals[off] = i | (m << kItemBits);
             ++off;
         }
+    });
+    // The walk above and the one that counted are the same code on the same
+    // record; should they ever disagree, unused slots get a tile id past the
+    // last tile, which sorts last and is ignored by the range kernel.
+    for (; off < end; ++off) {
+        pair_keys[off] = sentinel;
+        pair_vals[off] = 0u;
+    }
 }
 
 void launch_emit(const ViewInfo* views, const uint32_t* sorted_vals, const uint32_t* offsets,
-                 const uint32_t* counts, const Rect* rects, uint32_t n_items, int64_t N,
-                 uint32_t* pair_keys, uint32_t* pair_vals, hipStream_t s) {
+                 const uint32_t* counts, const float4* rec0, const float4* rec1, BlendParams bp,
+                 uint32_t n_items, int64_t N, uint32_t n_tiles, uint32_t* pair_keys,
+                 uint32_t* pair_vals, hipStream_t s) {
     if (n_items == 0) return;
     hipLaunchKernelGGL(k_emit, dim3((n_items + 255) / 256), dim3(256), 0, s, views, sorted_vals,
-                       offsets, counts, rects, n_items, N, pair_keys, pair_vals);
+                       offsets, counts, rec0, rec1, bp, n_items, N, n_tiles, pair_keys, pair_vals);
 }
 
 __global__ __launch_bounds__(256) void k_sum_u64(const uint32_t* __restrict__ counts, uint32_t n,
@@ -191,18 +272,21 @@ void launch_sum_u64(const uint32_t* counts, uint32_t n, unsigned long long* out,
     hipLaunchKernelGGL(k_sum_u64, dim3(blocks), dim3(256), 0, s, counts, n, out);
 }
 
-__global__ void k_tile_ranges(const uint32_t* __restrict__ keys, uint32_t n, uint2* __restrict__ ranges) {
+__global__ void k_tile_ranges(const uint32_t* __restrict__ keys, uint32_t n, uint32_t n_tiles,
+                              uint2* __restrict__ ranges) {
     uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     uint32_t t = keys[k];
+    if (t >= n_tiles) return;
     if (k == 0 || keys[k - 1] != t) ranges[t].x = k;
     if (k == n - 1 || keys[k + 1] != t) ranges[t].y = k + 1;
 }
 
-void launch_tile_ranges(const uint32_t* sorted_keys, uint32_t n_pairs, uint2* ranges, hipStream_t s) {
+void launch_tile_ranges(const uint32_t* sorted_keys, uint32_t n_pairs, uint32_t n_tiles,
+                        uint2* ranges, hipStream_t s) {
     if (n_pairs == 0) return;
     hipLaunchKernelGGL(k_tile_ranges, dim3((n_pairs + 255) / 256), dim3(256), 0, s, sorted_keys,
-                       n_pairs, ranges);
+                       n_pairs, n_tiles, ranges);
 }
 
 }  // namespace gsc

@@ -51,6 +51,31 @@ __global__ void k_sum_views(const float* __restrict__ VS, int n_views, int64_t N
     out[i] = a;
 }
 
+constexpr int kStageFloats = 2048;  // LDS staging of per-view sums (8 KB)
+constexpr int kMaxStageViews = 64;
+
+// Broadcast lane `o` of each quad to the whole quad (DPP quad_perm [o,o,o,o]).
+template <int O>
+__device__ __forceinline__ double quad_bcast(double x) {
+    constexpr int ctrl = O | (O << 2) | (O << 4) | (O << 6);
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), ctrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), ctrl, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double quad_bcast_rt(double x, int o) {
+    switch (o) {
+        case 0: return quad_bcast<0>(x);
+        case 1: return quad_bcast<1>(x);
+        case 2: return quad_bcast<2>(x);
+        default: return quad_bcast<3>(x);
+    }
+}
+
+// Fold + solve for L >= 1.  Four lanes per Gaussian; lane r owns the rows
+// i = 4k + r of A (lower triangle, FP64) and of B (four channels at a time).
+// The Cholesky factor is formed in registers (column j broadcast within the
+// quad), then L and B go through LDS so each lane can substitute one channel.
 template <int L>
 __global__ __launch_bounds__(64) void k_fold_solve(const ViewInfo* __restrict__ views, int n_views,
                                                    const float* __restrict__ means,
@@ -62,129 +87,182 @@ __global__ __launch_bounds__(64) void k_fold_solve(const ViewInfo* __restrict__ 
                                                    unsigned int* __restrict__ ill_count) {
     constexpr int NB = (L + 1) * (L + 1);
     constexpr int RPL = (NB + 3) / 4;  // rows per lane
-    constexpr int LDA = NB + 1;
-    __shared__ double As[16][NB * LDA];
+    constexpr int NL = NB * (NB + 1) / 2;  // packed lower triangle
+    __shared__ float stage[kStageFloats];
+    __shared__ float cen[kMaxStageViews][3];
+    __shared__ double Ls[16][NL];
     __shared__ double Bs[16][NB * 4];
-    __shared__ double Dg[16][NB];
     const int lane = threadIdx.x, q = lane >> 2, r = lane & 3;
-    const int64_t g = (int64_t)blockIdx.x * 16 + q;
+    const int64_t g0 = (int64_t)blockIdx.x * 16;
+    const int64_t g = g0 + q;
     const bool valid = g < N;
     const int stride = C + 1;
-    double* A = As[q];
-    double* Bq = Bs[q];
-    double mx = 0, my = 0, mz = 0;
+    const int per_view = 16 * stride;
+    const int vch = max(1, min(kMaxStageViews, kStageFloats / per_view));
+    const int64_t lim = N * (int64_t)stride;
+    float mx = 0.f, my = 0.f, mz = 0.f;
     if (valid) {
         mx = means[3 * g];
         my = means[3 * g + 1];
         mz = means[3 * g + 2];
     }
+    double sel[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) sel[e] = r == e ? 1.0 : 0.0;
+    double accA[RPL][NB];  // accA[k][j]: row 4k+r, column j <= 4k+r
+    double dinv[NB];       // reciprocal diagonal of the factor
     bool failed = false;
     double wsum = 0.0;
     for (int c0 = 0; c0 < C; c0 += 4) {
         const bool firstc = c0 == 0;
-        double accA[RPL][NB];
         double accB[RPL][4];
 #pragma unroll
         for (int k = 0; k < RPL; ++k) {
 #pragma unroll
-            for (int j = 0; j < NB && j < 4 * k + 4; ++j) accA[k][j] = 0.0;
+            for (int j = 0; j < NB; ++j)
+                if (firstc) accA[k][j] = 0.0;
 #pragma unroll
             for (int c = 0; c < 4; ++c) accB[k][c] = 0.0;
         }
         double wv = 0.0;
-        if (valid) {
-            for (int v = 0; v < n_views; ++v) {
-                const float* slot = VS + ((int64_t)v * N + g) * stride;
+        for (int v0 = 0; v0 < n_views; v0 += vch) {
+            const int nv = min(vch, n_views - v0);
+            __syncthreads();
+            // coalesced staging: for each view the block's 16 slots are
+            // contiguous; eight independent loads per lane are in flight
+            const int total = nv * per_view;
+            for (int base = lane; base < total; base += 64 * 8) {
+                float tmp[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int idx = base + 64 * u;
+                    const int vv = idx / per_view, rr = idx - vv * per_view;
+                    const int64_t gi = g0 * stride + rr;
+                    tmp[u] = (idx < total && gi < lim) ? VS[(int64_t)(v0 + vv) * lim + gi] : 0.0f;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (base + 64 * u < total) stage[base + 64 * u] = tmp[u];
+            }
+            for (int idx = lane; idx < nv; idx += 64) {
+                cen[idx][0] = (float)views[v0 + idx].centre[0];
+                cen[idx][1] = (float)views[v0 + idx].centre[1];
+                cen[idx][2] = (float)views[v0 + idx].centre[2];
+            }
+            __syncthreads();
+            if (!valid) continue;
+#pragma unroll 1
+            for (int vv = 0; vv < nv; ++vv) {
+                const float* slot = stage + vv * per_view + q * stride;
                 const float Vf = slot[0];
                 if (Vf == 0.0f) continue;
-                const double Vd = Vf;
-                const ViewInfo& Vi = views[v];
-                double dx = mx - Vi.centre[0], dy = my - Vi.centre[1], dz = mz - Vi.centre[2];
-                double inv = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+                const float dx = mx - cen[vv][0], dy = my - cen[vv][1], dz = mz - cen[vv][2];
+                const float inv = rsqrtf(dx * dx + dy * dy + dz * dz);
+                float phf[NB];
+                sh_eval<float, L>(dx * inv, dy * inv, dz * inv, phf);
                 double phi[NB];
-                sh_eval<double, L>(dx * inv, dy * inv, dz * inv, phi);
+#pragma unroll
+                for (int j = 0; j < NB; ++j) phi[j] = (double)phf[j];
+                const double Vd = Vf;
                 double S[4];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) S[c] = (c0 + c < C) ? (double)slot[1 + c0 + c] : 0.0;
 #pragma unroll
                 for (int k = 0; k < RPL; ++k) {
-                    double own = phi[4 * k];
-                    if (4 * k + 1 < NB && r == 1) own = phi[4 * k + 1 < NB ? 4 * k + 1 : 0];
-                    if (4 * k + 2 < NB && r == 2) own = phi[4 * k + 2 < NB ? 4 * k + 2 : 0];
-                    if (4 * k + 3 < NB && r == 3) own = phi[4 * k + 3 < NB ? 4 * k + 3 : 0];
+                    // phi of this lane's row 4k + r, selected arithmetically
+                    double own = sel[0] * phi[4 * k];
+#pragma unroll
+                    for (int e = 1; e < 4; ++e)
+                        if (4 * k + e < NB) own = fma(sel[e], phi[4 * k + e < NB ? 4 * k + e : 0], own);
                     if (firstc) {
-                        // lower triangle only: row 4k+r needs columns j <= 4k+r
                         const double vo = Vd * own;
 #pragma unroll
-                        for (int j = 0; j < NB && j < 4 * k + 4; ++j) accA[k][j] += vo * phi[j];
+                        for (int j = 0; j < NB; ++j)
+                            if (j < 4 * k + 4) accA[k][j] = fma(vo, phi[j], accA[k][j]);
                     }
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) accB[k][c] += own * S[c];
+                    for (int c = 0; c < 4; ++c) accB[k][c] = fma(own, S[c], accB[k][c]);
                 }
                 wv += Vd;
             }
         }
-        if (firstc) wsum = wv;
+        if (firstc) {
+            wsum = wv;
+            // regularise: the lane's own diagonal entries, selected arithmetically
+#pragma unroll
+            for (int k = 0; k < RPL; ++k)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (4 * k + e < NB)
+                        accA[k][4 * k + e < NB ? 4 * k + e : 0] =
+                            fma(sel[e] * wsum, lam.v[4 * k + e < NB ? 4 * k + e : 0],
+                                accA[k][4 * k + e < NB ? 4 * k + e : 0]);
+            // Right-looking Cholesky in registers.  Column j is scaled by its
+            // owner rows, then each entry L[m][j] is broadcast from the lane
+            // owning row m and every lane updates its own rows i >= m.
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const double djj = quad_bcast_rt(accA[j >> 2][j], j & 3);
+                const bool bad = !(djj > 0.0);
+                failed |= bad;
+                const double d = bad ? 1.0 : sqrt(djj);
+                const double id = 1.0 / d;
+                dinv[j] = id;
+#pragma unroll
+                for (int k = 0; k < RPL; ++k)
+                    if (4 * k + 3 > j) accA[k][j] = (4 * k + r > j) ? accA[k][j] * id : accA[k][j];
+#pragma unroll
+                for (int m = j + 1; m < NB; ++m) {
+                    const double lmj = quad_bcast_rt(accA[m >> 2][j], m & 3);
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k)
+                        if (4 * k + 3 >= m) {  // rows 4k..4k+3 may reach column m
+                            const bool act = 4 * k + r >= m;  // own row i = 4k + r needs i >= m
+                            accA[k][m] = act ? fma(-accA[k][j], lmj, accA[k][m]) : accA[k][m];
+                        }
+                }
+            }
+        }
+        // factor (packed lower, diagonal stored as 1/L_ii) and right-hand sides to LDS
+        if (firstc) {
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) {
+                const int i = 4 * k + r;
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
+                    if (j < 4 * k + 4 && i < NB && j <= i)
+                        Ls[q][i * (i + 1) / 2 + j] = (j == i) ? dinv[j] : accA[k][j];
+            }
+        }
 #pragma unroll
         for (int k = 0; k < RPL; ++k) {
             const int i = 4 * k + r;
             if (i < NB) {
-                if (firstc) {
 #pragma unroll
-                    for (int j = 0; j < NB && j < 4 * k + 4; ++j)
-                        if (j <= i) A[i * LDA + j] = accA[k][j];
-                    A[i * LDA + i] += wsum * lam.v[i];
-                }
-#pragma unroll
-                for (int c = 0; c < 4; ++c) Bq[i * 4 + c] = accB[k][c];
+                for (int c = 0; c < 4; ++c) Bs[q][i * 4 + c] = accB[k][c];
             }
         }
         __syncthreads();
-        if (firstc) {
-            // Right-looking Cholesky of the lower triangle, rows split over the quad.
-#pragma unroll 1
-            for (int j = 0; j < NB; ++j) {
-                double d = A[j * LDA + j];
-                const bool bad = !(d > 0.0);
-                failed |= bad;
-                d = bad ? 1.0 : sqrt(d);
-                const double id = 1.0 / d;
-                for (int i = j + 1; i < NB; ++i)
-                    if ((i & 3) == r) A[i * LDA + j] *= id;
-                if (r == 0) Dg[q][j] = d;
-                __syncthreads();
-                for (int i = j + 1; i < NB; ++i) {
-                    if ((i & 3) == r) {
-                        const double lij = A[i * LDA + j];
-                        for (int k = j + 1; k <= i; ++k) A[i * LDA + k] -= lij * A[k * LDA + j];
-                    }
-                }
-                __syncthreads();
-            }
-        }
         const int c = c0 + r;
         if (valid && c < C) {
-            double x[NB];
-#pragma unroll
-            for (int i = 0; i < NB; ++i) x[i] = Bq[i * 4 + r];
-#pragma unroll
+            double* x = Bs[q] + r;
+            const double* Lq = Ls[q];
+#pragma unroll 1
             for (int i = 0; i < NB; ++i) {
-                double s = x[i];
-#pragma unroll
-                for (int k = 0; k < i; ++k) s -= A[i * LDA + k] * x[k];
-                x[i] = s / Dg[q][i];
+                double s = x[i * 4];
+                const double* row = Lq + i * (i + 1) / 2;
+                for (int k = 0; k < i; ++k) s -= row[k] * x[k * 4];
+                x[i * 4] = s * row[i];
             }
-#pragma unroll
+#pragma unroll 1
             for (int i = NB - 1; i >= 0; --i) {
-                double s = x[i];
-#pragma unroll
-                for (int k = i + 1; k < NB; ++k) s -= A[k * LDA + i] * x[k];
-                x[i] = s / Dg[q][i];
+                double s = x[i * 4];
+                for (int k = i + 1; k < NB; ++k) s -= Lq[k * (k + 1) / 2 + i] * x[k * 4];
+                x[i * 4] = s * Lq[i * (i + 1) / 2 + i];
             }
             const bool zero = wsum == 0.0 || failed;
             float* out = coeffs + g * NB * C;
-#pragma unroll
-            for (int i = 0; i < NB; ++i) out[i * C + c] = zero ? 0.0f : (float)x[i];
+            for (int i = 0; i < NB; ++i) out[i * C + c] = zero ? 0.0f : (float)x[i * 4];
         }
         __syncthreads();
     }
@@ -196,13 +274,13 @@ __global__ __launch_bounds__(64) void k_fold_solve(const ViewInfo* __restrict__ 
         } else if (failed) {
             st = GSC_G_FAILED;
         } else {
-            double dmax = 0.0, dmin = 1e300;
+            double imax = 0.0, imin = 1e300;  // extremes of 1/L_ii
 #pragma unroll
             for (int i = 0; i < NB; ++i) {
-                dmax = fmax(dmax, Dg[q][i]);
-                dmin = fmin(dmin, Dg[q][i]);
+                imax = fmax(imax, dinv[i]);
+                imin = fmin(imin, dinv[i]);
             }
-            const double kap = (dmax / dmin) * (dmax / dmin);
+            const double kap = (imax / imin) * (imax / imin);
             if (kap > (double)kappa_max) {
                 st = GSC_G_ILL_COND;
                 atomicAdd(ill_count, 1u);
