@@ -155,8 +155,12 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint32_t* __restri
     hist[(uint64_t)d * nblocks + blockIdx.x] = sum;
 }
 
-// Stable scatter: ranks within the tile follow the original order
-// (iteration, wave, lane), offset by the scanned digit-major histogram.
+// Stable scatter of one 4096-key tile.  Each wave ranks its 1024 keys (16
+// rounds of 64) against per-wave digit counters in LDS, with no block
+// barrier; the four waves' counts then give every key its position in the
+// tile sorted by digit.  The tile is reordered through LDS and written out in
+// digit order, so each digit's run of keys is stored contiguously at the
+// offset the scanned digit-major histogram gives this tile.
 __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* __restrict__ keys_in,
                                                            const uint32_t* __restrict__ vals_in,
                                                            uint32_t* __restrict__ keys_out,
@@ -164,47 +168,73 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* __res
                                                            uint32_t n, int shift,
                                                            const uint32_t* __restrict__ offs,
                                                            uint32_t nblocks) {
-    __shared__ uint32_t base[256];
-    __shared__ uint32_t wc[kRsWaves][256];
-    int w = threadIdx.x >> 6;
-    base[threadIdx.x] = offs[(uint64_t)threadIdx.x * nblocks + blockIdx.x];
-    uint64_t tile0 = (uint64_t)blockIdx.x * kRsTile;
+    __shared__ uint32_t wcnt[kRsWaves][256];
+    __shared__ uint32_t dstart[256];
+    __shared__ uint32_t gbase[256];
+    __shared__ uint32_t wsum[kRsThreads / 64];
+    __shared__ uint32_t skey[kRsTile];
+    __shared__ uint32_t sval[kRsTile];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int k = lane; k < 256; k += 64) wcnt[w][k] = 0u;
+    gbase[threadIdx.x] = offs[(uint64_t)threadIdx.x * nblocks + blockIdx.x];
+    const uint64_t tile0 = (uint64_t)blockIdx.x * kRsTile;
+    const uint64_t base = tile0 + (uint64_t)w * (kRsTile / kRsWaves);
+    uint32_t kk[kRsItems], vv[kRsItems], rk[kRsItems];
+#pragma unroll
     for (int it = 0; it < kRsItems; ++it) {
-        for (int k = threadIdx.x; k < kRsWaves * 256; k += kRsThreads) (&wc[0][0])[k] = 0;
-        __syncthreads();
-        uint64_t idx = tile0 + (uint64_t)it * kRsThreads + threadIdx.x;
-        bool valid = idx < n;
-        uint32_t key = valid ? keys_in[idx] : 0u;
-        uint32_t val = valid ? vals_in[idx] : 0u;
-        uint32_t d = (key >> shift) & 255u;
+        const uint64_t idx = base + (uint64_t)it * 64 + lane;
+        const bool valid = idx < n;
+        const uint32_t key = valid ? keys_in[idx] : 0u;
+        const uint32_t val = valid ? vals_in[idx] : 0u;
+        const uint32_t d = (key >> shift) & 255u;
         uint64_t m = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            uint64_t bb = __ballot((d >> b) & 1u);
+            const uint64_t bb = __ballot((d >> b) & 1u);
             m &= ((d >> b) & 1u) ? bb : ~bb;
         }
-        uint32_t pre = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-        if (valid && pre == 0) wc[w][d] = (uint32_t)__popcll(m);
-        __syncthreads();
-        {
-            uint32_t t = threadIdx.x;
-            uint32_t run = base[t];
+        const uint32_t pre = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        const uint32_t c = wcnt[w][d];
+        __builtin_amdgcn_wave_barrier();
+        if (valid && pre == 0) wcnt[w][d] = c + (uint32_t)__popcll(m);
+        __builtin_amdgcn_wave_barrier();
+        kk[it] = key;
+        vv[it] = val;
+        rk[it] = valid ? c + pre : 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    {
+        // thread t owns digit t: prefix over the waves, then over the digits
+        const uint32_t t = threadIdx.x;
+        uint32_t run = 0;
 #pragma unroll
-            for (int k = 0; k < kRsWaves; ++k) {
-                uint32_t c = wc[k][t];
-                wc[k][t] = run;
-                run += c;
-            }
-            base[t] = run;
+        for (int k = 0; k < kRsWaves; ++k) {
+            const uint32_t c = wcnt[k][t];
+            wcnt[k][t] = run;
+            run += c;
         }
-        __syncthreads();
-        if (valid) {
-            uint32_t pos = wc[w][d] + pre;
-            keys_out[pos] = key;
-            vals_out[pos] = val;
+        uint32_t tot;
+        dstart[t] = block_exclusive_scan(run, wsum, &tot);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kRsItems; ++it) {
+        if (rk[it] != 0xFFFFFFFFu) {
+            const uint32_t d = (kk[it] >> shift) & 255u;
+            const uint32_t lp = dstart[d] + wcnt[w][d] + rk[it];
+            skey[lp] = kk[it];
+            sval[lp] = vv[it];
         }
-        __syncthreads();
+    }
+    __syncthreads();
+    const uint32_t cnt = (uint32_t)min((uint64_t)kRsTile, (uint64_t)n - tile0);
+    for (uint32_t i = threadIdx.x; i < cnt; i += kRsThreads) {
+        const uint32_t key = skey[i];
+        const uint32_t d = (key >> shift) & 255u;
+        const uint32_t gp = gbase[d] + (i - dstart[d]);
+        keys_out[gp] = key;
+        vals_out[gp] = sval[i];
     }
 }
 
