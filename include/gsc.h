@@ -97,7 +97,8 @@ enum {
     GSC_STAGE_EMIT = 3,       /* (tile, item) pair emission */
     GSC_STAGE_TILE_SORT = 4,  /* stable radix sort of pairs by tile, tile ranges */
     GSC_STAGE_BLEND = 5,      /* fused blend + accumulate (colorize) or blend + render */
-    GSC_STAGE_SOLVE = 6,      /* fold into normal equations + Cholesky solve */
+    GSC_STAGE_SOLVE = 6,      /* fold into normal equations + Cholesky solve (or its adjoint) */
+    GSC_STAGE_BLEND_ADJOINT = 7, /* backward: adjoint colours + two-pass blend adjoint */
     GSC_N_STAGES = 8
 };
 
@@ -188,6 +189,52 @@ gsc_status gsc_render(gsc_ctx* ctx, const float* means, const float* scales, con
                       const float* opacities, int64_t N, const gsc_camera* cams, int32_t n_cams,
                       const float* coeffs, int32_t C, int32_t sh_deg, float* images,
                       gsc_stream_t stream);
+
+/*
+ * Adjoint of gsc_colorize with respect to the targets and the opacities
+ * (eqs. 2, 10-14 differentiated; the pixel weights are recomputed, not
+ * stored).  With Bbar_g = (A_g + w_g Lambda)^{-1} grad_coeffs_g:
+ *   grad_targets_p = sum_g w_gp Bbar_g^T phi_gj
+ *   dL/dw_gp = beta^T (y_p - c_g^T phi_gj) - sum_{m,c} lambda_m Bbar_g[m][c] c_g[m][c],
+ *   beta = Bbar_g^T phi_gj,
+ * and dL/dw is taken through the front-to-back blend to the opacities:
+ *   dL/dalpha_k = u_k T_k - (1 - alpha_k)^{-1} sum_{i>k} u_i w_i,
+ *   dalpha/do = exp(-q/2) unless alpha is clamped at alpha_max.
+ * Footprint, alpha_min and early-stop decisions are piecewise constant and
+ * contribute nothing.
+ *   Inputs as for gsc_colorize, plus
+ *   coeffs: device [N, (L+1)^2, C] float32, the output of gsc_colorize for
+ *           the same inputs (the point of linearisation);
+ *   grad_coeffs: device [N, (L+1)^2, C] float32, dL/dcoeffs.
+ *   grad_targets: device output [rows, C] float32 or NULL with
+ *           rows = max_j(pixel_offset_j + H_j W_j); all of these rows are
+ *           overwritten (rows that no camera covers get zero).
+ *   grad_opacities: device output [N] float32 or NULL; overwritten.
+ * Unobserved Gaussians (w_g = 0) and Gaussians whose factorisation failed
+ * contribute zero.  Opacity gradients are summed with float atomics, so their
+ * last bits vary from run to run.
+ */
+gsc_status gsc_colorize_backward(gsc_ctx* ctx, const float* means, const float* scales,
+                                 const float* quats, const float* opacities, int64_t N,
+                                 const gsc_camera* cams, int32_t n_cams, const void* targets,
+                                 int32_t tdtype, int32_t C, int32_t sh_deg, const float* lambda,
+                                 int32_t n_lambda, const float* coeffs, const float* grad_coeffs,
+                                 float* grad_targets, float* grad_opacities, gsc_stream_t stream);
+
+/*
+ * Adjoint of gsc_render (eqs. 1-3) for an upstream gradient grad_images
+ * (device [rows, C] float32):
+ *   grad_coeffs_g = sum_{j,p} w_gp phi_gj grad_images_p^T
+ *   dL/dw_gp = (c_g^T phi_gj)^T grad_images_p, taken to the opacities as in
+ *   gsc_colorize_backward.
+ *   grad_coeffs: device output [N, (L+1)^2, C] float32 or NULL; overwritten.
+ *   grad_opacities: device output [N] float32 or NULL; overwritten.
+ */
+gsc_status gsc_render_backward(gsc_ctx* ctx, const float* means, const float* scales,
+                               const float* quats, const float* opacities, int64_t N,
+                               const gsc_camera* cams, int32_t n_cams, const float* coeffs,
+                               int32_t C, int32_t sh_deg, const float* grad_images,
+                               float* grad_coeffs, float* grad_opacities, gsc_stream_t stream);
 
 /* Statistics of the last call on `ctx` (host output).  Synchronises with the
  * device work of that call. */

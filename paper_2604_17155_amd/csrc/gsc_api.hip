@@ -78,7 +78,7 @@ struct gsc_ctx {
     gsc_options opt;
     // device scratch
     DevBuf views, views_all, cov, keys, vals, keys_alt, vals_alt, counts, counts_sorted, offsets, rec0, rec1,
-        sort_scratch, pkeys, pvals, pkeys_alt, pvals_alt, ranges, vs, gamma, misc;
+        sort_scratch, pkeys, pvals, pkeys_alt, pvals_alt, ranges, vs, gamma, bbar, misc;
     // host staging
     ViewInfo* h_views = nullptr;  // staging of one batch's table
     size_t h_views_cap = 0;
@@ -95,7 +95,7 @@ struct gsc_ctx {
     ~gsc_ctx() {
         DevBuf* all[] = {&views, &views_all, &cov, &keys, &vals, &keys_alt, &vals_alt, &counts, &counts_sorted,
                          &offsets, &rec0, &rec1, &sort_scratch, &pkeys, &pvals, &pkeys_alt,
-                         &pvals_alt, &ranges, &vs, &gamma, &misc};
+                         &pvals_alt, &ranges, &vs, &gamma, &bbar, &misc};
         for (DevBuf* b : all) b->release();
         if (h_views) (void)hipHostFree(h_views);
         if (h_all) (void)hipHostFree(h_all);
@@ -387,6 +387,25 @@ gsc_status ensure_common(gsc_ctx* ctx, const float* scales, const float* quats, 
     return GSC_OK;
 }
 
+// Upload the full camera table to ctx->views_all (used where the views of all
+// batches are needed at once: the fold over views).
+gsc_status upload_all_views(gsc_ctx* ctx, const std::vector<ViewInfo>& all, hipStream_t s) {
+    const int n_cams = (int)all.size();
+    if (n_cams == 0) return GSC_OK;
+    if ((size_t)n_cams > ctx->h_all_cap) {
+        if (ctx->h_all) GSC_HIP(hipHostFree(ctx->h_all));
+        ctx->h_all = nullptr;
+        ctx->h_all_cap = 0;
+        GSC_HIP(hipHostMalloc((void**)&ctx->h_all, sizeof(ViewInfo) * (size_t)n_cams));
+        ctx->h_all_cap = (size_t)n_cams;
+    }
+    for (int j = 0; j < n_cams; ++j) ctx->h_all[j] = all[j];
+    GSC_HIP(ctx->views_all.ensure(sizeof(ViewInfo) * (size_t)n_cams));
+    GSC_HIP(hipMemcpyAsync(ctx->views_all.p, ctx->h_all, sizeof(ViewInfo) * (size_t)n_cams,
+                           hipMemcpyHostToDevice, s));
+    return GSC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -478,18 +497,7 @@ gsc_status gsc_colorize_ex(gsc_ctx* ctx, const float* means, const float* scales
     if (x_sums && n_cams > 0)
         GSC_HIP(hipMemcpyAsync(x_sums, ctx->vs.p, 4 * vs_words, hipMemcpyDeviceToDevice, s));
     // fold + solve needs the full camera table (only the camera centres are used)
-    if (per_view && n_cams > 0) {
-        if ((size_t)n_cams > ctx->h_all_cap) {
-            if (ctx->h_all) GSC_HIP(hipHostFree(ctx->h_all));
-            ctx->h_all = nullptr;
-            GSC_HIP(hipHostMalloc((void**)&ctx->h_all, sizeof(ViewInfo) * (size_t)n_cams));
-            ctx->h_all_cap = (size_t)n_cams;
-        }
-        for (int j = 0; j < n_cams; ++j) ctx->h_all[j] = all[j];
-        GSC_HIP(ctx->views_all.ensure(sizeof(ViewInfo) * (size_t)n_cams));
-        GSC_HIP(hipMemcpyAsync(ctx->views_all.p, ctx->h_all, sizeof(ViewInfo) * (size_t)n_cams,
-                               hipMemcpyHostToDevice, s));
-    }
+    if (per_view && (st = upload_all_views(ctx, all, s)) != GSC_OK) return st;
     float* dc_scratch = nullptr;
     if (sh_deg == 0 && per_view) {
         GSC_HIP(ctx->gamma.ensure(4 * (size_t)N * (size_t)(C + 1)));
@@ -549,6 +557,163 @@ gsc_status gsc_render(gsc_ctx* ctx, const float* means, const float* scales, con
         return GSC_OK;
     });
     if (st != GSC_OK) return st;
+    ctx->stats_pending = true;
+    return GSC_OK;
+}
+
+gsc_status gsc_colorize_backward(gsc_ctx* ctx, const float* means, const float* scales,
+                                 const float* quats, const float* opacities, int64_t N,
+                                 const gsc_camera* cams, int32_t n_cams, const void* targets,
+                                 int32_t tdtype, int32_t C, int32_t sh_deg, const float* lambda,
+                                 int32_t n_lambda, const float* coeffs, const float* grad_coeffs,
+                                 float* grad_targets, float* grad_opacities, gsc_stream_t stream) {
+    if (!ctx) return fail(GSC_ERR_INVALID_ARG, "null ctx");
+    int64_t rows = 0;
+    gsc_status st = validate_geometry(means, scales, quats, opacities, N, cams, n_cams, &rows);
+    if (st != GSC_OK) return st;
+    if ((st = validate_channels(C, sh_deg)) != GSC_OK) return st;
+    if (tdtype != GSC_F32 && tdtype != GSC_BF16) return fail(GSC_ERR_INVALID_ARG, "tdtype must be GSC_F32 or GSC_BF16");
+    if (grad_opacities && rows > 0 && !targets) return fail(GSC_ERR_INVALID_ARG, "targets is null");
+    if (N > 0 && (!coeffs || !grad_coeffs)) return fail(GSC_ERR_INVALID_ARG, "coeffs or grad_coeffs is null");
+    double lam[kMaxNb];
+    if ((st = expand_lambda(lambda, n_lambda, sh_deg, lam)) != GSC_OK) return st;
+    if (ctx->opt.flags & GSC_FLAG_VALIDATE_ONLY) return GSC_OK;
+
+    hipStream_t s = (hipStream_t)stream;
+    memset(&ctx->stats, 0, sizeof(ctx->stats));
+    if (grad_targets && rows > 0) launch_fill_u32((uint32_t*)grad_targets, 0u, (uint64_t)rows * C, s);
+    if (grad_opacities && N > 0) launch_fill_u32((uint32_t*)grad_opacities, 0u, (uint64_t)N, s);
+    if (N == 0 || n_cams == 0 || (!grad_targets && !grad_opacities)) return GSC_OK;
+    const int nb = (sh_deg + 1) * (sh_deg + 1);
+    BlendParams bp = blend_params(ctx->opt);
+    if ((st = ensure_common(ctx, scales, quats, N, s)) != GSC_OK) return st;
+    std::vector<ViewInfo> all(n_cams);
+    for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j]);
+    // 1. visibilities V_gj (the normal matrices depend on the weights only)
+    const bool per_view = sh_deg > 0;
+    const uint64_t v_words = (uint64_t)(per_view ? n_cams : 1) * (uint64_t)N;
+    GSC_HIP(ctx->vs.ensure(4 * v_words));
+    launch_fill_u32(ctx->vs.as<uint32_t>(), 0u, v_words, s);
+    unsigned long long* d_counter = reinterpret_cast<unsigned long long*>(ctx->misc.p);
+    Binned last;
+    st = for_view_batches(ctx, all, n_cams, means, opacities, N, bp, s,
+                          [&](int v0, int nv, const Binned& bn) -> gsc_status {
+        StageTimer t(ctx, s, GSC_STAGE_BLEND);
+        launch_accumulate_weights(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
+                                  ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(),
+                                  ctx->rec1.as<float4>(), N, v0, per_view, bp, ctx->vs.as<float>(),
+                                  d_counter, s);
+        GSC_LAUNCHED("accumulate weights");
+        last = bn;
+        return GSC_OK;
+    });
+    if (st != GSC_OK) return st;
+    const gsc_stats pass1 = ctx->stats;
+    // 2. Bbar = (A + w Lambda)^{-1} dL/dc and rho
+    if (per_view && (st = upload_all_views(ctx, all, s)) != GSC_OK) return st;
+    const size_t nbc = (size_t)N * nb * C;
+    GSC_HIP(ctx->bbar.ensure(4 * (nbc + (size_t)N) + 4 * (size_t)N));
+    float* d_bbar = ctx->bbar.as<float>();
+    float* d_rho = d_bbar + nbc;
+    float* d_wsum = d_rho + N;
+    {
+        StageTimer t(ctx, s, GSC_STAGE_SOLVE);
+        launch_adjoint_solve(ctx->views_all.as<ViewInfo>(), n_cams, means, ctx->vs.as<float>(), per_view,
+                             N, C, sh_deg, lam, grad_coeffs, coeffs, d_bbar, d_rho, d_wsum, s);
+        GSC_LAUNCHED("adjoint solve");
+    }
+    // 3. per view batch: adjoint colours, then the two-pass blend adjoint
+    auto body = [&](int v0, int nv, const Binned& bn) -> gsc_status {
+        (void)v0;
+        GSC_HIP(ctx->gamma.ensure(4 * (size_t)nv * (size_t)N * (size_t)(C + 1)));
+        StageTimer t(ctx, s, GSC_STAGE_BLEND_ADJOINT);
+        launch_view_adjoint(ctx->views.as<ViewInfo>(), nv, means, coeffs, d_bbar, d_rho, N, C, sh_deg,
+                            false, ctx->gamma.as<float>(), s);
+        GSC_LAUNCHED("view adjoint");
+        launch_blend_adjoint(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
+                             ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(),
+                             targets, tdtype, C, N, ctx->gamma.as<float>(), bp, grad_targets,
+                             grad_opacities, s);
+        GSC_LAUNCHED("blend adjoint");
+        return GSC_OK;
+    };
+    if (pass1.view_batches == 1) {
+        st = body(0, n_cams, last);  // the binning of the only batch is still in place
+    } else {
+        st = for_view_batches(ctx, all, n_cams, means, opacities, N, bp, s, body);
+    }
+    if (st != GSC_OK) return st;
+    ctx->stats.pairs = pass1.pairs;
+    ctx->stats.items = pass1.items;
+    ctx->stats.view_batches = pass1.view_batches;
+    ctx->stats_pending = true;
+    return GSC_OK;
+}
+
+gsc_status gsc_render_backward(gsc_ctx* ctx, const float* means, const float* scales,
+                               const float* quats, const float* opacities, int64_t N,
+                               const gsc_camera* cams, int32_t n_cams, const float* coeffs,
+                               int32_t C, int32_t sh_deg, const float* grad_images,
+                               float* grad_coeffs, float* grad_opacities, gsc_stream_t stream) {
+    if (!ctx) return fail(GSC_ERR_INVALID_ARG, "null ctx");
+    int64_t rows = 0;
+    gsc_status st = validate_geometry(means, scales, quats, opacities, N, cams, n_cams, &rows);
+    if (st != GSC_OK) return st;
+    if ((st = validate_channels(C, sh_deg)) != GSC_OK) return st;
+    if (rows > 0 && !grad_images) return fail(GSC_ERR_INVALID_ARG, "grad_images is null");
+    if (N > 0 && !coeffs) return fail(GSC_ERR_INVALID_ARG, "coeffs is null");
+    if (ctx->opt.flags & GSC_FLAG_VALIDATE_ONLY) return GSC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    memset(&ctx->stats, 0, sizeof(ctx->stats));
+    const int nb = (sh_deg + 1) * (sh_deg + 1);
+    if (grad_coeffs && N > 0) launch_fill_u32((uint32_t*)grad_coeffs, 0u, (uint64_t)N * nb * C, s);
+    if (grad_opacities && N > 0) launch_fill_u32((uint32_t*)grad_opacities, 0u, (uint64_t)N, s);
+    if (N == 0 || n_cams == 0 || (!grad_coeffs && !grad_opacities)) return GSC_OK;
+    BlendParams bp = blend_params(ctx->opt);
+    if ((st = ensure_common(ctx, scales, quats, N, s)) != GSC_OK) return st;
+    std::vector<ViewInfo> all(n_cams);
+    for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j]);
+    const bool per_view = sh_deg > 0;
+    const uint64_t vs_words = (uint64_t)(per_view ? n_cams : 1) * (uint64_t)N * (uint64_t)(C + 1);
+    if (grad_coeffs) {
+        GSC_HIP(ctx->vs.ensure(4 * vs_words));
+        launch_fill_u32(ctx->vs.as<uint32_t>(), 0u, vs_words, s);
+    }
+    unsigned long long* d_counter = reinterpret_cast<unsigned long long*>(ctx->misc.p);
+    st = for_view_batches(ctx, all, n_cams, means, opacities, N, bp, s,
+                          [&](int v0, int nv, const Binned& bn) -> gsc_status {
+        if (grad_coeffs) {
+            // dL/dc folds sum_p w (dL/dimages_p) per (view, Gaussian): the
+            // forward accumulate with dL/dimages in place of the targets
+            StageTimer t(ctx, s, GSC_STAGE_BLEND);
+            launch_accumulate(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
+                              ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(),
+                              grad_images, GSC_F32, C, N, v0, per_view, bp, ctx->vs.as<float>(),
+                              d_counter, nullptr, s);
+            GSC_LAUNCHED("accumulate");
+        }
+        if (grad_opacities) {
+            GSC_HIP(ctx->gamma.ensure(4 * (size_t)nv * (size_t)N * (size_t)(C + 1)));
+            StageTimer t(ctx, s, GSC_STAGE_BLEND_ADJOINT);
+            launch_view_adjoint(ctx->views.as<ViewInfo>(), nv, means, coeffs, nullptr, nullptr, N, C,
+                                sh_deg, true, ctx->gamma.as<float>(), s);
+            GSC_LAUNCHED("view colours");
+            launch_blend_adjoint(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
+                                 ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(),
+                                 ctx->rec1.as<float4>(), grad_images, GSC_F32, C, N,
+                                 ctx->gamma.as<float>(), bp, nullptr, grad_opacities, s);
+            GSC_LAUNCHED("blend adjoint");
+        }
+        return GSC_OK;
+    });
+    if (st != GSC_OK) return st;
+    if (grad_coeffs) {
+        if (per_view && (st = upload_all_views(ctx, all, s)) != GSC_OK) return st;
+        StageTimer t(ctx, s, GSC_STAGE_SOLVE);
+        launch_fold_rhs(ctx->views_all.as<ViewInfo>(), n_cams, means, ctx->vs.as<float>(), per_view, N,
+                        C, sh_deg, grad_coeffs, s);
+        GSC_LAUNCHED("fold");
+    }
     ctx->stats_pending = true;
     return GSC_OK;
 }

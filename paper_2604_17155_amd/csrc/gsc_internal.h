@@ -108,4 +108,37 @@ void launch_fold_solve(const ViewInfo* views, int n_views, const float* means, c
                        float kappa_max, float* coeffs, uint8_t* status, float* wout,
                        float* dc_scratch, unsigned int* ill_count, hipStream_t s);
 
+// Weights-only accumulate: V[(view) * N + g] += sum_p w (stride 1).
+void launch_accumulate_weights(const ViewInfo* views, int n_views, uint32_t n_tiles,
+                               const uint2* ranges, const uint32_t* pair_vals, const float4* rec0,
+                               const float4* rec1, int64_t N, int view_first, bool per_view,
+                               BlendParams bp, float* V, unsigned long long* counter, hipStream_t s);
+
+// Adjoint solve: bbar = (A_g + w_g Lambda)^{-1} grad_coeffs and
+// rho_g = sum lambda_m bbar[m][c] coeffs[m][c].  V holds per-view
+// visibilities [n_views][N] (per_view) or their sums [N].  w_scratch: N floats
+// (sh_deg == 0 with per_view).
+void launch_adjoint_solve(const ViewInfo* views, int n_views, const float* means, const float* V,
+                          bool per_view, int64_t N, int C, int sh_deg, const double* lam_nb,
+                          const float* grad_coeffs, const float* coeffs, float* bbar, float* rho,
+                          float* w_scratch, hipStream_t s);
+
+// Per (view, Gaussian) adjoint colours: beta [n_views][N][C+1] = (beta_gj, delta_gj).
+// render: beta = c^T phi, delta = 0.  Otherwise beta = bbar^T phi and
+// delta = beta^T (c^T phi) + rho_g.
+void launch_view_adjoint(const ViewInfo* views, int n_views, const float* means, const float* coeffs,
+                         const float* bbar, const float* rho, int64_t N, int C, int sh_deg,
+                         bool render, float* beta, hipStream_t s);
+
+// Blend adjoint over the binned tiles: grad_y[row][c] = sum_g w beta (every
+// pixel of every view written, if grad_y) and grad_o[g] += dL/do (atomics, if grad_o).
+void launch_blend_adjoint(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
+                          const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
+                          const void* ypix, int ydtype, int C, int64_t N, const float* beta,
+                          BlendParams bp, float* grad_y, float* grad_o, hipStream_t s);
+
+// grad_coeffs[g][m][c] = sum_j phi_gj[m] S_gj[c] from per-view sums [n_views][N][C+1].
+void launch_fold_rhs(const ViewInfo* views, int n_views, const float* means, const float* VS,
+                     bool per_view, int64_t N, int C, int sh_deg, float* out, hipStream_t s);
+
 }  // namespace gsc

@@ -10,83 +10,10 @@
 // broadcast with v_readlane, so the loop needs no LDS and no barriers.
 #include "gsc_internal.h"
 #include "sh.h"
+#include "wave_ops.h"
 
 namespace gsc {
 
-namespace {
-
-template <int CTRL>
-__device__ __forceinline__ float dpp_mov(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-
-// Sum over the 64 lanes; the result is uniform.  All lanes must be active.
-__device__ __forceinline__ float wave_sum(float v) {
-    v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
-    v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
-    v += dpp_mov<0x141>(v);  // row_half_mirror
-    v += dpp_mov<0x140>(v);  // row_mirror: every lane holds its row's sum
-    float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
-    float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
-    float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
-    float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
-    return (r0 + r1) + (r2 + r3);
-}
-
-// Sums four per-lane values over the wave at once.  Quad exchanges split the
-// four values between lanes (lane bit 0 picks the pair, bit 1 the member),
-// rotations sum the four quads of a row, and two shuffles sum the rows.
-// On return lane L < 4 holds the total of value 2*(L&1) + (L>>1).
-__device__ __forceinline__ float wave_sum4_transposed(float v0, float v1, float v2, float v3,
-                                                      uint32_t lane) {
-    const bool b0 = lane & 1u, b1 = lane & 2u;
-    const float x0 = (b0 ? v2 : v0) + dpp_mov<0xB1>(b0 ? v0 : v2);
-    const float x1 = (b0 ? v3 : v1) + dpp_mov<0xB1>(b0 ? v1 : v3);
-    float y = (b1 ? x1 : x0) + dpp_mov<0x4E>(b1 ? x0 : x1);
-    y += dpp_mov<0x124>(y);  // row_ror:4
-    y += dpp_mov<0x128>(y);  // row_ror:8
-    y += __shfl_xor(y, 16, 64);
-    y += __shfl_xor(y, 32, 64);
-    return y;
-}
-
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false);
-    return (uint32_t)__builtin_amdgcn_readlane((int)v, 0) + (uint32_t)__builtin_amdgcn_readlane((int)v, 16) +
-           (uint32_t)__builtin_amdgcn_readlane((int)v, 32) + (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
-}
-
-__device__ __forceinline__ float bcast(float v, uint32_t lane) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), (int)lane));
-}
-__device__ __forceinline__ uint32_t bcast_u(uint32_t v, uint32_t lane) {
-    return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)lane);
-}
-
-__device__ __forceinline__ int find_view(const ViewInfo* __restrict__ views, int n_views, uint32_t tile) {
-    int lo = 0, hi = n_views - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (views[mid].tile_base <= tile) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
-template <bool BF16>
-__device__ __forceinline__ float load_target(const void* __restrict__ t, int64_t idx) {
-    if constexpr (BF16) {
-        uint32_t b = ((const uint16_t*)t)[idx];
-        return __uint_as_float(b << 16);
-    } else {
-        return ((const float*)t)[idx];
-    }
-}
-
-}  // namespace
 
 // CC: channels handled by this launch (chunk [c_off, c_off + CC) of C).
 template <int CC, bool BF16>
@@ -110,7 +37,7 @@ __global__ __launch_bounds__(256) void k_accumulate(
 
     float T[4];
     bool live[4];
-    float y[4][CC];
+    float y[4][CC > 0 ? CC : 1];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         int iy = iy0 + 4 * k;
@@ -153,7 +80,7 @@ __global__ __launch_bounds__(256) void k_accumulate(
             const float a0 = c1.x * dx * dx;
             const float b0 = c1.y * dx;
             float sv = 0.0f;
-            float ss[CC];
+            float ss[CC > 0 ? CC : 1];
 #pragma unroll
             for (int c = 0; c < CC; ++c) ss[c] = 0.0f;
             uint32_t nh = 0;
@@ -182,7 +109,10 @@ __global__ __launch_bounds__(256) void k_accumulate(
                     if (lane == 0) atomicAdd(gcount + g, tn);
                 }
                 float* slot = VS + (vs_view + g) * (int64_t)stride;
-                if constexpr (CC <= 3) {
+                if constexpr (CC == 0) {
+                    const float tv = wave_sum(sv);
+                    if (lane == 0) unsafeAtomicAdd(slot, tv);
+                } else if constexpr (CC <= 3) {
                     const float t = wave_sum4_transposed(sv, CC > 0 ? ss[0] : 0.0f,
                                                          CC > 1 ? ss[CC > 1 ? 1 : 0] : 0.0f,
                                                          CC > 2 ? ss[CC > 2 ? 2 : 0] : 0.0f, lane);
@@ -266,6 +196,16 @@ void launch_accumulate(const ViewInfo* views, int n_views, uint32_t n_tiles, con
     else
         launch_acc_cc<16>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, targets, tdtype, C,
                           N, view_first, per_view, bp, VS, counter, gcount, s);
+}
+
+void launch_accumulate_weights(const ViewInfo* views, int n_views, uint32_t n_tiles,
+                               const uint2* ranges, const uint32_t* pair_vals, const float4* rec0,
+                               const float4* rec1, int64_t N, int view_first, bool per_view,
+                               BlendParams bp, float* V, unsigned long long* counter, hipStream_t s) {
+    if (n_tiles == 0) return;
+    hipLaunchKernelGGL((k_accumulate<0, false>), dim3((n_tiles + 3) / 4), dim3(256), 0, s, views,
+                       n_views, n_tiles, ranges, pair_vals, rec0, rec1, (const void*)nullptr, 0, 0,
+                       N, view_first, (int)per_view, bp, V, counter, (uint32_t*)nullptr);
 }
 
 // ---- render ----------------------------------------------------------------

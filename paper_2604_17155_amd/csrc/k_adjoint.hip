@@ -1,0 +1,416 @@
+// Backward pass: hand-written adjoints of colorize and render with respect to
+// the target pixels and the opacities.
+//
+// Colorize.  The coefficients solve (A_g + w_g Lambda) c_g = B_g (eq. 14), so
+// for an upstream gradient dL/dc_g and Bbar_g = (A_g + w_g Lambda)^{-1} dL/dc_g
+//   dL = sum_g <Bbar_g, dB_g - dA_g c_g - dw_g Lambda c_g>.
+// B_g, A_g and w_g are sums over contributions of w*phi*y^T, w*phi*phi^T and w
+// (eqs. 10-13), hence
+//   dL/dy_p  = sum_g w_gp beta_gj            beta_gj  = Bbar_g^T phi_gj
+//   dL/dw_gp = beta^T y_p - delta_gj        delta_gj = beta^T gamma + rho_g
+// with gamma_gj = c_g^T phi_gj and rho_g = sum_{m,c} lambda_m Bbar[m][c] c[m][c].
+// Render (eqs. 1-3).  images_p = sum_g w_gp gamma_gj, so for dL/dimages_p
+//   dL/dc_g  = sum_{j,p} phi_gj w_gp (dL/dimages_p)^T
+//   dL/dw_gp = gamma^T (dL/dimages_p)        (beta = gamma, delta = 0).
+// Both then go through the adjoint of the front-to-back blend (eq. 2):
+// w_k = alpha_k T_k with T_k = prod_{i<k} (1 - alpha_i) over accepted entries, so
+//   dL/dalpha_k = u_k T_k - (1 - alpha_k)^{-1} sum_{i>k} u_i w_i,  u = dL/dw,
+// and alpha = min(alpha_max, o G) gives dalpha/do = G unless clamped.  The
+// skip, footprint and stop decisions are piecewise constant and carry no
+// derivative.
+//
+// The weights are recomputed, never stored: one tile pass forms per pixel the
+// total S = sum_k u_k w_k (and dL/dy), a second identical pass forms the
+// running prefix P_k, so that the suffix sum is S - P_k.  S and P are kept in
+// FP64, which keeps the suffix accurate deep into the pixel where it is many
+// orders below S.
+#include "gsc_internal.h"
+#include "sh.h"
+#include "wave_ops.h"
+
+namespace gsc {
+
+// beta[(v*N + g)*(C+1) + c] = beta_gj[c], and [.. + C] = delta_gj.
+template <int L, bool RENDER>
+__global__ void k_view_adjoint(const ViewInfo* __restrict__ views, const float* __restrict__ means,
+                               const float* __restrict__ coeffs, const float* __restrict__ bbar,
+                               const float* __restrict__ rho, int64_t N, int C,
+                               float* __restrict__ beta) {
+    constexpr int NB = (L + 1) * (L + 1);
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y;
+    if (g >= N) return;
+    const ViewInfo& V = views[v];
+    const double dx = (double)means[3 * g] - V.centre[0];
+    const double dy = (double)means[3 * g + 1] - V.centre[1];
+    const double dz = (double)means[3 * g + 2] - V.centre[2];
+    const double inv = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+    float phi[NB];
+    sh_eval<float, L>((float)(dx * inv), (float)(dy * inv), (float)(dz * inv), phi);
+    const float* cg = coeffs + g * NB * C;
+    float* out = beta + ((int64_t)v * N + g) * (C + 1);
+    if constexpr (RENDER) {
+        for (int c = 0; c < C; ++c) {
+            float a = 0.0f;
+#pragma unroll
+            for (int m = 0; m < NB; ++m) a = fmaf(cg[m * C + c], phi[m], a);
+            out[c] = a;
+        }
+        out[C] = 0.0f;
+    } else {
+        const float* bg = bbar + g * NB * C;
+        double delta = (double)rho[g];
+        for (int c = 0; c < C; ++c) {
+            float a = 0.0f, b = 0.0f;
+#pragma unroll
+            for (int m = 0; m < NB; ++m) {
+                a = fmaf(cg[m * C + c], phi[m], a);
+                b = fmaf(bg[m * C + c], phi[m], b);
+            }
+            out[c] = b;
+            delta += (double)a * (double)b;
+        }
+        out[C] = (float)delta;
+    }
+}
+
+void launch_view_adjoint(const ViewInfo* views, int n_views, const float* means, const float* coeffs,
+                         const float* bbar, const float* rho, int64_t N, int C, int sh_deg,
+                         bool render, float* beta, hipStream_t s) {
+    if (N <= 0 || n_views <= 0) return;
+    dim3 grid((unsigned)((N + 255) / 256), (unsigned)n_views), block(256);
+#define GSC_VA(LL)                                                                                   \
+    do {                                                                                             \
+        if (render)                                                                                  \
+            hipLaunchKernelGGL((k_view_adjoint<LL, true>), grid, block, 0, s, views, means, coeffs,  \
+                               bbar, rho, N, C, beta);                                               \
+        else                                                                                         \
+            hipLaunchKernelGGL((k_view_adjoint<LL, false>), grid, block, 0, s, views, means, coeffs, \
+                               bbar, rho, N, C, beta);                                               \
+    } while (0)
+    switch (sh_deg) {
+        case 0: GSC_VA(0); break;
+        case 1: GSC_VA(1); break;
+        case 2: GSC_VA(2); break;
+        default: GSC_VA(3); break;
+    }
+#undef GSC_VA
+}
+
+namespace {
+
+// One front-to-back step of one pixel (the decisions of the forward blend).
+struct Step {
+    float w;      // accepted weight alpha*T (0 if not accepted)
+    float alpha;  // alpha of the entry
+    float G;      // exp(-q/2)
+    float Tb;     // transmittance before the entry
+    bool take;
+};
+
+__device__ __forceinline__ Step blend_step(float& T, bool& live, float q2, float opac,
+                                           float qlim, const BlendParams& bp) {
+    Step st;
+    st.G = __builtin_amdgcn_exp2f(q2);
+    st.alpha = fminf(bp.alpha_max, opac * st.G);
+    const float test = fmaf(-T, st.alpha, T);
+    const bool cand = live && q2 >= qlim && st.alpha >= bp.alpha_min;
+    const bool stop = cand && test < bp.t_min;
+    st.take = cand && !stop;
+    live = live && !stop;
+    st.Tb = T;
+    st.w = st.take ? st.alpha * T : 0.0f;
+    T = st.take ? test : T;
+    return st;
+}
+
+}  // namespace
+
+// CC: channels of this launch (chunk [c_off, c_off + CC) of C).  dL/dw is
+// linear in the channels, so chunk launches add their shares of dL/do; the
+// first chunk also carries -delta.
+template <int CC, bool BF16, bool GY>
+__global__ __launch_bounds__(256) void k_blend_adjoint(
+    const ViewInfo* __restrict__ views, int n_views, uint32_t n_tiles, const uint2* __restrict__ ranges,
+    const uint32_t* __restrict__ pair_vals, const float4* __restrict__ rec0,
+    const float4* __restrict__ rec1, const void* __restrict__ ypix, int C, int c_off, int64_t N,
+    const float* __restrict__ beta, BlendParams bp, float* __restrict__ grad_y,
+    float* __restrict__ grad_o) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tile >= n_tiles) return;  // whole wave
+    const int vloc = find_view(views, n_views, tile);
+    const ViewInfo& V = views[vloc];
+    const uint32_t local = tile - V.tile_base;
+    const int tx = (int)(local % (uint32_t)V.tiles_x), ty = (int)(local / (uint32_t)V.tiles_x);
+    const int ix = tx * kTile + (int)(lane & 15);
+    const int iy0 = ty * kTile + (int)(lane >> 4);
+    const float px = (float)ix + 0.5f;
+    const int stride = C + 1;
+    const bool first_chunk = c_off == 0;
+    const int64_t item_base = (int64_t)vloc * N;
+    const float qlim = (float)(kExp2Scale * (double)bp.cut2);
+
+    bool inside[4];
+    float yv[4][CC];  // pixel values (read only when dL/do is wanted)
+    float pyk[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int iy = iy0 + 4 * k;
+        inside[k] = ix < V.width && iy < V.height;
+        pyk[k] = (float)iy + 0.5f;
+        const int64_t row = V.pixel_offset + (int64_t)iy * V.width + ix;
+#pragma unroll
+        for (int c = 0; c < CC; ++c)
+            yv[k][c] = (inside[k] && grad_o && c_off + c < C) ? load_target<BF16>(ypix, row * C + c_off + c) : 0.0f;
+    }
+    const uint2 rg = ranges[tile];
+
+    // ---- pass 1: S = sum_k u_k w_k per pixel, and dL/dy -------------------
+    float T[4];
+    bool live[4];
+    double S[4];
+    float gy[4][GY ? CC : 1];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        T[k] = 1.0f;
+        live[k] = inside[k];
+        S[k] = 0.0;
+#pragma unroll
+        for (int c = 0; c < (GY ? CC : 1); ++c) gy[k][c] = 0.0f;
+    }
+    bool wave_live = __ballot(inside[0] || inside[1] || inside[2] || inside[3]) != 0;
+    for (uint32_t b = rg.x; b < rg.y && wave_live; b += 64) {
+        const uint32_t nb = min(64u, rg.y - b);
+        const uint32_t pv = lane < nb ? pair_vals[b + lane] : 0u;
+        uint32_t pn = bcast_u(pv, 0);
+        float4 n0 = rec0[pn & kItemMask], n1 = rec1[pn & kItemMask];
+        for (uint32_t j = 0; j < nb; ++j) {
+            const uint32_t pc = pn;
+            const float4 c0 = n0, c1 = n1;
+            if (j + 1 < nb) {
+                pn = bcast_u(pv, j + 1);
+                n0 = rec0[pn & kItemMask];
+                n1 = rec1[pn & kItemMask];
+            }
+            const uint32_t bands = pc >> kItemBits;
+            const uint32_t item = pc & kItemMask;
+            const float* bp_ = beta + (int64_t)item * stride;
+            float bet[CC];
+#pragma unroll
+            for (int c = 0; c < CC; ++c) bet[c] = (c_off + c < C) ? bp_[c_off + c] : 0.0f;
+            const float del = first_chunk ? bp_[C] : 0.0f;
+            const float dx = (px - c0.x) - c0.z;
+            const float a0 = c1.x * dx * dx;
+            const float b0 = c1.y * dx;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (!((bands >> k) & 1u)) continue;
+                const float dy = (pyk[k] - c0.y) - c0.w;
+                const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
+                const Step st = blend_step(T[k], live[k], q2, c1.w, qlim, bp);
+                float u = -del;
+#pragma unroll
+                for (int c = 0; c < CC; ++c) u = fmaf(bet[c], yv[k][c], u);
+                S[k] += (double)(st.w * u);
+                if constexpr (GY) {
+#pragma unroll
+                    for (int c = 0; c < CC; ++c) gy[k][c] = fmaf(st.w, bet[c], gy[k][c]);
+                }
+            }
+            if (__ballot(live[0] || live[1] || live[2] || live[3]) == 0) {
+                wave_live = false;
+                break;
+            }
+        }
+    }
+    if constexpr (GY) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (!inside[k]) continue;
+            const int64_t row = V.pixel_offset + (int64_t)(iy0 + 4 * k) * V.width + ix;
+#pragma unroll
+            for (int c = 0; c < CC; ++c)
+                if (c_off + c < C) grad_y[row * C + c_off + c] = gy[k][c];
+        }
+    }
+    if (grad_o == nullptr) return;
+
+    // ---- pass 2: dL/dalpha per entry, reduced to dL/do per Gaussian -------
+    double P[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        T[k] = 1.0f;
+        live[k] = inside[k];
+        P[k] = 0.0;
+    }
+    wave_live = __ballot(inside[0] || inside[1] || inside[2] || inside[3]) != 0;
+    for (uint32_t b = rg.x; b < rg.y && wave_live; b += 64) {
+        const uint32_t nb = min(64u, rg.y - b);
+        const uint32_t pv = lane < nb ? pair_vals[b + lane] : 0u;
+        uint32_t pn = bcast_u(pv, 0);
+        float4 n0 = rec0[pn & kItemMask], n1 = rec1[pn & kItemMask];
+        for (uint32_t j = 0; j < nb; ++j) {
+            const uint32_t pc = pn;
+            const float4 c0 = n0, c1 = n1;
+            if (j + 1 < nb) {
+                pn = bcast_u(pv, j + 1);
+                n0 = rec0[pn & kItemMask];
+                n1 = rec1[pn & kItemMask];
+            }
+            const uint32_t bands = pc >> kItemBits;
+            const uint32_t item = pc & kItemMask;
+            const float* bp_ = beta + (int64_t)item * stride;
+            float bet[CC];
+#pragma unroll
+            for (int c = 0; c < CC; ++c) bet[c] = (c_off + c < C) ? bp_[c_off + c] : 0.0f;
+            const float del = first_chunk ? bp_[C] : 0.0f;
+            const float dx = (px - c0.x) - c0.z;
+            const float a0 = c1.x * dx * dx;
+            const float b0 = c1.y * dx;
+            float go = 0.0f;
+            uint32_t any = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (!((bands >> k) & 1u)) continue;
+                const float dy = (pyk[k] - c0.y) - c0.w;
+                const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
+                const Step st = blend_step(T[k], live[k], q2, c1.w, qlim, bp);
+                float u = -del;
+#pragma unroll
+                for (int c = 0; c < CC; ++c) u = fmaf(bet[c], yv[k][c], u);
+                P[k] += (double)(st.w * u);
+                const float suffix = (float)(S[k] - P[k]);
+                const float dal = u * st.Tb - suffix / (1.0f - st.alpha);
+                const bool clamped = c1.w * st.G >= bp.alpha_max;
+                go += (st.take && !clamped) ? dal * st.G : 0.0f;
+                any |= st.take ? 1u : 0u;
+            }
+            if (__ballot(any != 0) != 0) {
+                const float t = wave_sum(go);
+                if (lane == 0) unsafeAtomicAdd(grad_o + ((int64_t)item - item_base), t);
+            }
+            if (__ballot(live[0] || live[1] || live[2] || live[3]) == 0) {
+                wave_live = false;
+                break;
+            }
+        }
+    }
+}
+
+template <int CC, bool GY>
+static void launch_badj_cc(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
+                           const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
+                           const void* ypix, int ydtype, int C, int64_t N, const float* beta,
+                           BlendParams bp, float* grad_y, float* grad_o, hipStream_t s) {
+    dim3 grid((n_tiles + 3) / 4), block(256);
+    for (int c_off = 0; c_off < C; c_off += CC) {
+        if (ydtype == GSC_BF16)
+            hipLaunchKernelGGL((k_blend_adjoint<CC, true, GY>), grid, block, 0, s, views, n_views,
+                               n_tiles, ranges, pair_vals, rec0, rec1, ypix, C, c_off, N, beta, bp,
+                               grad_y, grad_o);
+        else
+            hipLaunchKernelGGL((k_blend_adjoint<CC, false, GY>), grid, block, 0, s, views, n_views,
+                               n_tiles, ranges, pair_vals, rec0, rec1, ypix, C, c_off, N, beta, bp,
+                               grad_y, grad_o);
+    }
+}
+
+template <bool GY>
+static void launch_badj(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
+                        const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
+                        const void* ypix, int ydtype, int C, int64_t N, const float* beta,
+                        BlendParams bp, float* grad_y, float* grad_o, hipStream_t s) {
+    switch (accumulate_chunk(C)) {
+        case 1: launch_badj_cc<1, GY>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C, N, beta, bp, grad_y, grad_o, s); break;
+        case 2: launch_badj_cc<2, GY>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C, N, beta, bp, grad_y, grad_o, s); break;
+        case 3: launch_badj_cc<3, GY>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C, N, beta, bp, grad_y, grad_o, s); break;
+        case 4: launch_badj_cc<4, GY>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C, N, beta, bp, grad_y, grad_o, s); break;
+        case 8: launch_badj_cc<8, GY>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C, N, beta, bp, grad_y, grad_o, s); break;
+        default: launch_badj_cc<16, GY>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C, N, beta, bp, grad_y, grad_o, s); break;
+    }
+}
+
+void launch_blend_adjoint(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
+                          const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
+                          const void* ypix, int ydtype, int C, int64_t N, const float* beta,
+                          BlendParams bp, float* grad_y, float* grad_o, hipStream_t s) {
+    if (n_tiles == 0 || (!grad_y && !grad_o)) return;
+    if (grad_y)
+        launch_badj<true>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C, N,
+                          beta, bp, grad_y, grad_o, s);
+    else
+        launch_badj<false>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C, N,
+                           beta, bp, grad_y, grad_o, s);
+}
+
+// grad_coeffs[g][m][c] = sum_j phi_gj[m] S_gj[c] from the per-view sums
+// VS[j][g] = (V_gj, S_gj[0..C)) (per_view), or phi = Y0 and one summed slot
+// per Gaussian (L = 0).  One thread per (Gaussian, CH channels); FP64 sums.
+template <int L>
+constexpr int fold_rhs_channels() { return L >= 3 ? 2 : 4; }
+
+template <int L>
+__global__ void k_fold_rhs(const ViewInfo* __restrict__ views, int n_views,
+                           const float* __restrict__ means, const float* __restrict__ VS,
+                           int per_view, int64_t N, int C, float* __restrict__ out) {
+    constexpr int NB = (L + 1) * (L + 1);
+    constexpr int CH = fold_rhs_channels<L>();
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c0 = blockIdx.y * CH;
+    if (g >= N) return;
+    const int stride = C + 1;
+    double acc[NB][CH];
+#pragma unroll
+    for (int m = 0; m < NB; ++m)
+#pragma unroll
+        for (int c = 0; c < CH; ++c) acc[m][c] = 0.0;
+    const int nv = per_view ? n_views : 1;
+    const float mx = means[3 * g], my = means[3 * g + 1], mz = means[3 * g + 2];
+    for (int v = 0; v < nv; ++v) {
+        const float* slot = VS + ((per_view ? (int64_t)v * N : 0) + g) * stride;
+        if (slot[0] == 0.0f) continue;  // no contribution in this view
+        float phi[NB];
+        if (per_view) {
+            const ViewInfo& Vw = views[v];
+            const float dx = mx - (float)Vw.centre[0], dy = my - (float)Vw.centre[1],
+                        dz = mz - (float)Vw.centre[2];
+            const float inv = rsqrtf(dx * dx + dy * dy + dz * dz);
+            sh_eval<float, L>(dx * inv, dy * inv, dz * inv, phi);
+        } else {
+            sh_eval<float, L>(0.0f, 0.0f, 1.0f, phi);
+        }
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const double sc = (c0 + c < C) ? (double)slot[1 + c0 + c] : 0.0;
+#pragma unroll
+            for (int m = 0; m < NB; ++m) acc[m][c] = fma((double)phi[m], sc, acc[m][c]);
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < NB; ++m)
+#pragma unroll
+        for (int c = 0; c < CH; ++c)
+            if (c0 + c < C) out[(g * NB + m) * C + c0 + c] = (float)acc[m][c];
+}
+
+template <int L>
+static void launch_fold_rhs_l(const ViewInfo* views, int n_views, const float* means, const float* VS,
+                              bool per_view, int64_t N, int C, float* out, hipStream_t s) {
+    constexpr int CH = fold_rhs_channels<L>();
+    dim3 grid((unsigned)((N + 127) / 128), (unsigned)((C + CH - 1) / CH)), block(128);
+    hipLaunchKernelGGL(k_fold_rhs<L>, grid, block, 0, s, views, n_views, means, VS, (int)per_view, N, C, out);
+}
+
+void launch_fold_rhs(const ViewInfo* views, int n_views, const float* means, const float* VS,
+                     bool per_view, int64_t N, int C, int sh_deg, float* out, hipStream_t s) {
+    if (N <= 0) return;
+    switch (sh_deg) {
+        case 0: launch_fold_rhs_l<0>(views, n_views, means, VS, per_view, N, C, out, s); break;
+        case 1: launch_fold_rhs_l<1>(views, n_views, means, VS, per_view, N, C, out, s); break;
+        case 2: launch_fold_rhs_l<2>(views, n_views, means, VS, per_view, N, C, out, s); break;
+        default: launch_fold_rhs_l<3>(views, n_views, means, VS, per_view, N, C, out, s); break;
+    }
+}
+
+}  // namespace gsc

@@ -76,12 +76,22 @@ __device__ __forceinline__ double quad_bcast_rt(double x, int o) {
 // i = 4k + r of A (lower triangle, FP64) and of B (four channels at a time).
 // The Cholesky factor is formed in registers (column j broadcast within the
 // quad), then L and B go through LDS so each lane can substitute one channel.
-template <int L>
+//
+// ADJ: adjoint solve for the backward pass.  VS then holds only the per-view
+// visibilities (stride 1); the right-hand sides are read from `rhs`
+// (dL/dc, [N][NB][C]) instead of being folded, the solution
+// Bbar = (A + w Lambda)^{-1} dL/dc is written to `out`, and
+// rho_g = sum_{m,c} lambda_m Bbar[m][c] cin[m][c] (cin = the forward
+// coefficients) to rho[g].
+template <int L, bool ADJ>
 __global__ __launch_bounds__(64) void k_fold_solve(const ViewInfo* __restrict__ views, int n_views,
                                                    const float* __restrict__ means,
-                                                   const float* __restrict__ VS, int64_t N, int C,
-                                                   LamNB lam, float kappa_max,
+                                                   const float* __restrict__ VS, int vs_stride,
+                                                   int64_t N, int C, LamNB lam, float kappa_max,
+                                                   const float* __restrict__ rhs,
+                                                   const float* __restrict__ cin,
                                                    float* __restrict__ coeffs,
+                                                   float* __restrict__ rho,
                                                    uint8_t* __restrict__ status,
                                                    float* __restrict__ wout,
                                                    unsigned int* __restrict__ ill_count) {
@@ -96,7 +106,7 @@ __global__ __launch_bounds__(64) void k_fold_solve(const ViewInfo* __restrict__ 
     const int64_t g0 = (int64_t)blockIdx.x * 16;
     const int64_t g = g0 + q;
     const bool valid = g < N;
-    const int stride = C + 1;
+    const int stride = vs_stride;
     const int per_view = 16 * stride;
     const int vch = max(1, min(kMaxStageViews, kStageFloats / per_view));
     const int64_t lim = N * (int64_t)stride;
@@ -113,6 +123,7 @@ __global__ __launch_bounds__(64) void k_fold_solve(const ViewInfo* __restrict__ 
     double dinv[NB];       // reciprocal diagonal of the factor
     bool failed = false;
     double wsum = 0.0;
+    double rho_part = 0.0;
     for (int c0 = 0; c0 < C; c0 += 4) {
         const bool firstc = c0 == 0;
         double accB[RPL][4];
@@ -125,7 +136,7 @@ __global__ __launch_bounds__(64) void k_fold_solve(const ViewInfo* __restrict__ 
             for (int c = 0; c < 4; ++c) accB[k][c] = 0.0;
         }
         double wv = 0.0;
-        for (int v0 = 0; v0 < n_views; v0 += vch) {
+        for (int v0 = 0; v0 < ((!ADJ || firstc) ? n_views : 0); v0 += vch) {
             const int nv = min(vch, n_views - v0);
             __syncthreads();
             // coalesced staging: for each view the block's 16 slots are
@@ -166,7 +177,7 @@ __global__ __launch_bounds__(64) void k_fold_solve(const ViewInfo* __restrict__ 
                 const double Vd = Vf;
                 double S[4];
 #pragma unroll
-                for (int c = 0; c < 4; ++c) S[c] = (c0 + c < C) ? (double)slot[1 + c0 + c] : 0.0;
+                for (int c = 0; c < 4; ++c) S[c] = (!ADJ && c0 + c < C) ? (double)slot[1 + c0 + c] : 0.0;
 #pragma unroll
                 for (int k = 0; k < RPL; ++k) {
                     // phi of this lane's row 4k + r, selected arithmetically
@@ -180,8 +191,10 @@ __global__ __launch_bounds__(64) void k_fold_solve(const ViewInfo* __restrict__ 
                         for (int j = 0; j < NB; ++j)
                             if (j < 4 * k + 4) accA[k][j] = fma(vo, phi[j], accA[k][j]);
                     }
+                    if constexpr (!ADJ) {
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) accB[k][c] = fma(own, S[c], accB[k][c]);
+                        for (int c = 0; c < 4; ++c) accB[k][c] = fma(own, S[c], accB[k][c]);
+                    }
                 }
                 wv += Vd;
             }
@@ -221,6 +234,15 @@ __global__ __launch_bounds__(64) void k_fold_solve(const ViewInfo* __restrict__ 
                             accA[k][m] = act ? fma(-accA[k][j], lmj, accA[k][m]) : accA[k][m];
                         }
                 }
+            }
+        }
+        if constexpr (ADJ) {
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) {
+                const int i = 4 * k + r;
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    accB[k][c] = (valid && i < NB && c0 + c < C) ? (double)rhs[(g * NB + i) * C + c0 + c] : 0.0;
             }
         }
         // factor (packed lower, diagonal stored as 1/L_ii) and right-hand sides to LDS
@@ -263,8 +285,19 @@ __global__ __launch_bounds__(64) void k_fold_solve(const ViewInfo* __restrict__ 
             const bool zero = wsum == 0.0 || failed;
             float* out = coeffs + g * NB * C;
             for (int i = 0; i < NB; ++i) out[i * C + c] = zero ? 0.0f : (float)x[i * 4];
+            if constexpr (ADJ) {
+                if (!zero)
+                    for (int i = 0; i < NB; ++i)
+                        rho_part = fma(lam.v[i] * x[i * 4], (double)cin[(g * NB + i) * C + c], rho_part);
+            }
         }
         __syncthreads();
+    }
+    if constexpr (ADJ) {
+        rho_part += __shfl_xor(rho_part, 1, 64);
+        rho_part += __shfl_xor(rho_part, 2, 64);
+        if (valid && r == 0) rho[g] = (float)rho_part;
+        return;
     }
     if (valid && r == 0) {
         if (wout) wout[g] = (float)wsum;
@@ -283,7 +316,7 @@ __global__ __launch_bounds__(64) void k_fold_solve(const ViewInfo* __restrict__ 
             const double kap = (imax / imin) * (imax / imin);
             if (kap > (double)kappa_max) {
                 st = GSC_G_ILL_COND;
-                atomicAdd(ill_count, 1u);
+                if (ill_count) atomicAdd(ill_count, 1u);
             }
         }
         if (status) status[g] = st;
@@ -312,10 +345,59 @@ void launch_fold_solve(const ViewInfo* views, int n_views, const float* means, c
     int nb = (sh_deg + 1) * (sh_deg + 1);
     for (int i = 0; i < nb; ++i) lam.v[i] = lam_nb[i];
     dim3 grid((unsigned)((N + 15) / 16)), block(64);
+    const float* nf = nullptr;
+    float* nw = nullptr;
     switch (sh_deg) {
-        case 1: hipLaunchKernelGGL(k_fold_solve<1>, grid, block, 0, s, views, n_views, means, VS, N, C, lam, kappa_max, coeffs, status, wout, ill_count); break;
-        case 2: hipLaunchKernelGGL(k_fold_solve<2>, grid, block, 0, s, views, n_views, means, VS, N, C, lam, kappa_max, coeffs, status, wout, ill_count); break;
-        default: hipLaunchKernelGGL(k_fold_solve<3>, grid, block, 0, s, views, n_views, means, VS, N, C, lam, kappa_max, coeffs, status, wout, ill_count); break;
+        case 1: hipLaunchKernelGGL((k_fold_solve<1, false>), grid, block, 0, s, views, n_views, means, VS, C + 1, N, C, lam, kappa_max, nf, nf, coeffs, nw, status, wout, ill_count); break;
+        case 2: hipLaunchKernelGGL((k_fold_solve<2, false>), grid, block, 0, s, views, n_views, means, VS, C + 1, N, C, lam, kappa_max, nf, nf, coeffs, nw, status, wout, ill_count); break;
+        default: hipLaunchKernelGGL((k_fold_solve<3, false>), grid, block, 0, s, views, n_views, means, VS, C + 1, N, C, lam, kappa_max, nf, nf, coeffs, nw, status, wout, ill_count); break;
+    }
+}
+
+// L = 0 adjoint: A_g + w_g Lambda = w_g (Y0^2 + lambda_0).
+__global__ void k_adjoint_dc(const float* __restrict__ W, int64_t N, int C, double lam0,
+                             const float* __restrict__ gc, const float* __restrict__ cin,
+                             float* __restrict__ bbar, float* __restrict__ rho) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= N) return;
+    const double w = W[g];
+    double r = 0.0;
+    for (int c = 0; c < C; ++c) {
+        const double b = w == 0.0 ? 0.0 : (double)gc[g * C + c] / (w * (kY0 * kY0 + lam0));
+        bbar[g * C + c] = (float)b;
+        r += lam0 * b * (double)cin[g * C + c];
+    }
+    rho[g] = (float)r;
+}
+
+void launch_adjoint_solve(const ViewInfo* views, int n_views, const float* means, const float* V,
+                          bool per_view, int64_t N, int C, int sh_deg, const double* lam_nb,
+                          const float* grad_coeffs, const float* coeffs, float* bbar, float* rho,
+                          float* w_scratch, hipStream_t s) {
+    if (N <= 0) return;
+    if (sh_deg == 0) {
+        const float* src = V;
+        if (per_view) {
+            hipLaunchKernelGGL(k_sum_views, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, V,
+                               n_views, N, 1, w_scratch);
+            src = w_scratch;
+        }
+        hipLaunchKernelGGL(k_adjoint_dc, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, src, N,
+                           C, lam_nb[0], grad_coeffs, coeffs, bbar, rho);
+        return;
+    }
+    LamNB lam;
+    for (int i = 0; i < kMaxNb; ++i) lam.v[i] = 0.0;
+    int nb = (sh_deg + 1) * (sh_deg + 1);
+    for (int i = 0; i < nb; ++i) lam.v[i] = lam_nb[i];
+    dim3 grid((unsigned)((N + 15) / 16)), block(64);
+    uint8_t* ns = nullptr;
+    float* nw = nullptr;
+    unsigned int* ni = nullptr;
+    switch (sh_deg) {
+        case 1: hipLaunchKernelGGL((k_fold_solve<1, true>), grid, block, 0, s, views, n_views, means, V, 1, N, C, lam, 0.0f, grad_coeffs, coeffs, bbar, rho, ns, nw, ni); break;
+        case 2: hipLaunchKernelGGL((k_fold_solve<2, true>), grid, block, 0, s, views, n_views, means, V, 1, N, C, lam, 0.0f, grad_coeffs, coeffs, bbar, rho, ns, nw, ni); break;
+        default: hipLaunchKernelGGL((k_fold_solve<3, true>), grid, block, 0, s, views, n_views, means, V, 1, N, C, lam, 0.0f, grad_coeffs, coeffs, bbar, rho, ns, nw, ni); break;
     }
 }
 

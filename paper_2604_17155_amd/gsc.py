@@ -43,7 +43,7 @@ class GscOptions(ct.Structure):
 
 
 GSC_FLAG_PROFILE = 2
-STAGES = ["project", "depth_sort", "scan", "emit", "tile_sort", "blend", "solve", "reserved"]
+STAGES = ["project", "depth_sort", "scan", "emit", "tile_sort", "blend", "solve", "blend_adjoint"]
 
 
 class GscStats(ct.Structure):
@@ -52,7 +52,7 @@ class GscStats(ct.Structure):
                 ("stage_ms", ct.c_float * 8), ("stage_launches", ct.c_uint32 * 8)]
 
     def stage_dict(self):
-        return {n: float(self.stage_ms[i]) for i, n in enumerate(STAGES[:7])}
+        return {n: float(self.stage_ms[i]) for i, n in enumerate(STAGES)}
 
 
 class GscExtras(ct.Structure):
@@ -93,6 +93,11 @@ def load(path: Optional[str] = None):
     lib.gsc_colorize_ex.restype = ct.c_int
     lib.gsc_render.argtypes = [P, P, P, P, P, i64, P, i32, P, i32, i32, P, P]
     lib.gsc_render.restype = ct.c_int
+    lib.gsc_colorize_backward.argtypes = [P, P, P, P, P, i64, P, i32, P, i32, i32, i32, P, i32, P, P,
+                                          P, P, P]
+    lib.gsc_colorize_backward.restype = ct.c_int
+    lib.gsc_render_backward.argtypes = [P, P, P, P, P, i64, P, i32, P, i32, i32, P, P, P, P]
+    lib.gsc_render_backward.restype = ct.c_int
     lib.gsc_get_stats.argtypes = [P, ct.POINTER(GscStats)]
     lib.gsc_get_stats.restype = ct.c_int
     lib.gsc_last_error.argtypes = []
@@ -233,8 +238,7 @@ class Context:
         N = int(means.shape[0])
         nb, C = int(coeffs.shape[1]), int(coeffs.shape[2])
         sh_deg = int(round(nb ** 0.5)) - 1
-        rows = sum(int(c.width) * int(c.height) for c in cams) if offsets is None else \
-            max(int(o) + int(c.width) * int(c.height) for o, c in zip(offsets, cams))
+        rows = _rows(cams, offsets)
         if images is None:
             images = torch.empty((rows, C), dtype=torch.float32, device=means.device)
         cam_arr = make_cameras(cams, offsets)
@@ -243,6 +247,71 @@ class Context:
                                  _ptr(images), _stream_ptr(stream))
         _check(self.lib, st)
         return images
+
+
+    def colorize_backward(self, means, scales, quats, opacities, cams, targets, sh_deg: int, lam,
+                          coeffs, grad_coeffs, want_targets: bool = True, want_opacities: bool = True,
+                          offsets=None, stream=None):
+        """Adjoint of colorize at `coeffs` for dL/dcoeffs = grad_coeffs.  Returns
+        (grad_targets [rows, C] float32 or None, grad_opacities [N] float32 or None)."""
+        import torch
+        N = int(means.shape[0])
+        C = int(targets.shape[1])
+        td = _tdtype(targets)
+        dev = means.device
+        gt = None
+        if want_targets:
+            # the library writes the camera rows; rows past the last camera stay zero
+            gt = torch.empty((int(targets.shape[0]), C), dtype=torch.float32, device=dev)
+            used = _rows(cams, offsets)
+            if used < gt.shape[0]:
+                gt[used:].zero_()
+        go = torch.empty((N,), dtype=torch.float32, device=dev) if want_opacities else None
+        lam_a = (ct.c_float * len(lam))(*[float(v) for v in lam])
+        cam_arr = make_cameras(cams, offsets)
+        st = self.lib.gsc_colorize_backward(self.handle, _ptr(means), _ptr(scales), _ptr(quats),
+                                            _ptr(opacities), N, cam_arr, len(cams), _ptr(targets), td,
+                                            C, sh_deg, lam_a, len(lam), _ptr(coeffs),
+                                            _ptr(grad_coeffs), _ptr(gt), _ptr(go), _stream_ptr(stream))
+        _check(self.lib, st)
+        return gt, go
+
+    def render_backward(self, means, scales, quats, opacities, cams, coeffs, grad_images,
+                        want_coeffs: bool = True, want_opacities: bool = True, offsets=None,
+                        stream=None):
+        """Adjoint of render for dL/dimages = grad_images.  Returns
+        (grad_coeffs [N,(L+1)^2,C] or None, grad_opacities [N] or None)."""
+        import torch
+        N = int(means.shape[0])
+        nb, C = int(coeffs.shape[1]), int(coeffs.shape[2])
+        sh_deg = int(round(nb ** 0.5)) - 1
+        dev = means.device
+        gc = torch.empty((N, nb, C), dtype=torch.float32, device=dev) if want_coeffs else None
+        go = torch.empty((N,), dtype=torch.float32, device=dev) if want_opacities else None
+        cam_arr = make_cameras(cams, offsets)
+        st = self.lib.gsc_render_backward(self.handle, _ptr(means), _ptr(scales), _ptr(quats),
+                                          _ptr(opacities), N, cam_arr, len(cams), _ptr(coeffs), C,
+                                          sh_deg, _ptr(grad_images), _ptr(gc), _ptr(go),
+                                          _stream_ptr(stream))
+        _check(self.lib, st)
+        return gc, go
+
+
+def _rows(cams, offsets=None) -> int:
+    if not len(cams):
+        return 0
+    if offsets is None:
+        return sum(int(c.width) * int(c.height) for c in cams)
+    return max(int(o) + int(c.width) * int(c.height) for o, c in zip(offsets, cams))
+
+
+def _tdtype(targets) -> int:
+    import torch
+    if targets.dtype == torch.float32:
+        return GSC_F32
+    if targets.dtype == torch.bfloat16:
+        return GSC_BF16
+    raise ValueError("targets must be float32 or bfloat16")
 
 
 def scene_tensors(scene, device="cuda"):

@@ -133,3 +133,32 @@ def test_render_validation(lib):
 def test_binding_has_no_fallback(tmp_path):
     with pytest.raises(ImportError):
         gsc.load(str(tmp_path / "missing.so"))
+
+
+def test_backward_validation(lib):
+    ctx = _vctx()
+    cams = syn.circle_cams(2, 3.0, 16, 16)
+    arr = gsc.make_cameras(cams)
+    lam = (ct.c_float * 1)(1e-4)
+    cb = lib.gsc_colorize_backward
+    # valid: both outputs, or only one of them
+    assert cb(ctx.handle, FAKE, FAKE, FAKE, FAKE, 10, arr, 2, FAKE, 0, 3, 0, lam, 1, FAKE, FAKE,
+              FAKE, FAKE, None) == gsc.GSC_OK
+    assert cb(ctx.handle, FAKE, FAKE, FAKE, FAKE, 10, arr, 2, None, 0, 3, 0, lam, 1, FAKE, FAKE,
+              FAKE, None, None) == gsc.GSC_OK
+    # missing upstream gradient, missing targets when dL/do is wanted, bad channel count
+    assert cb(ctx.handle, FAKE, FAKE, FAKE, FAKE, 10, arr, 2, FAKE, 0, 3, 0, lam, 1, FAKE, None,
+              FAKE, FAKE, None) == gsc.GSC_ERR_INVALID_ARG
+    assert "grad_coeffs" in lib.gsc_last_error().decode()
+    assert cb(ctx.handle, FAKE, FAKE, FAKE, FAKE, 10, arr, 2, None, 0, 3, 0, lam, 1, FAKE, FAKE,
+              None, FAKE, None) == gsc.GSC_ERR_INVALID_ARG
+    assert cb(ctx.handle, FAKE, FAKE, FAKE, FAKE, 10, arr, 2, FAKE, 0, 0, 0, lam, 1, FAKE, FAKE,
+              FAKE, FAKE, None) == gsc.GSC_ERR_INVALID_ARG
+    rb = lib.gsc_render_backward
+    assert rb(ctx.handle, FAKE, FAKE, FAKE, FAKE, 10, arr, 2, FAKE, 3, 0, FAKE, FAKE, FAKE,
+              None) == gsc.GSC_OK
+    assert rb(ctx.handle, FAKE, FAKE, FAKE, FAKE, 10, arr, 2, FAKE, 3, 0, None, FAKE, FAKE,
+              None) == gsc.GSC_ERR_INVALID_ARG
+    assert "grad_images" in lib.gsc_last_error().decode()
+    assert rb(ctx.handle, FAKE, FAKE, FAKE, FAKE, 10, arr, 2, None, 3, 0, FAKE, FAKE, FAKE,
+              None) == gsc.GSC_ERR_INVALID_ARG
