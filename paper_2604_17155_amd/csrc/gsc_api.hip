@@ -216,7 +216,8 @@ BlendParams blend_params(const gsc_options& o) {
     return bp;
 }
 
-ViewInfo make_view(const gsc_camera& c) {
+// View j of a single scene of N Gaussians: per-view sums at slots j*N + g.
+ViewInfo make_view(const gsc_camera& c, int j, int64_t N) {
     ViewInfo v;
     memset(&v, 0, sizeof(v));
     memcpy(v.R, c.R, sizeof(v.R));
@@ -229,6 +230,10 @@ ViewInfo make_view(const gsc_camera& c) {
     v.tiles_x = (c.width + kTile - 1) / kTile;
     v.tiles_y = (c.height + kTile - 1) / kTile;
     v.pixel_offset = c.pixel_offset;
+    v.g_offset = 0;
+    v.vs_base = (int64_t)j * N;
+    v.n_gauss = (uint32_t)N;
+    v.scene = 0;
     return v;
 }
 
@@ -258,18 +263,20 @@ gsc_status bin_views(gsc_ctx* ctx, const std::vector<ViewInfo>& all, int v0, int
         GSC_HIP(hipHostMalloc((void**)&ctx->h_views, sizeof(ViewInfo) * (size_t)nv));
         ctx->h_views_cap = (size_t)nv;
     }
-    uint64_t tiles = 0;
+    uint64_t tiles = 0, items = 0;
     for (int k = 0; k < nv; ++k) {
         ViewInfo v = all[v0 + k];
         v.tile_base = (uint32_t)tiles;
+        v.item_base = (uint32_t)items;
         tiles += (uint64_t)v.tiles_x * v.tiles_y;
+        items += v.n_gauss;
         ctx->h_views[k] = v;
     }
     if (tiles >= 0xffffffffull) return fail(GSC_ERR_CAPACITY, "too many tiles in one batch");
+    if (items > kMaxItemsPerBatch) return fail(GSC_ERR_CAPACITY, "too many items in one batch");
     GSC_HIP(ctx->views.ensure(sizeof(ViewInfo) * (size_t)nv));
     GSC_HIP(hipMemcpyAsync(ctx->views.p, ctx->h_views, sizeof(ViewInfo) * (size_t)nv,
                            hipMemcpyHostToDevice, s));
-    const uint64_t items = (uint64_t)nv * (uint64_t)N;
     out->n_items = items;
     out->n_tiles = (uint32_t)tiles;
     const uint32_t ni = (uint32_t)items;
@@ -286,7 +293,7 @@ gsc_status bin_views(gsc_ctx* ctx, const std::vector<ViewInfo>& all, int v0, int
     const ViewInfo* dviews = ctx->views.as<ViewInfo>();
     {
         StageTimer t(ctx, s, GSC_STAGE_PROJECT);
-        launch_project(dviews, nv, means, ctx->cov.as<float>(), opac, N, bp, ctx->keys.as<uint32_t>(),
+        launch_project(dviews, nv, ni, means, ctx->cov.as<float>(), opac, bp, ctx->keys.as<uint32_t>(),
                        ctx->vals.as<uint32_t>(), ctx->counts.as<uint32_t>(), ctx->rec0.as<float4>(),
                        ctx->rec1.as<float4>(), s);
         GSC_LAUNCHED("project");
@@ -328,9 +335,9 @@ gsc_status bin_views(gsc_ctx* ctx, const std::vector<ViewInfo>& all, int v0, int
     GSC_HIP(ctx->pvals_alt.ensure(4 * pairs + 4));
     {
         StageTimer t(ctx, s, GSC_STAGE_EMIT);
-        launch_emit(dviews, ctx->vals.as<uint32_t>(), ctx->offsets.as<uint32_t>(),
+        launch_emit(dviews, nv, ctx->vals.as<uint32_t>(), ctx->offsets.as<uint32_t>(),
                     ctx->counts.as<uint32_t>(), ctx->rec0.as<float4>(),
-                    ctx->rec1.as<float4>(), bp, ni, N, (uint32_t)tiles, ctx->pkeys.as<uint32_t>(),
+                    ctx->rec1.as<float4>(), bp, ni, (uint32_t)tiles, ctx->pkeys.as<uint32_t>(),
                     ctx->pvals.as<uint32_t>(), s);
         GSC_LAUNCHED("emit");
     }
@@ -476,7 +483,7 @@ gsc_status gsc_colorize_ex(gsc_ctx* ctx, const float* means, const float* scales
     BlendParams bp = blend_params(ctx->opt);
     if ((st = ensure_common(ctx, scales, quats, N, s)) != GSC_OK) return st;
     std::vector<ViewInfo> all(n_cams);
-    for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j]);
+    for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j], j, N);
     const bool per_view = sh_deg > 0 || x_sums != nullptr;
     const uint64_t vs_words = (uint64_t)(per_view ? std::max(n_cams, 1) : 1) * (uint64_t)N * (uint64_t)(C + 1);
     GSC_HIP(ctx->vs.ensure(4 * vs_words));
@@ -486,9 +493,10 @@ gsc_status gsc_colorize_ex(gsc_ctx* ctx, const float* means, const float* scales
     st = for_view_batches(ctx, all, n_cams, means, opacities, N, bp, s,
                           [&](int v0, int nv, const Binned& bn) -> gsc_status {
         StageTimer t(ctx, s, GSC_STAGE_BLEND, (uint32_t)((C + accumulate_chunk(C) - 1) / accumulate_chunk(C)));
+        (void)v0;
         launch_accumulate(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
                           ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(),
-                          targets, tdtype, C, N, v0, per_view, bp, ctx->vs.as<float>(), d_counter,
+                          targets, tdtype, C, per_view, bp, ctx->vs.as<float>(), d_counter,
                           x_cnt, s);
         GSC_LAUNCHED("accumulate");
         return GSC_OK;
@@ -540,19 +548,19 @@ gsc_status gsc_render(gsc_ctx* ctx, const float* means, const float* scales, con
     BlendParams bp = blend_params(ctx->opt);
     if ((st = ensure_common(ctx, scales, quats, N, s)) != GSC_OK) return st;
     std::vector<ViewInfo> all(n_cams);
-    for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j]);
+    for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j], j, N);
     unsigned long long* d_counter = reinterpret_cast<unsigned long long*>(ctx->misc.p);
     st = for_view_batches(ctx, all, n_cams, means, opacities, N, bp, s,
                           [&](int v0, int nv, const Binned& bn) -> gsc_status {
         (void)v0;
         StageTimer t(ctx, s, GSC_STAGE_BLEND, 1 + (uint32_t)((C + 3) / 4));
         GSC_HIP(ctx->gamma.ensure(4 * (size_t)nv * (size_t)std::max<int64_t>(N, 1) * (size_t)C));
-        launch_view_colors(ctx->views.as<ViewInfo>(), nv, means, coeffs, N, C, sh_deg,
-                           ctx->gamma.as<float>(), s);
+        launch_view_colors(ctx->views.as<ViewInfo>(), nv, (uint32_t)bn.n_items, means, coeffs, C,
+                           sh_deg, ctx->gamma.as<float>(), s);
         GSC_LAUNCHED("view colors");
         launch_render(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
                       ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(),
-                      ctx->gamma.as<float>(), C, N, bp, images, d_counter, s);
+                      ctx->gamma.as<float>(), C, bp, images, d_counter, s);
         GSC_LAUNCHED("render");
         return GSC_OK;
     });
@@ -588,7 +596,7 @@ gsc_status gsc_colorize_backward(gsc_ctx* ctx, const float* means, const float* 
     BlendParams bp = blend_params(ctx->opt);
     if ((st = ensure_common(ctx, scales, quats, N, s)) != GSC_OK) return st;
     std::vector<ViewInfo> all(n_cams);
-    for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j]);
+    for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j], j, N);
     // 1. visibilities V_gj (the normal matrices depend on the weights only)
     const bool per_view = sh_deg > 0;
     const uint64_t v_words = (uint64_t)(per_view ? n_cams : 1) * (uint64_t)N;
@@ -599,9 +607,10 @@ gsc_status gsc_colorize_backward(gsc_ctx* ctx, const float* means, const float* 
     st = for_view_batches(ctx, all, n_cams, means, opacities, N, bp, s,
                           [&](int v0, int nv, const Binned& bn) -> gsc_status {
         StageTimer t(ctx, s, GSC_STAGE_BLEND);
+        (void)v0;
         launch_accumulate_weights(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
                                   ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(),
-                                  ctx->rec1.as<float4>(), N, v0, per_view, bp, ctx->vs.as<float>(),
+                                  ctx->rec1.as<float4>(), per_view, bp, ctx->vs.as<float>(),
                                   d_counter, s);
         GSC_LAUNCHED("accumulate weights");
         last = bn;
@@ -627,12 +636,12 @@ gsc_status gsc_colorize_backward(gsc_ctx* ctx, const float* means, const float* 
         (void)v0;
         GSC_HIP(ctx->gamma.ensure(4 * (size_t)nv * (size_t)N * (size_t)(C + 1)));
         StageTimer t(ctx, s, GSC_STAGE_BLEND_ADJOINT);
-        launch_view_adjoint(ctx->views.as<ViewInfo>(), nv, means, coeffs, d_bbar, d_rho, N, C, sh_deg,
-                            false, ctx->gamma.as<float>(), s);
+        launch_view_adjoint(ctx->views.as<ViewInfo>(), nv, (uint32_t)bn.n_items, means, coeffs, d_bbar,
+                            d_rho, C, sh_deg, false, ctx->gamma.as<float>(), s);
         GSC_LAUNCHED("view adjoint");
         launch_blend_adjoint(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
                              ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(),
-                             targets, tdtype, C, N, ctx->gamma.as<float>(), bp, grad_targets,
+                             targets, tdtype, C, ctx->gamma.as<float>(), bp, grad_targets,
                              grad_opacities, s);
         GSC_LAUNCHED("blend adjoint");
         return GSC_OK;
@@ -672,7 +681,7 @@ gsc_status gsc_render_backward(gsc_ctx* ctx, const float* means, const float* sc
     BlendParams bp = blend_params(ctx->opt);
     if ((st = ensure_common(ctx, scales, quats, N, s)) != GSC_OK) return st;
     std::vector<ViewInfo> all(n_cams);
-    for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j]);
+    for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j], j, N);
     const bool per_view = sh_deg > 0;
     const uint64_t vs_words = (uint64_t)(per_view ? n_cams : 1) * (uint64_t)N * (uint64_t)(C + 1);
     if (grad_coeffs) {
@@ -686,21 +695,22 @@ gsc_status gsc_render_backward(gsc_ctx* ctx, const float* means, const float* sc
             // dL/dc folds sum_p w (dL/dimages_p) per (view, Gaussian): the
             // forward accumulate with dL/dimages in place of the targets
             StageTimer t(ctx, s, GSC_STAGE_BLEND);
+            (void)v0;
             launch_accumulate(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
                               ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(),
-                              grad_images, GSC_F32, C, N, v0, per_view, bp, ctx->vs.as<float>(),
+                              grad_images, GSC_F32, C, per_view, bp, ctx->vs.as<float>(),
                               d_counter, nullptr, s);
             GSC_LAUNCHED("accumulate");
         }
         if (grad_opacities) {
             GSC_HIP(ctx->gamma.ensure(4 * (size_t)nv * (size_t)N * (size_t)(C + 1)));
             StageTimer t(ctx, s, GSC_STAGE_BLEND_ADJOINT);
-            launch_view_adjoint(ctx->views.as<ViewInfo>(), nv, means, coeffs, nullptr, nullptr, N, C,
-                                sh_deg, true, ctx->gamma.as<float>(), s);
+            launch_view_adjoint(ctx->views.as<ViewInfo>(), nv, (uint32_t)bn.n_items, means, coeffs,
+                                nullptr, nullptr, C, sh_deg, true, ctx->gamma.as<float>(), s);
             GSC_LAUNCHED("view colours");
             launch_blend_adjoint(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
                                  ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(),
-                                 ctx->rec1.as<float4>(), grad_images, GSC_F32, C, N,
+                                 ctx->rec1.as<float4>(), grad_images, GSC_F32, C,
                                  ctx->gamma.as<float>(), bp, nullptr, grad_opacities, s);
             GSC_LAUNCHED("blend adjoint");
         }

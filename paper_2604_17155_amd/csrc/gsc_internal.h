@@ -13,7 +13,10 @@ constexpr int kTileShift = 4;
 constexpr int kMaxNb = 16;          // (L+1)^2 for L <= 3
 constexpr int kMaxC = 64;
 
-// One view as the kernels see it.
+// One view as the kernels see it.  A batch of views may mix scenes: each view
+// names its scene's Gaussians [g_offset, g_offset + n_gauss) in the
+// concatenated arrays.  The (view, Gaussian) items of a batch are numbered
+// view by view: item = item_base + local Gaussian index.
 struct ViewInfo {
     float R[9];
     float t[3];
@@ -22,9 +25,24 @@ struct ViewInfo {
     int32_t width, height;
     int32_t tiles_x, tiles_y;
     uint32_t tile_base;    // first global tile id of this view within its batch
-    uint32_t pad;
+    uint32_t item_base;    // first item of this view within its batch
     int64_t pixel_offset;  // first target row
+    int64_t g_offset;      // first Gaussian of the view's scene
+    int64_t vs_base;       // first per-view sum slot of this view (per-view layouts)
+    uint32_t n_gauss;      // Gaussians of the view's scene
+    uint32_t scene;        // scene index
 };
+
+// View of a batch item (binary search on item_base; n_views >= 1).
+__device__ inline int find_view_item(const ViewInfo* __restrict__ views, int n_views, uint32_t item) {
+    int lo = 0, hi = n_views - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (views[mid].item_base <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
 
 // Blend constants in the form the kernels use.
 struct BlendParams {
@@ -46,17 +64,18 @@ constexpr uint32_t kItemMask = (1u << kItemBits) - 1u;
 // ---- kernels launched from gsc_api.hip ----------------------------------
 void launch_cov3d(const float* scales, const float* quats, float* cov, int64_t N, hipStream_t s);
 
-void launch_project(const ViewInfo* views, int n_views, const float* means, const float* cov,
-                    const float* opac, int64_t N, BlendParams bp, uint32_t* keys, uint32_t* vals,
-                    uint32_t* counts, float4* rec0, float4* rec1, hipStream_t s);
+// One thread per batch item (n_items = sum of n_gauss over the batch's views).
+void launch_project(const ViewInfo* views, int n_views, uint32_t n_items, const float* means,
+                    const float* cov, const float* opac, BlendParams bp, uint32_t* keys,
+                    uint32_t* vals, uint32_t* counts, float4* rec0, float4* rec1, hipStream_t s);
 
 void launch_gather_counts(const uint32_t* sorted_vals, const uint32_t* counts, uint32_t* out,
                           uint32_t n, hipStream_t s);
 
-void launch_emit(const ViewInfo* views, const uint32_t* sorted_vals, const uint32_t* offsets,
-                 const uint32_t* counts, const float4* rec0, const float4* rec1, BlendParams bp,
-                 uint32_t n_items, int64_t N, uint32_t n_tiles, uint32_t* pair_keys,
-                 uint32_t* pair_vals, hipStream_t s);
+void launch_emit(const ViewInfo* views, int n_views, const uint32_t* sorted_vals,
+                 const uint32_t* offsets, const uint32_t* counts, const float4* rec0,
+                 const float4* rec1, BlendParams bp, uint32_t n_items, uint32_t n_tiles,
+                 uint32_t* pair_keys, uint32_t* pair_vals, hipStream_t s);
 
 // Sum of n uint32 counts into *out (u64, must be zeroed).
 void launch_sum_u64(const uint32_t* counts, uint32_t n, unsigned long long* out, hipStream_t s);
@@ -82,21 +101,20 @@ void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* va
 // Channels per accumulate launch for C channels (launches = ceil(C / chunk)).
 int accumulate_chunk(int C);
 
-// Accumulate V_gj and S_gj (per view when per_view, else summed over views).
+// Accumulate V_gj and S_gj into slot (view.vs_base + g) when per_view, else
+// into slot (view.g_offset + g), summed over views; slots hold C+1 floats.
 void launch_accumulate(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
                        const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
-                       const void* targets, int tdtype, int C, int64_t N, int view_first,
-                       bool per_view, BlendParams bp, float* VS, unsigned long long* counter,
-                       uint32_t* gcount, hipStream_t s);
+                       const void* targets, int tdtype, int C, bool per_view, BlendParams bp,
+                       float* VS, unsigned long long* counter, uint32_t* gcount, hipStream_t s);
 
-// Per-view colour gamma[v][g][c] = sum_m coeffs[g][m][c] phi_m(dir_gv).
-void launch_view_colors(const ViewInfo* views, int n_views, const float* means,
-                        const float* coeffs, int64_t N, int C, int sh_deg, float* gamma,
-                        hipStream_t s);
+// Per item colour gamma[item][c] = sum_m coeffs[g][m][c] phi_m(dir_gv).
+void launch_view_colors(const ViewInfo* views, int n_views, uint32_t n_items, const float* means,
+                        const float* coeffs, int C, int sh_deg, float* gamma, hipStream_t s);
 
 void launch_render(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
                    const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
-                   const float* gamma, int C, int64_t N, BlendParams bp, float* images,
+                   const float* gamma, int C, BlendParams bp, float* images,
                    unsigned long long* counter, hipStream_t s);
 
 // Fold the per-view sums into the regularised normal equations and solve.
@@ -108,11 +126,11 @@ void launch_fold_solve(const ViewInfo* views, int n_views, const float* means, c
                        float kappa_max, float* coeffs, uint8_t* status, float* wout,
                        float* dc_scratch, unsigned int* ill_count, hipStream_t s);
 
-// Weights-only accumulate: V[(view) * N + g] += sum_p w (stride 1).
+// Weights-only accumulate: V[slot] += sum_p w (stride 1; slots as in launch_accumulate).
 void launch_accumulate_weights(const ViewInfo* views, int n_views, uint32_t n_tiles,
                                const uint2* ranges, const uint32_t* pair_vals, const float4* rec0,
-                               const float4* rec1, int64_t N, int view_first, bool per_view,
-                               BlendParams bp, float* V, unsigned long long* counter, hipStream_t s);
+                               const float4* rec1, bool per_view, BlendParams bp, float* V,
+                               unsigned long long* counter, hipStream_t s);
 
 // Adjoint solve: bbar = (A_g + w_g Lambda)^{-1} grad_coeffs and
 // rho_g = sum lambda_m bbar[m][c] coeffs[m][c].  V holds per-view
@@ -123,19 +141,19 @@ void launch_adjoint_solve(const ViewInfo* views, int n_views, const float* means
                           const float* grad_coeffs, const float* coeffs, float* bbar, float* rho,
                           float* w_scratch, hipStream_t s);
 
-// Per (view, Gaussian) adjoint colours: beta [n_views][N][C+1] = (beta_gj, delta_gj).
+// Per item adjoint colours: beta [item][C+1] = (beta_gj, delta_gj).
 // render: beta = c^T phi, delta = 0.  Otherwise beta = bbar^T phi and
 // delta = beta^T (c^T phi) + rho_g.
-void launch_view_adjoint(const ViewInfo* views, int n_views, const float* means, const float* coeffs,
-                         const float* bbar, const float* rho, int64_t N, int C, int sh_deg,
-                         bool render, float* beta, hipStream_t s);
+void launch_view_adjoint(const ViewInfo* views, int n_views, uint32_t n_items, const float* means,
+                         const float* coeffs, const float* bbar, const float* rho, int C,
+                         int sh_deg, bool render, float* beta, hipStream_t s);
 
 // Blend adjoint over the binned tiles: grad_y[row][c] = sum_g w beta (every
 // pixel of every view written, if grad_y) and grad_o[g] += dL/do (atomics, if grad_o).
 void launch_blend_adjoint(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
                           const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
-                          const void* ypix, int ydtype, int C, int64_t N, const float* beta,
-                          BlendParams bp, float* grad_y, float* grad_o, hipStream_t s);
+                          const void* ypix, int ydtype, int C, const float* beta, BlendParams bp,
+                          float* grad_y, float* grad_o, hipStream_t s);
 
 // grad_coeffs[g][m][c] = sum_j phi_gj[m] S_gj[c] from per-view sums [n_views][N][C+1].
 void launch_fold_rhs(const ViewInfo* views, int n_views, const float* means, const float* VS,

@@ -20,8 +20,8 @@ template <int CC, bool BF16>
 __global__ __launch_bounds__(256) void k_accumulate(
     const ViewInfo* __restrict__ views, int n_views, uint32_t n_tiles, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ pair_vals, const float4* __restrict__ rec0,
-    const float4* __restrict__ rec1, const void* __restrict__ targets, int C, int c_off, int64_t N,
-    int view_first, int per_view, BlendParams bp, float* __restrict__ VS,
+    const float4* __restrict__ rec1, const void* __restrict__ targets, int C, int c_off,
+    int per_view, BlendParams bp, float* __restrict__ VS,
     unsigned long long* __restrict__ counter, uint32_t* __restrict__ gcount) {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t tile = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -51,8 +51,9 @@ __global__ __launch_bounds__(256) void k_accumulate(
     const uint2 rg = ranges[tile];
     uint32_t cnt = 0;
     bool wave_live = __ballot(live[0] || live[1] || live[2] || live[3]) != 0;
-    const int64_t vs_view = per_view ? (int64_t)(view_first + vloc) * N : 0;
-    const int64_t item_base = (int64_t)vloc * N;  // item = vloc * N + g
+    // item = V.item_base + g (g local to the view's scene)
+    const int64_t item_base = V.item_base;
+    const int64_t slot_base = per_view ? V.vs_base : V.g_offset;
     const bool first_chunk = c_off == 0;
 
     const float qlim = (float)(kExp2Scale * (double)bp.cut2);  // q <= cut2  <=>  q2 >= qlim
@@ -106,9 +107,9 @@ __global__ __launch_bounds__(256) void k_accumulate(
             if (__ballot(nh != 0) != 0) {
                 if (gcount != nullptr && first_chunk) {
                     const uint32_t tn = wave_sum_u32(nh);
-                    if (lane == 0) atomicAdd(gcount + g, tn);
+                    if (lane == 0) atomicAdd(gcount + V.g_offset + g, tn);
                 }
-                float* slot = VS + (vs_view + g) * (int64_t)stride;
+                float* slot = VS + (slot_base + g) * (int64_t)stride;
                 if constexpr (CC == 0) {
                     const float tv = wave_sum(sv);
                     if (lane == 0) unsafeAtomicAdd(slot, tv);
@@ -154,19 +155,18 @@ __global__ __launch_bounds__(256) void k_accumulate(
 template <int CC>
 static void launch_acc_cc(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
                           const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
-                          const void* targets, int tdtype, int C, int64_t N, int view_first,
-                          bool per_view, BlendParams bp, float* VS, unsigned long long* counter,
-                          uint32_t* gcount, hipStream_t s) {
+                          const void* targets, int tdtype, int C, bool per_view, BlendParams bp,
+                          float* VS, unsigned long long* counter, uint32_t* gcount, hipStream_t s) {
     dim3 grid((n_tiles + 3) / 4), block(256);
     for (int c_off = 0; c_off < C; c_off += CC) {
         if (tdtype == GSC_BF16)
             hipLaunchKernelGGL((k_accumulate<CC, true>), grid, block, 0, s, views, n_views, n_tiles,
-                               ranges, pair_vals, rec0, rec1, targets, C, c_off, N, view_first,
-                               (int)per_view, bp, VS, counter, gcount);
+                               ranges, pair_vals, rec0, rec1, targets, C, c_off, (int)per_view, bp,
+                               VS, counter, gcount);
         else
             hipLaunchKernelGGL((k_accumulate<CC, false>), grid, block, 0, s, views, n_views, n_tiles,
-                               ranges, pair_vals, rec0, rec1, targets, C, c_off, N, view_first,
-                               (int)per_view, bp, VS, counter, gcount);
+                               ranges, pair_vals, rec0, rec1, targets, C, c_off, (int)per_view, bp,
+                               VS, counter, gcount);
     }
 }
 
@@ -174,52 +174,45 @@ int accumulate_chunk(int C) { return C <= 3 ? C : (C <= 4 ? 4 : (C <= 8 ? 8 : 16
 
 void launch_accumulate(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
                        const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
-                       const void* targets, int tdtype, int C, int64_t N, int view_first,
-                       bool per_view, BlendParams bp, float* VS, unsigned long long* counter,
-                       uint32_t* gcount, hipStream_t s) {
+                       const void* targets, int tdtype, int C, bool per_view, BlendParams bp,
+                       float* VS, unsigned long long* counter, uint32_t* gcount, hipStream_t s) {
     if (n_tiles == 0) return;
-    if (C == 1)
-        launch_acc_cc<1>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, targets, tdtype, C,
-                         N, view_first, per_view, bp, VS, counter, gcount, s);
-    else if (C == 2)
-        launch_acc_cc<2>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, targets, tdtype, C,
-                         N, view_first, per_view, bp, VS, counter, gcount, s);
-    else if (C == 3)
-        launch_acc_cc<3>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, targets, tdtype, C,
-                         N, view_first, per_view, bp, VS, counter, gcount, s);
-    else if (C <= 4)
-        launch_acc_cc<4>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, targets, tdtype, C,
-                         N, view_first, per_view, bp, VS, counter, gcount, s);
-    else if (C <= 8)
-        launch_acc_cc<8>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, targets, tdtype, C,
-                         N, view_first, per_view, bp, VS, counter, gcount, s);
-    else
-        launch_acc_cc<16>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, targets, tdtype, C,
-                          N, view_first, per_view, bp, VS, counter, gcount, s);
+#define GSC_ACC(CCV)                                                                              \
+    launch_acc_cc<CCV>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, targets, tdtype, C, \
+                       per_view, bp, VS, counter, gcount, s)
+    switch (accumulate_chunk(C)) {
+        case 1: GSC_ACC(1); break;
+        case 2: GSC_ACC(2); break;
+        case 3: GSC_ACC(3); break;
+        case 4: GSC_ACC(4); break;
+        case 8: GSC_ACC(8); break;
+        default: GSC_ACC(16); break;
+    }
+#undef GSC_ACC
 }
 
 void launch_accumulate_weights(const ViewInfo* views, int n_views, uint32_t n_tiles,
                                const uint2* ranges, const uint32_t* pair_vals, const float4* rec0,
-                               const float4* rec1, int64_t N, int view_first, bool per_view,
-                               BlendParams bp, float* V, unsigned long long* counter, hipStream_t s) {
+                               const float4* rec1, bool per_view, BlendParams bp, float* V,
+                               unsigned long long* counter, hipStream_t s) {
     if (n_tiles == 0) return;
     hipLaunchKernelGGL((k_accumulate<0, false>), dim3((n_tiles + 3) / 4), dim3(256), 0, s, views,
                        n_views, n_tiles, ranges, pair_vals, rec0, rec1, (const void*)nullptr, 0, 0,
-                       N, view_first, (int)per_view, bp, V, counter, (uint32_t*)nullptr);
+                       (int)per_view, bp, V, counter, (uint32_t*)nullptr);
 }
 
 // ---- render ----------------------------------------------------------------
 
-// gamma[(v*N + g)*C + c] = sum_m coeffs[g][m][c] * phi_m(dir_gv)
+// gamma[item*C + c] = sum_m coeffs[g][m][c] * phi_m(dir_gv) for the batch items.
 template <int L>
-__global__ void k_view_colors(const ViewInfo* __restrict__ views, const float* __restrict__ means,
-                              const float* __restrict__ coeffs, int64_t N, int C,
-                              float* __restrict__ gamma) {
+__global__ void k_view_colors(const ViewInfo* __restrict__ views, int n_views, uint32_t n_items,
+                              const float* __restrict__ means, const float* __restrict__ coeffs,
+                              int C, float* __restrict__ gamma) {
     constexpr int NB = (L + 1) * (L + 1);
-    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int v = blockIdx.y;
-    if (g >= N) return;
-    const ViewInfo& V = views[v];
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_items) return;
+    const ViewInfo& V = views[find_view_item(views, n_views, i)];
+    const int64_t g = V.g_offset + (int64_t)(i - V.item_base);
     double dx = (double)means[3 * g] - V.centre[0];
     double dy = (double)means[3 * g + 1] - V.centre[1];
     double dz = (double)means[3 * g + 2] - V.centre[2];
@@ -227,7 +220,7 @@ __global__ void k_view_colors(const ViewInfo* __restrict__ views, const float* _
     float phi[NB];
     sh_eval<float, L>((float)(dx * inv), (float)(dy * inv), (float)(dz * inv), phi);
     const float* cg = coeffs + g * NB * C;
-    float* out = gamma + ((int64_t)v * N + g) * C;
+    float* out = gamma + (int64_t)i * C;
     for (int c = 0; c < C; ++c) {
         float a = 0.0f;
 #pragma unroll
@@ -236,15 +229,15 @@ __global__ void k_view_colors(const ViewInfo* __restrict__ views, const float* _
     }
 }
 
-void launch_view_colors(const ViewInfo* views, int n_views, const float* means, const float* coeffs,
-                        int64_t N, int C, int sh_deg, float* gamma, hipStream_t s) {
-    if (N <= 0 || n_views <= 0) return;
-    dim3 grid((unsigned)((N + 255) / 256), (unsigned)n_views);
+void launch_view_colors(const ViewInfo* views, int n_views, uint32_t n_items, const float* means,
+                        const float* coeffs, int C, int sh_deg, float* gamma, hipStream_t s) {
+    if (n_items == 0 || n_views <= 0) return;
+    dim3 grid((n_items + 255) / 256), block(256);
     switch (sh_deg) {
-        case 0: hipLaunchKernelGGL(k_view_colors<0>, grid, dim3(256), 0, s, views, means, coeffs, N, C, gamma); break;
-        case 1: hipLaunchKernelGGL(k_view_colors<1>, grid, dim3(256), 0, s, views, means, coeffs, N, C, gamma); break;
-        case 2: hipLaunchKernelGGL(k_view_colors<2>, grid, dim3(256), 0, s, views, means, coeffs, N, C, gamma); break;
-        default: hipLaunchKernelGGL(k_view_colors<3>, grid, dim3(256), 0, s, views, means, coeffs, N, C, gamma); break;
+        case 0: hipLaunchKernelGGL(k_view_colors<0>, grid, block, 0, s, views, n_views, n_items, means, coeffs, C, gamma); break;
+        case 1: hipLaunchKernelGGL(k_view_colors<1>, grid, block, 0, s, views, n_views, n_items, means, coeffs, C, gamma); break;
+        case 2: hipLaunchKernelGGL(k_view_colors<2>, grid, block, 0, s, views, n_views, n_items, means, coeffs, C, gamma); break;
+        default: hipLaunchKernelGGL(k_view_colors<3>, grid, block, 0, s, views, n_views, n_items, means, coeffs, C, gamma); break;
     }
 }
 
@@ -253,7 +246,7 @@ template <int CC>
 __global__ __launch_bounds__(256) void k_render(
     const ViewInfo* __restrict__ views, int n_views, uint32_t n_tiles, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ pair_vals, const float4* __restrict__ rec0,
-    const float4* __restrict__ rec1, const float* __restrict__ gamma, int C, int c_off, int64_t N,
+    const float4* __restrict__ rec1, const float* __restrict__ gamma, int C, int c_off,
     BlendParams bp, float* __restrict__ images, unsigned long long* __restrict__ counter) {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t tile = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -347,17 +340,17 @@ __global__ __launch_bounds__(256) void k_render(
 
 void launch_render(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
                    const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
-                   const float* gamma, int C, int64_t N, BlendParams bp, float* images,
+                   const float* gamma, int C, BlendParams bp, float* images,
                    unsigned long long* counter, hipStream_t s) {
     if (n_tiles == 0) return;
     dim3 grid((n_tiles + 3) / 4), block(256);
     for (int c_off = 0; c_off < C; c_off += 4) {
         if (C <= 3 && c_off == 0) {
             hipLaunchKernelGGL(k_render<3>, grid, block, 0, s, views, n_views, n_tiles, ranges,
-                               pair_vals, rec0, rec1, gamma, C, c_off, N, bp, images, counter);
+                               pair_vals, rec0, rec1, gamma, C, c_off, bp, images, counter);
         } else {
             hipLaunchKernelGGL(k_render<4>, grid, block, 0, s, views, n_views, n_tiles, ranges,
-                               pair_vals, rec0, rec1, gamma, C, c_off, N, bp, images, counter);
+                               pair_vals, rec0, rec1, gamma, C, c_off, bp, images, counter);
         }
     }
 }

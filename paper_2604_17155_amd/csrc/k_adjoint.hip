@@ -30,17 +30,17 @@
 
 namespace gsc {
 
-// beta[(v*N + g)*(C+1) + c] = beta_gj[c], and [.. + C] = delta_gj.
+// beta[item*(C+1) + c] = beta_gj[c], and [.. + C] = delta_gj.
 template <int L, bool RENDER>
-__global__ void k_view_adjoint(const ViewInfo* __restrict__ views, const float* __restrict__ means,
-                               const float* __restrict__ coeffs, const float* __restrict__ bbar,
-                               const float* __restrict__ rho, int64_t N, int C,
+__global__ void k_view_adjoint(const ViewInfo* __restrict__ views, int n_views, uint32_t n_items,
+                               const float* __restrict__ means, const float* __restrict__ coeffs,
+                               const float* __restrict__ bbar, const float* __restrict__ rho, int C,
                                float* __restrict__ beta) {
     constexpr int NB = (L + 1) * (L + 1);
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int v = blockIdx.y;
-    if (g >= N) return;
-    const ViewInfo& V = views[v];
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_items) return;
+    const ViewInfo& V = views[find_view_item(views, n_views, i)];
+    const int64_t g = V.g_offset + (int64_t)(i - V.item_base);
     const double dx = (double)means[3 * g] - V.centre[0];
     const double dy = (double)means[3 * g + 1] - V.centre[1];
     const double dz = (double)means[3 * g + 2] - V.centre[2];
@@ -48,7 +48,7 @@ __global__ void k_view_adjoint(const ViewInfo* __restrict__ views, const float* 
     float phi[NB];
     sh_eval<float, L>((float)(dx * inv), (float)(dy * inv), (float)(dz * inv), phi);
     const float* cg = coeffs + g * NB * C;
-    float* out = beta + ((int64_t)v * N + g) * (C + 1);
+    float* out = beta + (int64_t)i * (C + 1);
     if constexpr (RENDER) {
         for (int c = 0; c < C; ++c) {
             float a = 0.0f;
@@ -74,19 +74,19 @@ __global__ void k_view_adjoint(const ViewInfo* __restrict__ views, const float* 
     }
 }
 
-void launch_view_adjoint(const ViewInfo* views, int n_views, const float* means, const float* coeffs,
-                         const float* bbar, const float* rho, int64_t N, int C, int sh_deg,
-                         bool render, float* beta, hipStream_t s) {
-    if (N <= 0 || n_views <= 0) return;
-    dim3 grid((unsigned)((N + 255) / 256), (unsigned)n_views), block(256);
+void launch_view_adjoint(const ViewInfo* views, int n_views, uint32_t n_items, const float* means,
+                         const float* coeffs, const float* bbar, const float* rho, int C,
+                         int sh_deg, bool render, float* beta, hipStream_t s) {
+    if (n_items == 0 || n_views <= 0) return;
+    dim3 grid((n_items + 255) / 256), block(256);
 #define GSC_VA(LL)                                                                                   \
     do {                                                                                             \
         if (render)                                                                                  \
-            hipLaunchKernelGGL((k_view_adjoint<LL, true>), grid, block, 0, s, views, means, coeffs,  \
-                               bbar, rho, N, C, beta);                                               \
+            hipLaunchKernelGGL((k_view_adjoint<LL, true>), grid, block, 0, s, views, n_views,        \
+                               n_items, means, coeffs, bbar, rho, C, beta);                          \
         else                                                                                         \
-            hipLaunchKernelGGL((k_view_adjoint<LL, false>), grid, block, 0, s, views, means, coeffs, \
-                               bbar, rho, N, C, beta);                                               \
+            hipLaunchKernelGGL((k_view_adjoint<LL, false>), grid, block, 0, s, views, n_views,       \
+                               n_items, means, coeffs, bbar, rho, C, beta);                          \
     } while (0)
     switch (sh_deg) {
         case 0: GSC_VA(0); break;
@@ -133,7 +133,7 @@ template <int CC, bool BF16, bool GY>
 __global__ __launch_bounds__(256) void k_blend_adjoint(
     const ViewInfo* __restrict__ views, int n_views, uint32_t n_tiles, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ pair_vals, const float4* __restrict__ rec0,
-    const float4* __restrict__ rec1, const void* __restrict__ ypix, int C, int c_off, int64_t N,
+    const float4* __restrict__ rec1, const void* __restrict__ ypix, int C, int c_off,
     const float* __restrict__ beta, BlendParams bp, float* __restrict__ grad_y,
     float* __restrict__ grad_o) {
     const uint32_t lane = threadIdx.x & 63;
@@ -148,7 +148,8 @@ __global__ __launch_bounds__(256) void k_blend_adjoint(
     const float px = (float)ix + 0.5f;
     const int stride = C + 1;
     const bool first_chunk = c_off == 0;
-    const int64_t item_base = (int64_t)vloc * N;
+    // dL/do of item i goes to Gaussian g_offset + (i - item_base)
+    const int64_t g_shift = V.g_offset - (int64_t)V.item_base;
     const float qlim = (float)(kExp2Scale * (double)bp.cut2);
 
     bool inside[4];
@@ -288,7 +289,7 @@ __global__ __launch_bounds__(256) void k_blend_adjoint(
             }
             if (__ballot(any != 0) != 0) {
                 const float t = wave_sum(go);
-                if (lane == 0) unsafeAtomicAdd(grad_o + ((int64_t)item - item_base), t);
+                if (lane == 0) unsafeAtomicAdd(grad_o + ((int64_t)item + g_shift), t);
             }
             if (__ballot(live[0] || live[1] || live[2] || live[3]) == 0) {
                 wave_live = false;
@@ -301,17 +302,17 @@ __global__ __launch_bounds__(256) void k_blend_adjoint(
 template <int CC, bool GY>
 static void launch_badj_cc(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
                            const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
-                           const void* ypix, int ydtype, int C, int64_t N, const float* beta,
+                           const void* ypix, int ydtype, int C, const float* beta,
                            BlendParams bp, float* grad_y, float* grad_o, hipStream_t s) {
     dim3 grid((n_tiles + 3) / 4), block(256);
     for (int c_off = 0; c_off < C; c_off += CC) {
         if (ydtype == GSC_BF16)
             hipLaunchKernelGGL((k_blend_adjoint<CC, true, GY>), grid, block, 0, s, views, n_views,
-                               n_tiles, ranges, pair_vals, rec0, rec1, ypix, C, c_off, N, beta, bp,
+                               n_tiles, ranges, pair_vals, rec0, rec1, ypix, C, c_off, beta, bp,
                                grad_y, grad_o);
         else
             hipLaunchKernelGGL((k_blend_adjoint<CC, false, GY>), grid, block, 0, s, views, n_views,
-                               n_tiles, ranges, pair_vals, rec0, rec1, ypix, C, c_off, N, beta, bp,
+                               n_tiles, ranges, pair_vals, rec0, rec1, ypix, C, c_off, beta, bp,
                                grad_y, grad_o);
     }
 }
@@ -319,28 +320,28 @@ static void launch_badj_cc(const ViewInfo* views, int n_views, uint32_t n_tiles,
 template <bool GY>
 static void launch_badj(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
                         const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
-                        const void* ypix, int ydtype, int C, int64_t N, const float* beta,
+                        const void* ypix, int ydtype, int C, const float* beta,
                         BlendParams bp, float* grad_y, float* grad_o, hipStream_t s) {
     switch (accumulate_chunk(C)) {
-        case 1: launch_badj_cc<1, GY>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C, N, beta, bp, grad_y, grad_o, s); break;
-        case 2: launch_badj_cc<2, GY>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C, N, beta, bp, grad_y, grad_o, s); break;
-        case 3: launch_badj_cc<3, GY>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C, N, beta, bp, grad_y, grad_o, s); break;
-        case 4: launch_badj_cc<4, GY>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C, N, beta, bp, grad_y, grad_o, s); break;
-        case 8: launch_badj_cc<8, GY>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C, N, beta, bp, grad_y, grad_o, s); break;
-        default: launch_badj_cc<16, GY>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C, N, beta, bp, grad_y, grad_o, s); break;
+        case 1: launch_badj_cc<1, GY>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C, beta, bp, grad_y, grad_o, s); break;
+        case 2: launch_badj_cc<2, GY>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C, beta, bp, grad_y, grad_o, s); break;
+        case 3: launch_badj_cc<3, GY>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C, beta, bp, grad_y, grad_o, s); break;
+        case 4: launch_badj_cc<4, GY>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C, beta, bp, grad_y, grad_o, s); break;
+        case 8: launch_badj_cc<8, GY>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C, beta, bp, grad_y, grad_o, s); break;
+        default: launch_badj_cc<16, GY>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C, beta, bp, grad_y, grad_o, s); break;
     }
 }
 
 void launch_blend_adjoint(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
                           const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
-                          const void* ypix, int ydtype, int C, int64_t N, const float* beta,
-                          BlendParams bp, float* grad_y, float* grad_o, hipStream_t s) {
+                          const void* ypix, int ydtype, int C, const float* beta, BlendParams bp,
+                          float* grad_y, float* grad_o, hipStream_t s) {
     if (n_tiles == 0 || (!grad_y && !grad_o)) return;
     if (grad_y)
-        launch_badj<true>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C, N,
+        launch_badj<true>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C,
                           beta, bp, grad_y, grad_o, s);
     else
-        launch_badj<false>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C, N,
+        launch_badj<false>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C,
                            beta, bp, grad_y, grad_o, s);
 }
 
@@ -368,7 +369,7 @@ __global__ void k_fold_rhs(const ViewInfo* __restrict__ views, int n_views,
     const int nv = per_view ? n_views : 1;
     const float mx = means[3 * g], my = means[3 * g + 1], mz = means[3 * g + 2];
     for (int v = 0; v < nv; ++v) {
-        const float* slot = VS + ((per_view ? (int64_t)v * N : 0) + g) * stride;
+        const float* slot = VS + ((per_view ? views[v].vs_base : 0) + g) * stride;
         if (slot[0] == 0.0f) continue;  // no contribution in this view
         float phi[NB];
         if (per_view) {

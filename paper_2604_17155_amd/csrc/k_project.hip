@@ -101,7 +101,7 @@ __device__ inline uint32_t band_bits(const int* lo, const int* hi, int t) {
     return m;
 }
 
-// a2: one thread per (view, Gaussian).  Item index i = v * N + g.
+// a2: one thread per (view, Gaussian) item of the batch.
 // The projection is evaluated in FP64 (a few dozen operations per item) and
 // the pixel position is stored as an FP32 hi/lo pair, so that the blend can
 // form pixel offsets d = (p - u_hi) - u_lo exactly to one FP32 ulp of d; a
@@ -109,19 +109,18 @@ __device__ inline uint32_t band_bits(const int* lo, const int* hi, int t) {
 // enough to move alpha by ~1e-4 relative at the footprint edge.
 // A tile is binned only if its pixel centres come within the footprint
 // reach (3-sigma ellipse, shrunk by the alpha floor for faint splats).
-__global__ __launch_bounds__(256) void k_project(const ViewInfo* __restrict__ views,
-                                                 const float* __restrict__ means,
+__global__ __launch_bounds__(256) void k_project(const ViewInfo* __restrict__ views, int n_views,
+                                                 uint32_t n_items, const float* __restrict__ means,
                                                  const float* __restrict__ cov,
-                                                 const float* __restrict__ opac, int64_t N,
+                                                 const float* __restrict__ opac,
                                                  BlendParams bp, uint32_t* __restrict__ keys,
                                                  uint32_t* __restrict__ vals,
                                                  uint32_t* __restrict__ counts,
                                                  float4* __restrict__ rec0, float4* __restrict__ rec1) {
-    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int v = blockIdx.y;
-    if (g >= N) return;
-    const ViewInfo& V = views[v];
-    uint32_t i = (uint32_t)((int64_t)v * N + g);
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_items) return;
+    const ViewInfo& V = views[find_view_item(views, n_views, i)];
+    const int64_t g = V.g_offset + (int64_t)(i - V.item_base);
     float mx = means[3 * g], my = means[3 * g + 1], mz = means[3 * g + 2];
     float key = __fmaf_rn(V.R[6], mx, __fmaf_rn(V.R[7], my, __fmaf_rn(V.R[8], mz, V.t[2])));
     uint32_t kb = 0xFFFFFFFFu, cnt = 0;
@@ -181,12 +180,12 @@ __global__ __launch_bounds__(256) void k_project(const ViewInfo* __restrict__ vi
     rec1[i] = r1;
 }
 
-void launch_project(const ViewInfo* views, int n_views, const float* means, const float* cov,
-                    const float* opac, int64_t N, BlendParams bp, uint32_t* keys, uint32_t* vals,
-                    uint32_t* counts, float4* rec0, float4* rec1, hipStream_t s) {
-    if (N <= 0 || n_views <= 0) return;
-    hipLaunchKernelGGL(k_project, dim3((unsigned)((N + 255) / 256), (unsigned)n_views), dim3(256), 0,
-                       s, views, means, cov, opac, N, bp, keys, vals, counts, rec0, rec1);
+void launch_project(const ViewInfo* views, int n_views, uint32_t n_items, const float* means,
+                    const float* cov, const float* opac, BlendParams bp, uint32_t* keys,
+                    uint32_t* vals, uint32_t* counts, float4* rec0, float4* rec1, hipStream_t s) {
+    if (n_items == 0 || n_views <= 0) return;
+    hipLaunchKernelGGL(k_project, dim3((n_items + 255) / 256), dim3(256), 0, s, views, n_views,
+                       n_items, means, cov, opac, bp, keys, vals, counts, rec0, rec1);
 }
 
 __global__ void k_gather_counts(const uint32_t* __restrict__ sorted_vals,
@@ -205,17 +204,17 @@ void launch_gather_counts(const uint32_t* sorted_vals, const uint32_t* counts, u
 
 // a3: emit (global tile id, item) pairs in depth order; a stable sort by tile
 // id then yields every tile's list in front-to-back order.
-__global__ void k_emit(const ViewInfo* __restrict__ views, const uint32_t* __restrict__ sorted_vals,
+__global__ void k_emit(const ViewInfo* __restrict__ views, int n_views,
+                       const uint32_t* __restrict__ sorted_vals,
                        const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ counts,
                        const float4* __restrict__ rec0, const float4* __restrict__ rec1,
-                       BlendParams bp, uint32_t n_items, int64_t N, uint32_t sentinel,
+                       BlendParams bp, uint32_t n_items, uint32_t sentinel,
                        uint32_t* __restrict__ pair_keys, uint32_t* __restrict__ pair_vals) {
     uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_items) return;
     uint32_t i = sorted_vals[k];
     if (counts[i] == 0) return;
-    int v = (int)((int64_t)i / N);
-    const ViewInfo& V = views[v];
+    const ViewInfo& V = views[find_view_item(views, n_views, i)];
     const float4 r0 = rec0[i], r1 = rec1[i];
     uint32_t off = offsets[k];
     const uint32_t end = off + counts[i];
@@ -243,13 +242,14 @@ __global__ void k_emit(const ViewInfo* __restrict__ views, const uint32_t* __res
     }
 }
 
-void launch_emit(const ViewInfo* views, const uint32_t* sorted_vals, const uint32_t* offsets,
-                 const uint32_t* counts, const float4* rec0, const float4* rec1, BlendParams bp,
-                 uint32_t n_items, int64_t N, uint32_t n_tiles, uint32_t* pair_keys,
-                 uint32_t* pair_vals, hipStream_t s) {
+void launch_emit(const ViewInfo* views, int n_views, const uint32_t* sorted_vals,
+                 const uint32_t* offsets, const uint32_t* counts, const float4* rec0,
+                 const float4* rec1, BlendParams bp, uint32_t n_items, uint32_t n_tiles,
+                 uint32_t* pair_keys, uint32_t* pair_vals, hipStream_t s) {
     if (n_items == 0) return;
-    hipLaunchKernelGGL(k_emit, dim3((n_items + 255) / 256), dim3(256), 0, s, views, sorted_vals,
-                       offsets, counts, rec0, rec1, bp, n_items, N, n_tiles, pair_keys, pair_vals);
+    hipLaunchKernelGGL(k_emit, dim3((n_items + 255) / 256), dim3(256), 0, s, views, n_views,
+                       sorted_vals, offsets, counts, rec0, rec1, bp, n_items, n_tiles, pair_keys,
+                       pair_vals);
 }
 
 __global__ __launch_bounds__(256) void k_sum_u64(const uint32_t* __restrict__ counts, uint32_t n,
