@@ -236,6 +236,87 @@ gsc_status gsc_render_backward(gsc_ctx* ctx, const float* means, const float* sc
                                int32_t C, int32_t sh_deg, const float* grad_images,
                                float* grad_coeffs, float* grad_opacities, gsc_stream_t stream);
 
+/*
+ * Batched colorize of many scenes (plans).
+ *
+ * Several scenes of uneven size are colorized in one pass: all their views
+ * are binned and blended by the same launches, view batch by view batch.  A
+ * plan fixes every size in advance (gsc_plan_create projects the geometry
+ * once and counts its tile pairs exactly), so that gsc_colorize_batched
+ * allocates nothing, never synchronises and enqueues kernel launches only: it
+ * may be captured into a graph (hipStreamBeginCapture) and replayed.
+ *
+ * The scenes' Gaussians are concatenated: scene k owns the entries
+ * [gaussian_offset, gaussian_offset + n_gaussians) of means, scales, quats,
+ * opacities and of the coeffs / status outputs; ranges must not overlap.
+ * Its cameras are cams[camera_offset .. camera_offset + n_cameras), whose
+ * pixel_offset fields index one concatenated target array.  C, sh_deg and
+ * lambda are common to all scenes.
+ */
+typedef struct {
+    int64_t gaussian_offset;
+    int64_t n_gaussians; /* < 2^26 */
+    int32_t camera_offset;
+    int32_t n_cameras;
+} gsc_scene;
+
+typedef struct gsc_plan gsc_plan;
+
+typedef struct {
+    uint64_t contributions;     /* accepted contributions of the last run */
+    uint64_t items;             /* (view, Gaussian) items per run */
+    uint64_t pair_capacity;     /* tile pairs per run (exact for the planned geometry) */
+    uint32_t dropped_pairs;     /* items of the last run whose pairs exceeded the capacity
+                                   (non-zero only if the geometry changed after planning) */
+    uint32_t ill_conditioned;   /* Gaussians flagged GSC_G_ILL_COND by the last run */
+    uint32_t batches;           /* view batches per run */
+    uint32_t views;             /* views per run */
+    int32_t accumulate_chunk;   /* channels per accumulate launch in use */
+    int32_t tuned_chunk[4];     /* candidates timed by gsc_plan_autotune (0: unused) */
+    float tuned_ms[4];          /* their accumulate time per run, ms */
+} gsc_plan_info;
+
+/*
+ * Create a plan for `n_scenes` scenes (host table).  The geometry arrays
+ * (device) and the cameras (host, n_cams entries; copied) are recorded; the
+ * device arrays must stay valid, and unchanged, for the plan's lifetime.
+ * Projects every view once and synchronises `stream`.  The plan keeps `ctx`
+ * (options, profiling): destroy the plan before the context.
+ */
+gsc_status gsc_plan_create(gsc_ctx* ctx, const gsc_scene* scenes, int32_t n_scenes,
+                           const float* means, const float* scales, const float* quats,
+                           const float* opacities, const gsc_camera* cams, int32_t n_cams,
+                           int32_t C, int32_t sh_deg, gsc_plan** plan, gsc_stream_t stream);
+void gsc_plan_destroy(gsc_plan* plan);
+
+/*
+ * Colorize every scene of the plan (the per-scene result equals gsc_colorize
+ * on that scene alone, up to the order of float atomics).
+ *   targets: device [rows, C] (GSC_F32 or GSC_BF16), rows covering every camera;
+ *   lambda: host; coeffs: device output [n_total, (L+1)^2, C] with n_total =
+ *   max(gaussian_offset + n_gaussians); status: device output [n_total] or NULL.
+ *   Only the scenes' Gaussian ranges are written (L >= 1); for L = 0 every
+ *   entry below n_total is written (entries outside all scenes as unobserved).
+ * No allocation, no synchronisation, kernel launches only.  Runs of one plan
+ * must not overlap (they share its scratch).
+ */
+gsc_status gsc_colorize_batched(gsc_plan* plan, const void* targets, int32_t tdtype,
+                                const float* lambda, int32_t n_lambda, float* coeffs,
+                                uint8_t* status, gsc_stream_t stream);
+
+/*
+ * Autotune the plan's accumulate launch shape (channels per launch) on the
+ * given inputs: times each candidate over all view batches, keeps the fastest,
+ * then runs the plan once more so that coeffs/status hold a clean result.
+ * Synchronises `stream`.  Not capturable.
+ */
+gsc_status gsc_plan_autotune(gsc_plan* plan, const void* targets, int32_t tdtype,
+                             const float* lambda, int32_t n_lambda, float* coeffs,
+                             uint8_t* status, gsc_stream_t stream);
+
+/* Sizes of the plan and counters of its last run (host output; synchronises the device). */
+gsc_status gsc_plan_get_info(gsc_plan* plan, gsc_plan_info* out);
+
 /* Statistics of the last call on `ctx` (host output).  Synchronises with the
  * device work of that call. */
 gsc_status gsc_get_stats(gsc_ctx* ctx, gsc_stats* out);

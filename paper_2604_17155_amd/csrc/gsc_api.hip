@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -415,6 +416,190 @@ gsc_status upload_all_views(gsc_ctx* ctx, const std::vector<ViewInfo>& all, hipS
 
 }  // namespace
 
+// A batched multi-scene colorize with every size fixed in advance, so that a
+// run allocates nothing, never synchronises and consists of kernel launches
+// only (it can be captured into a graph and replayed).
+struct gsc_plan {
+    gsc_ctx* ctx = nullptr;  // options and profiling
+    BlendParams bp;
+    std::vector<gsc_scene> scenes;
+    const float *means = nullptr, *scales = nullptr, *quats = nullptr, *opac = nullptr;
+    int64_t n_total = 0;  // length of the concatenated Gaussian arrays
+    int C = 0, sh_deg = 0;
+    bool per_view = false;
+    struct Batch {
+        int v0, nv;
+        uint32_t n_items, n_tiles, pair_cap;
+        int tile_bits;
+    };
+    std::vector<Batch> batches;
+    std::vector<ViewInfo> views;      // all views, tile_base/item_base local to their batch
+    std::vector<int> scene_view0;     // first view of each scene in `views`
+    std::vector<int> scene_nviews;    // views of each scene in `views`
+    std::vector<int64_t> scene_vs0;   // first per-view slot of each scene
+    uint64_t vs_slots = 0;
+    uint32_t max_items = 0, max_pairs = 0, max_tiles = 0;
+    uint64_t items_total = 0, pairs_total = 0;
+    int acc_chunk = 0;                // channels per accumulate launch (0: default)
+    float tune_ms[4] = {0.f, 0.f, 0.f, 0.f};
+    int tune_chunks[4] = {0, 0, 0, 0};
+    DevBuf d_views, cov, keys, vals, keys_alt, vals_alt, counts, counts_sorted, offsets, rec0, rec1,
+        sort_scratch, pkeys, pvals, pkeys_alt, pvals_alt, ranges, vs, misc;
+    ~gsc_plan() {
+        DevBuf* all[] = {&d_views, &cov, &keys, &vals, &keys_alt, &vals_alt, &counts, &counts_sorted,
+                         &offsets, &rec0, &rec1, &sort_scratch, &pkeys, &pvals, &pkeys_alt,
+                         &pvals_alt, &ranges, &vs, &misc};
+        for (DevBuf* b : all) b->release();
+    }
+};
+
+namespace {
+// plan misc layout (device): [0] u64 contributions, [8] u32 live pair count of
+// the current batch, [12] u32 dropped-pair events, [16] u32 ill-conditioned
+// count, [24] u64 pair total (plan creation)
+constexpr size_t kPlanMiscBytes = 64;
+
+gsc_status validate_cameras(const gsc_camera* cams, int32_t n_cams) {
+    int64_t rows = 0;
+    return validate_geometry(nullptr, nullptr, nullptr, nullptr, 0, cams, n_cams, &rows);
+}
+
+// Project one batch of the plan and count its tile pairs (synchronises).
+gsc_status plan_count_pairs(gsc_plan* P, const gsc_plan::Batch& b, hipStream_t s, uint64_t* pairs) {
+    const ViewInfo* dv = P->d_views.as<ViewInfo>() + b.v0;
+    launch_project(dv, b.nv, b.n_items, P->means, P->cov.as<float>(), P->opac, P->bp,
+                   P->keys.as<uint32_t>(), P->vals.as<uint32_t>(), P->counts.as<uint32_t>(),
+                   P->rec0.as<float4>(), P->rec1.as<float4>(), s);
+    GSC_LAUNCHED("project");
+    unsigned long long* d64 = reinterpret_cast<unsigned long long*>(P->misc.as<char>() + 24);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(d64), 0u, 2, s);
+    launch_sum_u64(P->counts.as<uint32_t>(), b.n_items, d64, s);
+    GSC_LAUNCHED("count");
+    uint64_t h = 0;
+    GSC_HIP(hipMemcpyAsync(&h, d64, 8, hipMemcpyDeviceToHost, s));
+    GSC_HIP(hipStreamSynchronize(s));
+    *pairs = h;
+    return GSC_OK;
+}
+
+// Assign batch-local tile and item numbering to the views of every batch.
+void plan_number_views(gsc_plan* P) {
+    for (auto& b : P->batches) {
+        uint64_t tiles = 0, items = 0;
+        for (int k = 0; k < b.nv; ++k) {
+            ViewInfo& v = P->views[b.v0 + k];
+            v.tile_base = (uint32_t)tiles;
+            v.item_base = (uint32_t)items;
+            tiles += (uint64_t)v.tiles_x * v.tiles_y;
+            items += v.n_gauss;
+        }
+        b.n_tiles = (uint32_t)tiles;
+        b.n_items = (uint32_t)items;
+        b.tile_bits = bits_for(tiles + 1);
+    }
+}
+
+gsc_status plan_accumulate(gsc_plan* P, const gsc_plan::Batch& b, const void* targets, int tdtype,
+                           int chunk, hipStream_t s) {
+    const ViewInfo* dv = P->d_views.as<ViewInfo>() + b.v0;
+    unsigned long long* d_counter = reinterpret_cast<unsigned long long*>(P->misc.p);
+    launch_accumulate_chunked(dv, b.nv, b.n_tiles, P->ranges.as<uint2>(), P->pvals.as<uint32_t>(),
+                              P->rec0.as<float4>(), P->rec1.as<float4>(), targets, tdtype, P->C,
+                              P->per_view, P->bp, P->vs.as<float>(), d_counter, nullptr, chunk, s);
+    GSC_LAUNCHED("accumulate");
+    return GSC_OK;
+}
+
+// Everything of one batch up to the tile lists, enqueued without host reads.
+gsc_status plan_bin_batch(gsc_plan* P, const gsc_plan::Batch& b, hipStream_t s) {
+    gsc_ctx* ctx = P->ctx;
+    const ViewInfo* dv = P->d_views.as<ViewInfo>() + b.v0;
+    uint32_t* d_live = reinterpret_cast<uint32_t*>(P->misc.as<char>() + 8);
+    uint32_t* d_drop = reinterpret_cast<uint32_t*>(P->misc.as<char>() + 12);
+    {
+        StageTimer t(ctx, s, GSC_STAGE_PROJECT);
+        launch_project(dv, b.nv, b.n_items, P->means, P->cov.as<float>(), P->opac, P->bp,
+                       P->keys.as<uint32_t>(), P->vals.as<uint32_t>(), P->counts.as<uint32_t>(),
+                       P->rec0.as<float4>(), P->rec1.as<float4>(), s);
+        GSC_LAUNCHED("project");
+    }
+    {
+        StageTimer t(ctx, s, GSC_STAGE_DEPTH_SORT);
+        radix_sort(P->keys.as<uint32_t>(), P->vals.as<uint32_t>(), P->keys_alt.as<uint32_t>(),
+                   P->vals_alt.as<uint32_t>(), b.n_items, 32, P->sort_scratch.as<uint32_t>(), s);
+        GSC_LAUNCHED("depth sort");
+    }
+    {
+        StageTimer t(ctx, s, GSC_STAGE_SCAN);
+        launch_gather_counts(P->vals.as<uint32_t>(), P->counts.as<uint32_t>(),
+                             P->counts_sorted.as<uint32_t>(), b.n_items, s);
+        launch_scan(P->counts_sorted.as<uint32_t>(), P->offsets.as<uint32_t>(), b.n_items, d_live,
+                    P->sort_scratch.as<uint32_t>(), s);
+        GSC_LAUNCHED("count scan");
+    }
+    {
+        StageTimer t(ctx, s, GSC_STAGE_EMIT);
+        launch_emit(dv, b.nv, P->vals.as<uint32_t>(), P->offsets.as<uint32_t>(),
+                    P->counts.as<uint32_t>(), P->rec0.as<float4>(), P->rec1.as<float4>(), P->bp,
+                    b.n_items, b.n_tiles, P->pkeys.as<uint32_t>(), P->pvals.as<uint32_t>(), s,
+                    b.pair_cap, d_drop);
+        GSC_LAUNCHED("emit");
+    }
+    {
+        StageTimer t(ctx, s, GSC_STAGE_TILE_SORT);
+        radix_sort(P->pkeys.as<uint32_t>(), P->pvals.as<uint32_t>(), P->pkeys_alt.as<uint32_t>(),
+                   P->pvals_alt.as<uint32_t>(), b.pair_cap, b.tile_bits,
+                   P->sort_scratch.as<uint32_t>(), s, d_live);
+        launch_fill_u32(P->ranges.as<uint32_t>(), 0u, (uint64_t)2 * b.n_tiles, s);
+        launch_tile_ranges(P->pkeys.as<uint32_t>(), b.pair_cap, b.n_tiles, P->ranges.as<uint2>(), s,
+                           d_live);
+        GSC_LAUNCHED("tile sort");
+    }
+    return GSC_OK;
+}
+
+gsc_status plan_solve(gsc_plan* P, const double* lam, float* coeffs, uint8_t* status, hipStream_t s) {
+    gsc_ctx* ctx = P->ctx;
+    StageTimer t(ctx, s, GSC_STAGE_SOLVE);
+    unsigned int* d_ill = reinterpret_cast<unsigned int*>(P->misc.as<char>() + 16);
+    const int nb = (P->sh_deg + 1) * (P->sh_deg + 1);
+    if (!P->per_view) {
+        launch_fold_solve(nullptr, 0, P->means, P->vs.as<float>(), false, P->n_total, P->C, 0, lam,
+                          ctx->opt.kappa_max, coeffs, status, nullptr, nullptr, d_ill, s);
+        GSC_LAUNCHED("solve");
+        return GSC_OK;
+    }
+    for (size_t k = 0; k < P->scenes.size(); ++k) {
+        const gsc_scene& sc = P->scenes[k];
+        if (sc.n_gaussians == 0) continue;
+        launch_fold_solve(P->d_views.as<ViewInfo>() + P->scene_view0[k], P->scene_nviews[k],
+                          P->means + 3 * sc.gaussian_offset,
+                          P->vs.as<float>() + P->scene_vs0[k] * (P->C + 1), true, sc.n_gaussians,
+                          P->C, P->sh_deg, lam, ctx->opt.kappa_max,
+                          coeffs + sc.gaussian_offset * nb * P->C,
+                          status ? status + sc.gaussian_offset : nullptr, nullptr, nullptr, d_ill, s);
+        GSC_LAUNCHED("fold/solve");
+    }
+    return GSC_OK;
+}
+
+gsc_status plan_run(gsc_plan* P, const void* targets, int tdtype, const double* lam, float* coeffs,
+                    uint8_t* status, hipStream_t s) {
+    launch_fill_u32(P->misc.as<uint32_t>(), 0u, 6, s);
+    launch_fill_u32(P->vs.as<uint32_t>(), 0u, P->vs_slots * (uint64_t)(P->C + 1), s);
+    launch_cov3d(P->scales, P->quats, P->cov.as<float>(), P->n_total, s);
+    GSC_LAUNCHED("cov3d");
+    for (const auto& b : P->batches) {
+        gsc_status st = plan_bin_batch(P, b, s);
+        if (st != GSC_OK) return st;
+        StageTimer t(P->ctx, s, GSC_STAGE_BLEND);
+        if ((st = plan_accumulate(P, b, targets, tdtype, P->acc_chunk, s)) != GSC_OK) return st;
+    }
+    return plan_solve(P, lam, coeffs, status, s);
+}
+
+}  // namespace
+
 extern "C" {
 
 gsc_status gsc_default_options(gsc_options* out) {
@@ -725,6 +910,247 @@ gsc_status gsc_render_backward(gsc_ctx* ctx, const float* means, const float* sc
         GSC_LAUNCHED("fold");
     }
     ctx->stats_pending = true;
+    return GSC_OK;
+}
+
+gsc_status gsc_plan_create(gsc_ctx* ctx, const gsc_scene* scenes, int32_t n_scenes,
+                           const float* means, const float* scales, const float* quats,
+                           const float* opacities, const gsc_camera* cams, int32_t n_cams,
+                           int32_t C, int32_t sh_deg, gsc_plan** out, gsc_stream_t stream) {
+    if (!out) return fail(GSC_ERR_INVALID_ARG, "null plan pointer");
+    *out = nullptr;
+    if (!ctx) return fail(GSC_ERR_INVALID_ARG, "null ctx");
+    if (n_scenes < 0 || (n_scenes > 0 && !scenes)) return fail(GSC_ERR_INVALID_ARG, "bad scene table");
+    gsc_status st = validate_channels(C, sh_deg);
+    if (st != GSC_OK) return st;
+    if ((st = validate_cameras(cams, n_cams)) != GSC_OK) return st;
+    int64_t n_total = 0;
+    std::vector<std::pair<int64_t, int64_t>> ranges;
+    for (int k = 0; k < n_scenes; ++k) {
+        const gsc_scene& sc = scenes[k];
+        if (sc.n_gaussians < 0 || sc.n_gaussians > (int64_t)kItemMask)
+            return fail(GSC_ERR_INVALID_ARG, "scene %d: n_gaussians must be in [0, 2^26)", k);
+        if (sc.gaussian_offset < 0) return fail(GSC_ERR_INVALID_ARG, "scene %d: negative gaussian_offset", k);
+        if (sc.camera_offset < 0 || sc.n_cameras < 0 || (int64_t)sc.camera_offset + sc.n_cameras > n_cams)
+            return fail(GSC_ERR_INVALID_ARG, "scene %d: cameras out of range", k);
+        n_total = std::max<int64_t>(n_total, sc.gaussian_offset + sc.n_gaussians);
+        if (sc.n_gaussians > 0) ranges.push_back({sc.gaussian_offset, sc.gaussian_offset + sc.n_gaussians});
+    }
+    std::sort(ranges.begin(), ranges.end());
+    for (size_t k = 1; k < ranges.size(); ++k)
+        if (ranges[k].first < ranges[k - 1].second)
+            return fail(GSC_ERR_INVALID_ARG, "scenes share Gaussians");
+    if (n_total > 0 && (!means || !scales || !quats || !opacities))
+        return fail(GSC_ERR_INVALID_ARG, "null Gaussian array");
+    if (ctx->opt.flags & GSC_FLAG_VALIDATE_ONLY) return GSC_OK;
+
+    gsc_plan* P = new (std::nothrow) gsc_plan();
+    if (!P) return fail(GSC_ERR_HIP, "out of host memory");
+    std::unique_ptr<gsc_plan> guard(P);
+    hipStream_t s = (hipStream_t)stream;
+    P->ctx = ctx;
+    P->bp = blend_params(ctx->opt);
+    P->scenes.assign(scenes, scenes + n_scenes);
+    P->means = means; P->scales = scales; P->quats = quats; P->opac = opacities;
+    P->n_total = n_total;
+    P->C = C;
+    P->sh_deg = sh_deg;
+    P->per_view = sh_deg > 0;
+    // views scene by scene (scenes without Gaussians contribute none)
+    int64_t vs0 = 0;
+    for (int k = 0; k < n_scenes; ++k) {
+        const gsc_scene& sc = scenes[k];
+        P->scene_view0.push_back((int)P->views.size());
+        P->scene_vs0.push_back(vs0);
+        const int nv = sc.n_gaussians > 0 ? sc.n_cameras : 0;
+        P->scene_nviews.push_back(nv);
+        for (int j = 0; j < nv; ++j) {
+            ViewInfo v = make_view(cams[sc.camera_offset + j], 0, 0);
+            v.g_offset = sc.gaussian_offset;
+            v.n_gauss = (uint32_t)sc.n_gaussians;
+            v.scene = (uint32_t)k;
+            v.vs_base = vs0 + (int64_t)j * sc.n_gaussians;
+            P->views.push_back(v);
+        }
+        vs0 += (int64_t)nv * sc.n_gaussians;
+    }
+    P->vs_slots = P->per_view ? (uint64_t)vs0 : (uint64_t)std::max<int64_t>(n_total, 1);
+    // batches: consecutive views up to the item and tile limits
+    {
+        uint64_t items = 0, tiles = 0;
+        int v0 = 0;
+        for (int v = 0; v < (int)P->views.size(); ++v) {
+            const uint64_t ni = P->views[v].n_gauss, nt = (uint64_t)P->views[v].tiles_x * P->views[v].tiles_y;
+            if (v > v0 && (items + ni > kMaxItemsPerBatch || tiles + nt >= (1ull << 31))) {
+                P->batches.push_back({v0, v - v0, 0, 0, 0, 0});
+                v0 = v;
+                items = tiles = 0;
+            }
+            items += ni;
+            tiles += nt;
+        }
+        if (v0 < (int)P->views.size()) P->batches.push_back({v0, (int)P->views.size() - v0, 0, 0, 0, 0});
+    }
+    plan_number_views(P);
+    for (const auto& b : P->batches) P->max_items = std::max(P->max_items, b.n_items);
+    const size_t mi = (size_t)P->max_items;
+    GSC_HIP(P->misc.ensure(kPlanMiscBytes));
+    GSC_HIP(P->cov.ensure(sizeof(float) * 6 * (size_t)std::max<int64_t>(n_total, 1)));
+    GSC_HIP(P->keys.ensure(4 * mi + 4));
+    GSC_HIP(P->vals.ensure(4 * mi + 4));
+    GSC_HIP(P->keys_alt.ensure(4 * mi + 4));
+    GSC_HIP(P->vals_alt.ensure(4 * mi + 4));
+    GSC_HIP(P->counts.ensure(4 * mi + 4));
+    GSC_HIP(P->counts_sorted.ensure(4 * mi + 4));
+    GSC_HIP(P->offsets.ensure(4 * mi + 4));
+    GSC_HIP(P->rec0.ensure(16 * mi + 16));
+    GSC_HIP(P->rec1.ensure(16 * mi + 16));
+    GSC_HIP(P->d_views.ensure(sizeof(ViewInfo) * std::max<size_t>(P->views.size(), 1)));
+    if (!P->views.empty())
+        GSC_HIP(hipMemcpyAsync(P->d_views.p, P->views.data(), sizeof(ViewInfo) * P->views.size(),
+                               hipMemcpyHostToDevice, s));
+    launch_cov3d(scales, quats, P->cov.as<float>(), n_total, s);
+    GSC_LAUNCHED("cov3d");
+    // exact pair counts per batch (the geometry is fixed); split oversized batches
+    for (size_t k = 0; k < P->batches.size();) {
+        uint64_t pairs = 0;
+        if ((st = plan_count_pairs(P, P->batches[k], s, &pairs)) != GSC_OK) return st;
+        if (pairs >= kMaxPairsPerBatch) {
+            gsc_plan::Batch b = P->batches[k];
+            if (b.nv == 1) return fail(GSC_ERR_CAPACITY, "one view produces %llu tile pairs", (unsigned long long)pairs);
+            const int h = b.nv / 2;
+            P->batches[k].nv = h;
+            P->batches.insert(P->batches.begin() + k + 1, gsc_plan::Batch{b.v0 + h, b.nv - h, 0, 0, 0, 0});
+            plan_number_views(P);
+            GSC_HIP(hipMemcpyAsync(P->d_views.p, P->views.data(), sizeof(ViewInfo) * P->views.size(),
+                                   hipMemcpyHostToDevice, s));
+            continue;
+        }
+        P->batches[k].pair_cap = (uint32_t)pairs;
+        ++k;
+    }
+    GSC_HIP(hipStreamSynchronize(s));
+    for (const auto& b : P->batches) {
+        P->max_pairs = std::max(P->max_pairs, b.pair_cap);
+        P->max_tiles = std::max(P->max_tiles, b.n_tiles);
+        P->items_total += b.n_items;
+        P->pairs_total += b.pair_cap;
+    }
+    const size_t mp = (size_t)P->max_pairs;
+    GSC_HIP(P->pkeys.ensure(4 * mp + 4));
+    GSC_HIP(P->pvals.ensure(4 * mp + 4));
+    GSC_HIP(P->pkeys_alt.ensure(4 * mp + 4));
+    GSC_HIP(P->pvals_alt.ensure(4 * mp + 4));
+    GSC_HIP(P->ranges.ensure(sizeof(uint2) * ((size_t)P->max_tiles + 1)));
+    const size_t scr = std::max({radix_scratch_words(P->max_items), scan_scratch_words(P->max_items),
+                                 radix_scratch_words(P->max_pairs)});
+    GSC_HIP(P->sort_scratch.ensure(4 * scr + 256));
+    GSC_HIP(P->vs.ensure(4 * P->vs_slots * (size_t)(C + 1)));
+    *out = guard.release();
+    return GSC_OK;
+}
+
+void gsc_plan_destroy(gsc_plan* plan) { delete plan; }
+
+gsc_status gsc_colorize_batched(gsc_plan* plan, const void* targets, int32_t tdtype,
+                                const float* lambda, int32_t n_lambda, float* coeffs,
+                                uint8_t* status, gsc_stream_t stream) {
+    if (!plan) return fail(GSC_ERR_INVALID_ARG, "null plan");
+    if (tdtype != GSC_F32 && tdtype != GSC_BF16) return fail(GSC_ERR_INVALID_ARG, "tdtype must be GSC_F32 or GSC_BF16");
+    if (!plan->views.empty() && !targets) return fail(GSC_ERR_INVALID_ARG, "targets is null");
+    if (plan->n_total > 0 && !coeffs) return fail(GSC_ERR_INVALID_ARG, "coeffs is null");
+    double lam[kMaxNb];
+    gsc_status st = expand_lambda(lambda, n_lambda, plan->sh_deg, lam);
+    if (st != GSC_OK) return st;
+    if (plan->ctx->opt.flags & GSC_FLAG_VALIDATE_ONLY) return GSC_OK;
+    return plan_run(plan, targets, tdtype, lam, coeffs, status, (hipStream_t)stream);
+}
+
+gsc_status gsc_plan_autotune(gsc_plan* plan, const void* targets, int32_t tdtype,
+                             const float* lambda, int32_t n_lambda, float* coeffs,
+                             uint8_t* status, gsc_stream_t stream) {
+    if (!plan) return fail(GSC_ERR_INVALID_ARG, "null plan");
+    if (tdtype != GSC_F32 && tdtype != GSC_BF16) return fail(GSC_ERR_INVALID_ARG, "tdtype must be GSC_F32 or GSC_BF16");
+    if (!plan->views.empty() && !targets) return fail(GSC_ERR_INVALID_ARG, "targets is null");
+    if (plan->n_total > 0 && !coeffs) return fail(GSC_ERR_INVALID_ARG, "coeffs is null");
+    double lam[kMaxNb];
+    gsc_status st = expand_lambda(lambda, n_lambda, plan->sh_deg, lam);
+    if (st != GSC_OK) return st;
+    if (plan->ctx->opt.flags & GSC_FLAG_VALIDATE_ONLY) return GSC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    // candidates: the default split of C plus wider and narrower chunks
+    std::vector<int> cand;
+    for (int c : {accumulate_chunk(plan->C), 16, 8, 4})
+        if (std::find(cand.begin(), cand.end(), c) == cand.end() && c <= std::max(4, plan->C))
+            cand.push_back(c);
+    if (cand.size() > 4) cand.resize(4);
+    std::vector<float> tot(cand.size(), 0.0f);
+    hipEvent_t e0, e1;
+    GSC_HIP(hipEventCreate(&e0));
+    GSC_HIP(hipEventCreate(&e1));
+    const int saved_flags = plan->ctx->opt.flags;
+    plan->ctx->opt.flags &= ~GSC_FLAG_PROFILE;
+    auto cleanup = [&]() {
+        plan->ctx->opt.flags = saved_flags;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    };
+    launch_fill_u32(plan->misc.as<uint32_t>(), 0u, 6, s);
+    launch_cov3d(plan->scales, plan->quats, plan->cov.as<float>(), plan->n_total, s);
+    for (const auto& b : plan->batches) {
+        if ((st = plan_bin_batch(plan, b, s)) != GSC_OK) { cleanup(); return st; }
+        for (size_t k = 0; k < cand.size(); ++k) {
+            float best = 1e30f;
+            for (int rep = 0; rep < 2; ++rep) {
+                hipError_t e = hipEventRecord(e0, s);
+                if (e == hipSuccess) {
+                    if ((st = plan_accumulate(plan, b, targets, tdtype, cand[k], s)) != GSC_OK) { cleanup(); return st; }
+                    e = hipEventRecord(e1, s);
+                }
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.0f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) { cleanup(); return fail(GSC_ERR_HIP, "autotune timing: %s", hipGetErrorString(e)); }
+                best = std::min(best, ms);
+            }
+            tot[k] += best;
+        }
+    }
+    size_t bi = 0;
+    for (size_t k = 0; k < cand.size(); ++k) {
+        plan->tune_chunks[k] = cand[k];
+        plan->tune_ms[k] = tot[k];
+        if (tot[k] < tot[bi]) bi = k;
+    }
+    plan->acc_chunk = cand.empty() ? 0 : cand[bi];
+    cleanup();
+    if ((st = plan_run(plan, targets, tdtype, lam, coeffs, status, s)) != GSC_OK) return st;
+    GSC_HIP(hipStreamSynchronize(s));
+    return GSC_OK;
+}
+
+gsc_status gsc_plan_get_info(gsc_plan* plan, gsc_plan_info* out) {
+    if (!plan || !out) return fail(GSC_ERR_INVALID_ARG, "null plan or output");
+    memset(out, 0, sizeof(*out));
+    uint32_t buf[6] = {0, 0, 0, 0, 0, 0};
+    if (plan->misc.p) {
+        GSC_HIP(hipDeviceSynchronize());
+        GSC_HIP(hipMemcpy(buf, plan->misc.p, sizeof(buf), hipMemcpyDeviceToHost));
+    }
+    uint64_t contrib = 0;
+    memcpy(&contrib, buf, 8);
+    out->contributions = contrib;
+    out->dropped_pairs = buf[3];
+    out->ill_conditioned = buf[4];
+    out->batches = (uint32_t)plan->batches.size();
+    out->views = (uint32_t)plan->views.size();
+    out->items = plan->items_total;
+    out->pair_capacity = plan->pairs_total;
+    out->accumulate_chunk = plan->acc_chunk ? plan->acc_chunk : accumulate_chunk(plan->C);
+    for (int i = 0; i < 4; ++i) {
+        out->tuned_chunk[i] = plan->tune_chunks[i];
+        out->tuned_ms[i] = plan->tune_ms[i];
+    }
     return GSC_OK;
 }
 

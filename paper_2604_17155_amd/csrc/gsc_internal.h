@@ -72,17 +72,20 @@ void launch_project(const ViewInfo* views, int n_views, uint32_t n_items, const 
 void launch_gather_counts(const uint32_t* sorted_vals, const uint32_t* counts, uint32_t* out,
                           uint32_t n, hipStream_t s);
 
+// Pairs at offsets >= cap are dropped and counted in *overflow (if given).
 void launch_emit(const ViewInfo* views, int n_views, const uint32_t* sorted_vals,
                  const uint32_t* offsets, const uint32_t* counts, const float4* rec0,
                  const float4* rec1, BlendParams bp, uint32_t n_items, uint32_t n_tiles,
-                 uint32_t* pair_keys, uint32_t* pair_vals, hipStream_t s);
+                 uint32_t* pair_keys, uint32_t* pair_vals, hipStream_t s,
+                 uint32_t cap = 0xFFFFFFFFu, uint32_t* overflow = nullptr);
 
 // Sum of n uint32 counts into *out (u64, must be zeroed).
 void launch_sum_u64(const uint32_t* counts, uint32_t n, unsigned long long* out, hipStream_t s);
 
-// Pairs whose key is >= n_tiles are ignored.
+// Pairs whose key is >= n_tiles are ignored.  n_dev (optional, device): live
+// pair count, clamped to n_pairs.
 void launch_tile_ranges(const uint32_t* sorted_keys, uint32_t n_pairs, uint32_t n_tiles,
-                        uint2* ranges, hipStream_t s);
+                        uint2* ranges, hipStream_t s, const uint32_t* n_dev = nullptr);
 
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 
@@ -94,9 +97,12 @@ void launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total,
 
 // Stable LSD radix sort of (key, val) on the low `bits` bits of key. The
 // result ends in (keys, vals); alt buffers are scratch of the same size.
+// n_dev (optional, device): the live count, clamped to n (the capacity the
+// launches are sized for); no host synchronisation is needed.
 size_t radix_scratch_words(uint32_t n);
 void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
-                uint32_t n, int bits, uint32_t* scratch, hipStream_t s);
+                uint32_t n, int bits, uint32_t* scratch, hipStream_t s,
+                const uint32_t* n_dev = nullptr);
 
 // Channels per accumulate launch for C channels (launches = ceil(C / chunk)).
 int accumulate_chunk(int C);
@@ -107,6 +113,16 @@ void launch_accumulate(const ViewInfo* views, int n_views, uint32_t n_tiles, con
                        const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
                        const void* targets, int tdtype, int C, bool per_view, BlendParams bp,
                        float* VS, unsigned long long* counter, uint32_t* gcount, hipStream_t s);
+
+// As launch_accumulate with `chunk` channels per launch (1, 2, 3, 4, 8 or 16;
+// anything else picks accumulate_chunk(C)).
+bool accumulate_chunk_valid(int chunk);
+void launch_accumulate_chunked(const ViewInfo* views, int n_views, uint32_t n_tiles,
+                               const uint2* ranges, const uint32_t* pair_vals, const float4* rec0,
+                               const float4* rec1, const void* targets, int tdtype, int C,
+                               bool per_view, BlendParams bp, float* VS,
+                               unsigned long long* counter, uint32_t* gcount, int chunk,
+                               hipStream_t s);
 
 // Per item colour gamma[item][c] = sum_m coeffs[g][m][c] phi_m(dir_gv).
 void launch_view_colors(const ViewInfo* views, int n_views, uint32_t n_items, const float* means,

@@ -172,15 +172,30 @@ static void launch_acc_cc(const ViewInfo* views, int n_views, uint32_t n_tiles, 
 
 int accumulate_chunk(int C) { return C <= 3 ? C : (C <= 4 ? 4 : (C <= 8 ? 8 : 16)); }
 
+bool accumulate_chunk_valid(int chunk) {
+    return chunk == 1 || chunk == 2 || chunk == 3 || chunk == 4 || chunk == 8 || chunk == 16;
+}
+
 void launch_accumulate(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
                        const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
                        const void* targets, int tdtype, int C, bool per_view, BlendParams bp,
                        float* VS, unsigned long long* counter, uint32_t* gcount, hipStream_t s) {
+    launch_accumulate_chunked(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, targets,
+                              tdtype, C, per_view, bp, VS, counter, gcount, 0, s);
+}
+
+void launch_accumulate_chunked(const ViewInfo* views, int n_views, uint32_t n_tiles,
+                               const uint2* ranges, const uint32_t* pair_vals, const float4* rec0,
+                               const float4* rec1, const void* targets, int tdtype, int C,
+                               bool per_view, BlendParams bp, float* VS,
+                               unsigned long long* counter, uint32_t* gcount, int chunk,
+                               hipStream_t s) {
     if (n_tiles == 0) return;
+    if (!accumulate_chunk_valid(chunk)) chunk = accumulate_chunk(C);
 #define GSC_ACC(CCV)                                                                              \
     launch_acc_cc<CCV>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, targets, tdtype, C, \
                        per_view, bp, VS, counter, gcount, s)
-    switch (accumulate_chunk(C)) {
+    switch (chunk) {
         case 1: GSC_ACC(1); break;
         case 2: GSC_ACC(2); break;
         case 3: GSC_ACC(3); break;

@@ -208,7 +208,8 @@ __global__ void k_emit(const ViewInfo* __restrict__ views, int n_views,
                        const uint32_t* __restrict__ sorted_vals,
                        const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ counts,
                        const float4* __restrict__ rec0, const float4* __restrict__ rec1,
-                       BlendParams bp, uint32_t n_items, uint32_t sentinel,
+                       BlendParams bp, uint32_t n_items, uint32_t sentinel, uint32_t cap,
+                       uint32_t* __restrict__ overflow,
                        uint32_t* __restrict__ pair_keys, uint32_t* __restrict__ pair_vals) {
     uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_items) return;
@@ -217,7 +218,11 @@ __global__ void k_emit(const ViewInfo* __restrict__ views, int n_views,
     const ViewInfo& V = views[find_view_item(views, n_views, i)];
     const float4 r0 = rec0[i], r1 = rec1[i];
     uint32_t off = offsets[k];
-    const uint32_t end = off + counts[i];
+    uint32_t end = off + counts[i];
+    if (end > cap || end < off) {  // capacity exceeded: keep what fits, report the rest
+        if (overflow) atomicAdd(overflow, 1u);
+        end = off < cap ? cap : off;
+    }
     footprint_rows(r0, r1, reach_q(r1.w, bp), V.width, V.height,
                    [&](int ty, const int* lo, const int* hi) {
         int t0 = 1 << 30, t1 = -1;
@@ -245,11 +250,12 @@ __global__ void k_emit(const ViewInfo* __restrict__ views, int n_views,
 void launch_emit(const ViewInfo* views, int n_views, const uint32_t* sorted_vals,
                  const uint32_t* offsets, const uint32_t* counts, const float4* rec0,
                  const float4* rec1, BlendParams bp, uint32_t n_items, uint32_t n_tiles,
-                 uint32_t* pair_keys, uint32_t* pair_vals, hipStream_t s) {
+                 uint32_t* pair_keys, uint32_t* pair_vals, hipStream_t s, uint32_t cap,
+                 uint32_t* overflow) {
     if (n_items == 0) return;
     hipLaunchKernelGGL(k_emit, dim3((n_items + 255) / 256), dim3(256), 0, s, views, n_views,
-                       sorted_vals, offsets, counts, rec0, rec1, bp, n_items, n_tiles, pair_keys,
-                       pair_vals);
+                       sorted_vals, offsets, counts, rec0, rec1, bp, n_items, n_tiles, cap,
+                       overflow, pair_keys, pair_vals);
 }
 
 __global__ __launch_bounds__(256) void k_sum_u64(const uint32_t* __restrict__ counts, uint32_t n,
@@ -272,8 +278,10 @@ void launch_sum_u64(const uint32_t* counts, uint32_t n, unsigned long long* out,
     hipLaunchKernelGGL(k_sum_u64, dim3(blocks), dim3(256), 0, s, counts, n, out);
 }
 
-__global__ void k_tile_ranges(const uint32_t* __restrict__ keys, uint32_t n, uint32_t n_tiles,
+__global__ void k_tile_ranges(const uint32_t* __restrict__ keys, uint32_t n,
+                              const uint32_t* __restrict__ n_dev, uint32_t n_tiles,
                               uint2* __restrict__ ranges) {
+    if (n_dev) n = min(n, *n_dev);
     uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     uint32_t t = keys[k];
@@ -283,10 +291,10 @@ __global__ void k_tile_ranges(const uint32_t* __restrict__ keys, uint32_t n, uin
 }
 
 void launch_tile_ranges(const uint32_t* sorted_keys, uint32_t n_pairs, uint32_t n_tiles,
-                        uint2* ranges, hipStream_t s) {
+                        uint2* ranges, hipStream_t s, const uint32_t* n_dev) {
     if (n_pairs == 0) return;
     hipLaunchKernelGGL(k_tile_ranges, dim3((n_pairs + 255) / 256), dim3(256), 0, s, sorted_keys,
-                       n_pairs, n_tiles, ranges);
+                       n_pairs, n_dev, n_tiles, ranges);
 }
 
 }  // namespace gsc

@@ -3,6 +3,8 @@
 // The sort orders the (view, Gaussian) items by depth and then the emitted
 // (tile, item) pairs by tile.  Stability of every pass is what carries the
 // depth order (and the index tie-break) into each tile's list.
+#include <algorithm>
+
 #include "gsc_internal.h"
 
 namespace gsc {
@@ -134,9 +136,13 @@ void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
 // ---- radix sort ----------------------------------------------------------
 
 // Digit histogram of one 4096-key tile, written digit-major: hist[d * nblocks + b].
+// n_dev (optional): the live key count, read on the device and clamped to n;
+// the grid is sized for n.
 __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint32_t* __restrict__ keys, uint32_t n,
+                                                        const uint32_t* __restrict__ n_dev,
                                                         int shift, uint32_t* __restrict__ hist,
                                                         uint32_t nblocks) {
+    if (n_dev) n = min(n, *n_dev);
     __shared__ uint32_t h[kRsWaves][256];
     int w = threadIdx.x >> 6;
     for (int k = threadIdx.x; k < kRsWaves * 256; k += kRsThreads) (&h[0][0])[k] = 0;
@@ -165,9 +171,11 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* __res
                                                            const uint32_t* __restrict__ vals_in,
                                                            uint32_t* __restrict__ keys_out,
                                                            uint32_t* __restrict__ vals_out,
-                                                           uint32_t n, int shift,
+                                                           uint32_t n, const uint32_t* __restrict__ n_dev, int shift,
                                                            const uint32_t* __restrict__ offs,
                                                            uint32_t nblocks) {
+    if (n_dev) n = min(n, *n_dev);
+    if ((uint64_t)blockIdx.x * kRsTile >= n) return;  // whole block: no live keys
     __shared__ uint32_t wcnt[kRsWaves][256];
     __shared__ uint32_t dstart[256];
     __shared__ uint32_t gbase[256];
@@ -244,8 +252,18 @@ size_t radix_scratch_words(uint32_t n) {
     return (size_t)(((h + 63) / 64) * 64 + scan_scratch_words(h));
 }
 
+__global__ void k_copy_pairs(const uint32_t* __restrict__ ka, const uint32_t* __restrict__ va,
+                             uint32_t* __restrict__ kb, uint32_t* __restrict__ vb, uint32_t n,
+                             const uint32_t* __restrict__ n_dev) {
+    if (n_dev) n = min(n, *n_dev);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        kb[i] = ka[i];
+        vb[i] = va[i];
+    }
+}
+
 void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, uint32_t n,
-                int bits, uint32_t* scratch, hipStream_t s) {
+                int bits, uint32_t* scratch, hipStream_t s, const uint32_t* n_dev) {
     if (n <= 1 || bits <= 0) return;
     uint32_t nb = (n + kRsTile - 1) / kRsTile;
     uint32_t* hist = scratch;
@@ -254,17 +272,18 @@ void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* va
     uint32_t *sk = keys, *sv = vals, *dk = keys_alt, *dv = vals_alt;
     for (int p = 0; p < passes; ++p) {
         int shift = 8 * p;
-        hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kRsThreads), 0, s, sk, n, shift, hist, nb);
+        hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kRsThreads), 0, s, sk, n, n_dev, shift, hist, nb);
         launch_scan(hist, hist, 256u * nb, nullptr, sscr, s);
-        hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kRsThreads), 0, s, sk, sv, dk, dv, n, shift,
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kRsThreads), 0, s, sk, sv, dk, dv, n, n_dev, shift,
                            hist, nb);
         uint32_t* t;
         t = sk; sk = dk; dk = t;
         t = sv; sv = dv; dv = t;
     }
     if (sk != keys) {
-        (void)hipMemcpyAsync(keys, sk, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s);
-        (void)hipMemcpyAsync(vals, sv, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s);
+        // odd pass count: copy back with a kernel (plain kernel nodes under graph capture)
+        const uint32_t blocks = std::min<uint32_t>((n + 255) / 256, 8192u);
+        hipLaunchKernelGGL(k_copy_pairs, dim3(blocks), dim3(256), 0, s, sk, sv, keys, vals, n, n_dev);
     }
 }
 

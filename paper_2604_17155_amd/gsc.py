@@ -59,6 +59,19 @@ class GscExtras(ct.Structure):
     _fields_ = [("view_sums", ct.c_void_p), ("visibility", ct.c_void_p), ("counts", ct.c_void_p)]
 
 
+class GscScene(ct.Structure):
+    _fields_ = [("gaussian_offset", ct.c_int64), ("n_gaussians", ct.c_int64),
+                ("camera_offset", ct.c_int32), ("n_cameras", ct.c_int32)]
+
+
+class GscPlanInfo(ct.Structure):
+    _fields_ = [("contributions", ct.c_uint64), ("items", ct.c_uint64),
+                ("pair_capacity", ct.c_uint64), ("dropped_pairs", ct.c_uint32),
+                ("ill_conditioned", ct.c_uint32), ("batches", ct.c_uint32), ("views", ct.c_uint32),
+                ("accumulate_chunk", ct.c_int32), ("tuned_chunk", ct.c_int32 * 4),
+                ("tuned_ms", ct.c_float * 4)]
+
+
 class GscError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"gsc error {status}: {msg}")
@@ -98,6 +111,16 @@ def load(path: Optional[str] = None):
     lib.gsc_colorize_backward.restype = ct.c_int
     lib.gsc_render_backward.argtypes = [P, P, P, P, P, i64, P, i32, P, i32, i32, P, P, P, P]
     lib.gsc_render_backward.restype = ct.c_int
+    lib.gsc_plan_create.argtypes = [P, P, i32, P, P, P, P, P, i32, i32, i32, ct.POINTER(P), P]
+    lib.gsc_plan_create.restype = ct.c_int
+    lib.gsc_plan_destroy.argtypes = [P]
+    lib.gsc_plan_destroy.restype = None
+    lib.gsc_colorize_batched.argtypes = [P, P, i32, P, i32, P, P, P]
+    lib.gsc_colorize_batched.restype = ct.c_int
+    lib.gsc_plan_autotune.argtypes = [P, P, i32, P, i32, P, P, P]
+    lib.gsc_plan_autotune.restype = ct.c_int
+    lib.gsc_plan_get_info.argtypes = [P, ct.POINTER(GscPlanInfo)]
+    lib.gsc_plan_get_info.restype = ct.c_int
     lib.gsc_get_stats.argtypes = [P, ct.POINTER(GscStats)]
     lib.gsc_get_stats.restype = ct.c_int
     lib.gsc_last_error.argtypes = []
@@ -295,6 +318,76 @@ class Context:
                                           _stream_ptr(stream))
         _check(self.lib, st)
         return gc, go
+
+
+class Plan:
+    """A batched multi-scene colorize with all sizes fixed at creation.
+
+    scenes: sequence of (gaussian_offset, n_gaussians, camera_offset, n_cameras);
+    means/scales/quats/opacities: concatenated device tensors; cams: all cameras
+    (their pixel offsets index one concatenated target array; by default the
+    cameras' cumulative sizes).  run() allocates nothing when coeffs/status
+    are passed in, never synchronises, and may be captured into a graph."""
+
+    def __init__(self, context: Context, scenes, means, scales, quats, opacities, cams, C: int,
+                 sh_deg: int, offsets=None, stream=None):
+        self.context = context
+        self.lib = context.lib
+        self.C, self.sh_deg = int(C), int(sh_deg)
+        self._keep = (means, scales, quats, opacities)
+        tab = (GscScene * max(1, len(scenes)))()
+        for i, sc in enumerate(scenes):
+            tab[i].gaussian_offset, tab[i].n_gaussians = int(sc[0]), int(sc[1])
+            tab[i].camera_offset, tab[i].n_cameras = int(sc[2]), int(sc[3])
+        self.n_total = max([int(sc[0]) + int(sc[1]) for sc in scenes] or [0])
+        self.cam_arr = make_cameras(cams, offsets)
+        h = ct.c_void_p()
+        st = self.lib.gsc_plan_create(context.handle, tab, len(scenes), _ptr(means), _ptr(scales),
+                                      _ptr(quats), _ptr(opacities), self.cam_arr, len(cams), self.C,
+                                      self.sh_deg, ct.byref(h), _stream_ptr(stream))
+        _check(self.lib, st)
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.gsc_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _outputs(self, coeffs, status, device):
+        import torch
+        nb = (self.sh_deg + 1) ** 2
+        if coeffs is None:
+            coeffs = torch.zeros((self.n_total, nb, self.C), dtype=torch.float32, device=device)
+        if status is None:
+            status = torch.zeros((self.n_total,), dtype=torch.uint8, device=device)
+        return coeffs, status
+
+    def run(self, targets, lam, coeffs=None, status=None, stream=None):
+        coeffs, status = self._outputs(coeffs, status, targets.device)
+        lam_a = (ct.c_float * len(lam))(*[float(v) for v in lam])
+        st = self.lib.gsc_colorize_batched(self.handle, _ptr(targets), _tdtype(targets), lam_a,
+                                           len(lam), _ptr(coeffs), _ptr(status), _stream_ptr(stream))
+        _check(self.lib, st)
+        return coeffs, status
+
+    def autotune(self, targets, lam, coeffs=None, status=None, stream=None):
+        coeffs, status = self._outputs(coeffs, status, targets.device)
+        lam_a = (ct.c_float * len(lam))(*[float(v) for v in lam])
+        st = self.lib.gsc_plan_autotune(self.handle, _ptr(targets), _tdtype(targets), lam_a,
+                                        len(lam), _ptr(coeffs), _ptr(status), _stream_ptr(stream))
+        _check(self.lib, st)
+        return coeffs, status
+
+    def info(self) -> GscPlanInfo:
+        out = GscPlanInfo()
+        _check(self.lib, self.lib.gsc_plan_get_info(self.handle, ct.byref(out)))
+        return out
 
 
 def _rows(cams, offsets=None) -> int:

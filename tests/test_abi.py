@@ -162,3 +162,30 @@ def test_backward_validation(lib):
     assert "grad_images" in lib.gsc_last_error().decode()
     assert rb(ctx.handle, FAKE, FAKE, FAKE, FAKE, 10, arr, 2, None, 3, 0, FAKE, FAKE, FAKE,
               None) == gsc.GSC_ERR_INVALID_ARG
+
+
+def test_plan_validation(lib):
+    ctx = _vctx()
+    cams = syn.circle_cams(4, 3.0, 16, 16)
+    arr = gsc.make_cameras(cams)
+
+    def create(scenes, C=16, sh_deg=0):
+        tab = (gsc.GscScene * max(1, len(scenes)))()
+        for i, sc in enumerate(scenes):
+            tab[i].gaussian_offset, tab[i].n_gaussians = sc[0], sc[1]
+            tab[i].camera_offset, tab[i].n_cameras = sc[2], sc[3]
+        h = ct.c_void_p()
+        return lib.gsc_plan_create(ctx.handle, tab, len(scenes), FAKE, FAKE, FAKE, FAKE, arr, 4, C,
+                                   sh_deg, ct.byref(h), None)
+
+    assert create([(0, 100, 0, 2), (100, 50, 2, 2)]) == gsc.GSC_OK
+    assert create([]) == gsc.GSC_OK
+    assert create([(0, 100, 0, 2), (50, 100, 2, 2)]) == gsc.GSC_ERR_INVALID_ARG
+    assert "share" in lib.gsc_last_error().decode()
+    assert create([(0, 100, 3, 2)]) == gsc.GSC_ERR_INVALID_ARG
+    assert "cameras out of range" in lib.gsc_last_error().decode()
+    assert create([(0, -1, 0, 2)]) == gsc.GSC_ERR_INVALID_ARG
+    assert create([(0, 1 << 26, 0, 2)]) == gsc.GSC_ERR_INVALID_ARG
+    assert create([(0, 10, 0, 2)], C=65) == gsc.GSC_ERR_INVALID_ARG
+    assert create([(0, 10, 0, 2)], sh_deg=4) == gsc.GSC_ERR_INVALID_ARG
+    assert lib.gsc_colorize_batched(None, FAKE, 0, None, 1, FAKE, None, None) == gsc.GSC_ERR_INVALID_ARG
