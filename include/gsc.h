@@ -271,9 +271,10 @@ typedef struct {
     uint32_t ill_conditioned;   /* Gaussians flagged GSC_G_ILL_COND by the last run */
     uint32_t batches;           /* view batches per run */
     uint32_t views;             /* views per run */
-    int32_t accumulate_chunk;   /* channels per accumulate launch in use */
-    int32_t tuned_chunk[4];     /* candidates timed by gsc_plan_autotune (0: unused) */
-    float tuned_ms[4];          /* their accumulate time per run, ms */
+    int32_t accumulate_variant; /* accumulate launch shape in use: channels per launch,
+                                   plus 256 for the persistent work-queue launch */
+    int32_t tuned_variant[8];   /* shapes timed by gsc_plan_autotune (0: unused) */
+    float tuned_ms[8];          /* their accumulate time per run, ms */
 } gsc_plan_info;
 
 /*
@@ -305,10 +306,12 @@ gsc_status gsc_colorize_batched(gsc_plan* plan, const void* targets, int32_t tdt
                                 uint8_t* status, gsc_stream_t stream);
 
 /*
- * Autotune the plan's accumulate launch shape (channels per launch) on the
- * given inputs: times each candidate over all view batches, keeps the fastest,
- * then runs the plan once more so that coeffs/status hold a clean result.
- * Synchronises `stream`.  Not capturable.
+ * Autotune the plan's accumulate launch shape on the given inputs: channels
+ * per launch (each launch re-blends the tiles for its channel chunk) and the
+ * grid form (one block per four tiles, or a persistent grid whose waves take
+ * tiles from a queue).  Times each candidate over all view batches, keeps the
+ * fastest, then runs the plan once more so that coeffs/status hold a clean
+ * result.  Synchronises `stream`.  Not capturable.
  */
 gsc_status gsc_plan_autotune(gsc_plan* plan, const void* targets, int32_t tdtype,
                              const float* lambda, int32_t n_lambda, float* coeffs,

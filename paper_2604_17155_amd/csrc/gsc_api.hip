@@ -441,14 +441,15 @@ struct gsc_plan {
     uint32_t max_items = 0, max_pairs = 0, max_tiles = 0;
     uint64_t items_total = 0, pairs_total = 0;
     int acc_chunk = 0;                // channels per accumulate launch (0: default)
-    float tune_ms[4] = {0.f, 0.f, 0.f, 0.f};
-    int tune_chunks[4] = {0, 0, 0, 0};
+    bool acc_persistent = false;      // persistent work-queue accumulate
+    float tune_ms[8] = {};
+    int tune_variant[8] = {};
     DevBuf d_views, cov, keys, vals, keys_alt, vals_alt, counts, counts_sorted, offsets, rec0, rec1,
-        sort_scratch, pkeys, pvals, pkeys_alt, pvals_alt, ranges, vs, misc;
+        sort_scratch, pkeys, pvals, pkeys_alt, pvals_alt, ranges, vs, misc, queues;
     ~gsc_plan() {
         DevBuf* all[] = {&d_views, &cov, &keys, &vals, &keys_alt, &vals_alt, &counts, &counts_sorted,
                          &offsets, &rec0, &rec1, &sort_scratch, &pkeys, &pvals, &pkeys_alt,
-                         &pvals_alt, &ranges, &vs, &misc};
+                         &pvals_alt, &ranges, &vs, &misc, &queues};
         for (DevBuf* b : all) b->release();
     }
 };
@@ -500,12 +501,13 @@ void plan_number_views(gsc_plan* P) {
 }
 
 gsc_status plan_accumulate(gsc_plan* P, const gsc_plan::Batch& b, const void* targets, int tdtype,
-                           int chunk, hipStream_t s) {
+                           int chunk, bool persistent, hipStream_t s) {
     const ViewInfo* dv = P->d_views.as<ViewInfo>() + b.v0;
     unsigned long long* d_counter = reinterpret_cast<unsigned long long*>(P->misc.p);
     launch_accumulate_chunked(dv, b.nv, b.n_tiles, P->ranges.as<uint2>(), P->pvals.as<uint32_t>(),
                               P->rec0.as<float4>(), P->rec1.as<float4>(), targets, tdtype, P->C,
-                              P->per_view, P->bp, P->vs.as<float>(), d_counter, nullptr, chunk, s);
+                              P->per_view, P->bp, P->vs.as<float>(), d_counter, nullptr, chunk, s,
+                              persistent ? P->queues.as<uint32_t>() : nullptr);
     GSC_LAUNCHED("accumulate");
     return GSC_OK;
 }
@@ -593,7 +595,8 @@ gsc_status plan_run(gsc_plan* P, const void* targets, int tdtype, const double* 
         gsc_status st = plan_bin_batch(P, b, s);
         if (st != GSC_OK) return st;
         StageTimer t(P->ctx, s, GSC_STAGE_BLEND);
-        if ((st = plan_accumulate(P, b, targets, tdtype, P->acc_chunk, s)) != GSC_OK) return st;
+        if ((st = plan_accumulate(P, b, targets, tdtype, P->acc_chunk, P->acc_persistent, s)) != GSC_OK)
+            return st;
     }
     return plan_solve(P, lam, coeffs, status, s);
 }
@@ -1046,6 +1049,7 @@ gsc_status gsc_plan_create(gsc_ctx* ctx, const gsc_scene* scenes, int32_t n_scen
                                  radix_scratch_words(P->max_pairs)});
     GSC_HIP(P->sort_scratch.ensure(4 * scr + 256));
     GSC_HIP(P->vs.ensure(4 * P->vs_slots * (size_t)(C + 1)));
+    GSC_HIP(P->queues.ensure(4 * (size_t)kMaxC));
     *out = guard.release();
     return GSC_OK;
 }
@@ -1078,12 +1082,16 @@ gsc_status gsc_plan_autotune(gsc_plan* plan, const void* targets, int32_t tdtype
     if (st != GSC_OK) return st;
     if (plan->ctx->opt.flags & GSC_FLAG_VALIDATE_ONLY) return GSC_OK;
     hipStream_t s = (hipStream_t)stream;
-    // candidates: the default split of C plus wider and narrower chunks
-    std::vector<int> cand;
+    // candidates: (channels per launch, persistent or not); the default split
+    // of C plus wider and narrower chunks
+    std::vector<int> chunks;
     for (int c : {accumulate_chunk(plan->C), 16, 8, 4})
-        if (std::find(cand.begin(), cand.end(), c) == cand.end() && c <= std::max(4, plan->C))
-            cand.push_back(c);
-    if (cand.size() > 4) cand.resize(4);
+        if (std::find(chunks.begin(), chunks.end(), c) == chunks.end() && c <= std::max(4, plan->C))
+            chunks.push_back(c);
+    std::vector<int> cand;  // chunk | persistent << 8
+    for (int c : chunks)
+        for (int p = 0; p < 2; ++p) cand.push_back(c | (p << 8));
+    if (cand.size() > 8) cand.resize(8);
     std::vector<float> tot(cand.size(), 0.0f);
     hipEvent_t e0, e1;
     GSC_HIP(hipEventCreate(&e0));
@@ -1104,7 +1112,8 @@ gsc_status gsc_plan_autotune(gsc_plan* plan, const void* targets, int32_t tdtype
             for (int rep = 0; rep < 2; ++rep) {
                 hipError_t e = hipEventRecord(e0, s);
                 if (e == hipSuccess) {
-                    if ((st = plan_accumulate(plan, b, targets, tdtype, cand[k], s)) != GSC_OK) { cleanup(); return st; }
+                    if ((st = plan_accumulate(plan, b, targets, tdtype, cand[k] & 255, (cand[k] >> 8) != 0,
+                                              s)) != GSC_OK) { cleanup(); return st; }
                     e = hipEventRecord(e1, s);
                 }
                 if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -1118,11 +1127,12 @@ gsc_status gsc_plan_autotune(gsc_plan* plan, const void* targets, int32_t tdtype
     }
     size_t bi = 0;
     for (size_t k = 0; k < cand.size(); ++k) {
-        plan->tune_chunks[k] = cand[k];
+        plan->tune_variant[k] = cand[k];
         plan->tune_ms[k] = tot[k];
         if (tot[k] < tot[bi]) bi = k;
     }
-    plan->acc_chunk = cand.empty() ? 0 : cand[bi];
+    plan->acc_chunk = cand.empty() ? 0 : (cand[bi] & 255);
+    plan->acc_persistent = !cand.empty() && (cand[bi] >> 8) != 0;
     cleanup();
     if ((st = plan_run(plan, targets, tdtype, lam, coeffs, status, s)) != GSC_OK) return st;
     GSC_HIP(hipStreamSynchronize(s));
@@ -1146,9 +1156,10 @@ gsc_status gsc_plan_get_info(gsc_plan* plan, gsc_plan_info* out) {
     out->views = (uint32_t)plan->views.size();
     out->items = plan->items_total;
     out->pair_capacity = plan->pairs_total;
-    out->accumulate_chunk = plan->acc_chunk ? plan->acc_chunk : accumulate_chunk(plan->C);
-    for (int i = 0; i < 4; ++i) {
-        out->tuned_chunk[i] = plan->tune_chunks[i];
+    out->accumulate_variant = (plan->acc_chunk ? plan->acc_chunk : accumulate_chunk(plan->C)) |
+                              (plan->acc_persistent ? 256 : 0);
+    for (int i = 0; i < 8; ++i) {
+        out->tuned_variant[i] = plan->tune_variant[i];
         out->tuned_ms[i] = plan->tune_ms[i];
     }
     return GSC_OK;

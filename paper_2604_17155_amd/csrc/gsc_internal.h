@@ -115,14 +115,18 @@ void launch_accumulate(const ViewInfo* views, int n_views, uint32_t n_tiles, con
                        float* VS, unsigned long long* counter, uint32_t* gcount, hipStream_t s);
 
 // As launch_accumulate with `chunk` channels per launch (1, 2, 3, 4, 8 or 16;
-// anything else picks accumulate_chunk(C)).
+// anything else picks accumulate_chunk(C)).  queues (device, one word per
+// channel pass, zeroed here by a fill kernel): persistent launches of
+// kPersistentBlocks blocks that take tiles from a counter; nullptr: one
+// block per four tiles.
+constexpr uint32_t kPersistentBlocks = 2048;  // 8 blocks of 4 waves per CU
 bool accumulate_chunk_valid(int chunk);
 void launch_accumulate_chunked(const ViewInfo* views, int n_views, uint32_t n_tiles,
                                const uint2* ranges, const uint32_t* pair_vals, const float4* rec0,
                                const float4* rec1, const void* targets, int tdtype, int C,
                                bool per_view, BlendParams bp, float* VS,
                                unsigned long long* counter, uint32_t* gcount, int chunk,
-                               hipStream_t s);
+                               hipStream_t s, uint32_t* queues = nullptr);
 
 // Per item colour gamma[item][c] = sum_m coeffs[g][m][c] phi_m(dir_gv).
 void launch_view_colors(const ViewInfo* views, int n_views, uint32_t n_items, const float* means,

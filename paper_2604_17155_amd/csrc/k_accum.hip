@@ -12,20 +12,21 @@
 #include "sh.h"
 #include "wave_ops.h"
 
+#include <algorithm>
+
 namespace gsc {
 
 
-// CC: channels handled by this launch (chunk [c_off, c_off + CC) of C).
+// One tile, by one wave: blend its pixels front to back and add each
+// Gaussian's tile share of V and S (channels [c_off, c_off + CC) of C) to its
+// slot.  Returns this lane's accepted contributions.
 template <int CC, bool BF16>
-__global__ __launch_bounds__(256) void k_accumulate(
-    const ViewInfo* __restrict__ views, int n_views, uint32_t n_tiles, const uint2* __restrict__ ranges,
-    const uint32_t* __restrict__ pair_vals, const float4* __restrict__ rec0,
-    const float4* __restrict__ rec1, const void* __restrict__ targets, int C, int c_off,
-    int per_view, BlendParams bp, float* __restrict__ VS,
-    unsigned long long* __restrict__ counter, uint32_t* __restrict__ gcount) {
-    const uint32_t lane = threadIdx.x & 63;
-    const uint32_t tile = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (tile >= n_tiles) return;  // whole wave
+__device__ __forceinline__ uint32_t accumulate_tile(
+    uint32_t tile, uint32_t lane, const ViewInfo* __restrict__ views, int n_views,
+    const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_vals,
+    const float4* __restrict__ rec0, const float4* __restrict__ rec1,
+    const void* __restrict__ targets, int C, int c_off, int per_view, const BlendParams& bp,
+    float* __restrict__ VS, uint32_t* __restrict__ gcount) {
     const int vloc = find_view(views, n_views, tile);
     const ViewInfo& V = views[vloc];
     const uint32_t local = tile - V.tile_base;
@@ -146,7 +147,39 @@ __global__ __launch_bounds__(256) void k_accumulate(
             }
         }
     }
-    if (first_chunk) {
+    return cnt;
+}
+
+// CC: channels handled by this launch (chunk [c_off, c_off + CC) of C).
+// queue == nullptr: one tile per wave (4 per block) over a grid covering all
+// tiles.  Otherwise persistent: a fixed grid whose waves take tiles from the
+// counter *queue (zero before the launch) until none are left.
+template <int CC, bool BF16>
+__global__ __launch_bounds__(256) void k_accumulate(
+    const ViewInfo* __restrict__ views, int n_views, uint32_t n_tiles, const uint2* __restrict__ ranges,
+    const uint32_t* __restrict__ pair_vals, const float4* __restrict__ rec0,
+    const float4* __restrict__ rec1, const void* __restrict__ targets, int C, int c_off,
+    int per_view, BlendParams bp, float* __restrict__ VS,
+    unsigned long long* __restrict__ counter, uint32_t* __restrict__ gcount,
+    uint32_t* __restrict__ queue) {
+    const uint32_t lane = threadIdx.x & 63;
+    uint32_t cnt = 0;
+    if (queue == nullptr) {
+        const uint32_t tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+        if (tile >= n_tiles) return;  // whole wave
+        cnt = accumulate_tile<CC, BF16>(tile, lane, views, n_views, ranges, pair_vals, rec0, rec1,
+                                        targets, C, c_off, per_view, bp, VS, gcount);
+    } else {
+        for (;;) {
+            uint32_t t = 0;
+            if (lane == 0) t = atomicAdd(queue, 1u);
+            const uint32_t tile = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
+            if (tile >= n_tiles) break;  // uniform: every wave ends here
+            cnt += accumulate_tile<CC, BF16>(tile, lane, views, n_views, ranges, pair_vals, rec0,
+                                             rec1, targets, C, c_off, per_view, bp, VS, gcount);
+        }
+    }
+    if (c_off == 0) {
         const uint32_t tot = wave_sum_u32(cnt);
         if (lane == 0 && tot) atomicAdd(counter, (unsigned long long)tot);
     }
@@ -156,17 +189,21 @@ template <int CC>
 static void launch_acc_cc(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
                           const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
                           const void* targets, int tdtype, int C, bool per_view, BlendParams bp,
-                          float* VS, unsigned long long* counter, uint32_t* gcount, hipStream_t s) {
-    dim3 grid((n_tiles + 3) / 4), block(256);
-    for (int c_off = 0; c_off < C; c_off += CC) {
+                          float* VS, unsigned long long* counter, uint32_t* gcount,
+                          uint32_t* queues, hipStream_t s) {
+    const uint32_t full = (n_tiles + 3) / 4;
+    dim3 grid(queues ? std::min(full, kPersistentBlocks) : full), block(256);
+    int pass = 0;
+    for (int c_off = 0; c_off < C; c_off += CC, ++pass) {
+        uint32_t* q = queues ? queues + pass : nullptr;
         if (tdtype == GSC_BF16)
             hipLaunchKernelGGL((k_accumulate<CC, true>), grid, block, 0, s, views, n_views, n_tiles,
                                ranges, pair_vals, rec0, rec1, targets, C, c_off, (int)per_view, bp,
-                               VS, counter, gcount);
+                               VS, counter, gcount, q);
         else
             hipLaunchKernelGGL((k_accumulate<CC, false>), grid, block, 0, s, views, n_views, n_tiles,
                                ranges, pair_vals, rec0, rec1, targets, C, c_off, (int)per_view, bp,
-                               VS, counter, gcount);
+                               VS, counter, gcount, q);
     }
 }
 
@@ -189,12 +226,13 @@ void launch_accumulate_chunked(const ViewInfo* views, int n_views, uint32_t n_ti
                                const float4* rec1, const void* targets, int tdtype, int C,
                                bool per_view, BlendParams bp, float* VS,
                                unsigned long long* counter, uint32_t* gcount, int chunk,
-                               hipStream_t s) {
+                               hipStream_t s, uint32_t* queues) {
     if (n_tiles == 0) return;
     if (!accumulate_chunk_valid(chunk)) chunk = accumulate_chunk(C);
+    if (queues) launch_fill_u32(queues, 0u, (uint64_t)((C + chunk - 1) / chunk), s);
 #define GSC_ACC(CCV)                                                                              \
     launch_acc_cc<CCV>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, targets, tdtype, C, \
-                       per_view, bp, VS, counter, gcount, s)
+                       per_view, bp, VS, counter, gcount, queues, s)
     switch (chunk) {
         case 1: GSC_ACC(1); break;
         case 2: GSC_ACC(2); break;
@@ -213,7 +251,7 @@ void launch_accumulate_weights(const ViewInfo* views, int n_views, uint32_t n_ti
     if (n_tiles == 0) return;
     hipLaunchKernelGGL((k_accumulate<0, false>), dim3((n_tiles + 3) / 4), dim3(256), 0, s, views,
                        n_views, n_tiles, ranges, pair_vals, rec0, rec1, (const void*)nullptr, 0, 0,
-                       (int)per_view, bp, V, counter, (uint32_t*)nullptr);
+                       (int)per_view, bp, V, counter, (uint32_t*)nullptr, (uint32_t*)nullptr);
 }
 
 // ---- render ----------------------------------------------------------------

@@ -68,8 +68,8 @@ class GscPlanInfo(ct.Structure):
     _fields_ = [("contributions", ct.c_uint64), ("items", ct.c_uint64),
                 ("pair_capacity", ct.c_uint64), ("dropped_pairs", ct.c_uint32),
                 ("ill_conditioned", ct.c_uint32), ("batches", ct.c_uint32), ("views", ct.c_uint32),
-                ("accumulate_chunk", ct.c_int32), ("tuned_chunk", ct.c_int32 * 4),
-                ("tuned_ms", ct.c_float * 4)]
+                ("accumulate_variant", ct.c_int32), ("tuned_variant", ct.c_int32 * 8),
+                ("tuned_ms", ct.c_float * 8)]
 
 
 class GscError(RuntimeError):

@@ -163,11 +163,13 @@ def test_batched_autotune(ctx, gsc_mod):
     ref_c = ref_c.clone()
     c, _ = plan.autotune(y, lam)
     info = plan.info()
-    cands = [info.tuned_chunk[i] for i in range(4) if info.tuned_chunk[i]]
+    cands = [info.tuned_variant[i] for i in range(8) if info.tuned_variant[i]]
     times = [info.tuned_ms[i] for i in range(len(cands))]
-    print(f"autotune: candidates {cands} ms {['%.3f' % t for t in times]} -> chunk {info.accumulate_chunk}",
+    names = [f"{v & 255}ch{'/persistent' if v >> 8 else ''}" for v in cands]
+    print(f"autotune: {dict(zip(names, ['%.3f' % t for t in times]))} -> {info.accumulate_variant}",
           flush=True)
-    assert len(cands) >= 2 and info.accumulate_chunk in cands
+    assert len(cands) >= 4 and info.accumulate_variant in cands
+    assert any(v >> 8 for v in cands)  # persistent shapes were timed
     assert all(t > 0 for t in times)
     e, _ = parity.rel_errors(c.cpu().numpy(), dict(coeffs=ref_c.cpu().numpy().astype(np.float64),
                                                    status=np.zeros(len(c), np.uint8)))
