@@ -1,18 +1,30 @@
 #!/usr/bin/env python3
-"""Throughput of one colorization pass (Algorithm 1, steps 1-6) on MI355X.
+"""Throughput of colorization (Algorithm 1, steps 1-6) on MI355X.
 
-Workload: the view-dependent relighting scene -- 100k anisotropic Gaussians
-(20 blobs, log-scales N(-4, 0.5), random rotations, opacity Beta(2,2)),
-50 hemisphere cameras at 512x512, SH degree 3, C = 3 FP32 channels, per-band
-Lambda (1e-5, 1e-4, 1e-3, 1e-2).  Targets are the render of random
-ground-truth SH coefficients plus N(0, 0.01^2) noise, resident in HBM before
-timing.  One step = one gsc_colorize call (project, depth sort, binning, tile
-sort, fused blend + accumulate, FP64 fold + Cholesky solve).
+Default workload (`--workload relight`): the view-dependent relighting scene
+-- 100k anisotropic Gaussians (20 blobs, log-scales N(-4, 0.5), random
+rotations, opacity Beta(2,2)), 50 hemisphere cameras at 512x512, SH degree 3,
+C = 3 FP32 channels, per-band Lambda (1e-5, 1e-4, 1e-3, 1e-2).  Targets are
+the render of random ground-truth SH coefficients plus N(0, 0.01^2) noise,
+resident in HBM before timing.  One step = one gsc_colorize call (project,
+depth sort, binning, tile sort, fused blend + accumulate, FP64 fold +
+Cholesky solve).
 
-Prints one JSON line.  `value` is accepted Gaussian-pixel contributions per
-second; `roofline` rates the dominant kernel (fused blend + accumulate) by its
-algorithmic FP32 work against the MI355X vector peak, timed with HIP events on
-the stream it runs on; `cpu_baseline` times the FP64 oracle on the host.
+Other workloads (one JSON line each, same fields):
+  features  500k isotropic Gaussians, 100 cameras 960x540, L=0, C=64 BF16
+            feature targets (feature distillation).
+  batched   32 segmentation scenes of uneven size (5k-400k Gaussians, 20-200
+            cameras, 640x480 .. 1280x720), L=0, C=16 BF16 one-hot labels, as
+            one plan captured into a graph; a step is one graph replay.
+  diff      300k anisotropic Gaussians, 100 cameras 800x800, L=3, C=3: a step
+            is colorize + render of the loss mean((render(colorize(y1)) - y2)^2)
+            and its backward through both adjoints (targets and opacities).
+
+`value` is accepted Gaussian-pixel contributions per second of the colorize
+pass(es) in a step; `roofline` rates the dominant kernel (fused blend +
+accumulate) by its algorithmic FP32 work against the MI355X vector peak,
+timed with HIP events on the stream it runs on; `cpu_baseline` times the FP64
+oracle on the host on a bounded sample of the same workload.
 """
 import argparse
 import json
@@ -26,6 +38,7 @@ if ROOT not in sys.path:
 
 PEAK_FP32_VECTOR = 157.3e12  # MI355X FP32 vector FLOP/s
 PEAK_HBM = 8.0e12            # MI355X HBM3E bytes/s
+METRIC = "Gaussian-pixel contributions/sec (accumulate+solve)"
 
 
 def algorithmic_flops_per_contribution(C: int) -> float:
@@ -34,68 +47,68 @@ def algorithmic_flops_per_contribution(C: int) -> float:
     return 12.0 + 1.0 + 2.0 * (C + 1)
 
 
-def cpu_baseline(sc, threads: int):
-    """Time the FP64 oracle (as it stands) on the same workload on the host."""
+def host_threads() -> int:
+    return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
+def cpu_baseline(sc, threads: int, what: str):
+    """Time the FP64 oracle (as it stands) on `sc` on the host."""
     import oracle
     y = oracle.make_targets(sc, threads=threads)
     t0 = time.perf_counter()
     r = oracle.colorize(sc, y, threads=threads)
     dt = time.perf_counter() - t0
     return {"value": r["count"] / dt, "unit": "contributions/s", "cores": threads, "kind": "oracle",
-            "sample": f"one full colorize of the benchmark workload ({sc.N} Gaussians, "
-                      f"{len(sc.cams)} views {sc.cams[0].width}x{sc.cams[0].height}, L={sc.sh_deg}, "
-                      f"C={sc.C}; {r['count']} contributions in {dt:.2f} s; oracle-rendered targets)"}
+            "sample": f"{what}: one colorize of {sc.N} Gaussians, {len(sc.cams)} views "
+                      f"{sc.cams[0].width}x{sc.cams[0].height}, L={sc.sh_deg}, C={sc.C}; "
+                      f"{r['count']} contributions in {dt:.2f} s (oracle-rendered targets)"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--n", type=int, default=100_000)
-    ap.add_argument("--views", type=int, default=50)
-    ap.add_argument("--res", type=int, default=512)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path shards by views "
-              "across GPUs as described in the design notes, but no multi-GPU run exists.",
-              file=sys.stderr)
-        sys.exit(2)
-
+def gpu_targets(gsc, sc, which=0, bf16=False):
+    """Targets on the device: GPU render of ground-truth set `which` plus the
+    seeded noise, cast to BF16 (round to nearest even) when asked."""
     import numpy as np
     import torch
-
-    import __graft_entry__
-    __graft_entry__._ensure_built()
-    from paper_2604_17155_amd import gsc, synthetic as syn
-
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        sys.exit(1)
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-
-    sc = syn.make_relight(n=args.n, n_cams=args.views, res=args.res)
+    from paper_2604_17155_amd import synthetic as syn
     m, s, q, o = gsc.scene_tensors(sc)
-    # targets: GPU render of the ground-truth coefficients + seeded noise
     rctx = gsc.Context()
-    gt = torch.from_numpy(sc.gt[0].astype(np.float32)).to(dev)
+    gt = torch.from_numpy(sc.gt[which].astype(np.float32)).cuda()
     img = rctx.render(m, s, q, o, sc.cams, gt)
-    targets = (img + torch.from_numpy(syn.target_noise(sc)).to(dev)).contiguous()
-    del img, gt
-    lam = list(sc.lam)
+    if sc.noise_std:
+        img += torch.from_numpy(syn.target_noise(sc, which)).cuda()
+    return img.to(torch.bfloat16).contiguous() if bf16 else img.contiguous()
 
+
+def roofline(C, contrib, blend_ms_total, launches):
+    flops = algorithmic_flops_per_contribution(C) * contrib
+    achieved = flops / (blend_ms_total * 1e-3)
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
+            "kernel": "k_accumulate", "kernel_ms": blend_ms_total / max(1, launches),
+            "launches_per_step": launches,
+            "flop_per_contribution": algorithmic_flops_per_contribution(C)}
+
+
+def line(args, value, ms_per_step, dtype, config, roof):
+    return {"metric": METRIC, "value": value, "unit": "contributions/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": config, "roofline": roof}
+
+
+def run_single(args, gsc, sc, targets, label, dtype):
+    """Time `steps` gsc_colorize calls on one scene."""
+    import torch
+    m, s, q, o = gsc.scene_tensors(sc)
+    lam = list(sc.lam)
     ctx = gsc.Context(flags=gsc.GSC_FLAG_PROFILE)
     for _ in range(args.warmup):
         ctx.colorize(m, s, q, o, sc.cams, targets, sc.sh_deg, lam)
     torch.cuda.synchronize()
-    st0 = ctx.stats()  # drains warm-up timings
-    contrib = int(st0.contributions)
-
+    contrib = int(ctx.stats().contributions)  # also drains the warm-up timings
     stream = torch.cuda.current_stream()
-    coeffs = torch.empty((sc.N, sc.n_b, sc.C), dtype=torch.float32, device=dev)
-    status = torch.empty((sc.N,), dtype=torch.uint8, device=dev)
+    coeffs = torch.empty((sc.N, sc.n_b, sc.C), dtype=torch.float32, device="cuda")
+    status = torch.empty((sc.N,), dtype=torch.uint8, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -104,52 +117,185 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     st = ctx.stats()
-    assert int(st.contributions) == contrib or abs(int(st.contributions) - contrib) < 1e-6 * contrib
+    stages = {k: v / args.steps for k, v in st.stage_dict().items() if v}
+    launches = max(1, int(st.stage_launches[5]) // args.steps)
+    config = {"workload": label, "contributions_per_step": contrib,
+              "scenes_per_sec": args.steps / elapsed, "tile_pairs_per_step": int(st.pairs),
+              "stage_ms_per_step": stages}
+    return line(args, contrib * args.steps / elapsed, 1e3 * elapsed / args.steps, dtype, config,
+                roofline(sc.C, contrib, stages["blend"], launches))
 
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = contrib * args.steps / elapsed
-    stages = {k: v / args.steps for k, v in st.stage_dict().items()}
-    blend_launches = max(1, int(st.stage_launches[5]) // args.steps)
-    blend_ms = stages["blend"] / blend_launches
-    flops = algorithmic_flops_per_contribution(sc.C) * contrib / blend_launches
-    achieved = flops / (blend_ms * 1e-3)
-    out = {
-        "metric": "Gaussian-pixel contributions/sec (accumulate+solve)",
-        "value": value,
-        "unit": "contributions/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {
-            "workload": f"relighting: {sc.N} anisotropic Gaussians, {len(sc.cams)} hemisphere cameras "
-                        f"{args.res}x{args.res}, SH degree {sc.sh_deg}, C={sc.C}, FP32 targets",
-            "contributions_per_step": contrib,
-            "scenes_per_sec": args.steps / elapsed,
-            "tile_pairs_per_step": int(st.pairs),
-            "stage_ms_per_step": stages,
-        },
-        "roofline": {
-            "bound": "alu",
-            "achieved": achieved / 1e12,
-            "peak": PEAK_FP32_VECTOR / 1e12,
-            "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_VECTOR,
-            "traffic": None,
-            "kernel": "k_accumulate",
-            "kernel_ms": blend_ms,
-            "flop_per_contribution": algorithmic_flops_per_contribution(sc.C),
-        },
-    }
+
+def workload_relight(args, gsc):
+    from paper_2604_17155_amd import synthetic as syn
+    sc = syn.make_relight(n=args.n or 100_000, n_cams=args.views or 50, res=args.res or 512)
+    targets = gpu_targets(gsc, sc)
+    label = (f"relighting: {sc.N} anisotropic Gaussians, {len(sc.cams)} hemisphere cameras "
+             f"{sc.cams[0].width}x{sc.cams[0].height}, SH degree {sc.sh_deg}, C={sc.C}, FP32 targets")
+    out = run_single(args, gsc, sc, targets, label, "f32")
     if not args.no_cpu_baseline:
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        out["cpu_baseline"] = cpu_baseline(sc, threads)
-    print(json.dumps(out), flush=True)
+        out["cpu_baseline"] = cpu_baseline(sc, host_threads(), "the full benchmark workload")
+    return out
+
+
+def workload_features(args, gsc):
+    from paper_2604_17155_amd import synthetic as syn
+    sc = syn.make_features(n=args.n or 500_000, n_cams=args.views or 100)
+    targets = gpu_targets(gsc, sc, bf16=True)
+    label = (f"feature distillation: {sc.N} isotropic Gaussians, {len(sc.cams)} hemisphere cameras "
+             f"{sc.cams[0].width}x{sc.cams[0].height}, SH degree 0, C={sc.C}, BF16 targets")
+    out = run_single(args, gsc, sc, targets, label, "bf16")
+    if not args.no_cpu_baseline:
+        sub = syn.make_features(n=sc.N, n_cams=len(sc.cams))
+        sub.cams = sub.cams[:4]
+        out["cpu_baseline"] = cpu_baseline(sub, host_threads(), "first 4 views of the workload")
+    return out
+
+
+def workload_batched(args, gsc):
+    import numpy as np
+    import torch
+    from paper_2604_17155_amd import synthetic as syn
+    n_scenes = args.scenes
+    scenes = [syn.make_segment_scene(k) for k in range(n_scenes)]
+    table, cams = [], []
+    g0 = c0 = r0 = 0
+    for sc in scenes:
+        table.append((g0, sc.N, c0, len(sc.cams)))
+        g0, c0, r0 = g0 + sc.N, c0 + len(sc.cams), r0 + sc.n_pixels
+        cams += list(sc.cams)
+    C = scenes[0].C
+    targets = torch.empty((r0, C), dtype=torch.bfloat16, device="cuda")
+    r = 0
+    for sc in scenes:  # one scene at a time: its FP32 render is the only temporary
+        targets[r:r + sc.n_pixels] = gpu_targets(gsc, sc, bf16=True)
+        r += sc.n_pixels
+    cat = lambda f: torch.from_numpy(np.ascontiguousarray(np.concatenate([getattr(sc, f) for sc in scenes]))).cuda()
+    geo = [cat(f) for f in ("means", "scales", "quats", "opacities")]
+    ctx = gsc.Context()
+    plan = gsc.Plan(ctx, table, *geo, cams, C, 0)
+    lam = list(scenes[0].lam)
+    coeffs, status = plan.autotune(targets, lam)
+    info = plan.info()
+    contrib = int(info.contributions)
+    variant = int(info.accumulate_variant)
+    tuned = {f"{v & 255}ch{'/persistent' if v >> 8 else ''}": float(info.tuned_ms[i])
+             for i, v in enumerate(info.tuned_variant) if v}
+    acc_ms = [float(info.tuned_ms[i]) for i, v in enumerate(info.tuned_variant) if v == variant][0]
+    # capture one run and replay it
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(max(1, args.warmup)):
+            plan.run(targets, lam, coeffs, status)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.run(targets, lam, coeffs, status)
+    graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    info2 = plan.info()
+    assert int(info2.dropped_pairs) == 0
+    launches = (C + (variant & 255) - 1) // (variant & 255) * int(info.batches)
+    config = {"workload": f"multi-scene segmentation: {n_scenes} scenes, {g0} Gaussians in total "
+                          f"(5k-400k per scene), {c0} cameras 640x480..1280x720, SH degree 0, "
+                          f"C={C}, BF16 targets, one plan replayed as a graph",
+              "contributions_per_step": contrib, "scenes_per_sec": n_scenes * args.steps / elapsed,
+              "pixels": r0, "tile_pairs_per_step": int(info.pair_capacity),
+              "view_batches": int(info.batches), "autotune_accumulate_ms": tuned,
+              "accumulate_variant": variant}
+    out = line(args, contrib * args.steps / elapsed, 1e3 * elapsed / args.steps, "bf16", config,
+               roofline(C, contrib, acc_ms, launches))
+    if not args.no_cpu_baseline:
+        small = min(scenes, key=lambda sc: sc.N * len(sc.cams))
+        out["cpu_baseline"] = cpu_baseline(small, host_threads(), "the smallest scene of the batch")
+    return out
+
+
+def workload_diff(args, gsc):
+    import torch
+    from paper_2604_17155_amd import autograd as ag, synthetic as syn
+    sc = syn.make_diff(n=args.n or 300_000, n_cams=args.views or 100, res=args.res or 800)
+    y1 = gpu_targets(gsc, sc, 0)
+    y2 = gpu_targets(gsc, sc, 1)
+    m, s, q, o = gsc.scene_tensors(sc)
+    lam = list(sc.lam)
+    ctx = gsc.Context()
+    o_p = o.clone().requires_grad_(True)
+    y_p = y1.clone().requires_grad_(True)
+
+    def step():
+        c = ag.colorize(y_p, o_p, m, s, q, sc.cams, sc.sh_deg, lam, context=ctx)
+        img = ag.render(c, o_p, m, s, q, sc.cams, context=ctx)
+        loss = ((img - y2) ** 2).mean()
+        y_p.grad = None
+        o_p.grad = None
+        loss.backward()
+        return loss
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    c, _ = ctx.colorize(m, s, q, o, sc.cams, y1, sc.sh_deg, lam)
+    torch.cuda.synchronize()
+    contrib = int(ctx.stats().contributions)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    # kernel time of the forward accumulate, for the roofline
+    pctx = gsc.Context(flags=gsc.GSC_FLAG_PROFILE)
+    pctx.colorize(m, s, q, o, sc.cams, y1, sc.sh_deg, lam)
+    torch.cuda.synchronize()
+    st = pctx.stats()
+    config = {"workload": f"differentiable re-render loss: {sc.N} anisotropic Gaussians, {len(sc.cams)} "
+                          f"hemisphere cameras {sc.cams[0].width}x{sc.cams[0].height}, SH degree 3, C=3; "
+                          f"step = colorize + render + both adjoints (targets, opacities)",
+              "forward_contributions_per_step": contrib}
+    out = line(args, contrib * args.steps / elapsed, 1e3 * elapsed / args.steps, "f32", config,
+               roofline(sc.C, contrib, st.stage_dict()["blend"], max(1, int(st.stage_launches[5]))))
+    out["metric"] = "forward colorize contributions/sec over full forward+backward steps"
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="relight", choices=["relight", "features", "batched", "diff"])
+    ap.add_argument("--n", type=int, default=0, help="Gaussians (0: the workload's size)")
+    ap.add_argument("--views", type=int, default=0, help="cameras (0: the workload's count)")
+    ap.add_argument("--res", type=int, default=0, help="square resolution (0: the workload's)")
+    ap.add_argument("--scenes", type=int, default=32, help="scenes of the batched workload")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path shards by views "
+              "across GPUs as described in the design notes, but no multi-GPU run exists.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import __graft_entry__
+    __graft_entry__._ensure_built()
+    from paper_2604_17155_amd import gsc
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    fn = {"relight": workload_relight, "features": workload_features, "batched": workload_batched,
+          "diff": workload_diff}[args.workload]
+    print(json.dumps(fn(args, gsc)), flush=True)
 
 
 if __name__ == "__main__":

@@ -19,7 +19,12 @@ namespace gsc {
 
 // One tile, by one wave: blend its pixels front to back and add each
 // Gaussian's tile share of V and S (channels [c_off, c_off + CC) of C) to its
-// slot.  Returns this lane's accepted contributions.
+// slot.  Returns the wave's accepted contributions (uniform).
+//
+// A pixel that stopped (or lies outside the image) has T = 0.  Bands of four
+// pixel rows are skipped when the Gaussian's footprint misses them (bits of
+// the pair value) or when none of their pixels is live; the wave ends when no
+// band is live.
 template <int CC, bool BF16>
 __device__ __forceinline__ uint32_t accumulate_tile(
     uint32_t tile, uint32_t lane, const ViewInfo* __restrict__ views, int n_views,
@@ -27,7 +32,9 @@ __device__ __forceinline__ uint32_t accumulate_tile(
     const float4* __restrict__ rec0, const float4* __restrict__ rec1,
     const void* __restrict__ targets, int C, int c_off, int per_view, const BlendParams& bp,
     float* __restrict__ VS, uint32_t* __restrict__ gcount) {
-    const int vloc = find_view(views, n_views, tile);
+    constexpr int CCA = CC > 0 ? CC : 1;
+    tile = (uint32_t)__builtin_amdgcn_readfirstlane((int)tile);  // wave-uniform
+    const int vloc = __builtin_amdgcn_readfirstlane(find_view(views, n_views, tile));
     const ViewInfo& V = views[vloc];
     const uint32_t local = tile - V.tile_base;
     const int tx = (int)(local % (uint32_t)V.tiles_x), ty = (int)(local / (uint32_t)V.tiles_x);
@@ -37,32 +44,36 @@ __device__ __forceinline__ uint32_t accumulate_tile(
     const int stride = C + 1;
 
     float T[4];
-    bool live[4];
-    float y[4][CC > 0 ? CC : 1];
+    float y[4][CCA];
+    uint32_t alive = 0;  // bit k: band k has a live pixel (wave-uniform)
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        int iy = iy0 + 4 * k;
-        live[k] = ix < V.width && iy < V.height;
-        T[k] = 1.0f;
-        int64_t row = V.pixel_offset + (int64_t)iy * V.width + ix;
+        const int iy = iy0 + 4 * k;
+        const bool inside = ix < V.width && iy < V.height;
+        T[k] = inside ? 1.0f : 0.0f;
+        alive |= (__builtin_amdgcn_ballot_w64(inside) != 0 ? 1u : 0u) << k;
+        const int64_t row = V.pixel_offset + (int64_t)iy * V.width + ix;
 #pragma unroll
         for (int c = 0; c < CC; ++c)
-            y[k][c] = (live[k] && c_off + c < C) ? load_target<BF16>(targets, row * C + c_off + c) : 0.0f;
+            y[k][c] = (inside && c_off + c < C) ? load_target<BF16>(targets, row * C + c_off + c) : 0.0f;
     }
-    const uint2 rg = ranges[tile];
+    alive = (uint32_t)__builtin_amdgcn_readfirstlane((int)alive);
+    uint2 rg = ranges[tile];
+    rg.x = (uint32_t)__builtin_amdgcn_readfirstlane((int)rg.x);
+    rg.y = (uint32_t)__builtin_amdgcn_readfirstlane((int)rg.y);
     uint32_t cnt = 0;
-    bool wave_live = __ballot(live[0] || live[1] || live[2] || live[3]) != 0;
     // item = V.item_base + g (g local to the view's scene)
     const int64_t item_base = V.item_base;
     const int64_t slot_base = per_view ? V.vs_base : V.g_offset;
     const bool first_chunk = c_off == 0;
 
     const float qlim = (float)(kExp2Scale * (double)bp.cut2);  // q <= cut2  <=>  q2 >= qlim
+    const float amax = bp.alpha_max, amin = bp.alpha_min, tmin = bp.t_min;
     float pyk[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) pyk[k] = (float)(iy0 + 4 * k) + 0.5f;
 
-    for (uint32_t b = rg.x; b < rg.y && wave_live; b += 64) {
+    for (uint32_t b = rg.x; b < rg.y && alive != 0u; b += 64) {
         const uint32_t nb = min(64u, rg.y - b);
         const uint32_t pv = lane < nb ? pair_vals[b + lane] : 0u;
         // records are fetched with uniform addresses one entry ahead
@@ -76,50 +87,51 @@ __device__ __forceinline__ uint32_t accumulate_tile(
                 n0 = rec0[pn & kItemMask];
                 n1 = rec1[pn & kItemMask];
             }
-            const uint32_t bands = pc >> kItemBits;
+            const uint32_t bands = (pc >> kItemBits) & alive;
             const int64_t g = (int64_t)(pc & kItemMask) - item_base;
             const float dx = (px - c0.x) - c0.z;
             const float a0 = c1.x * dx * dx;
             const float b0 = c1.y * dx;
             float sv = 0.0f;
-            float ss[CC > 0 ? CC : 1];
+            float ss[CCA];
 #pragma unroll
-            for (int c = 0; c < CC; ++c) ss[c] = 0.0f;
-            uint32_t nh = 0;
+            for (int c = 0; c < CCA; ++c) ss[c] = 0.0f;
+            uint32_t nh = 0;    // contributions of this entry (wave total)
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                if (!((bands >> k) & 1u)) continue;  // uniform: footprint misses band k
+                if (!((bands >> k) & 1u)) continue;  // uniform
                 const float dy = (pyk[k] - c0.y) - c0.w;
                 const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
-                const float al = fminf(bp.alpha_max, c1.w * __builtin_amdgcn_exp2f(q2));
+                // min(alpha_max, o G) for o G >= 0
+                const float al = __builtin_amdgcn_fmed3f(c1.w * __builtin_amdgcn_exp2f(q2), 0.0f, amax);
                 const float test = fmaf(-T[k], al, T[k]);
-                const bool cand = live[k] && q2 >= qlim && al >= bp.alpha_min;
-                const bool stop = cand && test < bp.t_min;
-                const bool take = cand && !stop;
-                live[k] = live[k] && !stop;
+                const bool cand = q2 >= qlim && al >= amin && T[k] > 0.0f;
+                const bool keep = test >= tmin;  // else the pixel stops here
+                const bool take = cand && keep;
                 const float w = take ? al * T[k] : 0.0f;
-                T[k] = take ? test : T[k];
+                T[k] = cand ? (keep ? test : 0.0f) : T[k];
                 sv += w;
 #pragma unroll
                 for (int c = 0; c < CC; ++c) ss[c] = fmaf(w, y[k][c], ss[c]);
-                nh += take ? 1u : 0u;
+                nh += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(take));
+                if (__builtin_amdgcn_ballot_w64(T[k] > 0.0f) == 0) alive &= ~(1u << k);
             }
+            // keep the band mask and the count in scalar registers
+            alive = (uint32_t)__builtin_amdgcn_readfirstlane((int)alive);
+            nh = (uint32_t)__builtin_amdgcn_readfirstlane((int)nh);
             cnt += nh;
-            if (__ballot(nh != 0) != 0) {
-                if (gcount != nullptr && first_chunk) {
-                    const uint32_t tn = wave_sum_u32(nh);
-                    if (lane == 0) atomicAdd(gcount + V.g_offset + g, tn);
-                }
+            if (nh != 0u) {
+                if (gcount != nullptr && first_chunk && lane == 0) atomicAdd(gcount + V.g_offset + g, nh);
                 float* slot = VS + (slot_base + g) * (int64_t)stride;
                 if constexpr (CC == 0) {
                     const float tv = wave_sum(sv);
                     if (lane == 0) unsafeAtomicAdd(slot, tv);
                 } else if constexpr (CC <= 3) {
-                    const float t = wave_sum4_transposed(sv, CC > 0 ? ss[0] : 0.0f,
-                                                         CC > 1 ? ss[CC > 1 ? 1 : 0] : 0.0f,
-                                                         CC > 2 ? ss[CC > 2 ? 2 : 0] : 0.0f, lane);
+                    const float v1 = CC > 1 ? ss[CC > 1 ? 1 : 0] : 0.0f;
+                    const float v2 = CC > 2 ? ss[CC > 2 ? 2 : 0] : 0.0f;
+                    const float t = wave_sum4_transposed(sv, ss[0], v1, v2, lane);
                     if (lane < 4u) {
-                        const int idx = (int)(2u * (lane & 1u) + (lane >> 1));
+                        const int idx = transposed_index<4>(lane);
                         if (idx == 0) {
                             if (first_chunk) unsafeAtomicAdd(slot, t);
                         } else if (idx <= CC && c_off + idx - 1 < C) {
@@ -128,23 +140,15 @@ __device__ __forceinline__ uint32_t accumulate_tile(
                     }
                 } else {
                     const float tv = wave_sum(sv);
-                    float mine = tv;
-#pragma unroll
-                    for (int c = 0; c < CC; ++c) {
-                        const float ts = wave_sum(ss[c]);
-                        if (lane == (uint32_t)(c + 1)) mine = ts;
-                    }
-                    if (lane == 0) {
-                        if (first_chunk) unsafeAtomicAdd(slot, mine);
-                    } else if (lane <= (uint32_t)CC && c_off + (int)lane - 1 < C) {
-                        unsafeAtomicAdd(slot + c_off + lane, mine);
+                    const float t = wave_sum_transposed<CC>(ss, lane);
+                    if (lane == 0 && first_chunk) unsafeAtomicAdd(slot, tv);
+                    if (lane < (uint32_t)CC) {
+                        const int c = c_off + transposed_index<CC>(lane);
+                        if (c < C) unsafeAtomicAdd(slot + 1 + c, t);
                     }
                 }
             }
-            if (__ballot(live[0] || live[1] || live[2] || live[3]) == 0) {
-                wave_live = false;
-                break;
-            }
+            if (alive == 0u) break;
         }
     }
     return cnt;
@@ -179,10 +183,7 @@ __global__ __launch_bounds__(256) void k_accumulate(
                                              rec1, targets, C, c_off, per_view, bp, VS, gcount);
         }
     }
-    if (c_off == 0) {
-        const uint32_t tot = wave_sum_u32(cnt);
-        if (lane == 0 && tot) atomicAdd(counter, (unsigned long long)tot);
-    }
+    if (c_off == 0 && lane == 0 && cnt) atomicAdd(counter, (unsigned long long)cnt);
 }
 
 template <int CC>

@@ -10,34 +10,111 @@ __device__ __forceinline__ float dpp_mov(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
 }
 
-// Sum over the 64 lanes; the result is uniform.  All lanes must be active.
-__device__ __forceinline__ float wave_sum(float v) {
-    v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
-    v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
-    v += dpp_mov<0x141>(v);  // row_half_mirror
-    v += dpp_mov<0x140>(v);  // row_mirror: every lane holds its row's sum
-    float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
-    float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
-    float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
-    float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
-    return (r0 + r1) + (r2 + r3);
+// DPP controls (GFX9 encoding).
+constexpr int kQuadXor1 = 0xB1;   // quad_perm [1,0,3,2]
+constexpr int kQuadXor2 = 0x4E;   // quad_perm [2,3,0,1]
+constexpr int kRowShl4 = 0x104;   // lane L <- L + 4 within its row of 16
+constexpr int kRowShr4 = 0x114;   // lane L <- L - 4 within its row
+constexpr int kRowRor4 = 0x124;
+constexpr int kRowRor8 = 0x128;   // lane L <- L xor 8 within its row
+
+// x + (x from the lane 16 apart within each half-wave) and likewise 32 apart,
+// with the gfx950 lane-swap instructions (no LDS round trip).
+__device__ __forceinline__ float sum_xor16(float x) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float sum_xor32(float x) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-// Sums four per-lane values over the wave at once.  Quad exchanges split the
-// four values between lanes (lane bit 0 picks the pair, bit 1 the member),
-// rotations sum the four quads of a row, and two shuffles sum the rows.
-// On return lane L < 4 holds the total of value 2*(L&1) + (L>>1).
+// Sum over the 64 lanes; the result is uniform.  All lanes must be active.
+__device__ __forceinline__ float wave_sum(float v) {
+    v += dpp_mov<kQuadXor1>(v);
+    v += dpp_mov<kQuadXor2>(v);
+    v += dpp_mov<kRowRor4>(v);
+    v += dpp_mov<kRowRor8>(v);  // every lane holds its row's sum
+    v = sum_xor32(sum_xor16(v));
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+// Value of the partner at lane distance 2^S (every lane takes part in each
+// exchange: a lane-permuting read inside a divergent branch would see its
+// disabled partners as 0).
+template <int S>
+__device__ __forceinline__ float partner(float send, bool hi) {
+    if constexpr (S == 0) {
+        return dpp_mov<kQuadXor1>(send);
+    } else if constexpr (S == 1) {
+        return dpp_mov<kQuadXor2>(send);
+    } else if constexpr (S == 2) {
+        const float from_above = dpp_mov<kRowShl4>(send);  // lane L + 4
+        const float from_below = dpp_mov<kRowShr4>(send);  // lane L - 4
+        return hi ? from_below : from_above;
+    } else {
+        return dpp_mov<kRowRor8>(send);
+    }
+}
+
+// One halving step at lane distance 2^S over 2H values (indices fixed at
+// compile time, so the values stay in registers).
+template <int H, int S>
+__device__ __forceinline__ void halve(float* a, uint32_t lane) {
+    const bool hi = (lane >> S) & 1u;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        const float keep = hi ? a[i + H] : a[i];
+        const float send = hi ? a[i] : a[i + H];
+        a[i] = keep + partner<S>(send, hi);
+    }
+}
+
+// Sums NV per-lane values (NV = 4, 8 or 16) over the wave at once.  Each
+// exchange step at lane distance d = 1, 2, 4, 8 halves the values a lane
+// holds: the lane with bit d clear keeps the lower half and adds its
+// partner's lower half, the other keeps the upper half.  Once one value is
+// left, the remaining lane bits are summed without halving.  On return lane
+// L < NV holds the total of value bitrev(L) = sum_s bit_s(L) NV / 2^(s+1)
+// (e.g. NV = 4: 2*(L&1) + (L>>1)&1).  All lanes must be active.
+template <int NV>
+__device__ __forceinline__ float wave_sum_transposed(const float (&v)[NV], uint32_t lane) {
+    static_assert(NV == 4 || NV == 8 || NV == 16, "NV must be 4, 8 or 16");
+    float a[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) a[i] = v[i];
+    halve<NV / 2, 0>(a, lane);
+    halve<NV / 4, 1>(a, lane);
+    if constexpr (NV >= 8) halve<NV / 8, 2>(a, lane);
+    if constexpr (NV >= 16) halve<1, 3>(a, lane);
+    float y = a[0];
+    if constexpr (NV == 4) {
+        y += dpp_mov<kRowRor4>(y);
+        y += dpp_mov<kRowRor8>(y);
+    } else if constexpr (NV == 8) {
+        y += dpp_mov<kRowRor8>(y);
+    }
+    return sum_xor32(sum_xor16(y));
+}
+
+// Value index held by lane L < NV after wave_sum_transposed<NV>.
+template <int NV>
+__device__ __forceinline__ int transposed_index(uint32_t lane) {
+    int idx = 0, w = NV / 2;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        if (w == 0) break;
+        idx += ((lane >> s) & 1u) ? w : 0;
+        w /= 2;
+    }
+    return idx;
+}
+
+// Four values at once (NV = 4); lane L < 4 holds value 2*(L&1) + ((L>>1)&1).
 __device__ __forceinline__ float wave_sum4_transposed(float v0, float v1, float v2, float v3,
                                                       uint32_t lane) {
-    const bool b0 = lane & 1u, b1 = lane & 2u;
-    const float x0 = (b0 ? v2 : v0) + dpp_mov<0xB1>(b0 ? v0 : v2);
-    const float x1 = (b0 ? v3 : v1) + dpp_mov<0xB1>(b0 ? v1 : v3);
-    float y = (b1 ? x1 : x0) + dpp_mov<0x4E>(b1 ? x0 : x1);
-    y += dpp_mov<0x124>(y);  // row_ror:4
-    y += dpp_mov<0x128>(y);  // row_ror:8
-    y += __shfl_xor(y, 16, 64);
-    y += __shfl_xor(y, 32, 64);
-    return y;
+    const float v[4] = {v0, v1, v2, v3};
+    return wave_sum_transposed<4>(v, lane);
 }
 
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
