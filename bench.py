@@ -101,7 +101,7 @@ def run_single(args, gsc, sc, targets, label, dtype):
     import torch
     m, s, q, o = gsc.scene_tensors(sc)
     lam = list(sc.lam)
-    ctx = gsc.Context(flags=gsc.GSC_FLAG_PROFILE)
+    ctx = gsc.Context(flags=gsc.GSC_FLAG_PROFILE, bin_size=args.bin)
     for _ in range(args.warmup):
         ctx.colorize(m, s, q, o, sc.cams, targets, sc.sh_deg, lam)
     torch.cuda.synchronize()
@@ -172,7 +172,7 @@ def workload_batched(args, gsc):
         r += sc.n_pixels
     cat = lambda f: torch.from_numpy(np.ascontiguousarray(np.concatenate([getattr(sc, f) for sc in scenes]))).cuda()
     geo = [cat(f) for f in ("means", "scales", "quats", "opacities")]
-    ctx = gsc.Context()
+    ctx = gsc.Context(bin_size=args.bin)
     plan = gsc.Plan(ctx, table, *geo, cams, C, 0)
     lam = list(scenes[0].lam)
     coeffs, status = plan.autotune(targets, lam)
@@ -226,7 +226,7 @@ def workload_diff(args, gsc):
     y2 = gpu_targets(gsc, sc, 1)
     m, s, q, o = gsc.scene_tensors(sc)
     lam = list(sc.lam)
-    ctx = gsc.Context()
+    ctx = gsc.Context(bin_size=args.bin)
     o_p = o.clone().requires_grad_(True)
     y_p = y1.clone().requires_grad_(True)
 
@@ -251,7 +251,7 @@ def workload_diff(args, gsc):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     # kernel time of the forward accumulate, for the roofline
-    pctx = gsc.Context(flags=gsc.GSC_FLAG_PROFILE)
+    pctx = gsc.Context(flags=gsc.GSC_FLAG_PROFILE, bin_size=args.bin)
     pctx.colorize(m, s, q, o, sc.cams, y1, sc.sh_deg, lam)
     torch.cuda.synchronize()
     st = pctx.stats()
@@ -276,6 +276,7 @@ def main():
     ap.add_argument("--views", type=int, default=0, help="cameras (0: the workload's count)")
     ap.add_argument("--res", type=int, default=0, help="square resolution (0: the workload's)")
     ap.add_argument("--scenes", type=int, default=32, help="scenes of the batched workload")
+    ap.add_argument("--bin", type=int, default=0, help="screen bin size 16 or 32 (0: automatic)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path shards by views "

@@ -119,6 +119,9 @@ typedef struct {
     float znear;     /* 0.01 */
     float kappa_max; /* 1e6: threshold for the GSC_G_ILL_COND bit */
     int32_t flags;
+    int32_t bin_size; /* 0 (automatic), 16 or 32: pixels per side of the screen
+                         bins the Gaussians are sorted into; the result does not
+                         depend on it (the footprint test is per pixel) */
 } gsc_options;
 
 typedef struct {

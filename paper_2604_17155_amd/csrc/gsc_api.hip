@@ -77,8 +77,9 @@ constexpr uint64_t kMaxPairsPerBatch = 1ull << 31;
 
 struct gsc_ctx {
     gsc_options opt;
+    int bin = 16;  // bin size of the current call
     // device scratch
-    DevBuf views, views_all, cov, keys, vals, keys_alt, vals_alt, counts, counts_sorted, offsets, rec0, rec1,
+    DevBuf views, views_all, cov, keys, vals, keys_alt, vals_alt, counts, counts_sorted, offsets, rec0, rec1, rec2,
         sort_scratch, pkeys, pvals, pkeys_alt, pvals_alt, ranges, vs, gamma, bbar, misc;
     // host staging
     ViewInfo* h_views = nullptr;  // staging of one batch's table
@@ -95,7 +96,7 @@ struct gsc_ctx {
     std::vector<Mark> marks;
     ~gsc_ctx() {
         DevBuf* all[] = {&views, &views_all, &cov, &keys, &vals, &keys_alt, &vals_alt, &counts, &counts_sorted,
-                         &offsets, &rec0, &rec1, &sort_scratch, &pkeys, &pvals, &pkeys_alt,
+                         &offsets, &rec0, &rec1, &rec2, &sort_scratch, &pkeys, &pvals, &pkeys_alt,
                          &pvals_alt, &ranges, &vs, &gamma, &bbar, &misc};
         for (DevBuf* b : all) b->release();
         if (h_views) (void)hipHostFree(h_views);
@@ -143,6 +144,7 @@ struct StageTimer {
 // [16] u64 pair total (overflow check)
 namespace {
 constexpr size_t kMiscBytes = 64;
+constexpr int kDefaultBin = 16;
 // bin_views result asking the caller to retry with fewer views per batch
 constexpr gsc_status kSplit = (gsc_status)1;
 
@@ -154,8 +156,13 @@ gsc_status validate_options(const gsc_options* o) {
     if (!(o->dilation >= 0.0f)) return fail(GSC_ERR_INVALID_ARG, "dilation must be >= 0");
     if (!(o->znear > 0.0f)) return fail(GSC_ERR_INVALID_ARG, "znear must be > 0");
     if (!(o->kappa_max > 0.0f)) return fail(GSC_ERR_INVALID_ARG, "kappa_max must be > 0");
+    if (!(o->bin_size == 0 || o->bin_size == 16 || o->bin_size == 32))
+        return fail(GSC_ERR_INVALID_ARG, "bin_size must be 0, 16 or 32");
     return GSC_OK;
 }
+
+// Bin size for a call: the option, or the automatic choice.
+int resolve_bin(const gsc_options& o) { return o.bin_size ? o.bin_size : kDefaultBin; }
 
 gsc_status validate_geometry(const float* means, const float* scales, const float* quats,
                              const float* opac, int64_t N, const gsc_camera* cams, int32_t n_cams,
@@ -217,8 +224,9 @@ BlendParams blend_params(const gsc_options& o) {
     return bp;
 }
 
-// View j of a single scene of N Gaussians: per-view sums at slots j*N + g.
-ViewInfo make_view(const gsc_camera& c, int j, int64_t N) {
+// View j of a single scene of N Gaussians (per-view sums at slots j*N + g),
+// binned at `bin` pixels.
+ViewInfo make_view(const gsc_camera& c, int j, int64_t N, int bin) {
     ViewInfo v;
     memset(&v, 0, sizeof(v));
     memcpy(v.R, c.R, sizeof(v.R));
@@ -228,8 +236,8 @@ ViewInfo make_view(const gsc_camera& c, int j, int64_t N) {
         v.centre[i] = -((double)c.R[i] * c.t[0] + (double)c.R[3 + i] * c.t[1] + (double)c.R[6 + i] * c.t[2]);
     v.width = c.width;
     v.height = c.height;
-    v.tiles_x = (c.width + kTile - 1) / kTile;
-    v.tiles_y = (c.height + kTile - 1) / kTile;
+    v.tiles_x = (c.width + bin - 1) / bin;
+    v.tiles_y = (c.height + bin - 1) / bin;
     v.pixel_offset = c.pixel_offset;
     v.g_offset = 0;
     v.vs_base = (int64_t)j * N;
@@ -290,13 +298,14 @@ gsc_status bin_views(gsc_ctx* ctx, const std::vector<ViewInfo>& all, int v0, int
     GSC_HIP(ctx->offsets.ensure(4 * items + 4));
     GSC_HIP(ctx->rec0.ensure(16 * items + 16));
     GSC_HIP(ctx->rec1.ensure(16 * items + 16));
+    GSC_HIP(ctx->rec2.ensure(4 * items + 4));
     GSC_HIP(ctx->ranges.ensure(sizeof(uint2) * (tiles + 1)));
     const ViewInfo* dviews = ctx->views.as<ViewInfo>();
     {
         StageTimer t(ctx, s, GSC_STAGE_PROJECT);
         launch_project(dviews, nv, ni, means, ctx->cov.as<float>(), opac, bp, ctx->keys.as<uint32_t>(),
                        ctx->vals.as<uint32_t>(), ctx->counts.as<uint32_t>(), ctx->rec0.as<float4>(),
-                       ctx->rec1.as<float4>(), s);
+                       ctx->rec1.as<float4>(), ctx->rec2.as<uint32_t>(), ctx->bin, s);
         GSC_LAUNCHED("project");
     }
     size_t scr = std::max(radix_scratch_words(ni), scan_scratch_words(ni));
@@ -339,7 +348,7 @@ gsc_status bin_views(gsc_ctx* ctx, const std::vector<ViewInfo>& all, int v0, int
         launch_emit(dviews, nv, ctx->vals.as<uint32_t>(), ctx->offsets.as<uint32_t>(),
                     ctx->counts.as<uint32_t>(), ctx->rec0.as<float4>(),
                     ctx->rec1.as<float4>(), bp, ni, (uint32_t)tiles, ctx->pkeys.as<uint32_t>(),
-                    ctx->pvals.as<uint32_t>(), s);
+                    ctx->pvals.as<uint32_t>(), ctx->bin, s);
         GSC_LAUNCHED("emit");
     }
     size_t pscr = radix_scratch_words((uint32_t)pairs);
@@ -386,6 +395,7 @@ gsc_status for_view_batches(gsc_ctx* ctx, const std::vector<ViewInfo>& all, int 
 
 gsc_status ensure_common(gsc_ctx* ctx, const float* scales, const float* quats, int64_t N,
                          hipStream_t s) {
+    ctx->bin = resolve_bin(ctx->opt);
     GSC_HIP(ctx->misc.ensure(kMiscBytes));
     if (!ctx->h_total) GSC_HIP(hipHostMalloc((void**)&ctx->h_total, 64));
     GSC_HIP(ctx->cov.ensure(sizeof(float) * 6 * (size_t)std::max<int64_t>(N, 1)));
@@ -440,15 +450,16 @@ struct gsc_plan {
     uint64_t vs_slots = 0;
     uint32_t max_items = 0, max_pairs = 0, max_tiles = 0;
     uint64_t items_total = 0, pairs_total = 0;
+    int bin = 16;                     // bin size in pixels
     int acc_chunk = 0;                // channels per accumulate launch (0: default)
     bool acc_persistent = false;      // persistent work-queue accumulate
     float tune_ms[8] = {};
     int tune_variant[8] = {};
     DevBuf d_views, cov, keys, vals, keys_alt, vals_alt, counts, counts_sorted, offsets, rec0, rec1,
-        sort_scratch, pkeys, pvals, pkeys_alt, pvals_alt, ranges, vs, misc, queues;
+        rec2, sort_scratch, pkeys, pvals, pkeys_alt, pvals_alt, ranges, vs, misc, queues;
     ~gsc_plan() {
         DevBuf* all[] = {&d_views, &cov, &keys, &vals, &keys_alt, &vals_alt, &counts, &counts_sorted,
-                         &offsets, &rec0, &rec1, &sort_scratch, &pkeys, &pvals, &pkeys_alt,
+                         &offsets, &rec0, &rec1, &rec2, &sort_scratch, &pkeys, &pvals, &pkeys_alt,
                          &pvals_alt, &ranges, &vs, &misc, &queues};
         for (DevBuf* b : all) b->release();
     }
@@ -470,7 +481,7 @@ gsc_status plan_count_pairs(gsc_plan* P, const gsc_plan::Batch& b, hipStream_t s
     const ViewInfo* dv = P->d_views.as<ViewInfo>() + b.v0;
     launch_project(dv, b.nv, b.n_items, P->means, P->cov.as<float>(), P->opac, P->bp,
                    P->keys.as<uint32_t>(), P->vals.as<uint32_t>(), P->counts.as<uint32_t>(),
-                   P->rec0.as<float4>(), P->rec1.as<float4>(), s);
+                   P->rec0.as<float4>(), P->rec1.as<float4>(), P->rec2.as<uint32_t>(), P->bin, s);
     GSC_LAUNCHED("project");
     unsigned long long* d64 = reinterpret_cast<unsigned long long*>(P->misc.as<char>() + 24);
     launch_fill_u32(reinterpret_cast<uint32_t*>(d64), 0u, 2, s);
@@ -505,7 +516,8 @@ gsc_status plan_accumulate(gsc_plan* P, const gsc_plan::Batch& b, const void* ta
     const ViewInfo* dv = P->d_views.as<ViewInfo>() + b.v0;
     unsigned long long* d_counter = reinterpret_cast<unsigned long long*>(P->misc.p);
     launch_accumulate_chunked(dv, b.nv, b.n_tiles, P->ranges.as<uint2>(), P->pvals.as<uint32_t>(),
-                              P->rec0.as<float4>(), P->rec1.as<float4>(), targets, tdtype, P->C,
+                              P->rec0.as<float4>(), P->rec1.as<float4>(), P->rec2.as<uint32_t>(),
+                              P->bin, targets, tdtype, P->C,
                               P->per_view, P->bp, P->vs.as<float>(), d_counter, nullptr, chunk, s,
                               persistent ? P->queues.as<uint32_t>() : nullptr);
     GSC_LAUNCHED("accumulate");
@@ -522,7 +534,7 @@ gsc_status plan_bin_batch(gsc_plan* P, const gsc_plan::Batch& b, hipStream_t s) 
         StageTimer t(ctx, s, GSC_STAGE_PROJECT);
         launch_project(dv, b.nv, b.n_items, P->means, P->cov.as<float>(), P->opac, P->bp,
                        P->keys.as<uint32_t>(), P->vals.as<uint32_t>(), P->counts.as<uint32_t>(),
-                       P->rec0.as<float4>(), P->rec1.as<float4>(), s);
+                       P->rec0.as<float4>(), P->rec1.as<float4>(), P->rec2.as<uint32_t>(), P->bin, s);
         GSC_LAUNCHED("project");
     }
     {
@@ -543,7 +555,7 @@ gsc_status plan_bin_batch(gsc_plan* P, const gsc_plan::Batch& b, hipStream_t s) 
         StageTimer t(ctx, s, GSC_STAGE_EMIT);
         launch_emit(dv, b.nv, P->vals.as<uint32_t>(), P->offsets.as<uint32_t>(),
                     P->counts.as<uint32_t>(), P->rec0.as<float4>(), P->rec1.as<float4>(), P->bp,
-                    b.n_items, b.n_tiles, P->pkeys.as<uint32_t>(), P->pvals.as<uint32_t>(), s,
+                    b.n_items, b.n_tiles, P->pkeys.as<uint32_t>(), P->pvals.as<uint32_t>(), P->bin, s,
                     b.pair_cap, d_drop);
         GSC_LAUNCHED("emit");
     }
@@ -615,6 +627,7 @@ gsc_status gsc_default_options(gsc_options* out) {
     out->znear = 0.01f;
     out->kappa_max = 1e6f;
     out->flags = 0;
+    out->bin_size = 0;
     return GSC_OK;
 }
 
@@ -671,7 +684,7 @@ gsc_status gsc_colorize_ex(gsc_ctx* ctx, const float* means, const float* scales
     BlendParams bp = blend_params(ctx->opt);
     if ((st = ensure_common(ctx, scales, quats, N, s)) != GSC_OK) return st;
     std::vector<ViewInfo> all(n_cams);
-    for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j], j, N);
+    for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j], j, N, ctx->bin);
     const bool per_view = sh_deg > 0 || x_sums != nullptr;
     const uint64_t vs_words = (uint64_t)(per_view ? std::max(n_cams, 1) : 1) * (uint64_t)N * (uint64_t)(C + 1);
     GSC_HIP(ctx->vs.ensure(4 * vs_words));
@@ -683,7 +696,7 @@ gsc_status gsc_colorize_ex(gsc_ctx* ctx, const float* means, const float* scales
         StageTimer t(ctx, s, GSC_STAGE_BLEND, (uint32_t)((C + accumulate_chunk(C) - 1) / accumulate_chunk(C)));
         (void)v0;
         launch_accumulate(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
-                          ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(),
+                          ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(), ctx->rec2.as<uint32_t>(), ctx->bin,
                           targets, tdtype, C, per_view, bp, ctx->vs.as<float>(), d_counter,
                           x_cnt, s);
         GSC_LAUNCHED("accumulate");
@@ -736,7 +749,7 @@ gsc_status gsc_render(gsc_ctx* ctx, const float* means, const float* scales, con
     BlendParams bp = blend_params(ctx->opt);
     if ((st = ensure_common(ctx, scales, quats, N, s)) != GSC_OK) return st;
     std::vector<ViewInfo> all(n_cams);
-    for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j], j, N);
+    for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j], j, N, ctx->bin);
     unsigned long long* d_counter = reinterpret_cast<unsigned long long*>(ctx->misc.p);
     st = for_view_batches(ctx, all, n_cams, means, opacities, N, bp, s,
                           [&](int v0, int nv, const Binned& bn) -> gsc_status {
@@ -747,7 +760,7 @@ gsc_status gsc_render(gsc_ctx* ctx, const float* means, const float* scales, con
                            sh_deg, ctx->gamma.as<float>(), s);
         GSC_LAUNCHED("view colors");
         launch_render(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
-                      ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(),
+                      ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(), ctx->rec2.as<uint32_t>(), ctx->bin,
                       ctx->gamma.as<float>(), C, bp, images, d_counter, s);
         GSC_LAUNCHED("render");
         return GSC_OK;
@@ -784,7 +797,7 @@ gsc_status gsc_colorize_backward(gsc_ctx* ctx, const float* means, const float* 
     BlendParams bp = blend_params(ctx->opt);
     if ((st = ensure_common(ctx, scales, quats, N, s)) != GSC_OK) return st;
     std::vector<ViewInfo> all(n_cams);
-    for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j], j, N);
+    for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j], j, N, ctx->bin);
     // 1. visibilities V_gj (the normal matrices depend on the weights only)
     const bool per_view = sh_deg > 0;
     const uint64_t v_words = (uint64_t)(per_view ? n_cams : 1) * (uint64_t)N;
@@ -798,7 +811,7 @@ gsc_status gsc_colorize_backward(gsc_ctx* ctx, const float* means, const float* 
         (void)v0;
         launch_accumulate_weights(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
                                   ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(),
-                                  ctx->rec1.as<float4>(), per_view, bp, ctx->vs.as<float>(),
+                                  ctx->rec1.as<float4>(), ctx->rec2.as<uint32_t>(), ctx->bin, per_view, bp, ctx->vs.as<float>(),
                                   d_counter, s);
         GSC_LAUNCHED("accumulate weights");
         last = bn;
@@ -828,7 +841,7 @@ gsc_status gsc_colorize_backward(gsc_ctx* ctx, const float* means, const float* 
                             d_rho, C, sh_deg, false, ctx->gamma.as<float>(), s);
         GSC_LAUNCHED("view adjoint");
         launch_blend_adjoint(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
-                             ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(),
+                             ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(), ctx->rec2.as<uint32_t>(), ctx->bin,
                              targets, tdtype, C, ctx->gamma.as<float>(), bp, grad_targets,
                              grad_opacities, s);
         GSC_LAUNCHED("blend adjoint");
@@ -869,7 +882,7 @@ gsc_status gsc_render_backward(gsc_ctx* ctx, const float* means, const float* sc
     BlendParams bp = blend_params(ctx->opt);
     if ((st = ensure_common(ctx, scales, quats, N, s)) != GSC_OK) return st;
     std::vector<ViewInfo> all(n_cams);
-    for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j], j, N);
+    for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j], j, N, ctx->bin);
     const bool per_view = sh_deg > 0;
     const uint64_t vs_words = (uint64_t)(per_view ? n_cams : 1) * (uint64_t)N * (uint64_t)(C + 1);
     if (grad_coeffs) {
@@ -885,7 +898,7 @@ gsc_status gsc_render_backward(gsc_ctx* ctx, const float* means, const float* sc
             StageTimer t(ctx, s, GSC_STAGE_BLEND);
             (void)v0;
             launch_accumulate(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
-                              ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(),
+                              ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(), ctx->rec2.as<uint32_t>(), ctx->bin,
                               grad_images, GSC_F32, C, per_view, bp, ctx->vs.as<float>(),
                               d_counter, nullptr, s);
             GSC_LAUNCHED("accumulate");
@@ -898,7 +911,7 @@ gsc_status gsc_render_backward(gsc_ctx* ctx, const float* means, const float* sc
             GSC_LAUNCHED("view colours");
             launch_blend_adjoint(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
                                  ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(),
-                                 ctx->rec1.as<float4>(), grad_images, GSC_F32, C,
+                                 ctx->rec1.as<float4>(), ctx->rec2.as<uint32_t>(), ctx->bin, grad_images, GSC_F32, C,
                                  ctx->gamma.as<float>(), bp, nullptr, grad_opacities, s);
             GSC_LAUNCHED("blend adjoint");
         }
@@ -953,6 +966,7 @@ gsc_status gsc_plan_create(gsc_ctx* ctx, const gsc_scene* scenes, int32_t n_scen
     hipStream_t s = (hipStream_t)stream;
     P->ctx = ctx;
     P->bp = blend_params(ctx->opt);
+    P->bin = resolve_bin(ctx->opt);
     P->scenes.assign(scenes, scenes + n_scenes);
     P->means = means; P->scales = scales; P->quats = quats; P->opac = opacities;
     P->n_total = n_total;
@@ -968,7 +982,7 @@ gsc_status gsc_plan_create(gsc_ctx* ctx, const gsc_scene* scenes, int32_t n_scen
         const int nv = sc.n_gaussians > 0 ? sc.n_cameras : 0;
         P->scene_nviews.push_back(nv);
         for (int j = 0; j < nv; ++j) {
-            ViewInfo v = make_view(cams[sc.camera_offset + j], 0, 0);
+            ViewInfo v = make_view(cams[sc.camera_offset + j], 0, 0, P->bin);
             v.g_offset = sc.gaussian_offset;
             v.n_gauss = (uint32_t)sc.n_gaussians;
             v.scene = (uint32_t)k;
@@ -1008,6 +1022,7 @@ gsc_status gsc_plan_create(gsc_ctx* ctx, const gsc_scene* scenes, int32_t n_scen
     GSC_HIP(P->offsets.ensure(4 * mi + 4));
     GSC_HIP(P->rec0.ensure(16 * mi + 16));
     GSC_HIP(P->rec1.ensure(16 * mi + 16));
+    GSC_HIP(P->rec2.ensure(4 * mi + 4));
     GSC_HIP(P->d_views.ensure(sizeof(ViewInfo) * std::max<size_t>(P->views.size(), 1)));
     if (!P->views.empty())
         GSC_HIP(hipMemcpyAsync(P->d_views.p, P->views.data(), sizeof(ViewInfo) * P->views.size(),

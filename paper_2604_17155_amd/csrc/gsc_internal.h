@@ -10,6 +10,9 @@ namespace gsc {
 
 constexpr int kTile = 16;           // tile edge in pixels (16x16 = one wave, 4 pixels per lane)
 constexpr int kTileShift = 4;
+// Binning granularity: 16 (a bin is one tile) or 32 (a bin is 2x2 tiles).
+constexpr int kMinBin = 16;
+constexpr int kMaxBin = 32;
 constexpr int kMaxNb = 16;          // (L+1)^2 for L <= 3
 constexpr int kMaxC = 64;
 
@@ -23,8 +26,8 @@ struct ViewInfo {
     float fx, fy, cx, cy;
     double centre[3];      // camera centre -R^T t, for the SH view direction
     int32_t width, height;
-    int32_t tiles_x, tiles_y;
-    uint32_t tile_base;    // first global tile id of this view within its batch
+    int32_t tiles_x, tiles_y;  // bins per row and column
+    uint32_t tile_base;    // first global bin id of this view within its batch
     uint32_t item_base;    // first item of this view within its batch
     int64_t pixel_offset;  // first target row
     int64_t g_offset;      // first Gaussian of the view's scene
@@ -56,8 +59,11 @@ struct BlendParams {
 //        q2 = K*q = r1.x dx^2 + r1.y dx dy + r1.z dy^2 and exp(-q/2) = exp2(q2).
 constexpr double kExp2Scale = -0.72134752044448170368;  // -0.5 * log2(e)
 
-// Tile pairs carry the item index in the low 26 bits and, in the top 4 bits,
-// which 16x4 pixel bands (rows 4k..4k+3 of the tile) the footprint reaches.
+// Bin pairs carry the item index in the low 26 bits and a 4-bit mask above:
+// 16-pixel bins: which 16x4 pixel bands (rows 4k..4k+3 of the tile) the
+// footprint reaches; 32-pixel bins: which of the bin's four 16x16 tiles
+// (bit 2 * row half + column half).  The tile kernels run one wave per
+// 16x16 tile: (bin / 16)^2 waves per bin.
 constexpr uint32_t kItemBits = 26;
 constexpr uint32_t kItemMask = (1u << kItemBits) - 1u;
 
@@ -65,9 +71,11 @@ constexpr uint32_t kItemMask = (1u << kItemBits) - 1u;
 void launch_cov3d(const float* scales, const float* quats, float* cov, int64_t N, hipStream_t s);
 
 // One thread per batch item (n_items = sum of n_gauss over the batch's views).
+// rec2[i]: first | last << 16, the pixel rows of the item's footprint.
 void launch_project(const ViewInfo* views, int n_views, uint32_t n_items, const float* means,
                     const float* cov, const float* opac, BlendParams bp, uint32_t* keys,
-                    uint32_t* vals, uint32_t* counts, float4* rec0, float4* rec1, hipStream_t s);
+                    uint32_t* vals, uint32_t* counts, float4* rec0, float4* rec1, uint32_t* rec2,
+                    int bin, hipStream_t s);
 
 void launch_gather_counts(const uint32_t* sorted_vals, const uint32_t* counts, uint32_t* out,
                           uint32_t n, hipStream_t s);
@@ -76,7 +84,7 @@ void launch_gather_counts(const uint32_t* sorted_vals, const uint32_t* counts, u
 void launch_emit(const ViewInfo* views, int n_views, const uint32_t* sorted_vals,
                  const uint32_t* offsets, const uint32_t* counts, const float4* rec0,
                  const float4* rec1, BlendParams bp, uint32_t n_items, uint32_t n_tiles,
-                 uint32_t* pair_keys, uint32_t* pair_vals, hipStream_t s,
+                 uint32_t* pair_keys, uint32_t* pair_vals, int bin, hipStream_t s,
                  uint32_t cap = 0xFFFFFFFFu, uint32_t* overflow = nullptr);
 
 // Sum of n uint32 counts into *out (u64, must be zeroed).
@@ -110,7 +118,7 @@ int accumulate_chunk(int C);
 // Accumulate V_gj and S_gj into slot (view.vs_base + g) when per_view, else
 // into slot (view.g_offset + g), summed over views; slots hold C+1 floats.
 void launch_accumulate(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
-                       const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
+                       const uint32_t* pair_vals, const float4* rec0, const float4* rec1, const uint32_t* rec2, int bin,
                        const void* targets, int tdtype, int C, bool per_view, BlendParams bp,
                        float* VS, unsigned long long* counter, uint32_t* gcount, hipStream_t s);
 
@@ -123,7 +131,7 @@ constexpr uint32_t kPersistentBlocks = 2048;  // 8 blocks of 4 waves per CU
 bool accumulate_chunk_valid(int chunk);
 void launch_accumulate_chunked(const ViewInfo* views, int n_views, uint32_t n_tiles,
                                const uint2* ranges, const uint32_t* pair_vals, const float4* rec0,
-                               const float4* rec1, const void* targets, int tdtype, int C,
+                               const float4* rec1, const uint32_t* rec2, int bin, const void* targets, int tdtype, int C,
                                bool per_view, BlendParams bp, float* VS,
                                unsigned long long* counter, uint32_t* gcount, int chunk,
                                hipStream_t s, uint32_t* queues = nullptr);
@@ -133,7 +141,7 @@ void launch_view_colors(const ViewInfo* views, int n_views, uint32_t n_items, co
                         const float* coeffs, int C, int sh_deg, float* gamma, hipStream_t s);
 
 void launch_render(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
-                   const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
+                   const uint32_t* pair_vals, const float4* rec0, const float4* rec1, const uint32_t* rec2, int bin,
                    const float* gamma, int C, BlendParams bp, float* images,
                    unsigned long long* counter, hipStream_t s);
 
@@ -149,7 +157,7 @@ void launch_fold_solve(const ViewInfo* views, int n_views, const float* means, c
 // Weights-only accumulate: V[slot] += sum_p w (stride 1; slots as in launch_accumulate).
 void launch_accumulate_weights(const ViewInfo* views, int n_views, uint32_t n_tiles,
                                const uint2* ranges, const uint32_t* pair_vals, const float4* rec0,
-                               const float4* rec1, bool per_view, BlendParams bp, float* V,
+                               const float4* rec1, const uint32_t* rec2, int bin, bool per_view, BlendParams bp, float* V,
                                unsigned long long* counter, hipStream_t s);
 
 // Adjoint solve: bbar = (A_g + w_g Lambda)^{-1} grad_coeffs and
@@ -171,7 +179,7 @@ void launch_view_adjoint(const ViewInfo* views, int n_views, uint32_t n_items, c
 // Blend adjoint over the binned tiles: grad_y[row][c] = sum_g w beta (every
 // pixel of every view written, if grad_y) and grad_o[g] += dL/do (atomics, if grad_o).
 void launch_blend_adjoint(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
-                          const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
+                          const uint32_t* pair_vals, const float4* rec0, const float4* rec1, const uint32_t* rec2, int bin,
                           const void* ypix, int ydtype, int C, const float* beta, BlendParams bp,
                           float* grad_y, float* grad_o, hipStream_t s);
 

@@ -25,21 +25,18 @@ namespace gsc {
 // pixel rows are skipped when the Gaussian's footprint misses them (bits of
 // the pair value) or when none of their pixels is live; the wave ends when no
 // band is live.
-template <int CC, bool BF16>
+template <int CC, bool BF16, int BIN>
 __device__ __forceinline__ uint32_t accumulate_tile(
     uint32_t tile, uint32_t lane, const ViewInfo* __restrict__ views, int n_views,
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_vals,
     const float4* __restrict__ rec0, const float4* __restrict__ rec1,
-    const void* __restrict__ targets, int C, int c_off, int per_view, const BlendParams& bp,
-    float* __restrict__ VS, uint32_t* __restrict__ gcount) {
+    const uint32_t* __restrict__ rec2, const void* __restrict__ targets, int C, int c_off,
+    int per_view, const BlendParams& bp, float* __restrict__ VS, uint32_t* __restrict__ gcount) {
     constexpr int CCA = CC > 0 ? CC : 1;
-    tile = (uint32_t)__builtin_amdgcn_readfirstlane((int)tile);  // wave-uniform
-    const int vloc = __builtin_amdgcn_readfirstlane(find_view(views, n_views, tile));
-    const ViewInfo& V = views[vloc];
-    const uint32_t local = tile - V.tile_base;
-    const int tx = (int)(local % (uint32_t)V.tiles_x), ty = (int)(local / (uint32_t)V.tiles_x);
-    const int ix = tx * kTile + (int)(lane & 15);
-    const int iy0 = ty * kTile + (int)(lane >> 4);
+    const TileGeom tg = tile_geom<BIN>(tile, views, n_views);
+    const ViewInfo& V = views[tg.vloc];
+    const int ix = tg.x0 + (int)(lane & 15);
+    const int iy0 = tg.y0 + (int)(lane >> 4);
     const float px = (float)ix + 0.5f;
     const int stride = C + 1;
 
@@ -58,7 +55,7 @@ __device__ __forceinline__ uint32_t accumulate_tile(
             y[k][c] = (inside && c_off + c < C) ? load_target<BF16>(targets, row * C + c_off + c) : 0.0f;
     }
     alive = (uint32_t)__builtin_amdgcn_readfirstlane((int)alive);
-    uint2 rg = ranges[tile];
+    uint2 rg = ranges[tg.bin];
     rg.x = (uint32_t)__builtin_amdgcn_readfirstlane((int)rg.x);
     rg.y = (uint32_t)__builtin_amdgcn_readfirstlane((int)rg.y);
     uint32_t cnt = 0;
@@ -79,15 +76,19 @@ __device__ __forceinline__ uint32_t accumulate_tile(
         // records are fetched with uniform addresses one entry ahead
         uint32_t pn = bcast_u(pv, 0);
         float4 n0 = rec0[pn & kItemMask], n1 = rec1[pn & kItemMask];
+        uint32_t n2 = BIN == 32 ? rec2[pn & kItemMask] : 0u;
         for (uint32_t j = 0; j < nb; ++j) {
             const uint32_t pc = pn;
             const float4 c0 = n0, c1 = n1;
+            const uint32_t e2 = n2;
             if (j + 1 < nb) {
                 pn = bcast_u(pv, j + 1);
                 n0 = rec0[pn & kItemMask];
                 n1 = rec1[pn & kItemMask];
+                if constexpr (BIN == 32) n2 = rec2[pn & kItemMask];
             }
-            const uint32_t bands = (pc >> kItemBits) & alive;
+            const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2, tg.y0) & alive;
+            if (bands == 0u) continue;
             const int64_t g = (int64_t)(pc & kItemMask) - item_base;
             const float dx = (px - c0.x) - c0.z;
             const float a0 = c1.x * dx * dx;
@@ -158,11 +159,12 @@ __device__ __forceinline__ uint32_t accumulate_tile(
 // queue == nullptr: one tile per wave (4 per block) over a grid covering all
 // tiles.  Otherwise persistent: a fixed grid whose waves take tiles from the
 // counter *queue (zero before the launch) until none are left.
-template <int CC, bool BF16>
+template <int CC, bool BF16, int BIN>
 __global__ __launch_bounds__(256) void k_accumulate(
     const ViewInfo* __restrict__ views, int n_views, uint32_t n_tiles, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ pair_vals, const float4* __restrict__ rec0,
-    const float4* __restrict__ rec1, const void* __restrict__ targets, int C, int c_off,
+    const float4* __restrict__ rec1, const uint32_t* __restrict__ rec2,
+    const void* __restrict__ targets, int C, int c_off,
     int per_view, BlendParams bp, float* __restrict__ VS,
     unsigned long long* __restrict__ counter, uint32_t* __restrict__ gcount,
     uint32_t* __restrict__ queue) {
@@ -171,41 +173,60 @@ __global__ __launch_bounds__(256) void k_accumulate(
     if (queue == nullptr) {
         const uint32_t tile = blockIdx.x * 4 + (threadIdx.x >> 6);
         if (tile >= n_tiles) return;  // whole wave
-        cnt = accumulate_tile<CC, BF16>(tile, lane, views, n_views, ranges, pair_vals, rec0, rec1,
-                                        targets, C, c_off, per_view, bp, VS, gcount);
+        cnt = accumulate_tile<CC, BF16, BIN>(tile, lane, views, n_views, ranges, pair_vals, rec0,
+                                             rec1, rec2, targets, C, c_off, per_view, bp, VS, gcount);
     } else {
         for (;;) {
             uint32_t t = 0;
             if (lane == 0) t = atomicAdd(queue, 1u);
             const uint32_t tile = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
             if (tile >= n_tiles) break;  // uniform: every wave ends here
-            cnt += accumulate_tile<CC, BF16>(tile, lane, views, n_views, ranges, pair_vals, rec0,
-                                             rec1, targets, C, c_off, per_view, bp, VS, gcount);
+            cnt += accumulate_tile<CC, BF16, BIN>(tile, lane, views, n_views, ranges, pair_vals, rec0,
+                                                  rec1, rec2, targets, C, c_off, per_view, bp, VS,
+                                                  gcount);
         }
     }
     if (c_off == 0 && lane == 0 && cnt) atomicAdd(counter, (unsigned long long)cnt);
 }
 
-template <int CC>
-static void launch_acc_cc(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
-                          const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
-                          const void* targets, int tdtype, int C, bool per_view, BlendParams bp,
-                          float* VS, unsigned long long* counter, uint32_t* gcount,
-                          uint32_t* queues, hipStream_t s) {
-    const uint32_t full = (n_tiles + 3) / 4;
+// Waves (16x16 tiles) of a launch over n_bins bins of `bin` pixels.
+static inline uint32_t wave_tiles(uint32_t n_bins, int bin) { return bin == 32 ? 4u * n_bins : n_bins; }
+
+template <int CC, bool BF16, int BIN>
+static void launch_acc_k(const ViewInfo* views, int n_views, uint32_t n_wt, const uint2* ranges,
+                         const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
+                         const uint32_t* rec2, const void* targets, int C, bool per_view,
+                         BlendParams bp, float* VS, unsigned long long* counter, uint32_t* gcount,
+                         uint32_t* queues, hipStream_t s) {
+    const uint32_t full = (n_wt + 3) / 4;
     dim3 grid(queues ? std::min(full, kPersistentBlocks) : full), block(256);
     int pass = 0;
-    for (int c_off = 0; c_off < C; c_off += CC, ++pass) {
+    const int step = CC > 0 ? CC : C + 1;
+    for (int c_off = 0; c_off < std::max(C, 1); c_off += step, ++pass) {
         uint32_t* q = queues ? queues + pass : nullptr;
-        if (tdtype == GSC_BF16)
-            hipLaunchKernelGGL((k_accumulate<CC, true>), grid, block, 0, s, views, n_views, n_tiles,
-                               ranges, pair_vals, rec0, rec1, targets, C, c_off, (int)per_view, bp,
-                               VS, counter, gcount, q);
-        else
-            hipLaunchKernelGGL((k_accumulate<CC, false>), grid, block, 0, s, views, n_views, n_tiles,
-                               ranges, pair_vals, rec0, rec1, targets, C, c_off, (int)per_view, bp,
-                               VS, counter, gcount, q);
+        hipLaunchKernelGGL((k_accumulate<CC, BF16, BIN>), grid, block, 0, s, views, n_views, n_wt,
+                           ranges, pair_vals, rec0, rec1, rec2, targets, C, c_off, (int)per_view, bp,
+                           VS, counter, gcount, q);
     }
+}
+
+template <int CC>
+static void launch_acc_cc(const ViewInfo* views, int n_views, uint32_t n_bins, const uint2* ranges,
+                          const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
+                          const uint32_t* rec2, int bin, const void* targets, int tdtype, int C,
+                          bool per_view, BlendParams bp, float* VS, unsigned long long* counter,
+                          uint32_t* gcount, uint32_t* queues, hipStream_t s) {
+    const uint32_t n_wt = wave_tiles(n_bins, bin);
+    const bool bf = tdtype == GSC_BF16;
+#define GSC_ACCK(BFV, BINV)                                                                        \
+    launch_acc_k<CC, BFV, BINV>(views, n_views, n_wt, ranges, pair_vals, rec0, rec1, rec2, targets, \
+                                C, per_view, bp, VS, counter, gcount, queues, s)
+    if (bin == 32) {
+        if (bf) GSC_ACCK(true, 32); else GSC_ACCK(false, 32);
+    } else {
+        if (bf) GSC_ACCK(true, 16); else GSC_ACCK(false, 16);
+    }
+#undef GSC_ACCK
 }
 
 int accumulate_chunk(int C) { return C <= 3 ? C : (C <= 4 ? 4 : (C <= 8 ? 8 : 16)); }
@@ -216,24 +237,25 @@ bool accumulate_chunk_valid(int chunk) {
 
 void launch_accumulate(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
                        const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
-                       const void* targets, int tdtype, int C, bool per_view, BlendParams bp,
-                       float* VS, unsigned long long* counter, uint32_t* gcount, hipStream_t s) {
-    launch_accumulate_chunked(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, targets,
-                              tdtype, C, per_view, bp, VS, counter, gcount, 0, s);
+                       const uint32_t* rec2, int bin, const void* targets, int tdtype, int C,
+                       bool per_view, BlendParams bp, float* VS, unsigned long long* counter,
+                       uint32_t* gcount, hipStream_t s) {
+    launch_accumulate_chunked(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, rec2, bin,
+                              targets, tdtype, C, per_view, bp, VS, counter, gcount, 0, s);
 }
 
 void launch_accumulate_chunked(const ViewInfo* views, int n_views, uint32_t n_tiles,
                                const uint2* ranges, const uint32_t* pair_vals, const float4* rec0,
-                               const float4* rec1, const void* targets, int tdtype, int C,
-                               bool per_view, BlendParams bp, float* VS,
-                               unsigned long long* counter, uint32_t* gcount, int chunk,
-                               hipStream_t s, uint32_t* queues) {
+                               const float4* rec1, const uint32_t* rec2, int bin,
+                               const void* targets, int tdtype, int C, bool per_view,
+                               BlendParams bp, float* VS, unsigned long long* counter,
+                               uint32_t* gcount, int chunk, hipStream_t s, uint32_t* queues) {
     if (n_tiles == 0) return;
     if (!accumulate_chunk_valid(chunk)) chunk = accumulate_chunk(C);
     if (queues) launch_fill_u32(queues, 0u, (uint64_t)((C + chunk - 1) / chunk), s);
-#define GSC_ACC(CCV)                                                                              \
-    launch_acc_cc<CCV>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, targets, tdtype, C, \
-                       per_view, bp, VS, counter, gcount, queues, s)
+#define GSC_ACC(CCV)                                                                                \
+    launch_acc_cc<CCV>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, rec2, bin, targets,   \
+                       tdtype, C, per_view, bp, VS, counter, gcount, queues, s)
     switch (chunk) {
         case 1: GSC_ACC(1); break;
         case 2: GSC_ACC(2); break;
@@ -247,12 +269,16 @@ void launch_accumulate_chunked(const ViewInfo* views, int n_views, uint32_t n_ti
 
 void launch_accumulate_weights(const ViewInfo* views, int n_views, uint32_t n_tiles,
                                const uint2* ranges, const uint32_t* pair_vals, const float4* rec0,
-                               const float4* rec1, bool per_view, BlendParams bp, float* V,
-                               unsigned long long* counter, hipStream_t s) {
+                               const float4* rec1, const uint32_t* rec2, int bin, bool per_view,
+                               BlendParams bp, float* V, unsigned long long* counter, hipStream_t s) {
     if (n_tiles == 0) return;
-    hipLaunchKernelGGL((k_accumulate<0, false>), dim3((n_tiles + 3) / 4), dim3(256), 0, s, views,
-                       n_views, n_tiles, ranges, pair_vals, rec0, rec1, (const void*)nullptr, 0, 0,
-                       (int)per_view, bp, V, counter, (uint32_t*)nullptr, (uint32_t*)nullptr);
+    const uint32_t n_wt = wave_tiles(n_tiles, bin);
+    if (bin == 32)
+        launch_acc_k<0, false, 32>(views, n_views, n_wt, ranges, pair_vals, rec0, rec1, rec2, nullptr,
+                                   0, per_view, bp, V, counter, nullptr, nullptr, s);
+    else
+        launch_acc_k<0, false, 16>(views, n_views, n_wt, ranges, pair_vals, rec0, rec1, rec2, nullptr,
+                                   0, per_view, bp, V, counter, nullptr, nullptr, s);
 }
 
 // ---- render ----------------------------------------------------------------
@@ -295,55 +321,63 @@ void launch_view_colors(const ViewInfo* views, int n_views, uint32_t n_items, co
     }
 }
 
-// images[row][c] = sum_g w_gp * gamma_gv[c]; every pixel of every tile is written.
-template <int CC>
+// images[row][c] = sum_g w_gp * gamma_gv[c]; every pixel of every tile is
+// written.  Same tile walk and blend decisions as accumulate_tile.
+template <int CC, int BIN>
 __global__ __launch_bounds__(256) void k_render(
-    const ViewInfo* __restrict__ views, int n_views, uint32_t n_tiles, const uint2* __restrict__ ranges,
+    const ViewInfo* __restrict__ views, int n_views, uint32_t n_wt, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ pair_vals, const float4* __restrict__ rec0,
-    const float4* __restrict__ rec1, const float* __restrict__ gamma, int C, int c_off,
-    BlendParams bp, float* __restrict__ images, unsigned long long* __restrict__ counter) {
+    const float4* __restrict__ rec1, const uint32_t* __restrict__ rec2,
+    const float* __restrict__ gamma, int C, int c_off, BlendParams bp, float* __restrict__ images,
+    unsigned long long* __restrict__ counter) {
     const uint32_t lane = threadIdx.x & 63;
-    const uint32_t tile = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (tile >= n_tiles) return;
-    const int vloc = find_view(views, n_views, tile);
-    const ViewInfo& V = views[vloc];
-    const uint32_t local = tile - V.tile_base;
-    const int tx = (int)(local % (uint32_t)V.tiles_x), ty = (int)(local / (uint32_t)V.tiles_x);
-    const int ix = tx * kTile + (int)(lane & 15);
-    const int iy0 = ty * kTile + (int)(lane >> 4);
+    const uint32_t wt = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wt >= n_wt) return;
+    const TileGeom tg = tile_geom<BIN>(wt, views, n_views);
+    const ViewInfo& V = views[tg.vloc];
+    const int ix = tg.x0 + (int)(lane & 15);
+    const int iy0 = tg.y0 + (int)(lane >> 4);
     const float px = (float)ix + 0.5f;
     float T[4];
-    bool live[4], inside[4];
+    bool inside[4];
     float img[4][CC];
+    uint32_t alive = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         inside[k] = ix < V.width && iy0 + 4 * k < V.height;
-        live[k] = inside[k];
-        T[k] = 1.0f;
+        T[k] = inside[k] ? 1.0f : 0.0f;
+        alive |= (__builtin_amdgcn_ballot_w64(inside[k]) != 0 ? 1u : 0u) << k;
 #pragma unroll
         for (int c = 0; c < CC; ++c) img[k][c] = 0.0f;
     }
-    const uint2 rg = ranges[tile];
+    alive = (uint32_t)__builtin_amdgcn_readfirstlane((int)alive);
+    uint2 rg = ranges[tg.bin];
+    rg.x = (uint32_t)__builtin_amdgcn_readfirstlane((int)rg.x);
+    rg.y = (uint32_t)__builtin_amdgcn_readfirstlane((int)rg.y);
     uint32_t cnt = 0;
-    bool wave_live = __ballot(live[0] || live[1] || live[2] || live[3]) != 0;
     const float qlim = (float)(kExp2Scale * (double)bp.cut2);
+    const float amax = bp.alpha_max, amin = bp.alpha_min, tmin = bp.t_min;
     float pyk[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) pyk[k] = (float)(iy0 + 4 * k) + 0.5f;
-    for (uint32_t b = rg.x; b < rg.y && wave_live; b += 64) {
+    for (uint32_t b = rg.x; b < rg.y && alive != 0u; b += 64) {
         const uint32_t nb = min(64u, rg.y - b);
         const uint32_t pv = lane < nb ? pair_vals[b + lane] : 0u;
         uint32_t pn = bcast_u(pv, 0);
         float4 n0 = rec0[pn & kItemMask], n1 = rec1[pn & kItemMask];
+        uint32_t n2 = BIN == 32 ? rec2[pn & kItemMask] : 0u;
         for (uint32_t j = 0; j < nb; ++j) {
             const uint32_t pc = pn;
             const float4 c0 = n0, c1 = n1;
+            const uint32_t e2 = n2;
             if (j + 1 < nb) {
                 pn = bcast_u(pv, j + 1);
                 n0 = rec0[pn & kItemMask];
                 n1 = rec1[pn & kItemMask];
+                if constexpr (BIN == 32) n2 = rec2[pn & kItemMask];
             }
-            const uint32_t bands = pc >> kItemBits;
+            const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2, tg.y0) & alive;
+            if (bands == 0u) continue;
             const uint32_t item = pc & kItemMask;
             float col[CC];
             const float* gp = gamma + (int64_t)item * C + c_off;
@@ -352,30 +386,27 @@ __global__ __launch_bounds__(256) void k_render(
             const float dx = (px - c0.x) - c0.z;
             const float a0 = c1.x * dx * dx;
             const float b0 = c1.y * dx;
+            uint32_t nh = 0;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (!((bands >> k) & 1u)) continue;
-                if (!live[k]) continue;
                 const float dy = (pyk[k] - c0.y) - c0.w;
                 const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
-                if (q2 < qlim) continue;
-                const float al = fminf(bp.alpha_max, c1.w * __builtin_amdgcn_exp2f(q2));
-                if (al < bp.alpha_min) continue;
+                const float al = __builtin_amdgcn_fmed3f(c1.w * __builtin_amdgcn_exp2f(q2), 0.0f, amax);
                 const float test = fmaf(-T[k], al, T[k]);
-                if (test < bp.t_min) {
-                    live[k] = false;
-                    continue;
-                }
-                const float w = al * T[k];
-                T[k] = test;
+                const bool cand = q2 >= qlim && al >= amin && T[k] > 0.0f;
+                const bool keep = test >= tmin;
+                const bool take = cand && keep;
+                const float w = take ? al * T[k] : 0.0f;
+                T[k] = cand ? (keep ? test : 0.0f) : T[k];
 #pragma unroll
                 for (int c = 0; c < CC; ++c) img[k][c] = fmaf(w, col[c], img[k][c]);
-                ++cnt;
+                nh += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(take));
+                if (__builtin_amdgcn_ballot_w64(T[k] > 0.0f) == 0) alive &= ~(1u << k);
             }
-            if (__ballot(live[0] || live[1] || live[2] || live[3]) == 0) {
-                wave_live = false;
-                break;
-            }
+            alive = (uint32_t)__builtin_amdgcn_readfirstlane((int)alive);
+            cnt += (uint32_t)__builtin_amdgcn_readfirstlane((int)nh);
+            if (alive == 0u) break;
         }
     }
 #pragma unroll
@@ -386,27 +417,28 @@ __global__ __launch_bounds__(256) void k_render(
         for (int c = 0; c < CC; ++c)
             if (c_off + c < C) images[row * C + c_off + c] = img[k][c];
     }
-    if (c_off == 0) {
-        const uint32_t tot = wave_sum_u32(cnt);
-        if (lane == 0 && tot) atomicAdd(counter, (unsigned long long)tot);
-    }
+    if (c_off == 0 && lane == 0 && cnt) atomicAdd(counter, (unsigned long long)cnt);
 }
 
 void launch_render(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
                    const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
-                   const float* gamma, int C, BlendParams bp, float* images,
-                   unsigned long long* counter, hipStream_t s) {
+                   const uint32_t* rec2, int bin, const float* gamma, int C, BlendParams bp,
+                   float* images, unsigned long long* counter, hipStream_t s) {
     if (n_tiles == 0) return;
-    dim3 grid((n_tiles + 3) / 4), block(256);
+    const uint32_t n_wt = wave_tiles(n_tiles, bin);
+    dim3 grid((n_wt + 3) / 4), block(256);
+#define GSC_RENDER(CCV, BINV)                                                                     \
+    hipLaunchKernelGGL((k_render<CCV, BINV>), grid, block, 0, s, views, n_views, n_wt, ranges,    \
+                       pair_vals, rec0, rec1, rec2, gamma, C, c_off, bp, images, counter)
     for (int c_off = 0; c_off < C; c_off += 4) {
-        if (C <= 3 && c_off == 0) {
-            hipLaunchKernelGGL(k_render<3>, grid, block, 0, s, views, n_views, n_tiles, ranges,
-                               pair_vals, rec0, rec1, gamma, C, c_off, bp, images, counter);
+        const bool three = C <= 3 && c_off == 0;
+        if (bin == 32) {
+            if (three) GSC_RENDER(3, 32); else GSC_RENDER(4, 32);
         } else {
-            hipLaunchKernelGGL(k_render<4>, grid, block, 0, s, views, n_views, n_tiles, ranges,
-                               pair_vals, rec0, rec1, gamma, C, c_off, bp, images, counter);
+            if (three) GSC_RENDER(3, 16); else GSC_RENDER(4, 16);
         }
     }
+#undef GSC_RENDER
 }
 
 }  // namespace gsc

@@ -129,22 +129,21 @@ __device__ __forceinline__ Step blend_step(float& T, bool& live, float q2, float
 // CC: channels of this launch (chunk [c_off, c_off + CC) of C).  dL/dw is
 // linear in the channels, so chunk launches add their shares of dL/do; the
 // first chunk also carries -delta.
-template <int CC, bool BF16, bool GY>
+template <int CC, bool BF16, bool GY, int BIN>
 __global__ __launch_bounds__(256) void k_blend_adjoint(
-    const ViewInfo* __restrict__ views, int n_views, uint32_t n_tiles, const uint2* __restrict__ ranges,
+    const ViewInfo* __restrict__ views, int n_views, uint32_t n_wt, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ pair_vals, const float4* __restrict__ rec0,
-    const float4* __restrict__ rec1, const void* __restrict__ ypix, int C, int c_off,
+    const float4* __restrict__ rec1, const uint32_t* __restrict__ rec2,
+    const void* __restrict__ ypix, int C, int c_off,
     const float* __restrict__ beta, BlendParams bp, float* __restrict__ grad_y,
     float* __restrict__ grad_o) {
     const uint32_t lane = threadIdx.x & 63;
-    const uint32_t tile = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (tile >= n_tiles) return;  // whole wave
-    const int vloc = find_view(views, n_views, tile);
-    const ViewInfo& V = views[vloc];
-    const uint32_t local = tile - V.tile_base;
-    const int tx = (int)(local % (uint32_t)V.tiles_x), ty = (int)(local / (uint32_t)V.tiles_x);
-    const int ix = tx * kTile + (int)(lane & 15);
-    const int iy0 = ty * kTile + (int)(lane >> 4);
+    const uint32_t wt = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wt >= n_wt) return;  // whole wave
+    const TileGeom tg = tile_geom<BIN>(wt, views, n_views);
+    const ViewInfo& V = views[tg.vloc];
+    const int ix = tg.x0 + (int)(lane & 15);
+    const int iy0 = tg.y0 + (int)(lane >> 4);
     const float px = (float)ix + 0.5f;
     const int stride = C + 1;
     const bool first_chunk = c_off == 0;
@@ -165,7 +164,9 @@ __global__ __launch_bounds__(256) void k_blend_adjoint(
         for (int c = 0; c < CC; ++c)
             yv[k][c] = (inside[k] && grad_o && c_off + c < C) ? load_target<BF16>(ypix, row * C + c_off + c) : 0.0f;
     }
-    const uint2 rg = ranges[tile];
+    uint2 rg = ranges[tg.bin];
+    rg.x = (uint32_t)__builtin_amdgcn_readfirstlane((int)rg.x);
+    rg.y = (uint32_t)__builtin_amdgcn_readfirstlane((int)rg.y);
 
     // ---- pass 1: S = sum_k u_k w_k per pixel, and dL/dy -------------------
     float T[4];
@@ -186,15 +187,19 @@ __global__ __launch_bounds__(256) void k_blend_adjoint(
         const uint32_t pv = lane < nb ? pair_vals[b + lane] : 0u;
         uint32_t pn = bcast_u(pv, 0);
         float4 n0 = rec0[pn & kItemMask], n1 = rec1[pn & kItemMask];
+        uint32_t n2 = BIN == 32 ? rec2[pn & kItemMask] : 0u;
         for (uint32_t j = 0; j < nb; ++j) {
             const uint32_t pc = pn;
             const float4 c0 = n0, c1 = n1;
+            const uint32_t e2 = n2;
             if (j + 1 < nb) {
                 pn = bcast_u(pv, j + 1);
                 n0 = rec0[pn & kItemMask];
                 n1 = rec1[pn & kItemMask];
+                if constexpr (BIN == 32) n2 = rec2[pn & kItemMask];
             }
-            const uint32_t bands = pc >> kItemBits;
+            const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2, tg.y0);
+            if (bands == 0u) continue;
             const uint32_t item = pc & kItemMask;
             const float* bp_ = beta + (int64_t)item * stride;
             float bet[CC];
@@ -251,15 +256,19 @@ __global__ __launch_bounds__(256) void k_blend_adjoint(
         const uint32_t pv = lane < nb ? pair_vals[b + lane] : 0u;
         uint32_t pn = bcast_u(pv, 0);
         float4 n0 = rec0[pn & kItemMask], n1 = rec1[pn & kItemMask];
+        uint32_t n2 = BIN == 32 ? rec2[pn & kItemMask] : 0u;
         for (uint32_t j = 0; j < nb; ++j) {
             const uint32_t pc = pn;
             const float4 c0 = n0, c1 = n1;
+            const uint32_t e2 = n2;
             if (j + 1 < nb) {
                 pn = bcast_u(pv, j + 1);
                 n0 = rec0[pn & kItemMask];
                 n1 = rec1[pn & kItemMask];
+                if constexpr (BIN == 32) n2 = rec2[pn & kItemMask];
             }
-            const uint32_t bands = pc >> kItemBits;
+            const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2, tg.y0);
+            if (bands == 0u) continue;
             const uint32_t item = pc & kItemMask;
             const float* bp_ = beta + (int64_t)item * stride;
             float bet[CC];
@@ -300,49 +309,59 @@ __global__ __launch_bounds__(256) void k_blend_adjoint(
 }
 
 template <int CC, bool GY>
-static void launch_badj_cc(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
+static void launch_badj_cc(const ViewInfo* views, int n_views, uint32_t n_bins, const uint2* ranges,
                            const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
-                           const void* ypix, int ydtype, int C, const float* beta,
-                           BlendParams bp, float* grad_y, float* grad_o, hipStream_t s) {
-    dim3 grid((n_tiles + 3) / 4), block(256);
+                           const uint32_t* rec2, int bin, const void* ypix, int ydtype, int C,
+                           const float* beta, BlendParams bp, float* grad_y, float* grad_o,
+                           hipStream_t s) {
+    const uint32_t n_wt = bin == 32 ? 4u * n_bins : n_bins;
+    dim3 grid((n_wt + 3) / 4), block(256);
+#define GSC_BADJ(BFV, BINV)                                                                         \
+    hipLaunchKernelGGL((k_blend_adjoint<CC, BFV, GY, BINV>), grid, block, 0, s, views, n_views, n_wt, \
+                       ranges, pair_vals, rec0, rec1, rec2, ypix, C, c_off, beta, bp, grad_y, grad_o)
     for (int c_off = 0; c_off < C; c_off += CC) {
-        if (ydtype == GSC_BF16)
-            hipLaunchKernelGGL((k_blend_adjoint<CC, true, GY>), grid, block, 0, s, views, n_views,
-                               n_tiles, ranges, pair_vals, rec0, rec1, ypix, C, c_off, beta, bp,
-                               grad_y, grad_o);
-        else
-            hipLaunchKernelGGL((k_blend_adjoint<CC, false, GY>), grid, block, 0, s, views, n_views,
-                               n_tiles, ranges, pair_vals, rec0, rec1, ypix, C, c_off, beta, bp,
-                               grad_y, grad_o);
+        const bool bf = ydtype == GSC_BF16;
+        if (bin == 32) {
+            if (bf) GSC_BADJ(true, 32); else GSC_BADJ(false, 32);
+        } else {
+            if (bf) GSC_BADJ(true, 16); else GSC_BADJ(false, 16);
+        }
     }
+#undef GSC_BADJ
 }
 
 template <bool GY>
 static void launch_badj(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
                         const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
-                        const void* ypix, int ydtype, int C, const float* beta,
-                        BlendParams bp, float* grad_y, float* grad_o, hipStream_t s) {
+                        const uint32_t* rec2, int bin, const void* ypix, int ydtype, int C,
+                        const float* beta, BlendParams bp, float* grad_y, float* grad_o,
+                        hipStream_t s) {
+#define GSC_BA(CCV)                                                                                \
+    launch_badj_cc<CCV, GY>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, rec2, bin, ypix, \
+                            ydtype, C, beta, bp, grad_y, grad_o, s)
     switch (accumulate_chunk(C)) {
-        case 1: launch_badj_cc<1, GY>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C, beta, bp, grad_y, grad_o, s); break;
-        case 2: launch_badj_cc<2, GY>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C, beta, bp, grad_y, grad_o, s); break;
-        case 3: launch_badj_cc<3, GY>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C, beta, bp, grad_y, grad_o, s); break;
-        case 4: launch_badj_cc<4, GY>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C, beta, bp, grad_y, grad_o, s); break;
-        case 8: launch_badj_cc<8, GY>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C, beta, bp, grad_y, grad_o, s); break;
-        default: launch_badj_cc<16, GY>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C, beta, bp, grad_y, grad_o, s); break;
+        case 1: GSC_BA(1); break;
+        case 2: GSC_BA(2); break;
+        case 3: GSC_BA(3); break;
+        case 4: GSC_BA(4); break;
+        case 8: GSC_BA(8); break;
+        default: GSC_BA(16); break;
     }
+#undef GSC_BA
 }
 
 void launch_blend_adjoint(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
                           const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
-                          const void* ypix, int ydtype, int C, const float* beta, BlendParams bp,
-                          float* grad_y, float* grad_o, hipStream_t s) {
+                          const uint32_t* rec2, int bin, const void* ypix, int ydtype, int C,
+                          const float* beta, BlendParams bp, float* grad_y, float* grad_o,
+                          hipStream_t s) {
     if (n_tiles == 0 || (!grad_y && !grad_o)) return;
     if (grad_y)
-        launch_badj<true>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C,
-                          beta, bp, grad_y, grad_o, s);
+        launch_badj<true>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, rec2, bin, ypix,
+                          ydtype, C, beta, bp, grad_y, grad_o, s);
     else
-        launch_badj<false>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, ypix, ydtype, C,
-                           beta, bp, grad_y, grad_o, s);
+        launch_badj<false>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, rec2, bin, ypix,
+                           ydtype, C, beta, bp, grad_y, grad_o, s);
 }
 
 // grad_coeffs[g][m][c] = sum_j phi_gj[m] S_gj[c] from the per-view sums

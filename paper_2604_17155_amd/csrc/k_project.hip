@@ -47,14 +47,15 @@ __device__ inline float reach_q(float o, const BlendParams& bp) {
 }
 
 // Walks the pixel rows of a record's footprint {q <= qmax} and calls
-// visit(ty, lo, hi) once per tile row, where [lo[k], hi[k]] is the range of
-// tile columns holding a pixel centre of band k (rows 4k..4k+3 of the tile)
-// inside the footprint (lo > hi: none).  Row intervals are widened by 0.01
-// pixel, so the walk is conservative with respect to the blend's FP32 test.
-// Used identically for counting and emitting.
+// visit(ty, lo, hi) once per 16-row tile row, where [lo[k], hi[k]] is the
+// range of 16-column blocks holding a pixel centre of band k (rows 4k..4k+3
+// of the tile row) inside the footprint (lo > hi: none).  Row intervals are
+// widened by 0.01 pixel, so the walk is conservative with respect to the
+// blend's FP32 test.  *rows (optional) receives the first and last pixel row
+// walked.  Used identically for counting and emitting.
 template <typename Visit>
 __device__ inline void footprint_rows(float4 r0, float4 r1, float qmax, int W, int H,
-                                      Visit&& visit) {
+                                      Visit&& visit, int* rows = nullptr) {
     constexpr float kInvK = (float)(1.0 / kExp2Scale);
     const float a = r1.x * kInvK, b = 0.5f * r1.y * kInvK, c = r1.z * kInvK;
     const float det = a * c - b * b;
@@ -66,6 +67,10 @@ __device__ inline void footprint_rows(float4 r0, float4 r1, float qmax, int W, i
     const float fy1 = fminf(floorf(vc + ry), (float)(H - 1));
     if (!(fy0 <= fy1)) return;
     const int y0 = (int)fy0, y1 = (int)fy1;
+    if (rows) {
+        rows[0] = y0;
+        rows[1] = y1;
+    }
     int lo[4], hi[4];
     int cur = y0 >> kTileShift;
     for (int k = 0; k < 4; ++k) { lo[k] = 1 << 30; hi[k] = -1; }
@@ -95,10 +100,59 @@ __device__ inline void footprint_rows(float4 r0, float4 r1, float qmax, int W, i
     visit(cur, lo, hi);
 }
 
-__device__ inline uint32_t band_bits(const int* lo, const int* hi, int t) {
-    uint32_t m = 0;
-    for (int k = 0; k < 4; ++k) m |= (lo[k] <= t && t <= hi[k]) ? (1u << k) : 0u;
-    return m;
+// Footprint per bin row.  BIN = 16: the bin is the 16x16 tile and its 4-bit
+// mask marks the bands (rows 4k..4k+3) the footprint reaches.  BIN = 32: the
+// bin is a 32x32 block of four 16x16 tiles and bit 2h + c marks the tile in
+// row half h and column half c.  visit(bin_row, t0, t1, mask_of) is called
+// per bin row with the bin columns [t0, t1] and a function giving a bin
+// column's mask (0: not reached).
+template <int BIN, typename Visit>
+__device__ inline void footprint_bins(float4 r0, float4 r1, float qmax, int W, int H,
+                                      Visit&& visit, int* rows = nullptr) {
+    if constexpr (BIN == 16) {
+        footprint_rows(r0, r1, qmax, W, H, [&](int ty, const int* lo, const int* hi) {
+            int t0 = 1 << 30, t1 = -1;
+            for (int k = 0; k < 4; ++k) {
+                t0 = min(t0, lo[k]);
+                t1 = max(t1, hi[k]);
+            }
+            visit(ty, t0, t1, [&](int t) {
+                uint32_t m = 0;
+                for (int k = 0; k < 4; ++k) m |= (lo[k] <= t && t <= hi[k]) ? (1u << k) : 0u;
+                return m;
+            });
+        }, rows);
+    } else {
+        static_assert(BIN == 32, "bins are 16 or 32 pixels");
+        // 16-column block ranges of the two tile rows of the current bin row
+        int cur = -1, lo[2] = {1 << 30, 1 << 30}, hi[2] = {-1, -1};
+        auto flush = [&]() {
+            if (cur < 0) return;
+            const int b0 = min(lo[0], lo[1]), b1 = max(hi[0], hi[1]);
+            if (b0 <= b1)
+                visit(cur, b0 >> 1, b1 >> 1, [&](int t) {
+                    uint32_t m = 0;
+                    for (int h = 0; h < 2; ++h)
+                        for (int c = 0; c < 2; ++c)
+                            m |= (lo[h] <= 2 * t + c && 2 * t + c <= hi[h]) ? (1u << (2 * h + c)) : 0u;
+                    return m;
+                });
+        };
+        footprint_rows(r0, r1, qmax, W, H, [&](int ty, const int* l4, const int* h4) {
+            const int br = ty >> 1, h = ty & 1;
+            if (br != cur) {
+                flush();
+                cur = br;
+                lo[0] = lo[1] = 1 << 30;
+                hi[0] = hi[1] = -1;
+            }
+            for (int k = 0; k < 4; ++k) {
+                lo[h] = min(lo[h], l4[k]);
+                hi[h] = max(hi[h], h4[k]);
+            }
+        }, rows);
+        flush();
+    }
 }
 
 // a2: one thread per (view, Gaussian) item of the batch.
@@ -109,6 +163,8 @@ __device__ inline uint32_t band_bits(const int* lo, const int* hi, int t) {
 // enough to move alpha by ~1e-4 relative at the footprint edge.
 // A tile is binned only if its pixel centres come within the footprint
 // reach (3-sigma ellipse, shrunk by the alpha floor for faint splats).
+// rec2[i] = first | last << 16: the pixel rows the footprint walk covers.
+template <int BIN>
 __global__ __launch_bounds__(256) void k_project(const ViewInfo* __restrict__ views, int n_views,
                                                  uint32_t n_items, const float* __restrict__ means,
                                                  const float* __restrict__ cov,
@@ -116,7 +172,8 @@ __global__ __launch_bounds__(256) void k_project(const ViewInfo* __restrict__ vi
                                                  BlendParams bp, uint32_t* __restrict__ keys,
                                                  uint32_t* __restrict__ vals,
                                                  uint32_t* __restrict__ counts,
-                                                 float4* __restrict__ rec0, float4* __restrict__ rec1) {
+                                                 float4* __restrict__ rec0, float4* __restrict__ rec1,
+                                                 uint32_t* __restrict__ rec2) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_items) return;
     const ViewInfo& V = views[find_view_item(views, n_views, i)];
@@ -124,6 +181,7 @@ __global__ __launch_bounds__(256) void k_project(const ViewInfo* __restrict__ vi
     float mx = means[3 * g], my = means[3 * g + 1], mz = means[3 * g + 2];
     float key = __fmaf_rn(V.R[6], mx, __fmaf_rn(V.R[7], my, __fmaf_rn(V.R[8], mz, V.t[2])));
     uint32_t kb = 0xFFFFFFFFu, cnt = 0;
+    int rows[2] = {1, 0};
     float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
     const float og = opac[g];
     const float qmax = reach_q(og, bp);
@@ -162,14 +220,9 @@ __global__ __launch_bounds__(256) void k_project(const ViewInfo* __restrict__ vi
             r0 = make_float4(uh, vh, (float)(u - (double)uh), (float)(vv - (double)vh));
             r1 = make_float4((float)(kExp2Scale * syy * inv), (float)(-2.0 * kExp2Scale * sxy * inv),
                              (float)(kExp2Scale * sxx * inv), og);
-            footprint_rows(r0, r1, qmax, V.width, V.height, [&](int, const int* lo, const int* hi) {
-                int t0 = 1 << 30, t1 = -1;
-                for (int k = 0; k < 4; ++k) {
-                    t0 = min(t0, lo[k]);
-                    t1 = max(t1, hi[k]);
-                }
-                for (int t = t0; t <= t1; ++t) cnt += band_bits(lo, hi, t) != 0u;
-            });
+            footprint_bins<BIN>(r0, r1, qmax, V.width, V.height, [&](int, int t0, int t1, auto&& mask_of) {
+                for (int t = t0; t <= t1; ++t) cnt += mask_of(t) != 0u;
+            }, rows);
             if (cnt > 0) kb = __float_as_uint(key);
         }
     }
@@ -178,14 +231,20 @@ __global__ __launch_bounds__(256) void k_project(const ViewInfo* __restrict__ vi
     counts[i] = cnt;
     rec0[i] = r0;
     rec1[i] = r1;
+    rec2[i] = (uint32_t)(rows[0] & 0xFFFF) | ((uint32_t)(rows[1] & 0xFFFF) << 16);
 }
 
 void launch_project(const ViewInfo* views, int n_views, uint32_t n_items, const float* means,
                     const float* cov, const float* opac, BlendParams bp, uint32_t* keys,
-                    uint32_t* vals, uint32_t* counts, float4* rec0, float4* rec1, hipStream_t s) {
+                    uint32_t* vals, uint32_t* counts, float4* rec0, float4* rec1, uint32_t* rec2,
+                    int bin, hipStream_t s) {
     if (n_items == 0 || n_views <= 0) return;
-    hipLaunchKernelGGL(k_project, dim3((n_items + 255) / 256), dim3(256), 0, s, views, n_views,
-                       n_items, means, cov, opac, bp, keys, vals, counts, rec0, rec1);
+    if (bin == 32)
+        hipLaunchKernelGGL(k_project<32>, dim3((n_items + 255) / 256), dim3(256), 0, s, views, n_views,
+                           n_items, means, cov, opac, bp, keys, vals, counts, rec0, rec1, rec2);
+    else
+        hipLaunchKernelGGL(k_project<16>, dim3((n_items + 255) / 256), dim3(256), 0, s, views, n_views,
+                           n_items, means, cov, opac, bp, keys, vals, counts, rec0, rec1, rec2);
 }
 
 __global__ void k_gather_counts(const uint32_t* __restrict__ sorted_vals,
@@ -202,8 +261,9 @@ void launch_gather_counts(const uint32_t* sorted_vals, const uint32_t* counts, u
                        out, n);
 }
 
-// a3: emit (global tile id, item) pairs in depth order; a stable sort by tile
-// id then yields every tile's list in front-to-back order.
+// a3: emit (global bin id, item | mask) pairs in depth order; a stable sort by
+// bin id then yields every bin's list in front-to-back order.
+template <int BIN>
 __global__ void k_emit(const ViewInfo* __restrict__ views, int n_views,
                        const uint32_t* __restrict__ sorted_vals,
                        const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ counts,
@@ -223,15 +283,10 @@ __global__ void k_emit(const ViewInfo* __restrict__ views, int n_views,
         if (overflow) atomicAdd(overflow, 1u);
         end = off < cap ? cap : off;
     }
-    footprint_rows(r0, r1, reach_q(r1.w, bp), V.width, V.height,
-                   [&](int ty, const int* lo, const int* hi) {
-        int t0 = 1 << 30, t1 = -1;
-        for (int b = 0; b < 4; ++b) {
-            t0 = min(t0, lo[b]);
-            t1 = max(t1, hi[b]);
-        }
+    footprint_bins<BIN>(r0, r1, reach_q(r1.w, bp), V.width, V.height,
+                        [&](int ty, int t0, int t1, auto&& mask_of) {
         for (int t = t0; t <= t1; ++t) {
-            const uint32_t m = band_bits(lo, hi, t);
+            const uint32_t m = mask_of(t);
             if (m == 0u || off >= end) continue;
             pair_keys[off] = V.tile_base + (uint32_t)ty * (uint32_t)V.tiles_x + (uint32_t)t;
             pair_vals[off] = i | (m << kItemBits);
@@ -250,12 +305,17 @@ __global__ void k_emit(const ViewInfo* __restrict__ views, int n_views,
 void launch_emit(const ViewInfo* views, int n_views, const uint32_t* sorted_vals,
                  const uint32_t* offsets, const uint32_t* counts, const float4* rec0,
                  const float4* rec1, BlendParams bp, uint32_t n_items, uint32_t n_tiles,
-                 uint32_t* pair_keys, uint32_t* pair_vals, hipStream_t s, uint32_t cap,
+                 uint32_t* pair_keys, uint32_t* pair_vals, int bin, hipStream_t s, uint32_t cap,
                  uint32_t* overflow) {
     if (n_items == 0) return;
-    hipLaunchKernelGGL(k_emit, dim3((n_items + 255) / 256), dim3(256), 0, s, views, n_views,
-                       sorted_vals, offsets, counts, rec0, rec1, bp, n_items, n_tiles, cap,
-                       overflow, pair_keys, pair_vals);
+    if (bin == 32)
+        hipLaunchKernelGGL(k_emit<32>, dim3((n_items + 255) / 256), dim3(256), 0, s, views, n_views,
+                           sorted_vals, offsets, counts, rec0, rec1, bp, n_items, n_tiles, cap,
+                           overflow, pair_keys, pair_vals);
+    else
+        hipLaunchKernelGGL(k_emit<16>, dim3((n_items + 255) / 256), dim3(256), 0, s, views, n_views,
+                           sorted_vals, offsets, counts, rec0, rec1, bp, n_items, n_tiles, cap,
+                           overflow, pair_keys, pair_vals);
 }
 
 __global__ __launch_bounds__(256) void k_sum_u64(const uint32_t* __restrict__ counts, uint32_t n,

@@ -143,6 +143,51 @@ __device__ __forceinline__ int find_view(const ViewInfo* __restrict__ views, int
     return lo;
 }
 
+// The 16x16 tile a wave works on.  A launch over bins of BIN pixels runs
+// (BIN / 16)^2 waves per bin; wave tile vt is tile `quad` (bit 0: column
+// half, bit 1: row half) of bin vt / (BIN / 16)^2.
+struct TileGeom {
+    uint32_t bin;   // global bin id within the batch
+    uint32_t quad;  // tile within the bin (0 for 16-pixel bins)
+    int vloc;       // view of the bin within the batch table
+    int x0, y0;     // pixel origin of the tile
+};
+
+template <int BIN>
+__device__ __forceinline__ TileGeom tile_geom(uint32_t vt, const ViewInfo* __restrict__ views,
+                                              int n_views) {
+    TileGeom t;
+    vt = (uint32_t)__builtin_amdgcn_readfirstlane((int)vt);  // wave-uniform
+    t.bin = BIN == 32 ? vt >> 2 : vt;
+    t.quad = BIN == 32 ? (vt & 3u) : 0u;
+    t.vloc = __builtin_amdgcn_readfirstlane(find_view(views, n_views, t.bin));
+    const ViewInfo& V = views[t.vloc];
+    const uint32_t local = t.bin - V.tile_base;
+    const int bx = (int)(local % (uint32_t)V.tiles_x), by = (int)(local / (uint32_t)V.tiles_x);
+    t.x0 = bx * BIN + (int)(t.quad & 1u) * kTile;
+    t.y0 = by * BIN + (int)(t.quad >> 1) * kTile;
+    return t;
+}
+
+// Bands (rows y0 + 4k .. y0 + 4k + 3 of the tile) a list entry can reach:
+// the pair's band mask for 16-pixel bins; for 32-pixel bins, none unless the
+// pair marks this tile, else the bands met by the footprint's rows
+// [ext & 0xFFFF, ext >> 16].
+template <int BIN>
+__device__ __forceinline__ uint32_t entry_bands(uint32_t pc, uint32_t quad, uint32_t ext, int y0) {
+    const uint32_t m = pc >> kItemBits;
+    if constexpr (BIN == 16) {
+        return m;
+    } else {
+        if (!((m >> quad) & 1u)) return 0u;
+        const int ylo = (int)(ext & 0xFFFFu), yhi = (int)(ext >> 16);
+        uint32_t b = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) b |= (ylo <= y0 + 4 * k + 3 && yhi >= y0 + 4 * k) ? (1u << k) : 0u;
+        return b;
+    }
+}
+
 template <bool BF16>
 __device__ __forceinline__ float load_target(const void* __restrict__ t, int64_t idx) {
     if constexpr (BF16) {

@@ -103,7 +103,8 @@ def test_bad_camera_rejected(lib):
 
 
 def test_bad_options_rejected(lib):
-    for over in [dict(alpha_max=1.5), dict(t_min=-1.0), dict(znear=0.0), dict(sigma_cut=0.0)]:
+    for over in [dict(alpha_max=1.5), dict(t_min=-1.0), dict(znear=0.0), dict(sigma_cut=0.0),
+                 dict(bin_size=8), dict(bin_size=64)]:
         o = gsc.default_options()
         for k, v in over.items():
             setattr(o, k, v)

@@ -247,3 +247,11 @@ def test_adjoint_identities_full_size(ctx_prod, gsc_mod):
     print(f"render adjoint identity: {lhs:.9e} vs {rhs:.9e} (|d|/||gi|| ||img|| = "
           f"{abs(lhs - rhs) / scale:.1e}, |d|/|rhs| = {abs(lhs - rhs) / abs(rhs):.1e})", flush=True)
     assert abs(lhs - rhs) <= 1e-6 * scale
+
+
+def test_colorize_backward_bins_of_32_pixels(gsc_mod):
+    ctx = gsc_mod.Context(bin_size=32, **SMOOTH)
+    sc = syn.make_relight(n=6000, n_cams=8, res=128)
+    y = oracle.make_targets(sc)
+    et, eo, _, _ = colorize_backward_case(ctx, sc, y, smooth_opts(), "colorize adjoint L3 C3 smooth bin32")
+    assert et <= TOL_GRAD and eo <= TOL_GRAD

@@ -207,3 +207,14 @@ def test_batched_capacity_guard(ctx, gsc_mod):
     e, _ = parity.rel_errors(c.cpu().numpy(), dict(coeffs=ref_c.cpu().numpy().astype(np.float64),
                                                    status=np.zeros(len(c), np.uint8)))
     assert e.max() < 1e-5
+
+
+def test_batched_bins_of_32_pixels(gsc_mod):
+    import torch
+    ctx = gsc_mod.Context(bin_size=32)
+    scenes = segment_scenes()
+    targets = [oracle.make_targets(sc) for sc in scenes]
+    plan, table, tens, cams, y = make_plan(gsc_mod, ctx, scenes, targets)
+    coeffs, status = plan.run(y, list(scenes[0].lam))
+    torch.cuda.synchronize()
+    check_scenes(scenes, targets, table, coeffs.cpu().numpy(), status.cpu().numpy(), "batched bin32")

@@ -166,3 +166,42 @@ def test_relight_full_size(ctx):
     sc = syn.make_relight()
     y = oracle.make_targets(sc)
     _case(ctx, sc, y, "relight full 100k L3 50x512^2")
+
+
+@pytest.fixture(scope="module")
+def ctx32(gsc_mod):
+    return gsc_mod.Context(bin_size=32)
+
+
+@pytest.mark.parametrize("case", ["plain", "relight", "ragged", "features", "segment"])
+def test_bins_of_32_pixels(ctx32, case):
+    """The same workloads binned at 32x32 pixels (four wave tiles per bin):
+    the result does not depend on the binning."""
+    if case == "plain":
+        sc = syn.make_plain()
+    elif case == "relight":
+        sc = syn.make_relight(n=20000, n_cams=8, res=200)
+    elif case == "ragged":
+        sc = syn.make_relight(n=4000, n_cams=6, res=64, sh_deg=2)
+        sc.cams = syn.hemisphere_cams(6, 3.0, 200, 120)
+    elif case == "features":
+        sc = syn.make_features(n=20000, n_cams=6, width=240, height=136, C=64)
+    else:
+        sc = syn.make_segment_scene(0, n_override=8000, cams_override=10)
+        sc.cams = syn.hemisphere_cams(10, 3.0, 170, 110)
+    y = oracle.make_targets(sc)
+    _case(ctx32, sc, y, f"bin32 {case}")
+
+
+def test_render_bins_of_32_pixels(ctx32, gsc_mod):
+    import torch
+    sc = syn.make_relight(n=20000, n_cams=6, res=176)
+    coeffs = sc.gt[0]
+    m, s, q, o = gsc_mod.scene_tensors(sc)
+    img = ctx32.render(m, s, q, o, sc.cams, torch.from_numpy(coeffs.astype(np.float32)).cuda())
+    torch.cuda.synchronize()
+    err = np.abs(img.cpu().numpy() - oracle.render(sc, coeffs.astype(np.float32).astype(np.float64))).max(axis=1)
+    ref_full = oracle.colorize(sc, np.zeros((sc.n_pixels, 3), np.float32))
+    bad = int((err > 1e-4).sum())
+    print(f"render bin32: max err {err.max():.2e}, pixels >1e-4: {bad}, events {ref_full['events']}", flush=True)
+    assert bad <= ref_full["events"] and np.median(err) < 1e-6
