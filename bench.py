@@ -121,7 +121,7 @@ def run_single(args, gsc, sc, targets, label, dtype):
     launches = max(1, int(st.stage_launches[5]) // args.steps)
     config = {"workload": label, "contributions_per_step": contrib,
               "scenes_per_sec": args.steps / elapsed, "tile_pairs_per_step": int(st.pairs),
-              "stage_ms_per_step": stages}
+              "bin_size": int(st.bin_size), "stage_ms_per_step": stages}
     return line(args, contrib * args.steps / elapsed, 1e3 * elapsed / args.steps, dtype, config,
                 roofline(sc.C, contrib, stages["blend"], launches))
 
@@ -208,7 +208,8 @@ def workload_batched(args, gsc):
                           f"C={C}, BF16 targets, one plan replayed as a graph",
               "contributions_per_step": contrib, "scenes_per_sec": n_scenes * args.steps / elapsed,
               "pixels": r0, "tile_pairs_per_step": int(info.pair_capacity),
-              "view_batches": int(info.batches), "autotune_accumulate_ms": tuned,
+              "view_batches": int(info.batches), "bin_size": int(info.bin_size),
+              "autotune_accumulate_ms": tuned,
               "accumulate_variant": variant}
     out = line(args, contrib * args.steps / elapsed, 1e3 * elapsed / args.steps, "bf16", config,
                roofline(C, contrib, acc_ms, launches))

@@ -130,6 +130,7 @@ typedef struct {
     uint64_t items;         /* (view, Gaussian) projections of the last call */
     uint32_t view_batches;  /* view batches the last call was split into */
     uint32_t ill_conditioned; /* Gaussians flagged GSC_G_ILL_COND by the last colorize */
+    uint32_t bin_size;      /* screen bin size used by the last call (16 or 32 pixels) */
     /* GSC_FLAG_PROFILE: device time and kernel launches per stage, summed over
      * every call since the previous gsc_get_stats (up to 8192 stage records). */
     float stage_ms[GSC_N_STAGES];
@@ -274,6 +275,7 @@ typedef struct {
     uint32_t ill_conditioned;   /* Gaussians flagged GSC_G_ILL_COND by the last run */
     uint32_t batches;           /* view batches per run */
     uint32_t views;             /* views per run */
+    int32_t bin_size;           /* screen bin size of the plan (16 or 32 pixels) */
     int32_t accumulate_variant; /* accumulate launch shape in use: channels per launch,
                                    plus 256 for the persistent work-queue launch */
     int32_t tuned_variant[8];   /* shapes timed by gsc_plan_autotune (0: unused) */

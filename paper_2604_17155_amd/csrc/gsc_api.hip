@@ -143,8 +143,7 @@ struct StageTimer {
 // misc buffer layout (device): [0] u64 contributions, [8] u32 pair total, [12] u32 ill count,
 // [16] u64 pair total (overflow check)
 namespace {
-constexpr size_t kMiscBytes = 64;
-constexpr int kDefaultBin = 16;
+constexpr size_t kMiscBytes = 64;  // [32..63]: geometry statistics (4 doubles)
 // bin_views result asking the caller to retry with fewer views per batch
 constexpr gsc_status kSplit = (gsc_status)1;
 
@@ -161,8 +160,30 @@ gsc_status validate_options(const gsc_options* o) {
     return GSC_OK;
 }
 
-// Bin size for a call: the option, or the automatic choice.
-int resolve_bin(const gsc_options& o) { return o.bin_size ? o.bin_size : kDefaultBin; }
+// Automatic bin size.  32-pixel bins cut the (bin, Gaussian) pairs to sort
+// by ~2.5x once footprints span several 16-pixel tiles, at the price of a
+// coarser band cull in the blend; 16-pixel bins win for small footprints.
+// The estimate of the footprint diameter is 6 sigma with sigma the mean axis
+// scale projected at the distance from each camera to the centroid.
+constexpr double kBin32Diameter = 24.0;  // pixels
+
+int choose_bin(const double* stats /* host: sum scale, sum means */, int64_t N,
+               const gsc_camera* cams, int n_cams) {
+    if (N <= 0 || n_cams <= 0) return 16;
+    const double sbar = stats[0] / (double)N;
+    const double cx = stats[1] / N, cy = stats[2] / N, cz = stats[3] / N;
+    double acc = 0.0;
+    int n = 0;
+    for (int j = 0; j < n_cams; ++j) {
+        const gsc_camera& c = cams[j];
+        // camera-space depth of the centroid
+        const double z = c.R[6] * cx + c.R[7] * cy + c.R[8] * cz + c.t[2];
+        if (!(z > 1e-6)) continue;
+        acc += 6.0 * sbar * 0.5 * ((double)c.fx + (double)c.fy) / z;
+        ++n;
+    }
+    return (n > 0 && acc / n > kBin32Diameter) ? 32 : 16;
+}
 
 gsc_status validate_geometry(const float* means, const float* scales, const float* quats,
                              const float* opac, int64_t N, const gsc_camera* cams, int32_t n_cams,
@@ -393,11 +414,22 @@ gsc_status for_view_batches(gsc_ctx* ctx, const std::vector<ViewInfo>& all, int 
     return GSC_OK;
 }
 
-gsc_status ensure_common(gsc_ctx* ctx, const float* scales, const float* quats, int64_t N,
+gsc_status ensure_common(gsc_ctx* ctx, const float* means, const float* scales,
+                         const float* quats, int64_t N, const gsc_camera* cams, int n_cams,
                          hipStream_t s) {
-    ctx->bin = resolve_bin(ctx->opt);
     GSC_HIP(ctx->misc.ensure(kMiscBytes));
     if (!ctx->h_total) GSC_HIP(hipHostMalloc((void**)&ctx->h_total, 64));
+    ctx->bin = ctx->opt.bin_size;
+    if (ctx->bin == 0) {
+        double* d_stats = reinterpret_cast<double*>(ctx->misc.as<char>() + 32);
+        launch_geometry_stats(means, scales, N, d_stats, s);
+        GSC_LAUNCHED("geometry stats");
+        GSC_HIP(hipMemcpyAsync(ctx->h_total, d_stats, 32, hipMemcpyDeviceToHost, s));
+        GSC_HIP(hipStreamSynchronize(s));
+        double st[4];
+        memcpy(st, ctx->h_total, sizeof(st));
+        ctx->bin = choose_bin(st, N, cams, n_cams);
+    }
     GSC_HIP(ctx->cov.ensure(sizeof(float) * 6 * (size_t)std::max<int64_t>(N, 1)));
     launch_fill_u32(ctx->misc.as<uint32_t>(), 0u, kMiscBytes / 4, s);
     launch_cov3d(scales, quats, ctx->cov.as<float>(), N, s);
@@ -468,7 +500,7 @@ struct gsc_plan {
 namespace {
 // plan misc layout (device): [0] u64 contributions, [8] u32 live pair count of
 // the current batch, [12] u32 dropped-pair events, [16] u32 ill-conditioned
-// count, [24] u64 pair total (plan creation)
+// count, [24] u64 pair total (plan creation), [32..63] geometry statistics
 constexpr size_t kPlanMiscBytes = 64;
 
 gsc_status validate_cameras(const gsc_camera* cams, int32_t n_cams) {
@@ -682,7 +714,7 @@ gsc_status gsc_colorize_ex(gsc_ctx* ctx, const float* means, const float* scales
     float* x_vis = extras ? extras->visibility : nullptr;
     uint32_t* x_cnt = extras ? extras->counts : nullptr;
     BlendParams bp = blend_params(ctx->opt);
-    if ((st = ensure_common(ctx, scales, quats, N, s)) != GSC_OK) return st;
+    if ((st = ensure_common(ctx, means, scales, quats, N, cams, n_cams, s)) != GSC_OK) return st;
     std::vector<ViewInfo> all(n_cams);
     for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j], j, N, ctx->bin);
     const bool per_view = sh_deg > 0 || x_sums != nullptr;
@@ -747,7 +779,7 @@ gsc_status gsc_render(gsc_ctx* ctx, const float* means, const float* scales, con
     memset(&ctx->stats, 0, sizeof(ctx->stats));
     if (n_cams == 0) return GSC_OK;
     BlendParams bp = blend_params(ctx->opt);
-    if ((st = ensure_common(ctx, scales, quats, N, s)) != GSC_OK) return st;
+    if ((st = ensure_common(ctx, means, scales, quats, N, cams, n_cams, s)) != GSC_OK) return st;
     std::vector<ViewInfo> all(n_cams);
     for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j], j, N, ctx->bin);
     unsigned long long* d_counter = reinterpret_cast<unsigned long long*>(ctx->misc.p);
@@ -795,7 +827,7 @@ gsc_status gsc_colorize_backward(gsc_ctx* ctx, const float* means, const float* 
     if (N == 0 || n_cams == 0 || (!grad_targets && !grad_opacities)) return GSC_OK;
     const int nb = (sh_deg + 1) * (sh_deg + 1);
     BlendParams bp = blend_params(ctx->opt);
-    if ((st = ensure_common(ctx, scales, quats, N, s)) != GSC_OK) return st;
+    if ((st = ensure_common(ctx, means, scales, quats, N, cams, n_cams, s)) != GSC_OK) return st;
     std::vector<ViewInfo> all(n_cams);
     for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j], j, N, ctx->bin);
     // 1. visibilities V_gj (the normal matrices depend on the weights only)
@@ -880,7 +912,7 @@ gsc_status gsc_render_backward(gsc_ctx* ctx, const float* means, const float* sc
     if (grad_opacities && N > 0) launch_fill_u32((uint32_t*)grad_opacities, 0u, (uint64_t)N, s);
     if (N == 0 || n_cams == 0 || (!grad_coeffs && !grad_opacities)) return GSC_OK;
     BlendParams bp = blend_params(ctx->opt);
-    if ((st = ensure_common(ctx, scales, quats, N, s)) != GSC_OK) return st;
+    if ((st = ensure_common(ctx, means, scales, quats, N, cams, n_cams, s)) != GSC_OK) return st;
     std::vector<ViewInfo> all(n_cams);
     for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j], j, N, ctx->bin);
     const bool per_view = sh_deg > 0;
@@ -966,7 +998,17 @@ gsc_status gsc_plan_create(gsc_ctx* ctx, const gsc_scene* scenes, int32_t n_scen
     hipStream_t s = (hipStream_t)stream;
     P->ctx = ctx;
     P->bp = blend_params(ctx->opt);
-    P->bin = resolve_bin(ctx->opt);
+    P->bin = ctx->opt.bin_size;
+    GSC_HIP(P->misc.ensure(kPlanMiscBytes));
+    if (P->bin == 0) {
+        double* d_stats = reinterpret_cast<double*>(P->misc.as<char>() + 32);
+        launch_geometry_stats(means, scales, n_total, d_stats, s);
+        GSC_LAUNCHED("geometry stats");
+        double st[4] = {0.0, 0.0, 0.0, 0.0};
+        GSC_HIP(hipMemcpyAsync(st, d_stats, sizeof(st), hipMemcpyDeviceToHost, s));
+        GSC_HIP(hipStreamSynchronize(s));
+        P->bin = choose_bin(st, n_total, cams, n_cams);
+    }
     P->scenes.assign(scenes, scenes + n_scenes);
     P->means = means; P->scales = scales; P->quats = quats; P->opac = opacities;
     P->n_total = n_total;
@@ -1171,6 +1213,7 @@ gsc_status gsc_plan_get_info(gsc_plan* plan, gsc_plan_info* out) {
     out->views = (uint32_t)plan->views.size();
     out->items = plan->items_total;
     out->pair_capacity = plan->pairs_total;
+    out->bin_size = plan->bin;
     out->accumulate_variant = (plan->acc_chunk ? plan->acc_chunk : accumulate_chunk(plan->C)) |
                               (plan->acc_persistent ? 256 : 0);
     for (int i = 0; i < 8; ++i) {
@@ -1205,6 +1248,7 @@ gsc_status gsc_get_stats(gsc_ctx* ctx, gsc_stats* out) {
         ctx->marks.clear();
         ctx->ev_used = 0;
     }
+    ctx->stats.bin_size = (uint32_t)ctx->bin;
     *out = ctx->stats;
     return GSC_OK;
 }

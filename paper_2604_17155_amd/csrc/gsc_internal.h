@@ -70,6 +70,10 @@ constexpr uint32_t kItemMask = (1u << kItemBits) - 1u;
 // ---- kernels launched from gsc_api.hip ----------------------------------
 void launch_cov3d(const float* scales, const float* quats, float* cov, int64_t N, hipStream_t s);
 
+// out[0] = sum_g mean axis scale, out[1..3] = sum_g mean (device doubles).
+void launch_geometry_stats(const float* means, const float* scales, int64_t N, double* out,
+                           hipStream_t s);
+
 // One thread per batch item (n_items = sum of n_gauss over the batch's views).
 // rec2[i]: first | last << 16, the pixel rows of the item's footprint.
 void launch_project(const ViewInfo* views, int n_views, uint32_t n_items, const float* means,

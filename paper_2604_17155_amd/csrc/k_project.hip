@@ -4,6 +4,8 @@
 // "Differentiable renderer"): Sigma = R(q) diag(s^2) R(q)^T, EWA projection
 // Sigma_2D = J W Sigma W^T J^T + dilation*I, a 3-sigma footprint, and the
 // front-to-back order of eq. 2 keyed on the camera-space depth of the mean.
+#include <algorithm>
+
 #include "gsc_internal.h"
 
 namespace gsc {
@@ -34,6 +36,37 @@ void launch_cov3d(const float* scales, const float* quats, float* cov, int64_t N
     if (N <= 0) return;
     hipLaunchKernelGGL(k_cov3d, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, scales, quats,
                        cov, N);
+}
+
+// Sums over the Gaussians of the mean axis scale and of the mean position
+// (out: 4 doubles, zeroed by the caller), for the automatic bin size.
+__global__ __launch_bounds__(256) void k_geometry_stats(const float* __restrict__ means,
+                                                        const float* __restrict__ scales, int64_t N,
+                                                        double* __restrict__ out) {
+    __shared__ double part[4][4];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < N;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        acc[0] += (double)(scales[3 * g] + scales[3 * g + 1] + scales[3 * g + 2]) * (1.0 / 3.0);
+        for (int k = 0; k < 3; ++k) acc[1 + k] += (double)means[3 * g + k];
+    }
+    for (int k = 0; k < 4; ++k)
+        for (int d = 32; d >= 1; d >>= 1) acc[k] += __shfl_xor(acc[k], d, 64);
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < 4; ++k) part[threadIdx.x >> 6][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int k = threadIdx.x;
+        unsafeAtomicAdd(out + k, part[0][k] + part[1][k] + part[2][k] + part[3][k]);
+    }
+}
+
+void launch_geometry_stats(const float* means, const float* scales, int64_t N, double* out,
+                           hipStream_t s) {
+    launch_fill_u32(reinterpret_cast<uint32_t*>(out), 0u, 8, s);
+    if (N <= 0) return;
+    const int64_t blocks = std::min<int64_t>((N + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_geometry_stats, dim3((unsigned)blocks), dim3(256), 0, s, means, scales, N, out);
 }
 
 // Largest q at which a pixel can still pass both the footprint test

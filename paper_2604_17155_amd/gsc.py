@@ -49,6 +49,7 @@ STAGES = ["project", "depth_sort", "scan", "emit", "tile_sort", "blend", "solve"
 class GscStats(ct.Structure):
     _fields_ = [("contributions", ct.c_uint64), ("pairs", ct.c_uint64), ("items", ct.c_uint64),
                 ("view_batches", ct.c_uint32), ("ill_conditioned", ct.c_uint32),
+                ("bin_size", ct.c_uint32),
                 ("stage_ms", ct.c_float * 8), ("stage_launches", ct.c_uint32 * 8)]
 
     def stage_dict(self):
@@ -68,7 +69,7 @@ class GscPlanInfo(ct.Structure):
     _fields_ = [("contributions", ct.c_uint64), ("items", ct.c_uint64),
                 ("pair_capacity", ct.c_uint64), ("dropped_pairs", ct.c_uint32),
                 ("ill_conditioned", ct.c_uint32), ("batches", ct.c_uint32), ("views", ct.c_uint32),
-                ("accumulate_variant", ct.c_int32), ("tuned_variant", ct.c_int32 * 8),
+                ("bin_size", ct.c_int32), ("accumulate_variant", ct.c_int32), ("tuned_variant", ct.c_int32 * 8),
                 ("tuned_ms", ct.c_float * 8)]
 
 
