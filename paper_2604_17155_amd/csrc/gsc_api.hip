@@ -79,7 +79,7 @@ struct gsc_ctx {
     gsc_options opt;
     int bin = 16;  // bin size of the current call
     // device scratch
-    DevBuf views, views_all, cov, keys, vals, keys_alt, vals_alt, counts, counts_sorted, offsets, rec0, rec1, rec2,
+    DevBuf views, views_all, cov, keys, vals, keys_alt, vals_alt, counts, offsets, rec0, rec1, rec2,
         sort_scratch, pkeys, pvals, pkeys_alt, pvals_alt, ranges, vs, gamma, bbar, misc;
     // host staging
     ViewInfo* h_views = nullptr;  // staging of one batch's table
@@ -95,7 +95,7 @@ struct gsc_ctx {
     struct Mark { int stage; hipEvent_t a, b; uint32_t launches; };
     std::vector<Mark> marks;
     ~gsc_ctx() {
-        DevBuf* all[] = {&views, &views_all, &cov, &keys, &vals, &keys_alt, &vals_alt, &counts, &counts_sorted,
+        DevBuf* all[] = {&views, &views_all, &cov, &keys, &vals, &keys_alt, &vals_alt, &counts,
                          &offsets, &rec0, &rec1, &rec2, &sort_scratch, &pkeys, &pvals, &pkeys_alt,
                          &pvals_alt, &ranges, &vs, &gamma, &bbar, &misc};
         for (DevBuf* b : all) b->release();
@@ -315,19 +315,17 @@ gsc_status bin_views(gsc_ctx* ctx, const std::vector<ViewInfo>& all, int v0, int
     GSC_HIP(ctx->keys_alt.ensure(4 * items + 4));
     GSC_HIP(ctx->vals_alt.ensure(4 * items + 4));
     GSC_HIP(ctx->counts.ensure(4 * items + 4));
-    GSC_HIP(ctx->counts_sorted.ensure(4 * items + 4));
     GSC_HIP(ctx->offsets.ensure(4 * items + 4));
     GSC_HIP(ctx->rec0.ensure(16 * items + 16));
     GSC_HIP(ctx->rec1.ensure(16 * items + 16));
-    GSC_HIP(ctx->rec2.ensure(4 * items + 4));
+    GSC_HIP(ctx->rec2.ensure(8 * items + 8));
     GSC_HIP(ctx->ranges.ensure(sizeof(uint2) * (tiles + 1)));
     const ViewInfo* dviews = ctx->views.as<ViewInfo>();
     {
         StageTimer t(ctx, s, GSC_STAGE_PROJECT);
-        launch_project(dviews, nv, ni, means, ctx->cov.as<float>(), opac, bp, ctx->keys.as<uint32_t>(),
-                       ctx->vals.as<uint32_t>(), ctx->counts.as<uint32_t>(), ctx->rec0.as<float4>(),
-                       ctx->rec1.as<float4>(), ctx->rec2.as<uint32_t>(), ctx->bin, s);
-        GSC_LAUNCHED("project");
+        launch_depth_keys(dviews, nv, ni, means, opac, bp, ctx->keys.as<uint32_t>(),
+                          ctx->vals.as<uint32_t>(), s);
+        GSC_LAUNCHED("depth keys");
     }
     size_t scr = std::max(radix_scratch_words(ni), scan_scratch_words(ni));
     GSC_HIP(ctx->sort_scratch.ensure(4 * scr + 256));
@@ -337,14 +335,20 @@ gsc_status bin_views(gsc_ctx* ctx, const std::vector<ViewInfo>& all, int v0, int
                    ctx->vals_alt.as<uint32_t>(), ni, 32, ctx->sort_scratch.as<uint32_t>(), s);
         GSC_LAUNCHED("depth sort");
     }
+    {
+        // projection in depth order: records and counts land at the depth rank
+        StageTimer t(ctx, s, GSC_STAGE_PROJECT);
+        launch_project(dviews, nv, ni, ctx->vals.as<uint32_t>(), means, ctx->cov.as<float>(), opac, bp,
+                       ctx->counts.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(),
+                       ctx->rec2.as<uint2>(), ctx->bin, s);
+        GSC_LAUNCHED("project");
+    }
     StageTimer* scan_t = new StageTimer(ctx, s, GSC_STAGE_SCAN);
-    launch_gather_counts(ctx->vals.as<uint32_t>(), ctx->counts.as<uint32_t>(),
-                         ctx->counts_sorted.as<uint32_t>(), ni, s);
     uint32_t* d_total = reinterpret_cast<uint32_t*>(ctx->misc.as<char>() + 8);
     unsigned long long* d_total64 = reinterpret_cast<unsigned long long*>(ctx->misc.as<char>() + 16);
     launch_fill_u32(reinterpret_cast<uint32_t*>(d_total64), 0u, 2, s);
     launch_sum_u64(ctx->counts.as<uint32_t>(), ni, d_total64, s);
-    launch_scan(ctx->counts_sorted.as<uint32_t>(), ctx->offsets.as<uint32_t>(), ni, d_total,
+    launch_scan(ctx->counts.as<uint32_t>(), ctx->offsets.as<uint32_t>(), ni, d_total,
                 ctx->sort_scratch.as<uint32_t>(), s);
     delete scan_t;
     GSC_LAUNCHED("count scan");
@@ -487,10 +491,10 @@ struct gsc_plan {
     bool acc_persistent = false;      // persistent work-queue accumulate
     float tune_ms[8] = {};
     int tune_variant[8] = {};
-    DevBuf d_views, cov, keys, vals, keys_alt, vals_alt, counts, counts_sorted, offsets, rec0, rec1,
+    DevBuf d_views, cov, keys, vals, keys_alt, vals_alt, counts, offsets, rec0, rec1,
         rec2, sort_scratch, pkeys, pvals, pkeys_alt, pvals_alt, ranges, vs, misc, queues;
     ~gsc_plan() {
-        DevBuf* all[] = {&d_views, &cov, &keys, &vals, &keys_alt, &vals_alt, &counts, &counts_sorted,
+        DevBuf* all[] = {&d_views, &cov, &keys, &vals, &keys_alt, &vals_alt, &counts,
                          &offsets, &rec0, &rec1, &rec2, &sort_scratch, &pkeys, &pvals, &pkeys_alt,
                          &pvals_alt, &ranges, &vs, &misc, &queues};
         for (DevBuf* b : all) b->release();
@@ -511,9 +515,9 @@ gsc_status validate_cameras(const gsc_camera* cams, int32_t n_cams) {
 // Project one batch of the plan and count its tile pairs (synchronises).
 gsc_status plan_count_pairs(gsc_plan* P, const gsc_plan::Batch& b, hipStream_t s, uint64_t* pairs) {
     const ViewInfo* dv = P->d_views.as<ViewInfo>() + b.v0;
-    launch_project(dv, b.nv, b.n_items, P->means, P->cov.as<float>(), P->opac, P->bp,
-                   P->keys.as<uint32_t>(), P->vals.as<uint32_t>(), P->counts.as<uint32_t>(),
-                   P->rec0.as<float4>(), P->rec1.as<float4>(), P->rec2.as<uint32_t>(), P->bin, s);
+    launch_project(dv, b.nv, b.n_items, nullptr, P->means, P->cov.as<float>(), P->opac, P->bp,
+                   P->counts.as<uint32_t>(), P->rec0.as<float4>(), P->rec1.as<float4>(),
+                   P->rec2.as<uint2>(), P->bin, s);
     GSC_LAUNCHED("project");
     unsigned long long* d64 = reinterpret_cast<unsigned long long*>(P->misc.as<char>() + 24);
     launch_fill_u32(reinterpret_cast<uint32_t*>(d64), 0u, 2, s);
@@ -548,7 +552,7 @@ gsc_status plan_accumulate(gsc_plan* P, const gsc_plan::Batch& b, const void* ta
     const ViewInfo* dv = P->d_views.as<ViewInfo>() + b.v0;
     unsigned long long* d_counter = reinterpret_cast<unsigned long long*>(P->misc.p);
     launch_accumulate_chunked(dv, b.nv, b.n_tiles, P->ranges.as<uint2>(), P->pvals.as<uint32_t>(),
-                              P->rec0.as<float4>(), P->rec1.as<float4>(), P->rec2.as<uint32_t>(),
+                              P->rec0.as<float4>(), P->rec1.as<float4>(), P->rec2.as<uint2>(),
                               P->bin, targets, tdtype, P->C,
                               P->per_view, P->bp, P->vs.as<float>(), d_counter, nullptr, chunk, s,
                               persistent ? P->queues.as<uint32_t>() : nullptr);
@@ -564,10 +568,9 @@ gsc_status plan_bin_batch(gsc_plan* P, const gsc_plan::Batch& b, hipStream_t s) 
     uint32_t* d_drop = reinterpret_cast<uint32_t*>(P->misc.as<char>() + 12);
     {
         StageTimer t(ctx, s, GSC_STAGE_PROJECT);
-        launch_project(dv, b.nv, b.n_items, P->means, P->cov.as<float>(), P->opac, P->bp,
-                       P->keys.as<uint32_t>(), P->vals.as<uint32_t>(), P->counts.as<uint32_t>(),
-                       P->rec0.as<float4>(), P->rec1.as<float4>(), P->rec2.as<uint32_t>(), P->bin, s);
-        GSC_LAUNCHED("project");
+        launch_depth_keys(dv, b.nv, b.n_items, P->means, P->opac, P->bp, P->keys.as<uint32_t>(),
+                          P->vals.as<uint32_t>(), s);
+        GSC_LAUNCHED("depth keys");
     }
     {
         StageTimer t(ctx, s, GSC_STAGE_DEPTH_SORT);
@@ -576,10 +579,15 @@ gsc_status plan_bin_batch(gsc_plan* P, const gsc_plan::Batch& b, hipStream_t s) 
         GSC_LAUNCHED("depth sort");
     }
     {
+        StageTimer t(ctx, s, GSC_STAGE_PROJECT);
+        launch_project(dv, b.nv, b.n_items, P->vals.as<uint32_t>(), P->means, P->cov.as<float>(), P->opac,
+                       P->bp, P->counts.as<uint32_t>(), P->rec0.as<float4>(), P->rec1.as<float4>(),
+                       P->rec2.as<uint2>(), P->bin, s);
+        GSC_LAUNCHED("project");
+    }
+    {
         StageTimer t(ctx, s, GSC_STAGE_SCAN);
-        launch_gather_counts(P->vals.as<uint32_t>(), P->counts.as<uint32_t>(),
-                             P->counts_sorted.as<uint32_t>(), b.n_items, s);
-        launch_scan(P->counts_sorted.as<uint32_t>(), P->offsets.as<uint32_t>(), b.n_items, d_live,
+        launch_scan(P->counts.as<uint32_t>(), P->offsets.as<uint32_t>(), b.n_items, d_live,
                     P->sort_scratch.as<uint32_t>(), s);
         GSC_LAUNCHED("count scan");
     }
@@ -728,7 +736,7 @@ gsc_status gsc_colorize_ex(gsc_ctx* ctx, const float* means, const float* scales
         StageTimer t(ctx, s, GSC_STAGE_BLEND, (uint32_t)((C + accumulate_chunk(C) - 1) / accumulate_chunk(C)));
         (void)v0;
         launch_accumulate(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
-                          ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(), ctx->rec2.as<uint32_t>(), ctx->bin,
+                          ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(), ctx->rec2.as<uint2>(), ctx->bin,
                           targets, tdtype, C, per_view, bp, ctx->vs.as<float>(), d_counter,
                           x_cnt, s);
         GSC_LAUNCHED("accumulate");
@@ -788,11 +796,11 @@ gsc_status gsc_render(gsc_ctx* ctx, const float* means, const float* scales, con
         (void)v0;
         StageTimer t(ctx, s, GSC_STAGE_BLEND, 1 + (uint32_t)((C + 3) / 4));
         GSC_HIP(ctx->gamma.ensure(4 * (size_t)nv * (size_t)std::max<int64_t>(N, 1) * (size_t)C));
-        launch_view_colors(ctx->views.as<ViewInfo>(), nv, (uint32_t)bn.n_items, means, coeffs, C,
-                           sh_deg, ctx->gamma.as<float>(), s);
+        launch_view_colors(ctx->views.as<ViewInfo>(), nv, (uint32_t)bn.n_items, ctx->vals.as<uint32_t>(),
+                           means, coeffs, C, sh_deg, ctx->gamma.as<float>(), s);
         GSC_LAUNCHED("view colors");
         launch_render(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
-                      ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(), ctx->rec2.as<uint32_t>(), ctx->bin,
+                      ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(), ctx->rec2.as<uint2>(), ctx->bin,
                       ctx->gamma.as<float>(), C, bp, images, d_counter, s);
         GSC_LAUNCHED("render");
         return GSC_OK;
@@ -843,7 +851,7 @@ gsc_status gsc_colorize_backward(gsc_ctx* ctx, const float* means, const float* 
         (void)v0;
         launch_accumulate_weights(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
                                   ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(),
-                                  ctx->rec1.as<float4>(), ctx->rec2.as<uint32_t>(), ctx->bin, per_view, bp, ctx->vs.as<float>(),
+                                  ctx->rec1.as<float4>(), ctx->rec2.as<uint2>(), ctx->bin, per_view, bp, ctx->vs.as<float>(),
                                   d_counter, s);
         GSC_LAUNCHED("accumulate weights");
         last = bn;
@@ -869,11 +877,11 @@ gsc_status gsc_colorize_backward(gsc_ctx* ctx, const float* means, const float* 
         (void)v0;
         GSC_HIP(ctx->gamma.ensure(4 * (size_t)nv * (size_t)N * (size_t)(C + 1)));
         StageTimer t(ctx, s, GSC_STAGE_BLEND_ADJOINT);
-        launch_view_adjoint(ctx->views.as<ViewInfo>(), nv, (uint32_t)bn.n_items, means, coeffs, d_bbar,
-                            d_rho, C, sh_deg, false, ctx->gamma.as<float>(), s);
+        launch_view_adjoint(ctx->views.as<ViewInfo>(), nv, (uint32_t)bn.n_items, ctx->vals.as<uint32_t>(),
+                            means, coeffs, d_bbar, d_rho, C, sh_deg, false, ctx->gamma.as<float>(), s);
         GSC_LAUNCHED("view adjoint");
         launch_blend_adjoint(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
-                             ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(), ctx->rec2.as<uint32_t>(), ctx->bin,
+                             ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(), ctx->rec2.as<uint2>(), ctx->bin,
                              targets, tdtype, C, ctx->gamma.as<float>(), bp, grad_targets,
                              grad_opacities, s);
         GSC_LAUNCHED("blend adjoint");
@@ -930,7 +938,7 @@ gsc_status gsc_render_backward(gsc_ctx* ctx, const float* means, const float* sc
             StageTimer t(ctx, s, GSC_STAGE_BLEND);
             (void)v0;
             launch_accumulate(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
-                              ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(), ctx->rec2.as<uint32_t>(), ctx->bin,
+                              ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(), ctx->rec2.as<uint2>(), ctx->bin,
                               grad_images, GSC_F32, C, per_view, bp, ctx->vs.as<float>(),
                               d_counter, nullptr, s);
             GSC_LAUNCHED("accumulate");
@@ -938,12 +946,13 @@ gsc_status gsc_render_backward(gsc_ctx* ctx, const float* means, const float* sc
         if (grad_opacities) {
             GSC_HIP(ctx->gamma.ensure(4 * (size_t)nv * (size_t)N * (size_t)(C + 1)));
             StageTimer t(ctx, s, GSC_STAGE_BLEND_ADJOINT);
-            launch_view_adjoint(ctx->views.as<ViewInfo>(), nv, (uint32_t)bn.n_items, means, coeffs,
-                                nullptr, nullptr, C, sh_deg, true, ctx->gamma.as<float>(), s);
+            launch_view_adjoint(ctx->views.as<ViewInfo>(), nv, (uint32_t)bn.n_items,
+                                ctx->vals.as<uint32_t>(), means, coeffs, nullptr, nullptr, C, sh_deg,
+                                true, ctx->gamma.as<float>(), s);
             GSC_LAUNCHED("view colours");
             launch_blend_adjoint(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
                                  ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(),
-                                 ctx->rec1.as<float4>(), ctx->rec2.as<uint32_t>(), ctx->bin, grad_images, GSC_F32, C,
+                                 ctx->rec1.as<float4>(), ctx->rec2.as<uint2>(), ctx->bin, grad_images, GSC_F32, C,
                                  ctx->gamma.as<float>(), bp, nullptr, grad_opacities, s);
             GSC_LAUNCHED("blend adjoint");
         }
@@ -1060,11 +1069,10 @@ gsc_status gsc_plan_create(gsc_ctx* ctx, const gsc_scene* scenes, int32_t n_scen
     GSC_HIP(P->keys_alt.ensure(4 * mi + 4));
     GSC_HIP(P->vals_alt.ensure(4 * mi + 4));
     GSC_HIP(P->counts.ensure(4 * mi + 4));
-    GSC_HIP(P->counts_sorted.ensure(4 * mi + 4));
     GSC_HIP(P->offsets.ensure(4 * mi + 4));
     GSC_HIP(P->rec0.ensure(16 * mi + 16));
     GSC_HIP(P->rec1.ensure(16 * mi + 16));
-    GSC_HIP(P->rec2.ensure(4 * mi + 4));
+    GSC_HIP(P->rec2.ensure(8 * mi + 8));
     GSC_HIP(P->d_views.ensure(sizeof(ViewInfo) * std::max<size_t>(P->views.size(), 1)));
     if (!P->views.empty())
         GSC_HIP(hipMemcpyAsync(P->d_views.p, P->views.data(), sizeof(ViewInfo) * P->views.size(),

@@ -74,16 +74,21 @@ void launch_cov3d(const float* scales, const float* quats, float* cov, int64_t N
 void launch_geometry_stats(const float* means, const float* scales, int64_t N, double* out,
                            hipStream_t s);
 
-// One thread per batch item (n_items = sum of n_gauss over the batch's views).
-// rec2[i]: first | last << 16, the pixel rows of the item's footprint.
-void launch_project(const ViewInfo* views, int n_views, uint32_t n_items, const float* means,
-                    const float* cov, const float* opac, BlendParams bp, uint32_t* keys,
-                    uint32_t* vals, uint32_t* counts, float4* rec0, float4* rec1, uint32_t* rec2,
-                    int bin, hipStream_t s);
+// Depth keys of the batch items (n_items = sum of n_gauss over the batch's
+// views): keys[i] = binary32 depth bits or 0xFFFFFFFF (culled), vals[i] = i.
+void launch_depth_keys(const ViewInfo* views, int n_views, uint32_t n_items, const float* means,
+                       const float* opac, BlendParams bp, uint32_t* keys, uint32_t* vals,
+                       hipStream_t s);
 
-void launch_gather_counts(const uint32_t* sorted_vals, const uint32_t* counts, uint32_t* out,
-                          uint32_t n, hipStream_t s);
+// Projection in depth order: position k handles item i = order[k] (k if order
+// is null) and writes counts[k], rec0/rec1[k] and rec2[k] = (first | last << 16,
+// i): the pixel rows of the footprint and the item.
+void launch_project(const ViewInfo* views, int n_views, uint32_t n_items, const uint32_t* order,
+                    const float* means, const float* cov, const float* opac, BlendParams bp,
+                    uint32_t* counts, float4* rec0, float4* rec1, uint2* rec2, int bin,
+                    hipStream_t s);
 
+// Pairs of the depth-ordered records: pair values carry the depth rank k.
 // Pairs at offsets >= cap are dropped and counted in *overflow (if given).
 void launch_emit(const ViewInfo* views, int n_views, const uint32_t* sorted_vals,
                  const uint32_t* offsets, const uint32_t* counts, const float4* rec0,
@@ -122,7 +127,7 @@ int accumulate_chunk(int C);
 // Accumulate V_gj and S_gj into slot (view.vs_base + g) when per_view, else
 // into slot (view.g_offset + g), summed over views; slots hold C+1 floats.
 void launch_accumulate(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
-                       const uint32_t* pair_vals, const float4* rec0, const float4* rec1, const uint32_t* rec2, int bin,
+                       const uint32_t* pair_vals, const float4* rec0, const float4* rec1, const uint2* rec2, int bin,
                        const void* targets, int tdtype, int C, bool per_view, BlendParams bp,
                        float* VS, unsigned long long* counter, uint32_t* gcount, hipStream_t s);
 
@@ -135,17 +140,19 @@ constexpr uint32_t kPersistentBlocks = 2048;  // 8 blocks of 4 waves per CU
 bool accumulate_chunk_valid(int chunk);
 void launch_accumulate_chunked(const ViewInfo* views, int n_views, uint32_t n_tiles,
                                const uint2* ranges, const uint32_t* pair_vals, const float4* rec0,
-                               const float4* rec1, const uint32_t* rec2, int bin, const void* targets, int tdtype, int C,
+                               const float4* rec1, const uint2* rec2, int bin, const void* targets, int tdtype, int C,
                                bool per_view, BlendParams bp, float* VS,
                                unsigned long long* counter, uint32_t* gcount, int chunk,
                                hipStream_t s, uint32_t* queues = nullptr);
 
-// Per item colour gamma[item][c] = sum_m coeffs[g][m][c] phi_m(dir_gv).
-void launch_view_colors(const ViewInfo* views, int n_views, uint32_t n_items, const float* means,
-                        const float* coeffs, int C, int sh_deg, float* gamma, hipStream_t s);
+// Colour of the item of depth rank k (item order[k]):
+// gamma[k][c] = sum_m coeffs[g][m][c] phi_m(dir_gv).
+void launch_view_colors(const ViewInfo* views, int n_views, uint32_t n_items, const uint32_t* order,
+                        const float* means, const float* coeffs, int C, int sh_deg, float* gamma,
+                        hipStream_t s);
 
 void launch_render(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
-                   const uint32_t* pair_vals, const float4* rec0, const float4* rec1, const uint32_t* rec2, int bin,
+                   const uint32_t* pair_vals, const float4* rec0, const float4* rec1, const uint2* rec2, int bin,
                    const float* gamma, int C, BlendParams bp, float* images,
                    unsigned long long* counter, hipStream_t s);
 
@@ -161,7 +168,7 @@ void launch_fold_solve(const ViewInfo* views, int n_views, const float* means, c
 // Weights-only accumulate: V[slot] += sum_p w (stride 1; slots as in launch_accumulate).
 void launch_accumulate_weights(const ViewInfo* views, int n_views, uint32_t n_tiles,
                                const uint2* ranges, const uint32_t* pair_vals, const float4* rec0,
-                               const float4* rec1, const uint32_t* rec2, int bin, bool per_view, BlendParams bp, float* V,
+                               const float4* rec1, const uint2* rec2, int bin, bool per_view, BlendParams bp, float* V,
                                unsigned long long* counter, hipStream_t s);
 
 // Adjoint solve: bbar = (A_g + w_g Lambda)^{-1} grad_coeffs and
@@ -173,17 +180,18 @@ void launch_adjoint_solve(const ViewInfo* views, int n_views, const float* means
                           const float* grad_coeffs, const float* coeffs, float* bbar, float* rho,
                           float* w_scratch, hipStream_t s);
 
-// Per item adjoint colours: beta [item][C+1] = (beta_gj, delta_gj).
+// Adjoint colours of the item of depth rank k: beta [k][C+1] = (beta_gj, delta_gj).
 // render: beta = c^T phi, delta = 0.  Otherwise beta = bbar^T phi and
 // delta = beta^T (c^T phi) + rho_g.
-void launch_view_adjoint(const ViewInfo* views, int n_views, uint32_t n_items, const float* means,
-                         const float* coeffs, const float* bbar, const float* rho, int C,
-                         int sh_deg, bool render, float* beta, hipStream_t s);
+void launch_view_adjoint(const ViewInfo* views, int n_views, uint32_t n_items, const uint32_t* order,
+                         const float* means, const float* coeffs, const float* bbar,
+                         const float* rho, int C, int sh_deg, bool render, float* beta,
+                         hipStream_t s);
 
 // Blend adjoint over the binned tiles: grad_y[row][c] = sum_g w beta (every
 // pixel of every view written, if grad_y) and grad_o[g] += dL/do (atomics, if grad_o).
 void launch_blend_adjoint(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
-                          const uint32_t* pair_vals, const float4* rec0, const float4* rec1, const uint32_t* rec2, int bin,
+                          const uint32_t* pair_vals, const float4* rec0, const float4* rec1, const uint2* rec2, int bin,
                           const void* ypix, int ydtype, int C, const float* beta, BlendParams bp,
                           float* grad_y, float* grad_o, hipStream_t s);
 

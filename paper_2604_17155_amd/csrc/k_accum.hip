@@ -30,8 +30,9 @@ __device__ __forceinline__ uint32_t accumulate_tile(
     uint32_t tile, uint32_t lane, const ViewInfo* __restrict__ views, int n_views,
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_vals,
     const float4* __restrict__ rec0, const float4* __restrict__ rec1,
-    const uint32_t* __restrict__ rec2, const void* __restrict__ targets, int C, int c_off,
-    int per_view, const BlendParams& bp, float* __restrict__ VS, uint32_t* __restrict__ gcount) {
+    const uint2* __restrict__ rec2,
+    const void* __restrict__ targets, int C, int c_off, int per_view, const BlendParams& bp,
+    float* __restrict__ VS, uint32_t* __restrict__ gcount) {
     constexpr int CCA = CC > 0 ? CC : 1;
     const TileGeom tg = tile_geom<BIN>(tile, views, n_views);
     const ViewInfo& V = views[tg.vloc];
@@ -76,20 +77,19 @@ __device__ __forceinline__ uint32_t accumulate_tile(
         // records are fetched with uniform addresses one entry ahead
         uint32_t pn = bcast_u(pv, 0);
         float4 n0 = rec0[pn & kItemMask], n1 = rec1[pn & kItemMask];
-        uint32_t n2 = BIN == 32 ? rec2[pn & kItemMask] : 0u;
+        uint2 n2 = rec2[pn & kItemMask];
         for (uint32_t j = 0; j < nb; ++j) {
             const uint32_t pc = pn;
             const float4 c0 = n0, c1 = n1;
-            const uint32_t e2 = n2;
+            const uint2 e2 = n2;
             if (j + 1 < nb) {
                 pn = bcast_u(pv, j + 1);
                 n0 = rec0[pn & kItemMask];
                 n1 = rec1[pn & kItemMask];
-                if constexpr (BIN == 32) n2 = rec2[pn & kItemMask];
+                n2 = rec2[pn & kItemMask];
             }
-            const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2, tg.y0) & alive;
+            const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2.x, tg.y0) & alive;
             if (bands == 0u) continue;
-            const int64_t g = (int64_t)(pc & kItemMask) - item_base;
             const float dx = (px - c0.x) - c0.z;
             const float a0 = c1.x * dx * dx;
             const float b0 = c1.y * dx;
@@ -122,6 +122,8 @@ __device__ __forceinline__ uint32_t accumulate_tile(
             nh = (uint32_t)__builtin_amdgcn_readfirstlane((int)nh);
             cnt += nh;
             if (nh != 0u) {
+                // the pair carries the depth rank; the record names the item
+                const int64_t g = (int64_t)e2.y - item_base;
                 if (gcount != nullptr && first_chunk && lane == 0) atomicAdd(gcount + V.g_offset + g, nh);
                 float* slot = VS + (slot_base + g) * (int64_t)stride;
                 if constexpr (CC == 0) {
@@ -162,9 +164,9 @@ __device__ __forceinline__ uint32_t accumulate_tile(
 template <int CC, bool BF16, int BIN>
 __global__ __launch_bounds__(256) void k_accumulate(
     const ViewInfo* __restrict__ views, int n_views, uint32_t n_tiles, const uint2* __restrict__ ranges,
-    const uint32_t* __restrict__ pair_vals, const float4* __restrict__ rec0,
-    const float4* __restrict__ rec1, const uint32_t* __restrict__ rec2,
-    const void* __restrict__ targets, int C, int c_off,
+    const uint32_t* __restrict__ pair_vals,
+    const float4* __restrict__ rec0, const float4* __restrict__ rec1,
+    const uint2* __restrict__ rec2, const void* __restrict__ targets, int C, int c_off,
     int per_view, BlendParams bp, float* __restrict__ VS,
     unsigned long long* __restrict__ counter, uint32_t* __restrict__ gcount,
     uint32_t* __restrict__ queue) {
@@ -173,17 +175,18 @@ __global__ __launch_bounds__(256) void k_accumulate(
     if (queue == nullptr) {
         const uint32_t tile = blockIdx.x * 4 + (threadIdx.x >> 6);
         if (tile >= n_tiles) return;  // whole wave
-        cnt = accumulate_tile<CC, BF16, BIN>(tile, lane, views, n_views, ranges, pair_vals, rec0,
-                                             rec1, rec2, targets, C, c_off, per_view, bp, VS, gcount);
+        cnt = accumulate_tile<CC, BF16, BIN>(tile, lane, views, n_views, ranges, pair_vals,
+                                             rec0, rec1, rec2, targets, C, c_off, per_view, bp, VS,
+                                             gcount);
     } else {
         for (;;) {
             uint32_t t = 0;
             if (lane == 0) t = atomicAdd(queue, 1u);
             const uint32_t tile = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
             if (tile >= n_tiles) break;  // uniform: every wave ends here
-            cnt += accumulate_tile<CC, BF16, BIN>(tile, lane, views, n_views, ranges, pair_vals, rec0,
-                                                  rec1, rec2, targets, C, c_off, per_view, bp, VS,
-                                                  gcount);
+            cnt += accumulate_tile<CC, BF16, BIN>(tile, lane, views, n_views, ranges, pair_vals,
+                                                  rec0, rec1, rec2, targets, C, c_off,
+                                                  per_view, bp, VS, gcount);
         }
     }
     if (c_off == 0 && lane == 0 && cnt) atomicAdd(counter, (unsigned long long)cnt);
@@ -194,8 +197,9 @@ static inline uint32_t wave_tiles(uint32_t n_bins, int bin) { return bin == 32 ?
 
 template <int CC, bool BF16, int BIN>
 static void launch_acc_k(const ViewInfo* views, int n_views, uint32_t n_wt, const uint2* ranges,
-                         const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
-                         const uint32_t* rec2, const void* targets, int C, bool per_view,
+                         const uint32_t* pair_vals, const float4* rec0,
+                         const float4* rec1,
+                         const uint2* rec2, const void* targets, int C, bool per_view,
                          BlendParams bp, float* VS, unsigned long long* counter, uint32_t* gcount,
                          uint32_t* queues, hipStream_t s) {
     const uint32_t full = (n_wt + 3) / 4;
@@ -205,15 +209,16 @@ static void launch_acc_k(const ViewInfo* views, int n_views, uint32_t n_wt, cons
     for (int c_off = 0; c_off < std::max(C, 1); c_off += step, ++pass) {
         uint32_t* q = queues ? queues + pass : nullptr;
         hipLaunchKernelGGL((k_accumulate<CC, BF16, BIN>), grid, block, 0, s, views, n_views, n_wt,
-                           ranges, pair_vals, rec0, rec1, rec2, targets, C, c_off, (int)per_view, bp,
-                           VS, counter, gcount, q);
+                           ranges, pair_vals, rec0, rec1, rec2, targets, C, c_off,
+                           (int)per_view, bp, VS, counter, gcount, q);
     }
 }
 
 template <int CC>
 static void launch_acc_cc(const ViewInfo* views, int n_views, uint32_t n_bins, const uint2* ranges,
-                          const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
-                          const uint32_t* rec2, int bin, const void* targets, int tdtype, int C,
+                          const uint32_t* pair_vals, const float4* rec0,
+                          const float4* rec1,
+                          const uint2* rec2, int bin, const void* targets, int tdtype, int C,
                           bool per_view, BlendParams bp, float* VS, unsigned long long* counter,
                           uint32_t* gcount, uint32_t* queues, hipStream_t s) {
     const uint32_t n_wt = wave_tiles(n_bins, bin);
@@ -236,8 +241,9 @@ bool accumulate_chunk_valid(int chunk) {
 }
 
 void launch_accumulate(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
-                       const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
-                       const uint32_t* rec2, int bin, const void* targets, int tdtype, int C,
+                       const uint32_t* pair_vals, const float4* rec0,
+                       const float4* rec1,
+                       const uint2* rec2, int bin, const void* targets, int tdtype, int C,
                        bool per_view, BlendParams bp, float* VS, unsigned long long* counter,
                        uint32_t* gcount, hipStream_t s) {
     launch_accumulate_chunked(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, rec2, bin,
@@ -245,8 +251,9 @@ void launch_accumulate(const ViewInfo* views, int n_views, uint32_t n_tiles, con
 }
 
 void launch_accumulate_chunked(const ViewInfo* views, int n_views, uint32_t n_tiles,
-                               const uint2* ranges, const uint32_t* pair_vals, const float4* rec0,
-                               const float4* rec1, const uint32_t* rec2, int bin,
+                               const uint2* ranges, const uint32_t* pair_vals,
+                               const float4* rec0,
+                               const float4* rec1, const uint2* rec2, int bin,
                                const void* targets, int tdtype, int C, bool per_view,
                                BlendParams bp, float* VS, unsigned long long* counter,
                                uint32_t* gcount, int chunk, hipStream_t s, uint32_t* queues) {
@@ -254,7 +261,7 @@ void launch_accumulate_chunked(const ViewInfo* views, int n_views, uint32_t n_ti
     if (!accumulate_chunk_valid(chunk)) chunk = accumulate_chunk(C);
     if (queues) launch_fill_u32(queues, 0u, (uint64_t)((C + chunk - 1) / chunk), s);
 #define GSC_ACC(CCV)                                                                                \
-    launch_acc_cc<CCV>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, rec2, bin, targets,   \
+    launch_acc_cc<CCV>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, rec2, bin, targets, \
                        tdtype, C, per_view, bp, VS, counter, gcount, queues, s)
     switch (chunk) {
         case 1: GSC_ACC(1); break;
@@ -268,8 +275,9 @@ void launch_accumulate_chunked(const ViewInfo* views, int n_views, uint32_t n_ti
 }
 
 void launch_accumulate_weights(const ViewInfo* views, int n_views, uint32_t n_tiles,
-                               const uint2* ranges, const uint32_t* pair_vals, const float4* rec0,
-                               const float4* rec1, const uint32_t* rec2, int bin, bool per_view,
+                               const uint2* ranges, const uint32_t* pair_vals,
+                               const float4* rec0,
+                               const float4* rec1, const uint2* rec2, int bin, bool per_view,
                                BlendParams bp, float* V, unsigned long long* counter, hipStream_t s) {
     if (n_tiles == 0) return;
     const uint32_t n_wt = wave_tiles(n_tiles, bin);
@@ -283,14 +291,16 @@ void launch_accumulate_weights(const ViewInfo* views, int n_views, uint32_t n_ti
 
 // ---- render ----------------------------------------------------------------
 
-// gamma[item*C + c] = sum_m coeffs[g][m][c] * phi_m(dir_gv) for the batch items.
+// gamma[k*C + c] = sum_m coeffs[g][m][c] * phi_m(dir_gv) for the batch item of
+// depth rank k (item order[k]).
 template <int L>
 __global__ void k_view_colors(const ViewInfo* __restrict__ views, int n_views, uint32_t n_items,
-                              const float* __restrict__ means, const float* __restrict__ coeffs,
-                              int C, float* __restrict__ gamma) {
+                              const uint32_t* __restrict__ order, const float* __restrict__ means,
+                              const float* __restrict__ coeffs, int C, float* __restrict__ gamma) {
     constexpr int NB = (L + 1) * (L + 1);
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_items) return;
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_items) return;
+    const uint32_t i = order[k];
     const ViewInfo& V = views[find_view_item(views, n_views, i)];
     const int64_t g = V.g_offset + (int64_t)(i - V.item_base);
     double dx = (double)means[3 * g] - V.centre[0];
@@ -300,7 +310,7 @@ __global__ void k_view_colors(const ViewInfo* __restrict__ views, int n_views, u
     float phi[NB];
     sh_eval<float, L>((float)(dx * inv), (float)(dy * inv), (float)(dz * inv), phi);
     const float* cg = coeffs + g * NB * C;
-    float* out = gamma + (int64_t)i * C;
+    float* out = gamma + (int64_t)k * C;
     for (int c = 0; c < C; ++c) {
         float a = 0.0f;
 #pragma unroll
@@ -309,15 +319,16 @@ __global__ void k_view_colors(const ViewInfo* __restrict__ views, int n_views, u
     }
 }
 
-void launch_view_colors(const ViewInfo* views, int n_views, uint32_t n_items, const float* means,
-                        const float* coeffs, int C, int sh_deg, float* gamma, hipStream_t s) {
+void launch_view_colors(const ViewInfo* views, int n_views, uint32_t n_items, const uint32_t* order,
+                        const float* means, const float* coeffs, int C, int sh_deg, float* gamma,
+                        hipStream_t s) {
     if (n_items == 0 || n_views <= 0) return;
     dim3 grid((n_items + 255) / 256), block(256);
     switch (sh_deg) {
-        case 0: hipLaunchKernelGGL(k_view_colors<0>, grid, block, 0, s, views, n_views, n_items, means, coeffs, C, gamma); break;
-        case 1: hipLaunchKernelGGL(k_view_colors<1>, grid, block, 0, s, views, n_views, n_items, means, coeffs, C, gamma); break;
-        case 2: hipLaunchKernelGGL(k_view_colors<2>, grid, block, 0, s, views, n_views, n_items, means, coeffs, C, gamma); break;
-        default: hipLaunchKernelGGL(k_view_colors<3>, grid, block, 0, s, views, n_views, n_items, means, coeffs, C, gamma); break;
+        case 0: hipLaunchKernelGGL(k_view_colors<0>, grid, block, 0, s, views, n_views, n_items, order, means, coeffs, C, gamma); break;
+        case 1: hipLaunchKernelGGL(k_view_colors<1>, grid, block, 0, s, views, n_views, n_items, order, means, coeffs, C, gamma); break;
+        case 2: hipLaunchKernelGGL(k_view_colors<2>, grid, block, 0, s, views, n_views, n_items, order, means, coeffs, C, gamma); break;
+        default: hipLaunchKernelGGL(k_view_colors<3>, grid, block, 0, s, views, n_views, n_items, order, means, coeffs, C, gamma); break;
     }
 }
 
@@ -327,7 +338,7 @@ template <int CC, int BIN>
 __global__ __launch_bounds__(256) void k_render(
     const ViewInfo* __restrict__ views, int n_views, uint32_t n_wt, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ pair_vals, const float4* __restrict__ rec0,
-    const float4* __restrict__ rec1, const uint32_t* __restrict__ rec2,
+    const float4* __restrict__ rec1, const uint2* __restrict__ rec2,
     const float* __restrict__ gamma, int C, int c_off, BlendParams bp, float* __restrict__ images,
     unsigned long long* __restrict__ counter) {
     const uint32_t lane = threadIdx.x & 63;
@@ -365,18 +376,18 @@ __global__ __launch_bounds__(256) void k_render(
         const uint32_t pv = lane < nb ? pair_vals[b + lane] : 0u;
         uint32_t pn = bcast_u(pv, 0);
         float4 n0 = rec0[pn & kItemMask], n1 = rec1[pn & kItemMask];
-        uint32_t n2 = BIN == 32 ? rec2[pn & kItemMask] : 0u;
+        uint2 n2 = rec2[pn & kItemMask];
         for (uint32_t j = 0; j < nb; ++j) {
             const uint32_t pc = pn;
             const float4 c0 = n0, c1 = n1;
-            const uint32_t e2 = n2;
+            const uint2 e2 = n2;
             if (j + 1 < nb) {
                 pn = bcast_u(pv, j + 1);
                 n0 = rec0[pn & kItemMask];
                 n1 = rec1[pn & kItemMask];
-                if constexpr (BIN == 32) n2 = rec2[pn & kItemMask];
+                n2 = rec2[pn & kItemMask];
             }
-            const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2, tg.y0) & alive;
+            const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2.x, tg.y0) & alive;
             if (bands == 0u) continue;
             const uint32_t item = pc & kItemMask;
             float col[CC];
@@ -422,7 +433,7 @@ __global__ __launch_bounds__(256) void k_render(
 
 void launch_render(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
                    const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
-                   const uint32_t* rec2, int bin, const float* gamma, int C, BlendParams bp,
+                   const uint2* rec2, int bin, const float* gamma, int C, BlendParams bp,
                    float* images, unsigned long long* counter, hipStream_t s) {
     if (n_tiles == 0) return;
     const uint32_t n_wt = wave_tiles(n_tiles, bin);

@@ -30,15 +30,18 @@
 
 namespace gsc {
 
-// beta[item*(C+1) + c] = beta_gj[c], and [.. + C] = delta_gj.
+// beta[k*(C+1) + c] = beta_gj[c] and [.. + C] = delta_gj for the item of depth
+// rank k (item order[k]).
 template <int L, bool RENDER>
 __global__ void k_view_adjoint(const ViewInfo* __restrict__ views, int n_views, uint32_t n_items,
+                               const uint32_t* __restrict__ order,
                                const float* __restrict__ means, const float* __restrict__ coeffs,
                                const float* __restrict__ bbar, const float* __restrict__ rho, int C,
                                float* __restrict__ beta) {
     constexpr int NB = (L + 1) * (L + 1);
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_items) return;
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_items) return;
+    const uint32_t i = order[k];
     const ViewInfo& V = views[find_view_item(views, n_views, i)];
     const int64_t g = V.g_offset + (int64_t)(i - V.item_base);
     const double dx = (double)means[3 * g] - V.centre[0];
@@ -48,7 +51,7 @@ __global__ void k_view_adjoint(const ViewInfo* __restrict__ views, int n_views, 
     float phi[NB];
     sh_eval<float, L>((float)(dx * inv), (float)(dy * inv), (float)(dz * inv), phi);
     const float* cg = coeffs + g * NB * C;
-    float* out = beta + (int64_t)i * (C + 1);
+    float* out = beta + (int64_t)k * (C + 1);
     if constexpr (RENDER) {
         for (int c = 0; c < C; ++c) {
             float a = 0.0f;
@@ -74,19 +77,20 @@ __global__ void k_view_adjoint(const ViewInfo* __restrict__ views, int n_views, 
     }
 }
 
-void launch_view_adjoint(const ViewInfo* views, int n_views, uint32_t n_items, const float* means,
-                         const float* coeffs, const float* bbar, const float* rho, int C,
-                         int sh_deg, bool render, float* beta, hipStream_t s) {
+void launch_view_adjoint(const ViewInfo* views, int n_views, uint32_t n_items, const uint32_t* order,
+                         const float* means, const float* coeffs, const float* bbar,
+                         const float* rho, int C, int sh_deg, bool render, float* beta,
+                         hipStream_t s) {
     if (n_items == 0 || n_views <= 0) return;
     dim3 grid((n_items + 255) / 256), block(256);
 #define GSC_VA(LL)                                                                                   \
     do {                                                                                             \
         if (render)                                                                                  \
             hipLaunchKernelGGL((k_view_adjoint<LL, true>), grid, block, 0, s, views, n_views,        \
-                               n_items, means, coeffs, bbar, rho, C, beta);                          \
+                               n_items, order, means, coeffs, bbar, rho, C, beta);                          \
         else                                                                                         \
             hipLaunchKernelGGL((k_view_adjoint<LL, false>), grid, block, 0, s, views, n_views,       \
-                               n_items, means, coeffs, bbar, rho, C, beta);                          \
+                               n_items, order, means, coeffs, bbar, rho, C, beta);                          \
     } while (0)
     switch (sh_deg) {
         case 0: GSC_VA(0); break;
@@ -132,9 +136,9 @@ __device__ __forceinline__ Step blend_step(float& T, bool& live, float q2, float
 template <int CC, bool BF16, bool GY, int BIN>
 __global__ __launch_bounds__(256) void k_blend_adjoint(
     const ViewInfo* __restrict__ views, int n_views, uint32_t n_wt, const uint2* __restrict__ ranges,
-    const uint32_t* __restrict__ pair_vals, const float4* __restrict__ rec0,
-    const float4* __restrict__ rec1, const uint32_t* __restrict__ rec2,
-    const void* __restrict__ ypix, int C, int c_off,
+    const uint32_t* __restrict__ pair_vals,
+    const float4* __restrict__ rec0, const float4* __restrict__ rec1,
+    const uint2* __restrict__ rec2, const void* __restrict__ ypix, int C, int c_off,
     const float* __restrict__ beta, BlendParams bp, float* __restrict__ grad_y,
     float* __restrict__ grad_o) {
     const uint32_t lane = threadIdx.x & 63;
@@ -147,7 +151,8 @@ __global__ __launch_bounds__(256) void k_blend_adjoint(
     const float px = (float)ix + 0.5f;
     const int stride = C + 1;
     const bool first_chunk = c_off == 0;
-    // dL/do of item i goes to Gaussian g_offset + (i - item_base)
+    // dL/do of an entry goes to Gaussian g_offset + (item - item_base), the
+    // item being named by the entry's record
     const int64_t g_shift = V.g_offset - (int64_t)V.item_base;
     const float qlim = (float)(kExp2Scale * (double)bp.cut2);
 
@@ -187,18 +192,18 @@ __global__ __launch_bounds__(256) void k_blend_adjoint(
         const uint32_t pv = lane < nb ? pair_vals[b + lane] : 0u;
         uint32_t pn = bcast_u(pv, 0);
         float4 n0 = rec0[pn & kItemMask], n1 = rec1[pn & kItemMask];
-        uint32_t n2 = BIN == 32 ? rec2[pn & kItemMask] : 0u;
+        uint2 n2 = rec2[pn & kItemMask];
         for (uint32_t j = 0; j < nb; ++j) {
             const uint32_t pc = pn;
             const float4 c0 = n0, c1 = n1;
-            const uint32_t e2 = n2;
+            const uint2 e2 = n2;
             if (j + 1 < nb) {
                 pn = bcast_u(pv, j + 1);
                 n0 = rec0[pn & kItemMask];
                 n1 = rec1[pn & kItemMask];
-                if constexpr (BIN == 32) n2 = rec2[pn & kItemMask];
+                n2 = rec2[pn & kItemMask];
             }
-            const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2, tg.y0);
+            const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2.x, tg.y0);
             if (bands == 0u) continue;
             const uint32_t item = pc & kItemMask;
             const float* bp_ = beta + (int64_t)item * stride;
@@ -256,18 +261,18 @@ __global__ __launch_bounds__(256) void k_blend_adjoint(
         const uint32_t pv = lane < nb ? pair_vals[b + lane] : 0u;
         uint32_t pn = bcast_u(pv, 0);
         float4 n0 = rec0[pn & kItemMask], n1 = rec1[pn & kItemMask];
-        uint32_t n2 = BIN == 32 ? rec2[pn & kItemMask] : 0u;
+        uint2 n2 = rec2[pn & kItemMask];
         for (uint32_t j = 0; j < nb; ++j) {
             const uint32_t pc = pn;
             const float4 c0 = n0, c1 = n1;
-            const uint32_t e2 = n2;
+            const uint2 e2 = n2;
             if (j + 1 < nb) {
                 pn = bcast_u(pv, j + 1);
                 n0 = rec0[pn & kItemMask];
                 n1 = rec1[pn & kItemMask];
-                if constexpr (BIN == 32) n2 = rec2[pn & kItemMask];
+                n2 = rec2[pn & kItemMask];
             }
-            const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2, tg.y0);
+            const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2.x, tg.y0);
             if (bands == 0u) continue;
             const uint32_t item = pc & kItemMask;
             const float* bp_ = beta + (int64_t)item * stride;
@@ -298,7 +303,7 @@ __global__ __launch_bounds__(256) void k_blend_adjoint(
             }
             if (__ballot(any != 0) != 0) {
                 const float t = wave_sum(go);
-                if (lane == 0) unsafeAtomicAdd(grad_o + ((int64_t)item + g_shift), t);
+                if (lane == 0) unsafeAtomicAdd(grad_o + ((int64_t)e2.y + g_shift), t);
             }
             if (__ballot(live[0] || live[1] || live[2] || live[3]) == 0) {
                 wave_live = false;
@@ -310,10 +315,10 @@ __global__ __launch_bounds__(256) void k_blend_adjoint(
 
 template <int CC, bool GY>
 static void launch_badj_cc(const ViewInfo* views, int n_views, uint32_t n_bins, const uint2* ranges,
-                           const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
-                           const uint32_t* rec2, int bin, const void* ypix, int ydtype, int C,
-                           const float* beta, BlendParams bp, float* grad_y, float* grad_o,
-                           hipStream_t s) {
+                           const uint32_t* pair_vals, const float4* rec0,
+                           const float4* rec1, const uint2* rec2, int bin, const void* ypix,
+                           int ydtype, int C, const float* beta, BlendParams bp, float* grad_y,
+                           float* grad_o, hipStream_t s) {
     const uint32_t n_wt = bin == 32 ? 4u * n_bins : n_bins;
     dim3 grid((n_wt + 3) / 4), block(256);
 #define GSC_BADJ(BFV, BINV)                                                                         \
@@ -332,8 +337,9 @@ static void launch_badj_cc(const ViewInfo* views, int n_views, uint32_t n_bins, 
 
 template <bool GY>
 static void launch_badj(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
-                        const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
-                        const uint32_t* rec2, int bin, const void* ypix, int ydtype, int C,
+                        const uint32_t* pair_vals, const float4* rec0,
+                        const float4* rec1,
+                        const uint2* rec2, int bin, const void* ypix, int ydtype, int C,
                         const float* beta, BlendParams bp, float* grad_y, float* grad_o,
                         hipStream_t s) {
 #define GSC_BA(CCV)                                                                                \
@@ -351,8 +357,9 @@ static void launch_badj(const ViewInfo* views, int n_views, uint32_t n_tiles, co
 }
 
 void launch_blend_adjoint(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
-                          const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
-                          const uint32_t* rec2, int bin, const void* ypix, int ydtype, int C,
+                          const uint32_t* pair_vals, const float4* rec0,
+                          const float4* rec1,
+                          const uint2* rec2, int bin, const void* ypix, int ydtype, int C,
                           const float* beta, BlendParams bp, float* grad_y, float* grad_o,
                           hipStream_t s) {
     if (n_tiles == 0 || (!grad_y && !grad_o)) return;

@@ -188,7 +188,37 @@ __device__ inline void footprint_bins(float4 r0, float4 r1, float qmax, int W, i
     }
 }
 
-// a2: one thread per (view, Gaussian) item of the batch.
+// a2, first step: the depth key of every (view, Gaussian) item of the batch,
+// keys[i] = bits of the camera-space depth of the mean computed in binary32
+// (positive floats order like their bit patterns), 0xFFFFFFFF for items culled
+// by the near plane or too faint to pass the alpha floor anywhere; vals[i] = i.
+__global__ __launch_bounds__(256) void k_depth_keys(const ViewInfo* __restrict__ views, int n_views,
+                                                    uint32_t n_items, const float* __restrict__ means,
+                                                    const float* __restrict__ opac, BlendParams bp,
+                                                    uint32_t* __restrict__ keys,
+                                                    uint32_t* __restrict__ vals) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_items) return;
+    const ViewInfo& V = views[find_view_item(views, n_views, i)];
+    const int64_t g = V.g_offset + (int64_t)(i - V.item_base);
+    const float key = __fmaf_rn(V.R[6], means[3 * g],
+                                __fmaf_rn(V.R[7], means[3 * g + 1], __fmaf_rn(V.R[8], means[3 * g + 2], V.t[2])));
+    keys[i] = (key > bp.znear && reach_q(opac[g], bp) > 0.0f) ? __float_as_uint(key) : 0xFFFFFFFFu;
+    vals[i] = i;
+}
+
+void launch_depth_keys(const ViewInfo* views, int n_views, uint32_t n_items, const float* means,
+                       const float* opac, BlendParams bp, uint32_t* keys, uint32_t* vals,
+                       hipStream_t s) {
+    if (n_items == 0 || n_views <= 0) return;
+    hipLaunchKernelGGL(k_depth_keys, dim3((n_items + 255) / 256), dim3(256), 0, s, views, n_views,
+                       n_items, means, opac, bp, keys, vals);
+}
+
+// a2: projection of the items in depth order: thread k handles item
+// order[k] (k itself when order is null) and writes its record and tile-pair
+// count at position k, so that binning reads them contiguously; the random
+// reads go to the per-Gaussian geometry, which caches across views.
 // The projection is evaluated in FP64 (a few dozen operations per item) and
 // the pixel position is stored as an FP32 hi/lo pair, so that the blend can
 // form pixel offsets d = (p - u_hi) - u_lo exactly to one FP32 ulp of d; a
@@ -196,24 +226,25 @@ __device__ inline void footprint_bins(float4 r0, float4 r1, float qmax, int W, i
 // enough to move alpha by ~1e-4 relative at the footprint edge.
 // A tile is binned only if its pixel centres come within the footprint
 // reach (3-sigma ellipse, shrunk by the alpha floor for faint splats).
-// rec2[i] = first | last << 16: the pixel rows the footprint walk covers.
+// rec2[k] = (first | last << 16, i): the pixel rows the footprint walk covers
+// and the item.
 template <int BIN>
 __global__ __launch_bounds__(256) void k_project(const ViewInfo* __restrict__ views, int n_views,
-                                                 uint32_t n_items, const float* __restrict__ means,
+                                                 uint32_t n_items, const uint32_t* __restrict__ order,
+                                                 const float* __restrict__ means,
                                                  const float* __restrict__ cov,
                                                  const float* __restrict__ opac,
-                                                 BlendParams bp, uint32_t* __restrict__ keys,
-                                                 uint32_t* __restrict__ vals,
-                                                 uint32_t* __restrict__ counts,
+                                                 BlendParams bp, uint32_t* __restrict__ counts,
                                                  float4* __restrict__ rec0, float4* __restrict__ rec1,
-                                                 uint32_t* __restrict__ rec2) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_items) return;
+                                                 uint2* __restrict__ rec2) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_items) return;
+    const uint32_t i = order ? order[k] : k;
     const ViewInfo& V = views[find_view_item(views, n_views, i)];
     const int64_t g = V.g_offset + (int64_t)(i - V.item_base);
     float mx = means[3 * g], my = means[3 * g + 1], mz = means[3 * g + 2];
     float key = __fmaf_rn(V.R[6], mx, __fmaf_rn(V.R[7], my, __fmaf_rn(V.R[8], mz, V.t[2])));
-    uint32_t kb = 0xFFFFFFFFu, cnt = 0;
+    uint32_t cnt = 0;
     int rows[2] = {1, 0};
     float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
     const float og = opac[g];
@@ -256,46 +287,30 @@ __global__ __launch_bounds__(256) void k_project(const ViewInfo* __restrict__ vi
             footprint_bins<BIN>(r0, r1, qmax, V.width, V.height, [&](int, int t0, int t1, auto&& mask_of) {
                 for (int t = t0; t <= t1; ++t) cnt += mask_of(t) != 0u;
             }, rows);
-            if (cnt > 0) kb = __float_as_uint(key);
         }
     }
-    keys[i] = kb;
-    vals[i] = i;
-    counts[i] = cnt;
-    rec0[i] = r0;
-    rec1[i] = r1;
-    rec2[i] = (uint32_t)(rows[0] & 0xFFFF) | ((uint32_t)(rows[1] & 0xFFFF) << 16);
+    counts[k] = cnt;
+    rec0[k] = r0;
+    rec1[k] = r1;
+    rec2[k] = make_uint2((uint32_t)(rows[0] & 0xFFFF) | ((uint32_t)(rows[1] & 0xFFFF) << 16), i);
 }
 
-void launch_project(const ViewInfo* views, int n_views, uint32_t n_items, const float* means,
-                    const float* cov, const float* opac, BlendParams bp, uint32_t* keys,
-                    uint32_t* vals, uint32_t* counts, float4* rec0, float4* rec1, uint32_t* rec2,
-                    int bin, hipStream_t s) {
+void launch_project(const ViewInfo* views, int n_views, uint32_t n_items, const uint32_t* order,
+                    const float* means, const float* cov, const float* opac, BlendParams bp,
+                    uint32_t* counts, float4* rec0, float4* rec1, uint2* rec2, int bin,
+                    hipStream_t s) {
     if (n_items == 0 || n_views <= 0) return;
     if (bin == 32)
         hipLaunchKernelGGL(k_project<32>, dim3((n_items + 255) / 256), dim3(256), 0, s, views, n_views,
-                           n_items, means, cov, opac, bp, keys, vals, counts, rec0, rec1, rec2);
+                           n_items, order, means, cov, opac, bp, counts, rec0, rec1, rec2);
     else
         hipLaunchKernelGGL(k_project<16>, dim3((n_items + 255) / 256), dim3(256), 0, s, views, n_views,
-                           n_items, means, cov, opac, bp, keys, vals, counts, rec0, rec1, rec2);
+                           n_items, order, means, cov, opac, bp, counts, rec0, rec1, rec2);
 }
 
-__global__ void k_gather_counts(const uint32_t* __restrict__ sorted_vals,
-                                const uint32_t* __restrict__ counts, uint32_t* __restrict__ out,
-                                uint32_t n) {
-    uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) out[k] = counts[sorted_vals[k]];
-}
-
-void launch_gather_counts(const uint32_t* sorted_vals, const uint32_t* counts, uint32_t* out,
-                          uint32_t n, hipStream_t s) {
-    if (n == 0) return;
-    hipLaunchKernelGGL(k_gather_counts, dim3((n + 255) / 256), dim3(256), 0, s, sorted_vals, counts,
-                       out, n);
-}
-
-// a3: emit (global bin id, item | mask) pairs in depth order; a stable sort by
-// bin id then yields every bin's list in front-to-back order.
+// a3: emit (global bin id, k | mask) pairs in depth order, k being the depth
+// rank of the item (records, counts and offsets are in that order); a stable
+// sort by bin id then yields every bin's list in front-to-back order.
 template <int BIN>
 __global__ void k_emit(const ViewInfo* __restrict__ views, int n_views,
                        const uint32_t* __restrict__ sorted_vals,
@@ -306,12 +321,12 @@ __global__ void k_emit(const ViewInfo* __restrict__ views, int n_views,
                        uint32_t* __restrict__ pair_keys, uint32_t* __restrict__ pair_vals) {
     uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_items) return;
-    uint32_t i = sorted_vals[k];
-    if (counts[i] == 0) return;
-    const ViewInfo& V = views[find_view_item(views, n_views, i)];
-    const float4 r0 = rec0[i], r1 = rec1[i];
+    const uint32_t cnt = counts[k];
+    if (cnt == 0) return;
+    const ViewInfo& V = views[find_view_item(views, n_views, sorted_vals[k])];
+    const float4 r0 = rec0[k], r1 = rec1[k];
     uint32_t off = offsets[k];
-    uint32_t end = off + counts[i];
+    uint32_t end = off + cnt;
     if (end > cap || end < off) {  // capacity exceeded: keep what fits, report the rest
         if (overflow) atomicAdd(overflow, 1u);
         end = off < cap ? cap : off;
@@ -322,7 +337,7 @@ __global__ void k_emit(const ViewInfo* __restrict__ views, int n_views,
             const uint32_t m = mask_of(t);
             if (m == 0u || off >= end) continue;
             pair_keys[off] = V.tile_base + (uint32_t)ty * (uint32_t)V.tiles_x + (uint32_t)t;
-            pair_vals[off] = i | (m << kItemBits);
+            pair_vals[off] = k | (m << kItemBits);
             ++off;
         }
     });
