@@ -79,11 +79,15 @@ __device__ inline float reach_q(float o, const BlendParams& bp) {
     return q * (1.0f + 1e-4f) + 1e-3f;
 }
 
-// Walks the pixel rows of a record's footprint {q <= qmax} and calls
-// visit(ty, lo, hi) once per 16-row tile row, where [lo[k], hi[k]] is the
-// range of 16-column blocks holding a pixel centre of band k (rows 4k..4k+3
-// of the tile row) inside the footprint (lo > hi: none).  Row intervals are
-// widened by 0.01 pixel, so the walk is conservative with respect to the
+// Walks a record's footprint {q <= qmax} band by band (four pixel rows) and
+// calls visit(ty, lo, hi) once per 16-row tile row, where [lo[k], hi[k]] is a
+// range of 16-column blocks covering every pixel centre of band k (rows
+// 4k..4k+3 of the tile row) inside the footprint (lo > hi: none).  The x
+// extent of a band is taken over the continuous span of its row centres: the
+// left edge of the ellipse is convex and the right edge concave in y, so the
+// extremes lie at the span's ends or at the ellipse's leftmost / rightmost
+// point when that falls inside the span.  Extents are widened by 0.01 pixel
+// (and 1e-4 relative), so the walk is conservative with respect to the
 // blend's FP32 test.  *rows (optional) receives the first and last pixel row
 // walked.  Used identically for counting and emitting.
 template <typename Visit>
@@ -104,25 +108,42 @@ __device__ inline void footprint_rows(float4 r0, float4 r1, float qmax, int W, i
         rows[0] = y0;
         rows[1] = y1;
     }
+    const float cx = r0.x - 0.5f + r0.z;  // column index whose centre is the mean
+    // leftmost / rightmost point of the ellipse: dx = -+ sqrt(qmax Sxx) at
+    // dy = -+ sqrt(qmax / Sxx) Sxy, with Sxx = c / det, Sxy = -b / det
+    const float sxx = c / det, sxy = -b / det;
+    const float xr = sqrtf(qmax * sxx) * 1.0001f + 0.01f;
+    const float dyl = -sqrtf(qmax / sxx) * sxy;  // row offset of the leftmost point (rightmost: -dyl)
+    auto edges = [&](int y, float& l, float& r) {
+        const float dy = ((float)y + 0.5f - r0.y) - r0.w;
+        const float disc = fmaxf(qmax - cq * dy * dy, 0.0f);
+        const float half = sqrtf(disc * ia) * 1.0001f + 0.01f;
+        const float mid = cx - b * dy * ia;
+        l = mid - half;
+        r = mid + half;
+    };
     int lo[4], hi[4];
     int cur = y0 >> kTileShift;
     for (int k = 0; k < 4; ++k) { lo[k] = 1 << 30; hi[k] = -1; }
-    for (int y = y0; y <= y1; ++y) {
-        const int ty = y >> kTileShift;
+    for (int ya = y0; ya <= y1; ya = (ya | 3) + 1) {
+        const int yb = min(ya | 3, y1);  // rows [ya, yb] of one band
+        const int ty = ya >> kTileShift;
         if (ty != cur) {
             visit(cur, lo, hi);
             for (int k = 0; k < 4; ++k) { lo[k] = 1 << 30; hi[k] = -1; }
             cur = ty;
         }
-        const float dy = ((float)y + 0.5f - r0.y) - r0.w;
-        const float disc = qmax - cq * dy * dy;
-        if (disc < 0.0f) continue;
-        const float half = sqrtf(disc * ia) * 1.0001f + 0.01f;
-        const float mid = (r0.x - 0.5f + r0.z) - b * dy * ia;  // column index of the centre
-        const float xf = fmaxf(ceilf(mid - half), 0.0f);
-        const float xl = fminf(floorf(mid + half), (float)(W - 1));
+        float la, ra, lb, rb;
+        edges(ya, la, ra);
+        edges(yb, lb, rb);
+        float l = fminf(la, lb), r = fmaxf(ra, rb);
+        const float sa = ((float)ya + 0.5f - r0.y) - r0.w, sb = ((float)yb + 0.5f - r0.y) - r0.w;
+        if (sa <= dyl && dyl <= sb) l = cx - xr;
+        if (sa <= -dyl && -dyl <= sb) r = cx + xr;
+        const float xf = fmaxf(ceilf(l), 0.0f);
+        const float xl = fminf(floorf(r), (float)(W - 1));
         if (!(xf <= xl)) continue;
-        const int band = (y >> 2) & 3;
+        const int band = (ya >> 2) & 3;
         const int t0 = (int)xf >> kTileShift, t1 = (int)xl >> kTileShift;
         for (int k = 0; k < 4; ++k)
             if (k == band) {
