@@ -74,19 +74,25 @@ __device__ __forceinline__ uint32_t accumulate_tile(
     for (uint32_t b = rg.x; b < rg.y && alive != 0u; b += 64) {
         const uint32_t nb = min(64u, rg.y - b);
         const uint32_t pv = lane < nb ? pair_vals[b + lane] : 0u;
-        // records are fetched with uniform addresses one entry ahead
-        uint32_t pn = bcast_u(pv, 0);
+        // records are fetched with uniform addresses two entries ahead
+        uint32_t pn = bcast_u(pv, 0), pm = nb > 1 ? bcast_u(pv, 1) : 0u;
         float4 n0 = rec0[pn & kItemMask], n1 = rec1[pn & kItemMask];
         uint2 n2 = rec2[pn & kItemMask];
+        float4 m0 = rec0[pm & kItemMask], m1 = rec1[pm & kItemMask];
+        uint2 m2 = rec2[pm & kItemMask];
         for (uint32_t j = 0; j < nb; ++j) {
             const uint32_t pc = pn;
             const float4 c0 = n0, c1 = n1;
             const uint2 e2 = n2;
-            if (j + 1 < nb) {
-                pn = bcast_u(pv, j + 1);
-                n0 = rec0[pn & kItemMask];
-                n1 = rec1[pn & kItemMask];
-                n2 = rec2[pn & kItemMask];
+            pn = pm;
+            n0 = m0;
+            n1 = m1;
+            n2 = m2;
+            if (j + 2 < nb) {
+                pm = bcast_u(pv, j + 2);
+                m0 = rec0[pm & kItemMask];
+                m1 = rec1[pm & kItemMask];
+                m2 = rec2[pm & kItemMask];
             }
             const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2.x, tg.y0) & alive;
             if (bands == 0u) continue;
