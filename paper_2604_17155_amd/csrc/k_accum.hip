@@ -74,26 +74,18 @@ __device__ __forceinline__ uint32_t accumulate_tile(
     for (uint32_t b = rg.x; b < rg.y && alive != 0u; b += 64) {
         const uint32_t nb = min(64u, rg.y - b);
         const uint32_t pv = lane < nb ? pair_vals[b + lane] : 0u;
-        // records are fetched with uniform addresses two entries ahead
-        uint32_t pn = bcast_u(pv, 0), pm = nb > 1 ? bcast_u(pv, 1) : 0u;
-        float4 n0 = rec0[pn & kItemMask], n1 = rec1[pn & kItemMask];
-        uint2 n2 = rec2[pn & kItemMask];
-        float4 m0 = rec0[pm & kItemMask], m1 = rec1[pm & kItemMask];
-        uint2 m2 = rec2[pm & kItemMask];
+        // the chunk's records are gathered at once, one entry per lane, and
+        // broadcast entry by entry with v_readlane
+        const uint32_t it = pv & kItemMask;
+        const bool own = lane < nb;
+        const float4 R0 = own ? rec0[it] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 R1 = own ? rec1[it] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const uint2 R2 = own ? rec2[it] : make_uint2(0u, 0u);
         for (uint32_t j = 0; j < nb; ++j) {
-            const uint32_t pc = pn;
-            const float4 c0 = n0, c1 = n1;
-            const uint2 e2 = n2;
-            pn = pm;
-            n0 = m0;
-            n1 = m1;
-            n2 = m2;
-            if (j + 2 < nb) {
-                pm = bcast_u(pv, j + 2);
-                m0 = rec0[pm & kItemMask];
-                m1 = rec1[pm & kItemMask];
-                m2 = rec2[pm & kItemMask];
-            }
+            const uint32_t pc = bcast_u(pv, j);
+            const float4 c0 = make_float4(bcast(R0.x, j), bcast(R0.y, j), bcast(R0.z, j), bcast(R0.w, j));
+            const float4 c1 = make_float4(bcast(R1.x, j), bcast(R1.y, j), bcast(R1.z, j), bcast(R1.w, j));
+            const uint2 e2 = make_uint2(bcast_u(R2.x, j), bcast_u(R2.y, j));
             const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2.x, tg.y0) & alive;
             if (bands == 0u) continue;
             const float dx = (px - c0.x) - c0.z;
