@@ -71,23 +71,40 @@ __device__ __forceinline__ uint32_t accumulate_tile(
 #pragma unroll
     for (int k = 0; k < 4; ++k) pyk[k] = (float)(iy0 + 4 * k) + 0.5f;
 
+    // The list is walked in chunks of 64 entries.  A chunk's records are
+    // gathered at once, one entry per lane, and broadcast entry by entry with
+    // v_readlane; the next chunk's gather (and the pair values of the one
+    // after) are in flight while a chunk is blended.
+    auto load_pv = [&](uint32_t b) -> uint32_t {
+        return b + lane < rg.y ? pair_vals[b + lane] : 0u;
+    };
+    auto gather = [&](uint32_t pv, uint32_t b, float4& R0, float4& R1, uint2& R2) {
+        const uint32_t it = pv & kItemMask;
+        const bool own = b + lane < rg.y;
+        R0 = own ? rec0[it] : make_float4(0.f, 0.f, 0.f, 0.f);
+        R1 = own ? rec1[it] : make_float4(0.f, 0.f, 0.f, 0.f);
+        R2 = own ? rec2[it] : make_uint2(0u, 0u);
+    };
+    // (wide channel chunks have no registers to spare for the second buffer:
+    // there the next chunk is gathered when the current one is done)
+    constexpr bool kDouble = CC <= 4;
+    uint32_t pv = load_pv(rg.x), pvn = load_pv(rg.x + 64);
+    float4 R0, R1;
+    uint2 R2;
+    gather(pv, rg.x, R0, R1, R2);
     for (uint32_t b = rg.x; b < rg.y && alive != 0u; b += 64) {
         const uint32_t nb = min(64u, rg.y - b);
-        const uint32_t pv = lane < nb ? pair_vals[b + lane] : 0u;
-        // the chunk's records are gathered at once, one entry per lane, and
-        // broadcast entry by entry with v_readlane
-        const uint32_t it = pv & kItemMask;
-        const bool own = lane < nb;
-        const float4 R0 = own ? rec0[it] : make_float4(0.f, 0.f, 0.f, 0.f);
-        const float4 R1 = own ? rec1[it] : make_float4(0.f, 0.f, 0.f, 0.f);
-        const uint2 R2 = own ? rec2[it] : make_uint2(0u, 0u);
+        float4 Q0, Q1;
+        uint2 Q2;
+        if constexpr (kDouble) gather(pvn, b + 64, Q0, Q1, Q2);
+        const uint32_t pvnn = load_pv(b + 128);
         for (uint32_t j = 0; j < nb; ++j) {
             const uint32_t pc = bcast_u(pv, j);
-            const float4 c0 = make_float4(bcast(R0.x, j), bcast(R0.y, j), bcast(R0.z, j), bcast(R0.w, j));
-            const float4 c1 = make_float4(bcast(R1.x, j), bcast(R1.y, j), bcast(R1.z, j), bcast(R1.w, j));
             const uint2 e2 = make_uint2(bcast_u(R2.x, j), bcast_u(R2.y, j));
             const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2.x, tg.y0) & alive;
             if (bands == 0u) continue;
+            const float4 c0 = make_float4(bcast(R0.x, j), bcast(R0.y, j), bcast(R0.z, j), bcast(R0.w, j));
+            const float4 c1 = make_float4(bcast(R1.x, j), bcast(R1.y, j), bcast(R1.z, j), bcast(R1.w, j));
             const float dx = (px - c0.x) - c0.z;
             const float a0 = c1.x * dx * dx;
             const float b0 = c1.y * dx;
@@ -151,6 +168,15 @@ __device__ __forceinline__ uint32_t accumulate_tile(
             }
             if (alive == 0u) break;
         }
+        if constexpr (kDouble) {
+            R0 = Q0;
+            R1 = Q1;
+            R2 = Q2;
+        } else {
+            gather(pvn, b + 64, R0, R1, R2);
+        }
+        pv = pvn;
+        pvn = pvnn;
     }
     return cnt;
 }
