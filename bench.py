@@ -79,11 +79,37 @@ def gpu_targets(gsc, sc, which=0, bf16=False):
     return img.to(torch.bfloat16).contiguous() if bf16 else img.contiguous()
 
 
-def roofline(C, contrib, blend_ms_total, launches):
+# HBM bytes per k_accumulate launch, from FETCH_SIZE (x2) and WRITE_SIZE counter
+# runs (profiles/accumulate_*.md), valid only for the kernel sources they were
+# taken on: the digest of those sources is kept beside each figure.
+MEASURED_TRAFFIC = {
+    "relight": {"bytes": 1.898e9, "sources": "e83141bc8ac7e364"},
+}
+ACCUMULATE_SOURCES = ("paper_2604_17155_amd/csrc/k_accum.hip", "paper_2604_17155_amd/csrc/wave_ops.h")
+
+
+def accumulate_sources_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ACCUMULATE_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    m = MEASURED_TRAFFIC.get(workload)
+    if m is None or m["sources"] != accumulate_sources_digest():
+        return None
+    return m["bytes"]
+
+
+def roofline(C, contrib, blend_ms_total, launches, workload=None):
     flops = algorithmic_flops_per_contribution(C) * contrib
     achieved = flops / (blend_ms_total * 1e-3)
     return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
-            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR,
+            "traffic": measured_traffic(workload),
             "kernel": "k_accumulate", "kernel_ms": blend_ms_total / max(1, launches),
             "launches_per_step": launches,
             "flop_per_contribution": algorithmic_flops_per_contribution(C)}
@@ -96,7 +122,7 @@ def line(args, value, ms_per_step, dtype, config, roof):
             "data": "synthetic", "config": config, "roofline": roof}
 
 
-def run_single(args, gsc, sc, targets, label, dtype):
+def run_single(args, gsc, sc, targets, label, dtype, traffic_key=None):
     """Time `steps` gsc_colorize calls on one scene."""
     import torch
     m, s, q, o = gsc.scene_tensors(sc)
@@ -123,7 +149,7 @@ def run_single(args, gsc, sc, targets, label, dtype):
               "scenes_per_sec": args.steps / elapsed, "tile_pairs_per_step": int(st.pairs),
               "bin_size": int(st.bin_size), "stage_ms_per_step": stages}
     return line(args, contrib * args.steps / elapsed, 1e3 * elapsed / args.steps, dtype, config,
-                roofline(sc.C, contrib, stages["blend"], launches))
+                roofline(sc.C, contrib, stages["blend"], launches, traffic_key))
 
 
 def workload_relight(args, gsc):
@@ -132,7 +158,8 @@ def workload_relight(args, gsc):
     targets = gpu_targets(gsc, sc)
     label = (f"relighting: {sc.N} anisotropic Gaussians, {len(sc.cams)} hemisphere cameras "
              f"{sc.cams[0].width}x{sc.cams[0].height}, SH degree {sc.sh_deg}, C={sc.C}, FP32 targets")
-    out = run_single(args, gsc, sc, targets, label, "f32")
+    default_size = not (args.n or args.views or args.res or args.bin)
+    out = run_single(args, gsc, sc, targets, label, "f32", "relight" if default_size else None)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, host_threads(), "the full benchmark workload")
     return out
