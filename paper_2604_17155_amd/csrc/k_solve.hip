@@ -5,10 +5,9 @@
 //   A_g = sum_j V_gj phi_gj phi_gj^T  and  B_g = sum_j phi_gj S_gj^T
 // and accumulates them over the views in FP64 registers (FP32 accumulation
 // of A over tens of views loses ~1e-4 relative at the condition numbers the
-// paper's Lambda produces).  The quad then writes A_g + w_g Lambda to LDS,
-// factors it with a cooperative FP64 Cholesky and each lane solves one
-// right-hand-side column.  The factor stays in LDS for further channel
-// chunks of four.
+// paper's Lambda produces).  The quad then factors A_g + w_g Lambda with a
+// cooperative FP64 Cholesky and solves four right-hand-side columns at a
+// time, all in registers; the factor stays there for further channel chunks.
 // L = 0: A_g = w_g Y0^2 is a scalar and c_g = Y0 S_g / (w_g (Y0^2 + lambda_0)).
 #include "gsc_internal.h"
 #include "sh.h"
@@ -51,9 +50,6 @@ __global__ void k_sum_views(const float* __restrict__ VS, int n_views, int64_t N
     out[i] = a;
 }
 
-constexpr int kStageFloats = 2048;  // LDS staging of per-view sums (8 KB)
-constexpr int kMaxStageViews = 64;
-
 // Broadcast lane `o` of each quad to the whole quad (DPP quad_perm [o,o,o,o]).
 template <int O>
 __device__ __forceinline__ double quad_bcast(double x) {
@@ -63,19 +59,37 @@ __device__ __forceinline__ double quad_bcast(double x) {
     return __hiloint2double(hi, lo);
 }
 
-__device__ __forceinline__ double quad_bcast_rt(double x, int o) {
-    switch (o) {
-        case 0: return quad_bcast<0>(x);
-        case 1: return quad_bcast<1>(x);
-        case 2: return quad_bcast<2>(x);
-        default: return quad_bcast<3>(x);
-    }
+// Sum over the quad (DPP quad_perm [1,0,3,2] then [2,3,0,1]); every lane of
+// the quad gets the same value.
+__device__ __forceinline__ double quad_sum(double x) {
+    constexpr int x1 = 1 | (0 << 2) | (3 << 4) | (2 << 6);
+    constexpr int x2 = 2 | (3 << 2) | (0 << 4) | (1 << 6);
+    x += __hiloint2double(__builtin_amdgcn_update_dpp(0, __double2hiint(x), x1, 0xF, 0xF, false),
+                          __builtin_amdgcn_update_dpp(0, __double2loint(x), x1, 0xF, 0xF, false));
+    x += __hiloint2double(__builtin_amdgcn_update_dpp(0, __double2hiint(x), x2, 0xF, 0xF, false),
+                          __builtin_amdgcn_update_dpp(0, __double2loint(x), x2, 0xF, 0xF, false));
+    return x;
 }
 
-// Fold + solve for L >= 1.  Four lanes per Gaussian; lane r owns the rows
-// i = 4k + r of A (lower triangle, FP64) and of B (four channels at a time).
-// The Cholesky factor is formed in registers (column j broadcast within the
-// quad), then L and B go through LDS so each lane can substitute one channel.
+__device__ __forceinline__ double quad_max(double x) {
+    constexpr int x1 = 1 | (0 << 2) | (3 << 4) | (2 << 6);
+    constexpr int x2 = 2 | (3 << 2) | (0 << 4) | (1 << 6);
+    x = fmax(x, __hiloint2double(__builtin_amdgcn_update_dpp(0, __double2hiint(x), x1, 0xF, 0xF, false),
+                                 __builtin_amdgcn_update_dpp(0, __double2loint(x), x1, 0xF, 0xF, false)));
+    x = fmax(x, __hiloint2double(__builtin_amdgcn_update_dpp(0, __double2hiint(x), x2, 0xF, 0xF, false),
+                                 __builtin_amdgcn_update_dpp(0, __double2loint(x), x2, 0xF, 0xF, false)));
+    return x;
+}
+
+// Fold + solve for L >= 1.  Four lanes (a quad) per Gaussian; lane r owns
+// the rows i = 4k + r of A (lower triangle) and of the right-hand sides,
+// four channels at a time, all in FP64 registers.  The views' sums are read
+// in groups of four (the next group in flight while one is folded) and
+// folded two views at a time.  The Cholesky factor is formed in place
+// (column j broadcast within the quad; the owner of row j keeps 1/L_jj on
+// the diagonal), forward substitution broadcasts each solved entry to the
+// quad, and back substitution sums each column's products over the quad.
+// No LDS.
 //
 // ADJ: adjoint solve for the backward pass.  VS then holds only the per-view
 // visibilities (stride 1); the right-hand sides are read from `rhs`
@@ -84,32 +98,23 @@ __device__ __forceinline__ double quad_bcast_rt(double x, int o) {
 // rho_g = sum_{m,c} lambda_m Bbar[m][c] cin[m][c] (cin = the forward
 // coefficients) to rho[g].
 template <int L, bool ADJ>
-__global__ __launch_bounds__(64) void k_fold_solve(const ViewInfo* __restrict__ views, int n_views,
-                                                   const float* __restrict__ means,
-                                                   const float* __restrict__ VS, int vs_stride,
-                                                   int64_t N, int C, LamNB lam, float kappa_max,
-                                                   const float* __restrict__ rhs,
-                                                   const float* __restrict__ cin,
-                                                   float* __restrict__ coeffs,
-                                                   float* __restrict__ rho,
-                                                   uint8_t* __restrict__ status,
-                                                   float* __restrict__ wout,
-                                                   unsigned int* __restrict__ ill_count) {
+__global__ __launch_bounds__(256) void k_fold_solve(const ViewInfo* __restrict__ views, int n_views,
+                                                    const float* __restrict__ means,
+                                                    const float* __restrict__ VS, int vs_stride,
+                                                    int64_t N, int C, LamNB lam, float kappa_max,
+                                                    const float* __restrict__ rhs,
+                                                    const float* __restrict__ cin,
+                                                    float* __restrict__ coeffs,
+                                                    float* __restrict__ rho,
+                                                    uint8_t* __restrict__ status,
+                                                    float* __restrict__ wout,
+                                                    unsigned int* __restrict__ ill_count) {
     constexpr int NB = (L + 1) * (L + 1);
     constexpr int RPL = (NB + 3) / 4;  // rows per lane
-    constexpr int NL = NB * (NB + 1) / 2;  // packed lower triangle
-    __shared__ float stage[kStageFloats];
-    __shared__ float cen[kMaxStageViews][3];
-    __shared__ double Ls[16][NL];
-    __shared__ double Bs[16][NB * 4];
-    const int lane = threadIdx.x, q = lane >> 2, r = lane & 3;
-    const int64_t g0 = (int64_t)blockIdx.x * 16;
-    const int64_t g = g0 + q;
+    const int r = threadIdx.x & 3;
+    const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 2;
     const bool valid = g < N;
     const int stride = vs_stride;
-    const int per_view = 16 * stride;
-    const int vch = max(1, min(kMaxStageViews, kStageFloats / per_view));
-    const int64_t lim = N * (int64_t)stride;
     float mx = 0.f, my = 0.f, mz = 0.f;
     if (valid) {
         mx = means[3 * g];
@@ -119,8 +124,9 @@ __global__ __launch_bounds__(64) void k_fold_solve(const ViewInfo* __restrict__ 
     double sel[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) sel[e] = r == e ? 1.0 : 0.0;
-    double accA[RPL][NB];  // accA[k][j]: row 4k+r, column j <= 4k+r
-    double dinv[NB];       // reciprocal diagonal of the factor
+    // accA[k][j]: row 4k+r, column j <= 4k+r; after the factorisation the
+    // owner's diagonal entry holds 1/L_ii
+    double accA[RPL][NB];
     bool failed = false;
     double wsum = 0.0;
     double rho_part = 0.0;
@@ -136,67 +142,71 @@ __global__ __launch_bounds__(64) void k_fold_solve(const ViewInfo* __restrict__ 
             for (int c = 0; c < 4; ++c) accB[k][c] = 0.0;
         }
         double wv = 0.0;
-        for (int v0 = 0; v0 < ((!ADJ || firstc) ? n_views : 0); v0 += vch) {
-            const int nv = min(vch, n_views - v0);
-            __syncthreads();
-            // coalesced staging: for each view the block's 16 slots are
-            // contiguous; eight independent loads per lane are in flight
-            const int total = nv * per_view;
-            for (int base = lane; base < total; base += 64 * 8) {
-                float tmp[8];
+        const int nvw = (valid && (!ADJ || firstc)) ? n_views : 0;
+        const float* slot = VS + g * (int64_t)stride;
+        const int64_t vstep = N * (int64_t)stride;
+        constexpr int kGroup = 4;
+        float cV[kGroup], cS[kGroup][4], nV[kGroup], nS[kGroup][4];
+        auto load_group = [&](int v0, float (&gV)[kGroup], float (&gS)[kGroup][4]) {
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int idx = base + 64 * u;
-                    const int vv = idx / per_view, rr = idx - vv * per_view;
-                    const int64_t gi = g0 * stride + rr;
-                    tmp[u] = (idx < total && gi < lim) ? VS[(int64_t)(v0 + vv) * lim + gi] : 0.0f;
-                }
+            for (int u = 0; u < kGroup; ++u) {
+                const bool in = v0 + u < nvw;
+                const float* p = slot + (int64_t)(v0 + u) * vstep;
+                gV[u] = in ? p[0] : 0.0f;
 #pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    if (base + 64 * u < total) stage[base + 64 * u] = tmp[u];
+                for (int c = 0; c < 4; ++c) gS[u][c] = (in && !ADJ && c0 + c < C) ? p[1 + c0 + c] : 0.0f;
             }
-            for (int idx = lane; idx < nv; idx += 64) {
-                cen[idx][0] = (float)views[v0 + idx].centre[0];
-                cen[idx][1] = (float)views[v0 + idx].centre[1];
-                cen[idx][2] = (float)views[v0 + idx].centre[2];
-            }
-            __syncthreads();
-            if (!valid) continue;
+        };
+        load_group(0, cV, cS);
 #pragma unroll 1
-            for (int vv = 0; vv < nv; ++vv) {
-                const float* slot = stage + vv * per_view + q * stride;
-                const float Vf = slot[0];
-                if (Vf == 0.0f) continue;
-                const float dx = mx - cen[vv][0], dy = my - cen[vv][1], dz = mz - cen[vv][2];
-                const float inv = rsqrtf(dx * dx + dy * dy + dz * dz);
-                float phf[NB];
-                sh_eval<float, L>(dx * inv, dy * inv, dz * inv, phf);
-                double phi[NB];
+        for (int v0 = 0; v0 < nvw; v0 += kGroup) {
+            load_group(v0 + kGroup, nV, nS);
 #pragma unroll
-                for (int j = 0; j < NB; ++j) phi[j] = (double)phf[j];
-                const double Vd = Vf;
-                double S[4];
+            for (int u = 0; u < kGroup; u += 2) {
+                // two views at once: independent SH evaluations
+                float phf[2][NB];
+                double Vd[2];
 #pragma unroll
-                for (int c = 0; c < 4; ++c) S[c] = (!ADJ && c0 + c < C) ? (double)slot[1 + c0 + c] : 0.0;
+                for (int h = 0; h < 2; ++h) {
+                    const int v = v0 + u + h;
+                    const bool use = v < nvw && cV[u + h] != 0.0f;
+                    const int vv = v < nvw ? v : 0;
+                    const float dx = mx - (float)views[vv].centre[0];
+                    const float dy = my - (float)views[vv].centre[1];
+                    const float dz = mz - (float)views[vv].centre[2];
+                    const float inv = rsqrtf(dx * dx + dy * dy + dz * dz);
+                    sh_eval<float, L>(dx * inv, dy * inv, dz * inv, phf[h]);
+                    Vd[h] = use ? (double)cV[u + h] : 0.0;
+                }
 #pragma unroll
                 for (int k = 0; k < RPL; ++k) {
-                    // phi of this lane's row 4k + r, selected arithmetically
-                    double own = sel[0] * phi[4 * k];
 #pragma unroll
-                    for (int e = 1; e < 4; ++e)
-                        if (4 * k + e < NB) own = fma(sel[e], phi[4 * k + e < NB ? 4 * k + e : 0], own);
-                    if (firstc) {
-                        const double vo = Vd * own;
+                    for (int h = 0; h < 2; ++h) {
+                        double own = sel[0] * (double)phf[h][4 * k];
 #pragma unroll
-                        for (int j = 0; j < NB; ++j)
-                            if (j < 4 * k + 4) accA[k][j] = fma(vo, phi[j], accA[k][j]);
-                    }
-                    if constexpr (!ADJ) {
+                        for (int e = 1; e < 4; ++e)
+                            if (4 * k + e < NB) own = fma(sel[e], (double)phf[h][4 * k + e < NB ? 4 * k + e : 0], own);
+                        if (firstc) {
+                            const double vo = Vd[h] * own;
 #pragma unroll
-                        for (int c = 0; c < 4; ++c) accB[k][c] = fma(own, S[c], accB[k][c]);
+                            for (int j = 0; j < NB; ++j)
+                                if (j < 4 * k + 4) accA[k][j] = fma(vo, (double)phf[h][j], accA[k][j]);
+                        }
+                        if constexpr (!ADJ) {
+                            const double ow = Vd[h] != 0.0 ? own : 0.0;
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) accB[k][c] = fma(ow, (double)cS[u + h][c], accB[k][c]);
+                        }
                     }
                 }
-                wv += Vd;
+                wv += Vd[0];
+                wv += Vd[1];
+            }
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u) {
+                cV[u] = nV[u];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) cS[u][c] = nS[u][c];
             }
         }
         if (firstc) {
@@ -215,18 +225,32 @@ __global__ __launch_bounds__(64) void k_fold_solve(const ViewInfo* __restrict__ 
             // owning row m and every lane updates its own rows i >= m.
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
-                const double djj = quad_bcast_rt(accA[j >> 2][j], j & 3);
+                double djj;
+                switch (j & 3) {
+                    case 0: djj = quad_bcast<0>(accA[j >> 2][j]); break;
+                    case 1: djj = quad_bcast<1>(accA[j >> 2][j]); break;
+                    case 2: djj = quad_bcast<2>(accA[j >> 2][j]); break;
+                    default: djj = quad_bcast<3>(accA[j >> 2][j]); break;
+                }
                 const bool bad = !(djj > 0.0);
                 failed |= bad;
                 const double d = bad ? 1.0 : sqrt(djj);
                 const double id = 1.0 / d;
-                dinv[j] = id;
 #pragma unroll
                 for (int k = 0; k < RPL; ++k)
-                    if (4 * k + 3 > j) accA[k][j] = (4 * k + r > j) ? accA[k][j] * id : accA[k][j];
+                    if (4 * k + 3 >= j) {
+                        const int i = 4 * k + r;
+                        accA[k][j] = i > j ? accA[k][j] * id : (i == j ? id : accA[k][j]);
+                    }
 #pragma unroll
                 for (int m = j + 1; m < NB; ++m) {
-                    const double lmj = quad_bcast_rt(accA[m >> 2][j], m & 3);
+                    double lmj;
+                    switch (m & 3) {
+                        case 0: lmj = quad_bcast<0>(accA[m >> 2][j]); break;
+                        case 1: lmj = quad_bcast<1>(accA[m >> 2][j]); break;
+                        case 2: lmj = quad_bcast<2>(accA[m >> 2][j]); break;
+                        default: lmj = quad_bcast<3>(accA[m >> 2][j]); break;
+                    }
 #pragma unroll
                     for (int k = 0; k < RPL; ++k)
                         if (4 * k + 3 >= m) {  // rows 4k..4k+3 may reach column m
@@ -245,60 +269,92 @@ __global__ __launch_bounds__(64) void k_fold_solve(const ViewInfo* __restrict__ 
                     accB[k][c] = (valid && i < NB && c0 + c < C) ? (double)rhs[(g * NB + i) * C + c0 + c] : 0.0;
             }
         }
-        // factor (packed lower, diagonal stored as 1/L_ii) and right-hand sides to LDS
-        if (firstc) {
+        // forward substitution L y = b: y_j = b_j / L_jj is broadcast from its
+        // owner, and every lane updates its own rows m > j
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int kj = j >> 2;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double t = accB[kj][c] * accA[kj][j];
+                double yj;
+                switch (j & 3) {
+                    case 0: yj = quad_bcast<0>(t); break;
+                    case 1: yj = quad_bcast<1>(t); break;
+                    case 2: yj = quad_bcast<2>(t); break;
+                    default: yj = quad_bcast<3>(t); break;
+                }
+                accB[kj][c] = r == (j & 3) ? yj : accB[kj][c];
+#pragma unroll
+                for (int k = 0; k < RPL; ++k)
+                    if (4 * k + 3 > j) {
+                        const bool act = 4 * k + r > j && 4 * k + r < NB;
+                        accB[k][c] = act ? fma(-accA[k][j], yj, accB[k][c]) : accB[k][c];
+                    }
+            }
+        }
+        // back substitution L^T x = y: x_i = (y_i - sum_{k>i} L_ki x_k) / L_ii,
+        // the sum taken over each lane's solved rows, then over the quad
+#pragma unroll
+        for (int i = NB - 1; i >= 0; --i) {
+            const int ki = i >> 2;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                double p = 0.0;
+#pragma unroll
+                for (int k = 0; k < RPL; ++k)
+                    if (4 * k + 3 > i) {
+                        const bool act = 4 * k + r > i && 4 * k + r < NB;
+                        p = act ? fma(accA[k][i], accB[k][c], p) : p;
+                    }
+                p = quad_sum(p);
+                accB[ki][c] = r == (i & 3) ? (accB[ki][c] - p) * accA[ki][i] : accB[ki][c];
+            }
+        }
+        const bool zero = wsum == 0.0 || failed;
+        if (valid) {
+            float* out = coeffs + g * NB * C;
 #pragma unroll
             for (int k = 0; k < RPL; ++k) {
                 const int i = 4 * k + r;
+                if (i >= NB) continue;
 #pragma unroll
-                for (int j = 0; j < NB; ++j)
-                    if (j < 4 * k + 4 && i < NB && j <= i)
-                        Ls[q][i * (i + 1) / 2 + j] = (j == i) ? dinv[j] : accA[k][j];
+                for (int c = 0; c < 4; ++c) {
+                    if (c0 + c >= C) continue;
+                    out[i * C + c0 + c] = zero ? 0.0f : (float)accB[k][c];
+                    if constexpr (ADJ) {
+                        double lk = lam.v[4 * k];
+#pragma unroll
+                        for (int e = 1; e < 4; ++e)
+                            if (4 * k + e < NB) lk = r == e ? lam.v[4 * k + e < NB ? 4 * k + e : 0] : lk;
+                        if (!zero)
+                            rho_part = fma(lk * accB[k][c], (double)cin[(g * NB + i) * C + c0 + c],
+                                           rho_part);
+                    }
+                }
             }
         }
-#pragma unroll
-        for (int k = 0; k < RPL; ++k) {
-            const int i = 4 * k + r;
-            if (i < NB) {
-#pragma unroll
-                for (int c = 0; c < 4; ++c) Bs[q][i * 4 + c] = accB[k][c];
-            }
-        }
-        __syncthreads();
-        const int c = c0 + r;
-        if (valid && c < C) {
-            double* x = Bs[q] + r;
-            const double* Lq = Ls[q];
-#pragma unroll 1
-            for (int i = 0; i < NB; ++i) {
-                double s = x[i * 4];
-                const double* row = Lq + i * (i + 1) / 2;
-                for (int k = 0; k < i; ++k) s -= row[k] * x[k * 4];
-                x[i * 4] = s * row[i];
-            }
-#pragma unroll 1
-            for (int i = NB - 1; i >= 0; --i) {
-                double s = x[i * 4];
-                for (int k = i + 1; k < NB; ++k) s -= Lq[k * (k + 1) / 2 + i] * x[k * 4];
-                x[i * 4] = s * Lq[i * (i + 1) / 2 + i];
-            }
-            const bool zero = wsum == 0.0 || failed;
-            float* out = coeffs + g * NB * C;
-            for (int i = 0; i < NB; ++i) out[i * C + c] = zero ? 0.0f : (float)x[i * 4];
-            if constexpr (ADJ) {
-                if (!zero)
-                    for (int i = 0; i < NB; ++i)
-                        rho_part = fma(lam.v[i] * x[i * 4], (double)cin[(g * NB + i) * C + c], rho_part);
-            }
-        }
-        __syncthreads();
     }
     if constexpr (ADJ) {
-        rho_part += __shfl_xor(rho_part, 1, 64);
-        rho_part += __shfl_xor(rho_part, 2, 64);
+        rho_part = quad_sum(rho_part);
         if (valid && r == 0) rho[g] = (float)rho_part;
         return;
     }
+    // condition estimate from the extremes of 1/L_ii over the quad
+    double imax = 0.0, imin = 1e300;
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) {
+        double dk = accA[k][4 * k];
+#pragma unroll
+        for (int e = 1; e < 4; ++e)
+            if (4 * k + e < NB) dk = r == e ? accA[k][4 * k + e < NB ? 4 * k + e : 0] : dk;
+        if (4 * k + r < NB) {
+            imax = fmax(imax, dk);
+            imin = fmin(imin, dk);
+        }
+    }
+    imax = quad_max(imax);
+    imin = -quad_max(-imin);
     if (valid && r == 0) {
         if (wout) wout[g] = (float)wsum;
         uint8_t st = 0;
@@ -307,12 +363,6 @@ __global__ __launch_bounds__(64) void k_fold_solve(const ViewInfo* __restrict__ 
         } else if (failed) {
             st = GSC_G_FAILED;
         } else {
-            double imax = 0.0, imin = 1e300;  // extremes of 1/L_ii
-#pragma unroll
-            for (int i = 0; i < NB; ++i) {
-                imax = fmax(imax, dinv[i]);
-                imin = fmin(imin, dinv[i]);
-            }
             const double kap = (imax / imin) * (imax / imin);
             if (kap > (double)kappa_max) {
                 st = GSC_G_ILL_COND;
@@ -344,7 +394,7 @@ void launch_fold_solve(const ViewInfo* views, int n_views, const float* means, c
     for (int i = 0; i < kMaxNb; ++i) lam.v[i] = 0.0;
     int nb = (sh_deg + 1) * (sh_deg + 1);
     for (int i = 0; i < nb; ++i) lam.v[i] = lam_nb[i];
-    dim3 grid((unsigned)((N + 15) / 16)), block(64);
+    dim3 grid((unsigned)((N + 63) / 64)), block(256);
     const float* nf = nullptr;
     float* nw = nullptr;
     switch (sh_deg) {
@@ -390,7 +440,7 @@ void launch_adjoint_solve(const ViewInfo* views, int n_views, const float* means
     for (int i = 0; i < kMaxNb; ++i) lam.v[i] = 0.0;
     int nb = (sh_deg + 1) * (sh_deg + 1);
     for (int i = 0; i < nb; ++i) lam.v[i] = lam_nb[i];
-    dim3 grid((unsigned)((N + 15) / 16)), block(64);
+    dim3 grid((unsigned)((N + 63) / 64)), block(256);
     uint8_t* ns = nullptr;
     float* nw = nullptr;
     unsigned int* ni = nullptr;
