@@ -122,6 +122,11 @@ typedef struct {
     int32_t bin_size; /* 0 (automatic), 16 or 32: pixels per side of the screen
                          bins the Gaussians are sorted into; the result does not
                          depend on it (the footprint test is per pixel) */
+    int32_t accumulate_variant; /* 0 (automatic) or a variant code of the blend +
+                         accumulate launch: channels per launch (1, 2, 3, 4, 8, 16),
+                         or 128 + 16, 32 or 64 for the matrix-core form, which
+                         applies to BF16 targets only (other targets then use
+                         the automatic choice).  A tuned plan uses its own. */
 } gsc_options;
 
 typedef struct {
@@ -277,7 +282,9 @@ typedef struct {
     uint32_t views;             /* views per run */
     int32_t bin_size;           /* screen bin size of the plan (16 or 32 pixels) */
     int32_t accumulate_variant; /* accumulate launch shape in use: channels per launch,
-                                   plus 256 for the persistent work-queue launch */
+                                   plus 128 for the matrix-core form (BF16 targets;
+                                   16, 32 or 64 channels per launch), plus 256 for the
+                                   persistent work-queue launch */
     int32_t tuned_variant[8];   /* shapes timed by gsc_plan_autotune (0: unused) */
     float tuned_ms[8];          /* their accumulate time per run, ms */
 } gsc_plan_info;
@@ -312,9 +319,10 @@ gsc_status gsc_colorize_batched(gsc_plan* plan, const void* targets, int32_t tdt
 
 /*
  * Autotune the plan's accumulate launch shape on the given inputs: channels
- * per launch (each launch re-blends the tiles for its channel chunk) and the
- * grid form (one block per four tiles, or a persistent grid whose waves take
- * tiles from a queue).  Times each candidate over all view batches, keeps the
+ * per launch (each launch re-blends the tiles for its channel chunk), the
+ * arithmetic (vector lanes, or for BF16 targets matrix cores on blocks of 16
+ * channels) and the grid form (one block per few tiles, or a persistent grid
+ * whose waves take tiles from a queue).  Times each candidate over all view batches, keeps the
  * fastest, then runs the plan once more so that coeffs/status hold a clean
  * result.  Synchronises `stream`.  Not capturable.
  */

@@ -157,6 +157,9 @@ gsc_status validate_options(const gsc_options* o) {
     if (!(o->kappa_max > 0.0f)) return fail(GSC_ERR_INVALID_ARG, "kappa_max must be > 0");
     if (!(o->bin_size == 0 || o->bin_size == 16 || o->bin_size == 32))
         return fail(GSC_ERR_INVALID_ARG, "bin_size must be 0, 16 or 32");
+    if (o->accumulate_variant != 0 && !accumulate_chunk_valid(o->accumulate_variant, GSC_F32) &&
+        !accumulate_chunk_valid(o->accumulate_variant, GSC_BF16))
+        return fail(GSC_ERR_INVALID_ARG, "accumulate_variant %d is not a variant code", o->accumulate_variant);
     return GSC_OK;
 }
 
@@ -487,7 +490,8 @@ struct gsc_plan {
     uint32_t max_items = 0, max_pairs = 0, max_tiles = 0;
     uint64_t items_total = 0, pairs_total = 0;
     int bin = 16;                     // bin size in pixels
-    int acc_chunk = 0;                // channels per accumulate launch (0: default)
+    int acc_chunk = 0;                // accumulate variant (0: default for the targets' type)
+    int last_tdtype = GSC_F32;        // target type of the last run
     bool acc_persistent = false;      // persistent work-queue accumulate
     float tune_ms[8] = {};
     int tune_variant[8] = {};
@@ -639,6 +643,7 @@ gsc_status plan_solve(gsc_plan* P, const double* lam, float* coeffs, uint8_t* st
 
 gsc_status plan_run(gsc_plan* P, const void* targets, int tdtype, const double* lam, float* coeffs,
                     uint8_t* status, hipStream_t s) {
+    P->last_tdtype = tdtype;
     launch_fill_u32(P->misc.as<uint32_t>(), 0u, 6, s);
     launch_fill_u32(P->vs.as<uint32_t>(), 0u, P->vs_slots * (uint64_t)(P->C + 1), s);
     launch_cov3d(P->scales, P->quats, P->cov.as<float>(), P->n_total, s);
@@ -647,7 +652,8 @@ gsc_status plan_run(gsc_plan* P, const void* targets, int tdtype, const double* 
         gsc_status st = plan_bin_batch(P, b, s);
         if (st != GSC_OK) return st;
         StageTimer t(P->ctx, s, GSC_STAGE_BLEND);
-        if ((st = plan_accumulate(P, b, targets, tdtype, P->acc_chunk, P->acc_persistent, s)) != GSC_OK)
+        const int chunk = P->acc_chunk ? P->acc_chunk : P->ctx->opt.accumulate_variant;
+        if ((st = plan_accumulate(P, b, targets, tdtype, chunk, P->acc_persistent, s)) != GSC_OK)
             return st;
     }
     return plan_solve(P, lam, coeffs, status, s);
@@ -668,6 +674,7 @@ gsc_status gsc_default_options(gsc_options* out) {
     out->kappa_max = 1e6f;
     out->flags = 0;
     out->bin_size = 0;
+    out->accumulate_variant = 0;
     return GSC_OK;
 }
 
@@ -733,12 +740,15 @@ gsc_status gsc_colorize_ex(gsc_ctx* ctx, const float* means, const float* scales
     unsigned long long* d_counter = reinterpret_cast<unsigned long long*>(ctx->misc.p);
     st = for_view_batches(ctx, all, n_cams, means, opacities, N, bp, s,
                           [&](int v0, int nv, const Binned& bn) -> gsc_status {
-        StageTimer t(ctx, s, GSC_STAGE_BLEND, (uint32_t)((C + accumulate_chunk(C) - 1) / accumulate_chunk(C)));
+        const int chunk = accumulate_chunk_valid(ctx->opt.accumulate_variant, tdtype)
+                              ? ctx->opt.accumulate_variant
+                              : accumulate_chunk(C, tdtype);
+        StageTimer t(ctx, s, GSC_STAGE_BLEND, (uint32_t)accumulate_launches(C, chunk));
         (void)v0;
-        launch_accumulate(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
-                          ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(), ctx->rec2.as<uint2>(), ctx->bin,
-                          targets, tdtype, C, per_view, bp, ctx->vs.as<float>(), d_counter,
-                          x_cnt, s);
+        launch_accumulate_chunked(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
+                                  ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(),
+                                  ctx->rec2.as<uint2>(), ctx->bin, targets, tdtype, C, per_view, bp,
+                                  ctx->vs.as<float>(), d_counter, x_cnt, chunk, s);
         GSC_LAUNCHED("accumulate");
         return GSC_OK;
     });
@@ -1150,8 +1160,14 @@ gsc_status gsc_plan_autotune(gsc_plan* plan, const void* targets, int32_t tdtype
     // candidates: (channels per launch, persistent or not); the default split
     // of C plus wider and narrower chunks
     std::vector<int> chunks;
-    for (int c : {accumulate_chunk(plan->C), 16, 8, 4})
-        if (std::find(chunks.begin(), chunks.end(), c) == chunks.end() && c <= std::max(4, plan->C))
+    std::vector<int> pool;
+    if (tdtype == GSC_BF16)  // matrix-core forms up to the channels needed
+        for (int ch : {16, 32, 64})
+            if (ch < plan->C + 16) pool.push_back(kChunkMfma | ch);
+    for (int c : {accumulate_chunk(plan->C, GSC_F32), 16, 8, 4}) pool.push_back(c);
+    for (int c : pool)
+        if (std::find(chunks.begin(), chunks.end(), c) == chunks.end() &&
+            chunk_channels(c) <= std::max(4, plan->C + ((c & kChunkMfma) ? 15 : 0)))
             chunks.push_back(c);
     std::vector<int> cand;  // chunk | persistent << 8
     for (int c : chunks)
@@ -1222,7 +1238,10 @@ gsc_status gsc_plan_get_info(gsc_plan* plan, gsc_plan_info* out) {
     out->items = plan->items_total;
     out->pair_capacity = plan->pairs_total;
     out->bin_size = plan->bin;
-    out->accumulate_variant = (plan->acc_chunk ? plan->acc_chunk : accumulate_chunk(plan->C)) |
+    const int chosen = plan->acc_chunk ? plan->acc_chunk : plan->ctx->opt.accumulate_variant;
+    out->accumulate_variant = (accumulate_chunk_valid(chosen, plan->last_tdtype)
+                                   ? chosen
+                                   : accumulate_chunk(plan->C, plan->last_tdtype)) |
                               (plan->acc_persistent ? 256 : 0);
     for (int i = 0; i < 8; ++i) {
         out->tuned_variant[i] = plan->tune_variant[i];

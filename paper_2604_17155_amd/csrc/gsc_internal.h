@@ -121,8 +121,17 @@ void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* va
                 uint32_t n, int bits, uint32_t* scratch, hipStream_t s,
                 const uint32_t* n_dev = nullptr);
 
-// Channels per accumulate launch for C channels (launches = ceil(C / chunk)).
-int accumulate_chunk(int C);
+// Accumulate variants ("chunks"): the channels per launch (launches =
+// ceil(C / channels)), plus kChunkMfma for the matrix-core form (BF16
+// targets; 16, 32 or 64 channels per launch).
+constexpr int kChunkMfma = 128;
+inline int chunk_channels(int chunk) { return chunk & (kChunkMfma - 1); }
+inline int accumulate_launches(int C, int chunk) {
+    const int ch = chunk_channels(chunk);
+    return (C + ch - 1) / ch;
+}
+// Default variant for C channels of targets of type tdtype.
+int accumulate_chunk(int C, int tdtype);
 
 // Accumulate V_gj and S_gj into slot (view.vs_base + g) when per_view, else
 // into slot (view.g_offset + g), summed over views; slots hold C+1 floats.
@@ -131,13 +140,14 @@ void launch_accumulate(const ViewInfo* views, int n_views, uint32_t n_tiles, con
                        const void* targets, int tdtype, int C, bool per_view, BlendParams bp,
                        float* VS, unsigned long long* counter, uint32_t* gcount, hipStream_t s);
 
-// As launch_accumulate with `chunk` channels per launch (1, 2, 3, 4, 8 or 16;
-// anything else picks accumulate_chunk(C)).  queues (device, one word per
+// As launch_accumulate with accumulate variant `chunk` (1, 2, 3, 4, 8 or 16
+// channels per launch, or kChunkMfma | 16, 32 or 64 for BF16 targets;
+// anything else picks accumulate_chunk(C, tdtype)).  queues (device, one word per
 // channel pass, zeroed here by a fill kernel): persistent launches of
 // kPersistentBlocks blocks that take tiles from a counter; nullptr: one
 // block per four tiles.
 constexpr uint32_t kPersistentBlocks = 2048;  // 8 blocks of 4 waves per CU
-bool accumulate_chunk_valid(int chunk);
+bool accumulate_chunk_valid(int chunk, int tdtype);
 void launch_accumulate_chunked(const ViewInfo* views, int n_views, uint32_t n_tiles,
                                const uint2* ranges, const uint32_t* pair_vals, const float4* rec0,
                                const float4* rec1, const uint2* rec2, int bin, const void* targets, int tdtype, int C,

@@ -36,6 +36,9 @@ __device__ __forceinline__ uint32_t accumulate_tile(
     constexpr int CCA = CC > 0 ? CC : 1;
     const TileGeom tg = tile_geom<BIN>(tile, views, n_views);
     const ViewInfo& V = views[tg.vloc];
+    // view fields read once (plain values: the conditions below need no branch)
+    const int vw = V.width, vh = V.height;
+    const int64_t poff = V.pixel_offset;
     const int ix = tg.x0 + (int)(lane & 15);
     const int iy0 = tg.y0 + (int)(lane >> 4);
     const float px = (float)ix + 0.5f;
@@ -47,13 +50,18 @@ __device__ __forceinline__ uint32_t accumulate_tile(
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int iy = iy0 + 4 * k;
-        const bool inside = ix < V.width && iy < V.height;
+        const bool inside = (ix < vw) & (iy < vh);
         T[k] = inside ? 1.0f : 0.0f;
         alive |= (__builtin_amdgcn_ballot_w64(inside) != 0 ? 1u : 0u) << k;
-        const int64_t row = V.pixel_offset + (int64_t)iy * V.width + ix;
+        const int64_t row = poff + (int64_t)iy * vw + ix;
+        // unconditional loads (element 0 stands in for pixels outside the
+        // image): no branch per load
 #pragma unroll
-        for (int c = 0; c < CC; ++c)
-            y[k][c] = (inside && c_off + c < C) ? load_target<BF16>(targets, row * C + c_off + c) : 0.0f;
+        for (int c = 0; c < CC; ++c) {
+            const bool use = inside && c_off + c < C;
+            const float v = load_target<BF16>(targets, use ? row * C + c_off + c : 0);
+            y[k][c] = use ? v : 0.0f;
+        }
     }
     alive = (uint32_t)__builtin_amdgcn_readfirstlane((int)alive);
     uint2 rg = ranges[tg.bin];
@@ -258,9 +266,328 @@ static void launch_acc_cc(const ViewInfo* views, int n_views, uint32_t n_bins, c
 #undef GSC_ACCK
 }
 
-int accumulate_chunk(int C) { return C <= 3 ? C : (C <= 4 ? 4 : (C <= 8 ? 8 : 16)); }
+// ---- matrix-core accumulate (BF16 targets, channel blocks of 16) ----------
+//
+// The channel sums S_g[c] = sum_p w_gp y_p[c] of a tile are a product
+// W (Gaussians x pixels) . Y (pixels x channels).  Here the blend runs as in
+// accumulate_tile, but each entry's weights go to LDS as a row of W, split
+// into a BF16 high part and a BF16 remainder (w = hi + lo to ~2^-17
+// relative).  Every 16 entries, v_mfma_f32_16x16x32_bf16 forms
+// (W_hi + W_lo) . [Y | 1] over the tile's 256 pixels (eight K-steps of 32
+// pixels): the targets, held as B operands in registers for the whole tile,
+// give S, and a block of ones gives V = sum_p w from the same split weights.
+// (With one channel block, groups of 8 entries fill rows 0..7 only.)
+// K index k = 32 s + 8 (lane / 16) + i of K-step s is tile pixel k (row k/16,
+// column k%16); the blend's lane l owns pixels l + 64 j, j = 0..3.
 
-bool accumulate_chunk_valid(int chunk) {
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kWRow = 264;       // LDS row of W in BF16 elements (256 + padding against bank conflicts)
+constexpr int kMfmaWaves = 2;    // waves per block
+
+// W rows of one wave: ROWS list entries per matrix product (8 or 16; with 8,
+// rows 8..15 of the A operand are zero and less LDS per wave leaves room for
+// more waves).
+template <int ROWS>
+struct alignas(16) MfmaLds {
+    __bf16 whi[ROWS * kWRow];
+    __bf16 wlo[ROWS * kWRow];
+    uint32_t gslot[ROWS];  // local Gaussian of each group row (0xFFFFFFFF: no contribution)
+};
+
+template <int NBLK>
+constexpr int mfma_rows() { return NBLK == 1 ? 8 : 16; }
+
+template <int NBLK, int BIN>
+__device__ __forceinline__ uint32_t accumulate_tile_mfma(
+    uint32_t tile, uint32_t lane, MfmaLds<mfma_rows<NBLK>()>& L, const ViewInfo* __restrict__ views, int n_views,
+    const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_vals,
+    const float4* __restrict__ rec0, const float4* __restrict__ rec1, const uint2* __restrict__ rec2,
+    const uint16_t* __restrict__ targets, int C, int c_off, int per_view, const BlendParams& bp,
+    float* __restrict__ VS, uint32_t* __restrict__ gcount) {
+    const TileGeom tg = tile_geom<BIN>(tile, views, n_views);
+    const ViewInfo& V = views[tg.vloc];
+    // view fields read once (plain values: the conditions below need no branch)
+    const int vw = V.width, vh = V.height;
+    const int64_t poff = V.pixel_offset;
+    const int ix = tg.x0 + (int)(lane & 15);
+    const int iy0 = tg.y0 + (int)(lane >> 4);
+    const float px = (float)ix + 0.5f;
+    const int stride = C + 1;
+    const uint32_t n16 = lane & 15, q4 = lane >> 4;
+    constexpr int ROWS = mfma_rows<NBLK>();
+
+    // targets of the tile as B operands: Y[s][b] holds pixels 32 s + 8 q4 + i
+    // (tile row 2 s + q4/2, columns 8 (q4&1) + i) of channel c_off + 16 b + n16
+    bf16x8_t Y[8][NBLK];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const int gy = tg.y0 + 2 * s + (int)(q4 >> 1);
+        const int gx0 = tg.x0 + 8 * (int)(q4 & 1u);
+#pragma unroll
+        for (int b = 0; b < NBLK; ++b) {
+            const int c = c_off + 16 * b + (int)n16;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int gx = gx0 + i;
+                const bool in = (gx < vw) & (gy < vh) & (c < C);
+                const int64_t row = poff + (int64_t)gy * vw + gx;
+                // unconditional load (element 0 stands in outside): no branch
+                const uint16_t u = targets[in ? row * C + c : 0];
+                Y[s][b][i] = __builtin_bit_cast(__bf16, in ? u : (uint16_t)0);
+            }
+        }
+    }
+    bf16x8_t ones;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) ones[i] = (__bf16)1.0f;
+
+    float T[4];
+    uint32_t alive = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const bool inside = (ix < vw) & (iy0 + 4 * k < vh);
+        T[k] = inside ? 1.0f : 0.0f;
+        alive |= (__builtin_amdgcn_ballot_w64(inside) != 0 ? 1u : 0u) << k;
+    }
+    alive = (uint32_t)__builtin_amdgcn_readfirstlane((int)alive);
+    uint2 rg = ranges[tg.bin];
+    rg.x = (uint32_t)__builtin_amdgcn_readfirstlane((int)rg.x);
+    rg.y = (uint32_t)__builtin_amdgcn_readfirstlane((int)rg.y);
+    uint32_t cnt = 0;
+    const int64_t item_base = V.item_base;
+    const int64_t slot_base = per_view ? V.vs_base : V.g_offset;
+    const int64_t g_off = V.g_offset;
+    const bool first_chunk = c_off == 0;
+    const float qlim = (float)(kExp2Scale * (double)bp.cut2);
+    const float amax = bp.alpha_max, amin = bp.alpha_min, tmin = bp.t_min;
+    float pyk[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pyk[k] = (float)(iy0 + 4 * k) + 0.5f;
+
+    // W rows start (and are left) zero
+    {
+        uint4* wz = reinterpret_cast<uint4*>(&L.whi[0]);
+        constexpr int n4 = 2 * ROWS * kWRow * 2 / 16;  // both planes
+        for (int i = (int)lane; i < n4; i += 64) wz[i] = make_uint4(0u, 0u, 0u, 0u);
+        __builtin_amdgcn_wave_barrier();
+    }
+
+    // one matrix product over the group's `rows` entries, then the atomics
+    auto flush = [&](uint32_t rows) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        floatx4_t D[NBLK], DV;
+#pragma unroll
+        for (int b = 0; b < NBLK; ++b) D[b] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+        DV = floatx4_t{0.f, 0.f, 0.f, 0.f};
+        const uint32_t arow = n16 < (uint32_t)ROWS ? n16 : 0u;
+        const __bf16* ah_p = &L.whi[arow * kWRow + 8 * q4];
+        const __bf16* al_p = &L.wlo[arow * kWRow + 8 * q4];
+        bf16x8_t zero8;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) zero8[i] = (__bf16)0.0f;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            bf16x8_t ah = *reinterpret_cast<const bf16x8_t*>(ah_p + 32 * s);
+            bf16x8_t al = *reinterpret_cast<const bf16x8_t*>(al_p + 32 * s);
+            if (ROWS < 16 && n16 >= (uint32_t)ROWS) {
+                ah = zero8;
+                al = zero8;
+            }
+            if (first_chunk) {
+                DV = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, ones, DV, 0, 0, 0);
+                DV = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, ones, DV, 0, 0, 0);
+            }
+#pragma unroll
+            for (int b = 0; b < NBLK; ++b) {
+                D[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, Y[s][b], D[b], 0, 0, 0);
+                D[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, Y[s][b], D[b], 0, 0, 0);
+            }
+        }
+        // lane holds rows 4 q4 + i, column n16
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t m = 4 * q4 + (uint32_t)i;
+            if (m >= rows) continue;
+            const uint32_t gl = L.gslot[m];
+            if (gl == 0xFFFFFFFFu) continue;
+            float* slot = VS + (slot_base + (int64_t)gl) * (int64_t)stride;
+            if (first_chunk && n16 == 0) unsafeAtomicAdd(slot, DV[i]);
+#pragma unroll
+            for (int b = 0; b < NBLK; ++b) {
+                const int c = c_off + 16 * b + (int)n16;
+                if (c < C) unsafeAtomicAdd(slot + 1 + c, D[b][i]);
+            }
+        }
+        // clear the rows used
+        __builtin_amdgcn_wave_barrier();
+        uint4* wh = reinterpret_cast<uint4*>(&L.whi[0]);
+        uint4* wl = reinterpret_cast<uint4*>(&L.wlo[0]);
+        const uint32_t n4 = rows * kWRow * 2 / 16;
+        for (uint32_t i = lane; i < n4; i += 64) {
+            wh[i] = make_uint4(0u, 0u, 0u, 0u);
+            wl[i] = make_uint4(0u, 0u, 0u, 0u);
+        }
+        __builtin_amdgcn_wave_barrier();
+    };
+
+    // list walk: chunks of 64 entries gathered one per lane; the entries whose
+    // footprint can reach a live band of this tile are taken in order
+    auto load_pv = [&](uint32_t b) -> uint32_t { return b + lane < rg.y ? pair_vals[b + lane] : 0u; };
+    uint32_t b = rg.x;
+    uint32_t pv = load_pv(b);
+    float4 R0 = make_float4(0.f, 0.f, 0.f, 0.f), R1 = R0;
+    uint2 R2 = make_uint2(0u, 0u);
+    auto gather = [&](uint32_t p, uint32_t base) {
+        const uint32_t it = p & kItemMask;
+        const bool own = base + lane < rg.y && pair_reaches<BIN>(p, tg.quad, alive);
+        R0 = own ? rec0[it] : make_float4(0.f, 0.f, 0.f, 0.f);
+        R1 = own ? rec1[it] : make_float4(0.f, 0.f, 0.f, 0.f);
+        R2 = own ? rec2[it] : make_uint2(0u, 0u);
+    };
+    uint64_t sm = 0;  // entries of the chunk still to take
+    auto survivors = [&]() -> uint64_t {
+        const bool own = b + lane < rg.y && pair_reaches<BIN>(pv, tg.quad, alive);
+        const uint32_t bl = entry_bands<BIN>(pv, tg.quad, R2.x, tg.y0) & alive;
+        return __builtin_amdgcn_ballot_w64(own && bl != 0u);
+    };
+    if (b < rg.y) {
+        gather(pv, b);
+        sm = survivors();
+    }
+    uint32_t rows = 0;
+    while (alive != 0u) {
+        if (sm == 0) {
+            b += 64;
+            if (b >= rg.y) break;
+            pv = load_pv(b);
+            gather(pv, b);
+            sm = survivors();
+            continue;
+        }
+        const uint32_t j = (uint32_t)__builtin_ctzll(sm);
+        sm &= sm - 1;
+        const uint32_t pc = bcast_u(pv, j);
+        const uint2 e2 = make_uint2(bcast_u(R2.x, j), bcast_u(R2.y, j));
+        const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2.x, tg.y0) & alive;
+        if (bands == 0u) continue;
+        const float4 c0 = make_float4(bcast(R0.x, j), bcast(R0.y, j), bcast(R0.z, j), bcast(R0.w, j));
+        const float4 c1 = make_float4(bcast(R1.x, j), bcast(R1.y, j), bcast(R1.z, j), bcast(R1.w, j));
+        const float dx = (px - c0.x) - c0.z;
+        const float a0 = c1.x * dx * dx;
+        const float b0 = c1.y * dx;
+        uint32_t nh = 0;
+        __bf16* wrow_h = &L.whi[rows * kWRow];
+        __bf16* wrow_l = &L.wlo[rows * kWRow];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (!((bands >> k) & 1u)) continue;  // uniform
+            const float dy = (pyk[k] - c0.y) - c0.w;
+            const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
+            const float al = __builtin_amdgcn_fmed3f(c1.w * __builtin_amdgcn_exp2f(q2), 0.0f, amax);
+            const float test = fmaf(-T[k], al, T[k]);
+            const bool cand = q2 >= qlim && al >= amin && T[k] > 0.0f;
+            const bool keep = test >= tmin;
+            const bool take = cand && keep;
+            const float w = take ? al * T[k] : 0.0f;
+            T[k] = cand ? (keep ? test : 0.0f) : T[k];
+            const __bf16 hi = (__bf16)w;
+            const __bf16 lo = (__bf16)(w - (float)hi);
+            wrow_h[lane + 64 * k] = hi;
+            wrow_l[lane + 64 * k] = lo;
+            nh += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(take));
+            if (__builtin_amdgcn_ballot_w64(T[k] > 0.0f) == 0) alive &= ~(1u << k);
+        }
+        alive = (uint32_t)__builtin_amdgcn_readfirstlane((int)alive);
+        nh = (uint32_t)__builtin_amdgcn_readfirstlane((int)nh);
+        cnt += nh;
+        const uint32_t gl = (uint32_t)((int64_t)e2.y - item_base);
+        if (lane == 0) L.gslot[rows] = nh != 0u ? gl : 0xFFFFFFFFu;
+        if (nh != 0u && gcount != nullptr && first_chunk && lane == 0) atomicAdd(gcount + g_off + gl, nh);
+        if (++rows == (uint32_t)ROWS) {
+            flush(rows);
+            rows = 0;
+        }
+    }
+    if (rows != 0u) flush(rows);
+    return cnt;
+}
+
+template <int NBLK, int BIN>
+__global__ __launch_bounds__(64 * kMfmaWaves) void k_accumulate_mfma(
+    const ViewInfo* __restrict__ views, int n_views, uint32_t n_tiles, const uint2* __restrict__ ranges,
+    const uint32_t* __restrict__ pair_vals, const float4* __restrict__ rec0,
+    const float4* __restrict__ rec1, const uint2* __restrict__ rec2,
+    const uint16_t* __restrict__ targets, int C, int c_off, int per_view, BlendParams bp,
+    float* __restrict__ VS, unsigned long long* __restrict__ counter, uint32_t* __restrict__ gcount,
+    uint32_t* __restrict__ queue) {
+    __shared__ MfmaLds<mfma_rows<NBLK>()> lds[kMfmaWaves];
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t cnt = 0;
+    if (queue == nullptr) {
+        const uint32_t tile = blockIdx.x * kMfmaWaves + w;
+        if (tile >= n_tiles) return;  // whole wave
+        cnt = accumulate_tile_mfma<NBLK, BIN>(tile, lane, lds[w], views, n_views, ranges, pair_vals,
+                                              rec0, rec1, rec2, targets, C, c_off, per_view, bp, VS,
+                                              gcount);
+    } else {
+        for (;;) {
+            uint32_t t = 0;
+            if (lane == 0) t = atomicAdd(queue, 1u);
+            const uint32_t tile = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
+            if (tile >= n_tiles) break;  // uniform: every wave ends here
+            cnt += accumulate_tile_mfma<NBLK, BIN>(tile, lane, lds[w], views, n_views, ranges,
+                                                   pair_vals, rec0, rec1, rec2, targets, C, c_off,
+                                                   per_view, bp, VS, gcount);
+        }
+    }
+    if (c_off == 0 && lane == 0 && cnt) atomicAdd(counter, (unsigned long long)cnt);
+}
+
+template <int NBLK, int BIN>
+static void launch_acc_mfma(const ViewInfo* views, int n_views, uint32_t n_wt, const uint2* ranges,
+                            const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
+                            const uint2* rec2, const void* targets, int C, bool per_view,
+                            BlendParams bp, float* VS, unsigned long long* counter, uint32_t* gcount,
+                            uint32_t* queues, hipStream_t s) {
+    const uint32_t full = (n_wt + kMfmaWaves - 1) / kMfmaWaves;
+    dim3 grid(queues ? std::min(full, 2 * kPersistentBlocks) : full), block(64 * kMfmaWaves);
+    int pass = 0;
+    for (int c_off = 0; c_off < C; c_off += 16 * NBLK, ++pass) {
+        uint32_t* q = queues ? queues + pass : nullptr;
+        hipLaunchKernelGGL((k_accumulate_mfma<NBLK, BIN>), grid, block, 0, s, views, n_views, n_wt,
+                           ranges, pair_vals, rec0, rec1, rec2, (const uint16_t*)targets, C, c_off,
+                           (int)per_view, bp, VS, counter, gcount, q);
+    }
+}
+
+template <int NBLK>
+static void launch_acc_mfma_bin(const ViewInfo* views, int n_views, uint32_t n_bins, const uint2* ranges,
+                                const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
+                                const uint2* rec2, int bin, const void* targets, int C, bool per_view,
+                                BlendParams bp, float* VS, unsigned long long* counter,
+                                uint32_t* gcount, uint32_t* queues, hipStream_t s) {
+    const uint32_t n_wt = wave_tiles(n_bins, bin);
+    if (bin == 32)
+        launch_acc_mfma<NBLK, 32>(views, n_views, n_wt, ranges, pair_vals, rec0, rec1, rec2, targets, C,
+                                  per_view, bp, VS, counter, gcount, queues, s);
+    else
+        launch_acc_mfma<NBLK, 16>(views, n_views, n_wt, ranges, pair_vals, rec0, rec1, rec2, targets, C,
+                                  per_view, bp, VS, counter, gcount, queues, s);
+}
+
+int accumulate_chunk(int C, int tdtype) {
+    if (tdtype == GSC_BF16 && C >= 16) return kChunkMfma | (C <= 16 ? 16 : (C <= 32 ? 32 : 64));
+    return C <= 3 ? C : (C <= 4 ? 4 : (C <= 8 ? 8 : 16));
+}
+
+bool accumulate_chunk_valid(int chunk, int tdtype) {
+    if (chunk & kChunkMfma) {
+        const int ch = chunk_channels(chunk);
+        return tdtype == GSC_BF16 && chunk == (kChunkMfma | ch) && (ch == 16 || ch == 32 || ch == 64);
+    }
     return chunk == 1 || chunk == 2 || chunk == 3 || chunk == 4 || chunk == 8 || chunk == 16;
 }
 
@@ -282,8 +609,20 @@ void launch_accumulate_chunked(const ViewInfo* views, int n_views, uint32_t n_ti
                                BlendParams bp, float* VS, unsigned long long* counter,
                                uint32_t* gcount, int chunk, hipStream_t s, uint32_t* queues) {
     if (n_tiles == 0) return;
-    if (!accumulate_chunk_valid(chunk)) chunk = accumulate_chunk(C);
-    if (queues) launch_fill_u32(queues, 0u, (uint64_t)((C + chunk - 1) / chunk), s);
+    if (!accumulate_chunk_valid(chunk, tdtype)) chunk = accumulate_chunk(C, tdtype);
+    if (queues) launch_fill_u32(queues, 0u, (uint64_t)accumulate_launches(C, chunk), s);
+    if (chunk & kChunkMfma) {
+#define GSC_ACCM(NB)                                                                               \
+    launch_acc_mfma_bin<NB>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, rec2, bin,     \
+                            targets, C, per_view, bp, VS, counter, gcount, queues, s)
+        switch (chunk_channels(chunk)) {
+            case 16: GSC_ACCM(1); break;
+            case 32: GSC_ACCM(2); break;
+            default: GSC_ACCM(4); break;
+        }
+#undef GSC_ACCM
+        return;
+    }
 #define GSC_ACC(CCV)                                                                                \
     launch_acc_cc<CCV>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, rec2, bin, targets, \
                        tdtype, C, per_view, bp, VS, counter, gcount, queues, s)

@@ -345,7 +345,7 @@ static void launch_badj(const ViewInfo* views, int n_views, uint32_t n_tiles, co
 #define GSC_BA(CCV)                                                                                \
     launch_badj_cc<CCV, GY>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, rec2, bin, ypix, \
                             ydtype, C, beta, bp, grad_y, grad_o, s)
-    switch (accumulate_chunk(C)) {
+    switch (accumulate_chunk(C, GSC_F32)) {  // vector-lane channel chunks
         case 1: GSC_BA(1); break;
         case 2: GSC_BA(2); break;
         case 3: GSC_BA(3); break;

@@ -188,6 +188,16 @@ __device__ __forceinline__ uint32_t entry_bands(uint32_t pc, uint32_t quad, uint
     }
 }
 
+// Whether a list entry can reach a live band of this tile judging by its
+// pair value alone: for 16-pixel bins the pair's band bits; for 32-pixel
+// bins only whether the pair marks this tile (its rows come with the record).
+template <int BIN>
+__device__ __forceinline__ bool pair_reaches(uint32_t pc, uint32_t quad, uint32_t alive) {
+    const uint32_t m = pc >> kItemBits;
+    if constexpr (BIN == 16) return (m & alive) != 0u;
+    else return ((m >> quad) & 1u) != 0u;
+}
+
 template <bool BF16>
 __device__ __forceinline__ float load_target(const void* __restrict__ t, int64_t idx) {
     if constexpr (BF16) {

@@ -39,7 +39,8 @@ class GscCamera(ct.Structure):
 class GscOptions(ct.Structure):
     _fields_ = [("alpha_min", ct.c_float), ("alpha_max", ct.c_float), ("t_min", ct.c_float),
                 ("sigma_cut", ct.c_float), ("dilation", ct.c_float), ("znear", ct.c_float),
-                ("kappa_max", ct.c_float), ("flags", ct.c_int32), ("bin_size", ct.c_int32)]
+                ("kappa_max", ct.c_float), ("flags", ct.c_int32), ("bin_size", ct.c_int32),
+                ("accumulate_variant", ct.c_int32)]
 
 
 GSC_FLAG_PROFILE = 2

@@ -104,7 +104,9 @@ def test_bad_camera_rejected(lib):
 
 def test_bad_options_rejected(lib):
     for over in [dict(alpha_max=1.5), dict(t_min=-1.0), dict(znear=0.0), dict(sigma_cut=0.0),
-                 dict(bin_size=8), dict(bin_size=64)]:
+                 dict(bin_size=8), dict(bin_size=64), dict(accumulate_variant=5),
+                 dict(accumulate_variant=128 | 48), dict(accumulate_variant=128 | 8),
+                 dict(accumulate_variant=256 | 16)]:
         o = gsc.default_options()
         for k, v in over.items():
             setattr(o, k, v)
@@ -113,8 +115,18 @@ def test_bad_options_rejected(lib):
         assert st == gsc.GSC_ERR_INVALID_ARG
 
 
+def test_accumulate_variants_accepted(lib):
+    for v in [0, 1, 2, 3, 4, 8, 16, 128 | 16, 128 | 32, 128 | 64]:
+        o = gsc.default_options()
+        o.accumulate_variant = v
+        h = ct.c_void_p()
+        assert lib.gsc_ctx_create(ct.byref(h), ct.byref(o)) == gsc.GSC_OK, v
+        lib.gsc_ctx_destroy(h)
+
+
 def test_default_options_values(lib):
     o = gsc.default_options()
+    assert o.accumulate_variant == 0 and o.bin_size == 0
     assert o.alpha_min == np.float32(1 / 255)
     assert o.alpha_max == np.float32(0.99)
     assert o.t_min == np.float32(1e-4)

@@ -98,6 +98,51 @@ def test_segment_like_c16(ctx):
     _case(ctx, sc, y, "segment 8k L0 C16 bf16")
 
 
+# accumulate variants: vector lanes (16 channels per launch) and the
+# matrix-core form with 16, 32 and 64 channels per launch
+BF16_VARIANTS = [16, 128 | 16, 128 | 32, 128 | 64]
+
+
+@pytest.fixture(scope="module")
+def ragged_features():
+    """C = 40 BF16 feature channels: the last block of 16 (or 32, 64) is
+    partly outside C."""
+    sc = syn.make_features(n=12000, n_cams=6, width=200, height=120, C=40)
+    y = oracle.make_targets(sc)
+    return sc, y, oracle.colorize(sc, y)
+
+
+@pytest.mark.parametrize("bin_size", [16, 32])
+@pytest.mark.parametrize("variant", BF16_VARIANTS)
+def test_accumulate_variants_bf16(gsc_mod, ragged_features, variant, bin_size):
+    sc, y, ref = ragged_features
+    ctx = gsc_mod.Context(bin_size=bin_size, accumulate_variant=variant)
+    c, st, stats = run_gpu(ctx, sc, y)
+    assert stats.bin_size == bin_size
+    msg = parity.check_colorize(c, st, ref, count_gpu=stats.contributions,
+                                label=f"features L0 C40 bf16 variant {variant} bin {bin_size}")
+    print(msg, flush=True)
+
+
+def test_matrix_core_per_view_l1(gsc_mod):
+    """L = 1 with 16 BF16 channels: the matrix-core accumulate writes per-view
+    sums that the FP64 fold consumes."""
+    rng = np.random.default_rng(77)
+    sc = syn.make_features(n=4000, n_cams=8, width=128, height=96, C=16)
+    sc.sh_deg = 1
+    sc.gt = [rng.normal(0.0, 1.0, (sc.N, 4, 16)) * np.array([1.0, 0.1, 0.1, 0.1])[None, :, None]]
+    sc.lam = np.array([1e-4, 1e-3], dtype=np.float32)
+    y = oracle.make_targets(sc)
+    assert y.dtype == np.uint16
+    for variant in (128 | 16, 16):
+        ctx = gsc_mod.Context(accumulate_variant=variant)
+        print(f"[case] L1 C16 bf16 variant {variant}", flush=True)
+        ref = oracle.colorize(sc, y)
+        c, st, stats = run_gpu(ctx, sc, y)
+        print(parity.check_colorize(c, st, ref, count_gpu=stats.contributions,
+                                    label=f"L1 C16 bf16 variant {variant}"), flush=True)
+
+
 def test_degenerate_inputs(ctx, gsc_mod):
     import torch
     # no Gaussians
