@@ -127,7 +127,7 @@ def run_single(args, gsc, sc, targets, label, dtype, traffic_key=None):
     import torch
     m, s, q, o = gsc.scene_tensors(sc)
     lam = list(sc.lam)
-    ctx = gsc.Context(flags=gsc.GSC_FLAG_PROFILE, bin_size=args.bin)
+    ctx = gsc.Context(flags=gsc.GSC_FLAG_PROFILE, bin_size=args.bin, accumulate_variant=args.variant)
     for _ in range(args.warmup):
         ctx.colorize(m, s, q, o, sc.cams, targets, sc.sh_deg, lam)
     torch.cuda.synchronize()
@@ -158,7 +158,7 @@ def workload_relight(args, gsc):
     targets = gpu_targets(gsc, sc)
     label = (f"relighting: {sc.N} anisotropic Gaussians, {len(sc.cams)} hemisphere cameras "
              f"{sc.cams[0].width}x{sc.cams[0].height}, SH degree {sc.sh_deg}, C={sc.C}, FP32 targets")
-    default_size = not (args.n or args.views or args.res or args.bin)
+    default_size = not (args.n or args.views or args.res or args.bin or args.variant)
     out = run_single(args, gsc, sc, targets, label, "f32", "relight" if default_size else None)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, host_threads(), "the full benchmark workload")
@@ -305,6 +305,8 @@ def main():
     ap.add_argument("--res", type=int, default=0, help="square resolution (0: the workload's)")
     ap.add_argument("--scenes", type=int, default=32, help="scenes of the batched workload")
     ap.add_argument("--bin", type=int, default=0, help="screen bin size 16 or 32 (0: automatic)")
+    ap.add_argument("--variant", type=int, default=0,
+                    help="accumulate variant code (0: automatic; see gsc_options.accumulate_variant)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path shards by views "

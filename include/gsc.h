@@ -123,10 +123,13 @@ typedef struct {
                          bins the Gaussians are sorted into; the result does not
                          depend on it (the footprint test is per pixel) */
     int32_t accumulate_variant; /* 0 (automatic) or a variant code of the blend +
-                         accumulate launch: channels per launch (1, 2, 3, 4, 8, 16),
-                         or 128 + 16, 32 or 64 for the matrix-core form, which
-                         applies to BF16 targets only (other targets then use
-                         the automatic choice).  A tuned plan uses its own. */
+                         accumulate launch: channels per launch (1, 2, 3, 4, 8, 16);
+                         128 + 16, 32 or 64 for the matrix-core form on BF16
+                         targets; 129 for the packed matrix-core form (all
+                         channels and a ones column in one block: C <= 15 for
+                         BF16, C <= 7 for FP32 targets).  A code that does not
+                         apply to the call falls back to the automatic choice.
+                         A tuned plan uses its own. */
 } gsc_options;
 
 typedef struct {
@@ -281,9 +284,8 @@ typedef struct {
     uint32_t batches;           /* view batches per run */
     uint32_t views;             /* views per run */
     int32_t bin_size;           /* screen bin size of the plan (16 or 32 pixels) */
-    int32_t accumulate_variant; /* accumulate launch shape in use: channels per launch,
-                                   plus 128 for the matrix-core form (BF16 targets;
-                                   16, 32 or 64 channels per launch), plus 256 for the
+    int32_t accumulate_variant; /* accumulate launch shape in use: a variant code as
+                                   for gsc_options.accumulate_variant, plus 256 for the
                                    persistent work-queue launch */
     int32_t tuned_variant[8];   /* shapes timed by gsc_plan_autotune (0: unused) */
     float tuned_ms[8];          /* their accumulate time per run, ms */

@@ -740,9 +740,7 @@ gsc_status gsc_colorize_ex(gsc_ctx* ctx, const float* means, const float* scales
     unsigned long long* d_counter = reinterpret_cast<unsigned long long*>(ctx->misc.p);
     st = for_view_batches(ctx, all, n_cams, means, opacities, N, bp, s,
                           [&](int v0, int nv, const Binned& bn) -> gsc_status {
-        const int chunk = accumulate_chunk_valid(ctx->opt.accumulate_variant, tdtype)
-                              ? ctx->opt.accumulate_variant
-                              : accumulate_chunk(C, tdtype);
+        const int chunk = resolve_chunk(ctx->opt.accumulate_variant, C, tdtype);
         StageTimer t(ctx, s, GSC_STAGE_BLEND, (uint32_t)accumulate_launches(C, chunk));
         (void)v0;
         launch_accumulate_chunked(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
@@ -1161,6 +1159,7 @@ gsc_status gsc_plan_autotune(gsc_plan* plan, const void* targets, int32_t tdtype
     // of C plus wider and narrower chunks
     std::vector<int> chunks;
     std::vector<int> pool;
+    if (plan->C <= (tdtype == GSC_BF16 ? 15 : 7)) pool.push_back(kChunkPacked);
     if (tdtype == GSC_BF16)  // matrix-core forms up to the channels needed
         for (int ch : {16, 32, 64})
             if (ch < plan->C + 16) pool.push_back(kChunkMfma | ch);
@@ -1239,9 +1238,7 @@ gsc_status gsc_plan_get_info(gsc_plan* plan, gsc_plan_info* out) {
     out->pair_capacity = plan->pairs_total;
     out->bin_size = plan->bin;
     const int chosen = plan->acc_chunk ? plan->acc_chunk : plan->ctx->opt.accumulate_variant;
-    out->accumulate_variant = (accumulate_chunk_valid(chosen, plan->last_tdtype)
-                                   ? chosen
-                                   : accumulate_chunk(plan->C, plan->last_tdtype)) |
+    out->accumulate_variant = resolve_chunk(chosen, plan->C, plan->last_tdtype) |
                               (plan->acc_persistent ? 256 : 0);
     for (int i = 0; i < 8; ++i) {
         out->tuned_variant[i] = plan->tune_variant[i];

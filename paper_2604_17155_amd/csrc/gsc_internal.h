@@ -122,16 +122,23 @@ void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* va
                 const uint32_t* n_dev = nullptr);
 
 // Accumulate variants ("chunks"): the channels per launch (launches =
-// ceil(C / channels)), plus kChunkMfma for the matrix-core form (BF16
-// targets; 16, 32 or 64 channels per launch).
+// ceil(C / channels)), plus kChunkMfma for the matrix-core forms: BF16
+// targets in blocks of 16, 32 or 64 channels per launch, or (kChunkMfma | 1)
+// all channels and a ones column packed into one block of 16 (C <= 15 for
+// BF16 targets, C <= 7 for FP32 targets, split into BF16 high and low parts).
 constexpr int kChunkMfma = 128;
+constexpr int kChunkPacked = kChunkMfma | 1;
 inline int chunk_channels(int chunk) { return chunk & (kChunkMfma - 1); }
 inline int accumulate_launches(int C, int chunk) {
+    if (chunk == kChunkPacked) return 1;
     const int ch = chunk_channels(chunk);
     return (C + ch - 1) / ch;
 }
 // Default variant for C channels of targets of type tdtype.
 int accumulate_chunk(int C, int tdtype);
+// `requested` if it is a valid variant that applies to C channels of type
+// tdtype, else the default.
+int resolve_chunk(int requested, int C, int tdtype);
 
 // Accumulate V_gj and S_gj into slot (view.vs_base + g) when per_view, else
 // into slot (view.g_offset + g), summed over views; slots hold C+1 floats.

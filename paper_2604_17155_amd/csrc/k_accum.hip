@@ -299,12 +299,17 @@ struct alignas(16) MfmaLds {
 template <int NBLK>
 constexpr int mfma_rows() { return NBLK == 1 ? 8 : 16; }
 
-template <int NBLK, int BIN>
+// YM: target layout in the B operand.  0: BF16, NBLK blocks of 16 channels,
+// V from a separate product against ones.  1: BF16, C <= 15 channels packed
+// with a ones column (column C) in one block.  2: FP32, C <= 7 channels
+// split into BF16 high parts (columns 0..C-1) and remainders (columns
+// C..2C-1), ones in column 2C.  Packed forms run in one launch (c_off = 0).
+template <int NBLK, int BIN, int YM>
 __device__ __forceinline__ uint32_t accumulate_tile_mfma(
     uint32_t tile, uint32_t lane, MfmaLds<mfma_rows<NBLK>()>& L, const ViewInfo* __restrict__ views, int n_views,
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_vals,
     const float4* __restrict__ rec0, const float4* __restrict__ rec1, const uint2* __restrict__ rec2,
-    const uint16_t* __restrict__ targets, int C, int c_off, int per_view, const BlendParams& bp,
+    const void* __restrict__ targets, int C, int c_off, int per_view, const BlendParams& bp,
     float* __restrict__ VS, uint32_t* __restrict__ gcount) {
     const TileGeom tg = tile_geom<BIN>(tile, views, n_views);
     const ViewInfo& V = views[tg.vloc];
@@ -321,21 +326,34 @@ __device__ __forceinline__ uint32_t accumulate_tile_mfma(
     // targets of the tile as B operands: Y[s][b] holds pixels 32 s + 8 q4 + i
     // (tile row 2 s + q4/2, columns 8 (q4&1) + i) of channel c_off + 16 b + n16
     bf16x8_t Y[8][NBLK];
+    // packed forms: the channel this lane's column reads, and its role
+    const int pc = YM == 2 ? ((int)n16 < C ? (int)n16 : (int)n16 - C) : (int)n16;
+    const bool pcol = YM == 2 ? (int)n16 < 2 * C : (int)n16 < C;   // a target column
+    const bool pone = YM == 2 ? (int)n16 == 2 * C : (int)n16 == C;  // the ones column
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
         const int gy = tg.y0 + 2 * s + (int)(q4 >> 1);
         const int gx0 = tg.x0 + 8 * (int)(q4 & 1u);
 #pragma unroll
         for (int b = 0; b < NBLK; ++b) {
-            const int c = c_off + 16 * b + (int)n16;
+            const int c = YM == 0 ? c_off + 16 * b + (int)n16 : pc;
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const int gx = gx0 + i;
-                const bool in = (gx < vw) & (gy < vh) & (c < C);
+                const bool in = (gx < vw) & (gy < vh) & (YM == 0 ? c < C : pcol);
                 const int64_t row = poff + (int64_t)gy * vw + gx;
                 // unconditional load (element 0 stands in outside): no branch
-                const uint16_t u = targets[in ? row * C + c : 0];
-                Y[s][b][i] = __builtin_bit_cast(__bf16, in ? u : (uint16_t)0);
+                const int64_t e = in ? row * C + c : 0;
+                if constexpr (YM == 2) {
+                    const float f = ((const float*)targets)[e];
+                    const __bf16 hi = (__bf16)f;
+                    const __bf16 v = (int)n16 < C ? hi : (__bf16)(f - (float)hi);
+                    Y[s][b][i] = in ? v : (pone ? (__bf16)1.0f : (__bf16)0.0f);
+                } else {
+                    const uint16_t u = ((const uint16_t*)targets)[e];
+                    const __bf16 v = __builtin_bit_cast(__bf16, u);
+                    Y[s][b][i] = in ? v : ((YM == 1 && pone) ? (__bf16)1.0f : (__bf16)0.0f);
+                }
             }
         }
     }
@@ -396,7 +414,7 @@ __device__ __forceinline__ uint32_t accumulate_tile_mfma(
                 ah = zero8;
                 al = zero8;
             }
-            if (first_chunk) {
+            if (YM == 0 && first_chunk) {
                 DV = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, ones, DV, 0, 0, 0);
                 DV = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, ones, DV, 0, 0, 0);
             }
@@ -410,15 +428,22 @@ __device__ __forceinline__ uint32_t accumulate_tile_mfma(
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const uint32_t m = 4 * q4 + (uint32_t)i;
+            float lo = 0.0f;
+            if constexpr (YM == 2) lo = __shfl(D[0][i], (int)lane + C, 64);  // remainder column
             if (m >= rows) continue;
             const uint32_t gl = L.gslot[m];
             if (gl == 0xFFFFFFFFu) continue;
             float* slot = VS + (slot_base + (int64_t)gl) * (int64_t)stride;
-            if (first_chunk && n16 == 0) unsafeAtomicAdd(slot, DV[i]);
+            if constexpr (YM == 0) {
+                if (first_chunk && n16 == 0) unsafeAtomicAdd(slot, DV[i]);
 #pragma unroll
-            for (int b = 0; b < NBLK; ++b) {
-                const int c = c_off + 16 * b + (int)n16;
-                if (c < C) unsafeAtomicAdd(slot + 1 + c, D[b][i]);
+                for (int b = 0; b < NBLK; ++b) {
+                    const int c = c_off + 16 * b + (int)n16;
+                    if (c < C) unsafeAtomicAdd(slot + 1 + c, D[b][i]);
+                }
+            } else {
+                if (pone) unsafeAtomicAdd(slot, D[0][i]);
+                else if ((int)n16 < C) unsafeAtomicAdd(slot + 1 + n16, D[0][i] + lo);
             }
         }
         // clear the rows used
@@ -515,12 +540,12 @@ __device__ __forceinline__ uint32_t accumulate_tile_mfma(
     return cnt;
 }
 
-template <int NBLK, int BIN>
+template <int NBLK, int BIN, int YM>
 __global__ __launch_bounds__(64 * kMfmaWaves) void k_accumulate_mfma(
     const ViewInfo* __restrict__ views, int n_views, uint32_t n_tiles, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ pair_vals, const float4* __restrict__ rec0,
     const float4* __restrict__ rec1, const uint2* __restrict__ rec2,
-    const uint16_t* __restrict__ targets, int C, int c_off, int per_view, BlendParams bp,
+    const void* __restrict__ targets, int C, int c_off, int per_view, BlendParams bp,
     float* __restrict__ VS, unsigned long long* __restrict__ counter, uint32_t* __restrict__ gcount,
     uint32_t* __restrict__ queue) {
     __shared__ MfmaLds<mfma_rows<NBLK>()> lds[kMfmaWaves];
@@ -529,7 +554,7 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void k_accumulate_mfma(
     if (queue == nullptr) {
         const uint32_t tile = blockIdx.x * kMfmaWaves + w;
         if (tile >= n_tiles) return;  // whole wave
-        cnt = accumulate_tile_mfma<NBLK, BIN>(tile, lane, lds[w], views, n_views, ranges, pair_vals,
+        cnt = accumulate_tile_mfma<NBLK, BIN, YM>(tile, lane, lds[w], views, n_views, ranges, pair_vals,
                                               rec0, rec1, rec2, targets, C, c_off, per_view, bp, VS,
                                               gcount);
     } else {
@@ -538,7 +563,7 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void k_accumulate_mfma(
             if (lane == 0) t = atomicAdd(queue, 1u);
             const uint32_t tile = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
             if (tile >= n_tiles) break;  // uniform: every wave ends here
-            cnt += accumulate_tile_mfma<NBLK, BIN>(tile, lane, lds[w], views, n_views, ranges,
+            cnt += accumulate_tile_mfma<NBLK, BIN, YM>(tile, lane, lds[w], views, n_views, ranges,
                                                    pair_vals, rec0, rec1, rec2, targets, C, c_off,
                                                    per_view, bp, VS, gcount);
         }
@@ -546,7 +571,7 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void k_accumulate_mfma(
     if (c_off == 0 && lane == 0 && cnt) atomicAdd(counter, (unsigned long long)cnt);
 }
 
-template <int NBLK, int BIN>
+template <int NBLK, int BIN, int YM>
 static void launch_acc_mfma(const ViewInfo* views, int n_views, uint32_t n_wt, const uint2* ranges,
                             const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
                             const uint2* rec2, const void* targets, int C, bool per_view,
@@ -555,15 +580,16 @@ static void launch_acc_mfma(const ViewInfo* views, int n_views, uint32_t n_wt, c
     const uint32_t full = (n_wt + kMfmaWaves - 1) / kMfmaWaves;
     dim3 grid(queues ? std::min(full, 2 * kPersistentBlocks) : full), block(64 * kMfmaWaves);
     int pass = 0;
-    for (int c_off = 0; c_off < C; c_off += 16 * NBLK, ++pass) {
+    const int step = YM == 0 ? 16 * NBLK : C;  // packed forms: one launch
+    for (int c_off = 0; c_off < C; c_off += step, ++pass) {
         uint32_t* q = queues ? queues + pass : nullptr;
-        hipLaunchKernelGGL((k_accumulate_mfma<NBLK, BIN>), grid, block, 0, s, views, n_views, n_wt,
-                           ranges, pair_vals, rec0, rec1, rec2, (const uint16_t*)targets, C, c_off,
+        hipLaunchKernelGGL((k_accumulate_mfma<NBLK, BIN, YM>), grid, block, 0, s, views, n_views, n_wt,
+                           ranges, pair_vals, rec0, rec1, rec2, targets, C, c_off,
                            (int)per_view, bp, VS, counter, gcount, q);
     }
 }
 
-template <int NBLK>
+template <int NBLK, int YM>
 static void launch_acc_mfma_bin(const ViewInfo* views, int n_views, uint32_t n_bins, const uint2* ranges,
                                 const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
                                 const uint2* rec2, int bin, const void* targets, int C, bool per_view,
@@ -571,10 +597,10 @@ static void launch_acc_mfma_bin(const ViewInfo* views, int n_views, uint32_t n_b
                                 uint32_t* gcount, uint32_t* queues, hipStream_t s) {
     const uint32_t n_wt = wave_tiles(n_bins, bin);
     if (bin == 32)
-        launch_acc_mfma<NBLK, 32>(views, n_views, n_wt, ranges, pair_vals, rec0, rec1, rec2, targets, C,
+        launch_acc_mfma<NBLK, 32, YM>(views, n_views, n_wt, ranges, pair_vals, rec0, rec1, rec2, targets, C,
                                   per_view, bp, VS, counter, gcount, queues, s);
     else
-        launch_acc_mfma<NBLK, 16>(views, n_views, n_wt, ranges, pair_vals, rec0, rec1, rec2, targets, C,
+        launch_acc_mfma<NBLK, 16, YM>(views, n_views, n_wt, ranges, pair_vals, rec0, rec1, rec2, targets, C,
                                   per_view, bp, VS, counter, gcount, queues, s);
 }
 
@@ -583,10 +609,18 @@ int accumulate_chunk(int C, int tdtype) {
     return C <= 3 ? C : (C <= 4 ? 4 : (C <= 8 ? 8 : 16));
 }
 
+int resolve_chunk(int requested, int C, int tdtype) {
+    if (!accumulate_chunk_valid(requested, tdtype)) return accumulate_chunk(C, tdtype);
+    if (requested == kChunkPacked && C > (tdtype == GSC_BF16 ? 15 : 7)) return accumulate_chunk(C, tdtype);
+    return requested;
+}
+
 bool accumulate_chunk_valid(int chunk, int tdtype) {
     if (chunk & kChunkMfma) {
         const int ch = chunk_channels(chunk);
-        return tdtype == GSC_BF16 && chunk == (kChunkMfma | ch) && (ch == 16 || ch == 32 || ch == 64);
+        if (chunk != (kChunkMfma | ch)) return false;
+        if (ch == 1) return true;  // packed form; fits_packed() checks C
+        return tdtype == GSC_BF16 && (ch == 16 || ch == 32 || ch == 64);
     }
     return chunk == 1 || chunk == 2 || chunk == 3 || chunk == 4 || chunk == 8 || chunk == 16;
 }
@@ -609,16 +643,19 @@ void launch_accumulate_chunked(const ViewInfo* views, int n_views, uint32_t n_ti
                                BlendParams bp, float* VS, unsigned long long* counter,
                                uint32_t* gcount, int chunk, hipStream_t s, uint32_t* queues) {
     if (n_tiles == 0) return;
-    if (!accumulate_chunk_valid(chunk, tdtype)) chunk = accumulate_chunk(C, tdtype);
+    chunk = resolve_chunk(chunk, C, tdtype);
     if (queues) launch_fill_u32(queues, 0u, (uint64_t)accumulate_launches(C, chunk), s);
     if (chunk & kChunkMfma) {
-#define GSC_ACCM(NB)                                                                               \
-    launch_acc_mfma_bin<NB>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, rec2, bin,     \
-                            targets, C, per_view, bp, VS, counter, gcount, queues, s)
+#define GSC_ACCM(NB, YMV)                                                                          \
+    launch_acc_mfma_bin<NB, YMV>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, rec2, bin, \
+                                 targets, C, per_view, bp, VS, counter, gcount, queues, s)
         switch (chunk_channels(chunk)) {
-            case 16: GSC_ACCM(1); break;
-            case 32: GSC_ACCM(2); break;
-            default: GSC_ACCM(4); break;
+            case 1:
+                if (tdtype == GSC_BF16) GSC_ACCM(1, 1); else GSC_ACCM(1, 2);
+                break;
+            case 16: GSC_ACCM(1, 0); break;
+            case 32: GSC_ACCM(2, 0); break;
+            default: GSC_ACCM(4, 0); break;
         }
 #undef GSC_ACCM
         return;

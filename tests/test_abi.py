@@ -116,7 +116,7 @@ def test_bad_options_rejected(lib):
 
 
 def test_accumulate_variants_accepted(lib):
-    for v in [0, 1, 2, 3, 4, 8, 16, 128 | 16, 128 | 32, 128 | 64]:
+    for v in [0, 1, 2, 3, 4, 8, 16, 128 | 1, 128 | 16, 128 | 32, 128 | 64]:
         o = gsc.default_options()
         o.accumulate_variant = v
         h = ct.c_void_p()

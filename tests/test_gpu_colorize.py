@@ -124,6 +124,40 @@ def test_accumulate_variants_bf16(gsc_mod, ragged_features, variant, bin_size):
     print(msg, flush=True)
 
 
+PACKED = 128 | 1  # all channels and a ones column in one matrix-core block
+
+
+def _packed_scenes():
+    out = []
+    sc = syn.make_relight(n=12000, n_cams=10, res=160)
+    out.append((sc, "relight 12k L3 C3 f32"))
+    rng = np.random.Generator(np.random.PCG64(7))
+    sc = syn.make_relight(n=4000, n_cams=6, res=64, sh_deg=2,
+                          lam=rng.uniform(1e-4, 1e-2, 9).astype(np.float32))
+    sc.cams = syn.hemisphere_cams(6, 3.0, 200, 120)
+    sc.C = 7
+    sc.gt = [np.concatenate([sc.gt[0], sc.gt[0] * 0.5, sc.gt[0][:, :, :1] * -0.7], axis=2)]
+    out.append((sc, "ragged 200x120 L2 C7 f32"))
+    sc = syn.make_features(n=8000, n_cams=6, width=176, height=112, C=12)
+    out.append((sc, "features 8k L0 C12 bf16"))
+    return out
+
+
+@pytest.mark.parametrize("bin_size", [16, 32])
+@pytest.mark.parametrize("idx", [0, 1, 2])
+def test_packed_matrix_core(gsc_mod, idx, bin_size):
+    """The packed matrix-core accumulate (FP32 targets split into BF16 high
+    and low parts, or BF16 targets, with V from a ones column)."""
+    sc, label = _packed_scenes()[idx]
+    y = oracle.make_targets(sc)
+    ctx = gsc_mod.Context(bin_size=bin_size, accumulate_variant=PACKED)
+    print(f"[case] packed {label} bin {bin_size}", flush=True)
+    ref = oracle.colorize(sc, y)
+    c, st, stats = run_gpu(ctx, sc, y)
+    print(parity.check_colorize(c, st, ref, count_gpu=stats.contributions,
+                                label=f"packed {label} bin {bin_size}"), flush=True)
+
+
 def test_matrix_core_per_view_l1(gsc_mod):
     """L = 1 with 16 BF16 channels: the matrix-core accumulate writes per-view
     sums that the FP64 fold consumes."""
