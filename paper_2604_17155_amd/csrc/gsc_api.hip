@@ -297,14 +297,17 @@ gsc_status bin_views(gsc_ctx* ctx, const std::vector<ViewInfo>& all, int v0, int
         ctx->h_views_cap = (size_t)nv;
     }
     uint64_t tiles = 0, items = 0;
+    bool uniform = true;
     for (int k = 0; k < nv; ++k) {
         ViewInfo v = all[v0 + k];
         v.tile_base = (uint32_t)tiles;
         v.item_base = (uint32_t)items;
         tiles += (uint64_t)v.tiles_x * v.tiles_y;
         items += v.n_gauss;
+        uniform = uniform && v.n_gauss == all[v0].n_gauss;
         ctx->h_views[k] = v;
     }
+    for (int k = 0; k < nv; ++k) ctx->h_views[k].uniform_n = uniform ? all[v0].n_gauss : 0u;
     if (tiles >= 0xffffffffull) return fail(GSC_ERR_CAPACITY, "too many tiles in one batch");
     if (items > kMaxItemsPerBatch) return fail(GSC_ERR_CAPACITY, "too many items in one batch");
     GSC_HIP(ctx->views.ensure(sizeof(ViewInfo) * (size_t)nv));
@@ -538,13 +541,16 @@ gsc_status plan_count_pairs(gsc_plan* P, const gsc_plan::Batch& b, hipStream_t s
 void plan_number_views(gsc_plan* P) {
     for (auto& b : P->batches) {
         uint64_t tiles = 0, items = 0;
+        bool uniform = true;
         for (int k = 0; k < b.nv; ++k) {
             ViewInfo& v = P->views[b.v0 + k];
             v.tile_base = (uint32_t)tiles;
             v.item_base = (uint32_t)items;
             tiles += (uint64_t)v.tiles_x * v.tiles_y;
             items += v.n_gauss;
+            uniform = uniform && v.n_gauss == P->views[b.v0].n_gauss;
         }
+        for (int k = 0; k < b.nv; ++k) P->views[b.v0 + k].uniform_n = uniform ? P->views[b.v0].n_gauss : 0u;
         b.n_tiles = (uint32_t)tiles;
         b.n_items = (uint32_t)items;
         b.tile_bits = bits_for(tiles + 1);

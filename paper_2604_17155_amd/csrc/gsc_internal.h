@@ -34,10 +34,15 @@ struct ViewInfo {
     int64_t vs_base;       // first per-view sum slot of this view (per-view layouts)
     uint32_t n_gauss;      // Gaussians of the view's scene
     uint32_t scene;        // scene index
+    uint32_t uniform_n;    // n_gauss when every view of the batch has the same
+                           // count (item = view * n + g), else 0
 };
 
-// View of a batch item (binary search on item_base; n_views >= 1).
+// View of a batch item: a division when every view has the same count,
+// else a binary search on item_base (n_views >= 1).
 __device__ inline int find_view_item(const ViewInfo* __restrict__ views, int n_views, uint32_t item) {
+    const uint32_t un = views[0].uniform_n;
+    if (un != 0u) return min((int)(item / un), n_views - 1);
     int lo = 0, hi = n_views - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
