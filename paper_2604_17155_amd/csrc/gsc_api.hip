@@ -344,7 +344,7 @@ gsc_status bin_views(gsc_ctx* ctx, const std::vector<ViewInfo>& all, int v0, int
     {
         // projection in depth order: records and counts land at the depth rank
         StageTimer t(ctx, s, GSC_STAGE_PROJECT);
-        launch_project(dviews, nv, ni, ctx->vals.as<uint32_t>(), means, ctx->cov.as<float>(), opac, bp,
+        launch_project(dviews, nv, ni, ctx->vals.as<uint32_t>(), ctx->cov.as<float>(), bp,
                        ctx->counts.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(),
                        ctx->rec2.as<uint2>(), ctx->bin, s);
         GSC_LAUNCHED("project");
@@ -425,8 +425,8 @@ gsc_status for_view_batches(gsc_ctx* ctx, const std::vector<ViewInfo>& all, int 
 }
 
 gsc_status ensure_common(gsc_ctx* ctx, const float* means, const float* scales,
-                         const float* quats, int64_t N, const gsc_camera* cams, int n_cams,
-                         hipStream_t s) {
+                         const float* quats, const float* opac, int64_t N, const gsc_camera* cams,
+                         int n_cams, hipStream_t s) {
     GSC_HIP(ctx->misc.ensure(kMiscBytes));
     if (!ctx->h_total) GSC_HIP(hipHostMalloc((void**)&ctx->h_total, 64));
     ctx->bin = ctx->opt.bin_size;
@@ -440,9 +440,9 @@ gsc_status ensure_common(gsc_ctx* ctx, const float* means, const float* scales,
         memcpy(st, ctx->h_total, sizeof(st));
         ctx->bin = choose_bin(st, N, cams, n_cams);
     }
-    GSC_HIP(ctx->cov.ensure(sizeof(float) * 6 * (size_t)std::max<int64_t>(N, 1)));
+    GSC_HIP(ctx->cov.ensure(sizeof(float) * kGeoStride * (size_t)std::max<int64_t>(N, 1)));
     launch_fill_u32(ctx->misc.as<uint32_t>(), 0u, kMiscBytes / 4, s);
-    launch_cov3d(scales, quats, ctx->cov.as<float>(), N, s);
+    launch_cov3d(means, opac, scales, quats, ctx->cov.as<float>(), N, s);
     GSC_LAUNCHED("cov3d");
     return GSC_OK;
 }
@@ -522,7 +522,7 @@ gsc_status validate_cameras(const gsc_camera* cams, int32_t n_cams) {
 // Project one batch of the plan and count its tile pairs (synchronises).
 gsc_status plan_count_pairs(gsc_plan* P, const gsc_plan::Batch& b, hipStream_t s, uint64_t* pairs) {
     const ViewInfo* dv = P->d_views.as<ViewInfo>() + b.v0;
-    launch_project(dv, b.nv, b.n_items, nullptr, P->means, P->cov.as<float>(), P->opac, P->bp,
+    launch_project(dv, b.nv, b.n_items, nullptr, P->cov.as<float>(), P->bp,
                    P->counts.as<uint32_t>(), P->rec0.as<float4>(), P->rec1.as<float4>(),
                    P->rec2.as<uint2>(), P->bin, s);
     GSC_LAUNCHED("project");
@@ -590,7 +590,7 @@ gsc_status plan_bin_batch(gsc_plan* P, const gsc_plan::Batch& b, hipStream_t s) 
     }
     {
         StageTimer t(ctx, s, GSC_STAGE_PROJECT);
-        launch_project(dv, b.nv, b.n_items, P->vals.as<uint32_t>(), P->means, P->cov.as<float>(), P->opac,
+        launch_project(dv, b.nv, b.n_items, P->vals.as<uint32_t>(), P->cov.as<float>(),
                        P->bp, P->counts.as<uint32_t>(), P->rec0.as<float4>(), P->rec1.as<float4>(),
                        P->rec2.as<uint2>(), P->bin, s);
         GSC_LAUNCHED("project");
@@ -652,7 +652,7 @@ gsc_status plan_run(gsc_plan* P, const void* targets, int tdtype, const double* 
     P->last_tdtype = tdtype;
     launch_fill_u32(P->misc.as<uint32_t>(), 0u, 6, s);
     launch_fill_u32(P->vs.as<uint32_t>(), 0u, P->vs_slots * (uint64_t)(P->C + 1), s);
-    launch_cov3d(P->scales, P->quats, P->cov.as<float>(), P->n_total, s);
+    launch_cov3d(P->means, P->opac, P->scales, P->quats, P->cov.as<float>(), P->n_total, s);
     GSC_LAUNCHED("cov3d");
     for (const auto& b : P->batches) {
         gsc_status st = plan_bin_batch(P, b, s);
@@ -735,7 +735,7 @@ gsc_status gsc_colorize_ex(gsc_ctx* ctx, const float* means, const float* scales
     float* x_vis = extras ? extras->visibility : nullptr;
     uint32_t* x_cnt = extras ? extras->counts : nullptr;
     BlendParams bp = blend_params(ctx->opt);
-    if ((st = ensure_common(ctx, means, scales, quats, N, cams, n_cams, s)) != GSC_OK) return st;
+    if ((st = ensure_common(ctx, means, scales, quats, opacities, N, cams, n_cams, s)) != GSC_OK) return st;
     std::vector<ViewInfo> all(n_cams);
     for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j], j, N, ctx->bin);
     const bool per_view = sh_deg > 0 || x_sums != nullptr;
@@ -801,7 +801,7 @@ gsc_status gsc_render(gsc_ctx* ctx, const float* means, const float* scales, con
     memset(&ctx->stats, 0, sizeof(ctx->stats));
     if (n_cams == 0) return GSC_OK;
     BlendParams bp = blend_params(ctx->opt);
-    if ((st = ensure_common(ctx, means, scales, quats, N, cams, n_cams, s)) != GSC_OK) return st;
+    if ((st = ensure_common(ctx, means, scales, quats, opacities, N, cams, n_cams, s)) != GSC_OK) return st;
     std::vector<ViewInfo> all(n_cams);
     for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j], j, N, ctx->bin);
     unsigned long long* d_counter = reinterpret_cast<unsigned long long*>(ctx->misc.p);
@@ -849,7 +849,7 @@ gsc_status gsc_colorize_backward(gsc_ctx* ctx, const float* means, const float* 
     if (N == 0 || n_cams == 0 || (!grad_targets && !grad_opacities)) return GSC_OK;
     const int nb = (sh_deg + 1) * (sh_deg + 1);
     BlendParams bp = blend_params(ctx->opt);
-    if ((st = ensure_common(ctx, means, scales, quats, N, cams, n_cams, s)) != GSC_OK) return st;
+    if ((st = ensure_common(ctx, means, scales, quats, opacities, N, cams, n_cams, s)) != GSC_OK) return st;
     std::vector<ViewInfo> all(n_cams);
     for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j], j, N, ctx->bin);
     // 1. visibilities V_gj (the normal matrices depend on the weights only)
@@ -934,7 +934,7 @@ gsc_status gsc_render_backward(gsc_ctx* ctx, const float* means, const float* sc
     if (grad_opacities && N > 0) launch_fill_u32((uint32_t*)grad_opacities, 0u, (uint64_t)N, s);
     if (N == 0 || n_cams == 0 || (!grad_coeffs && !grad_opacities)) return GSC_OK;
     BlendParams bp = blend_params(ctx->opt);
-    if ((st = ensure_common(ctx, means, scales, quats, N, cams, n_cams, s)) != GSC_OK) return st;
+    if ((st = ensure_common(ctx, means, scales, quats, opacities, N, cams, n_cams, s)) != GSC_OK) return st;
     std::vector<ViewInfo> all(n_cams);
     for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j], j, N, ctx->bin);
     const bool per_view = sh_deg > 0;
@@ -1077,7 +1077,7 @@ gsc_status gsc_plan_create(gsc_ctx* ctx, const gsc_scene* scenes, int32_t n_scen
     for (const auto& b : P->batches) P->max_items = std::max(P->max_items, b.n_items);
     const size_t mi = (size_t)P->max_items;
     GSC_HIP(P->misc.ensure(kPlanMiscBytes));
-    GSC_HIP(P->cov.ensure(sizeof(float) * 6 * (size_t)std::max<int64_t>(n_total, 1)));
+    GSC_HIP(P->cov.ensure(sizeof(float) * kGeoStride * (size_t)std::max<int64_t>(n_total, 1)));
     GSC_HIP(P->keys.ensure(4 * mi + 4));
     GSC_HIP(P->vals.ensure(4 * mi + 4));
     GSC_HIP(P->keys_alt.ensure(4 * mi + 4));
@@ -1091,7 +1091,7 @@ gsc_status gsc_plan_create(gsc_ctx* ctx, const gsc_scene* scenes, int32_t n_scen
     if (!P->views.empty())
         GSC_HIP(hipMemcpyAsync(P->d_views.p, P->views.data(), sizeof(ViewInfo) * P->views.size(),
                                hipMemcpyHostToDevice, s));
-    launch_cov3d(scales, quats, P->cov.as<float>(), n_total, s);
+    launch_cov3d(means, opacities, scales, quats, P->cov.as<float>(), n_total, s);
     GSC_LAUNCHED("cov3d");
     // exact pair counts per batch (the geometry is fixed); split oversized batches
     for (size_t k = 0; k < P->batches.size();) {
@@ -1190,7 +1190,7 @@ gsc_status gsc_plan_autotune(gsc_plan* plan, const void* targets, int32_t tdtype
         (void)hipEventDestroy(e1);
     };
     launch_fill_u32(plan->misc.as<uint32_t>(), 0u, 6, s);
-    launch_cov3d(plan->scales, plan->quats, plan->cov.as<float>(), plan->n_total, s);
+    launch_cov3d(plan->means, plan->opac, plan->scales, plan->quats, plan->cov.as<float>(), plan->n_total, s);
     for (const auto& b : plan->batches) {
         if ((st = plan_bin_batch(plan, b, s)) != GSC_OK) { cleanup(); return st; }
         for (size_t k = 0; k < cand.size(); ++k) {

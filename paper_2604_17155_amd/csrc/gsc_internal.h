@@ -73,7 +73,12 @@ constexpr uint32_t kItemBits = 26;
 constexpr uint32_t kItemMask = (1u << kItemBits) - 1u;
 
 // ---- kernels launched from gsc_api.hip ----------------------------------
-void launch_cov3d(const float* scales, const float* quats, float* cov, int64_t N, hipStream_t s);
+// Per-Gaussian geometry packed for the projection's gathers: one 64-byte
+// record geo[g] = (mean x, y, z, opacity, Sigma xx, xy, xz, yy, yz, zz, 0...)
+// with Sigma = R(q) diag(s^2) R(q)^T.
+constexpr int kGeoStride = 16;  // floats per record
+void launch_cov3d(const float* means, const float* opac, const float* scales, const float* quats,
+                  float* geo, int64_t N, hipStream_t s);
 
 // out[0] = sum_g mean axis scale, out[1..3] = sum_g mean (device doubles).
 void launch_geometry_stats(const float* means, const float* scales, int64_t N, double* out,
@@ -89,9 +94,8 @@ void launch_depth_keys(const ViewInfo* views, int n_views, uint32_t n_items, con
 // is null) and writes counts[k], rec0/rec1[k] and rec2[k] = (first | last << 16,
 // i): the pixel rows of the footprint and the item.
 void launch_project(const ViewInfo* views, int n_views, uint32_t n_items, const uint32_t* order,
-                    const float* means, const float* cov, const float* opac, BlendParams bp,
-                    uint32_t* counts, float4* rec0, float4* rec1, uint2* rec2, int bin,
-                    hipStream_t s);
+                    const float* geo, BlendParams bp, uint32_t* counts, float4* rec0, float4* rec1,
+                    uint2* rec2, int bin, hipStream_t s);
 
 // Pairs of the depth-ordered records: pair values carry the depth rank k.
 // Pairs at offsets >= cap are dropped and counted in *overflow (if given).

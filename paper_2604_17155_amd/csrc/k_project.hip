@@ -11,8 +11,9 @@
 namespace gsc {
 
 // a1: 3D covariance, 6 floats per Gaussian (xx xy xz yy yz zz).
-__global__ void k_cov3d(const float* __restrict__ scales, const float* __restrict__ quats,
-                        float* __restrict__ cov, int64_t N) {
+__global__ void k_cov3d(const float* __restrict__ means, const float* __restrict__ opac,
+                        const float* __restrict__ scales, const float* __restrict__ quats,
+                        float* __restrict__ geo, int64_t N) {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= N) return;
     float w = quats[4 * g], x = quats[4 * g + 1], y = quats[4 * g + 2], z = quats[4 * g + 3];
@@ -29,13 +30,18 @@ __global__ void k_cov3d(const float* __restrict__ scales, const float* __restric
         for (int j = i; j < 3; ++j) {
             S[k++] = R[i][0] * d[0] * R[j][0] + R[i][1] * d[1] * R[j][1] + R[i][2] * d[2] * R[j][2];
         }
-    for (int i = 0; i < 6; ++i) cov[6 * g + i] = S[i];
+    float4* o = reinterpret_cast<float4*>(geo + kGeoStride * g);
+    o[0] = make_float4(means[3 * g], means[3 * g + 1], means[3 * g + 2], opac[g]);
+    o[1] = make_float4(S[0], S[1], S[2], S[3]);
+    o[2] = make_float4(S[4], S[5], 0.0f, 0.0f);
+    o[3] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
-void launch_cov3d(const float* scales, const float* quats, float* cov, int64_t N, hipStream_t s) {
+void launch_cov3d(const float* means, const float* opac, const float* scales, const float* quats,
+                  float* geo, int64_t N, hipStream_t s) {
     if (N <= 0) return;
-    hipLaunchKernelGGL(k_cov3d, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, scales, quats,
-                       cov, N);
+    hipLaunchKernelGGL(k_cov3d, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, means, opac,
+                       scales, quats, geo, N);
 }
 
 // Sums over the Gaussians of the mean axis scale and of the mean position
@@ -252,9 +258,7 @@ void launch_depth_keys(const ViewInfo* views, int n_views, uint32_t n_items, con
 template <int BIN>
 __global__ __launch_bounds__(256) void k_project(const ViewInfo* __restrict__ views, int n_views,
                                                  uint32_t n_items, const uint32_t* __restrict__ order,
-                                                 const float* __restrict__ means,
-                                                 const float* __restrict__ cov,
-                                                 const float* __restrict__ opac,
+                                                 const float* __restrict__ geo,
                                                  BlendParams bp, uint32_t* __restrict__ counts,
                                                  float4* __restrict__ rec0, float4* __restrict__ rec1,
                                                  uint2* __restrict__ rec2) {
@@ -263,12 +267,15 @@ __global__ __launch_bounds__(256) void k_project(const ViewInfo* __restrict__ vi
     const uint32_t i = order ? order[k] : k;
     const ViewInfo& V = views[find_view_item(views, n_views, i)];
     const int64_t g = V.g_offset + (int64_t)(i - V.item_base);
-    float mx = means[3 * g], my = means[3 * g + 1], mz = means[3 * g + 2];
+    // one 64-byte record per Gaussian: a single cache line per random gather
+    const float4* gr = reinterpret_cast<const float4*>(geo + kGeoStride * g);
+    const float4 ga = gr[0], gb = gr[1], gc = gr[2];
+    float mx = ga.x, my = ga.y, mz = ga.z;
     float key = __fmaf_rn(V.R[6], mx, __fmaf_rn(V.R[7], my, __fmaf_rn(V.R[8], mz, V.t[2])));
     uint32_t cnt = 0;
     int rows[2] = {1, 0};
     float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
-    const float og = opac[g];
+    const float og = ga.w;
     const float qmax = reach_q(og, bp);
     if (key > bp.znear && qmax > 0.0f) {
         double R[9];
@@ -281,8 +288,7 @@ __global__ __launch_bounds__(256) void k_project(const ViewInfo* __restrict__ vi
         const double fx = V.fx, fy = V.fy;
         const double j00 = fx * iz, j02 = -fx * tx * iz * iz;
         const double j11 = fy * iz, j12 = -fy * ty * iz * iz;
-        const float* c = cov + 6 * g;
-        const double S[3][3] = {{c[0], c[1], c[2]}, {c[1], c[3], c[4]}, {c[2], c[4], c[5]}};
+        const double S[3][3] = {{gb.x, gb.y, gb.z}, {gb.y, gb.w, gc.x}, {gb.z, gc.x, gc.y}};
         // Sc = W S W^T
         double M[3][3];
         for (int a = 0; a < 3; ++a)
@@ -317,16 +323,15 @@ __global__ __launch_bounds__(256) void k_project(const ViewInfo* __restrict__ vi
 }
 
 void launch_project(const ViewInfo* views, int n_views, uint32_t n_items, const uint32_t* order,
-                    const float* means, const float* cov, const float* opac, BlendParams bp,
-                    uint32_t* counts, float4* rec0, float4* rec1, uint2* rec2, int bin,
-                    hipStream_t s) {
+                    const float* geo, BlendParams bp, uint32_t* counts, float4* rec0, float4* rec1,
+                    uint2* rec2, int bin, hipStream_t s) {
     if (n_items == 0 || n_views <= 0) return;
     if (bin == 32)
         hipLaunchKernelGGL(k_project<32>, dim3((n_items + 255) / 256), dim3(256), 0, s, views, n_views,
-                           n_items, order, means, cov, opac, bp, counts, rec0, rec1, rec2);
+                           n_items, order, geo, bp, counts, rec0, rec1, rec2);
     else
         hipLaunchKernelGGL(k_project<16>, dim3((n_items + 255) / 256), dim3(256), 0, s, views, n_views,
-                           n_items, order, means, cov, opac, bp, counts, rec0, rec1, rec2);
+                           n_items, order, geo, bp, counts, rec0, rec1, rec2);
 }
 
 // a3: emit (global bin id, k | mask) pairs in depth order, k being the depth
