@@ -115,6 +115,28 @@ def roofline(C, contrib, blend_ms_total, launches, workload=None):
             "flop_per_contribution": algorithmic_flops_per_contribution(C)}
 
 
+def variant_name(v: int) -> str:
+    """Readable accumulate variant code (see gsc_options.accumulate_variant)."""
+    ch = v & 127
+    base = ("mfma-packed" if ch == 1 else f"mfma{ch}") if v & 128 else f"vec{ch}"
+    return base + ("/persistent" if v & 256 else "")
+
+
+def variant_launches(C: int, v: int) -> int:
+    ch = v & 127
+    if v & 128 and ch == 1:
+        return 1
+    return (C + ch - 1) // ch
+
+
+def hbm_view(target_bytes: float, kernel_ms_total: float):
+    """The accumulate's algorithmic HBM traffic (the targets, read once per
+    step) against the MI355X HBM peak."""
+    gbs = target_bytes / (kernel_ms_total * 1e-3) / 1e9
+    return {"target_bytes": target_bytes, "achieved_GBps": gbs, "peak_GBps": PEAK_HBM / 1e9,
+            "frac": gbs * 1e9 / PEAK_HBM}
+
+
 def line(args, value, ms_per_step, dtype, config, roof):
     return {"metric": METRIC, "value": value, "unit": "contributions/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -145,9 +167,11 @@ def run_single(args, gsc, sc, targets, label, dtype, traffic_key=None):
     st = ctx.stats()
     stages = {k: v / args.steps for k, v in st.stage_dict().items() if v}
     launches = max(1, int(st.stage_launches[5]) // args.steps)
+    tbytes = float(sum(c.width * c.height for c in sc.cams)) * sc.C * (2 if dtype == "bf16" else 4)
     config = {"workload": label, "contributions_per_step": contrib,
               "scenes_per_sec": args.steps / elapsed, "tile_pairs_per_step": int(st.pairs),
-              "bin_size": int(st.bin_size), "stage_ms_per_step": stages}
+              "bin_size": int(st.bin_size), "stage_ms_per_step": stages,
+              "accumulate_hbm": hbm_view(tbytes, stages["blend"])}
     return line(args, contrib * args.steps / elapsed, 1e3 * elapsed / args.steps, dtype, config,
                 roofline(sc.C, contrib, stages["blend"], launches, traffic_key))
 
@@ -206,8 +230,7 @@ def workload_batched(args, gsc):
     info = plan.info()
     contrib = int(info.contributions)
     variant = int(info.accumulate_variant)
-    tuned = {f"{v & 255}ch{'/persistent' if v >> 8 else ''}": float(info.tuned_ms[i])
-             for i, v in enumerate(info.tuned_variant) if v}
+    tuned = {variant_name(v): float(info.tuned_ms[i]) for i, v in enumerate(info.tuned_variant) if v}
     acc_ms = [float(info.tuned_ms[i]) for i, v in enumerate(info.tuned_variant) if v == variant][0]
     # capture one run and replay it
     side = torch.cuda.Stream()
@@ -229,7 +252,7 @@ def workload_batched(args, gsc):
     elapsed = time.perf_counter() - t0
     info2 = plan.info()
     assert int(info2.dropped_pairs) == 0
-    launches = (C + (variant & 255) - 1) // (variant & 255) * int(info.batches)
+    launches = variant_launches(C, variant) * int(info.batches)
     config = {"workload": f"multi-scene segmentation: {n_scenes} scenes, {g0} Gaussians in total "
                           f"(5k-400k per scene), {c0} cameras 640x480..1280x720, SH degree 0, "
                           f"C={C}, BF16 targets, one plan replayed as a graph",
@@ -237,7 +260,8 @@ def workload_batched(args, gsc):
               "pixels": r0, "tile_pairs_per_step": int(info.pair_capacity),
               "view_batches": int(info.batches), "bin_size": int(info.bin_size),
               "autotune_accumulate_ms": tuned,
-              "accumulate_variant": variant}
+              "accumulate_variant": variant_name(variant),
+              "accumulate_hbm": hbm_view(float(r0) * C * 2, acc_ms)}
     out = line(args, contrib * args.steps / elapsed, 1e3 * elapsed / args.steps, "bf16", config,
                roofline(C, contrib, acc_ms, launches))
     if not args.no_cpu_baseline:

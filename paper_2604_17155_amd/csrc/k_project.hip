@@ -94,17 +94,21 @@ __device__ inline float reach_q(float o, const BlendParams& bp) {
 // extremes lie at the span's ends or at the ellipse's leftmost / rightmost
 // point when that falls inside the span.  Extents are widened by 0.01 pixel
 // (and 1e-4 relative), so the walk is conservative with respect to the
-// blend's FP32 test.  *rows (optional) receives the first and last pixel row
-// walked.  Used identically for counting and emitting.
-template <typename Visit>
+// blend's FP32 test (and cover the ~1 ulp of the hardware square root used
+// here).  *rows (optional) receives the first and last pixel row walked.
+// Used identically for counting and emitting.
+// STEP = 16 walks whole tile rows instead of bands (only [lo[0], hi[0]] is
+// then set): the extent over a tile row's span is the union of its bands'.
+template <int STEP = 4, typename Visit>
 __device__ inline void footprint_rows(float4 r0, float4 r1, float qmax, int W, int H,
                                       Visit&& visit, int* rows = nullptr) {
+    static_assert(STEP == 4 || STEP == 16, "steps of a band or of a tile row");
     constexpr float kInvK = (float)(1.0 / kExp2Scale);
     const float a = r1.x * kInvK, b = 0.5f * r1.y * kInvK, c = r1.z * kInvK;
     const float det = a * c - b * b;
     if (!(a > 0.0f && det > 0.0f && qmax > 0.0f)) return;
     const float ia = 1.0f / a, cq = det * ia;  // q = a (dx + b dy / a)^2 + cq dy^2
-    const float ry = sqrtf(qmax / cq) * 1.0001f + 0.01f;
+    const float ry = __builtin_amdgcn_sqrtf(qmax / cq) * 1.0001f + 0.01f;
     const float vc = r0.y - 0.5f + r0.w;  // row index whose centre is the mean
     const float fy0 = fmaxf(ceilf(vc - ry), 0.0f);
     const float fy1 = fminf(floorf(vc + ry), (float)(H - 1));
@@ -118,12 +122,12 @@ __device__ inline void footprint_rows(float4 r0, float4 r1, float qmax, int W, i
     // leftmost / rightmost point of the ellipse: dx = -+ sqrt(qmax Sxx) at
     // dy = -+ sqrt(qmax / Sxx) Sxy, with Sxx = c / det, Sxy = -b / det
     const float sxx = c / det, sxy = -b / det;
-    const float xr = sqrtf(qmax * sxx) * 1.0001f + 0.01f;
-    const float dyl = -sqrtf(qmax / sxx) * sxy;  // row offset of the leftmost point (rightmost: -dyl)
+    const float xr = __builtin_amdgcn_sqrtf(qmax * sxx) * 1.0001f + 0.01f;
+    const float dyl = -__builtin_amdgcn_sqrtf(qmax / sxx) * sxy;  // row offset of the leftmost point (rightmost: -dyl)
     auto edges = [&](int y, float& l, float& r) {
         const float dy = ((float)y + 0.5f - r0.y) - r0.w;
         const float disc = fmaxf(qmax - cq * dy * dy, 0.0f);
-        const float half = sqrtf(disc * ia) * 1.0001f + 0.01f;
+        const float half = __builtin_amdgcn_sqrtf(disc * ia) * 1.0001f + 0.01f;
         const float mid = cx - b * dy * ia;
         l = mid - half;
         r = mid + half;
@@ -131,8 +135,8 @@ __device__ inline void footprint_rows(float4 r0, float4 r1, float qmax, int W, i
     int lo[4], hi[4];
     int cur = y0 >> kTileShift;
     for (int k = 0; k < 4; ++k) { lo[k] = 1 << 30; hi[k] = -1; }
-    for (int ya = y0; ya <= y1; ya = (ya | 3) + 1) {
-        const int yb = min(ya | 3, y1);  // rows [ya, yb] of one band
+    for (int ya = y0; ya <= y1; ya = (ya | (STEP - 1)) + 1) {
+        const int yb = min(ya | (STEP - 1), y1);  // rows [ya, yb] of one band (tile row)
         const int ty = ya >> kTileShift;
         if (ty != cur) {
             visit(cur, lo, hi);
@@ -149,7 +153,7 @@ __device__ inline void footprint_rows(float4 r0, float4 r1, float qmax, int W, i
         const float xf = fmaxf(ceilf(l), 0.0f);
         const float xl = fminf(floorf(r), (float)(W - 1));
         if (!(xf <= xl)) continue;
-        const int band = (ya >> 2) & 3;
+        const int band = STEP == 4 ? (ya >> 2) & 3 : 0;
         const int t0 = (int)xf >> kTileShift, t1 = (int)xl >> kTileShift;
         for (int k = 0; k < 4; ++k)
             if (k == band) {
@@ -198,7 +202,7 @@ __device__ inline void footprint_bins(float4 r0, float4 r1, float qmax, int W, i
                     return m;
                 });
         };
-        footprint_rows(r0, r1, qmax, W, H, [&](int ty, const int* l4, const int* h4) {
+        footprint_rows<16>(r0, r1, qmax, W, H, [&](int ty, const int* l4, const int* h4) {
             const int br = ty >> 1, h = ty & 1;
             if (br != cur) {
                 flush();

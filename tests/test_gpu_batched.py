@@ -165,7 +165,7 @@ def test_batched_autotune(ctx, gsc_mod):
     info = plan.info()
     cands = [info.tuned_variant[i] for i in range(8) if info.tuned_variant[i]]
     times = [info.tuned_ms[i] for i in range(len(cands))]
-    names = [f"{v & 255}ch{'/persistent' if v >> 8 else ''}" for v in cands]
+    names = [f"{v & 511}" for v in cands]
     print(f"autotune: {dict(zip(names, ['%.3f' % t for t in times]))} -> {info.accumulate_variant}",
           flush=True)
     assert len(cands) >= 4 and info.accumulate_variant in cands
