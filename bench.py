@@ -317,9 +317,23 @@ def workload_diff(args, gsc):
     return out
 
 
+def copy_calibration():
+    """One plain device copy of a known size (256 MiB read, 256 MiB written):
+    the reference for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copied_bytes": a.numel() * 4}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 256 MiB device copy (counter calibration) and exit")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -337,6 +351,9 @@ def main():
               "across GPUs as described in the design notes, but no multi-GPU run exists.",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import torch
 

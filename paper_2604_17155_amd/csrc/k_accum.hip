@@ -106,75 +106,147 @@ __device__ __forceinline__ uint32_t accumulate_tile(
         uint2 Q2;
         if constexpr (kDouble) gather(pvn, b + 64, Q0, Q1, Q2);
         const uint32_t pvnn = load_pv(b + 128);
-        for (uint32_t j = 0; j < nb; ++j) {
-            const uint32_t pc = bcast_u(pv, j);
-            const uint2 e2 = make_uint2(bcast_u(R2.x, j), bcast_u(R2.y, j));
-            const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2.x, tg.y0) & alive;
-            if (bands == 0u) continue;
-            const float4 c0 = make_float4(bcast(R0.x, j), bcast(R0.y, j), bcast(R0.z, j), bcast(R0.w, j));
-            const float4 c1 = make_float4(bcast(R1.x, j), bcast(R1.y, j), bcast(R1.z, j), bcast(R1.w, j));
-            const float dx = (px - c0.x) - c0.z;
-            const float a0 = c1.x * dx * dx;
-            const float b0 = c1.y * dx;
-            float sv = 0.0f;
-            float ss[CCA];
+        if constexpr (CC >= 1 && CC <= 3) {
+            // Entries in groups of four: each entry's tile sums (V, S) stay in
+            // a fixed register slot, and one wave reduction of the group's 16
+            // values (lane e*4+v, bit-reversed) feeds one atomic per value.
+            bool stop = false;
+            for (uint32_t j0 = 0; j0 < nb && !stop; j0 += 4) {
+                float pend[16];
 #pragma unroll
-            for (int c = 0; c < CCA; ++c) ss[c] = 0.0f;
-            uint32_t nh = 0;    // contributions of this entry (wave total)
+                for (int i = 0; i < 16; ++i) pend[i] = 0.0f;
+                int64_t gslot[4] = {0, 0, 0, 0};
+                bool has[4] = {false, false, false, false};
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (!((bands >> k) & 1u)) continue;  // uniform
-                const float dy = (pyk[k] - c0.y) - c0.w;
-                const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
-                // min(alpha_max, o G) for o G >= 0
-                const float al = __builtin_amdgcn_fmed3f(c1.w * __builtin_amdgcn_exp2f(q2), 0.0f, amax);
-                const float test = fmaf(-T[k], al, T[k]);
-                const bool cand = q2 >= qlim && al >= amin && T[k] > 0.0f;
-                const bool keep = test >= tmin;  // else the pixel stops here
-                const bool take = cand && keep;
-                const float w = take ? al * T[k] : 0.0f;
-                T[k] = cand ? (keep ? test : 0.0f) : T[k];
-                sv += w;
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t j = j0 + (uint32_t)u;
+                    if (j >= nb || stop) continue;  // uniform
+                    const uint32_t pc = bcast_u(pv, j);
+                    const uint2 e2 = make_uint2(bcast_u(R2.x, j), bcast_u(R2.y, j));
+                    const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2.x, tg.y0) & alive;
+                    if (bands == 0u) continue;
+                    const float4 c0 = make_float4(bcast(R0.x, j), bcast(R0.y, j), bcast(R0.z, j), bcast(R0.w, j));
+                    const float4 c1 = make_float4(bcast(R1.x, j), bcast(R1.y, j), bcast(R1.z, j), bcast(R1.w, j));
+                    const float dx = (px - c0.x) - c0.z;
+                    const float a0 = c1.x * dx * dx;
+                    const float b0 = c1.y * dx;
+                    float sv = 0.0f, s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
+                    uint32_t nh = 0;
 #pragma unroll
-                for (int c = 0; c < CC; ++c) ss[c] = fmaf(w, y[k][c], ss[c]);
-                nh += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(take));
-                if (__builtin_amdgcn_ballot_w64(T[k] > 0.0f) == 0) alive &= ~(1u << k);
-            }
-            // keep the band mask and the count in scalar registers
-            alive = (uint32_t)__builtin_amdgcn_readfirstlane((int)alive);
-            nh = (uint32_t)__builtin_amdgcn_readfirstlane((int)nh);
-            cnt += nh;
-            if (nh != 0u) {
-                // the pair carries the depth rank; the record names the item
-                const int64_t g = (int64_t)e2.y - item_base;
-                if (gcount != nullptr && first_chunk && lane == 0) atomicAdd(gcount + V.g_offset + g, nh);
-                float* slot = VS + (slot_base + g) * (int64_t)stride;
-                if constexpr (CC == 0) {
-                    const float tv = wave_sum(sv);
-                    if (lane == 0) unsafeAtomicAdd(slot, tv);
-                } else if constexpr (CC <= 3) {
-                    const float v1 = CC > 1 ? ss[CC > 1 ? 1 : 0] : 0.0f;
-                    const float v2 = CC > 2 ? ss[CC > 2 ? 2 : 0] : 0.0f;
-                    const float t = wave_sum4_transposed(sv, ss[0], v1, v2, lane);
-                    if (lane < 4u) {
-                        const int idx = transposed_index<4>(lane);
-                        if (idx == 0) {
-                            if (first_chunk) unsafeAtomicAdd(slot, t);
-                        } else if (idx <= CC && c_off + idx - 1 < C) {
-                            unsafeAtomicAdd(slot + c_off + idx, t);
-                        }
+                    for (int k = 0; k < 4; ++k) {
+                        if (!((bands >> k) & 1u)) continue;  // uniform
+                        const float dy = (pyk[k] - c0.y) - c0.w;
+                        const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
+                        const float al = __builtin_amdgcn_fmed3f(c1.w * __builtin_amdgcn_exp2f(q2), 0.0f, amax);
+                        const float test = fmaf(-T[k], al, T[k]);
+                        const bool cand = q2 >= qlim && al >= amin && T[k] > 0.0f;
+                        const bool keep = test >= tmin;
+                        const bool take = cand && keep;
+                        const float w = take ? al * T[k] : 0.0f;
+                        T[k] = cand ? (keep ? test : 0.0f) : T[k];
+                        sv += w;
+                        s0 = fmaf(w, y[k][0], s0);
+                        if constexpr (CC > 1) s1 = fmaf(w, y[k][CC > 1 ? 1 : 0], s1);
+                        if constexpr (CC > 2) s2 = fmaf(w, y[k][CC > 2 ? 2 : 0], s2);
+                        nh += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(take));
+                        if (__builtin_amdgcn_ballot_w64(T[k] > 0.0f) == 0) alive &= ~(1u << k);
                     }
-                } else {
-                    const float tv = wave_sum(sv);
-                    const float t = wave_sum_transposed<CC>(ss, lane);
-                    if (lane == 0 && first_chunk) unsafeAtomicAdd(slot, tv);
-                    if (lane < (uint32_t)CC) {
-                        const int c = c_off + transposed_index<CC>(lane);
-                        if (c < C) unsafeAtomicAdd(slot + 1 + c, t);
+                    alive = (uint32_t)__builtin_amdgcn_readfirstlane((int)alive);
+                    nh = (uint32_t)__builtin_amdgcn_readfirstlane((int)nh);
+                    cnt += nh;
+                    if (nh != 0u) {
+                        const int64_t g = (int64_t)e2.y - item_base;
+                        if (gcount != nullptr && first_chunk && lane == 0) atomicAdd(gcount + V.g_offset + g, nh);
+                        has[u] = true;
+                        gslot[u] = slot_base + g;
+                        pend[4 * u] = sv;
+                        pend[4 * u + 1] = s0;
+                        pend[4 * u + 2] = s1;
+                        pend[4 * u + 3] = s2;
                     }
+                    if (alive == 0u) stop = true;
+                }
+                if (has[0] || has[1] || has[2] || has[3]) {
+                    const float t = wave_sum_transposed<16>(pend, lane);
+                    const int idx = transposed_index<16>(lane);
+                    const int e = idx >> 2, v = idx & 3;
+                    const bool he = e == 0 ? has[0] : (e == 1 ? has[1] : (e == 2 ? has[2] : has[3]));
+                    const int64_t sl = e == 0 ? gslot[0] : (e == 1 ? gslot[1] : (e == 2 ? gslot[2] : gslot[3]));
+                    const bool use = lane < 16u && he && (v == 0 ? first_chunk : (v <= CC && c_off + v - 1 < C));
+                    if (use) unsafeAtomicAdd(VS + sl * (int64_t)stride + (v == 0 ? 0 : c_off + v), t);
                 }
             }
-            if (alive == 0u) break;
+        } else {
+            for (uint32_t j = 0; j < nb; ++j) {
+                const uint32_t pc = bcast_u(pv, j);
+                const uint2 e2 = make_uint2(bcast_u(R2.x, j), bcast_u(R2.y, j));
+                const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2.x, tg.y0) & alive;
+                if (bands == 0u) continue;
+                const float4 c0 = make_float4(bcast(R0.x, j), bcast(R0.y, j), bcast(R0.z, j), bcast(R0.w, j));
+                const float4 c1 = make_float4(bcast(R1.x, j), bcast(R1.y, j), bcast(R1.z, j), bcast(R1.w, j));
+                const float dx = (px - c0.x) - c0.z;
+                const float a0 = c1.x * dx * dx;
+                const float b0 = c1.y * dx;
+                float sv = 0.0f;
+                float ss[CCA];
+    #pragma unroll
+                for (int c = 0; c < CCA; ++c) ss[c] = 0.0f;
+                uint32_t nh = 0;    // contributions of this entry (wave total)
+    #pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (!((bands >> k) & 1u)) continue;  // uniform
+                    const float dy = (pyk[k] - c0.y) - c0.w;
+                    const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
+                    // min(alpha_max, o G) for o G >= 0
+                    const float al = __builtin_amdgcn_fmed3f(c1.w * __builtin_amdgcn_exp2f(q2), 0.0f, amax);
+                    const float test = fmaf(-T[k], al, T[k]);
+                    const bool cand = q2 >= qlim && al >= amin && T[k] > 0.0f;
+                    const bool keep = test >= tmin;  // else the pixel stops here
+                    const bool take = cand && keep;
+                    const float w = take ? al * T[k] : 0.0f;
+                    T[k] = cand ? (keep ? test : 0.0f) : T[k];
+                    sv += w;
+    #pragma unroll
+                    for (int c = 0; c < CC; ++c) ss[c] = fmaf(w, y[k][c], ss[c]);
+                    nh += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(take));
+                    if (__builtin_amdgcn_ballot_w64(T[k] > 0.0f) == 0) alive &= ~(1u << k);
+                }
+                // keep the band mask and the count in scalar registers
+                alive = (uint32_t)__builtin_amdgcn_readfirstlane((int)alive);
+                nh = (uint32_t)__builtin_amdgcn_readfirstlane((int)nh);
+                cnt += nh;
+                if (nh != 0u) {
+                    // the pair carries the depth rank; the record names the item
+                    const int64_t g = (int64_t)e2.y - item_base;
+                    if (gcount != nullptr && first_chunk && lane == 0) atomicAdd(gcount + V.g_offset + g, nh);
+                    float* slot = VS + (slot_base + g) * (int64_t)stride;
+                    if constexpr (CC == 0) {
+                        const float tv = wave_sum(sv);
+                        if (lane == 0) unsafeAtomicAdd(slot, tv);
+                    } else if constexpr (CC <= 3) {
+                        const float v1 = CC > 1 ? ss[CC > 1 ? 1 : 0] : 0.0f;
+                        const float v2 = CC > 2 ? ss[CC > 2 ? 2 : 0] : 0.0f;
+                        const float t = wave_sum4_transposed(sv, ss[0], v1, v2, lane);
+                        if (lane < 4u) {
+                            const int idx = transposed_index<4>(lane);
+                            if (idx == 0) {
+                                if (first_chunk) unsafeAtomicAdd(slot, t);
+                            } else if (idx <= CC && c_off + idx - 1 < C) {
+                                unsafeAtomicAdd(slot + c_off + idx, t);
+                            }
+                        }
+                    } else {
+                        const float tv = wave_sum(sv);
+                        const float t = wave_sum_transposed<CC>(ss, lane);
+                        if (lane == 0 && first_chunk) unsafeAtomicAdd(slot, tv);
+                        if (lane < (uint32_t)CC) {
+                            const int c = c_off + transposed_index<CC>(lane);
+                            if (c < C) unsafeAtomicAdd(slot + 1 + c, t);
+                        }
+                    }
+                }
+                if (alive == 0u) break;
+            }
         }
         if constexpr (kDouble) {
             R0 = Q0;
@@ -605,7 +677,9 @@ static void launch_acc_mfma_bin(const ViewInfo* views, int n_views, uint32_t n_b
 }
 
 int accumulate_chunk(int C, int tdtype) {
-    if (tdtype == GSC_BF16 && C >= 16) return kChunkMfma | (C <= 16 ? 16 : (C <= 32 ? 32 : 64));
+    // (one 64-channel launch holds its targets in 128 registers and runs one
+    // wave per SIMD; two 32-channel launches measure as fast or faster)
+    if (tdtype == GSC_BF16 && C >= 16) return kChunkMfma | (C <= 16 ? 16 : 32);
     return C <= 3 ? C : (C <= 4 ? 4 : (C <= 8 ? 8 : 16));
 }
 
