@@ -86,7 +86,14 @@ enum {
 /* Option flags. */
 enum {
     GSC_FLAG_VALIDATE_ONLY = 1, /* check the arguments and return; enqueue nothing */
-    GSC_FLAG_PROFILE = 2        /* time each pipeline stage with events on the call's stream */
+    GSC_FLAG_PROFILE = 2,       /* time each pipeline stage with events on the call's stream */
+    GSC_FLAG_REUSE_BINNING = 4  /* reuse the tile lists of the previous call on this context
+                                   when it had one view batch and this call passes the same
+                                   means, scales, quats and opacities pointers, N, cameras
+                                   and blend options: the caller guarantees that the
+                                   contents of those arrays are unchanged since that call
+                                   (e.g. colorize, render and their adjoints in one
+                                   optimisation step); otherwise the call bins anew */
 };
 
 /* Pipeline stages timed under GSC_FLAG_PROFILE (indices of gsc_stats.stage_ms). */

@@ -4,7 +4,8 @@ Gradients flow to the targets and the opacities only (the geometry is held
 fixed, as in the paper's setting of a trained splat scene).  The backward
 passes call the hand-written adjoints gsc_colorize_backward and
 gsc_render_backward, which recompute the per-pixel weights instead of storing
-them.
+them.  Calls on the same geometry tensors (unmodified, same cameras) reuse
+the previous call's tile lists.
 
     coeffs = colorize(targets, opacities, means, scales, quats, cams, sh_deg, lam)
     images = render(coeffs, opacities, means, scales, quats, cams)
@@ -32,7 +33,7 @@ class ColorizeFn(torch.autograd.Function):
     def forward(ctx, targets, opacities, means, scales, quats, cams, sh_deg, lam, context, offsets):
         g = context or default_context()
         coeffs, _ = g.colorize(means, scales, quats, opacities, cams, targets, sh_deg, lam,
-                               offsets=offsets, with_status=False)
+                               offsets=offsets, with_status=False, reuse_binning=True)
         ctx.save_for_backward(targets, opacities, means, scales, quats, coeffs)
         ctx.cams, ctx.sh_deg, ctx.lam, ctx.g, ctx.offsets = cams, sh_deg, list(lam), g, offsets
         return coeffs
@@ -47,7 +48,7 @@ class ColorizeFn(torch.autograd.Function):
                                              ctx.sh_deg, ctx.lam, coeffs,
                                              grad_coeffs.detach().float().contiguous(),
                                              want_targets=want_t, want_opacities=want_o,
-                                             offsets=ctx.offsets)
+                                             offsets=ctx.offsets, reuse_binning=True)
             if gt is not None and gt.dtype != targets.dtype:
                 gt = gt.to(targets.dtype)
         return gt, go, None, None, None, None, None, None, None, None
@@ -58,7 +59,8 @@ class RenderFn(torch.autograd.Function):
     def forward(ctx, coeffs, opacities, means, scales, quats, cams, context, offsets):
         g = context or default_context()
         coeffs = coeffs.detach().float().contiguous()
-        images = g.render(means, scales, quats, opacities, cams, coeffs, offsets=offsets)
+        images = g.render(means, scales, quats, opacities, cams, coeffs, offsets=offsets,
+                          reuse_binning=True)
         ctx.save_for_backward(coeffs, opacities, means, scales, quats)
         ctx.cams, ctx.g, ctx.offsets = cams, g, offsets
         return images
@@ -72,7 +74,7 @@ class RenderFn(torch.autograd.Function):
             gc, go = ctx.g.render_backward(means, scales, quats, opacities, ctx.cams, coeffs,
                                            grad_images.detach().float().contiguous(),
                                            want_coeffs=want_c, want_opacities=want_o,
-                                           offsets=ctx.offsets)
+                                           offsets=ctx.offsets, reuse_binning=True)
         return gc, go, None, None, None, None, None, None
 
 

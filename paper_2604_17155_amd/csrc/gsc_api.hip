@@ -75,9 +75,32 @@ constexpr uint64_t kMaxPairsPerBatch = 1ull << 31;
 
 }  // namespace
 
+// What a binning depends on: the geometry arrays (by address; their contents
+// are the caller's promise under GSC_FLAG_REUSE_BINNING), the cameras, the
+// blend constants and the requested bin size.
+struct BinKey {
+    const float *means = nullptr, *scales = nullptr, *quats = nullptr, *opac = nullptr;
+    int64_t N = 0;
+    std::vector<gsc_camera> cams;
+    BlendParams bp{};
+    int bin_opt = 0;
+    bool same(const BinKey& o) const {
+        return means == o.means && scales == o.scales && quats == o.quats && opac == o.opac && N == o.N &&
+               bin_opt == o.bin_opt && cams.size() == o.cams.size() &&
+               (cams.empty() || memcmp(cams.data(), o.cams.data(), sizeof(gsc_camera) * cams.size()) == 0) &&
+               memcmp(&bp, &o.bp, sizeof(bp)) == 0;
+    }
+};
+
 struct gsc_ctx {
     gsc_options opt;
     int bin = 16;  // bin size of the current call
+    // the single-batch binning left in the buffers by the last call
+    bool cache_valid = false;
+    BinKey cache_key;
+    int cache_bin = 16;
+    uint32_t cache_tiles = 0, cache_pairs = 0;
+    uint64_t cache_items = 0;
     // device scratch
     DevBuf views, views_all, cov, keys, vals, keys_alt, vals_alt, counts, offsets, rec0, rec1, rec2,
         sort_scratch, pkeys, pvals, pkeys_alt, pvals_alt, ranges, vs, gamma, bbar, misc;
@@ -403,9 +426,23 @@ gsc_status bin_views(gsc_ctx* ctx, const std::vector<ViewInfo>& all, int v0, int
 template <typename Body>
 gsc_status for_view_batches(gsc_ctx* ctx, const std::vector<ViewInfo>& all, int n_cams,
                             const float* means, const float* opac, int64_t N, const BlendParams& bp,
-                            hipStream_t s, Body body) {
+                            hipStream_t s, Body body, const BinKey* key = nullptr, bool reuse = false) {
+    if (reuse) {  // the only batch of the previous call is still in place
+        Binned bn;
+        bn.n_tiles = ctx->cache_tiles;
+        bn.n_pairs = ctx->cache_pairs;
+        bn.n_items = ctx->cache_items;
+        gsc_status st = body(0, n_cams, bn);
+        if (st != GSC_OK) return st;
+        ctx->stats.pairs += bn.n_pairs;
+        ctx->stats.items += bn.n_items;
+        ctx->stats.view_batches += 1;
+        return GSC_OK;
+    }
     int per = (int)std::max<int64_t>(1, (int64_t)(kMaxItemsPerBatch / (uint64_t)std::max<int64_t>(N, 1)));
-    int v = 0;
+    int v = 0, batches = 0;
+    ctx->cache_valid = false;
+    Binned last;
     while (v < n_cams) {
         int nv = std::min(per, n_cams - v);
         Binned bn;
@@ -420,15 +457,55 @@ gsc_status for_view_batches(gsc_ctx* ctx, const std::vector<ViewInfo>& all, int 
         ctx->stats.items += bn.n_items;
         ctx->stats.view_batches += 1;
         v += nv;
+        ++batches;
+        last = bn;
+    }
+    if (key && batches == 1) {
+        ctx->cache_valid = true;
+        ctx->cache_key = *key;
+        ctx->cache_bin = ctx->bin;
+        ctx->cache_tiles = last.n_tiles;
+        ctx->cache_pairs = last.n_pairs;
+        ctx->cache_items = last.n_items;
     }
     return GSC_OK;
 }
 
+template <typename Body>
+gsc_status for_view_batches_k(gsc_ctx* ctx, const std::vector<ViewInfo>& all, int n_cams,
+                              const float* means, const float* opac, int64_t N, const BlendParams& bp,
+                              hipStream_t s, const BinKey* key, bool reuse, Body body) {
+    return for_view_batches(ctx, all, n_cams, means, opac, N, bp, s, body, key, reuse);
+}
+
+BinKey make_key(const gsc_ctx* ctx, const float* means, const float* scales, const float* quats,
+                const float* opac, int64_t N, const gsc_camera* cams, int n_cams, const BlendParams& bp) {
+    BinKey k;
+    k.means = means;
+    k.scales = scales;
+    k.quats = quats;
+    k.opac = opac;
+    k.N = N;
+    k.cams.assign(cams, cams + n_cams);
+    k.bp = bp;
+    k.bin_opt = ctx->opt.bin_size;
+    return k;
+}
+
+bool can_reuse(const gsc_ctx* ctx, const BinKey& key) {
+    return (ctx->opt.flags & GSC_FLAG_REUSE_BINNING) && ctx->cache_valid && ctx->cache_key.same(key);
+}
+
 gsc_status ensure_common(gsc_ctx* ctx, const float* means, const float* scales,
                          const float* quats, const float* opac, int64_t N, const gsc_camera* cams,
-                         int n_cams, hipStream_t s) {
+                         int n_cams, hipStream_t s, bool reuse = false) {
     GSC_HIP(ctx->misc.ensure(kMiscBytes));
     if (!ctx->h_total) GSC_HIP(hipHostMalloc((void**)&ctx->h_total, 64));
+    if (reuse) {  // bin size and packed geometry of the cached binning
+        ctx->bin = ctx->cache_bin;
+        launch_fill_u32(ctx->misc.as<uint32_t>(), 0u, kMiscBytes / 4, s);
+        return GSC_OK;
+    }
     ctx->bin = ctx->opt.bin_size;
     if (ctx->bin == 0) {
         double* d_stats = reinterpret_cast<double*>(ctx->misc.as<char>() + 32);
@@ -735,7 +812,9 @@ gsc_status gsc_colorize_ex(gsc_ctx* ctx, const float* means, const float* scales
     float* x_vis = extras ? extras->visibility : nullptr;
     uint32_t* x_cnt = extras ? extras->counts : nullptr;
     BlendParams bp = blend_params(ctx->opt);
-    if ((st = ensure_common(ctx, means, scales, quats, opacities, N, cams, n_cams, s)) != GSC_OK) return st;
+    const BinKey key = make_key(ctx, means, scales, quats, opacities, N, cams, n_cams, bp);
+    const bool reuse = can_reuse(ctx, key);
+    if ((st = ensure_common(ctx, means, scales, quats, opacities, N, cams, n_cams, s, reuse)) != GSC_OK) return st;
     std::vector<ViewInfo> all(n_cams);
     for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j], j, N, ctx->bin);
     const bool per_view = sh_deg > 0 || x_sums != nullptr;
@@ -744,7 +823,7 @@ gsc_status gsc_colorize_ex(gsc_ctx* ctx, const float* means, const float* scales
     launch_fill_u32(ctx->vs.as<uint32_t>(), 0u, vs_words, s);
     if (x_cnt) launch_fill_u32(x_cnt, 0u, (uint64_t)N, s);
     unsigned long long* d_counter = reinterpret_cast<unsigned long long*>(ctx->misc.p);
-    st = for_view_batches(ctx, all, n_cams, means, opacities, N, bp, s,
+    st = for_view_batches_k(ctx, all, n_cams, means, opacities, N, bp, s, &key, reuse,
                           [&](int v0, int nv, const Binned& bn) -> gsc_status {
         const int chunk = resolve_chunk(ctx->opt.accumulate_variant, C, tdtype);
         StageTimer t(ctx, s, GSC_STAGE_BLEND, (uint32_t)accumulate_launches(C, chunk));
@@ -801,17 +880,19 @@ gsc_status gsc_render(gsc_ctx* ctx, const float* means, const float* scales, con
     memset(&ctx->stats, 0, sizeof(ctx->stats));
     if (n_cams == 0) return GSC_OK;
     BlendParams bp = blend_params(ctx->opt);
-    if ((st = ensure_common(ctx, means, scales, quats, opacities, N, cams, n_cams, s)) != GSC_OK) return st;
+    const BinKey key = make_key(ctx, means, scales, quats, opacities, N, cams, n_cams, bp);
+    const bool reuse = can_reuse(ctx, key);
+    if ((st = ensure_common(ctx, means, scales, quats, opacities, N, cams, n_cams, s, reuse)) != GSC_OK) return st;
     std::vector<ViewInfo> all(n_cams);
     for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j], j, N, ctx->bin);
     unsigned long long* d_counter = reinterpret_cast<unsigned long long*>(ctx->misc.p);
-    st = for_view_batches(ctx, all, n_cams, means, opacities, N, bp, s,
+    st = for_view_batches_k(ctx, all, n_cams, means, opacities, N, bp, s, &key, reuse,
                           [&](int v0, int nv, const Binned& bn) -> gsc_status {
         (void)v0;
         StageTimer t(ctx, s, GSC_STAGE_BLEND, 1 + (uint32_t)((C + 3) / 4));
         GSC_HIP(ctx->gamma.ensure(4 * (size_t)nv * (size_t)std::max<int64_t>(N, 1) * (size_t)C));
-        launch_view_colors(ctx->views.as<ViewInfo>(), nv, (uint32_t)bn.n_items, ctx->vals.as<uint32_t>(),
-                           means, coeffs, C, sh_deg, ctx->gamma.as<float>(), s);
+        launch_view_colors(ctx->views.as<ViewInfo>(), nv, (uint32_t)bn.n_items, means, coeffs, C,
+                           sh_deg, ctx->gamma.as<float>(), s);
         GSC_LAUNCHED("view colors");
         launch_render(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
                       ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(), ctx->rec2.as<uint2>(), ctx->bin,
@@ -849,7 +930,9 @@ gsc_status gsc_colorize_backward(gsc_ctx* ctx, const float* means, const float* 
     if (N == 0 || n_cams == 0 || (!grad_targets && !grad_opacities)) return GSC_OK;
     const int nb = (sh_deg + 1) * (sh_deg + 1);
     BlendParams bp = blend_params(ctx->opt);
-    if ((st = ensure_common(ctx, means, scales, quats, opacities, N, cams, n_cams, s)) != GSC_OK) return st;
+    const BinKey key = make_key(ctx, means, scales, quats, opacities, N, cams, n_cams, bp);
+    const bool reuse = can_reuse(ctx, key);
+    if ((st = ensure_common(ctx, means, scales, quats, opacities, N, cams, n_cams, s, reuse)) != GSC_OK) return st;
     std::vector<ViewInfo> all(n_cams);
     for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j], j, N, ctx->bin);
     // 1. visibilities V_gj (the normal matrices depend on the weights only)
@@ -859,7 +942,7 @@ gsc_status gsc_colorize_backward(gsc_ctx* ctx, const float* means, const float* 
     launch_fill_u32(ctx->vs.as<uint32_t>(), 0u, v_words, s);
     unsigned long long* d_counter = reinterpret_cast<unsigned long long*>(ctx->misc.p);
     Binned last;
-    st = for_view_batches(ctx, all, n_cams, means, opacities, N, bp, s,
+    st = for_view_batches_k(ctx, all, n_cams, means, opacities, N, bp, s, &key, reuse,
                           [&](int v0, int nv, const Binned& bn) -> gsc_status {
         StageTimer t(ctx, s, GSC_STAGE_BLEND);
         (void)v0;
@@ -891,8 +974,8 @@ gsc_status gsc_colorize_backward(gsc_ctx* ctx, const float* means, const float* 
         (void)v0;
         GSC_HIP(ctx->gamma.ensure(4 * (size_t)nv * (size_t)N * (size_t)(C + 1)));
         StageTimer t(ctx, s, GSC_STAGE_BLEND_ADJOINT);
-        launch_view_adjoint(ctx->views.as<ViewInfo>(), nv, (uint32_t)bn.n_items, ctx->vals.as<uint32_t>(),
-                            means, coeffs, d_bbar, d_rho, C, sh_deg, false, ctx->gamma.as<float>(), s);
+        launch_view_adjoint(ctx->views.as<ViewInfo>(), nv, (uint32_t)bn.n_items, means, coeffs, d_bbar,
+                            d_rho, C, sh_deg, false, ctx->gamma.as<float>(), s);
         GSC_LAUNCHED("view adjoint");
         launch_blend_adjoint(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
                              ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(), ctx->rec2.as<uint2>(), ctx->bin,
@@ -904,7 +987,7 @@ gsc_status gsc_colorize_backward(gsc_ctx* ctx, const float* means, const float* 
     if (pass1.view_batches == 1) {
         st = body(0, n_cams, last);  // the binning of the only batch is still in place
     } else {
-        st = for_view_batches(ctx, all, n_cams, means, opacities, N, bp, s, body);
+        st = for_view_batches(ctx, all, n_cams, means, opacities, N, bp, s, body, &key, false);
     }
     if (st != GSC_OK) return st;
     ctx->stats.pairs = pass1.pairs;
@@ -934,7 +1017,9 @@ gsc_status gsc_render_backward(gsc_ctx* ctx, const float* means, const float* sc
     if (grad_opacities && N > 0) launch_fill_u32((uint32_t*)grad_opacities, 0u, (uint64_t)N, s);
     if (N == 0 || n_cams == 0 || (!grad_coeffs && !grad_opacities)) return GSC_OK;
     BlendParams bp = blend_params(ctx->opt);
-    if ((st = ensure_common(ctx, means, scales, quats, opacities, N, cams, n_cams, s)) != GSC_OK) return st;
+    const BinKey key = make_key(ctx, means, scales, quats, opacities, N, cams, n_cams, bp);
+    const bool reuse = can_reuse(ctx, key);
+    if ((st = ensure_common(ctx, means, scales, quats, opacities, N, cams, n_cams, s, reuse)) != GSC_OK) return st;
     std::vector<ViewInfo> all(n_cams);
     for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j], j, N, ctx->bin);
     const bool per_view = sh_deg > 0;
@@ -944,7 +1029,7 @@ gsc_status gsc_render_backward(gsc_ctx* ctx, const float* means, const float* sc
         launch_fill_u32(ctx->vs.as<uint32_t>(), 0u, vs_words, s);
     }
     unsigned long long* d_counter = reinterpret_cast<unsigned long long*>(ctx->misc.p);
-    st = for_view_batches(ctx, all, n_cams, means, opacities, N, bp, s,
+    st = for_view_batches_k(ctx, all, n_cams, means, opacities, N, bp, s, &key, reuse,
                           [&](int v0, int nv, const Binned& bn) -> gsc_status {
         if (grad_coeffs) {
             // dL/dc folds sum_p w (dL/dimages_p) per (view, Gaussian): the
@@ -960,9 +1045,8 @@ gsc_status gsc_render_backward(gsc_ctx* ctx, const float* means, const float* sc
         if (grad_opacities) {
             GSC_HIP(ctx->gamma.ensure(4 * (size_t)nv * (size_t)N * (size_t)(C + 1)));
             StageTimer t(ctx, s, GSC_STAGE_BLEND_ADJOINT);
-            launch_view_adjoint(ctx->views.as<ViewInfo>(), nv, (uint32_t)bn.n_items,
-                                ctx->vals.as<uint32_t>(), means, coeffs, nullptr, nullptr, C, sh_deg,
-                                true, ctx->gamma.as<float>(), s);
+            launch_view_adjoint(ctx->views.as<ViewInfo>(), nv, (uint32_t)bn.n_items, means, coeffs,
+                                nullptr, nullptr, C, sh_deg, true, ctx->gamma.as<float>(), s);
             GSC_LAUNCHED("view colours");
             launch_blend_adjoint(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
                                  ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(),

@@ -171,11 +171,10 @@ void launch_accumulate_chunked(const ViewInfo* views, int n_views, uint32_t n_ti
                                unsigned long long* counter, uint32_t* gcount, int chunk,
                                hipStream_t s, uint32_t* queues = nullptr);
 
-// Colour of the item of depth rank k (item order[k]):
-// gamma[k][c] = sum_m coeffs[g][m][c] phi_m(dir_gv).
-void launch_view_colors(const ViewInfo* views, int n_views, uint32_t n_items, const uint32_t* order,
-                        const float* means, const float* coeffs, int C, int sh_deg, float* gamma,
-                        hipStream_t s);
+// Colour of batch item i (view v, Gaussian g):
+// gamma[i][c] = sum_m coeffs[g][m][c] phi_m(dir_gv).
+void launch_view_colors(const ViewInfo* views, int n_views, uint32_t n_items, const float* means,
+                        const float* coeffs, int C, int sh_deg, float* gamma, hipStream_t s);
 
 void launch_render(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
                    const uint32_t* pair_vals, const float4* rec0, const float4* rec1, const uint2* rec2, int bin,
@@ -206,13 +205,12 @@ void launch_adjoint_solve(const ViewInfo* views, int n_views, const float* means
                           const float* grad_coeffs, const float* coeffs, float* bbar, float* rho,
                           float* w_scratch, hipStream_t s);
 
-// Adjoint colours of the item of depth rank k: beta [k][C+1] = (beta_gj, delta_gj).
+// Adjoint colours of batch item i: beta [i][C+1] = (beta_gj, delta_gj).
 // render: beta = c^T phi, delta = 0.  Otherwise beta = bbar^T phi and
 // delta = beta^T (c^T phi) + rho_g.
-void launch_view_adjoint(const ViewInfo* views, int n_views, uint32_t n_items, const uint32_t* order,
-                         const float* means, const float* coeffs, const float* bbar,
-                         const float* rho, int C, int sh_deg, bool render, float* beta,
-                         hipStream_t s);
+void launch_view_adjoint(const ViewInfo* views, int n_views, uint32_t n_items, const float* means,
+                         const float* coeffs, const float* bbar, const float* rho, int C, int sh_deg,
+                         bool render, float* beta, hipStream_t s);
 
 // Blend adjoint over the binned tiles: grad_y[row][c] = sum_g w beta (every
 // pixel of every view written, if grad_y) and grad_o[g] += dL/do (atomics, if grad_o).

@@ -765,16 +765,16 @@ void launch_accumulate_weights(const ViewInfo* views, int n_views, uint32_t n_ti
 
 // ---- render ----------------------------------------------------------------
 
-// gamma[k*C + c] = sum_m coeffs[g][m][c] * phi_m(dir_gv) for the batch item of
-// depth rank k (item order[k]).
+// gamma[i*C + c] = sum_m coeffs[g][m][c] * phi_m(dir_gv) for batch item i
+// (view v, Gaussian g): items in their own order, so that consecutive threads
+// read consecutive Gaussians' coefficients.
 template <int L>
 __global__ void k_view_colors(const ViewInfo* __restrict__ views, int n_views, uint32_t n_items,
-                              const uint32_t* __restrict__ order, const float* __restrict__ means,
-                              const float* __restrict__ coeffs, int C, float* __restrict__ gamma) {
+                              const float* __restrict__ means, const float* __restrict__ coeffs,
+                              int C, float* __restrict__ gamma) {
     constexpr int NB = (L + 1) * (L + 1);
-    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n_items) return;
-    const uint32_t i = order[k];
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_items) return;
     const ViewInfo& V = views[find_view_item(views, n_views, i)];
     const int64_t g = V.g_offset + (int64_t)(i - V.item_base);
     double dx = (double)means[3 * g] - V.centre[0];
@@ -784,7 +784,7 @@ __global__ void k_view_colors(const ViewInfo* __restrict__ views, int n_views, u
     float phi[NB];
     sh_eval<float, L>((float)(dx * inv), (float)(dy * inv), (float)(dz * inv), phi);
     const float* cg = coeffs + g * NB * C;
-    float* out = gamma + (int64_t)k * C;
+    float* out = gamma + (int64_t)i * C;
     for (int c = 0; c < C; ++c) {
         float a = 0.0f;
 #pragma unroll
@@ -793,16 +793,15 @@ __global__ void k_view_colors(const ViewInfo* __restrict__ views, int n_views, u
     }
 }
 
-void launch_view_colors(const ViewInfo* views, int n_views, uint32_t n_items, const uint32_t* order,
-                        const float* means, const float* coeffs, int C, int sh_deg, float* gamma,
-                        hipStream_t s) {
+void launch_view_colors(const ViewInfo* views, int n_views, uint32_t n_items, const float* means,
+                        const float* coeffs, int C, int sh_deg, float* gamma, hipStream_t s) {
     if (n_items == 0 || n_views <= 0) return;
     dim3 grid((n_items + 255) / 256), block(256);
     switch (sh_deg) {
-        case 0: hipLaunchKernelGGL(k_view_colors<0>, grid, block, 0, s, views, n_views, n_items, order, means, coeffs, C, gamma); break;
-        case 1: hipLaunchKernelGGL(k_view_colors<1>, grid, block, 0, s, views, n_views, n_items, order, means, coeffs, C, gamma); break;
-        case 2: hipLaunchKernelGGL(k_view_colors<2>, grid, block, 0, s, views, n_views, n_items, order, means, coeffs, C, gamma); break;
-        default: hipLaunchKernelGGL(k_view_colors<3>, grid, block, 0, s, views, n_views, n_items, order, means, coeffs, C, gamma); break;
+        case 0: hipLaunchKernelGGL(k_view_colors<0>, grid, block, 0, s, views, n_views, n_items, means, coeffs, C, gamma); break;
+        case 1: hipLaunchKernelGGL(k_view_colors<1>, grid, block, 0, s, views, n_views, n_items, means, coeffs, C, gamma); break;
+        case 2: hipLaunchKernelGGL(k_view_colors<2>, grid, block, 0, s, views, n_views, n_items, means, coeffs, C, gamma); break;
+        default: hipLaunchKernelGGL(k_view_colors<3>, grid, block, 0, s, views, n_views, n_items, means, coeffs, C, gamma); break;
     }
 }
 
@@ -863,7 +862,7 @@ __global__ __launch_bounds__(256) void k_render(
             }
             const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2.x, tg.y0) & alive;
             if (bands == 0u) continue;
-            const uint32_t item = pc & kItemMask;
+            const uint32_t item = e2.y;  // the record names the item
             float col[CC];
             const float* gp = gamma + (int64_t)item * C + c_off;
 #pragma unroll

@@ -30,18 +30,16 @@
 
 namespace gsc {
 
-// beta[k*(C+1) + c] = beta_gj[c] and [.. + C] = delta_gj for the item of depth
-// rank k (item order[k]).
+// beta[i*(C+1) + c] = beta_gj[c] and [.. + C] = delta_gj for batch item i
+// (view v, Gaussian g), items in their own order (coalesced coefficient reads).
 template <int L, bool RENDER>
 __global__ void k_view_adjoint(const ViewInfo* __restrict__ views, int n_views, uint32_t n_items,
-                               const uint32_t* __restrict__ order,
                                const float* __restrict__ means, const float* __restrict__ coeffs,
                                const float* __restrict__ bbar, const float* __restrict__ rho, int C,
                                float* __restrict__ beta) {
     constexpr int NB = (L + 1) * (L + 1);
-    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n_items) return;
-    const uint32_t i = order[k];
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_items) return;
     const ViewInfo& V = views[find_view_item(views, n_views, i)];
     const int64_t g = V.g_offset + (int64_t)(i - V.item_base);
     const double dx = (double)means[3 * g] - V.centre[0];
@@ -51,7 +49,7 @@ __global__ void k_view_adjoint(const ViewInfo* __restrict__ views, int n_views, 
     float phi[NB];
     sh_eval<float, L>((float)(dx * inv), (float)(dy * inv), (float)(dz * inv), phi);
     const float* cg = coeffs + g * NB * C;
-    float* out = beta + (int64_t)k * (C + 1);
+    float* out = beta + (int64_t)i * (C + 1);
     if constexpr (RENDER) {
         for (int c = 0; c < C; ++c) {
             float a = 0.0f;
@@ -77,20 +75,19 @@ __global__ void k_view_adjoint(const ViewInfo* __restrict__ views, int n_views, 
     }
 }
 
-void launch_view_adjoint(const ViewInfo* views, int n_views, uint32_t n_items, const uint32_t* order,
-                         const float* means, const float* coeffs, const float* bbar,
-                         const float* rho, int C, int sh_deg, bool render, float* beta,
-                         hipStream_t s) {
+void launch_view_adjoint(const ViewInfo* views, int n_views, uint32_t n_items, const float* means,
+                         const float* coeffs, const float* bbar, const float* rho, int C, int sh_deg,
+                         bool render, float* beta, hipStream_t s) {
     if (n_items == 0 || n_views <= 0) return;
     dim3 grid((n_items + 255) / 256), block(256);
 #define GSC_VA(LL)                                                                                   \
     do {                                                                                             \
         if (render)                                                                                  \
             hipLaunchKernelGGL((k_view_adjoint<LL, true>), grid, block, 0, s, views, n_views,        \
-                               n_items, order, means, coeffs, bbar, rho, C, beta);                          \
+                               n_items, means, coeffs, bbar, rho, C, beta);                          \
         else                                                                                         \
             hipLaunchKernelGGL((k_view_adjoint<LL, false>), grid, block, 0, s, views, n_views,       \
-                               n_items, order, means, coeffs, bbar, rho, C, beta);                          \
+                               n_items, means, coeffs, bbar, rho, C, beta);                          \
     } while (0)
     switch (sh_deg) {
         case 0: GSC_VA(0); break;
@@ -205,7 +202,7 @@ __global__ __launch_bounds__(256) void k_blend_adjoint(
             }
             const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2.x, tg.y0);
             if (bands == 0u) continue;
-            const uint32_t item = pc & kItemMask;
+            const uint32_t item = e2.y;  // the record names the item
             const float* bp_ = beta + (int64_t)item * stride;
             float bet[CC];
 #pragma unroll
@@ -274,7 +271,7 @@ __global__ __launch_bounds__(256) void k_blend_adjoint(
             }
             const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2.x, tg.y0);
             if (bands == 0u) continue;
-            const uint32_t item = pc & kItemMask;
+            const uint32_t item = e2.y;  // the record names the item
             const float* bp_ = beta + (int64_t)item * stride;
             float bet[CC];
 #pragma unroll

@@ -9,6 +9,7 @@ anything else.
 from __future__ import annotations
 
 import ctypes as ct
+import weakref
 import os
 from typing import Optional, Sequence
 
@@ -44,6 +45,7 @@ class GscOptions(ct.Structure):
 
 
 GSC_FLAG_PROFILE = 2
+GSC_FLAG_REUSE_BINNING = 4
 STAGES = ["project", "depth_sort", "scan", "emit", "tile_sort", "blend", "solve", "blend_adjoint"]
 
 
@@ -204,6 +206,34 @@ class Context:
             setattr(self.options, k, v)
         _check(self.lib, self.lib.gsc_ctx_set_options(self.handle, ct.byref(self.options)))
 
+
+    # --- binning reuse -------------------------------------------------------
+    # The library may reuse the tile lists of the previous call on this context
+    # (GSC_FLAG_REUSE_BINNING) when the geometry is unchanged.  That is only
+    # asked for when the caller allows it (reuse_binning=True) and the
+    # geometry tensors are the very objects of the previous call, unmodified
+    # since (same version counters), with the same cameras.
+    def _reuse_begin(self, tensors, cam_arr, allow: bool) -> bool:
+        last = getattr(self, "_last_geo", None)
+        ok = False
+        if allow and last is not None:
+            refs, vers, cb = last
+            ok = (all(r() is t for r, t in zip(refs, tensors)) and
+                  vers == tuple(int(t._version) for t in tensors) and cb == bytes(cam_arr))
+        if ok:
+            self.options.flags |= GSC_FLAG_REUSE_BINNING
+            _check(self.lib, self.lib.gsc_ctx_set_options(self.handle, ct.byref(self.options)))
+        self._last_geo = None
+        return ok
+
+    def _reuse_end(self, tensors, cam_arr, used: bool, succeeded: bool):
+        if used:
+            self.options.flags &= ~GSC_FLAG_REUSE_BINNING
+            _check(self.lib, self.lib.gsc_ctx_set_options(self.handle, ct.byref(self.options)))
+        if succeeded:
+            self._last_geo = ([weakref.ref(t) for t in tensors],
+                              tuple(int(t._version) for t in tensors), bytes(cam_arr))
+
     def stats(self) -> GscStats:
         out = GscStats()
         _check(self.lib, self.lib.gsc_get_stats(self.handle, ct.byref(out)))
@@ -211,7 +241,7 @@ class Context:
 
     def colorize(self, means, scales, quats, opacities, cams, targets, sh_deg: int, lam,
                  coeffs=None, status=None, offsets=None, stream=None, with_status: bool = True,
-                 extras=None):
+                 extras=None, reuse_binning: bool = False):
         """Solve the per-Gaussian regularised normal equations.  Returns
         (coeffs [N,(L+1)^2,C] float32, status [N] uint8 or None).
 
@@ -247,17 +277,20 @@ class Context:
                 xd["counts"] = torch.zeros((N,), dtype=torch.int32, device=dev)
             xs = GscExtras(_ptr(xd.get("view_sums")), _ptr(xd.get("visibility")),
                            _ptr(xd.get("counts")))
+        geo = (means, scales, quats, opacities)
+        used = self._reuse_begin(geo, cam_arr, reuse_binning)
         st = self.lib.gsc_colorize_ex(self.handle, _ptr(means), _ptr(scales), _ptr(quats),
                                       _ptr(opacities), N, cam_arr, len(cams), _ptr(targets), td, C,
                                       sh_deg, lam_a, len(lam), _ptr(coeffs), _ptr(status),
                                       None if xs is None else ct.byref(xs), _stream_ptr(stream))
+        self._reuse_end(geo, cam_arr, used, st == GSC_OK)
         _check(self.lib, st)
         if xd is not None:
             return coeffs, status, xd
         return coeffs, status
 
     def render(self, means, scales, quats, opacities, cams, coeffs, images=None, offsets=None,
-               stream=None):
+               stream=None, reuse_binning: bool = False):
         """Render coefficients [N,(L+1)^2,C] to images [sum HW, C] float32."""
         import torch
         N = int(means.shape[0])
@@ -267,16 +300,19 @@ class Context:
         if images is None:
             images = torch.empty((rows, C), dtype=torch.float32, device=means.device)
         cam_arr = make_cameras(cams, offsets)
+        geo = (means, scales, quats, opacities)
+        used = self._reuse_begin(geo, cam_arr, reuse_binning)
         st = self.lib.gsc_render(self.handle, _ptr(means), _ptr(scales), _ptr(quats),
                                  _ptr(opacities), N, cam_arr, len(cams), _ptr(coeffs), C, sh_deg,
                                  _ptr(images), _stream_ptr(stream))
+        self._reuse_end(geo, cam_arr, used, st == GSC_OK)
         _check(self.lib, st)
         return images
 
 
     def colorize_backward(self, means, scales, quats, opacities, cams, targets, sh_deg: int, lam,
                           coeffs, grad_coeffs, want_targets: bool = True, want_opacities: bool = True,
-                          offsets=None, stream=None):
+                          offsets=None, stream=None, reuse_binning: bool = False):
         """Adjoint of colorize at `coeffs` for dL/dcoeffs = grad_coeffs.  Returns
         (grad_targets [rows, C] float32 or None, grad_opacities [N] float32 or None)."""
         import torch
@@ -294,16 +330,19 @@ class Context:
         go = torch.empty((N,), dtype=torch.float32, device=dev) if want_opacities else None
         lam_a = (ct.c_float * len(lam))(*[float(v) for v in lam])
         cam_arr = make_cameras(cams, offsets)
+        geo = (means, scales, quats, opacities)
+        used = self._reuse_begin(geo, cam_arr, reuse_binning)
         st = self.lib.gsc_colorize_backward(self.handle, _ptr(means), _ptr(scales), _ptr(quats),
                                             _ptr(opacities), N, cam_arr, len(cams), _ptr(targets), td,
                                             C, sh_deg, lam_a, len(lam), _ptr(coeffs),
                                             _ptr(grad_coeffs), _ptr(gt), _ptr(go), _stream_ptr(stream))
+        self._reuse_end(geo, cam_arr, used, st == GSC_OK)
         _check(self.lib, st)
         return gt, go
 
     def render_backward(self, means, scales, quats, opacities, cams, coeffs, grad_images,
                         want_coeffs: bool = True, want_opacities: bool = True, offsets=None,
-                        stream=None):
+                        stream=None, reuse_binning: bool = False):
         """Adjoint of render for dL/dimages = grad_images.  Returns
         (grad_coeffs [N,(L+1)^2,C] or None, grad_opacities [N] or None)."""
         import torch
@@ -314,10 +353,13 @@ class Context:
         gc = torch.empty((N, nb, C), dtype=torch.float32, device=dev) if want_coeffs else None
         go = torch.empty((N,), dtype=torch.float32, device=dev) if want_opacities else None
         cam_arr = make_cameras(cams, offsets)
+        geo = (means, scales, quats, opacities)
+        used = self._reuse_begin(geo, cam_arr, reuse_binning)
         st = self.lib.gsc_render_backward(self.handle, _ptr(means), _ptr(scales), _ptr(quats),
                                           _ptr(opacities), N, cam_arr, len(cams), _ptr(coeffs), C,
                                           sh_deg, _ptr(grad_images), _ptr(gc), _ptr(go),
                                           _stream_ptr(stream))
+        self._reuse_end(geo, cam_arr, used, st == GSC_OK)
         _check(self.lib, st)
         return gc, go
 

@@ -201,6 +201,55 @@ def test_autograd_rerender_loss(ctx_smooth, gsc_mod):
     assert ey <= TOL_GRAD and eo <= TOL_GRAD
 
 
+def test_binning_reuse(gsc_mod):
+    """Calls on the same, unmodified geometry tensors reuse the previous call's
+    tile lists (no projection launched) with the same result as a fresh
+    binning; an in-place change of the opacities, other cameras, or a call
+    that does not allow reuse bin anew."""
+    import torch
+    sc = syn.make_relight(seed_offset=31, n=6000, n_cams=6, res=128)
+    y = _dev(oracle.make_targets(sc))
+    m, s, q, o = gsc_mod.scene_tensors(sc)
+    lam = list(sc.lam)
+    ctx = gsc_mod.Context(flags=gsc_mod.GSC_FLAG_PROFILE)
+    fresh = gsc_mod.Context()
+
+    def projected(c):
+        return int(c.stats().stage_launches[0])
+
+    c1, _ = ctx.colorize(m, s, q, o, sc.cams, y, sc.sh_deg, lam, reuse_binning=True)
+    torch.cuda.synchronize()
+    assert projected(ctx) > 0  # nothing to reuse yet
+    c2, _ = ctx.colorize(m, s, q, o, sc.cams, y, sc.sh_deg, lam, reuse_binning=True)
+    torch.cuda.synchronize()
+    assert projected(ctx) == 0  # reused
+    img = ctx.render(m, s, q, o, sc.cams, c2, reuse_binning=True)
+    torch.cuda.synchronize()
+    assert projected(ctx) == 0
+    ref, _ = fresh.colorize(m, s, q, o, sc.cams, y, sc.sh_deg, lam)
+    img_ref = fresh.render(m, s, q, o, sc.cams, ref)
+    torch.cuda.synchronize()
+    assert torch.allclose(c2, ref, rtol=1e-5, atol=1e-6)
+    assert torch.allclose(img, img_ref, rtol=1e-5, atol=1e-6)
+    # an in-place change of the opacities: new binning, new result
+    o.mul_(0.8)
+    c3, _ = ctx.colorize(m, s, q, o, sc.cams, y, sc.sh_deg, lam, reuse_binning=True)
+    torch.cuda.synchronize()
+    assert projected(ctx) > 0
+    ref3, _ = fresh.colorize(m, s, q, o, sc.cams, y, sc.sh_deg, lam)
+    torch.cuda.synchronize()
+    assert torch.allclose(c3, ref3, rtol=1e-5, atol=1e-6)
+    assert not torch.allclose(c3, ref, rtol=1e-3, atol=1e-4)
+    # other cameras
+    ctx.colorize(m, s, q, o, sc.cams[:4], y, sc.sh_deg, lam, reuse_binning=True)
+    torch.cuda.synchronize()
+    assert projected(ctx) > 0
+    # reuse not allowed by the caller
+    ctx.colorize(m, s, q, o, sc.cams[:4], y, sc.sh_deg, lam)
+    torch.cuda.synchronize()
+    assert projected(ctx) > 0
+
+
 def test_backward_degenerate(ctx_prod, gsc_mod):
     import torch
     from tests import tiny
