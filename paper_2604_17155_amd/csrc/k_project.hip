@@ -341,42 +341,73 @@ void launch_project(const ViewInfo* views, int n_views, uint32_t n_items, const 
 // a3: emit (global bin id, k | mask) pairs in depth order, k being the depth
 // rank of the item (records, counts and offsets are in that order); a stable
 // sort by bin id then yields every bin's list in front-to-back order.
+constexpr uint32_t kEmitStage = 3072;  // pairs a block stages in LDS (24 KB)
+
 template <int BIN>
-__global__ void k_emit(const ViewInfo* __restrict__ views, int n_views,
-                       const uint32_t* __restrict__ sorted_vals,
-                       const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ counts,
-                       const float4* __restrict__ rec0, const float4* __restrict__ rec1,
-                       BlendParams bp, uint32_t n_items, uint32_t sentinel, uint32_t cap,
-                       uint32_t* __restrict__ overflow,
-                       uint32_t* __restrict__ pair_keys, uint32_t* __restrict__ pair_vals) {
-    uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n_items) return;
-    const uint32_t cnt = counts[k];
-    if (cnt == 0) return;
-    const ViewInfo& V = views[find_view_item(views, n_views, sorted_vals[k])];
-    const float4 r0 = rec0[k], r1 = rec1[k];
-    uint32_t off = offsets[k];
-    uint32_t end = off + cnt;
-    if (end > cap || end < off) {  // capacity exceeded: keep what fits, report the rest
-        if (overflow) atomicAdd(overflow, 1u);
-        end = off < cap ? cap : off;
-    }
-    footprint_bins<BIN>(r0, r1, reach_q(r1.w, bp), V.width, V.height,
-                        [&](int ty, int t0, int t1, auto&& mask_of) {
-        for (int t = t0; t <= t1; ++t) {
-            const uint32_t m = mask_of(t);
-            if (m == 0u || off >= end) continue;
-            pair_keys[off] = V.tile_base + (uint32_t)ty * (uint32_t)V.tiles_x + (uint32_t)t;
-            pair_vals[off] = k | (m << kItemBits);
-            ++off;
+__global__ __launch_bounds__(256) void k_emit(const ViewInfo* __restrict__ views, int n_views,
+                                              const uint32_t* __restrict__ sorted_vals,
+                                              const uint32_t* __restrict__ offsets,
+                                              const uint32_t* __restrict__ counts,
+                                              const float4* __restrict__ rec0,
+                                              const float4* __restrict__ rec1, BlendParams bp,
+                                              uint32_t n_items, uint32_t sentinel, uint32_t cap,
+                                              uint32_t* __restrict__ overflow,
+                                              uint32_t* __restrict__ pair_keys,
+                                              uint32_t* __restrict__ pair_vals) {
+    // The block's items are consecutive depth ranks, so their pairs form one
+    // contiguous range [base, end_all): when it fits, the pairs are assembled
+    // in LDS and stored with full-width coalesced writes.
+    __shared__ uint32_t skey[kEmitStage];
+    __shared__ uint32_t sval[kEmitStage];
+    const uint32_t k0 = blockIdx.x * blockDim.x;
+    const uint32_t klast = min(k0 + blockDim.x, n_items) - 1;
+    const uint32_t base = offsets[k0];
+    const uint32_t end_all = offsets[klast] + counts[klast];
+    const bool staged = end_all - base <= kEmitStage;
+    const uint32_t k = k0 + threadIdx.x;
+    if (k < n_items) {
+        const uint32_t cnt = counts[k];
+        if (cnt != 0) {
+            const ViewInfo& V = views[find_view_item(views, n_views, sorted_vals[k])];
+            const float4 r0 = rec0[k], r1 = rec1[k];
+            uint32_t off = offsets[k];
+            uint32_t end = off + cnt;
+            if (end > cap || end < off) {  // capacity exceeded: keep what fits, report the rest
+                if (overflow) atomicAdd(overflow, 1u);
+                end = off < cap ? cap : off;
+            }
+            auto put = [&](uint32_t o, uint32_t key, uint32_t val) {
+                if (staged) {
+                    skey[o - base] = key;
+                    sval[o - base] = val;
+                } else {
+                    pair_keys[o] = key;
+                    pair_vals[o] = val;
+                }
+            };
+            footprint_bins<BIN>(r0, r1, reach_q(r1.w, bp), V.width, V.height,
+                                [&](int ty, int t0, int t1, auto&& mask_of) {
+                for (int t = t0; t <= t1; ++t) {
+                    const uint32_t m = mask_of(t);
+                    if (m == 0u || off >= end) continue;
+                    put(off, V.tile_base + (uint32_t)ty * (uint32_t)V.tiles_x + (uint32_t)t,
+                        k | (m << kItemBits));
+                    ++off;
+                }
+            });
+            // The walk above and the one that counted are the same code on the
+            // same record; should they ever disagree, unused slots get a tile
+            // id past the last tile, which sorts last and is ignored by the
+            // range kernel.
+            for (; off < end; ++off) put(off, sentinel, 0u);
         }
-    });
-    // The walk above and the one that counted are the same code on the same
-    // record; should they ever disagree, unused slots get a tile id past the
-    // last tile, which sorts last and is ignored by the range kernel.
-    for (; off < end; ++off) {
-        pair_keys[off] = sentinel;
-        pair_vals[off] = 0u;
+    }
+    if (!staged) return;  // uniform over the block
+    __syncthreads();
+    const uint32_t lim = min(end_all, max(cap, base));
+    for (uint32_t o = base + threadIdx.x; o < lim; o += blockDim.x) {
+        pair_keys[o] = skey[o - base];
+        pair_vals[o] = sval[o - base];
     }
 }
 
