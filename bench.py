@@ -61,7 +61,7 @@ def cpu_baseline(sc, threads: int, what: str):
     return {"value": r["count"] / dt, "unit": "contributions/s", "cores": threads, "kind": "oracle",
             "sample": f"{what}: one colorize of {sc.N} Gaussians, {len(sc.cams)} views "
                       f"{sc.cams[0].width}x{sc.cams[0].height}, L={sc.sh_deg}, C={sc.C}; "
-                      f"{r['count']} contributions in {dt:.2f} s (oracle-rendered targets)"}
+                      f"{r['count']} contributions in {dt:.3g} s (oracle-rendered targets)"}
 
 
 def gpu_targets(gsc, sc, which=0, bf16=False):
@@ -270,6 +270,49 @@ def workload_batched(args, gsc):
     return out
 
 
+def workload_plain(args, gsc):
+    """The plain 2k-Gaussian scene (8 views 64x64, L=0, C=3) as a one-scene
+    plan captured into a graph: a step is one replay (scenes/s)."""
+    import torch
+    from paper_2604_17155_amd import synthetic as syn
+    sc = syn.make_plain(n=args.n or 2000, n_cams=args.views or 8, res=args.res or 64)
+    targets = gpu_targets(gsc, sc)
+    m, s, q, o = gsc.scene_tensors(sc)
+    ctx = gsc.Context(bin_size=args.bin, accumulate_variant=args.variant)
+    plan = gsc.Plan(ctx, [(0, sc.N, 0, len(sc.cams))], m, s, q, o, list(sc.cams), sc.C, sc.sh_deg)
+    lam = list(sc.lam)
+    coeffs, status = plan.run(targets, lam)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(max(1, args.warmup)):
+            plan.run(targets, lam, coeffs, status)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.run(targets, lam, coeffs, status)
+    graph.replay()
+    torch.cuda.synchronize()
+    contrib = int(plan.info().contributions)
+    steps = max(args.steps, 200)  # a replay takes tens of microseconds
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    config = {"workload": f"plain: {sc.N} isotropic Gaussians, {len(sc.cams)} circle cameras "
+                          f"{sc.cams[0].width}x{sc.cams[0].height}, SH degree 0, C=3, FP32 targets, "
+                          f"one-scene plan replayed as a graph",
+              "contributions_per_step": contrib, "scenes_per_sec": steps / elapsed,
+              "replays": steps}
+    out = line(args, contrib * steps / elapsed, 1e3 * elapsed / steps, "f32", config, None)
+    out["steps"] = steps
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sc, host_threads(), "the full workload")
+    return out
+
+
 def workload_diff(args, gsc):
     import torch
     from paper_2604_17155_amd import autograd as ag, synthetic as syn
@@ -337,7 +380,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="relight", choices=["relight", "features", "batched", "diff"])
+    ap.add_argument("--workload", default="relight",
+                    choices=["relight", "features", "batched", "diff", "plain"])
     ap.add_argument("--n", type=int, default=0, help="Gaussians (0: the workload's size)")
     ap.add_argument("--views", type=int, default=0, help="cameras (0: the workload's count)")
     ap.add_argument("--res", type=int, default=0, help="square resolution (0: the workload's)")
@@ -366,6 +410,7 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     fn = {"relight": workload_relight, "features": workload_features, "batched": workload_batched,
+          "plain": workload_plain,
           "diff": workload_diff}[args.workload]
     print(json.dumps(fn(args, gsc)), flush=True)
 
