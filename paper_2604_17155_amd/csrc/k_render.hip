@@ -1,0 +1,167 @@
+// Render: per-item view colours from SH coefficients, then the same
+// front-to-back tile blend as the accumulate pass, writing each pixel's
+// blended colour (eq. 2 with the colours of eq. 3).
+#include "gsc_internal.h"
+#include "sh.h"
+#include "wave_ops.h"
+
+namespace gsc {
+
+static inline uint32_t wave_tiles(uint32_t n_bins, int bin) { return bin == 32 ? 4u * n_bins : n_bins; }
+
+// gamma[i*C + c] = sum_m coeffs[g][m][c] * phi_m(dir_gv) for batch item i
+// (view v, Gaussian g): items in their own order, so that consecutive threads
+// read consecutive Gaussians' coefficients.
+template <int L>
+__global__ void k_view_colors(const ViewInfo* __restrict__ views, int n_views, uint32_t n_items,
+                              const float* __restrict__ means, const float* __restrict__ coeffs,
+                              int C, float* __restrict__ gamma) {
+    constexpr int NB = (L + 1) * (L + 1);
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_items) return;
+    const ViewInfo& V = views[find_view_item(views, n_views, i)];
+    const int64_t g = V.g_offset + (int64_t)(i - V.item_base);
+    double dx = (double)means[3 * g] - V.centre[0];
+    double dy = (double)means[3 * g + 1] - V.centre[1];
+    double dz = (double)means[3 * g + 2] - V.centre[2];
+    double inv = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+    float phi[NB];
+    sh_eval<float, L>((float)(dx * inv), (float)(dy * inv), (float)(dz * inv), phi);
+    const float* cg = coeffs + g * NB * C;
+    float* out = gamma + (int64_t)i * C;
+    for (int c = 0; c < C; ++c) {
+        float a = 0.0f;
+#pragma unroll
+        for (int m = 0; m < NB; ++m) a += cg[m * C + c] * phi[m];
+        out[c] = a;
+    }
+}
+
+void launch_view_colors(const ViewInfo* views, int n_views, uint32_t n_items, const float* means,
+                        const float* coeffs, int C, int sh_deg, float* gamma, hipStream_t s) {
+    if (n_items == 0 || n_views <= 0) return;
+    dim3 grid((n_items + 255) / 256), block(256);
+    switch (sh_deg) {
+        case 0: hipLaunchKernelGGL(k_view_colors<0>, grid, block, 0, s, views, n_views, n_items, means, coeffs, C, gamma); break;
+        case 1: hipLaunchKernelGGL(k_view_colors<1>, grid, block, 0, s, views, n_views, n_items, means, coeffs, C, gamma); break;
+        case 2: hipLaunchKernelGGL(k_view_colors<2>, grid, block, 0, s, views, n_views, n_items, means, coeffs, C, gamma); break;
+        default: hipLaunchKernelGGL(k_view_colors<3>, grid, block, 0, s, views, n_views, n_items, means, coeffs, C, gamma); break;
+    }
+}
+
+// images[row][c] = sum_g w_gp * gamma_gv[c]; every pixel of every tile is
+// written.  Same tile walk and blend decisions as accumulate_tile.
+template <int CC, int BIN>
+__global__ __launch_bounds__(256) void k_render(
+    const ViewInfo* __restrict__ views, int n_views, uint32_t n_wt, const uint2* __restrict__ ranges,
+    const uint32_t* __restrict__ pair_vals, const float4* __restrict__ rec0,
+    const float4* __restrict__ rec1, const uint2* __restrict__ rec2,
+    const float* __restrict__ gamma, int C, int c_off, BlendParams bp, float* __restrict__ images,
+    unsigned long long* __restrict__ counter) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wt = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wt >= n_wt) return;
+    const TileGeom tg = tile_geom<BIN>(wt, views, n_views);
+    const ViewInfo& V = views[tg.vloc];
+    const int ix = tg.x0 + (int)(lane & 15);
+    const int iy0 = tg.y0 + (int)(lane >> 4);
+    const float px = (float)ix + 0.5f;
+    float T[4];
+    bool inside[4];
+    float img[4][CC];
+    uint32_t alive = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        inside[k] = ix < V.width && iy0 + 4 * k < V.height;
+        T[k] = inside[k] ? 1.0f : 0.0f;
+        alive |= (__builtin_amdgcn_ballot_w64(inside[k]) != 0 ? 1u : 0u) << k;
+#pragma unroll
+        for (int c = 0; c < CC; ++c) img[k][c] = 0.0f;
+    }
+    alive = (uint32_t)__builtin_amdgcn_readfirstlane((int)alive);
+    uint2 rg = ranges[tg.bin];
+    rg.x = (uint32_t)__builtin_amdgcn_readfirstlane((int)rg.x);
+    rg.y = (uint32_t)__builtin_amdgcn_readfirstlane((int)rg.y);
+    uint32_t cnt = 0;
+    const float qlim = (float)(kExp2Scale * (double)bp.cut2);
+    const float amax = bp.alpha_max, amin = bp.alpha_min, tmin = bp.t_min;
+    float pyk[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pyk[k] = (float)(iy0 + 4 * k) + 0.5f;
+    for (uint32_t b = rg.x; b < rg.y && alive != 0u; b += 64) {
+        const uint32_t nb = min(64u, rg.y - b);
+        const uint32_t pv = lane < nb ? pair_vals[b + lane] : 0u;
+        uint32_t pn = bcast_u(pv, 0);
+        float4 n0 = rec0[pn & kItemMask], n1 = rec1[pn & kItemMask];
+        uint2 n2 = rec2[pn & kItemMask];
+        for (uint32_t j = 0; j < nb; ++j) {
+            const uint32_t pc = pn;
+            const float4 c0 = n0, c1 = n1;
+            const uint2 e2 = n2;
+            if (j + 1 < nb) {
+                pn = bcast_u(pv, j + 1);
+                n0 = rec0[pn & kItemMask];
+                n1 = rec1[pn & kItemMask];
+                n2 = rec2[pn & kItemMask];
+            }
+            const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2.x, tg.y0) & alive;
+            if (bands == 0u) continue;
+            const uint32_t item = e2.y;  // the record names the item
+            float col[CC];
+            const float* gp = gamma + (int64_t)item * C + c_off;
+#pragma unroll
+            for (int c = 0; c < CC; ++c) col[c] = (c_off + c < C) ? gp[c] : 0.0f;
+            const float dx = (px - c0.x) - c0.z;
+            const float a0 = c1.x * dx * dx;
+            const float b0 = c1.y * dx;
+            uint32_t nh = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (!((bands >> k) & 1u)) continue;
+                const float dy = (pyk[k] - c0.y) - c0.w;
+                const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
+                uint64_t taken;
+                const float w = pixel_step(q2, c1.w, T[k], qlim, amin, amax, tmin, taken);
+#pragma unroll
+                for (int c = 0; c < CC; ++c) img[k][c] = fmaf(w, col[c], img[k][c]);
+                nh += (uint32_t)__popcll(taken);
+                if (__builtin_amdgcn_ballot_w64(T[k] > 0.0f) == 0) alive &= ~(1u << k);
+            }
+            alive = (uint32_t)__builtin_amdgcn_readfirstlane((int)alive);
+            cnt += (uint32_t)__builtin_amdgcn_readfirstlane((int)nh);
+            if (alive == 0u) break;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (!inside[k]) continue;
+        int64_t row = V.pixel_offset + (int64_t)(iy0 + 4 * k) * V.width + ix;
+#pragma unroll
+        for (int c = 0; c < CC; ++c)
+            if (c_off + c < C) images[row * C + c_off + c] = img[k][c];
+    }
+    if (c_off == 0 && lane == 0 && cnt) atomicAdd(counter, (unsigned long long)cnt);
+}
+
+void launch_render(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
+                   const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
+                   const uint2* rec2, int bin, const float* gamma, int C, BlendParams bp,
+                   float* images, unsigned long long* counter, hipStream_t s) {
+    if (n_tiles == 0) return;
+    const uint32_t n_wt = wave_tiles(n_tiles, bin);
+    dim3 grid((n_wt + 3) / 4), block(256);
+#define GSC_RENDER(CCV, BINV)                                                                     \
+    hipLaunchKernelGGL((k_render<CCV, BINV>), grid, block, 0, s, views, n_views, n_wt, ranges,    \
+                       pair_vals, rec0, rec1, rec2, gamma, C, c_off, bp, images, counter)
+    for (int c_off = 0; c_off < C; c_off += 4) {
+        const bool three = C <= 3 && c_off == 0;
+        if (bin == 32) {
+            if (three) GSC_RENDER(3, 32); else GSC_RENDER(4, 32);
+        } else {
+            if (three) GSC_RENDER(3, 16); else GSC_RENDER(4, 16);
+        }
+    }
+#undef GSC_RENDER
+}
+
+}  // namespace gsc

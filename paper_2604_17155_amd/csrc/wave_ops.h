@@ -198,6 +198,28 @@ __device__ __forceinline__ bool pair_reaches(uint32_t pc, uint32_t quad, uint32_
     else return ((m >> quad) & 1u) != 0u;
 }
 
+// One front-to-back step of one pixel (eq. 2).  alpha = min(alpha_max, o 2^q2)
+// is used when the pixel lies inside the cut-off ellipse (q2 >= qlim) and
+// alpha >= alpha_min; a used alpha that would take T below t_min stops the
+// pixel (T = 0) and contributes nothing.  A live pixel has T >= t_min, so an
+// unused Gaussian (effective alpha 0) leaves T as it is through the same
+// test, and a stopped pixel (T = 0) stays at 0.  Returns the weight alpha T
+// (0 unless used); `taken` gets the wave's lanes that contributed, built
+// from one ballot per condition (each a compare the step makes anyway).
+__device__ __forceinline__ float pixel_step(float q2, float opac, float& T, float qlim, float amin,
+                                            float amax, float tmin, uint64_t& taken) {
+    const float al = __builtin_amdgcn_fmed3f(opac * __builtin_amdgcn_exp2f(q2), 0.0f, amax);
+    const bool inq = q2 >= qlim, ina = al >= amin;
+    const float ae = (inq & ina) ? al : 0.0f;
+    const float test = fmaf(-T, ae, T);
+    const bool keep = test >= tmin, live = T > 0.0f;
+    taken = __builtin_amdgcn_ballot_w64(inq) & __builtin_amdgcn_ballot_w64(ina) &
+            __builtin_amdgcn_ballot_w64(keep) & __builtin_amdgcn_ballot_w64(live);
+    const float w = keep ? T * ae : 0.0f;
+    T = keep ? test : 0.0f;
+    return w;
+}
+
 template <bool BF16>
 __device__ __forceinline__ float load_target(const void* __restrict__ t, int64_t idx) {
     if constexpr (BF16) {
