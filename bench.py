@@ -149,7 +149,8 @@ def run_single(args, gsc, sc, targets, label, dtype, traffic_key=None):
     import torch
     m, s, q, o = gsc.scene_tensors(sc)
     lam = list(sc.lam)
-    ctx = gsc.Context(flags=gsc.GSC_FLAG_PROFILE, bin_size=args.bin, accumulate_variant=args.variant)
+    ctx = gsc.Context(flags=gsc.GSC_FLAG_PROFILE, bin_size=args.bin, accumulate_variant=args.variant,
+                      schedule=args.schedule)
     for _ in range(args.warmup):
         ctx.colorize(m, s, q, o, sc.cams, targets, sc.sh_deg, lam)
     torch.cuda.synchronize()
@@ -171,6 +172,7 @@ def run_single(args, gsc, sc, targets, label, dtype, traffic_key=None):
     config = {"workload": label, "contributions_per_step": contrib,
               "scenes_per_sec": args.steps / elapsed, "tile_pairs_per_step": int(st.pairs),
               "bin_size": int(st.bin_size), "stage_ms_per_step": stages,
+              "tile_schedule": ["automatic", "grid", "longest first"][args.schedule],
               "accumulate_hbm": hbm_view(tbytes, stages["blend"])}
     return line(args, contrib * args.steps / elapsed, 1e3 * elapsed / args.steps, dtype, config,
                 roofline(sc.C, contrib, stages["blend"], launches, traffic_key))
@@ -182,7 +184,7 @@ def workload_relight(args, gsc):
     targets = gpu_targets(gsc, sc)
     label = (f"relighting: {sc.N} anisotropic Gaussians, {len(sc.cams)} hemisphere cameras "
              f"{sc.cams[0].width}x{sc.cams[0].height}, SH degree {sc.sh_deg}, C={sc.C}, FP32 targets")
-    default_size = not (args.n or args.views or args.res or args.bin or args.variant)
+    default_size = not (args.n or args.views or args.res or args.bin or args.variant or args.schedule)
     out = run_single(args, gsc, sc, targets, label, "f32", "relight" if default_size else None)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, host_threads(), "the full benchmark workload")
@@ -387,6 +389,8 @@ def main():
     ap.add_argument("--res", type=int, default=0, help="square resolution (0: the workload's)")
     ap.add_argument("--scenes", type=int, default=32, help="scenes of the batched workload")
     ap.add_argument("--bin", type=int, default=0, help="screen bin size 16 or 32 (0: automatic)")
+    ap.add_argument("--schedule", type=int, default=0,
+                    help="tile schedule of the accumulate launch (0: automatic, 1: grid, 2: longest first)")
     ap.add_argument("--variant", type=int, default=0,
                     help="accumulate variant code (0: automatic; see gsc_options.accumulate_variant)")
     args = ap.parse_args()

@@ -137,7 +137,17 @@ typedef struct {
                          BF16, C <= 7 for FP32 targets).  A code that does not
                          apply to the call falls back to the automatic choice.
                          A tuned plan uses its own. */
+    int32_t schedule;   /* order in which the blend + accumulate launch takes
+                           its 16x16 tiles: GSC_SCHEDULE_AUTO (0),
+                           GSC_SCHEDULE_GRID (1: one wave per tile, in tile
+                           index order) or GSC_SCHEDULE_LONGEST_FIRST (2:
+                           waves take tiles from a work queue, bins with the
+                           longest lists first).  The result does not depend
+                           on it beyond the order of floating-point atomic
+                           additions. */
 } gsc_options;
+
+enum { GSC_SCHEDULE_AUTO = 0, GSC_SCHEDULE_GRID = 1, GSC_SCHEDULE_LONGEST_FIRST = 2 };
 
 typedef struct {
     uint64_t contributions; /* accepted (Gaussian, view, pixel) triples of the last call */

@@ -103,7 +103,8 @@ struct gsc_ctx {
     uint64_t cache_items = 0;
     // device scratch
     DevBuf views, views_all, cov, keys, vals, keys_alt, vals_alt, counts, offsets, rec0, rec1, rec2,
-        sort_scratch, pkeys, pvals, pkeys_alt, pvals_alt, ranges, vs, gamma, bbar, misc;
+        sort_scratch, pkeys, pvals, pkeys_alt, pvals_alt, ranges, vs, gamma, bbar, misc, order, queues;
+    bool order_valid = false;  // `order` holds the tile order of the current binning
     // host staging
     ViewInfo* h_views = nullptr;  // staging of one batch's table
     size_t h_views_cap = 0;
@@ -120,7 +121,7 @@ struct gsc_ctx {
     ~gsc_ctx() {
         DevBuf* all[] = {&views, &views_all, &cov, &keys, &vals, &keys_alt, &vals_alt, &counts,
                          &offsets, &rec0, &rec1, &rec2, &sort_scratch, &pkeys, &pvals, &pkeys_alt,
-                         &pvals_alt, &ranges, &vs, &gamma, &bbar, &misc};
+                         &pvals_alt, &ranges, &vs, &gamma, &bbar, &misc, &order, &queues};
         for (DevBuf* b : all) b->release();
         if (h_views) (void)hipHostFree(h_views);
         if (h_all) (void)hipHostFree(h_all);
@@ -183,6 +184,8 @@ gsc_status validate_options(const gsc_options* o) {
     if (o->accumulate_variant != 0 && !accumulate_chunk_valid(o->accumulate_variant, GSC_F32) &&
         !accumulate_chunk_valid(o->accumulate_variant, GSC_BF16))
         return fail(GSC_ERR_INVALID_ARG, "accumulate_variant %d is not a variant code", o->accumulate_variant);
+    if (!(o->schedule >= GSC_SCHEDULE_AUTO && o->schedule <= GSC_SCHEDULE_LONGEST_FIRST))
+        return fail(GSC_ERR_INVALID_ARG, "schedule must be 0, 1 or 2");
     return GSC_OK;
 }
 
@@ -312,6 +315,7 @@ struct Binned {
 gsc_status bin_views(gsc_ctx* ctx, const std::vector<ViewInfo>& all, int v0, int nv,
                      const float* means, const float* opac, int64_t N, const BlendParams& bp,
                      hipStream_t s, Binned* out) {
+    ctx->order_valid = false;  // until this binning's order is built
     // tile numbering local to the batch
     if ((size_t)nv > ctx->h_views_cap) {
         if (ctx->h_views) GSC_HIP(hipHostFree(ctx->h_views));
@@ -417,6 +421,13 @@ gsc_status bin_views(gsc_ctx* ctx, const std::vector<ViewInfo>& all, int v0, int
         launch_tile_ranges(ctx->pkeys.as<uint32_t>(), (uint32_t)pairs, (uint32_t)tiles,
                            ctx->ranges.as<uint2>(), s);
         GSC_LAUNCHED("tile ranges");
+        ctx->order_valid = false;
+        if (ctx->opt.schedule != GSC_SCHEDULE_GRID) {
+            GSC_HIP(ctx->order.ensure(4 * tile_order_words((uint32_t)tiles)));
+            launch_tile_order(ctx->ranges.as<uint2>(), (uint32_t)tiles, ctx->order.as<uint32_t>(), s);
+            GSC_LAUNCHED("tile order");
+            ctx->order_valid = true;
+        }
     }
     return GSC_OK;
 }
@@ -758,6 +769,7 @@ gsc_status gsc_default_options(gsc_options* out) {
     out->flags = 0;
     out->bin_size = 0;
     out->accumulate_variant = 0;
+    out->schedule = GSC_SCHEDULE_AUTO;
     return GSC_OK;
 }
 
@@ -828,10 +840,17 @@ gsc_status gsc_colorize_ex(gsc_ctx* ctx, const float* means, const float* scales
         const int chunk = resolve_chunk(ctx->opt.accumulate_variant, C, tdtype);
         StageTimer t(ctx, s, GSC_STAGE_BLEND, (uint32_t)accumulate_launches(C, chunk));
         (void)v0;
+        uint32_t* queues = nullptr;
+        const uint32_t* order = nullptr;
+        if (ctx->opt.schedule != GSC_SCHEDULE_GRID && ctx->order_valid) {
+            GSC_HIP(ctx->queues.ensure(4 * (size_t)(kMaxC + 1)));
+            queues = ctx->queues.as<uint32_t>();
+            order = ctx->order.as<uint32_t>() + bn.n_tiles;
+        }
         launch_accumulate_chunked(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
                                   ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(),
                                   ctx->rec2.as<uint2>(), ctx->bin, targets, tdtype, C, per_view, bp,
-                                  ctx->vs.as<float>(), d_counter, x_cnt, chunk, s);
+                                  ctx->vs.as<float>(), d_counter, x_cnt, chunk, s, queues, order);
         GSC_LAUNCHED("accumulate");
         return GSC_OK;
     });

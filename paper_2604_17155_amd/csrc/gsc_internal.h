@@ -126,6 +126,11 @@ void launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total,
 // n_dev (optional, device): the live count, clamped to n (the capacity the
 // launches are sized for); no host synchronisation is needed.
 size_t radix_scratch_words(uint32_t n);
+// Bins by decreasing list length (ranges[b].y - ranges[b].x, saturated at
+// 65535; equal lengths in bin order) at work + n_bins.  work holds
+// tile_order_words(n_bins) words.
+size_t tile_order_words(uint32_t n_bins);
+const uint32_t* launch_tile_order(const uint2* ranges, uint32_t n_bins, uint32_t* work, hipStream_t s);
 void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                 uint32_t n, int bits, uint32_t* scratch, hipStream_t s,
                 const uint32_t* n_dev = nullptr);
@@ -161,7 +166,8 @@ void launch_accumulate(const ViewInfo* views, int n_views, uint32_t n_tiles, con
 // anything else picks accumulate_chunk(C, tdtype)).  queues (device, one word per
 // channel pass, zeroed here by a fill kernel): persistent launches of
 // kPersistentBlocks blocks that take tiles from a counter; nullptr: one
-// block per four tiles.
+// block per four tiles.  order (device, optional, with queues): the bins in
+// the order their tiles are taken (launch_tile_order).
 constexpr uint32_t kPersistentBlocks = 2048;  // 8 blocks of 4 waves per CU
 bool accumulate_chunk_valid(int chunk, int tdtype);
 void launch_accumulate_chunked(const ViewInfo* views, int n_views, uint32_t n_tiles,
@@ -169,7 +175,8 @@ void launch_accumulate_chunked(const ViewInfo* views, int n_views, uint32_t n_ti
                                const float4* rec1, const uint2* rec2, int bin, const void* targets, int tdtype, int C,
                                bool per_view, BlendParams bp, float* VS,
                                unsigned long long* counter, uint32_t* gcount, int chunk,
-                               hipStream_t s, uint32_t* queues = nullptr);
+                               hipStream_t s, uint32_t* queues = nullptr,
+                               const uint32_t* order = nullptr);
 
 // Colour of batch item i (view v, Gaussian g):
 // gamma[i][c] = sum_m coeffs[g][m][c] phi_m(dir_gv).

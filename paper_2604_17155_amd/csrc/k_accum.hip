@@ -252,7 +252,8 @@ __device__ __forceinline__ uint32_t accumulate_tile(
 // CC: channels handled by this launch (chunk [c_off, c_off + CC) of C).
 // queue == nullptr: one tile per wave (4 per block) over a grid covering all
 // tiles.  Otherwise persistent: a fixed grid whose waves take tiles from the
-// counter *queue (zero before the launch) until none are left.
+// counter *queue (zero before the launch) until none are left, in the order
+// `order` gives (nullptr: tile index order).
 template <int CC, bool BF16, int BIN>
 __global__ __launch_bounds__(256) void k_accumulate(
     const ViewInfo* __restrict__ views, int n_views, uint32_t n_tiles, const uint2* __restrict__ ranges,
@@ -261,7 +262,7 @@ __global__ __launch_bounds__(256) void k_accumulate(
     const uint2* __restrict__ rec2, const void* __restrict__ targets, int C, int c_off,
     int per_view, BlendParams bp, float* __restrict__ VS,
     unsigned long long* __restrict__ counter, uint32_t* __restrict__ gcount,
-    uint32_t* __restrict__ queue) {
+    uint32_t* __restrict__ queue, const uint32_t* __restrict__ order) {
     const uint32_t lane = threadIdx.x & 63;
     uint32_t cnt = 0;
     if (queue == nullptr) {
@@ -274,8 +275,9 @@ __global__ __launch_bounds__(256) void k_accumulate(
         for (;;) {
             uint32_t t = 0;
             if (lane == 0) t = atomicAdd(queue, 1u);
-            const uint32_t tile = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
-            if (tile >= n_tiles) break;  // uniform: every wave ends here
+            const uint32_t tq = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
+            if (tq >= n_tiles) break;  // uniform: every wave ends here
+            const uint32_t tile = queued_tile<BIN>(tq, order);
             cnt += accumulate_tile<CC, BF16, BIN>(tile, lane, views, n_views, ranges, pair_vals,
                                                   rec0, rec1, rec2, targets, C, c_off,
                                                   per_view, bp, VS, gcount);
@@ -293,7 +295,7 @@ static void launch_acc_k(const ViewInfo* views, int n_views, uint32_t n_wt, cons
                          const float4* rec1,
                          const uint2* rec2, const void* targets, int C, bool per_view,
                          BlendParams bp, float* VS, unsigned long long* counter, uint32_t* gcount,
-                         uint32_t* queues, hipStream_t s) {
+                         uint32_t* queues, const uint32_t* order, hipStream_t s) {
     const uint32_t full = (n_wt + 3) / 4;
     dim3 grid(queues ? std::min(full, kPersistentBlocks) : full), block(256);
     int pass = 0;
@@ -302,7 +304,7 @@ static void launch_acc_k(const ViewInfo* views, int n_views, uint32_t n_wt, cons
         uint32_t* q = queues ? queues + pass : nullptr;
         hipLaunchKernelGGL((k_accumulate<CC, BF16, BIN>), grid, block, 0, s, views, n_views, n_wt,
                            ranges, pair_vals, rec0, rec1, rec2, targets, C, c_off,
-                           (int)per_view, bp, VS, counter, gcount, q);
+                           (int)per_view, bp, VS, counter, gcount, q, q ? order : nullptr);
     }
 }
 
@@ -312,12 +314,12 @@ static void launch_acc_cc(const ViewInfo* views, int n_views, uint32_t n_bins, c
                           const float4* rec1,
                           const uint2* rec2, int bin, const void* targets, int tdtype, int C,
                           bool per_view, BlendParams bp, float* VS, unsigned long long* counter,
-                          uint32_t* gcount, uint32_t* queues, hipStream_t s) {
+                          uint32_t* gcount, uint32_t* queues, const uint32_t* order, hipStream_t s) {
     const uint32_t n_wt = wave_tiles(n_bins, bin);
     const bool bf = tdtype == GSC_BF16;
 #define GSC_ACCK(BFV, BINV)                                                                        \
     launch_acc_k<CC, BFV, BINV>(views, n_views, n_wt, ranges, pair_vals, rec0, rec1, rec2, targets, \
-                                C, per_view, bp, VS, counter, gcount, queues, s)
+                                C, per_view, bp, VS, counter, gcount, queues, order, s)
     if (bin == 32) {
         if (bf) GSC_ACCK(true, 32); else GSC_ACCK(false, 32);
     } else {
@@ -607,7 +609,7 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void k_accumulate_mfma(
     const float4* __restrict__ rec1, const uint2* __restrict__ rec2,
     const void* __restrict__ targets, int C, int c_off, int per_view, BlendParams bp,
     float* __restrict__ VS, unsigned long long* __restrict__ counter, uint32_t* __restrict__ gcount,
-    uint32_t* __restrict__ queue) {
+    uint32_t* __restrict__ queue, const uint32_t* __restrict__ order) {
     __shared__ MfmaLds<mfma_rows<NBLK>()> lds[kMfmaWaves];
     const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint32_t cnt = 0;
@@ -621,8 +623,9 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void k_accumulate_mfma(
         for (;;) {
             uint32_t t = 0;
             if (lane == 0) t = atomicAdd(queue, 1u);
-            const uint32_t tile = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
-            if (tile >= n_tiles) break;  // uniform: every wave ends here
+            const uint32_t tq = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
+            if (tq >= n_tiles) break;  // uniform: every wave ends here
+            const uint32_t tile = queued_tile<BIN>(tq, order);
             cnt += accumulate_tile_mfma<NBLK, BIN, YM>(tile, lane, lds[w], views, n_views, ranges,
                                                    pair_vals, rec0, rec1, rec2, targets, C, c_off,
                                                    per_view, bp, VS, gcount);
@@ -636,7 +639,7 @@ static void launch_acc_mfma(const ViewInfo* views, int n_views, uint32_t n_wt, c
                             const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
                             const uint2* rec2, const void* targets, int C, bool per_view,
                             BlendParams bp, float* VS, unsigned long long* counter, uint32_t* gcount,
-                            uint32_t* queues, hipStream_t s) {
+                            uint32_t* queues, const uint32_t* order, hipStream_t s) {
     const uint32_t full = (n_wt + kMfmaWaves - 1) / kMfmaWaves;
     dim3 grid(queues ? std::min(full, 2 * kPersistentBlocks) : full), block(64 * kMfmaWaves);
     int pass = 0;
@@ -645,7 +648,7 @@ static void launch_acc_mfma(const ViewInfo* views, int n_views, uint32_t n_wt, c
         uint32_t* q = queues ? queues + pass : nullptr;
         hipLaunchKernelGGL((k_accumulate_mfma<NBLK, BIN, YM>), grid, block, 0, s, views, n_views, n_wt,
                            ranges, pair_vals, rec0, rec1, rec2, targets, C, c_off,
-                           (int)per_view, bp, VS, counter, gcount, q);
+                           (int)per_view, bp, VS, counter, gcount, q, q ? order : nullptr);
     }
 }
 
@@ -654,14 +657,15 @@ static void launch_acc_mfma_bin(const ViewInfo* views, int n_views, uint32_t n_b
                                 const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
                                 const uint2* rec2, int bin, const void* targets, int C, bool per_view,
                                 BlendParams bp, float* VS, unsigned long long* counter,
-                                uint32_t* gcount, uint32_t* queues, hipStream_t s) {
+                                uint32_t* gcount, uint32_t* queues, const uint32_t* order,
+                                hipStream_t s) {
     const uint32_t n_wt = wave_tiles(n_bins, bin);
     if (bin == 32)
         launch_acc_mfma<NBLK, 32, YM>(views, n_views, n_wt, ranges, pair_vals, rec0, rec1, rec2, targets, C,
-                                  per_view, bp, VS, counter, gcount, queues, s);
+                                  per_view, bp, VS, counter, gcount, queues, order, s);
     else
         launch_acc_mfma<NBLK, 16, YM>(views, n_views, n_wt, ranges, pair_vals, rec0, rec1, rec2, targets, C,
-                                  per_view, bp, VS, counter, gcount, queues, s);
+                                  per_view, bp, VS, counter, gcount, queues, order, s);
 }
 
 int accumulate_chunk(int C, int tdtype) {
@@ -703,14 +707,15 @@ void launch_accumulate_chunked(const ViewInfo* views, int n_views, uint32_t n_ti
                                const float4* rec1, const uint2* rec2, int bin,
                                const void* targets, int tdtype, int C, bool per_view,
                                BlendParams bp, float* VS, unsigned long long* counter,
-                               uint32_t* gcount, int chunk, hipStream_t s, uint32_t* queues) {
+                               uint32_t* gcount, int chunk, hipStream_t s, uint32_t* queues,
+                               const uint32_t* order) {
     if (n_tiles == 0) return;
     chunk = resolve_chunk(chunk, C, tdtype);
     if (queues) launch_fill_u32(queues, 0u, (uint64_t)accumulate_launches(C, chunk), s);
     if (chunk & kChunkMfma) {
 #define GSC_ACCM(NB, YMV)                                                                          \
     launch_acc_mfma_bin<NB, YMV>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, rec2, bin, \
-                                 targets, C, per_view, bp, VS, counter, gcount, queues, s)
+                                 targets, C, per_view, bp, VS, counter, gcount, queues, order, s)
         switch (chunk_channels(chunk)) {
             case 1:
                 if (tdtype == GSC_BF16) GSC_ACCM(1, 1); else GSC_ACCM(1, 2);
@@ -724,7 +729,7 @@ void launch_accumulate_chunked(const ViewInfo* views, int n_views, uint32_t n_ti
     }
 #define GSC_ACC(CCV)                                                                                \
     launch_acc_cc<CCV>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, rec2, bin, targets, \
-                       tdtype, C, per_view, bp, VS, counter, gcount, queues, s)
+                       tdtype, C, per_view, bp, VS, counter, gcount, queues, order, s)
     switch (chunk) {
         case 1: GSC_ACC(1); break;
         case 2: GSC_ACC(2); break;
@@ -745,10 +750,10 @@ void launch_accumulate_weights(const ViewInfo* views, int n_views, uint32_t n_ti
     const uint32_t n_wt = wave_tiles(n_tiles, bin);
     if (bin == 32)
         launch_acc_k<0, false, 32>(views, n_views, n_wt, ranges, pair_vals, rec0, rec1, rec2, nullptr,
-                                   0, per_view, bp, V, counter, nullptr, nullptr, s);
+                                   0, per_view, bp, V, counter, nullptr, nullptr, nullptr, s);
     else
         launch_acc_k<0, false, 16>(views, n_views, n_wt, ranges, pair_vals, rec0, rec1, rec2, nullptr,
-                                   0, per_view, bp, V, counter, nullptr, nullptr, s);
+                                   0, per_view, bp, V, counter, nullptr, nullptr, nullptr, s);
 }
 
 }  // namespace gsc

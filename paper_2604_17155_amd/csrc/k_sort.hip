@@ -287,4 +287,26 @@ void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* va
     }
 }
 
+__global__ void k_tile_work_keys(const uint2* __restrict__ ranges, uint32_t n_bins,
+                                 uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_bins) return;
+    const uint2 r = ranges[b];
+    keys[b] = 0xFFFFu - min(r.y - r.x, 0xFFFFu);
+    vals[b] = b;
+}
+
+size_t tile_order_words(uint32_t n_bins) {
+    return 4 * (size_t)n_bins + radix_scratch_words(n_bins);
+}
+
+const uint32_t* launch_tile_order(const uint2* ranges, uint32_t n_bins, uint32_t* work, hipStream_t s) {
+    uint32_t *keys = work, *vals = work + n_bins, *keys_alt = work + 2 * (size_t)n_bins,
+             *vals_alt = work + 3 * (size_t)n_bins;
+    if (n_bins == 0) return vals;
+    hipLaunchKernelGGL(k_tile_work_keys, dim3((n_bins + 255) / 256), dim3(256), 0, s, ranges, n_bins, keys, vals);
+    radix_sort(keys, vals, keys_alt, vals_alt, n_bins, 16, work + 4 * (size_t)n_bins, s);
+    return vals;
+}
+
 }  // namespace gsc

@@ -169,6 +169,16 @@ __device__ __forceinline__ TileGeom tile_geom(uint32_t vt, const ViewInfo* __res
     return t;
 }
 
+// The wave tile taken t-th from a persistent launch's queue.  With `order`
+// (bins by decreasing list length) the longest lists start first, so that
+// no long tile is left to run alone at the end of the launch.
+template <int BIN>
+__device__ __forceinline__ uint32_t queued_tile(uint32_t t, const uint32_t* __restrict__ order) {
+    if (order == nullptr) return t;
+    if constexpr (BIN == 32) return order[t >> 2] * 4u + (t & 3u);
+    else return order[t];
+}
+
 // Bands (rows y0 + 4k .. y0 + 4k + 3 of the tile) a list entry can reach:
 // the pair's band mask for 16-pixel bins; for 32-pixel bins, none unless the
 // pair marks this tile, else the bands met by the footprint's rows

@@ -106,7 +106,7 @@ def test_bad_options_rejected(lib):
     for over in [dict(alpha_max=1.5), dict(t_min=-1.0), dict(znear=0.0), dict(sigma_cut=0.0),
                  dict(bin_size=8), dict(bin_size=64), dict(accumulate_variant=5),
                  dict(accumulate_variant=128 | 48), dict(accumulate_variant=128 | 8),
-                 dict(accumulate_variant=256 | 16)]:
+                 dict(accumulate_variant=256 | 16), dict(schedule=3), dict(schedule=-1)]:
         o = gsc.default_options()
         for k, v in over.items():
             setattr(o, k, v)
@@ -127,6 +127,7 @@ def test_accumulate_variants_accepted(lib):
 def test_default_options_values(lib):
     o = gsc.default_options()
     assert o.accumulate_variant == 0 and o.bin_size == 0
+    assert o.schedule == gsc.GSC_SCHEDULE_AUTO
     assert o.alpha_min == np.float32(1 / 255)
     assert o.alpha_max == np.float32(0.99)
     assert o.t_min == np.float32(1e-4)

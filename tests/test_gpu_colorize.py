@@ -124,6 +124,36 @@ def test_accumulate_variants_bf16(gsc_mod, ragged_features, variant, bin_size):
     print(msg, flush=True)
 
 
+@pytest.mark.parametrize("bin_size", [16, 32])
+@pytest.mark.parametrize("schedule", [1, 2])
+def test_tile_schedules(gsc_mod, schedule, bin_size):
+    """Tiles in index order (one wave each) and longest lists first from a
+    work queue: C = 5 over ragged 200x120 views, one and several channel
+    launches."""
+    rng = np.random.Generator(np.random.PCG64(11))
+    sc = syn.make_relight(n=6000, n_cams=8, res=64, sh_deg=2,
+                          lam=rng.uniform(1e-4, 1e-2, 9).astype(np.float32))
+    sc.cams = syn.hemisphere_cams(8, 3.0, 200, 120)
+    sc.C = 5
+    sc.gt = [np.concatenate([sc.gt[0], sc.gt[0][:, :, :2] * 0.5], axis=2)]
+    y = oracle.make_targets(sc)
+    ref = oracle.colorize(sc, y)
+    for variant in (0, 2):
+        ctx = gsc_mod.Context(bin_size=bin_size, schedule=schedule, accumulate_variant=variant)
+        c, st, stats = run_gpu(ctx, sc, y)
+        print(parity.check_colorize(c, st, ref, count_gpu=stats.contributions,
+                                    label=f"schedule {schedule} bin {bin_size} variant {variant}"), flush=True)
+
+
+@pytest.mark.parametrize("schedule", [1, 2])
+def test_tile_schedules_matrix_core(gsc_mod, ragged_features, schedule):
+    sc, y, ref = ragged_features
+    ctx = gsc_mod.Context(bin_size=32, schedule=schedule, accumulate_variant=128 | 16)
+    c, st, stats = run_gpu(ctx, sc, y)
+    print(parity.check_colorize(c, st, ref, count_gpu=stats.contributions,
+                                label=f"features C40 bf16 matrix core schedule {schedule}"), flush=True)
+
+
 PACKED = 128 | 1  # all channels and a ones column in one matrix-core block
 
 
