@@ -323,7 +323,7 @@ def workload_diff(args, gsc):
     y2 = gpu_targets(gsc, sc, 1)
     m, s, q, o = gsc.scene_tensors(sc)
     lam = list(sc.lam)
-    ctx = gsc.Context(bin_size=args.bin)
+    ctx = gsc.Context(bin_size=args.bin, schedule=args.schedule)
     o_p = o.clone().requires_grad_(True)
     y_p = y1.clone().requires_grad_(True)
 

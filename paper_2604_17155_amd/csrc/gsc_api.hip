@@ -103,7 +103,8 @@ struct gsc_ctx {
     uint64_t cache_items = 0;
     // device scratch
     DevBuf views, views_all, cov, keys, vals, keys_alt, vals_alt, counts, offsets, rec0, rec1, rec2,
-        sort_scratch, pkeys, pvals, pkeys_alt, pvals_alt, ranges, vs, gamma, bbar, misc, order, queues;
+        sort_scratch, pkeys, pvals, pkeys_alt, pvals_alt, ranges, vs, gamma, bbar, misc, order, queues,
+        coef_t;
     bool order_valid = false;  // `order` holds the tile order of the current binning
     // host staging
     ViewInfo* h_views = nullptr;  // staging of one batch's table
@@ -121,7 +122,7 @@ struct gsc_ctx {
     ~gsc_ctx() {
         DevBuf* all[] = {&views, &views_all, &cov, &keys, &vals, &keys_alt, &vals_alt, &counts,
                          &offsets, &rec0, &rec1, &rec2, &sort_scratch, &pkeys, &pvals, &pkeys_alt,
-                         &pvals_alt, &ranges, &vs, &gamma, &bbar, &misc, &order, &queues};
+                         &pvals_alt, &ranges, &vs, &gamma, &bbar, &misc, &order, &queues, &coef_t};
         for (DevBuf* b : all) b->release();
         if (h_views) (void)hipHostFree(h_views);
         if (h_all) (void)hipHostFree(h_all);
@@ -308,6 +309,13 @@ struct Binned {
     uint32_t n_pairs = 0;
     uint64_t n_items = 0;
 };
+
+// The tile order of the current binning for launches that take it, or
+// nullptr (tile index order) under GSC_SCHEDULE_GRID.
+const uint32_t* tile_order(const gsc_ctx* ctx, uint32_t n_tiles) {
+    if (ctx->opt.schedule == GSC_SCHEDULE_GRID || !ctx->order_valid) return nullptr;
+    return ctx->order.as<uint32_t>() + n_tiles;
+}
 
 // Project, depth-sort, emit and tile-sort the views [v0, v0+nv) of `all`.
 // The batch's ViewInfo table is uploaded to ctx->views (tile_base local to
@@ -587,11 +595,11 @@ struct gsc_plan {
     float tune_ms[8] = {};
     int tune_variant[8] = {};
     DevBuf d_views, cov, keys, vals, keys_alt, vals_alt, counts, offsets, rec0, rec1,
-        rec2, sort_scratch, pkeys, pvals, pkeys_alt, pvals_alt, ranges, vs, misc, queues;
+        rec2, sort_scratch, pkeys, pvals, pkeys_alt, pvals_alt, ranges, vs, misc, queues, order;
     ~gsc_plan() {
         DevBuf* all[] = {&d_views, &cov, &keys, &vals, &keys_alt, &vals_alt, &counts,
                          &offsets, &rec0, &rec1, &rec2, &sort_scratch, &pkeys, &pvals, &pkeys_alt,
-                         &pvals_alt, &ranges, &vs, &misc, &queues};
+                         &pvals_alt, &ranges, &vs, &misc, &queues, &order};
         for (DevBuf* b : all) b->release();
     }
 };
@@ -653,7 +661,8 @@ gsc_status plan_accumulate(gsc_plan* P, const gsc_plan::Batch& b, const void* ta
                               P->rec0.as<float4>(), P->rec1.as<float4>(), P->rec2.as<uint2>(),
                               P->bin, targets, tdtype, P->C,
                               P->per_view, P->bp, P->vs.as<float>(), d_counter, nullptr, chunk, s,
-                              persistent ? P->queues.as<uint32_t>() : nullptr);
+                              persistent ? P->queues.as<uint32_t>() : nullptr,
+                              P->order.as<uint32_t>() + b.n_tiles);
     GSC_LAUNCHED("accumulate");
     return GSC_OK;
 }
@@ -705,6 +714,7 @@ gsc_status plan_bin_batch(gsc_plan* P, const gsc_plan::Batch& b, hipStream_t s) 
         launch_fill_u32(P->ranges.as<uint32_t>(), 0u, (uint64_t)2 * b.n_tiles, s);
         launch_tile_ranges(P->pkeys.as<uint32_t>(), b.pair_cap, b.n_tiles, P->ranges.as<uint2>(), s,
                            d_live);
+        launch_tile_order(P->ranges.as<uint2>(), b.n_tiles, P->order.as<uint32_t>(), s);
         GSC_LAUNCHED("tile sort");
     }
     return GSC_OK;
@@ -842,10 +852,9 @@ gsc_status gsc_colorize_ex(gsc_ctx* ctx, const float* means, const float* scales
         (void)v0;
         uint32_t* queues = nullptr;
         const uint32_t* order = nullptr;
-        if (ctx->opt.schedule != GSC_SCHEDULE_GRID && ctx->order_valid) {
+        if ((order = tile_order(ctx, bn.n_tiles)) != nullptr) {
             GSC_HIP(ctx->queues.ensure(4 * (size_t)(kMaxC + 1)));
             queues = ctx->queues.as<uint32_t>();
-            order = ctx->order.as<uint32_t>() + bn.n_tiles;
         }
         launch_accumulate_chunked(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
                                   ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(),
@@ -905,17 +914,21 @@ gsc_status gsc_render(gsc_ctx* ctx, const float* means, const float* scales, con
     std::vector<ViewInfo> all(n_cams);
     for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j], j, N, ctx->bin);
     unsigned long long* d_counter = reinterpret_cast<unsigned long long*>(ctx->misc.p);
+    const int kc = (sh_deg + 1) * (sh_deg + 1) * C;
+    GSC_HIP(ctx->coef_t.ensure(4 * (size_t)std::max<int64_t>(N, 1) * (size_t)kc));
+    launch_transpose(coeffs, N, kc, ctx->coef_t.as<float>(), s);
+    GSC_LAUNCHED("transpose");
     st = for_view_batches_k(ctx, all, n_cams, means, opacities, N, bp, s, &key, reuse,
                           [&](int v0, int nv, const Binned& bn) -> gsc_status {
         (void)v0;
         StageTimer t(ctx, s, GSC_STAGE_BLEND, 1 + (uint32_t)((C + 3) / 4));
         GSC_HIP(ctx->gamma.ensure(4 * (size_t)nv * (size_t)std::max<int64_t>(N, 1) * (size_t)C));
-        launch_view_colors(ctx->views.as<ViewInfo>(), nv, (uint32_t)bn.n_items, means, coeffs, C,
-                           sh_deg, ctx->gamma.as<float>(), s);
+        launch_view_colors(ctx->views.as<ViewInfo>(), nv, (uint32_t)bn.n_items, means,
+                           ctx->coef_t.as<float>(), N, C, sh_deg, ctx->gamma.as<float>(), s);
         GSC_LAUNCHED("view colors");
         launch_render(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
                       ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(), ctx->rec2.as<uint2>(), ctx->bin,
-                      ctx->gamma.as<float>(), C, bp, images, d_counter, s);
+                      ctx->gamma.as<float>(), C, bp, images, d_counter, s, tile_order(ctx, bn.n_tiles));
         GSC_LAUNCHED("render");
         return GSC_OK;
     });
@@ -968,7 +981,7 @@ gsc_status gsc_colorize_backward(gsc_ctx* ctx, const float* means, const float* 
         launch_accumulate_weights(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
                                   ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(),
                                   ctx->rec1.as<float4>(), ctx->rec2.as<uint2>(), ctx->bin, per_view, bp, ctx->vs.as<float>(),
-                                  d_counter, s);
+                                  d_counter, s, tile_order(ctx, bn.n_tiles));
         GSC_LAUNCHED("accumulate weights");
         last = bn;
         return GSC_OK;
@@ -988,18 +1001,25 @@ gsc_status gsc_colorize_backward(gsc_ctx* ctx, const float* means, const float* 
                              N, C, sh_deg, lam, grad_coeffs, coeffs, d_bbar, d_rho, d_wsum, s);
         GSC_LAUNCHED("adjoint solve");
     }
+    // coefficients and Bbar transposed for the adjoint colours
+    GSC_HIP(ctx->coef_t.ensure(4 * 2 * nbc));
+    float* d_coef_t = ctx->coef_t.as<float>();
+    float* d_bbar_t = d_coef_t + nbc;
+    launch_transpose(coeffs, N, nb * C, d_coef_t, s);
+    launch_transpose(d_bbar, N, nb * C, d_bbar_t, s);
+    GSC_LAUNCHED("transpose");
     // 3. per view batch: adjoint colours, then the two-pass blend adjoint
     auto body = [&](int v0, int nv, const Binned& bn) -> gsc_status {
         (void)v0;
         GSC_HIP(ctx->gamma.ensure(4 * (size_t)nv * (size_t)N * (size_t)(C + 1)));
         StageTimer t(ctx, s, GSC_STAGE_BLEND_ADJOINT);
-        launch_view_adjoint(ctx->views.as<ViewInfo>(), nv, (uint32_t)bn.n_items, means, coeffs, d_bbar,
-                            d_rho, C, sh_deg, false, ctx->gamma.as<float>(), s);
+        launch_view_adjoint(ctx->views.as<ViewInfo>(), nv, (uint32_t)bn.n_items, means, d_coef_t,
+                            d_bbar_t, N, d_rho, C, sh_deg, false, ctx->gamma.as<float>(), s);
         GSC_LAUNCHED("view adjoint");
         launch_blend_adjoint(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
                              ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(), ctx->rec2.as<uint2>(), ctx->bin,
                              targets, tdtype, C, ctx->gamma.as<float>(), bp, grad_targets,
-                             grad_opacities, s);
+                             grad_opacities, s, tile_order(ctx, bn.n_tiles));
         GSC_LAUNCHED("blend adjoint");
         return GSC_OK;
     };
@@ -1048,6 +1068,11 @@ gsc_status gsc_render_backward(gsc_ctx* ctx, const float* means, const float* sc
         launch_fill_u32(ctx->vs.as<uint32_t>(), 0u, vs_words, s);
     }
     unsigned long long* d_counter = reinterpret_cast<unsigned long long*>(ctx->misc.p);
+    if (grad_opacities) {
+        GSC_HIP(ctx->coef_t.ensure(4 * (size_t)N * (size_t)(nb * C)));
+        launch_transpose(coeffs, N, nb * C, ctx->coef_t.as<float>(), s);
+        GSC_LAUNCHED("transpose");
+    }
     st = for_view_batches_k(ctx, all, n_cams, means, opacities, N, bp, s, &key, reuse,
                           [&](int v0, int nv, const Binned& bn) -> gsc_status {
         if (grad_coeffs) {
@@ -1058,19 +1083,21 @@ gsc_status gsc_render_backward(gsc_ctx* ctx, const float* means, const float* sc
             launch_accumulate(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
                               ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(), ctx->rec2.as<uint2>(), ctx->bin,
                               grad_images, GSC_F32, C, per_view, bp, ctx->vs.as<float>(),
-                              d_counter, nullptr, s);
+                              d_counter, nullptr, s, tile_order(ctx, bn.n_tiles));
             GSC_LAUNCHED("accumulate");
         }
         if (grad_opacities) {
             GSC_HIP(ctx->gamma.ensure(4 * (size_t)nv * (size_t)N * (size_t)(C + 1)));
             StageTimer t(ctx, s, GSC_STAGE_BLEND_ADJOINT);
-            launch_view_adjoint(ctx->views.as<ViewInfo>(), nv, (uint32_t)bn.n_items, means, coeffs,
-                                nullptr, nullptr, C, sh_deg, true, ctx->gamma.as<float>(), s);
+            launch_view_adjoint(ctx->views.as<ViewInfo>(), nv, (uint32_t)bn.n_items, means,
+                                ctx->coef_t.as<float>(), nullptr, N, nullptr, C, sh_deg, true,
+                                ctx->gamma.as<float>(), s);
             GSC_LAUNCHED("view colours");
             launch_blend_adjoint(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
                                  ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(),
                                  ctx->rec1.as<float4>(), ctx->rec2.as<uint2>(), ctx->bin, grad_images, GSC_F32, C,
-                                 ctx->gamma.as<float>(), bp, nullptr, grad_opacities, s);
+                                 ctx->gamma.as<float>(), bp, nullptr, grad_opacities, s,
+                                 tile_order(ctx, bn.n_tiles));
             GSC_LAUNCHED("blend adjoint");
         }
         return GSC_OK;
@@ -1227,6 +1254,7 @@ gsc_status gsc_plan_create(gsc_ctx* ctx, const gsc_scene* scenes, int32_t n_scen
     GSC_HIP(P->pkeys_alt.ensure(4 * mp + 4));
     GSC_HIP(P->pvals_alt.ensure(4 * mp + 4));
     GSC_HIP(P->ranges.ensure(sizeof(uint2) * ((size_t)P->max_tiles + 1)));
+    GSC_HIP(P->order.ensure(4 * tile_order_words(P->max_tiles)));
     const size_t scr = std::max({radix_scratch_words(P->max_items), scan_scratch_words(P->max_items),
                                  radix_scratch_words(P->max_pairs)});
     GSC_HIP(P->sort_scratch.ensure(4 * scr + 256));

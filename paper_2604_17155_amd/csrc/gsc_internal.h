@@ -159,7 +159,8 @@ int resolve_chunk(int requested, int C, int tdtype);
 void launch_accumulate(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
                        const uint32_t* pair_vals, const float4* rec0, const float4* rec1, const uint2* rec2, int bin,
                        const void* targets, int tdtype, int C, bool per_view, BlendParams bp,
-                       float* VS, unsigned long long* counter, uint32_t* gcount, hipStream_t s);
+                       float* VS, unsigned long long* counter, uint32_t* gcount, hipStream_t s,
+                       const uint32_t* order = nullptr);
 
 // As launch_accumulate with accumulate variant `chunk` (1, 2, 3, 4, 8 or 16
 // channels per launch, or kChunkMfma | 16, 32 or 64 for BF16 targets;
@@ -178,15 +179,22 @@ void launch_accumulate_chunked(const ViewInfo* views, int n_views, uint32_t n_ti
                                hipStream_t s, uint32_t* queues = nullptr,
                                const uint32_t* order = nullptr);
 
+// out[k][r] = in[r][k] (rows x K row-major in, K x rows row-major out).
+void launch_transpose(const float* in, int64_t rows, int K, float* out, hipStream_t s);
+
 // Colour of batch item i (view v, Gaussian g):
-// gamma[i][c] = sum_m coeffs[g][m][c] phi_m(dir_gv).
+// gamma[i][c] = sum_m coeffs[g][m][c] phi_m(dir_gv), from the coefficients
+// transposed: coeffs_t[m * C + c][g], rows of ldn floats (consecutive items
+// read consecutive floats).
 void launch_view_colors(const ViewInfo* views, int n_views, uint32_t n_items, const float* means,
-                        const float* coeffs, int C, int sh_deg, float* gamma, hipStream_t s);
+                        const float* coeffs_t, int64_t ldn, int C, int sh_deg, float* gamma,
+                        hipStream_t s);
 
 void launch_render(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
                    const uint32_t* pair_vals, const float4* rec0, const float4* rec1, const uint2* rec2, int bin,
                    const float* gamma, int C, BlendParams bp, float* images,
-                   unsigned long long* counter, hipStream_t s);
+                   unsigned long long* counter, hipStream_t s,
+                       const uint32_t* order = nullptr);
 
 // Fold the per-view sums into the regularised normal equations and solve.
 // per_view: VS holds [n_views][N][C+1] (else [N][C+1] summed over views).
@@ -201,7 +209,8 @@ void launch_fold_solve(const ViewInfo* views, int n_views, const float* means, c
 void launch_accumulate_weights(const ViewInfo* views, int n_views, uint32_t n_tiles,
                                const uint2* ranges, const uint32_t* pair_vals, const float4* rec0,
                                const float4* rec1, const uint2* rec2, int bin, bool per_view, BlendParams bp, float* V,
-                               unsigned long long* counter, hipStream_t s);
+                               unsigned long long* counter, hipStream_t s,
+                       const uint32_t* order = nullptr);
 
 // Adjoint solve: bbar = (A_g + w_g Lambda)^{-1} grad_coeffs and
 // rho_g = sum lambda_m bbar[m][c] coeffs[m][c].  V holds per-view
@@ -214,17 +223,19 @@ void launch_adjoint_solve(const ViewInfo* views, int n_views, const float* means
 
 // Adjoint colours of batch item i: beta [i][C+1] = (beta_gj, delta_gj).
 // render: beta = c^T phi, delta = 0.  Otherwise beta = bbar^T phi and
-// delta = beta^T (c^T phi) + rho_g.
+// delta = beta^T (c^T phi) + rho_g.  coeffs_t and bbar_t are transposed as
+// for launch_view_colors (rows of ldn floats).
 void launch_view_adjoint(const ViewInfo* views, int n_views, uint32_t n_items, const float* means,
-                         const float* coeffs, const float* bbar, const float* rho, int C, int sh_deg,
-                         bool render, float* beta, hipStream_t s);
+                         const float* coeffs_t, const float* bbar_t, int64_t ldn, const float* rho,
+                         int C, int sh_deg, bool render, float* beta, hipStream_t s);
 
 // Blend adjoint over the binned tiles: grad_y[row][c] = sum_g w beta (every
 // pixel of every view written, if grad_y) and grad_o[g] += dL/do (atomics, if grad_o).
 void launch_blend_adjoint(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
                           const uint32_t* pair_vals, const float4* rec0, const float4* rec1, const uint2* rec2, int bin,
                           const void* ypix, int ydtype, int C, const float* beta, BlendParams bp,
-                          float* grad_y, float* grad_o, hipStream_t s);
+                          float* grad_y, float* grad_o, hipStream_t s,
+                       const uint32_t* order = nullptr);
 
 // grad_coeffs[g][m][c] = sum_j phi_gj[m] S_gj[c] from per-view sums [n_views][N][C+1].
 void launch_fold_rhs(const ViewInfo* views, int n_views, const float* means, const float* VS,

@@ -252,8 +252,8 @@ __device__ __forceinline__ uint32_t accumulate_tile(
 // CC: channels handled by this launch (chunk [c_off, c_off + CC) of C).
 // queue == nullptr: one tile per wave (4 per block) over a grid covering all
 // tiles.  Otherwise persistent: a fixed grid whose waves take tiles from the
-// counter *queue (zero before the launch) until none are left, in the order
-// `order` gives (nullptr: tile index order).
+// counter *queue (zero before the launch) until none are left.  Either way
+// tiles come in the order `order` gives (nullptr: tile index order).
 template <int CC, bool BF16, int BIN>
 __global__ __launch_bounds__(256) void k_accumulate(
     const ViewInfo* __restrict__ views, int n_views, uint32_t n_tiles, const uint2* __restrict__ ranges,
@@ -266,8 +266,9 @@ __global__ __launch_bounds__(256) void k_accumulate(
     const uint32_t lane = threadIdx.x & 63;
     uint32_t cnt = 0;
     if (queue == nullptr) {
-        const uint32_t tile = blockIdx.x * 4 + (threadIdx.x >> 6);
-        if (tile >= n_tiles) return;  // whole wave
+        const uint32_t wi = blockIdx.x * 4 + (threadIdx.x >> 6);
+        if (wi >= n_tiles) return;  // whole wave
+        const uint32_t tile = queued_tile<BIN>(wi, order);  // blocks start in index order
         cnt = accumulate_tile<CC, BF16, BIN>(tile, lane, views, n_views, ranges, pair_vals,
                                              rec0, rec1, rec2, targets, C, c_off, per_view, bp, VS,
                                              gcount);
@@ -304,7 +305,7 @@ static void launch_acc_k(const ViewInfo* views, int n_views, uint32_t n_wt, cons
         uint32_t* q = queues ? queues + pass : nullptr;
         hipLaunchKernelGGL((k_accumulate<CC, BF16, BIN>), grid, block, 0, s, views, n_views, n_wt,
                            ranges, pair_vals, rec0, rec1, rec2, targets, C, c_off,
-                           (int)per_view, bp, VS, counter, gcount, q, q ? order : nullptr);
+                           (int)per_view, bp, VS, counter, gcount, q, order);
     }
 }
 
@@ -614,8 +615,9 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void k_accumulate_mfma(
     const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint32_t cnt = 0;
     if (queue == nullptr) {
-        const uint32_t tile = blockIdx.x * kMfmaWaves + w;
-        if (tile >= n_tiles) return;  // whole wave
+        const uint32_t wi = blockIdx.x * kMfmaWaves + w;
+        if (wi >= n_tiles) return;  // whole wave
+        const uint32_t tile = queued_tile<BIN>(wi, order);  // blocks start in index order
         cnt = accumulate_tile_mfma<NBLK, BIN, YM>(tile, lane, lds[w], views, n_views, ranges, pair_vals,
                                               rec0, rec1, rec2, targets, C, c_off, per_view, bp, VS,
                                               gcount);
@@ -648,7 +650,7 @@ static void launch_acc_mfma(const ViewInfo* views, int n_views, uint32_t n_wt, c
         uint32_t* q = queues ? queues + pass : nullptr;
         hipLaunchKernelGGL((k_accumulate_mfma<NBLK, BIN, YM>), grid, block, 0, s, views, n_views, n_wt,
                            ranges, pair_vals, rec0, rec1, rec2, targets, C, c_off,
-                           (int)per_view, bp, VS, counter, gcount, q, q ? order : nullptr);
+                           (int)per_view, bp, VS, counter, gcount, q, order);
     }
 }
 
@@ -696,9 +698,9 @@ void launch_accumulate(const ViewInfo* views, int n_views, uint32_t n_tiles, con
                        const float4* rec1,
                        const uint2* rec2, int bin, const void* targets, int tdtype, int C,
                        bool per_view, BlendParams bp, float* VS, unsigned long long* counter,
-                       uint32_t* gcount, hipStream_t s) {
+                       uint32_t* gcount, hipStream_t s, const uint32_t* order) {
     launch_accumulate_chunked(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, rec2, bin,
-                              targets, tdtype, C, per_view, bp, VS, counter, gcount, 0, s);
+                              targets, tdtype, C, per_view, bp, VS, counter, gcount, 0, s, nullptr, order);
 }
 
 void launch_accumulate_chunked(const ViewInfo* views, int n_views, uint32_t n_tiles,
@@ -745,15 +747,16 @@ void launch_accumulate_weights(const ViewInfo* views, int n_views, uint32_t n_ti
                                const uint2* ranges, const uint32_t* pair_vals,
                                const float4* rec0,
                                const float4* rec1, const uint2* rec2, int bin, bool per_view,
-                               BlendParams bp, float* V, unsigned long long* counter, hipStream_t s) {
+                               BlendParams bp, float* V, unsigned long long* counter, hipStream_t s,
+                               const uint32_t* order) {
     if (n_tiles == 0) return;
     const uint32_t n_wt = wave_tiles(n_tiles, bin);
     if (bin == 32)
         launch_acc_k<0, false, 32>(views, n_views, n_wt, ranges, pair_vals, rec0, rec1, rec2, nullptr,
-                                   0, per_view, bp, V, counter, nullptr, nullptr, nullptr, s);
+                                   0, per_view, bp, V, counter, nullptr, nullptr, order, s);
     else
         launch_acc_k<0, false, 16>(views, n_views, n_wt, ranges, pair_vals, rec0, rec1, rec2, nullptr,
-                                   0, per_view, bp, V, counter, nullptr, nullptr, nullptr, s);
+                                   0, per_view, bp, V, counter, nullptr, nullptr, order, s);
 }
 
 }  // namespace gsc

@@ -31,12 +31,14 @@
 namespace gsc {
 
 // beta[i*(C+1) + c] = beta_gj[c] and [.. + C] = delta_gj for batch item i
-// (view v, Gaussian g), items in their own order (coalesced coefficient reads).
+// (view v, Gaussian g), items in their own order; the coefficient arrays are
+// transposed ([m * C + c][g], rows of ldn floats) so that consecutive threads
+// read consecutive floats.
 template <int L, bool RENDER>
 __global__ void k_view_adjoint(const ViewInfo* __restrict__ views, int n_views, uint32_t n_items,
-                               const float* __restrict__ means, const float* __restrict__ coeffs,
-                               const float* __restrict__ bbar, const float* __restrict__ rho, int C,
-                               float* __restrict__ beta) {
+                               const float* __restrict__ means, const float* __restrict__ coeffs_t,
+                               const float* __restrict__ bbar_t, int64_t ldn,
+                               const float* __restrict__ rho, int C, float* __restrict__ beta) {
     constexpr int NB = (L + 1) * (L + 1);
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_items) return;
@@ -48,25 +50,26 @@ __global__ void k_view_adjoint(const ViewInfo* __restrict__ views, int n_views, 
     const double inv = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
     float phi[NB];
     sh_eval<float, L>((float)(dx * inv), (float)(dy * inv), (float)(dz * inv), phi);
-    const float* cg = coeffs + g * NB * C;
+    const float* cg = coeffs_t + g;
     float* out = beta + (int64_t)i * (C + 1);
     if constexpr (RENDER) {
         for (int c = 0; c < C; ++c) {
             float a = 0.0f;
 #pragma unroll
-            for (int m = 0; m < NB; ++m) a = fmaf(cg[m * C + c], phi[m], a);
+            for (int m = 0; m < NB; ++m) a = fmaf(cg[(int64_t)(m * C + c) * ldn], phi[m], a);
             out[c] = a;
         }
         out[C] = 0.0f;
     } else {
-        const float* bg = bbar + g * NB * C;
+        const float* bg = bbar_t + g;
         double delta = (double)rho[g];
         for (int c = 0; c < C; ++c) {
             float a = 0.0f, b = 0.0f;
 #pragma unroll
             for (int m = 0; m < NB; ++m) {
-                a = fmaf(cg[m * C + c], phi[m], a);
-                b = fmaf(bg[m * C + c], phi[m], b);
+                const int64_t k = (int64_t)(m * C + c) * ldn;
+                a = fmaf(cg[k], phi[m], a);
+                b = fmaf(bg[k], phi[m], b);
             }
             out[c] = b;
             delta += (double)a * (double)b;
@@ -76,18 +79,18 @@ __global__ void k_view_adjoint(const ViewInfo* __restrict__ views, int n_views, 
 }
 
 void launch_view_adjoint(const ViewInfo* views, int n_views, uint32_t n_items, const float* means,
-                         const float* coeffs, const float* bbar, const float* rho, int C, int sh_deg,
-                         bool render, float* beta, hipStream_t s) {
+                         const float* coeffs_t, const float* bbar_t, int64_t ldn, const float* rho,
+                         int C, int sh_deg, bool render, float* beta, hipStream_t s) {
     if (n_items == 0 || n_views <= 0) return;
     dim3 grid((n_items + 255) / 256), block(256);
 #define GSC_VA(LL)                                                                                   \
     do {                                                                                             \
         if (render)                                                                                  \
             hipLaunchKernelGGL((k_view_adjoint<LL, true>), grid, block, 0, s, views, n_views,        \
-                               n_items, means, coeffs, bbar, rho, C, beta);                          \
+                               n_items, means, coeffs_t, bbar_t, ldn, rho, C, beta);                 \
         else                                                                                         \
             hipLaunchKernelGGL((k_view_adjoint<LL, false>), grid, block, 0, s, views, n_views,       \
-                               n_items, means, coeffs, bbar, rho, C, beta);                          \
+                               n_items, means, coeffs_t, bbar_t, ldn, rho, C, beta);                 \
     } while (0)
     switch (sh_deg) {
         case 0: GSC_VA(0); break;
@@ -137,10 +140,11 @@ __global__ __launch_bounds__(256) void k_blend_adjoint(
     const float4* __restrict__ rec0, const float4* __restrict__ rec1,
     const uint2* __restrict__ rec2, const void* __restrict__ ypix, int C, int c_off,
     const float* __restrict__ beta, BlendParams bp, float* __restrict__ grad_y,
-    float* __restrict__ grad_o) {
+    float* __restrict__ grad_o, const uint32_t* __restrict__ order) {
     const uint32_t lane = threadIdx.x & 63;
-    const uint32_t wt = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (wt >= n_wt) return;  // whole wave
+    const uint32_t wi = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wi >= n_wt) return;  // whole wave
+    const uint32_t wt = queued_tile<BIN>(wi, order);  // blocks start in index order
     const TileGeom tg = tile_geom<BIN>(wt, views, n_views);
     const ViewInfo& V = views[tg.vloc];
     const int ix = tg.x0 + (int)(lane & 15);
@@ -315,12 +319,12 @@ static void launch_badj_cc(const ViewInfo* views, int n_views, uint32_t n_bins, 
                            const uint32_t* pair_vals, const float4* rec0,
                            const float4* rec1, const uint2* rec2, int bin, const void* ypix,
                            int ydtype, int C, const float* beta, BlendParams bp, float* grad_y,
-                           float* grad_o, hipStream_t s) {
+                           float* grad_o, const uint32_t* order, hipStream_t s) {
     const uint32_t n_wt = bin == 32 ? 4u * n_bins : n_bins;
     dim3 grid((n_wt + 3) / 4), block(256);
 #define GSC_BADJ(BFV, BINV)                                                                         \
     hipLaunchKernelGGL((k_blend_adjoint<CC, BFV, GY, BINV>), grid, block, 0, s, views, n_views, n_wt, \
-                       ranges, pair_vals, rec0, rec1, rec2, ypix, C, c_off, beta, bp, grad_y, grad_o)
+                       ranges, pair_vals, rec0, rec1, rec2, ypix, C, c_off, beta, bp, grad_y, grad_o, order)
     for (int c_off = 0; c_off < C; c_off += CC) {
         const bool bf = ydtype == GSC_BF16;
         if (bin == 32) {
@@ -338,10 +342,10 @@ static void launch_badj(const ViewInfo* views, int n_views, uint32_t n_tiles, co
                         const float4* rec1,
                         const uint2* rec2, int bin, const void* ypix, int ydtype, int C,
                         const float* beta, BlendParams bp, float* grad_y, float* grad_o,
-                        hipStream_t s) {
+                        const uint32_t* order, hipStream_t s) {
 #define GSC_BA(CCV)                                                                                \
     launch_badj_cc<CCV, GY>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, rec2, bin, ypix, \
-                            ydtype, C, beta, bp, grad_y, grad_o, s)
+                            ydtype, C, beta, bp, grad_y, grad_o, order, s)
     switch (accumulate_chunk(C, GSC_F32)) {  // vector-lane channel chunks
         case 1: GSC_BA(1); break;
         case 2: GSC_BA(2); break;
@@ -358,14 +362,14 @@ void launch_blend_adjoint(const ViewInfo* views, int n_views, uint32_t n_tiles, 
                           const float4* rec1,
                           const uint2* rec2, int bin, const void* ypix, int ydtype, int C,
                           const float* beta, BlendParams bp, float* grad_y, float* grad_o,
-                          hipStream_t s) {
+                          hipStream_t s, const uint32_t* order) {
     if (n_tiles == 0 || (!grad_y && !grad_o)) return;
     if (grad_y)
         launch_badj<true>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, rec2, bin, ypix,
-                          ydtype, C, beta, bp, grad_y, grad_o, s);
+                          ydtype, C, beta, bp, grad_y, grad_o, order, s);
     else
         launch_badj<false>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, rec2, bin, ypix,
-                           ydtype, C, beta, bp, grad_y, grad_o, s);
+                           ydtype, C, beta, bp, grad_y, grad_o, order, s);
 }
 
 // grad_coeffs[g][m][c] = sum_j phi_gj[m] S_gj[c] from the per-view sums

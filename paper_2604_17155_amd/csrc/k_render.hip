@@ -9,13 +9,40 @@ namespace gsc {
 
 static inline uint32_t wave_tiles(uint32_t n_bins, int bin) { return bin == 32 ? 4u * n_bins : n_bins; }
 
+// 64 x 64 tiles through LDS: rows read and columns written as contiguous
+// runs (the padded row keeps the column reads free of bank conflicts).
+__global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ in, int64_t rows, int K,
+                                                   float* __restrict__ out) {
+    __shared__ float t[64][65];
+    const int64_t r0 = (int64_t)blockIdx.x * 64;
+    const int k0 = (int)blockIdx.y * 64;
+    const int tx = (int)(threadIdx.x & 63), ty = (int)(threadIdx.x >> 6);
+    for (int j = ty; j < 64; j += 4) {
+        const int64_t r = r0 + j;
+        const int k = k0 + tx;
+        t[j][tx] = (r < rows && k < K) ? in[r * K + k] : 0.0f;
+    }
+    __syncthreads();
+    for (int j = ty; j < 64; j += 4) {
+        const int k = k0 + j;
+        const int64_t r = r0 + tx;
+        if (k < K && r < rows) out[(int64_t)k * rows + r] = t[tx][j];
+    }
+}
+
+void launch_transpose(const float* in, int64_t rows, int K, float* out, hipStream_t s) {
+    if (rows <= 0 || K <= 0) return;
+    dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((K + 63) / 64)), block(256);
+    hipLaunchKernelGGL(k_transpose, grid, block, 0, s, in, rows, K, out);
+}
+
 // gamma[i*C + c] = sum_m coeffs[g][m][c] * phi_m(dir_gv) for batch item i
-// (view v, Gaussian g): items in their own order, so that consecutive threads
-// read consecutive Gaussians' coefficients.
+// (view v, Gaussian g): items in their own order, reading the transposed
+// coefficients, so that consecutive threads read consecutive floats.
 template <int L>
 __global__ void k_view_colors(const ViewInfo* __restrict__ views, int n_views, uint32_t n_items,
-                              const float* __restrict__ means, const float* __restrict__ coeffs,
-                              int C, float* __restrict__ gamma) {
+                              const float* __restrict__ means, const float* __restrict__ coeffs_t,
+                              int64_t ldn, int C, float* __restrict__ gamma) {
     constexpr int NB = (L + 1) * (L + 1);
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_items) return;
@@ -27,26 +54,31 @@ __global__ void k_view_colors(const ViewInfo* __restrict__ views, int n_views, u
     double inv = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
     float phi[NB];
     sh_eval<float, L>((float)(dx * inv), (float)(dy * inv), (float)(dz * inv), phi);
-    const float* cg = coeffs + g * NB * C;
+    const float* cg = coeffs_t + g;
     float* out = gamma + (int64_t)i * C;
     for (int c = 0; c < C; ++c) {
         float a = 0.0f;
 #pragma unroll
-        for (int m = 0; m < NB; ++m) a += cg[m * C + c] * phi[m];
+        for (int m = 0; m < NB; ++m) a += cg[(int64_t)(m * C + c) * ldn] * phi[m];
         out[c] = a;
     }
 }
 
 void launch_view_colors(const ViewInfo* views, int n_views, uint32_t n_items, const float* means,
-                        const float* coeffs, int C, int sh_deg, float* gamma, hipStream_t s) {
+                        const float* coeffs_t, int64_t ldn, int C, int sh_deg, float* gamma,
+                        hipStream_t s) {
     if (n_items == 0 || n_views <= 0) return;
     dim3 grid((n_items + 255) / 256), block(256);
+#define GSC_VC(LL)                                                                                   \
+    hipLaunchKernelGGL(k_view_colors<LL>, grid, block, 0, s, views, n_views, n_items, means, coeffs_t, \
+                       ldn, C, gamma)
     switch (sh_deg) {
-        case 0: hipLaunchKernelGGL(k_view_colors<0>, grid, block, 0, s, views, n_views, n_items, means, coeffs, C, gamma); break;
-        case 1: hipLaunchKernelGGL(k_view_colors<1>, grid, block, 0, s, views, n_views, n_items, means, coeffs, C, gamma); break;
-        case 2: hipLaunchKernelGGL(k_view_colors<2>, grid, block, 0, s, views, n_views, n_items, means, coeffs, C, gamma); break;
-        default: hipLaunchKernelGGL(k_view_colors<3>, grid, block, 0, s, views, n_views, n_items, means, coeffs, C, gamma); break;
+        case 0: GSC_VC(0); break;
+        case 1: GSC_VC(1); break;
+        case 2: GSC_VC(2); break;
+        default: GSC_VC(3); break;
     }
+#undef GSC_VC
 }
 
 // images[row][c] = sum_g w_gp * gamma_gv[c]; every pixel of every tile is
@@ -57,10 +89,11 @@ __global__ __launch_bounds__(256) void k_render(
     const uint32_t* __restrict__ pair_vals, const float4* __restrict__ rec0,
     const float4* __restrict__ rec1, const uint2* __restrict__ rec2,
     const float* __restrict__ gamma, int C, int c_off, BlendParams bp, float* __restrict__ images,
-    unsigned long long* __restrict__ counter) {
+    unsigned long long* __restrict__ counter, const uint32_t* __restrict__ order) {
     const uint32_t lane = threadIdx.x & 63;
-    const uint32_t wt = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (wt >= n_wt) return;
+    const uint32_t wi = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wi >= n_wt) return;
+    const uint32_t wt = queued_tile<BIN>(wi, order);  // blocks start in index order
     const TileGeom tg = tile_geom<BIN>(wt, views, n_views);
     const ViewInfo& V = views[tg.vloc];
     const int ix = tg.x0 + (int)(lane & 15);
@@ -146,13 +179,13 @@ __global__ __launch_bounds__(256) void k_render(
 void launch_render(const ViewInfo* views, int n_views, uint32_t n_tiles, const uint2* ranges,
                    const uint32_t* pair_vals, const float4* rec0, const float4* rec1,
                    const uint2* rec2, int bin, const float* gamma, int C, BlendParams bp,
-                   float* images, unsigned long long* counter, hipStream_t s) {
+                   float* images, unsigned long long* counter, hipStream_t s, const uint32_t* order) {
     if (n_tiles == 0) return;
     const uint32_t n_wt = wave_tiles(n_tiles, bin);
     dim3 grid((n_wt + 3) / 4), block(256);
 #define GSC_RENDER(CCV, BINV)                                                                     \
     hipLaunchKernelGGL((k_render<CCV, BINV>), grid, block, 0, s, views, n_views, n_wt, ranges,    \
-                       pair_vals, rec0, rec1, rec2, gamma, C, c_off, bp, images, counter)
+                       pair_vals, rec0, rec1, rec2, gamma, C, c_off, bp, images, counter, order)
     for (int c_off = 0; c_off < C; c_off += 4) {
         const bool three = C <= 3 && c_off == 0;
         if (bin == 32) {

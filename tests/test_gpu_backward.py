@@ -304,3 +304,25 @@ def test_colorize_backward_bins_of_32_pixels(gsc_mod):
     y = oracle.make_targets(sc)
     et, eo, _, _ = colorize_backward_case(ctx, sc, y, smooth_opts(), "colorize adjoint L3 C3 smooth bin32")
     assert et <= TOL_GRAD and eo <= TOL_GRAD
+
+
+@pytest.mark.parametrize("schedule", [1, 2])
+def test_backward_tile_schedules(gsc_mod, schedule):
+    """Colorize and render adjoints with tiles in index order (grid) and
+    longest lists first."""
+    import torch
+    ctx = gsc_mod.Context(schedule=schedule, **SMOOTH)
+    sc = syn.make_relight(n=6000, n_cams=8, res=128)
+    y = oracle.make_targets(sc)
+    et, eo, _, _ = colorize_backward_case(ctx, sc, y, smooth_opts(), f"colorize adjoint schedule {schedule}")
+    assert et <= TOL_GRAD and eo <= TOL_GRAD
+    c32 = sc.gt[0].astype(np.float32)
+    gi = np.random.default_rng(3).standard_normal((sc.n_pixels, 3)).astype(np.float32)
+    gc_ref, go_ref = oracle.render_backward(sc, c32.astype(np.float64), gi.astype(np.float64),
+                                            opts=smooth_opts())
+    m, s, q, o = gsc_mod.scene_tensors(sc)
+    gc, go = ctx.render_backward(m, s, q, o, sc.cams, _dev(c32), _dev(gi))
+    torch.cuda.synchronize()
+    ec, eo2 = rel_l2(gc.cpu().numpy(), gc_ref), rel_l2(go.cpu().numpy(), go_ref)
+    print(f"render adjoint schedule {schedule}: grad_coeffs {ec:.2e}; grad_opacities {eo2:.2e}", flush=True)
+    assert ec <= TOL_GRAD and eo2 <= TOL_GRAD
