@@ -105,23 +105,28 @@ __device__ __forceinline__ uint32_t accumulate_tile(
         uint2 Q2;
         if constexpr (kDouble) gather(pvn, b + 64, Q0, Q1, Q2);
         const uint32_t pvnn = load_pv(b + 128);
+        // the chunk's entries that can reach a live band, one bit per lane in
+        // list order: the walk visits only these
+        uint64_t todo = __builtin_amdgcn_ballot_w64(
+            lane < nb && (entry_bands<BIN>(pv, tg.quad, R2.x, tg.y0) & alive) != 0u);
         if constexpr (CC >= 1 && CC <= 3) {
             // Entries in groups of four: each entry's tile sums (V, S) stay in
             // a fixed register slot, and one wave reduction of the group's 16
             // values (lane e*4+v, bit-reversed) feeds one atomic per value.
             // Tile liveness is refreshed once per group: entries after the
             // last live pixel stopped meet T = 0 everywhere and add nothing.
-            for (uint32_t j0 = 0; j0 < nb && alive != 0u; j0 += 4) {
+            while (todo != 0u && alive != 0u) {
                 float pend[16];
                 int64_t gslot[4];
                 bool has[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const uint32_t j = min(j0 + (uint32_t)u, 63u);
+                    const bool any = todo != 0u;
+                    const uint32_t j = any ? (uint32_t)__builtin_ctzll(todo) : 0u;
+                    todo &= todo - 1u;
                     const uint32_t pc = bcast_u(pv, j);
                     const uint2 e2 = make_uint2(bcast_u(R2.x, j), bcast_u(R2.y, j));
-                    const uint32_t bands =
-                        j0 + (uint32_t)u < nb ? entry_bands<BIN>(pc, tg.quad, e2.x, tg.y0) & alive : 0u;
+                    const uint32_t bands = any ? entry_bands<BIN>(pc, tg.quad, e2.x, tg.y0) & alive : 0u;
                     float sv = 0.0f, s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
                     uint32_t nh = 0;
                     if (bands != 0u) {
@@ -171,7 +176,9 @@ __device__ __forceinline__ uint32_t accumulate_tile(
                 }
             }
         } else {
-            for (uint32_t j = 0; j < nb; ++j) {
+            while (todo != 0u) {
+                const uint32_t j = (uint32_t)__builtin_ctzll(todo);
+                todo &= todo - 1u;
                 const uint32_t pc = bcast_u(pv, j);
                 const uint2 e2 = make_uint2(bcast_u(R2.x, j), bcast_u(R2.y, j));
                 const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2.x, tg.y0) & alive;
