@@ -141,8 +141,9 @@ typedef struct {
                            its 16x16 tiles: GSC_SCHEDULE_AUTO (0),
                            GSC_SCHEDULE_GRID (1: one wave per tile, in tile
                            index order) or GSC_SCHEDULE_LONGEST_FIRST (2:
-                           waves take tiles from a work queue, bins with the
-                           longest lists first).  The result does not depend
+                           waves take tiles from a work queue, bins in
+                           decreasing octave of list length, tile index
+                           order within an octave).  The result does not depend
                            on it beyond the order of floating-point atomic
                            additions. */
 } gsc_options;

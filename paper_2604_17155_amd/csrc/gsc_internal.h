@@ -126,9 +126,9 @@ void launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total,
 // n_dev (optional, device): the live count, clamped to n (the capacity the
 // launches are sized for); no host synchronisation is needed.
 size_t radix_scratch_words(uint32_t n);
-// Bins by decreasing list length (ranges[b].y - ranges[b].x, saturated at
-// 65535; equal lengths in bin order) at work + n_bins.  work holds
-// tile_order_words(n_bins) words.
+// Bins by decreasing octave of their list length (floor log2 of
+// ranges[b].y - ranges[b].x + 1; bin order within an octave) at
+// work + n_bins.  work holds tile_order_words(n_bins) words.
 size_t tile_order_words(uint32_t n_bins);
 const uint32_t* launch_tile_order(const uint2* ranges, uint32_t n_bins, uint32_t* work, hipStream_t s);
 void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,

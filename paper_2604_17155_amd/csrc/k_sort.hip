@@ -292,7 +292,9 @@ __global__ void k_tile_work_keys(const uint2* __restrict__ ranges, uint32_t n_bi
     const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= n_bins) return;
     const uint2 r = ranges[b];
-    keys[b] = 0xFFFFu - min(r.y - r.x, 0xFFFFu);
+    // the octave of the list length, longest first; index order within one
+    // octave keeps neighbouring tiles of a view together (shared records in L2)
+    keys[b] = 31u - (31u - __clz(r.y - r.x + 1u));
     vals[b] = b;
 }
 
@@ -305,7 +307,7 @@ const uint32_t* launch_tile_order(const uint2* ranges, uint32_t n_bins, uint32_t
              *vals_alt = work + 3 * (size_t)n_bins;
     if (n_bins == 0) return vals;
     hipLaunchKernelGGL(k_tile_work_keys, dim3((n_bins + 255) / 256), dim3(256), 0, s, ranges, n_bins, keys, vals);
-    radix_sort(keys, vals, keys_alt, vals_alt, n_bins, 16, work + 4 * (size_t)n_bins, s);
+    radix_sort(keys, vals, keys_alt, vals_alt, n_bins, 5, work + 4 * (size_t)n_bins, s);
     return vals;
 }
 

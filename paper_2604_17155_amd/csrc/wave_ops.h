@@ -170,8 +170,8 @@ __device__ __forceinline__ TileGeom tile_geom(uint32_t vt, const ViewInfo* __res
 }
 
 // The wave tile taken t-th from a persistent launch's queue.  With `order`
-// (bins by decreasing list length) the longest lists start first, so that
-// no long tile is left to run alone at the end of the launch.
+// (bins by decreasing octave of list length) the longest lists start first,
+// so that no long tile is left to run alone at the end of the launch.
 template <int BIN>
 __device__ __forceinline__ uint32_t queued_tile(uint32_t t, const uint32_t* __restrict__ order) {
     if (order == nullptr) return t;
