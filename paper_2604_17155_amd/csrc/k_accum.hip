@@ -581,18 +581,13 @@ __device__ __forceinline__ uint32_t accumulate_tile_mfma(
             if (!((bands >> k) & 1u)) continue;  // uniform
             const float dy = (pyk[k] - c0.y) - c0.w;
             const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
-            const float al = __builtin_amdgcn_fmed3f(c1.w * __builtin_amdgcn_exp2f(q2), 0.0f, amax);
-            const float test = fmaf(-T[k], al, T[k]);
-            const bool cand = q2 >= qlim && al >= amin && T[k] > 0.0f;
-            const bool keep = test >= tmin;
-            const bool take = cand && keep;
-            const float w = take ? al * T[k] : 0.0f;
-            T[k] = cand ? (keep ? test : 0.0f) : T[k];
+            uint64_t taken;
+            const float w = pixel_step(q2, c1.w, T[k], qlim, amin, amax, tmin, taken);
             const __bf16 hi = (__bf16)w;
             const __bf16 lo = (__bf16)(w - (float)hi);
             wrow_h[lane + 64 * k] = hi;
             wrow_l[lane + 64 * k] = lo;
-            nh += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(take));
+            nh += (uint32_t)__popcll(taken);
             if (__builtin_amdgcn_ballot_w64(T[k] > 0.0f) == 0) alive &= ~(1u << k);
         }
         alive = (uint32_t)__builtin_amdgcn_readfirstlane((int)alive);
