@@ -174,68 +174,93 @@ __global__ __launch_bounds__(256) void k_blend_adjoint(
     rg.x = (uint32_t)__builtin_amdgcn_readfirstlane((int)rg.x);
     rg.y = (uint32_t)__builtin_amdgcn_readfirstlane((int)rg.y);
 
-    // ---- pass 1: S = sum_k u_k w_k per pixel, and dL/dy -------------------
+    // Both passes walk the list the same way, so that they take the same
+    // decisions.  A chunk of 64 entries is gathered at once, one entry per
+    // lane (records and the entry's adjoint colours), and broadcast entry by
+    // entry; only entries reaching a band with a live pixel are visited.  A
+    // pixel that stopped adds nothing in either pass, so the skipped entries
+    // and bands change no sum.
+    uint32_t alive0 = 0;  // bands holding a pixel of the image
+#pragma unroll
+    for (int k = 0; k < 4; ++k) alive0 |= (__builtin_amdgcn_ballot_w64(inside[k]) != 0 ? 1u : 0u) << k;
+    alive0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)alive0);
     float T[4];
     bool live[4];
+    auto walk = [&](auto&& body) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            T[k] = 1.0f;
+            live[k] = inside[k];
+        }
+        uint32_t alive = alive0;
+        for (uint32_t b = rg.x; b < rg.y && alive != 0u; b += 64) {
+            const uint32_t nb = min(64u, rg.y - b);
+            const bool own = lane < nb;
+            const uint32_t pv = own ? pair_vals[b + lane] : 0u;
+            const uint32_t it = pv & kItemMask;
+            const float4 R0 = own ? rec0[it] : make_float4(0.f, 0.f, 0.f, 0.f);
+            const float4 R1 = own ? rec1[it] : make_float4(0.f, 0.f, 0.f, 0.f);
+            const uint2 R2 = own ? rec2[it] : make_uint2(0u, 0u);
+            const float* bl = beta + (int64_t)R2.y * stride;  // the record names the item
+            float RB[CC];
+#pragma unroll
+            for (int c = 0; c < CC; ++c) RB[c] = (own && c_off + c < C) ? bl[c_off + c] : 0.0f;
+            const float RD = (own && first_chunk) ? bl[C] : 0.0f;
+            uint64_t todo = __builtin_amdgcn_ballot_w64(
+                own && (entry_bands<BIN>(pv, tg.quad, R2.x, tg.y0) & alive) != 0u);
+            while (todo != 0u) {
+                const uint32_t j = (uint32_t)__builtin_ctzll(todo);
+                todo &= todo - 1u;
+                const uint32_t pc = bcast_u(pv, j);
+                const uint2 e2 = make_uint2(bcast_u(R2.x, j), bcast_u(R2.y, j));
+                const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2.x, tg.y0) & alive;
+                if (bands == 0u) continue;
+                const float4 c0 = make_float4(bcast(R0.x, j), bcast(R0.y, j), bcast(R0.z, j), bcast(R0.w, j));
+                const float4 c1 = make_float4(bcast(R1.x, j), bcast(R1.y, j), bcast(R1.z, j), bcast(R1.w, j));
+                float bet[CC];
+#pragma unroll
+                for (int c = 0; c < CC; ++c) bet[c] = bcast(RB[c], j);
+                const float del = bcast(RD, j);
+                body(bands, c0, c1, e2, bet, del);
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (((bands >> k) & 1u) && __builtin_amdgcn_ballot_w64(live[k]) == 0) alive &= ~(1u << k);
+                alive = (uint32_t)__builtin_amdgcn_readfirstlane((int)alive);
+                if (alive == 0u) break;
+            }
+        }
+    };
+
+    // ---- pass 1: S = sum_k u_k w_k per pixel, and dL/dy -------------------
     double S[4];
     float gy[4][GY ? CC : 1];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        T[k] = 1.0f;
-        live[k] = inside[k];
         S[k] = 0.0;
 #pragma unroll
         for (int c = 0; c < (GY ? CC : 1); ++c) gy[k][c] = 0.0f;
     }
-    bool wave_live = __ballot(inside[0] || inside[1] || inside[2] || inside[3]) != 0;
-    for (uint32_t b = rg.x; b < rg.y && wave_live; b += 64) {
-        const uint32_t nb = min(64u, rg.y - b);
-        const uint32_t pv = lane < nb ? pair_vals[b + lane] : 0u;
-        uint32_t pn = bcast_u(pv, 0);
-        float4 n0 = rec0[pn & kItemMask], n1 = rec1[pn & kItemMask];
-        uint2 n2 = rec2[pn & kItemMask];
-        for (uint32_t j = 0; j < nb; ++j) {
-            const uint32_t pc = pn;
-            const float4 c0 = n0, c1 = n1;
-            const uint2 e2 = n2;
-            if (j + 1 < nb) {
-                pn = bcast_u(pv, j + 1);
-                n0 = rec0[pn & kItemMask];
-                n1 = rec1[pn & kItemMask];
-                n2 = rec2[pn & kItemMask];
-            }
-            const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2.x, tg.y0);
-            if (bands == 0u) continue;
-            const uint32_t item = e2.y;  // the record names the item
-            const float* bp_ = beta + (int64_t)item * stride;
-            float bet[CC];
+    walk([&](uint32_t bands, const float4& c0, const float4& c1, const uint2& e2, const float (&bet)[CC],
+             float del) {
+        const float dx = (px - c0.x) - c0.z;
+        const float a0 = c1.x * dx * dx;
+        const float b0 = c1.y * dx;
 #pragma unroll
-            for (int c = 0; c < CC; ++c) bet[c] = (c_off + c < C) ? bp_[c_off + c] : 0.0f;
-            const float del = first_chunk ? bp_[C] : 0.0f;
-            const float dx = (px - c0.x) - c0.z;
-            const float a0 = c1.x * dx * dx;
-            const float b0 = c1.y * dx;
+        for (int k = 0; k < 4; ++k) {
+            if (!((bands >> k) & 1u)) continue;  // uniform
+            const float dy = (pyk[k] - c0.y) - c0.w;
+            const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
+            const Step st = blend_step(T[k], live[k], q2, c1.w, qlim, bp);
+            float u = -del;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (!((bands >> k) & 1u)) continue;
-                const float dy = (pyk[k] - c0.y) - c0.w;
-                const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
-                const Step st = blend_step(T[k], live[k], q2, c1.w, qlim, bp);
-                float u = -del;
+            for (int c = 0; c < CC; ++c) u = fmaf(bet[c], yv[k][c], u);
+            S[k] += (double)(st.w * u);
+            if constexpr (GY) {
 #pragma unroll
-                for (int c = 0; c < CC; ++c) u = fmaf(bet[c], yv[k][c], u);
-                S[k] += (double)(st.w * u);
-                if constexpr (GY) {
-#pragma unroll
-                    for (int c = 0; c < CC; ++c) gy[k][c] = fmaf(st.w, bet[c], gy[k][c]);
-                }
-            }
-            if (__ballot(live[0] || live[1] || live[2] || live[3]) == 0) {
-                wave_live = false;
-                break;
+                for (int c = 0; c < CC; ++c) gy[k][c] = fmaf(st.w, bet[c], gy[k][c]);
             }
         }
-    }
+    });
     if constexpr (GY) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -251,67 +276,35 @@ __global__ __launch_bounds__(256) void k_blend_adjoint(
     // ---- pass 2: dL/dalpha per entry, reduced to dL/do per Gaussian -------
     double P[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        T[k] = 1.0f;
-        live[k] = inside[k];
-        P[k] = 0.0;
-    }
-    wave_live = __ballot(inside[0] || inside[1] || inside[2] || inside[3]) != 0;
-    for (uint32_t b = rg.x; b < rg.y && wave_live; b += 64) {
-        const uint32_t nb = min(64u, rg.y - b);
-        const uint32_t pv = lane < nb ? pair_vals[b + lane] : 0u;
-        uint32_t pn = bcast_u(pv, 0);
-        float4 n0 = rec0[pn & kItemMask], n1 = rec1[pn & kItemMask];
-        uint2 n2 = rec2[pn & kItemMask];
-        for (uint32_t j = 0; j < nb; ++j) {
-            const uint32_t pc = pn;
-            const float4 c0 = n0, c1 = n1;
-            const uint2 e2 = n2;
-            if (j + 1 < nb) {
-                pn = bcast_u(pv, j + 1);
-                n0 = rec0[pn & kItemMask];
-                n1 = rec1[pn & kItemMask];
-                n2 = rec2[pn & kItemMask];
-            }
-            const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2.x, tg.y0);
-            if (bands == 0u) continue;
-            const uint32_t item = e2.y;  // the record names the item
-            const float* bp_ = beta + (int64_t)item * stride;
-            float bet[CC];
+    for (int k = 0; k < 4; ++k) P[k] = 0.0;
+    walk([&](uint32_t bands, const float4& c0, const float4& c1, const uint2& e2, const float (&bet)[CC],
+             float del) {
+        const float dx = (px - c0.x) - c0.z;
+        const float a0 = c1.x * dx * dx;
+        const float b0 = c1.y * dx;
+        float go = 0.0f;
+        uint32_t any = 0;
 #pragma unroll
-            for (int c = 0; c < CC; ++c) bet[c] = (c_off + c < C) ? bp_[c_off + c] : 0.0f;
-            const float del = first_chunk ? bp_[C] : 0.0f;
-            const float dx = (px - c0.x) - c0.z;
-            const float a0 = c1.x * dx * dx;
-            const float b0 = c1.y * dx;
-            float go = 0.0f;
-            uint32_t any = 0;
+        for (int k = 0; k < 4; ++k) {
+            if (!((bands >> k) & 1u)) continue;  // uniform
+            const float dy = (pyk[k] - c0.y) - c0.w;
+            const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
+            const Step st = blend_step(T[k], live[k], q2, c1.w, qlim, bp);
+            float u = -del;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (!((bands >> k) & 1u)) continue;
-                const float dy = (pyk[k] - c0.y) - c0.w;
-                const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
-                const Step st = blend_step(T[k], live[k], q2, c1.w, qlim, bp);
-                float u = -del;
-#pragma unroll
-                for (int c = 0; c < CC; ++c) u = fmaf(bet[c], yv[k][c], u);
-                P[k] += (double)(st.w * u);
-                const float suffix = (float)(S[k] - P[k]);
-                const float dal = u * st.Tb - suffix / (1.0f - st.alpha);
-                const bool clamped = c1.w * st.G >= bp.alpha_max;
-                go += (st.take && !clamped) ? dal * st.G : 0.0f;
-                any |= st.take ? 1u : 0u;
-            }
-            if (__ballot(any != 0) != 0) {
-                const float t = wave_sum(go);
-                if (lane == 0) unsafeAtomicAdd(grad_o + ((int64_t)e2.y + g_shift), t);
-            }
-            if (__ballot(live[0] || live[1] || live[2] || live[3]) == 0) {
-                wave_live = false;
-                break;
-            }
+            for (int c = 0; c < CC; ++c) u = fmaf(bet[c], yv[k][c], u);
+            P[k] += (double)(st.w * u);
+            const float suffix = (float)(S[k] - P[k]);
+            const float dal = u * st.Tb - suffix / (1.0f - st.alpha);
+            const bool clamped = c1.w * st.G >= bp.alpha_max;
+            go += (st.take && !clamped) ? dal * st.G : 0.0f;
+            any |= st.take ? 1u : 0u;
         }
-    }
+        if (__ballot(any != 0) != 0) {
+            const float t = wave_sum(go);
+            if (lane == 0) unsafeAtomicAdd(grad_o + ((int64_t)e2.y + g_shift), t);
+        }
+    });
 }
 
 template <int CC, bool GY>
