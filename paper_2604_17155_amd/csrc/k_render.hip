@@ -121,29 +121,35 @@ __global__ __launch_bounds__(256) void k_render(
     float pyk[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) pyk[k] = (float)(iy0 + 4 * k) + 0.5f;
+    // A chunk of 64 entries is gathered at once, one entry per lane (records
+    // and the item's colours), and broadcast entry by entry; only entries
+    // reaching a band with a live pixel are visited.
     for (uint32_t b = rg.x; b < rg.y && alive != 0u; b += 64) {
         const uint32_t nb = min(64u, rg.y - b);
-        const uint32_t pv = lane < nb ? pair_vals[b + lane] : 0u;
-        uint32_t pn = bcast_u(pv, 0);
-        float4 n0 = rec0[pn & kItemMask], n1 = rec1[pn & kItemMask];
-        uint2 n2 = rec2[pn & kItemMask];
-        for (uint32_t j = 0; j < nb; ++j) {
-            const uint32_t pc = pn;
-            const float4 c0 = n0, c1 = n1;
-            const uint2 e2 = n2;
-            if (j + 1 < nb) {
-                pn = bcast_u(pv, j + 1);
-                n0 = rec0[pn & kItemMask];
-                n1 = rec1[pn & kItemMask];
-                n2 = rec2[pn & kItemMask];
-            }
-            const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2.x, tg.y0) & alive;
-            if (bands == 0u) continue;
-            const uint32_t item = e2.y;  // the record names the item
-            float col[CC];
-            const float* gp = gamma + (int64_t)item * C + c_off;
+        const bool own = lane < nb;
+        const uint32_t pv = own ? pair_vals[b + lane] : 0u;
+        const uint32_t it = pv & kItemMask;
+        const float4 R0 = own ? rec0[it] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 R1 = own ? rec1[it] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const uint2 R2 = own ? rec2[it] : make_uint2(0u, 0u);
+        const float* gl = gamma + (int64_t)R2.y * C + c_off;  // the record names the item
+        float RC[CC];
 #pragma unroll
-            for (int c = 0; c < CC; ++c) col[c] = (c_off + c < C) ? gp[c] : 0.0f;
+        for (int c = 0; c < CC; ++c) RC[c] = (own && c_off + c < C) ? gl[c] : 0.0f;
+        uint64_t todo = __builtin_amdgcn_ballot_w64(
+            own && (entry_bands<BIN>(pv, tg.quad, R2.x, tg.y0) & alive) != 0u);
+        while (todo != 0u) {
+            const uint32_t j = (uint32_t)__builtin_ctzll(todo);
+            todo &= todo - 1u;
+            const uint32_t pc = bcast_u(pv, j);
+            const uint32_t ext = bcast_u(R2.x, j);
+            const uint32_t bands = entry_bands<BIN>(pc, tg.quad, ext, tg.y0) & alive;
+            if (bands == 0u) continue;
+            const float4 c0 = make_float4(bcast(R0.x, j), bcast(R0.y, j), bcast(R0.z, j), bcast(R0.w, j));
+            const float4 c1 = make_float4(bcast(R1.x, j), bcast(R1.y, j), bcast(R1.z, j), bcast(R1.w, j));
+            float col[CC];
+#pragma unroll
+            for (int c = 0; c < CC; ++c) col[c] = bcast(RC[c], j);
             const float dx = (px - c0.x) - c0.z;
             const float a0 = c1.x * dx * dx;
             const float b0 = c1.y * dx;
