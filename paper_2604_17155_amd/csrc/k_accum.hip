@@ -40,7 +40,6 @@ __device__ __forceinline__ uint32_t accumulate_tile(
     const int64_t poff = V.pixel_offset;
     const int ix = tg.x0 + (int)(lane & 15);
     const int iy0 = tg.y0 + (int)(lane >> 4);
-    const float px = (float)ix + 0.5f;
     const int stride = C + 1;
 
     float T[4];
@@ -74,9 +73,11 @@ __device__ __forceinline__ uint32_t accumulate_tile(
 
     const float qlim = (float)(kExp2Scale * (double)bp.cut2);  // q <= cut2  <=>  q2 >= qlim
     const float amax = bp.alpha_max, amin = bp.alpha_min, tmin = bp.t_min;
-    float pyk[4];
+    // the lane's pixel column and rows within the tile
+    const float lx = (float)(lane & 15);
+    float lyk[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) pyk[k] = (float)(iy0 + 4 * k) + 0.5f;
+    for (int k = 0; k < 4; ++k) lyk[k] = (float)((lane >> 4) + 4 * k);
 
     // The list is walked in chunks of 64 entries.  A chunk's records are
     // gathered at once, one entry per lane, and broadcast entry by entry with
@@ -85,10 +86,15 @@ __device__ __forceinline__ uint32_t accumulate_tile(
     auto load_pv = [&](uint32_t b) -> uint32_t {
         return b + lane < rg.y ? pair_vals[b + lane] : 0u;
     };
-    auto gather = [&](uint32_t pv, uint32_t b, float4& R0, float4& R1, uint2& R2) {
+    // R0 keeps, per entry, the offset of the tile's first pixel centre from
+    // the projected centre, (x0 + 1/2 - u_hi) - u_lo and the same in y: a
+    // lane's offset is then that plus its pixel's column (row) in the tile.
+    const float ox = (float)tg.x0 + 0.5f, oy = (float)tg.y0 + 0.5f;
+    auto gather = [&](uint32_t pv, uint32_t b, float2& R0, float4& R1, uint2& R2) {
         const uint32_t it = pv & kItemMask;
         const bool own = b + lane < rg.y;
-        R0 = own ? rec0[it] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 r = own ? rec0[it] : make_float4(0.f, 0.f, 0.f, 0.f);
+        R0 = make_float2((ox - r.x) - r.z, (oy - r.y) - r.w);
         R1 = own ? rec1[it] : make_float4(0.f, 0.f, 0.f, 0.f);
         R2 = own ? rec2[it] : make_uint2(0u, 0u);
     };
@@ -96,12 +102,14 @@ __device__ __forceinline__ uint32_t accumulate_tile(
     // there the next chunk is gathered when the current one is done)
     constexpr bool kDouble = CC <= 4;
     uint32_t pv = load_pv(rg.x), pvn = load_pv(rg.x + 64);
-    float4 R0, R1;
+    float2 R0;
+    float4 R1;
     uint2 R2;
     gather(pv, rg.x, R0, R1, R2);
     for (uint32_t b = rg.x; b < rg.y && alive != 0u; b += 64) {
         const uint32_t nb = min(64u, rg.y - b);
-        float4 Q0, Q1;
+        float2 Q0;
+        float4 Q1;
         uint2 Q2;
         if constexpr (kDouble) gather(pvn, b + 64, Q0, Q1, Q2);
         const uint32_t pvnn = load_pv(b + 128);
@@ -130,15 +138,15 @@ __device__ __forceinline__ uint32_t accumulate_tile(
                     float sv = 0.0f, s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
                     uint32_t nh = 0;
                     if (bands != 0u) {
-                        const float4 c0 = make_float4(bcast(R0.x, j), bcast(R0.y, j), bcast(R0.z, j), bcast(R0.w, j));
+                        const float2 c0 = make_float2(bcast(R0.x, j), bcast(R0.y, j));
                         const float4 c1 = make_float4(bcast(R1.x, j), bcast(R1.y, j), bcast(R1.z, j), bcast(R1.w, j));
-                        const float dx = (px - c0.x) - c0.z;
+                        const float dx = c0.x + lx;
                         const float a0 = c1.x * dx * dx;
                         const float b0 = c1.y * dx;
 #pragma unroll
                         for (int k = 0; k < 4; ++k) {
                             if (!((bands >> k) & 1u)) continue;  // uniform
-                            const float dy = (pyk[k] - c0.y) - c0.w;
+                            const float dy = c0.y + lyk[k];
                             const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
                             uint64_t taken;
                             const float w = pixel_step(q2, c1.w, T[k], qlim, amin, amax, tmin, taken);
@@ -183,9 +191,9 @@ __device__ __forceinline__ uint32_t accumulate_tile(
                 const uint2 e2 = make_uint2(bcast_u(R2.x, j), bcast_u(R2.y, j));
                 const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2.x, tg.y0) & alive;
                 if (bands == 0u) continue;
-                const float4 c0 = make_float4(bcast(R0.x, j), bcast(R0.y, j), bcast(R0.z, j), bcast(R0.w, j));
+                const float2 c0 = make_float2(bcast(R0.x, j), bcast(R0.y, j));
                 const float4 c1 = make_float4(bcast(R1.x, j), bcast(R1.y, j), bcast(R1.z, j), bcast(R1.w, j));
-                const float dx = (px - c0.x) - c0.z;
+                const float dx = c0.x + lx;
                 const float a0 = c1.x * dx * dx;
                 const float b0 = c1.y * dx;
                 float sv = 0.0f;
@@ -196,7 +204,7 @@ __device__ __forceinline__ uint32_t accumulate_tile(
     #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     if (!((bands >> k) & 1u)) continue;  // uniform
-                    const float dy = (pyk[k] - c0.y) - c0.w;
+                    const float dy = c0.y + lyk[k];
                     const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
                     uint64_t taken;
                     const float w = pixel_step(q2, c1.w, T[k], qlim, amin, amax, tmin, taken);
