@@ -396,7 +396,6 @@ __device__ __forceinline__ uint32_t accumulate_tile_mfma(
     const int64_t poff = V.pixel_offset;
     const int ix = tg.x0 + (int)(lane & 15);
     const int iy0 = tg.y0 + (int)(lane >> 4);
-    const float px = (float)ix + 0.5f;
     const int stride = C + 1;
     const uint32_t n16 = lane & 15, q4 = lane >> 4;
     constexpr int ROWS = mfma_rows<NBLK>();
@@ -458,9 +457,14 @@ __device__ __forceinline__ uint32_t accumulate_tile_mfma(
     const bool first_chunk = c_off == 0;
     const float qlim = (float)(kExp2Scale * (double)bp.cut2);
     const float amax = bp.alpha_max, amin = bp.alpha_min, tmin = bp.t_min;
-    float pyk[4];
+    // the lane's pixel column and rows within the tile; R0 below keeps, per
+    // entry, the offset of the tile's first pixel centre from the projected
+    // centre
+    const float lx = (float)(lane & 15);
+    float lyk[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) pyk[k] = (float)(iy0 + 4 * k) + 0.5f;
+    for (int k = 0; k < 4; ++k) lyk[k] = (float)((lane >> 4) + 4 * k);
+    const float ox = (float)tg.x0 + 0.5f, oy = (float)tg.y0 + 0.5f;
 
     // W rows start (and are left) zero
     {
@@ -541,12 +545,14 @@ __device__ __forceinline__ uint32_t accumulate_tile_mfma(
     auto load_pv = [&](uint32_t b) -> uint32_t { return b + lane < rg.y ? pair_vals[b + lane] : 0u; };
     uint32_t b = rg.x;
     uint32_t pv = load_pv(b);
-    float4 R0 = make_float4(0.f, 0.f, 0.f, 0.f), R1 = R0;
+    float2 R0 = make_float2(0.f, 0.f);
+    float4 R1 = make_float4(0.f, 0.f, 0.f, 0.f);
     uint2 R2 = make_uint2(0u, 0u);
     auto gather = [&](uint32_t p, uint32_t base) {
         const uint32_t it = p & kItemMask;
         const bool own = base + lane < rg.y && pair_reaches<BIN>(p, tg.quad, alive);
-        R0 = own ? rec0[it] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 r = own ? rec0[it] : make_float4(0.f, 0.f, 0.f, 0.f);
+        R0 = make_float2((ox - r.x) - r.z, (oy - r.y) - r.w);
         R1 = own ? rec1[it] : make_float4(0.f, 0.f, 0.f, 0.f);
         R2 = own ? rec2[it] : make_uint2(0u, 0u);
     };
@@ -576,9 +582,9 @@ __device__ __forceinline__ uint32_t accumulate_tile_mfma(
         const uint2 e2 = make_uint2(bcast_u(R2.x, j), bcast_u(R2.y, j));
         const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2.x, tg.y0) & alive;
         if (bands == 0u) continue;
-        const float4 c0 = make_float4(bcast(R0.x, j), bcast(R0.y, j), bcast(R0.z, j), bcast(R0.w, j));
+        const float2 c0 = make_float2(bcast(R0.x, j), bcast(R0.y, j));
         const float4 c1 = make_float4(bcast(R1.x, j), bcast(R1.y, j), bcast(R1.z, j), bcast(R1.w, j));
-        const float dx = (px - c0.x) - c0.z;
+        const float dx = c0.x + lx;
         const float a0 = c1.x * dx * dx;
         const float b0 = c1.y * dx;
         uint32_t nh = 0;
@@ -587,7 +593,7 @@ __device__ __forceinline__ uint32_t accumulate_tile_mfma(
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             if (!((bands >> k) & 1u)) continue;  // uniform
-            const float dy = (pyk[k] - c0.y) - c0.w;
+            const float dy = c0.y + lyk[k];
             const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
             uint64_t taken;
             const float w = pixel_step(q2, c1.w, T[k], qlim, amin, amax, tmin, taken);

@@ -149,7 +149,6 @@ __global__ __launch_bounds__(256) void k_blend_adjoint(
     const ViewInfo& V = views[tg.vloc];
     const int ix = tg.x0 + (int)(lane & 15);
     const int iy0 = tg.y0 + (int)(lane >> 4);
-    const float px = (float)ix + 0.5f;
     const int stride = C + 1;
     const bool first_chunk = c_off == 0;
     // dL/do of an entry goes to Gaussian g_offset + (item - item_base), the
@@ -159,12 +158,17 @@ __global__ __launch_bounds__(256) void k_blend_adjoint(
 
     bool inside[4];
     float yv[4][CC];  // pixel values (read only when dL/do is wanted)
-    float pyk[4];
+    // the lane's pixel column and rows within the tile; R0 below keeps, per
+    // entry, the offset of the tile's first pixel centre from the projected
+    // centre
+    const float lx = (float)(lane & 15);
+    float lyk[4];
+    const float ox = (float)tg.x0 + 0.5f, oy = (float)tg.y0 + 0.5f;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int iy = iy0 + 4 * k;
         inside[k] = ix < V.width && iy < V.height;
-        pyk[k] = (float)iy + 0.5f;
+        lyk[k] = (float)((lane >> 4) + 4 * k);
         const int64_t row = V.pixel_offset + (int64_t)iy * V.width + ix;
 #pragma unroll
         for (int c = 0; c < CC; ++c)
@@ -198,7 +202,8 @@ __global__ __launch_bounds__(256) void k_blend_adjoint(
             const bool own = lane < nb;
             const uint32_t pv = own ? pair_vals[b + lane] : 0u;
             const uint32_t it = pv & kItemMask;
-            const float4 R0 = own ? rec0[it] : make_float4(0.f, 0.f, 0.f, 0.f);
+            const float4 r = own ? rec0[it] : make_float4(0.f, 0.f, 0.f, 0.f);
+            const float2 R0 = make_float2((ox - r.x) - r.z, (oy - r.y) - r.w);
             const float4 R1 = own ? rec1[it] : make_float4(0.f, 0.f, 0.f, 0.f);
             const uint2 R2 = own ? rec2[it] : make_uint2(0u, 0u);
             const float* bl = beta + (int64_t)R2.y * stride;  // the record names the item
@@ -215,7 +220,7 @@ __global__ __launch_bounds__(256) void k_blend_adjoint(
                 const uint2 e2 = make_uint2(bcast_u(R2.x, j), bcast_u(R2.y, j));
                 const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2.x, tg.y0) & alive;
                 if (bands == 0u) continue;
-                const float4 c0 = make_float4(bcast(R0.x, j), bcast(R0.y, j), bcast(R0.z, j), bcast(R0.w, j));
+                const float2 c0 = make_float2(bcast(R0.x, j), bcast(R0.y, j));
                 const float4 c1 = make_float4(bcast(R1.x, j), bcast(R1.y, j), bcast(R1.z, j), bcast(R1.w, j));
                 float bet[CC];
 #pragma unroll
@@ -240,15 +245,15 @@ __global__ __launch_bounds__(256) void k_blend_adjoint(
 #pragma unroll
         for (int c = 0; c < (GY ? CC : 1); ++c) gy[k][c] = 0.0f;
     }
-    walk([&](uint32_t bands, const float4& c0, const float4& c1, const uint2& e2, const float (&bet)[CC],
+    walk([&](uint32_t bands, const float2& c0, const float4& c1, const uint2& e2, const float (&bet)[CC],
              float del) {
-        const float dx = (px - c0.x) - c0.z;
+        const float dx = c0.x + lx;
         const float a0 = c1.x * dx * dx;
         const float b0 = c1.y * dx;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             if (!((bands >> k) & 1u)) continue;  // uniform
-            const float dy = (pyk[k] - c0.y) - c0.w;
+            const float dy = c0.y + lyk[k];
             const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
             const Step st = blend_step(T[k], live[k], q2, c1.w, qlim, bp);
             float u = -del;
@@ -277,9 +282,9 @@ __global__ __launch_bounds__(256) void k_blend_adjoint(
     double P[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) P[k] = 0.0;
-    walk([&](uint32_t bands, const float4& c0, const float4& c1, const uint2& e2, const float (&bet)[CC],
+    walk([&](uint32_t bands, const float2& c0, const float4& c1, const uint2& e2, const float (&bet)[CC],
              float del) {
-        const float dx = (px - c0.x) - c0.z;
+        const float dx = c0.x + lx;
         const float a0 = c1.x * dx * dx;
         const float b0 = c1.y * dx;
         float go = 0.0f;
@@ -287,7 +292,7 @@ __global__ __launch_bounds__(256) void k_blend_adjoint(
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             if (!((bands >> k) & 1u)) continue;  // uniform
-            const float dy = (pyk[k] - c0.y) - c0.w;
+            const float dy = c0.y + lyk[k];
             const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
             const Step st = blend_step(T[k], live[k], q2, c1.w, qlim, bp);
             float u = -del;

@@ -98,7 +98,6 @@ __global__ __launch_bounds__(256) void k_render(
     const ViewInfo& V = views[tg.vloc];
     const int ix = tg.x0 + (int)(lane & 15);
     const int iy0 = tg.y0 + (int)(lane >> 4);
-    const float px = (float)ix + 0.5f;
     float T[4];
     bool inside[4];
     float img[4][CC];
@@ -118,9 +117,14 @@ __global__ __launch_bounds__(256) void k_render(
     uint32_t cnt = 0;
     const float qlim = (float)(kExp2Scale * (double)bp.cut2);
     const float amax = bp.alpha_max, amin = bp.alpha_min, tmin = bp.t_min;
-    float pyk[4];
+    // the lane's pixel column and rows within the tile; R0 below keeps, per
+    // entry, the offset of the tile's first pixel centre from the projected
+    // centre
+    const float lx = (float)(lane & 15);
+    float lyk[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) pyk[k] = (float)(iy0 + 4 * k) + 0.5f;
+    for (int k = 0; k < 4; ++k) lyk[k] = (float)((lane >> 4) + 4 * k);
+    const float ox = (float)tg.x0 + 0.5f, oy = (float)tg.y0 + 0.5f;
     // A chunk of 64 entries is gathered at once, one entry per lane (records
     // and the item's colours), and broadcast entry by entry; only entries
     // reaching a band with a live pixel are visited.
@@ -129,7 +133,8 @@ __global__ __launch_bounds__(256) void k_render(
         const bool own = lane < nb;
         const uint32_t pv = own ? pair_vals[b + lane] : 0u;
         const uint32_t it = pv & kItemMask;
-        const float4 R0 = own ? rec0[it] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 r = own ? rec0[it] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float2 R0 = make_float2((ox - r.x) - r.z, (oy - r.y) - r.w);
         const float4 R1 = own ? rec1[it] : make_float4(0.f, 0.f, 0.f, 0.f);
         const uint2 R2 = own ? rec2[it] : make_uint2(0u, 0u);
         const float* gl = gamma + (int64_t)R2.y * C + c_off;  // the record names the item
@@ -145,19 +150,19 @@ __global__ __launch_bounds__(256) void k_render(
             const uint32_t ext = bcast_u(R2.x, j);
             const uint32_t bands = entry_bands<BIN>(pc, tg.quad, ext, tg.y0) & alive;
             if (bands == 0u) continue;
-            const float4 c0 = make_float4(bcast(R0.x, j), bcast(R0.y, j), bcast(R0.z, j), bcast(R0.w, j));
+            const float2 c0 = make_float2(bcast(R0.x, j), bcast(R0.y, j));
             const float4 c1 = make_float4(bcast(R1.x, j), bcast(R1.y, j), bcast(R1.z, j), bcast(R1.w, j));
             float col[CC];
 #pragma unroll
             for (int c = 0; c < CC; ++c) col[c] = bcast(RC[c], j);
-            const float dx = (px - c0.x) - c0.z;
+            const float dx = c0.x + lx;
             const float a0 = c1.x * dx * dx;
             const float b0 = c1.y * dx;
             uint32_t nh = 0;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (!((bands >> k) & 1u)) continue;
-                const float dy = (pyk[k] - c0.y) - c0.w;
+                const float dy = c0.y + lyk[k];
                 const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
                 uint64_t taken;
                 const float w = pixel_step(q2, c1.w, T[k], qlim, amin, amax, tmin, taken);
