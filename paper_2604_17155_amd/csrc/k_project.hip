@@ -427,13 +427,19 @@ void launch_emit(const ViewInfo* views, int n_views, const uint32_t* sorted_vals
                            overflow, pair_keys, pair_vals);
 }
 
+// A modest grid (one 64-bit atomic per block on the same word) reading 16
+// bytes per thread and step; counts is 16-byte aligned.
 __global__ __launch_bounds__(256) void k_sum_u64(const uint32_t* __restrict__ counts, uint32_t n,
                                                 unsigned long long* __restrict__ out) {
     __shared__ unsigned long long part[4];
     unsigned long long acc = 0;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * blockDim.x)
-        acc += counts[i];
+    const uint4* c4 = reinterpret_cast<const uint4*>(counts);
+    const uint32_t n4 = n / 4;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += gridDim.x * blockDim.x) {
+        const uint4 v = c4[i];
+        acc += (unsigned long long)v.x + v.y + v.z + v.w;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < n - 4 * n4) acc += counts[4 * n4 + threadIdx.x];
     for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
     __syncthreads();
@@ -442,8 +448,9 @@ __global__ __launch_bounds__(256) void k_sum_u64(const uint32_t* __restrict__ co
 
 void launch_sum_u64(const uint32_t* counts, uint32_t n, unsigned long long* out, hipStream_t s) {
     if (n == 0) return;
-    uint32_t blocks = (n + 255) / 256;
-    if (blocks > 2048) blocks = 2048;
+    // about eight 16-byte loads per thread, at most 1024 atomics
+    uint32_t blocks = (n / 4 + 2047) / 2048;
+    blocks = blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks);
     hipLaunchKernelGGL(k_sum_u64, dim3(blocks), dim3(256), 0, s, counts, n, out);
 }
 
@@ -451,12 +458,17 @@ __global__ void k_tile_ranges(const uint32_t* __restrict__ keys, uint32_t n,
                               const uint32_t* __restrict__ n_dev, uint32_t n_tiles,
                               uint2* __restrict__ ranges) {
     if (n_dev) n = min(n, *n_dev);
-    uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    uint32_t t = keys[k];
-    if (t >= n_tiles) return;
-    if (k == 0 || keys[k - 1] != t) ranges[t].x = k;
-    if (k == n - 1 || keys[k + 1] != t) ranges[t].y = k + 1;
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t lane = threadIdx.x & 63;
+    // neighbours from the adjacent lanes; loads only at the wave's edges
+    const uint32_t t = k < n ? keys[k] : 0xFFFFFFFFu;
+    uint32_t prev = (uint32_t)__shfl_up((int)t, 1, 64);
+    uint32_t next = (uint32_t)__shfl_down((int)t, 1, 64);
+    if (lane == 0) prev = (k > 0 && k - 1 < n) ? keys[k - 1] : 0xFFFFFFFFu;
+    if (lane == 63) next = k + 1 < n ? keys[k + 1] : 0xFFFFFFFFu;
+    if (k >= n || t >= n_tiles) return;
+    if (k == 0 || prev != t) ranges[t].x = k;
+    if (k == n - 1 || next != t) ranges[t].y = k + 1;
 }
 
 void launch_tile_ranges(const uint32_t* sorted_keys, uint32_t n_pairs, uint32_t n_tiles,
