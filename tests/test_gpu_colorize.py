@@ -253,6 +253,31 @@ def test_render_matches_oracle(ctx, gsc_mod):
     assert abs(int(stats.contributions) - ref_full["count"]) <= ref_full["events"]
 
 
+def test_render_l2_six_channels_ragged(ctx, gsc_mod):
+    """L = 2, C = 6 (two render launches of four channels, the second partly
+    outside C), 200x120 views: the transposed coefficient reads for every
+    (m, c) row."""
+    import torch
+    rng = np.random.default_rng(21)
+    sc = syn.make_relight(n=6000, n_cams=5, res=64, sh_deg=2)
+    sc.cams = syn.hemisphere_cams(5, 3.0, 200, 120)
+    coeffs = rng.normal(0.0, 0.3, (sc.N, 9, 6))
+    coeffs[:, 0, :] += 0.5
+    m, s, q, o = gsc_mod.scene_tensors(sc)
+    img = ctx.render(m, s, q, o, sc.cams, torch.from_numpy(coeffs.astype(np.float32)).cuda())
+    torch.cuda.synchronize()
+    img = img.cpu().numpy()
+    sc.C = 6
+    ref32 = oracle.render(sc, coeffs.astype(np.float32).astype(np.float64))
+    err = np.abs(img - ref32).max(axis=1)
+    ref_full = oracle.colorize(sc, np.zeros((sc.n_pixels, 6), np.float32))
+    bad = int((err > 1e-4).sum())
+    print(f"render L2 C6: max err {err.max():.2e}, pixels >1e-4: {bad}, events {ref_full['events']}", flush=True)
+    assert img.shape == (sc.n_pixels, 6)
+    assert bad <= ref_full["events"]
+    assert np.median(err) < 1e-6
+
+
 def test_repeat_and_context_reuse(ctx):
     sc_big = syn.make_relight(n=20000, n_cams=10, res=160)
     y_big = oracle.make_targets(sc_big)
