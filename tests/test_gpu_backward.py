@@ -155,6 +155,26 @@ def test_render_backward_smooth(ctx_smooth, gsc_mod):
     assert ec <= TOL_GRAD and eo <= TOL_GRAD
 
 
+def test_render_backward_l1_five_channels(ctx_smooth, gsc_mod):
+    """L = 1, C = 5 on 150x90 views: transposed coefficient reads for every
+    (m, c) row in the render adjoint."""
+    import torch
+    rng = np.random.default_rng(5)
+    sc = syn.make_relight(n=3000, n_cams=5, res=64, sh_deg=1)
+    sc.cams = syn.hemisphere_cams(5, 3.0, 150, 90)
+    sc.C = 5
+    c32 = (rng.normal(0.0, 0.3, (sc.N, 4, 5)) + np.array([0.5, 0, 0, 0])[None, :, None]).astype(np.float32)
+    gi = rng.standard_normal((sc.n_pixels, 5)).astype(np.float32)
+    gc_ref, go_ref = oracle.render_backward(sc, c32.astype(np.float64), gi.astype(np.float64),
+                                            opts=smooth_opts())
+    m, s, q, o = gsc_mod.scene_tensors(sc)
+    gc, go = ctx_smooth.render_backward(m, s, q, o, sc.cams, _dev(c32), _dev(gi))
+    torch.cuda.synchronize()
+    ec, eo = rel_l2(gc.cpu().numpy(), gc_ref), rel_l2(go.cpu().numpy(), go_ref)
+    print(f"render adjoint L1 C5 smooth: grad_coeffs {ec:.2e}; grad_opacities {eo:.2e}", flush=True)
+    assert ec <= TOL_GRAD and eo <= TOL_GRAD
+
+
 def test_render_backward_l0_production(ctx_prod, gsc_mod):
     import torch
     sc = syn.make_plain()
