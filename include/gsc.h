@@ -128,7 +128,10 @@ typedef struct {
     int32_t flags;
     int32_t bin_size; /* 0 (automatic), 16 or 32: pixels per side of the screen
                          bins the Gaussians are sorted into; the result does not
-                         depend on it (the footprint test is per pixel) */
+                         depend on it (the footprint test is per pixel).  The
+                         automatic choice reads geometry statistics back once
+                         and is reused by later calls on the same geometry
+                         pointers, Gaussian count and cameras. */
     int32_t accumulate_variant; /* 0 (automatic) or a variant code of the blend +
                          accumulate launch: channels per launch (1, 2, 3, 4, 8, 16);
                          128 + 16, 32 or 64 for the matrix-core form on BF16
@@ -141,9 +144,11 @@ typedef struct {
                            its 16x16 tiles: GSC_SCHEDULE_AUTO (0),
                            GSC_SCHEDULE_GRID (1: one wave per tile, in tile
                            index order) or GSC_SCHEDULE_LONGEST_FIRST (2:
-                           waves take tiles from a work queue, bins in
-                           decreasing octave of list length, tile index
-                           order within an octave).  The result does not depend
+                           bins in decreasing octave of list length, tile
+                           index order within an octave; the grid's blocks
+                           map to tiles in that order, or, for the
+                           matrix-core form, a persistent grid takes them from
+                           a work queue).  The result does not depend
                            on it beyond the order of floating-point atomic
                            additions. */
 } gsc_options;

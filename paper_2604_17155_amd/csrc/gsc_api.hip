@@ -95,6 +95,11 @@ struct BinKey {
 struct gsc_ctx {
     gsc_options opt;
     int bin = 16;  // bin size of the current call
+    // The automatic bin size of the last call and what it was chosen for
+    // (geometry buffers, size, cameras): a call on the same ones reuses it
+    // without reading statistics back.  The choice only steers performance.
+    BinKey bin_choice_key;
+    int bin_choice = 0;
     // the single-batch binning left in the buffers by the last call
     bool cache_valid = false;
     BinKey cache_key;
@@ -527,14 +532,25 @@ gsc_status ensure_common(gsc_ctx* ctx, const float* means, const float* scales,
     }
     ctx->bin = ctx->opt.bin_size;
     if (ctx->bin == 0) {
-        double* d_stats = reinterpret_cast<double*>(ctx->misc.as<char>() + 32);
-        launch_geometry_stats(means, scales, N, d_stats, s);
-        GSC_LAUNCHED("geometry stats");
-        GSC_HIP(hipMemcpyAsync(ctx->h_total, d_stats, 32, hipMemcpyDeviceToHost, s));
-        GSC_HIP(hipStreamSynchronize(s));
-        double st[4];
-        memcpy(st, ctx->h_total, sizeof(st));
-        ctx->bin = choose_bin(st, N, cams, n_cams);
+        BinKey key;
+        key.means = means;
+        key.scales = scales;
+        key.N = N;
+        key.cams.assign(cams, cams + n_cams);
+        if (ctx->bin_choice != 0 && key.same(ctx->bin_choice_key)) {
+            ctx->bin = ctx->bin_choice;
+        } else {
+            double* d_stats = reinterpret_cast<double*>(ctx->misc.as<char>() + 32);
+            launch_geometry_stats(means, scales, N, d_stats, s);
+            GSC_LAUNCHED("geometry stats");
+            GSC_HIP(hipMemcpyAsync(ctx->h_total, d_stats, 32, hipMemcpyDeviceToHost, s));
+            GSC_HIP(hipStreamSynchronize(s));
+            double st[4];
+            memcpy(st, ctx->h_total, sizeof(st));
+            ctx->bin = choose_bin(st, N, cams, n_cams);
+            ctx->bin_choice = ctx->bin;
+            ctx->bin_choice_key = std::move(key);
+        }
     }
     GSC_HIP(ctx->cov.ensure(sizeof(float) * kGeoStride * (size_t)std::max<int64_t>(N, 1)));
     launch_fill_u32(ctx->misc.as<uint32_t>(), 0u, kMiscBytes / 4, s);
@@ -850,9 +866,13 @@ gsc_status gsc_colorize_ex(gsc_ctx* ctx, const float* means, const float* scales
         const int chunk = resolve_chunk(ctx->opt.accumulate_variant, C, tdtype);
         StageTimer t(ctx, s, GSC_STAGE_BLEND, (uint32_t)accumulate_launches(C, chunk));
         (void)v0;
+        // Tiles in the longest-first order: the vector form as a grid whose
+        // blocks map to tiles through the order (the hardware dispatches
+        // blocks in index order), the matrix-core form as a persistent grid
+        // taking tiles from a work queue (each measured the faster for it).
         uint32_t* queues = nullptr;
-        const uint32_t* order = nullptr;
-        if ((order = tile_order(ctx, bn.n_tiles)) != nullptr) {
+        const uint32_t* order = tile_order(ctx, bn.n_tiles);
+        if (order != nullptr && (chunk & kChunkMfma)) {
             GSC_HIP(ctx->queues.ensure(4 * (size_t)(kMaxC + 1)));
             queues = ctx->queues.as<uint32_t>();
         }
