@@ -375,7 +375,13 @@ struct alignas(16) MfmaLds {
 };
 
 template <int NBLK>
-constexpr int mfma_rows() { return NBLK == 1 ? 8 : 16; }
+constexpr int mfma_rows() { return NBLK <= 2 ? 8 : 16; }
+// Waves per SIMD the register allocation of the 32-channel form is held to
+// (its weight rows in LDS then allow them): 208 registers ran at two waves per
+// SIMD, 168 at three.  The 64-channel form keeps its 128 target registers
+// unconstrained.
+template <int NBLK>
+constexpr int mfma_waves_per_simd() { return NBLK == 2 ? 3 : 1; }
 
 // YM: target layout in the B operand.  0: BF16, NBLK blocks of 16 channels,
 // V from a separate product against ones.  1: BF16, C <= 15 channels packed
@@ -620,7 +626,8 @@ __device__ __forceinline__ uint32_t accumulate_tile_mfma(
 }
 
 template <int NBLK, int BIN, int YM>
-__global__ __launch_bounds__(64 * kMfmaWaves) void k_accumulate_mfma(
+__global__ __launch_bounds__(64 * kMfmaWaves)
+__attribute__((amdgpu_waves_per_eu(mfma_waves_per_simd<NBLK>()))) void k_accumulate_mfma(
     const ViewInfo* __restrict__ views, int n_views, uint32_t n_tiles, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ pair_vals, const float4* __restrict__ rec0,
     const float4* __restrict__ rec1, const uint2* __restrict__ rec2,
