@@ -269,8 +269,14 @@ __device__ __forceinline__ uint32_t accumulate_tile(
 // tiles.  Otherwise persistent: a fixed grid whose waves take tiles from the
 // counter *queue (zero before the launch) until none are left.  Either way
 // tiles come in the order `order` gives (nullptr: tile index order).
+// Waves per SIMD the register allocation is held to: the forms of up to
+// three channels fit seven (72 registers) and run faster there; wider ones
+// spill when held below their natural count and are left alone.
+template <int CC>
+constexpr int acc_waves_per_simd() { return CC >= 1 && CC <= 3 ? 7 : 1; }
+
 template <int CC, bool BF16, int BIN>
-__global__ __launch_bounds__(256) void k_accumulate(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(acc_waves_per_simd<CC>()))) void k_accumulate(
     const ViewInfo* __restrict__ views, int n_views, uint32_t n_tiles, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ pair_vals,
     const float4* __restrict__ rec0, const float4* __restrict__ rec1,
