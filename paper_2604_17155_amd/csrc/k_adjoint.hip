@@ -133,8 +133,13 @@ __device__ __forceinline__ Step blend_step(float& T, bool& live, float q2, float
 // CC: channels of this launch (chunk [c_off, c_off + CC) of C).  dL/dw is
 // linear in the channels, so chunk launches add their shares of dL/do; the
 // first chunk also carries -delta.
+// The forms of up to three channels are held to seven waves per SIMD (72
+// registers), as the forward accumulate.
+template <int CC>
+constexpr int adj_waves_per_simd() { return CC >= 1 && CC <= 3 ? 7 : 1; }
+
 template <int CC, bool BF16, bool GY, int BIN>
-__global__ __launch_bounds__(256) void k_blend_adjoint(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(adj_waves_per_simd<CC>()))) void k_blend_adjoint(
     const ViewInfo* __restrict__ views, int n_views, uint32_t n_wt, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ pair_vals,
     const float4* __restrict__ rec0, const float4* __restrict__ rec1,
