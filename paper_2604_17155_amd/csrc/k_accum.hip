@@ -382,12 +382,13 @@ struct alignas(16) MfmaLds {
 
 template <int NBLK>
 constexpr int mfma_rows() { return NBLK <= 2 ? 8 : 16; }
-// Waves per SIMD the register allocation of the 32-channel form is held to
-// (its weight rows in LDS then allow them): 208 registers ran at two waves per
-// SIMD, 168 at three.  The 64-channel form keeps its 128 target registers
-// unconstrained.
+// Waves per SIMD the register allocation is held to (the weight rows in LDS
+// allow them): the 32-channel form ran at two waves per SIMD with 208
+// registers and runs at three with 168; the 16-channel and packed forms at
+// four (128 registers, up from three).  The 64-channel form keeps its 128
+// target registers unconstrained.
 template <int NBLK>
-constexpr int mfma_waves_per_simd() { return NBLK == 2 ? 3 : 1; }
+constexpr int mfma_waves_per_simd() { return NBLK == 2 ? 3 : (NBLK == 1 ? 4 : 1); }
 
 // YM: target layout in the B operand.  0: BF16, NBLK blocks of 16 channels,
 // V from a separate product against ones.  1: BF16, C <= 15 channels packed
