@@ -341,7 +341,7 @@ void launch_project(const ViewInfo* views, int n_views, uint32_t n_items, const 
 // a3: emit (global bin id, k | mask) pairs in depth order, k being the depth
 // rank of the item (records, counts and offsets are in that order); a stable
 // sort by bin id then yields every bin's list in front-to-back order.
-constexpr uint32_t kEmitStage = 3072;  // pairs a block stages in LDS (24 KB)
+constexpr uint32_t kEmitStage = 2048;  // pairs a block stages in LDS (16 KB: eight resident blocks per CU)
 
 template <int BIN>
 __global__ __launch_bounds__(256) void k_emit(const ViewInfo* __restrict__ views, int n_views,
