@@ -142,22 +142,27 @@ __global__ __launch_bounds__(256) void k_fold_solve(const ViewInfo* __restrict__
             for (int c = 0; c < 4; ++c) accB[k][c] = 0.0;
         }
         double wv = 0.0;
-        const int nvw = (valid && (!ADJ || firstc)) ? n_views : 0;
-        const float* slot = VS + g * (int64_t)stride;
+        // The view loop and the view index are the same on every lane, so the
+        // view centres come through scalar loads and waiting for them never
+        // waits for the vector loads of the next group.  The sums are loaded
+        // without branches (an invalid lane reads its block's first slot, a
+        // view past the end reads the last view) and masked where used.
+        const int nvw = (!ADJ || firstc) ? n_views : 0;
+        const float* slot = VS + (valid ? g : (int64_t)blockIdx.x * (blockDim.x >> 2)) * (int64_t)stride;
         const int64_t vstep = N * (int64_t)stride;
         constexpr int kGroup = 4;
         float cV[kGroup], cS[kGroup][4], nV[kGroup], nS[kGroup][4];
         auto load_group = [&](int v0, float (&gV)[kGroup], float (&gS)[kGroup][4]) {
 #pragma unroll
             for (int u = 0; u < kGroup; ++u) {
-                const bool in = v0 + u < nvw;
-                const float* p = slot + (int64_t)(v0 + u) * vstep;
-                gV[u] = in ? p[0] : 0.0f;
+                const int vl = v0 + u < nvw ? v0 + u : nvw - 1;
+                const float* p = slot + (int64_t)vl * vstep;
+                gV[u] = p[0];
 #pragma unroll
-                for (int c = 0; c < 4; ++c) gS[u][c] = (in && !ADJ && c0 + c < C) ? p[1 + c0 + c] : 0.0f;
+                for (int c = 0; c < 4; ++c) gS[u][c] = (!ADJ && c0 + c < C) ? p[1 + c0 + c] : 0.0f;
             }
         };
-        load_group(0, cV, cS);
+        if (nvw > 0) load_group(0, cV, cS);
 #pragma unroll 1
         for (int v0 = 0; v0 < nvw; v0 += kGroup) {
             load_group(v0 + kGroup, nV, nS);
@@ -169,7 +174,7 @@ __global__ __launch_bounds__(256) void k_fold_solve(const ViewInfo* __restrict__
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const int v = v0 + u + h;
-                    const bool use = v < nvw && cV[u + h] != 0.0f;
+                    const bool use = valid && v < nvw && cV[u + h] != 0.0f;
                     const int vv = v < nvw ? v : 0;
                     const float dx = mx - (float)views[vv].centre[0];
                     const float dy = my - (float)views[vv].centre[1];
@@ -177,6 +182,8 @@ __global__ __launch_bounds__(256) void k_fold_solve(const ViewInfo* __restrict__
                     const float inv = rsqrtf(dx * dx + dy * dy + dz * dz);
                     sh_eval<float, L>(dx * inv, dy * inv, dz * inv, phf[h]);
                     Vd[h] = use ? (double)cV[u + h] : 0.0;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) cS[u + h][c] = use ? cS[u + h][c] : 0.0f;
                 }
 #pragma unroll
                 for (int k = 0; k < RPL; ++k) {
