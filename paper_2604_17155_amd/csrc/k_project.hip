@@ -454,27 +454,44 @@ void launch_sum_u64(const uint32_t* counts, uint32_t n, unsigned long long* out,
     hipLaunchKernelGGL(k_sum_u64, dim3(blocks), dim3(256), 0, s, counts, n, out);
 }
 
-__global__ void k_tile_ranges(const uint32_t* __restrict__ keys, uint32_t n,
-                              const uint32_t* __restrict__ n_dev, uint32_t n_tiles,
-                              uint2* __restrict__ ranges) {
+// Thread q owns keys 4q .. 4q + 3 (one 16-byte load where all four are
+// live); neighbours across threads come from the adjacent lanes, with loads
+// only at the wave's edges.
+__global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t* __restrict__ keys, uint32_t n,
+                                                     const uint32_t* __restrict__ n_dev, uint32_t n_tiles,
+                                                     uint2* __restrict__ ranges) {
     if (n_dev) n = min(n, *n_dev);
-    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t lane = threadIdx.x & 63;
-    // neighbours from the adjacent lanes; loads only at the wave's edges
-    const uint32_t t = k < n ? keys[k] : 0xFFFFFFFFu;
-    uint32_t prev = (uint32_t)__shfl_up((int)t, 1, 64);
-    uint32_t next = (uint32_t)__shfl_down((int)t, 1, 64);
-    if (lane == 0) prev = (k > 0 && k - 1 < n) ? keys[k - 1] : 0xFFFFFFFFu;
-    if (lane == 63) next = k + 1 < n ? keys[k + 1] : 0xFFFFFFFFu;
-    if (k >= n || t >= n_tiles) return;
-    if (k == 0 || prev != t) ranges[t].x = k;
-    if (k == n - 1 || next != t) ranges[t].y = k + 1;
+    const uint64_t k0 = 4ull * q;
+    uint32_t t[4];
+    if (k0 + 3 < n) {
+        const uint4 v = reinterpret_cast<const uint4*>(keys)[q];
+        t[0] = v.x; t[1] = v.y; t[2] = v.z; t[3] = v.w;
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) t[e] = k0 + e < n ? keys[k0 + e] : 0xFFFFFFFFu;
+    }
+    uint32_t prev = (uint32_t)__shfl_up((int)t[3], 1, 64);
+    uint32_t next = (uint32_t)__shfl_down((int)t[0], 1, 64);
+    if (lane == 0) prev = (k0 > 0 && k0 - 1 < n) ? keys[k0 - 1] : 0xFFFFFFFFu;
+    if (lane == 63) next = k0 + 4 < n ? keys[k0 + 4] : 0xFFFFFFFFu;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const uint64_t k = k0 + e;
+        if (k >= n || t[e] >= n_tiles) continue;
+        const uint32_t p = e == 0 ? prev : t[e > 0 ? e - 1 : 0];
+        const uint32_t x = e == 3 ? next : t[e < 3 ? e + 1 : 3];
+        if (k == 0 || p != t[e]) ranges[t[e]].x = (uint32_t)k;
+        if (k + 1 == n || x != t[e]) ranges[t[e]].y = (uint32_t)(k + 1);
+    }
 }
 
 void launch_tile_ranges(const uint32_t* sorted_keys, uint32_t n_pairs, uint32_t n_tiles,
                         uint2* ranges, hipStream_t s, const uint32_t* n_dev) {
     if (n_pairs == 0) return;
-    hipLaunchKernelGGL(k_tile_ranges, dim3((n_pairs + 255) / 256), dim3(256), 0, s, sorted_keys,
+    const uint32_t quads = (uint32_t)(((uint64_t)n_pairs + 3) / 4);
+    hipLaunchKernelGGL(k_tile_ranges, dim3((quads + 255) / 256), dim3(256), 0, s, sorted_keys,
                        n_pairs, n_dev, n_tiles, ranges);
 }
 
