@@ -63,10 +63,22 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __
     if (threadIdx.x == 0) bsums[blockIdx.x] = tot;
 }
 
+// Down-sweep of one 2048-element block.  The block's offset is bsums[b] when
+// the block sums have been scanned already; with `raw` they have not, and the
+// block adds up bsums[0 .. b) itself (a few KB read from L2 for up to 2048
+// blocks, in place of a launch that scans them).
 __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* in, uint32_t* out,
                                                             uint32_t n, const uint32_t* bsums,
-                                                            uint32_t* total) {
+                                                            uint32_t* total, int raw) {
     __shared__ uint32_t wsum[kScanThreads / 64];
+    uint32_t off = 0u;
+    if (bsums && raw) {
+        uint32_t part = 0u;
+        for (uint32_t i = threadIdx.x; i < blockIdx.x; i += kScanThreads) part += bsums[i];
+        block_exclusive_scan(part, wsum, &off);
+    } else if (bsums) {
+        off = bsums[blockIdx.x];
+    }
     uint64_t base = (uint64_t)blockIdx.x * kScanBlock + (uint64_t)threadIdx.x * kScanItems;
     uint32_t x[kScanItems];
     uint32_t s = 0;
@@ -78,7 +90,6 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* in, 
     }
     uint32_t tot;
     uint32_t pre = block_exclusive_scan(s, wsum, &tot);
-    uint32_t off = bsums ? bsums[blockIdx.x] : 0u;
     pre += off;
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
@@ -106,16 +117,17 @@ void launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total,
     }
     if (n <= (uint32_t)kScanBlock) {
         hipLaunchKernelGGL(k_scan_down, dim3(1), dim3(kScanThreads), 0, s, in, out, n,
-                           (const uint32_t*)nullptr, total);
+                           (const uint32_t*)nullptr, total, 0);
         return;
     }
     uint32_t nb = (n + kScanBlock - 1) / kScanBlock;
     uint32_t* bs = scratch;
     uint32_t* rest = scratch + ((nb + 63) / 64) * 64;
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, s, in, n, bs);
-    launch_scan(bs, bs, nb, nullptr, rest, s);
+    const int raw = nb <= (uint32_t)kScanBlock ? 1 : 0;
+    if (!raw) launch_scan(bs, bs, nb, nullptr, rest, s);
     hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kScanThreads), 0, s, in, out, n,
-                       (const uint32_t*)bs, total);
+                       (const uint32_t*)bs, total, raw);
 }
 
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, uint64_t n) {
