@@ -168,8 +168,9 @@ __global__ __launch_bounds__(256) void k_fold_solve(const ViewInfo* __restrict__
             load_group(v0 + kGroup, nV, nS);
 #pragma unroll
             for (int u = 0; u < kGroup; u += 2) {
-                // two views at once: independent SH evaluations
-                float phf[2][NB];
+                // two views at once: independent SH evaluations, in FP64 (as
+                // fast as FP32 here, and no widening of the 16 values)
+                double phd[2][NB];
                 double Vd[2];
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
@@ -180,8 +181,9 @@ __global__ __launch_bounds__(256) void k_fold_solve(const ViewInfo* __restrict__
                     const float dy = my - (float)views[vv].centre[1];
                     const float dz = mz - (float)views[vv].centre[2];
                     const float inv = rsqrtf(dx * dx + dy * dy + dz * dz);
-                    sh_eval<float, L>(dx * inv, dy * inv, dz * inv, phf[h]);
+                    sh_eval<double, L>((double)(dx * inv), (double)(dy * inv), (double)(dz * inv), phd[h]);
                     Vd[h] = use ? (double)cV[u + h] : 0.0;
+                    // unused views add nothing to B (their sums read as 0)
 #pragma unroll
                     for (int c = 0; c < 4; ++c) cS[u + h][c] = use ? cS[u + h][c] : 0.0f;
                 }
@@ -189,20 +191,19 @@ __global__ __launch_bounds__(256) void k_fold_solve(const ViewInfo* __restrict__
                 for (int k = 0; k < RPL; ++k) {
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
-                        double own = sel[0] * (double)phf[h][4 * k];
+                        double own = sel[0] * phd[h][4 * k];
 #pragma unroll
                         for (int e = 1; e < 4; ++e)
-                            if (4 * k + e < NB) own = fma(sel[e], (double)phf[h][4 * k + e < NB ? 4 * k + e : 0], own);
+                            if (4 * k + e < NB) own = fma(sel[e], phd[h][4 * k + e < NB ? 4 * k + e : 0], own);
                         if (firstc) {
                             const double vo = Vd[h] * own;
 #pragma unroll
                             for (int j = 0; j < NB; ++j)
-                                if (j < 4 * k + 4) accA[k][j] = fma(vo, (double)phf[h][j], accA[k][j]);
+                                if (j < 4 * k + 4) accA[k][j] = fma(vo, phd[h][j], accA[k][j]);
                         }
                         if constexpr (!ADJ) {
-                            const double ow = Vd[h] != 0.0 ? own : 0.0;
 #pragma unroll
-                            for (int c = 0; c < 4; ++c) accB[k][c] = fma(ow, (double)cS[u + h][c], accB[k][c]);
+                            for (int c = 0; c < 4; ++c) accB[k][c] = fma(own, (double)cS[u + h][c], accB[k][c]);
                         }
                     }
                 }
