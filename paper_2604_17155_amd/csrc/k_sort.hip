@@ -14,9 +14,9 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanBlock = kScanThreads * kScanItems;  // 2048
 
-constexpr int kRsThreads = 256;
+constexpr int kRsThreads = 512;
 constexpr int kRsItems = 16;
-constexpr int kRsTile = kRsThreads * kRsItems;  // 4096
+constexpr int kRsTile = kRsThreads * kRsItems;  // 8192: runs of ~32 keys per digit
 constexpr int kRsWaves = kRsThreads / 64;
 
 __device__ inline uint32_t wave_inclusive_scan(uint32_t v) {
@@ -29,7 +29,8 @@ __device__ inline uint32_t wave_inclusive_scan(uint32_t v) {
     return v;
 }
 
-// Exclusive scan over the 256 threads of a block; returns the block total in *total.
+// Exclusive scan over the NT threads of a block; returns the block total in *total.
+template <int NT = kScanThreads>
 __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* wsum, uint32_t* total) {
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint32_t inc = wave_inclusive_scan(v);
@@ -37,7 +38,7 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* wsum, uint
     __syncthreads();
     uint32_t off = 0, all = 0;
 #pragma unroll
-    for (int k = 0; k < kScanThreads / 64; ++k) {
+    for (int k = 0; k < NT / 64; ++k) {
         uint32_t s = wsum[k];
         if (k < w) off += s;
         all += s;
@@ -147,7 +148,7 @@ void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
 
 // ---- radix sort ----------------------------------------------------------
 
-// Digit histogram of one 4096-key tile, written digit-major: hist[d * nblocks + b].
+// Digit histogram of one 8192-key tile, written digit-major: hist[d * nblocks + b].
 // n_dev (optional): the live key count, read on the device and clamped to n;
 // the grid is sized for n.
 __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint32_t* __restrict__ keys, uint32_t n,
@@ -167,16 +168,18 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint32_t* __restri
     }
     __syncthreads();
     uint32_t d = threadIdx.x;
+    if (d >= 256u) return;
     uint32_t sum = 0;
 #pragma unroll
     for (int k = 0; k < kRsWaves; ++k) sum += h[k][d];
     hist[(uint64_t)d * nblocks + blockIdx.x] = sum;
 }
 
-// Stable scatter of one 4096-key tile.  Each wave ranks its 1024 keys (16
-// rounds of 64) against per-wave digit counters in LDS, with no block
-// barrier; the four waves' counts then give every key its position in the
-// tile sorted by digit.  The tile is reordered through LDS and written out in
+// Stable scatter of one 8192-key tile (512 threads, 74 KB of LDS: two blocks
+// and sixteen waves per CU).  Each wave ranks its 1024 keys (16 rounds of 64)
+// against per-wave digit counters in LDS, with no block barrier; the eight
+// waves' counts then give every key its position in the tile sorted by digit
+// (threads 0..255 own one digit each).  The tile is reordered through LDS and written out in
 // digit order, so each digit's run of keys is stored contiguously at the
 // offset the scanned digit-major histogram gives this tile.
 __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* __restrict__ keys_in,
@@ -196,7 +199,7 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* __res
     __shared__ uint32_t sval[kRsTile];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int k = lane; k < 256; k += 64) wcnt[w][k] = 0u;
-    gbase[threadIdx.x] = offs[(uint64_t)threadIdx.x * nblocks + blockIdx.x];
+    if (threadIdx.x < 256) gbase[threadIdx.x] = offs[(uint64_t)threadIdx.x * nblocks + blockIdx.x];
     const uint64_t tile0 = (uint64_t)blockIdx.x * kRsTile;
     const uint64_t base = tile0 + (uint64_t)w * (kRsTile / kRsWaves);
     uint32_t kk[kRsItems], vv[kRsItems], rk[kRsItems];
@@ -228,14 +231,17 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* __res
         // thread t owns digit t: prefix over the waves, then over the digits
         const uint32_t t = threadIdx.x;
         uint32_t run = 0;
+        if (t < 256) {
 #pragma unroll
-        for (int k = 0; k < kRsWaves; ++k) {
-            const uint32_t c = wcnt[k][t];
-            wcnt[k][t] = run;
-            run += c;
+            for (int k = 0; k < kRsWaves; ++k) {
+                const uint32_t c = wcnt[k][t];
+                wcnt[k][t] = run;
+                run += c;
+            }
         }
         uint32_t tot;
-        dstart[t] = block_exclusive_scan(run, wsum, &tot);
+        const uint32_t ds = block_exclusive_scan<kRsThreads>(run, wsum, &tot);
+        if (t < 256) dstart[t] = ds;
     }
     __syncthreads();
 #pragma unroll
