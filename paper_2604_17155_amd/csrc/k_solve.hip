@@ -402,7 +402,9 @@ void launch_fold_solve(const ViewInfo* views, int n_views, const float* means, c
     for (int i = 0; i < kMaxNb; ++i) lam.v[i] = 0.0;
     int nb = (sh_deg + 1) * (sh_deg + 1);
     for (int i = 0; i < nb; ++i) lam.v[i] = lam_nb[i];
-    dim3 grid((unsigned)((N + 63) / 64)), block(256);
+    // one wave (16 Gaussians) per block: at one wave per SIMD a block then
+    // starts on any free SIMD, not only when four are free on one CU
+    dim3 grid((unsigned)((N + 15) / 16)), block(64);
     const float* nf = nullptr;
     float* nw = nullptr;
     switch (sh_deg) {
@@ -448,7 +450,9 @@ void launch_adjoint_solve(const ViewInfo* views, int n_views, const float* means
     for (int i = 0; i < kMaxNb; ++i) lam.v[i] = 0.0;
     int nb = (sh_deg + 1) * (sh_deg + 1);
     for (int i = 0; i < nb; ++i) lam.v[i] = lam_nb[i];
-    dim3 grid((unsigned)((N + 63) / 64)), block(256);
+    // one wave (16 Gaussians) per block: at one wave per SIMD a block then
+    // starts on any free SIMD, not only when four are free on one CU
+    dim3 grid((unsigned)((N + 15) / 16)), block(64);
     uint8_t* ns = nullptr;
     float* nw = nullptr;
     unsigned int* ni = nullptr;
