@@ -151,6 +151,11 @@ typedef struct {
                            a work queue).  The result does not depend
                            on it beyond the order of floating-point atomic
                            additions. */
+    uint32_t profile_stages; /* GSC_FLAG_PROFILE: the stages to time, bit s for
+                                stage s (GSC_STAGE_*); 0 times every stage.
+                                Each timed stage adds an event pair to the
+                                stream, so a caller timing the whole call can
+                                keep to the stages it needs. */
 } gsc_options;
 
 enum { GSC_SCHEDULE_AUTO = 0, GSC_SCHEDULE_GRID = 1, GSC_SCHEDULE_LONGEST_FIRST = 2 };

@@ -148,6 +148,7 @@ struct StageTimer {
     hipEvent_t a = nullptr;
     StageTimer(gsc_ctx* c, hipStream_t st, int stg, uint32_t n = 1) : ctx(c), s(st), stage(stg), launches(n) {
         if (!(ctx->opt.flags & GSC_FLAG_PROFILE)) return;
+        if (ctx->opt.profile_stages != 0u && !((ctx->opt.profile_stages >> (stg & 31)) & 1u)) return;
         a = take();
         if (a) (void)hipEventRecord(a, s);
     }
@@ -796,6 +797,7 @@ gsc_status gsc_default_options(gsc_options* out) {
     out->bin_size = 0;
     out->accumulate_variant = 0;
     out->schedule = GSC_SCHEDULE_AUTO;
+    out->profile_stages = 0u;
     return GSC_OK;
 }
 

@@ -128,6 +128,7 @@ def test_default_options_values(lib):
     o = gsc.default_options()
     assert o.accumulate_variant == 0 and o.bin_size == 0
     assert o.schedule == gsc.GSC_SCHEDULE_AUTO
+    assert o.profile_stages == 0
     assert o.alpha_min == np.float32(1 / 255)
     assert o.alpha_max == np.float32(0.99)
     assert o.t_min == np.float32(1e-4)
