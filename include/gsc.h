@@ -156,6 +156,18 @@ typedef struct {
                                 Each timed stage adds an event pair to the
                                 stream, so a caller timing the whole call can
                                 keep to the stages it needs. */
+    uint32_t batch_items;    /* 0, or at most 2^26: (view, Gaussian) items per view
+                                batch.  Views are binned and blended in batches
+                                of consecutive views whose items stay within
+                                this bound (a view with more items forms a batch
+                                of its own); 0 = 2^26.  Smaller batches need less
+                                scratch and take more launches.  The result does
+                                not depend on it. */
+    uint32_t batch_pairs;    /* 0, or at most 2^31 - 1: (bin, item) pairs per view
+                                batch.  A batch of several views whose pairs
+                                exceed it is split in halves until they fit or
+                                it holds one view; 0 = 2^31 - 1, the limit of a
+                                single view.  The result does not depend on it. */
 } gsc_options;
 
 enum { GSC_SCHEDULE_AUTO = 0, GSC_SCHEDULE_GRID = 1, GSC_SCHEDULE_LONGEST_FIRST = 2 };

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <memory>
 #include <string>
 #include <vector>
@@ -73,6 +74,14 @@ constexpr uint64_t kMaxItemsPerBatch = 1ull << 26;
 // Upper bound on (tile, item) pairs per batch (uint32 offsets).
 constexpr uint64_t kMaxPairsPerBatch = 1ull << 31;
 
+// The batch bounds of a set of options (gsc_options.batch_items / batch_pairs).
+inline uint64_t batch_item_limit(const gsc_options& o) {
+    return o.batch_items ? (uint64_t)o.batch_items : kMaxItemsPerBatch;
+}
+inline uint64_t batch_pair_limit(const gsc_options& o) {
+    return o.batch_pairs ? (uint64_t)o.batch_pairs : kMaxPairsPerBatch - 1;
+}
+
 }  // namespace
 
 // What a binning depends on: the geometry arrays (by address; their contents
@@ -124,11 +133,13 @@ struct gsc_ctx {
     size_t ev_used = 0;
     struct Mark { int stage; hipEvent_t a, b; uint32_t launches; };
     std::vector<Mark> marks;
+    std::array<DevBuf*, 25> bufs() {
+        return {&views, &views_all, &cov, &keys, &vals, &keys_alt, &vals_alt, &counts,
+                &offsets, &rec0, &rec1, &rec2, &sort_scratch, &pkeys, &pvals, &pkeys_alt,
+                &pvals_alt, &ranges, &vs, &gamma, &bbar, &misc, &order, &queues, &coef_t};
+    }
     ~gsc_ctx() {
-        DevBuf* all[] = {&views, &views_all, &cov, &keys, &vals, &keys_alt, &vals_alt, &counts,
-                         &offsets, &rec0, &rec1, &rec2, &sort_scratch, &pkeys, &pvals, &pkeys_alt,
-                         &pvals_alt, &ranges, &vs, &gamma, &bbar, &misc, &order, &queues, &coef_t};
-        for (DevBuf* b : all) b->release();
+        for (DevBuf* b : bufs()) b->release();
         if (h_views) (void)hipHostFree(h_views);
         if (h_all) (void)hipHostFree(h_all);
         if (h_total) (void)hipHostFree(h_total);
@@ -193,6 +204,10 @@ gsc_status validate_options(const gsc_options* o) {
         return fail(GSC_ERR_INVALID_ARG, "accumulate_variant %d is not a variant code", o->accumulate_variant);
     if (!(o->schedule >= GSC_SCHEDULE_AUTO && o->schedule <= GSC_SCHEDULE_LONGEST_FIRST))
         return fail(GSC_ERR_INVALID_ARG, "schedule must be 0, 1 or 2");
+    if ((uint64_t)o->batch_items > kMaxItemsPerBatch)
+        return fail(GSC_ERR_INVALID_ARG, "batch_items must be at most 2^26 (got %u)", o->batch_items);
+    if ((uint64_t)o->batch_pairs >= kMaxPairsPerBatch)
+        return fail(GSC_ERR_INVALID_ARG, "batch_pairs must be below 2^31 (got %u)", o->batch_pairs);
     return GSC_OK;
 }
 
@@ -326,7 +341,7 @@ const uint32_t* tile_order(const gsc_ctx* ctx, uint32_t n_tiles) {
 // Project, depth-sort, emit and tile-sort the views [v0, v0+nv) of `all`.
 // The batch's ViewInfo table is uploaded to ctx->views (tile_base local to
 // the batch).  Synchronises `s` once to read the pair count.
-gsc_status bin_views(gsc_ctx* ctx, const std::vector<ViewInfo>& all, int v0, int nv,
+gsc_status bin_views(gsc_ctx* ctx, const ViewInfo* all, int v0, int nv,
                      const float* means, const float* opac, int64_t N, const BlendParams& bp,
                      hipStream_t s, Binned* out) {
     ctx->order_valid = false;  // until this binning's order is built
@@ -403,8 +418,8 @@ gsc_status bin_views(gsc_ctx* ctx, const std::vector<ViewInfo>& all, int v0, int
     GSC_HIP(hipStreamSynchronize(s));
     uint64_t pairs64 = 0;
     memcpy(&pairs64, reinterpret_cast<const char*>(ctx->h_total) + 8, 8);
+    if (pairs64 > batch_pair_limit(ctx->opt) && nv > 1) return kSplit;
     if (pairs64 >= kMaxPairsPerBatch) {
-        if (nv > 1) return kSplit;
         return fail(GSC_ERR_CAPACITY, "one view produces %llu tile pairs (limit %llu)",
                     (unsigned long long)pairs64, (unsigned long long)kMaxPairsPerBatch);
     }
@@ -447,9 +462,10 @@ gsc_status bin_views(gsc_ctx* ctx, const std::vector<ViewInfo>& all, int v0, int
 }
 
 // Run `body(v0, nv, binned)` over consecutive view batches.  A batch holds at
-// most kMaxItemsPerBatch items; a batch whose tile pairs overflow is halved.
+// most batch_item_limit() items (or one view); a batch of several views whose
+// tile pairs exceed batch_pair_limit() is halved.
 template <typename Body>
-gsc_status for_view_batches(gsc_ctx* ctx, const std::vector<ViewInfo>& all, int n_cams,
+gsc_status for_view_batches(gsc_ctx* ctx, const ViewInfo* all, int n_cams,
                             const float* means, const float* opac, int64_t N, const BlendParams& bp,
                             hipStream_t s, Body body, const BinKey* key = nullptr, bool reuse = false) {
     if (reuse) {  // the only batch of the previous call is still in place
@@ -464,7 +480,7 @@ gsc_status for_view_batches(gsc_ctx* ctx, const std::vector<ViewInfo>& all, int 
         ctx->stats.view_batches += 1;
         return GSC_OK;
     }
-    int per = (int)std::max<int64_t>(1, (int64_t)(kMaxItemsPerBatch / (uint64_t)std::max<int64_t>(N, 1)));
+    int per = (int)std::max<int64_t>(1, (int64_t)(batch_item_limit(ctx->opt) / (uint64_t)std::max<int64_t>(N, 1)));
     int v = 0, batches = 0;
     ctx->cache_valid = false;
     Binned last;
@@ -497,7 +513,7 @@ gsc_status for_view_batches(gsc_ctx* ctx, const std::vector<ViewInfo>& all, int 
 }
 
 template <typename Body>
-gsc_status for_view_batches_k(gsc_ctx* ctx, const std::vector<ViewInfo>& all, int n_cams,
+gsc_status for_view_batches_k(gsc_ctx* ctx, const ViewInfo* all, int n_cams,
                               const float* means, const float* opac, int64_t N, const BlendParams& bp,
                               hipStream_t s, const BinKey* key, bool reuse, Body body) {
     return for_view_batches(ctx, all, n_cams, means, opac, N, bp, s, body, key, reuse);
@@ -562,8 +578,7 @@ gsc_status ensure_common(gsc_ctx* ctx, const float* means, const float* scales,
 
 // Upload the full camera table to ctx->views_all (used where the views of all
 // batches are needed at once: the fold over views).
-gsc_status upload_all_views(gsc_ctx* ctx, const std::vector<ViewInfo>& all, hipStream_t s) {
-    const int n_cams = (int)all.size();
+gsc_status upload_all_views(gsc_ctx* ctx, const ViewInfo* all, int n_cams, hipStream_t s) {
     if (n_cams == 0) return GSC_OK;
     if ((size_t)n_cams > ctx->h_all_cap) {
         if (ctx->h_all) GSC_HIP(hipHostFree(ctx->h_all));
@@ -798,6 +813,8 @@ gsc_status gsc_default_options(gsc_options* out) {
     out->accumulate_variant = 0;
     out->schedule = GSC_SCHEDULE_AUTO;
     out->profile_stages = 0u;
+    out->batch_items = 0u;
+    out->batch_pairs = 0u;
     return GSC_OK;
 }
 
@@ -827,13 +844,16 @@ gsc_status gsc_ctx_set_options(gsc_ctx* ctx, const gsc_options* opt) {
     return GSC_OK;
 }
 
-gsc_status gsc_colorize_ex(gsc_ctx* ctx, const float* means, const float* scales,
-                           const float* quats, const float* opacities, int64_t N,
-                           const gsc_camera* cams, int32_t n_cams, const void* targets,
-                           int32_t tdtype, int32_t C, int32_t sh_deg, const float* lambda,
-                           int32_t n_lambda, float* coeffs, uint8_t* status,
-                           const gsc_extras* extras, gsc_stream_t stream) {
-    if (!ctx) return fail(GSC_ERR_INVALID_ARG, "null ctx");
+}  // extern "C"
+
+namespace {
+
+// Validation shared by the colorize entry points.
+gsc_status validate_colorize(const float* means, const float* scales, const float* quats,
+                             const float* opacities, int64_t N, const gsc_camera* cams,
+                             int32_t n_cams, const void* targets, int32_t tdtype, int32_t C,
+                             int32_t sh_deg, const float* lambda, int32_t n_lambda, float* coeffs,
+                             double* lam) {
     int64_t rows = 0;
     gsc_status st = validate_geometry(means, scales, quats, opacities, N, cams, n_cams, &rows);
     if (st != GSC_OK) return st;
@@ -841,21 +861,23 @@ gsc_status gsc_colorize_ex(gsc_ctx* ctx, const float* means, const float* scales
     if (tdtype != GSC_F32 && tdtype != GSC_BF16) return fail(GSC_ERR_INVALID_ARG, "tdtype must be GSC_F32 or GSC_BF16");
     if (rows > 0 && !targets) return fail(GSC_ERR_INVALID_ARG, "targets is null");
     if (N > 0 && !coeffs) return fail(GSC_ERR_INVALID_ARG, "coeffs is null");
-    double lam[kMaxNb];
-    if ((st = expand_lambda(lambda, n_lambda, sh_deg, lam)) != GSC_OK) return st;
-    if (ctx->opt.flags & GSC_FLAG_VALIDATE_ONLY) return GSC_OK;
+    return expand_lambda(lambda, n_lambda, sh_deg, lam);
+}
 
-    hipStream_t s = (hipStream_t)stream;
-    memset(&ctx->stats, 0, sizeof(ctx->stats));
-    if (N == 0) return GSC_OK;
+// The colorize pipeline on validated arguments (N > 0).  `all` holds n_cams
+// view slots, filled here.  key / reuse: binning reuse (key may be null).
+gsc_status colorize_core(gsc_ctx* ctx, const float* means, const float* scales,
+                         const float* quats, const float* opacities, int64_t N,
+                         const gsc_camera* cams, int32_t n_cams, const void* targets,
+                         int32_t tdtype, int32_t C, int32_t sh_deg, const double* lam,
+                         float* coeffs, uint8_t* status, const gsc_extras* extras, hipStream_t s,
+                         const BinKey* key, bool reuse, ViewInfo* all) {
+    gsc_status st;
     float* x_sums = extras ? extras->view_sums : nullptr;
     float* x_vis = extras ? extras->visibility : nullptr;
     uint32_t* x_cnt = extras ? extras->counts : nullptr;
     BlendParams bp = blend_params(ctx->opt);
-    const BinKey key = make_key(ctx, means, scales, quats, opacities, N, cams, n_cams, bp);
-    const bool reuse = can_reuse(ctx, key);
     if ((st = ensure_common(ctx, means, scales, quats, opacities, N, cams, n_cams, s, reuse)) != GSC_OK) return st;
-    std::vector<ViewInfo> all(n_cams);
     for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j], j, N, ctx->bin);
     const bool per_view = sh_deg > 0 || x_sums != nullptr;
     const uint64_t vs_words = (uint64_t)(per_view ? std::max(n_cams, 1) : 1) * (uint64_t)N * (uint64_t)(C + 1);
@@ -863,7 +885,7 @@ gsc_status gsc_colorize_ex(gsc_ctx* ctx, const float* means, const float* scales
     launch_fill_u32(ctx->vs.as<uint32_t>(), 0u, vs_words, s);
     if (x_cnt) launch_fill_u32(x_cnt, 0u, (uint64_t)N, s);
     unsigned long long* d_counter = reinterpret_cast<unsigned long long*>(ctx->misc.p);
-    st = for_view_batches_k(ctx, all, n_cams, means, opacities, N, bp, s, &key, reuse,
+    st = for_view_batches_k(ctx, all, n_cams, means, opacities, N, bp, s, key, reuse,
                           [&](int v0, int nv, const Binned& bn) -> gsc_status {
         const int chunk = resolve_chunk(ctx->opt.accumulate_variant, C, tdtype);
         StageTimer t(ctx, s, GSC_STAGE_BLEND, (uint32_t)accumulate_launches(C, chunk));
@@ -889,7 +911,7 @@ gsc_status gsc_colorize_ex(gsc_ctx* ctx, const float* means, const float* scales
     if (x_sums && n_cams > 0)
         GSC_HIP(hipMemcpyAsync(x_sums, ctx->vs.p, 4 * vs_words, hipMemcpyDeviceToDevice, s));
     // fold + solve needs the full camera table (only the camera centres are used)
-    if (per_view && (st = upload_all_views(ctx, all, s)) != GSC_OK) return st;
+    if (per_view && (st = upload_all_views(ctx, all, n_cams, s)) != GSC_OK) return st;
     float* dc_scratch = nullptr;
     if (sh_deg == 0 && per_view) {
         GSC_HIP(ctx->gamma.ensure(4 * (size_t)N * (size_t)(C + 1)));
@@ -903,6 +925,32 @@ gsc_status gsc_colorize_ex(gsc_ctx* ctx, const float* means, const float* scales
     GSC_LAUNCHED("fold/solve");
     ctx->stats_pending = true;
     return GSC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gsc_status gsc_colorize_ex(gsc_ctx* ctx, const float* means, const float* scales,
+                           const float* quats, const float* opacities, int64_t N,
+                           const gsc_camera* cams, int32_t n_cams, const void* targets,
+                           int32_t tdtype, int32_t C, int32_t sh_deg, const float* lambda,
+                           int32_t n_lambda, float* coeffs, uint8_t* status,
+                           const gsc_extras* extras, gsc_stream_t stream) {
+    if (!ctx) return fail(GSC_ERR_INVALID_ARG, "null ctx");
+    double lam[kMaxNb];
+    gsc_status st = validate_colorize(means, scales, quats, opacities, N, cams, n_cams, targets,
+                                      tdtype, C, sh_deg, lambda, n_lambda, coeffs, lam);
+    if (st != GSC_OK) return st;
+    if (ctx->opt.flags & GSC_FLAG_VALIDATE_ONLY) return GSC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    memset(&ctx->stats, 0, sizeof(ctx->stats));
+    if (N == 0) return GSC_OK;
+    const BinKey key = make_key(ctx, means, scales, quats, opacities, N, cams, n_cams, blend_params(ctx->opt));
+    const bool reuse = can_reuse(ctx, key);
+    std::vector<ViewInfo> all(std::max(n_cams, 1));
+    return colorize_core(ctx, means, scales, quats, opacities, N, cams, n_cams, targets, tdtype, C,
+                         sh_deg, lam, coeffs, status, extras, s, &key, reuse, all.data());
 }
 
 gsc_status gsc_colorize(gsc_ctx* ctx, const float* means, const float* scales, const float* quats,
@@ -940,7 +988,7 @@ gsc_status gsc_render(gsc_ctx* ctx, const float* means, const float* scales, con
     GSC_HIP(ctx->coef_t.ensure(4 * (size_t)std::max<int64_t>(N, 1) * (size_t)kc));
     launch_transpose(coeffs, N, kc, ctx->coef_t.as<float>(), s);
     GSC_LAUNCHED("transpose");
-    st = for_view_batches_k(ctx, all, n_cams, means, opacities, N, bp, s, &key, reuse,
+    st = for_view_batches_k(ctx, all.data(), n_cams, means, opacities, N, bp, s, &key, reuse,
                           [&](int v0, int nv, const Binned& bn) -> gsc_status {
         (void)v0;
         StageTimer t(ctx, s, GSC_STAGE_BLEND, 1 + (uint32_t)((C + 3) / 4));
@@ -996,7 +1044,7 @@ gsc_status gsc_colorize_backward(gsc_ctx* ctx, const float* means, const float* 
     launch_fill_u32(ctx->vs.as<uint32_t>(), 0u, v_words, s);
     unsigned long long* d_counter = reinterpret_cast<unsigned long long*>(ctx->misc.p);
     Binned last;
-    st = for_view_batches_k(ctx, all, n_cams, means, opacities, N, bp, s, &key, reuse,
+    st = for_view_batches_k(ctx, all.data(), n_cams, means, opacities, N, bp, s, &key, reuse,
                           [&](int v0, int nv, const Binned& bn) -> gsc_status {
         StageTimer t(ctx, s, GSC_STAGE_BLEND);
         (void)v0;
@@ -1011,7 +1059,7 @@ gsc_status gsc_colorize_backward(gsc_ctx* ctx, const float* means, const float* 
     if (st != GSC_OK) return st;
     const gsc_stats pass1 = ctx->stats;
     // 2. Bbar = (A + w Lambda)^{-1} dL/dc and rho
-    if (per_view && (st = upload_all_views(ctx, all, s)) != GSC_OK) return st;
+    if (per_view && (st = upload_all_views(ctx, all.data(), n_cams, s)) != GSC_OK) return st;
     const size_t nbc = (size_t)N * nb * C;
     GSC_HIP(ctx->bbar.ensure(4 * (nbc + (size_t)N) + 4 * (size_t)N));
     float* d_bbar = ctx->bbar.as<float>();
@@ -1048,7 +1096,7 @@ gsc_status gsc_colorize_backward(gsc_ctx* ctx, const float* means, const float* 
     if (pass1.view_batches == 1) {
         st = body(0, n_cams, last);  // the binning of the only batch is still in place
     } else {
-        st = for_view_batches(ctx, all, n_cams, means, opacities, N, bp, s, body, &key, false);
+        st = for_view_batches(ctx, all.data(), n_cams, means, opacities, N, bp, s, body, &key, false);
     }
     if (st != GSC_OK) return st;
     ctx->stats.pairs = pass1.pairs;
@@ -1095,7 +1143,7 @@ gsc_status gsc_render_backward(gsc_ctx* ctx, const float* means, const float* sc
         launch_transpose(coeffs, N, nb * C, ctx->coef_t.as<float>(), s);
         GSC_LAUNCHED("transpose");
     }
-    st = for_view_batches_k(ctx, all, n_cams, means, opacities, N, bp, s, &key, reuse,
+    st = for_view_batches_k(ctx, all.data(), n_cams, means, opacities, N, bp, s, &key, reuse,
                           [&](int v0, int nv, const Binned& bn) -> gsc_status {
         if (grad_coeffs) {
             // dL/dc folds sum_p w (dL/dimages_p) per (view, Gaussian): the
@@ -1126,7 +1174,7 @@ gsc_status gsc_render_backward(gsc_ctx* ctx, const float* means, const float* sc
     });
     if (st != GSC_OK) return st;
     if (grad_coeffs) {
-        if (per_view && (st = upload_all_views(ctx, all, s)) != GSC_OK) return st;
+        if (per_view && (st = upload_all_views(ctx, all.data(), n_cams, s)) != GSC_OK) return st;
         StageTimer t(ctx, s, GSC_STAGE_SOLVE);
         launch_fold_rhs(ctx->views_all.as<ViewInfo>(), n_cams, means, ctx->vs.as<float>(), per_view, N,
                         C, sh_deg, grad_coeffs, s);
@@ -1215,7 +1263,7 @@ gsc_status gsc_plan_create(gsc_ctx* ctx, const gsc_scene* scenes, int32_t n_scen
         int v0 = 0;
         for (int v = 0; v < (int)P->views.size(); ++v) {
             const uint64_t ni = P->views[v].n_gauss, nt = (uint64_t)P->views[v].tiles_x * P->views[v].tiles_y;
-            if (v > v0 && (items + ni > kMaxItemsPerBatch || tiles + nt >= (1ull << 31))) {
+            if (v > v0 && (items + ni > batch_item_limit(ctx->opt) || tiles + nt >= (1ull << 31))) {
                 P->batches.push_back({v0, v - v0, 0, 0, 0, 0});
                 v0 = v;
                 items = tiles = 0;
@@ -1249,7 +1297,7 @@ gsc_status gsc_plan_create(gsc_ctx* ctx, const gsc_scene* scenes, int32_t n_scen
     for (size_t k = 0; k < P->batches.size();) {
         uint64_t pairs = 0;
         if ((st = plan_count_pairs(P, P->batches[k], s, &pairs)) != GSC_OK) return st;
-        if (pairs >= kMaxPairsPerBatch) {
+        if (pairs >= kMaxPairsPerBatch || (pairs > batch_pair_limit(ctx->opt) && P->batches[k].nv > 1)) {
             gsc_plan::Batch b = P->batches[k];
             if (b.nv == 1) return fail(GSC_ERR_CAPACITY, "one view produces %llu tile pairs", (unsigned long long)pairs);
             const int h = b.nv / 2;

@@ -42,7 +42,8 @@ class GscOptions(ct.Structure):
                 ("sigma_cut", ct.c_float), ("dilation", ct.c_float), ("znear", ct.c_float),
                 ("kappa_max", ct.c_float), ("flags", ct.c_int32), ("bin_size", ct.c_int32),
                 ("accumulate_variant", ct.c_int32), ("schedule", ct.c_int32),
-                ("profile_stages", ct.c_uint32)]
+                ("profile_stages", ct.c_uint32), ("batch_items", ct.c_uint32),
+                ("batch_pairs", ct.c_uint32)]
 
 
 GSC_SCHEDULE_AUTO, GSC_SCHEDULE_GRID, GSC_SCHEDULE_LONGEST_FIRST = 0, 1, 2

@@ -204,3 +204,19 @@ def test_plan_validation(lib):
     assert create([(0, 10, 0, 2)], C=65) == gsc.GSC_ERR_INVALID_ARG
     assert create([(0, 10, 0, 2)], sh_deg=4) == gsc.GSC_ERR_INVALID_ARG
     assert lib.gsc_colorize_batched(None, FAKE, 0, None, 1, FAKE, None, None) == gsc.GSC_ERR_INVALID_ARG
+
+
+def test_batch_limit_options(lib):
+    o = gsc.default_options()
+    assert o.batch_items == 0 and o.batch_pairs == 0
+    for over, ok in [(dict(batch_items=1), True), (dict(batch_items=1 << 26), True),
+                     (dict(batch_items=(1 << 26) + 1), False), (dict(batch_pairs=5), True),
+                     (dict(batch_pairs=(1 << 31) - 1), True), (dict(batch_pairs=1 << 31), False)]:
+        o = gsc.default_options()
+        for k, v in over.items():
+            setattr(o, k, v)
+        h = ct.c_void_p()
+        st = lib.gsc_ctx_create(ct.byref(h), ct.byref(o))
+        assert (st == gsc.GSC_OK) == ok, over
+        if st == gsc.GSC_OK:
+            lib.gsc_ctx_destroy(h)
