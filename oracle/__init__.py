@@ -48,28 +48,66 @@ class OcCamera(ct.Structure):
 class OcOptions(ct.Structure):
     _fields_ = [("alpha_min", ct.c_float), ("alpha_max", ct.c_float), ("t_min", ct.c_float),
                 ("sigma_cut", ct.c_float), ("dilation", ct.c_float), ("znear", ct.c_float),
-                ("eps_q", ct.c_double), ("eps_a", ct.c_double), ("eps_t", ct.c_double)]
+                ("eps_q", ct.c_double), ("eps_a", ct.c_double), ("eps_t", ct.c_double),
+                ("eps_p", ct.c_double), ("p_span", ct.c_double), ("eps_cov", ct.c_double)]
+
+
+# unit roundoff of binary32 (round to nearest)
+U32 = 2.0 ** -24
 
 
 @dataclasses.dataclass
 class Options:
-    """Blending constants (3DGS conventions) and event margins.
+    """Blending constants (3DGS conventions) and the event margins.
 
     Thresholds are single-precision numbers so that both sides compare against
-    the identical threshold value."""
+    the identical threshold value.
+
+    The margins model an implementation that evaluates the pixel decisions in
+    binary32 from a projection computed in binary64 (see gsc_oracle.c,
+    oc_options).  Each is the worst-case count of roundings it covers, in
+    units of u = 2^-24 (a rounding moves a value by at most u of it), times
+    a safety factor of about 1.5:
+      eps_q    6u  q: conic rounded once, a*dx*dx (two), b*dx (one), two fused
+                   adds: at most 4u of the sum of the terms' magnitudes (a
+                   binary32 emulation without fused adds peaked at 4.3u);
+      eps_p  4.5u  pixel offsets (tile centre point - centre_hi) - centre_lo
+                   + (pixel - centre point): three roundings per axis of
+                   quantities of at most |d| + 7.5 pixels, so at most
+                   u (3 |d| + 15), taken as eps_p (|d| + p_span), p_span = 5;
+      eps_cov 1e-14  the 3D covariance R diag(s^2) R^T is formed in binary64
+                   (its error is then a few units of 2^-53), against the bound
+                   s_max sqrt(q) |v| + sum_k s_k^2 ((|R|^T|v|)_k)^2 of
+                   gsc_oracle.c.  (A binary32 covariance would need about
+                   20u: a binary32 emulation on the reduced relighting scene
+                   peaked at 9.3u of that bound.);
+      eps_a    4u  alpha beyond q: exp2 within one ulp (2u) and the product
+                   with the opacity (u);
+      eps_t  1.5u  one fused T (1 - alpha) update (u).
+    """
     alpha_min: float = float(np.float32(1.0 / 255.0))
     alpha_max: float = float(np.float32(0.99))
     t_min: float = float(np.float32(1e-4))
     sigma_cut: float = 3.0
     dilation: float = float(np.float32(0.3))
     znear: float = float(np.float32(0.01))
-    eps_q: float = 2e-5
-    eps_a: float = 2e-5
-    eps_t: float = 2e-5
+    eps_q: float = 6 * U32
+    eps_a: float = 4 * U32
+    eps_t: float = 1.5 * U32
+    eps_p: float = 4.5 * U32
+    p_span: float = 5.0
+    eps_cov: float = 1e-14
 
     def c(self) -> OcOptions:
         return OcOptions(self.alpha_min, self.alpha_max, self.t_min, self.sigma_cut,
-                         self.dilation, self.znear, self.eps_q, self.eps_a, self.eps_t)
+                         self.dilation, self.znear, self.eps_q, self.eps_a, self.eps_t,
+                         self.eps_p, self.p_span, self.eps_cov)
+
+    def scaled_margins(self, k: float) -> "Options":
+        """The same options with every margin multiplied by k."""
+        return dataclasses.replace(self, eps_q=self.eps_q * k, eps_a=self.eps_a * k,
+                                   eps_t=self.eps_t * k, eps_p=self.eps_p * k,
+                                   eps_cov=self.eps_cov * k)
 
 
 def _f(a):
@@ -87,8 +125,8 @@ def load():
     i64, i32 = ct.c_int64, ct.c_int
     lib.oc_sh_basis.argtypes = [i32, P, i64, P]
     lib.oc_colorize.argtypes = [P, P, P, P, i64, P, i32, P, i32, i32, i32, P, i32, P, P, P, P, P,
-                                P, P, P, P, P, P, i32]
-    lib.oc_render.argtypes = [P, P, P, P, i64, P, i32, P, i32, i32, P, P, P, i32]
+                                P, P, P, P, P, P, P, i32]
+    lib.oc_render.argtypes = [P, P, P, P, i64, P, i32, P, i32, i32, P, P, P, P, i32]
     lib.oc_colorize_backward.argtypes = [P, P, P, P, i64, P, i32, P, i32, i32, i32, P, i32, P, P,
                                          P, P, P, i32]
     lib.oc_render_backward.argtypes = [P, P, P, P, i64, P, i32, P, i32, i32, P, P, P, P, i32]
@@ -140,8 +178,10 @@ def colorize(scene, targets, want: Optional[np.ndarray] = None, opts: Optional[O
              lam=None, with_kappa: bool = False, threads=None):
     """Oracle colorization (Algorithm 1, steps 1-6).  Returns a dict with
     coeffs [N,nb,C], status, A (regularised), B, w, flip (bound on the
-    coefficient change near-threshold decisions could cause), kappa, cnt,
-    count (accepted contributions) and events."""
+    coefficient change near-threshold decisions could cause), kappa, cnt
+    (accepted contributions per Gaussian), ndec (near-threshold decisions on
+    each Gaussian's own acceptance), count (accepted contributions) and
+    events (near-threshold decisions)."""
     lib = load()
     opts = opts or Options()
     m, s, q, o = _geom(scene)
@@ -157,6 +197,7 @@ def colorize(scene, targets, want: Optional[np.ndarray] = None, opts: Optional[O
     flip = np.zeros(N, np.float64)
     kappa = np.zeros(N, np.float64) if with_kappa else None
     cnt = np.zeros(N, np.int64)
+    ndec = np.zeros(N, np.int64)
     stats = np.zeros(2, np.int64)
     wp = None
     if want is not None:
@@ -166,15 +207,18 @@ def colorize(scene, targets, want: Optional[np.ndarray] = None, opts: Optional[O
                          len(scene.cams), _f(t), td, C, scene.sh_deg, _f(lam), lam.size,
                          ct.byref(oo), None if wp is None else _f(wp), _f(coeffs), _f(status),
                          _f(A), _f(B), _f(w), _f(flip), None if kappa is None else _f(kappa),
-                         _f(cnt), _f(stats), _threads(threads))
+                         _f(cnt), _f(ndec), _f(stats), _threads(threads))
     if rc != 0:
         raise ValueError("oracle colorize rejected its arguments")
     return dict(coeffs=coeffs, status=status, A=A, B=B, w=w, flip=flip, kappa=kappa, cnt=cnt,
-                count=int(stats[0]), events=int(stats[1]))
+                ndec=ndec, count=int(stats[0]), events=int(stats[1]))
 
 
-def render(scene, coeffs, opts: Optional[Options] = None, threads=None):
-    """Oracle render (eq. 1-3) of coefficients [N,nb,C] -> images [rows, C] float64."""
+def render(scene, coeffs, opts: Optional[Options] = None, threads=None, with_bound: bool = False):
+    """Oracle render (eq. 1-3) of coefficients [N,nb,C] -> images [rows, C] float64.
+    with_bound: also return, per pixel, a bound on how far an implementation
+    within the event margins may render it away from the result (max over
+    channels)."""
     lib = load()
     opts = opts or Options()
     m, s, q, o = _geom(scene)
@@ -183,14 +227,15 @@ def render(scene, coeffs, opts: Optional[Options] = None, threads=None):
     L = int(round(np.sqrt(coeffs.shape[1]))) - 1
     cams = cameras(scene.cams)
     img = np.zeros((scene.n_pixels, C), np.float64)
+    bound = np.zeros(scene.n_pixels, np.float64) if with_bound else None
     stats = np.zeros(2, np.int64)
     oo = opts.c()
     rc = lib.oc_render(_f(m), _f(s), _f(q), _f(o), scene.N, ct.cast(cams, ct.c_void_p),
-                       len(scene.cams), _f(coeffs), C, L, ct.byref(oo), _f(img), _f(stats),
-                       _threads(threads))
+                       len(scene.cams), _f(coeffs), C, L, ct.byref(oo), _f(img),
+                       None if bound is None else _f(bound), _f(stats), _threads(threads))
     if rc != 0:
         raise ValueError("oracle render rejected its arguments")
-    return img
+    return (img, bound) if with_bound else img
 
 
 def colorize_backward(scene, targets, coeffs, grad_coeffs, opts: Optional[Options] = None,

@@ -55,9 +55,26 @@ typedef struct {
     int64_t pixel_offset;
 } oc_camera;
 
+/*
+ * Blend constants, plus a model of how far an implementation that evaluates
+ * the decision quantities in binary32 may stray from their exact values
+ * (used only to record near-threshold decisions, see blend_view):
+ *   eps_q   relative error of q = d^T Sigma_2D^{-1} d per unit of the sum of
+ *           its terms' magnitudes (conic rounded to binary32, two products
+ *           and two fused adds);
+ *   eps_p   relative error of a pixel offset d formed in binary32 from a
+ *           centre held exactly, per unit of (|d| + p_span), p_span being
+ *           the largest distance from the point the offsets are formed
+ *           against;
+ *   eps_cov relative error of the binary32 3D covariance entries per unit of
+ *           the largest squared axis scale;
+ *   eps_a   relative error of alpha beyond that inherited from q (exp and
+ *           the product with the opacity);
+ *   eps_t   relative rounding of each transmittance update T (1 - alpha).
+ */
 typedef struct {
     float alpha_min, alpha_max, t_min, sigma_cut, dilation, znear;
-    double eps_q, eps_a, eps_t;
+    double eps_q, eps_a, eps_t, eps_p, p_span, eps_cov;
 } oc_options;
 
 #define OC_MAX_NB 16
@@ -125,12 +142,15 @@ int oc_sh_basis(int L, const double* dirs, int64_t n, double* out) {
 typedef struct {
     const float* means;
     const float* opac;
+    const float* scales;
     double* cov3; /* [N][6]: xx xy xz yy yz zz */
+    double* rot;  /* [N][9]: R(q), row-major (for the covariance margin) */
     int64_t N;
 } scene_t;
 
-/* Sigma = R(q) diag(s^2) R(q)^T with q = (w,x,y,z) normalised. */
-static void covariance3d(const float* s, const float* q, double* out) {
+/* Sigma = R(q) diag(s^2) R(q)^T with q = (w,x,y,z) normalised; rot_out
+ * (9 doubles, may be NULL) receives R(q). */
+static void covariance3d(const float* s, const float* q, double* out, double* rot_out) {
     double w = q[0], x = q[1], y = q[2], z = q[3];
     double n = sqrt(w * w + x * x + y * y + z * z);
     w /= n; x /= n; y /= n; z /= n;
@@ -148,6 +168,8 @@ static void covariance3d(const float* s, const float* q, double* out) {
         }
     out[0] = S[0][0]; out[1] = S[0][1]; out[2] = S[0][2];
     out[3] = S[1][1]; out[4] = S[1][2]; out[5] = S[2][2];
+    if (rot_out)
+        for (int i = 0; i < 9; ++i) rot_out[i] = R[i / 3][i % 3];
 }
 
 typedef struct {
@@ -156,6 +178,9 @@ typedef struct {
     double u, v;       /* projected mean, pixel units */
     double ca, cb, cc; /* conic = inverse of the 2D covariance */
     double sxx, sxy, syy;
+    double JW[2][3];   /* J W: world directions -> pixels, for the covariance margin */
+    const double* rot; /* R(q) of the Gaussian */
+    double s2[3];      /* squared axis scales */
     int x0, x1, y0, y1; /* inclusive pixel range that may satisfy q <= sigma_cut^2 */
 } proj_t;
 
@@ -209,6 +234,10 @@ static void project_one(const scene_t* sc, const oc_camera* cam, const oc_option
         }
     S2[0][0] += o->dilation;
     S2[1][1] += o->dilation;
+    for (int i = 0; i < 2; ++i)
+        for (int k = 0; k < 3; ++k) P->JW[i][k] = J[i][0] * W[0][k] + J[i][1] * W[1][k] + J[i][2] * W[2][k];
+    P->rot = sc->rot + 9 * g;
+    for (int k = 0; k < 3; ++k) P->s2[k] = (double)sc->scales[3 * g + k] * sc->scales[3 * g + k];
     P->sxx = S2[0][0];
     P->sxy = 0.5 * (S2[0][1] + S2[1][0]);
     P->syy = S2[1][1];
@@ -266,9 +295,11 @@ static void push(elist_t* L, entry_t en) {
 
 /* A near-threshold decision: the weight `m` of Gaussian g at pixel (x, y)
  * may appear, vanish or be rescaled in an implementation that decides the
- * other way within rounding. */
+ * other way within rounding.  kind 0: g's own acceptance at that pixel may
+ * differ (its contribution count may change by one); kind 1: only its weight
+ * may be rescaled (an earlier decision at that pixel may differ). */
 typedef struct {
-    int32_t g, x, y;
+    int32_t g, x, y, kind;
     double m;
 } event_t;
 
@@ -277,7 +308,7 @@ typedef struct {
     int64_t n, cap;
 } evlist_t;
 
-static void push_ev(evlist_t* L, int64_t g, int x, int y, double m) {
+static void push_ev(evlist_t* L, int64_t g, int x, int y, double m, int kind) {
     if (!L) return;
     if (L->n == L->cap) {
         L->cap = L->cap ? 2 * L->cap : 256;
@@ -286,6 +317,7 @@ static void push_ev(evlist_t* L, int64_t g, int x, int y, double m) {
     L->e[L->n].g = (int32_t)g;
     L->e[L->n].x = x;
     L->e[L->n].y = y;
+    L->e[L->n].kind = kind;
     L->e[L->n].m = m;
     L->n++;
 }
@@ -323,20 +355,59 @@ static void sort_by_key(int64_t* idx, int64_t n, const proj_t* P, int64_t* tmp) 
 
 typedef struct {
     int64_t count;   /* accepted contributions */
-    int64_t events;  /* near-threshold decisions */
+    int64_t events;  /* near-threshold decisions (kind 0 events) */
 } vstats_t;
+
+/* How far a binary32 evaluation may move q and alpha at one pixel (oc_options):
+ *   q: eps_q times the sum of the magnitudes of q's terms; the pixel offset
+ *      error eps_p (|d| + p_span) per axis through dq/dd = 2 r, r = conic d;
+ *      the covariance error |r^T dSigma_2D r| = |v^T dSigma_3D v| with
+ *      v = (J W)^T r.  A rotation R + dR and rounded products give
+ *      v^T dSigma v <= 2 |dR^T v| |D R^T v| + (rounding) sum_k s_k^2 ((|R|^T |v|)_k)^2,
+ *      and |D R^T v| <= s_max sqrt(v^T Sigma v) <= s_max sqrt(q) (since
+ *      q = r^T Sigma_2D r >= v^T Sigma v); so the bound is
+ *      eps_cov (s_max sqrt(q) |v| + sum_k s_k^2 ((|R|^T |v|)_k)^2);
+ *   alpha (relative): eps_a plus half the q bound (exp(-q/2)). */
+static void pixel_margins(const proj_t* p, const oc_options* o, double dx, double dy, double q,
+                          double* mq, double* ma) {
+    double qa = fabs(p->ca * dx * dx) + 2.0 * fabs(p->cb * dx * dy) + fabs(p->cc * dy * dy);
+    double rx = p->ca * dx + p->cb * dy, ry = p->cb * dx + p->cc * dy;
+    double m = o->eps_q * qa + 2.0 * o->eps_p * (fabs(rx) * (fabs(dx) + o->p_span) +
+                                                 fabs(ry) * (fabs(dy) + o->p_span));
+    double v[3], vn = 0.0, smax = 0.0, rs = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        v[k] = p->JW[0][k] * rx + p->JW[1][k] * ry;
+        vn += v[k] * v[k];
+        smax = fmax(smax, p->s2[k]);
+    }
+    for (int k = 0; k < 3; ++k) {
+        double a = 0.0; /* (|R|^T |v|)_k */
+        for (int i = 0; i < 3; ++i) a += fabs(p->rot[3 * i + k]) * fabs(v[i]);
+        rs += p->s2[k] * a * a;
+    }
+    m += o->eps_cov * (sqrt(smax) * sqrt(fmax(q, 0.0)) * sqrt(vn) + rs);
+    *mq = m;
+    *ma = o->eps_a + 0.5 * m;
+}
 
 /*
  * Blend one view.  Appends every accepted contribution (pixel, Gaussian,
  * weight) to `out` in front-to-back order per pixel (rows ascending).
  * pix_mask (H*W bytes, may be NULL) restricts the pixels evaluated.
- * ev (may be NULL) receives the near-threshold events:
- *   - footprint or alpha-floor decision within eps of its threshold: the
- *     Gaussian's own weight there, and every later weight at that pixel
- *     rescaled by (1 - alpha) (tracked as the pixel's pending alpha mass);
- *   - stop decision within (eps_t + pending alpha mass) of T_min: the weight
- *     of the deciding Gaussian and of the next candidates at that pixel,
- *     which an implementation that decides the other way would (not) accept.
+ * ev (may be NULL) receives the decisions that an implementation evaluating
+ * q, alpha and T in binary32 (margins of oc_options) might take the other
+ * way, as events carrying the weight that could appear, vanish or be
+ * rescaled:
+ *   - footprint or alpha-floor decision within its margin: g's own weight
+ *     alpha T (kind 0); the weights of every later Gaussian at the pixel may
+ *     then be rescaled by (1 - alpha)^(+-1), tracked as the pending mass
+ *     pend = sum alpha/(1 - alpha) and recorded as (e^pend - 1) w (kind 1);
+ *   - stop decision within the transmittance margin (accumulated rounding
+ *     of T plus the pending mass): if the pixel stops here, an
+ *     implementation that does not stop accepts this and possibly further
+ *     candidates while its T stays above t_min (kind 0 each); if the pixel
+ *     goes on, an implementation may stop here, dropping this and every
+ *     later weight at the pixel (kind 0 each).
  */
 static void blend_view(const scene_t* sc, const oc_camera* cam, const oc_options* o,
                        const uint8_t* pix_mask, proj_t* P, elist_t* out, evlist_t* ev,
@@ -364,10 +435,14 @@ static void blend_view(const scene_t* sc, const oc_camera* cam, const oc_options
         const proj_t* p = &P[order[k]];
         for (int y = p->y0; y <= p->y1; ++y) rlist[fill[y]++] = order[k];
     }
+    /* per pixel of the current row */
     double* T = (double*)malloc(sizeof(double) * (size_t)W);
-    double* pend = (double*)malloc(sizeof(double) * (size_t)W);
+    double* terr = (double*)malloc(sizeof(double) * (size_t)W);  /* relative error bound of T */
+    double* pend = (double*)malloc(sizeof(double) * (size_t)W);  /* pending rescale mass */
+    double* ghostT = (double*)malloc(sizeof(double) * (size_t)W);  /* T of a walk that did not stop */
+    double* ghostM = (double*)malloc(sizeof(double) * (size_t)W);
     uint8_t* done = (uint8_t*)malloc((size_t)W);
-    uint8_t* unsure = (uint8_t*)malloc((size_t)W); /* candidates left to mark after a near stop */
+    uint8_t* fragile = (uint8_t*)malloc((size_t)W);  /* an implementation may have stopped earlier */
     double s2 = (double)o->sigma_cut * (double)o->sigma_cut;
     double amin = o->alpha_min, amax = o->alpha_max, tmin = o->t_min;
     for (int y = 0; y < H; ++y) {
@@ -380,9 +455,12 @@ static void blend_view(const scene_t* sc, const oc_camera* cam, const oc_options
         }
         for (int x = 0; x < W; ++x) {
             T[x] = 1.0;
+            terr[x] = 0.0;
             pend[x] = 0.0;
+            ghostT[x] = 0.0;
+            ghostM[x] = 0.0;
             done[x] = mrow ? (mrow[x] ? 0 : 1) : 0;
-            unsure[x] = 0;
+            fragile[x] = 0;
         }
         double py = y + 0.5;
         for (int64_t k = rcount[y]; k < rcount[y + 1]; ++k) {
@@ -391,51 +469,76 @@ static void blend_view(const scene_t* sc, const oc_camera* cam, const oc_options
             int xs = p->x0 > xlo ? p->x0 : xlo, xe = p->x1 < xhi ? p->x1 : xhi;
             double o_g = sc->opac[g];
             for (int x = xs; x <= xe; ++x) {
-                if (done[x] && !unsure[x]) continue;
+                if (done[x] && !(ghostT[x] > 0.0)) continue;
                 double dx = x + 0.5 - p->u, dy = py - p->v;
                 double q = p->ca * dx * dx + 2.0 * p->cb * dx * dy + p->cc * dy * dy;
                 double G = exp(-0.5 * q);
                 double araw = o_g * G;
                 double alpha = araw < amax ? araw : amax;
-                int may_pass = q <= s2 * (1.0 + o->eps_q) && araw >= amin * (1.0 - o->eps_a);
-                if (unsure[x] && may_pass) {
-                    push_ev(ev, g, x, y, alpha * T[x]);
-                    unsure[x]--;
+                double mq = 0.0, ma = 0.0;
+                if (ev) pixel_margins(p, o, dx, dy, q, &mq, &ma);
+                double mq_cut = mq + o->eps_q * s2; /* plus the rounding of the threshold */
+                int may_pass = q <= s2 + mq_cut && araw >= amin * (1.0 - ma);
+                if (ghostT[x] > 0.0) {
+                    /* the pixel stopped near the threshold; an implementation
+                     * that went on may accept g while its T stays above t_min */
+                    if (may_pass) {
+                        if (ghostT[x] * (1.0 - alpha) >= tmin * (1.0 - ghostM[x])) {
+                            push_ev(ev, g, x, y, alpha * ghostT[x], 0);
+                            st->events++;
+                            ghostT[x] *= 1.0 - alpha;
+                        } else {
+                            ghostT[x] = 0.0;
+                        }
+                    }
+                    continue; /* done[x] */
                 }
-                if (done[x]) continue;
-                if (fabs(q - s2) <= o->eps_q * s2 && araw >= amin * (1.0 - o->eps_a)) {
+                if (ev && fabs(q - s2) <= mq_cut && araw >= amin * (1.0 - ma)) {
                     st->events++;
-                    push_ev(ev, g, x, y, alpha * T[x]);
-                    pend[x] += alpha;
+                    push_ev(ev, g, x, y, alpha * T[x], 0);
+                    pend[x] += alpha / (1.0 - alpha);
                 }
                 if (q > s2) continue;
-                if (fabs(araw - amin) <= o->eps_a * amin) {
+                if (ev && fabs(araw - amin) <= ma * amin) {
                     st->events++;
-                    push_ev(ev, g, x, y, alpha * T[x]);
-                    pend[x] += alpha;
+                    push_ev(ev, g, x, y, alpha * T[x], 0);
+                    pend[x] += alpha / (1.0 - alpha);
                 }
                 if (alpha < amin) continue;
+                /* alpha's own error does not reach T where it is surely clamped */
+                double da = araw >= amax * (1.0 + ma) ? 0.0 : ma;
+                double terr_new = terr[x] + da * alpha / (1.0 - alpha) + o->eps_t;
+                double mrel = terr_new + expm1(pend[x]);
                 double test = T[x] * (1.0 - alpha);
-                if (fabs(test - tmin) <= (o->eps_t + pend[x]) * tmin) {
-                    st->events++;
-                    push_ev(ev, g, x, y, alpha * T[x]);
-                    unsure[x] = 2;
-                }
+                int tnear = ev && fabs(test - tmin) <= mrel * tmin;
                 if (test < tmin) {
+                    if (tnear) {
+                        st->events++;
+                        push_ev(ev, g, x, y, alpha * T[x], 0);
+                        ghostT[x] = test;
+                        ghostM[x] = mrel;
+                    }
                     done[x] = 1;
                     continue;
                 }
+                double w = alpha * T[x];
+                if (tnear || fragile[x]) {
+                    st->events++;
+                    push_ev(ev, g, x, y, w, 0);
+                    fragile[x] = 1;
+                }
+                if (pend[x] > 0.0) push_ev(ev, g, x, y, expm1(pend[x]) * w, 1);
                 entry_t en;
                 en.x = x;
                 en.g = (int32_t)g;
-                en.w = alpha * T[x];
+                en.w = w;
                 en.alpha = alpha;
                 en.G = G;
                 en.clamped = araw >= amax;
-                if (pend[x] > 0.0) push_ev(ev, g, x, y, pend[x] * en.w);
                 push(out, en);
                 st->count++;
                 T[x] = test;
+                terr[x] = terr_new;
             }
         }
         /* row marker: x of entries is within the row; encode the row by
@@ -446,7 +549,7 @@ static void blend_view(const scene_t* sc, const oc_camera* cam, const oc_options
         sentinel.g = -1;
         push(out, sentinel);
     }
-    free(T); free(pend); free(done); free(unsure);
+    free(T); free(terr); free(pend); free(ghostT); free(ghostM); free(done); free(fragile);
     free(order); free(tmp); free(rcount); free(rlist); free(fill);
 }
 
@@ -558,9 +661,12 @@ static void build_scene(scene_t* sc, const float* means, const float* scales, co
                         const float* opac, int64_t N) {
     sc->means = means;
     sc->opac = opac;
+    sc->scales = scales;
     sc->N = N;
     sc->cov3 = (double*)malloc(sizeof(double) * 6 * (size_t)(N > 0 ? N : 1));
-    for (int64_t g = 0; g < N; ++g) covariance3d(scales + 3 * g, quats + 4 * g, sc->cov3 + 6 * g);
+    sc->rot = (double*)malloc(sizeof(double) * 9 * (size_t)(N > 0 ? N : 1));
+    for (int64_t g = 0; g < N; ++g)
+        covariance3d(scales + 3 * g, quats + 4 * g, sc->cov3 + 6 * g, sc->rot + 9 * g);
 }
 
 /* Pixel mask of one view: union of the pixel ranges of the wanted Gaussians. */
@@ -588,20 +694,26 @@ static uint8_t* wanted_mask(const scene_t* sc, const oc_camera* cam, const oc_op
  * Outputs (each may be NULL except coeffs):
  *   coeffs [N][nb][C]; status [N] (bit0 unobserved, bit2 factorisation failed);
  *   A_out [N][nb][nb] regularised normal matrix; B_out [N][nb][C]; w_out [N];
- *   flip_out [N]: first-order bound on ||dc_g||_F from every near-threshold
+ *   flip_out [N]: bound on ||dc_g||_F from every near-threshold
  *   event touching g, sum_e m_e ||(A_g + w_g Lambda)^{-1} (phi (y_p - c^T phi)^T
  *   - Lambda c)||_F (a weight m added at pixel p changes B by m phi y^T and
  *   A + w Lambda by m (phi phi^T + Lambda));
+ *   the factor 1/(1 - s), s = sum_e m_e ||(A_g + w_g Lambda)^{-1}
+ *   (phi phi^T + Lambda)||, makes it hold beyond first order (infinite when
+ *   s >= 1);
  *   kappa_out [N]; cnt_out [N] accepted contributions per Gaussian;
+ *   ndec_out [N] near-threshold decisions on g's own acceptance: an
+ *   implementation within the margins accepts g exactly cnt_out[g] times
+ *   when ndec_out[g] = 0, and differs by at most ndec_out[g] otherwise;
  *   stats[0] total accepted contributions of the wanted Gaussians,
- *   stats[1] near-threshold events.
+ *   stats[1] near-threshold decisions.
  */
 int oc_colorize(const float* means, const float* scales, const float* quats, const float* opac,
                 int64_t N, const oc_camera* cams, int n_cams, const void* targets, int tdtype,
                 int C, int L, const float* lam, int n_lambda, const oc_options* o,
                 const uint8_t* want, double* coeffs, uint8_t* status, double* A_out, double* B_out,
                 double* w_out, double* flip_out, double* kappa_out, int64_t* cnt_out,
-                int64_t* stats, int n_threads) {
+                int64_t* ndec_out, int64_t* stats, int n_threads) {
     if (check_common(N, n_cams, C, L)) return -1;
     if (!(n_lambda == 1 || n_lambda == L + 1 || n_lambda == (L + 1) * (L + 1))) return -1;
     int nb = (L + 1) * (L + 1);
@@ -726,13 +838,28 @@ int oc_colorize(const float* means, const float* scales, const float* quats, con
             }
             if (kappa_out) kappa_out[g] = jacobi_cond(nb, A);
         }
+        int64_t ndec = 0;
+        for (int64_t i = ev_start[g]; i < ev_start[g + 1]; ++i) ndec += ev_all[i].kind == 0;
+        if (ndec_out) ndec_out[g] = ndec;
         if (flip_out && ev_start[g + 1] > ev_start[g]) {
             /* an event on a Gaussian the oracle sees as unobserved: its weight
              * alone would make it observed; report an unbounded effect */
             if (w == 0.0 || (stt & 4)) {
                 flip = INFINITY;
             } else {
-                double M[OC_MAX_NB * 64];
+                /* Events change the system to (A + E) c' = B + F with
+                 * E = sum +-m (phi phi^T + Lambda), F = sum +-m phi y^T, so
+                 * c' - c = (A + E)^{-1} sum +-m r,  r = phi (y - c^T phi)^T - Lambda c
+                 * (A c = B).  Hence ||c' - c|| <= sum m ||A^{-1} r|| / (1 - s)
+                 * with s = sum m ||A^{-1} (phi phi^T + Lambda)|| < 1. */
+                double M[OC_MAX_NB * 64], Lam[OC_MAX_NB * OC_MAX_NB], u[OC_MAX_NB];
+                memset(Lam, 0, sizeof(Lam));
+                for (int r = 0; r < nb; ++r) Lam[r * nb + r] = lamx[r];
+                chol_solve(nb, nb, Lm, Lam);
+                double nl = 0.0;
+                for (int i2 = 0; i2 < nb * nb; ++i2) nl += Lam[i2] * Lam[i2];
+                nl = sqrt(nl);
+                double first = 0.0, sres = 0.0;
                 for (int64_t i = ev_start[g]; i < ev_start[g + 1]; ++i) {
                     const event_t* e = &ev_all[i];
                     const oc_camera* cam = &cams[ev_view[i]];
@@ -749,8 +876,15 @@ int oc_colorize(const float* means, const float* scales, const float* quats, con
                     chol_solve(nb, C, Lm, M);
                     double mn = 0.0;
                     for (int i2 = 0; i2 < nb * C; ++i2) mn += M[i2] * M[i2];
-                    flip += e->m * sqrt(mn);
+                    first += e->m * sqrt(mn);
+                    double pn = 0.0;
+                    for (int r = 0; r < nb; ++r) { u[r] = phi[r]; pn += phi[r] * phi[r]; }
+                    chol_solve(nb, 1, Lm, u);
+                    double un = 0.0;
+                    for (int r = 0; r < nb; ++r) un += u[r] * u[r];
+                    sres += e->m * (sqrt(un) * sqrt(pn) + nl);
                 }
+                flip = sres < 1.0 ? first / (1.0 - sres) : INFINITY;
             }
         }
         if (flip_out) flip_out[g] = flip;
@@ -762,16 +896,20 @@ int oc_colorize(const float* means, const float* scales, const float* quats, con
     }
     for (int j = 0; j < n_cams; ++j) free(evs[j].e);
     free(evs); free(ev_start); free(ev_all); free(ev_view);
-    free(per_view); free(kidx); free(sc.cov3);
+    free(per_view); free(kidx); free(sc.cov3); free(sc.rot);
     return 0;
 }
 
 /* ------------------------------------------------------------------ */
 /* Render (eq. 1-3): img_p = sum_g w_gp * phi_gj^T c_g                 */
 /* ------------------------------------------------------------------ */
+/* pix_bound [rows] (may be NULL): per pixel, a bound on how far an
+ * implementation within the event margins may render that pixel away from
+ * `images` (max over channels): sum over the pixel's events of m ||gamma_g||_inf. */
 int oc_render(const float* means, const float* scales, const float* quats, const float* opac,
               int64_t N, const oc_camera* cams, int n_cams, const double* coeffs, int C, int L,
-              const oc_options* o, double* images, int64_t* stats, int n_threads) {
+              const oc_options* o, double* images, double* pix_bound, int64_t* stats,
+              int n_threads) {
     if (check_common(N, n_cams, C, L)) return -1;
     int nb = (L + 1) * (L + 1);
     scene_t sc;
@@ -803,10 +941,22 @@ int oc_render(const float* means, const float* scales, const float* quats, const
             }
             lst.n = 0;
             vstats_t st = {0, 0};
-            blend_view(&sc, cam, o, NULL, P, &lst, NULL, &st);
+            evlist_t ev = {0, 0, 0};
+            blend_view(&sc, cam, o, NULL, P, &lst, pix_bound ? &ev : NULL, &st);
             tot += st.count;
             double* img = images + (size_t)cam->pixel_offset * C;
             memset(img, 0, sizeof(double) * (size_t)cam->width * cam->height * C);
+            if (pix_bound) {
+                double* pb = pix_bound + (size_t)cam->pixel_offset;
+                memset(pb, 0, sizeof(double) * (size_t)cam->width * cam->height);
+                for (int64_t i = 0; i < ev.n; ++i) {
+                    const event_t* e = &ev.e[i];
+                    double gm = 0.0;
+                    for (int c = 0; c < C; ++c) gm = fmax(gm, fabs(gam[(size_t)e->g * C + c]));
+                    pb[(size_t)e->y * cam->width + e->x] += e->m * gm;
+                }
+                free(ev.e);
+            }
             int64_t row_start = 0;
             for (int64_t i = 0; i < lst.n; ++i) {
                 if (lst.e[i].g >= 0) continue;
@@ -822,7 +972,7 @@ int oc_render(const float* means, const float* scales, const float* quats, const
         free(P); free(gam); free(lst.e);
     }
     if (stats) stats[0] = tot;
-    free(sc.cov3);
+    free(sc.cov3); free(sc.rot);
     return 0;
 }
 
@@ -875,7 +1025,7 @@ int oc_colorize_backward(const float* means, const float* scales, const float* q
     double* w = (double*)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
     double* tmpc = (double*)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1) * nb * C);
     int rc = oc_colorize(means, scales, quats, opac, N, cams, n_cams, targets, tdtype, C, L, lam,
-                         n_lambda, o, NULL, tmpc, NULL, A, NULL, w, NULL, NULL, NULL, NULL,
+                         n_lambda, o, NULL, tmpc, NULL, A, NULL, w, NULL, NULL, NULL, NULL, NULL,
                          n_threads);
     if (rc) { free(A); free(w); free(tmpc); return rc; }
     double* Bbar = (double*)calloc((size_t)(N > 0 ? N : 1) * nb * C, sizeof(double));
@@ -963,7 +1113,7 @@ int oc_colorize_backward(const float* means, const float* scales, const float* q
             grad_opac[g] = s;
         }
     }
-    free(go_view); free(Bbar); free(rho); free(A); free(w); free(tmpc); free(sc.cov3);
+    free(go_view); free(Bbar); free(rho); free(A); free(w); free(tmpc); free(sc.cov3); free(sc.rot);
     return 0;
 }
 
@@ -1064,7 +1214,7 @@ int oc_render_backward(const float* means, const float* scales, const float* qua
             }
         }
     }
-    free(go_view); free(gs_view); free(sc.cov3);
+    free(go_view); free(gs_view); free(sc.cov3); free(sc.rot);
     return 0;
 }
 
@@ -1085,7 +1235,7 @@ int oc_project(const float* means, const float* scales, const float* quats, cons
         r[0] = P.visible; r[1] = P.key; r[2] = P.u; r[3] = P.v;
         r[4] = P.ca; r[5] = P.cb; r[6] = P.cc; r[7] = P.sxx; r[8] = P.sxy; r[9] = P.syy;
     }
-    free(sc.cov3);
+    free(sc.cov3); free(sc.rot);
     return 0;
 }
 
@@ -1120,7 +1270,7 @@ int64_t oc_contributions(const float* means, const float* scales, const float* q
             row_start = i + 1;
         }
     }
-    free(P); free(lst.e); free(sc.cov3);
+    free(P); free(lst.e); free(sc.cov3); free(sc.rot);
     return n;
 }
 

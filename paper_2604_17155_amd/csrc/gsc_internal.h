@@ -74,8 +74,8 @@ constexpr uint32_t kItemMask = (1u << kItemBits) - 1u;
 
 // ---- kernels launched from gsc_api.hip ----------------------------------
 // Per-Gaussian geometry packed for the projection's gathers: one 64-byte
-// record geo[g] = (mean x, y, z, opacity, Sigma xx, xy, xz, yy, yz, zz, 0...)
-// with Sigma = R(q) diag(s^2) R(q)^T.
+// record geo[g] = float (mean x, y, z, opacity), then double (Sigma xx, xy,
+// xz, yy, yz, zz) with Sigma = R(q) diag(s^2) R(q)^T.
 constexpr int kGeoStride = 16;  // floats per record
 void launch_cov3d(const float* means, const float* opac, const float* scales, const float* quats,
                   float* geo, int64_t N, hipStream_t s);

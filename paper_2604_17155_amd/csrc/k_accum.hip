@@ -74,10 +74,10 @@ __device__ __forceinline__ uint32_t accumulate_tile(
     const float qlim = (float)(kExp2Scale * (double)bp.cut2);  // q <= cut2  <=>  q2 >= qlim
     const float amax = bp.alpha_max, amin = bp.alpha_min, tmin = bp.t_min;
     // the lane's pixel column and rows within the tile
-    const float lx = (float)(lane & 15);
+    const float lx = tile_offset_col(lane);
     float lyk[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) lyk[k] = (float)((lane >> 4) + 4 * k);
+    for (int k = 0; k < 4; ++k) lyk[k] = tile_offset_row(lane, k);
 
     // The list is walked in chunks of 64 entries.  A chunk's records are
     // gathered at once, one entry per lane, and broadcast entry by entry with
@@ -86,10 +86,11 @@ __device__ __forceinline__ uint32_t accumulate_tile(
     auto load_pv = [&](uint32_t b) -> uint32_t {
         return b + lane < rg.y ? pair_vals[b + lane] : 0u;
     };
-    // R0 keeps, per entry, the offset of the tile's first pixel centre from
-    // the projected centre, (x0 + 1/2 - u_hi) - u_lo and the same in y: a
-    // lane's offset is then that plus its pixel's column (row) in the tile.
-    const float ox = (float)tg.x0 + 0.5f, oy = (float)tg.y0 + 0.5f;
+    // R0 keeps, per entry, the offset of the tile's centre point from the
+    // projected centre, (x0 + 8 - u_hi) - u_lo and the same in y: a lane's
+    // offset is then that plus its pixel's offset from the point
+    // (tile_offset_col / tile_offset_row).
+    const float ox = tile_centre(tg.x0), oy = tile_centre(tg.y0);
     auto gather = [&](uint32_t pv, uint32_t b, float2& R0, float4& R1, uint2& R2) {
         const uint32_t it = pv & kItemMask;
         const bool own = b + lane < rg.y;
@@ -470,14 +471,13 @@ __device__ __forceinline__ uint32_t accumulate_tile_mfma(
     const bool first_chunk = c_off == 0;
     const float qlim = (float)(kExp2Scale * (double)bp.cut2);
     const float amax = bp.alpha_max, amin = bp.alpha_min, tmin = bp.t_min;
-    // the lane's pixel column and rows within the tile; R0 below keeps, per
-    // entry, the offset of the tile's first pixel centre from the projected
-    // centre
-    const float lx = (float)(lane & 15);
+    // the lane's pixel offsets from the tile's centre point; R0 below keeps,
+    // per entry, the offset of that point from the projected centre
+    const float lx = tile_offset_col(lane);
     float lyk[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) lyk[k] = (float)((lane >> 4) + 4 * k);
-    const float ox = (float)tg.x0 + 0.5f, oy = (float)tg.y0 + 0.5f;
+    for (int k = 0; k < 4; ++k) lyk[k] = tile_offset_row(lane, k);
+    const float ox = tile_centre(tg.x0), oy = tile_centre(tg.y0);
 
     // W rows start (and are left) zero
     {

@@ -163,17 +163,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(adj_waves_p
 
     bool inside[4];
     float yv[4][CC];  // pixel values (read only when dL/do is wanted)
-    // the lane's pixel column and rows within the tile; R0 below keeps, per
-    // entry, the offset of the tile's first pixel centre from the projected
-    // centre
-    const float lx = (float)(lane & 15);
+    // the lane's pixel offsets from the tile's centre point; R0 below keeps,
+    // per entry, the offset of that point from the projected centre
+    const float lx = tile_offset_col(lane);
     float lyk[4];
-    const float ox = (float)tg.x0 + 0.5f, oy = (float)tg.y0 + 0.5f;
+    const float ox = tile_centre(tg.x0), oy = tile_centre(tg.y0);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int iy = iy0 + 4 * k;
         inside[k] = ix < V.width && iy < V.height;
-        lyk[k] = (float)((lane >> 4) + 4 * k);
+        lyk[k] = tile_offset_row(lane, k);
         const int64_t row = V.pixel_offset + (int64_t)iy * V.width + ix;
 #pragma unroll
         for (int c = 0; c < CC; ++c)

@@ -10,31 +10,36 @@
 
 namespace gsc {
 
-// a1: 3D covariance, 6 floats per Gaussian (xx xy xz yy yz zz).
+// a1: 3D covariance Sigma = R(q) diag(s^2) R(q)^T, evaluated in FP64 (a few
+// dozen operations per Gaussian): the projection that consumes it is FP64,
+// and a binary32 covariance would be the largest error in the blend's
+// footprint and alpha decisions (a thin Gaussian's rounded rotation moves q by
+// up to ~1e-5 relative at its 3-sigma edge).  Record layout: float4 (mean,
+// opacity), then the six terms xx xy xz yy yz zz as doubles (64 bytes).
 __global__ void k_cov3d(const float* __restrict__ means, const float* __restrict__ opac,
                         const float* __restrict__ scales, const float* __restrict__ quats,
                         float* __restrict__ geo, int64_t N) {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= N) return;
-    float w = quats[4 * g], x = quats[4 * g + 1], y = quats[4 * g + 2], z = quats[4 * g + 3];
-    float inv = rsqrtf(w * w + x * x + y * y + z * z);
+    double w = quats[4 * g], x = quats[4 * g + 1], y = quats[4 * g + 2], z = quats[4 * g + 3];
+    const double inv = 1.0 / sqrt(w * w + x * x + y * y + z * z);
     w *= inv; x *= inv; y *= inv; z *= inv;
-    float R[3][3] = {{1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y)},
-                     {2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x)},
-                     {2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)}};
-    float s0 = scales[3 * g], s1 = scales[3 * g + 1], s2 = scales[3 * g + 2];
-    float d[3] = {s0 * s0, s1 * s1, s2 * s2};
-    float S[6];
+    const double R[3][3] = {{1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y)},
+                            {2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x)},
+                            {2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)}};
+    const double s0 = scales[3 * g], s1 = scales[3 * g + 1], s2 = scales[3 * g + 2];
+    const double d[3] = {s0 * s0, s1 * s1, s2 * s2};
+    double S[6];
     int k = 0;
     for (int i = 0; i < 3; ++i)
-        for (int j = i; j < 3; ++j) {
+        for (int j = i; j < 3; ++j)
             S[k++] = R[i][0] * d[0] * R[j][0] + R[i][1] * d[1] * R[j][1] + R[i][2] * d[2] * R[j][2];
-        }
     float4* o = reinterpret_cast<float4*>(geo + kGeoStride * g);
     o[0] = make_float4(means[3 * g], means[3 * g + 1], means[3 * g + 2], opac[g]);
-    o[1] = make_float4(S[0], S[1], S[2], S[3]);
-    o[2] = make_float4(S[4], S[5], 0.0f, 0.0f);
-    o[3] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    double2* od = reinterpret_cast<double2*>(o + 1);
+    od[0] = make_double2(S[0], S[1]);
+    od[1] = make_double2(S[2], S[3]);
+    od[2] = make_double2(S[4], S[5]);
 }
 
 void launch_cov3d(const float* means, const float* opac, const float* scales, const float* quats,
@@ -273,7 +278,9 @@ __global__ __launch_bounds__(256) void k_project(const ViewInfo* __restrict__ vi
     const int64_t g = V.g_offset + (int64_t)(i - V.item_base);
     // one 64-byte record per Gaussian: a single cache line per random gather
     const float4* gr = reinterpret_cast<const float4*>(geo + kGeoStride * g);
-    const float4 ga = gr[0], gb = gr[1], gc = gr[2];
+    const double2* gd = reinterpret_cast<const double2*>(gr + 1);
+    const float4 ga = gr[0];
+    const double2 s01 = gd[0], s23 = gd[1], s45 = gd[2];  // xx xy | xz yy | yz zz
     float mx = ga.x, my = ga.y, mz = ga.z;
     float key = __fmaf_rn(V.R[6], mx, __fmaf_rn(V.R[7], my, __fmaf_rn(V.R[8], mz, V.t[2])));
     uint32_t cnt = 0;
@@ -292,7 +299,7 @@ __global__ __launch_bounds__(256) void k_project(const ViewInfo* __restrict__ vi
         const double fx = V.fx, fy = V.fy;
         const double j00 = fx * iz, j02 = -fx * tx * iz * iz;
         const double j11 = fy * iz, j12 = -fy * ty * iz * iz;
-        const double S[3][3] = {{gb.x, gb.y, gb.z}, {gb.y, gb.w, gc.x}, {gb.z, gc.x, gc.y}};
+        const double S[3][3] = {{s01.x, s01.y, s23.x}, {s01.y, s23.y, s45.x}, {s23.x, s45.x, s45.y}};
         // Sc = W S W^T
         double M[3][3];
         for (int a = 0; a < 3; ++a)

@@ -117,14 +117,13 @@ __global__ __launch_bounds__(256) void k_render(
     uint32_t cnt = 0;
     const float qlim = (float)(kExp2Scale * (double)bp.cut2);
     const float amax = bp.alpha_max, amin = bp.alpha_min, tmin = bp.t_min;
-    // the lane's pixel column and rows within the tile; R0 below keeps, per
-    // entry, the offset of the tile's first pixel centre from the projected
-    // centre
-    const float lx = (float)(lane & 15);
+    // the lane's pixel offsets from the tile's centre point; R0 below keeps,
+    // per entry, the offset of that point from the projected centre
+    const float lx = tile_offset_col(lane);
     float lyk[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) lyk[k] = (float)((lane >> 4) + 4 * k);
-    const float ox = (float)tg.x0 + 0.5f, oy = (float)tg.y0 + 0.5f;
+    for (int k = 0; k < 4; ++k) lyk[k] = tile_offset_row(lane, k);
+    const float ox = tile_centre(tg.x0), oy = tile_centre(tg.y0);
     // A chunk of 64 entries is gathered at once, one entry per lane (records
     // and the item's colours), and broadcast entry by entry; only entries
     // reaching a band with a live pixel are visited.

@@ -216,6 +216,20 @@ __device__ __forceinline__ bool pair_reaches(uint32_t pc, uint32_t quad, uint32_
 // test, and a stopped pixel (T = 0) stays at 0.  Returns the weight alpha T
 // (0 unless used); `taken` gets the wave's lanes that contributed, built
 // from one ballot per condition (each a compare the step makes anyway).
+// Pixel offsets d = pixel centre - projected centre within a 16x16 tile are
+// formed against the tile's centre point x0 + 8 (between its two middle pixel
+// columns): an entry's offset of that point, (x0 + 8 - u_hi) - u_lo, is
+// formed once and broadcast, and a lane adds its pixel's offset from the
+// point, column - 7.5 (exact).  Every binary32 step then rounds a quantity of
+// at most |d| + 7.5 pixels, so |error of d| <= u (3 |d| + 15) per axis.  The
+// blend, render and adjoint kernels all form d this way, so they take the
+// same pixel decisions.
+__device__ __forceinline__ float tile_centre(int x0) { return (float)x0 + 8.0f; }
+__device__ __forceinline__ float tile_offset_col(uint32_t lane) { return (float)(lane & 15) - 7.5f; }
+__device__ __forceinline__ float tile_offset_row(uint32_t lane, int k) {
+    return (float)((lane >> 4) + 4 * k) - 7.5f;
+}
+
 __device__ __forceinline__ float pixel_step(float q2, float opac, float& T, float qlim, float amin,
                                             float amax, float tmin, uint64_t& taken) {
     const float al = __builtin_amdgcn_fmed3f(opac * __builtin_amdgcn_exp2f(q2), 0.0f, amax);

@@ -31,23 +31,42 @@ def ctx(gsc_mod):
     return gsc_mod.Context()
 
 
-def run_gpu(ctx, sc, y, lam=None):
+def run_gpu(ctx, sc, y, lam=None, counts=False):
+    """GPU colorize; with counts=True also the per-Gaussian contribution
+    counts (as a fourth element)."""
     import torch
     from paper_2604_17155_amd import gsc
     m, s, q, o = gsc.scene_tensors(sc)
     lam = list(sc.lam if lam is None else lam)
-    coeffs, status = ctx.colorize(m, s, q, o, sc.cams, parity.to_device_targets(y), sc.sh_deg, lam)
+    out = ctx.colorize(m, s, q, o, sc.cams, parity.to_device_targets(y), sc.sh_deg, lam,
+                       extras={"counts"} if counts else None)
     torch.cuda.synchronize()
-    return coeffs.cpu().numpy(), status.cpu().numpy(), ctx.stats()
+    res = (out[0].cpu().numpy(), out[1].cpu().numpy(), ctx.stats())
+    if counts:
+        res = res + (out[2]["counts"].cpu().numpy(),)
+    return res
 
 
-def _case(ctx, sc, y, label, want=None):
+def check(ctx, sc, y, ref, label, max_flagged=None):
+    """Colorize on the GPU and gate against `ref`: coefficients, statuses, and
+    per-Gaussian and total contribution counts."""
+    c, st, stats, cnt = run_gpu(ctx, sc, y, counts=True)
+    msg = parity.check_colorize(c, st, ref, count_gpu=stats.contributions, cnt_gpu=cnt, label=label,
+                                max_flagged=max_flagged)
+    print(msg, flush=True)
+    return c, st, stats
+
+
+def _case(ctx, sc, y, label, want=None, max_flagged=None):
     print(f"[case] {label}: N={sc.N} cams={len(sc.cams)} L={sc.sh_deg} C={sc.C} dtype={y.dtype}", flush=True)
     ref = oracle.colorize(sc, y, want=want)
+    if want is None:
+        c, st, stats = check(ctx, sc, y, ref, label, max_flagged=max_flagged)
+        print(f"| contributions gpu={stats.contributions} oracle={ref['count']} decisions={ref['events']}",
+              flush=True)
+        return c, st, stats, ref
     c, st, stats = run_gpu(ctx, sc, y)
-    msg = parity.check_colorize(c, st, ref, want=want,
-                                count_gpu=None if want is not None else stats.contributions,
-                                label=label)
+    msg = parity.check_colorize(c, st, ref, want=want, label=label, max_flagged=max_flagged)
     print(msg, f"| contributions gpu={stats.contributions} oracle={ref['count']} events={ref['events']}",
           flush=True)
     return c, st, stats, ref
@@ -117,11 +136,8 @@ def ragged_features():
 def test_accumulate_variants_bf16(gsc_mod, ragged_features, variant, bin_size):
     sc, y, ref = ragged_features
     ctx = gsc_mod.Context(bin_size=bin_size, accumulate_variant=variant)
-    c, st, stats = run_gpu(ctx, sc, y)
+    c, st, stats = check(ctx, sc, y, ref, f"features L0 C40 bf16 variant {variant} bin {bin_size}")
     assert stats.bin_size == bin_size
-    msg = parity.check_colorize(c, st, ref, count_gpu=stats.contributions,
-                                label=f"features L0 C40 bf16 variant {variant} bin {bin_size}")
-    print(msg, flush=True)
 
 
 @pytest.mark.parametrize("bin_size", [16, 32])
@@ -140,18 +156,14 @@ def test_tile_schedules(gsc_mod, schedule, bin_size):
     ref = oracle.colorize(sc, y)
     for variant in (0, 2):
         ctx = gsc_mod.Context(bin_size=bin_size, schedule=schedule, accumulate_variant=variant)
-        c, st, stats = run_gpu(ctx, sc, y)
-        print(parity.check_colorize(c, st, ref, count_gpu=stats.contributions,
-                                    label=f"schedule {schedule} bin {bin_size} variant {variant}"), flush=True)
+        check(ctx, sc, y, ref, f"schedule {schedule} bin {bin_size} variant {variant}")
 
 
 @pytest.mark.parametrize("schedule", [1, 2])
 def test_tile_schedules_matrix_core(gsc_mod, ragged_features, schedule):
     sc, y, ref = ragged_features
     ctx = gsc_mod.Context(bin_size=32, schedule=schedule, accumulate_variant=128 | 16)
-    c, st, stats = run_gpu(ctx, sc, y)
-    print(parity.check_colorize(c, st, ref, count_gpu=stats.contributions,
-                                label=f"features C40 bf16 matrix core schedule {schedule}"), flush=True)
+    check(ctx, sc, y, ref, f"features C40 bf16 matrix core schedule {schedule}")
 
 
 PACKED = 128 | 1  # all channels and a ones column in one matrix-core block
@@ -183,9 +195,7 @@ def test_packed_matrix_core(gsc_mod, idx, bin_size):
     ctx = gsc_mod.Context(bin_size=bin_size, accumulate_variant=PACKED)
     print(f"[case] packed {label} bin {bin_size}", flush=True)
     ref = oracle.colorize(sc, y)
-    c, st, stats = run_gpu(ctx, sc, y)
-    print(parity.check_colorize(c, st, ref, count_gpu=stats.contributions,
-                                label=f"packed {label} bin {bin_size}"), flush=True)
+    check(ctx, sc, y, ref, f"packed {label} bin {bin_size}")
 
 
 def test_matrix_core_per_view_l1(gsc_mod):
@@ -202,9 +212,7 @@ def test_matrix_core_per_view_l1(gsc_mod):
         ctx = gsc_mod.Context(accumulate_variant=variant)
         print(f"[case] L1 C16 bf16 variant {variant}", flush=True)
         ref = oracle.colorize(sc, y)
-        c, st, stats = run_gpu(ctx, sc, y)
-        print(parity.check_colorize(c, st, ref, count_gpu=stats.contributions,
-                                    label=f"L1 C16 bf16 variant {variant}"), flush=True)
+        check(ctx, sc, y, ref, f"L1 C16 bf16 variant {variant}")
 
 
 def test_degenerate_inputs(ctx, gsc_mod):
@@ -227,9 +235,8 @@ def test_degenerate_inputs(ctx, gsc_mod):
                     lam=[1e-4, 1e-3])
     y = np.random.default_rng(0).uniform(0, 1, (sc.n_pixels, 1)).astype(np.float32)
     ref = oracle.colorize(sc, y)
-    c, st, stats = run_gpu(ctx, sc, y)
+    c, st, stats = check(ctx, sc, y, ref, "tiny")
     assert list(st & 1) == list(ref["status"] & 1) == [0, 1, 1, 0]
-    parity.check_colorize(c, st, ref, count_gpu=stats.contributions, label="tiny")
 
 
 def test_render_matches_oracle(ctx, gsc_mod):
@@ -241,15 +248,10 @@ def test_render_matches_oracle(ctx, gsc_mod):
     torch.cuda.synchronize()
     img = img.cpu().numpy()
     # the oracle renders the float32-rounded coefficients the GPU sees
-    ref32 = oracle.render(sc, coeffs.astype(np.float32).astype(np.float64))
-    err = np.abs(img - ref32).max(axis=1)
+    ref32, pb = oracle.render(sc, coeffs.astype(np.float32).astype(np.float64), with_bound=True)
     stats = ctx.stats()
+    print(parity.check_render(img, ref32, pb, label="render L3 C3"), flush=True)
     ref_full = oracle.colorize(sc, np.zeros((sc.n_pixels, 3), np.float32))
-    # every near-threshold decision changes at most one pixel
-    bad = int((err > 1e-4).sum())
-    print(f"render: max err {err.max():.2e}, pixels >1e-4: {bad}, events {ref_full['events']}", flush=True)
-    assert bad <= ref_full["events"]
-    assert np.median(err) < 1e-6
     assert abs(int(stats.contributions) - ref_full["count"]) <= ref_full["events"]
 
 
@@ -268,14 +270,9 @@ def test_render_l2_six_channels_ragged(ctx, gsc_mod):
     torch.cuda.synchronize()
     img = img.cpu().numpy()
     sc.C = 6
-    ref32 = oracle.render(sc, coeffs.astype(np.float32).astype(np.float64))
-    err = np.abs(img - ref32).max(axis=1)
-    ref_full = oracle.colorize(sc, np.zeros((sc.n_pixels, 6), np.float32))
-    bad = int((err > 1e-4).sum())
-    print(f"render L2 C6: max err {err.max():.2e}, pixels >1e-4: {bad}, events {ref_full['events']}", flush=True)
+    ref32, pb = oracle.render(sc, coeffs.astype(np.float32).astype(np.float64), with_bound=True)
     assert img.shape == (sc.n_pixels, 6)
-    assert bad <= ref_full["events"]
-    assert np.median(err) < 1e-6
+    print(parity.check_render(img, ref32, pb, label="render L2 C6"), flush=True)
 
 
 def test_repeat_and_context_reuse(ctx):
@@ -291,7 +288,7 @@ def test_repeat_and_context_reuse(ctx):
     assert e.max() < 1e-5  # only the order of float atomics differs
     ref = oracle.colorize(sc_small, y_small)
     e, obs = parity.rel_errors(b, ref)
-    assert e[obs & ~parity.flagged(ref)].max() <= parity.TOL_F32
+    assert np.all(e[obs] <= parity.TOL_F32 + parity.bound(ref)[obs])
 
 
 def test_relight_full_size(ctx):
@@ -299,7 +296,7 @@ def test_relight_full_size(ctx):
     configuration, compared on every Gaussian."""
     sc = syn.make_relight()
     y = oracle.make_targets(sc)
-    _case(ctx, sc, y, "relight full 100k L3 50x512^2")
+    _case(ctx, sc, y, "relight full 100k L3 50x512^2", max_flagged=0.015)
 
 
 @pytest.fixture(scope="module")
@@ -334,8 +331,5 @@ def test_render_bins_of_32_pixels(ctx32, gsc_mod):
     m, s, q, o = gsc_mod.scene_tensors(sc)
     img = ctx32.render(m, s, q, o, sc.cams, torch.from_numpy(coeffs.astype(np.float32)).cuda())
     torch.cuda.synchronize()
-    err = np.abs(img.cpu().numpy() - oracle.render(sc, coeffs.astype(np.float32).astype(np.float64))).max(axis=1)
-    ref_full = oracle.colorize(sc, np.zeros((sc.n_pixels, 3), np.float32))
-    bad = int((err > 1e-4).sum())
-    print(f"render bin32: max err {err.max():.2e}, pixels >1e-4: {bad}, events {ref_full['events']}", flush=True)
-    assert bad <= ref_full["events"] and np.median(err) < 1e-6
+    ref32, pb = oracle.render(sc, coeffs.astype(np.float32).astype(np.float64), with_bound=True)
+    print(parity.check_render(img.cpu().numpy(), ref32, pb, label="render bin32"), flush=True)
