@@ -232,6 +232,36 @@ gsc_status gsc_colorize_ex(gsc_ctx* ctx, const float* means, const float* scales
                            const gsc_extras* extras, gsc_stream_t stream);
 
 /*
+ * gsc_colorize for callers that cannot allocate memory (code under graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and arguments as gsc_colorize, with every scratch buffer taken
+ * from a fixed 64 MiB array of device memory that each GPU holds from the
+ * time the library is loaded until the process ends, and the host staging
+ * of the camera tables held in static arrays.  No hipMalloc, hipFree or other
+ * allocation happens in the call; the caller still passes every input and
+ * output.  Like gsc_colorize it reads the tile-pair count back once, so it
+ * synchronises `stream`.
+ *   ctx supplies the options (GSC_FLAG_PROFILE and GSC_FLAG_REUSE_BINNING are
+ *   ignored) and receives the statistics; its own scratch is not used.
+ * Limits: at most 1024 cameras, and the whole call (geometry records,
+ * per-item keys and records, tile pairs and sort scratch, per-view sums of
+ * [n_cams, N, C+1] floats for L > 0) must fit in the 64 MiB: a call whose
+ * known sizes exceed it is rejected before any device work with
+ * GSC_ERR_CAPACITY; one whose tile pairs turn out not to fit returns
+ * GSC_ERR_CAPACITY after the pair count (coefficients then unspecified).
+ * All calls on one GPU share the array, which keeps the last call's
+ * contents (statistics of the last call are read from it): calls are
+ * serialised within a process, and calls on one GPU that overlap (other
+ * processes, or enqueued work still running on another stream) race.
+ */
+gsc_status gsc_colorize_noalloc(gsc_ctx* ctx, const float* means, const float* scales,
+                                const float* quats, const float* opacities, int64_t N,
+                                const gsc_camera* cams, int32_t n_cams, const void* targets,
+                                int32_t tdtype, int32_t C, int32_t sh_deg, const float* lambda,
+                                int32_t n_lambda, float* coeffs, uint8_t* status,
+                                gsc_stream_t stream);
+
+/*
  * Render (eqs. 1-3): images[p] = sum_g w_gp * c_g^T phi_gj over the same
  * front-to-back blend, background zero.
  *   coeffs: device [N, (L+1)^2, C] float32; images: device output

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <array>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -44,11 +45,33 @@ gsc_status fail(gsc_status st, const char* fmt, ...) {
             return fail(GSC_ERR_HIP, "%s launch failed: %s", what, hipGetErrorString(e_)); \
     } while (0)
 
+// A fixed region of device memory that buffers are carved from instead of
+// being allocated (the allocation-free entry point).  Carving only moves a
+// cursor; nothing carved is ever freed.
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0;
+    size_t used = 0;
+    size_t need = 0;  // bytes the first request that did not fit would have needed
+};
+
 struct DevBuf {
     void* p = nullptr;
     size_t cap = 0;
+    Arena* arena = nullptr;  // non-null: carve from the arena, never allocate
     hipError_t ensure(size_t bytes) {
         if (bytes <= cap && p) return hipSuccess;
+        if (arena) {
+            const size_t off = (arena->used + 255) & ~(size_t)255;
+            if (off + bytes > arena->cap) {
+                if (arena->need == 0) arena->need = off + bytes;
+                return hipErrorOutOfMemory;
+            }
+            p = arena->base + off;
+            cap = bytes;
+            arena->used = off + bytes;
+            return hipSuccess;
+        }
         if (p) {
             hipError_t e = hipFree(p);
             if (e != hipSuccess) return e;
@@ -61,7 +84,7 @@ struct DevBuf {
         return e;
     }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p && !arena) (void)hipFree(p);
         p = nullptr;
         cap = 0;
     }
@@ -126,8 +149,14 @@ struct gsc_ctx {
     ViewInfo* h_all = nullptr;    // staging of the full camera table
     size_t h_all_cap = 0;
     uint32_t* h_total = nullptr;
+    // allocation-free working context: buffers carved from an arena, host
+    // staging in static arrays (never freed here), no host allocation
+    bool no_alloc = false;
     gsc_stats stats;
     bool stats_pending = false;
+    // device words the pending statistics are read from (the misc layout
+    // below); null: misc
+    const void* stats_dev = nullptr;
     // GSC_FLAG_PROFILE: event pairs recorded during the last call
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
@@ -140,9 +169,11 @@ struct gsc_ctx {
     }
     ~gsc_ctx() {
         for (DevBuf* b : bufs()) b->release();
-        if (h_views) (void)hipHostFree(h_views);
-        if (h_all) (void)hipHostFree(h_all);
-        if (h_total) (void)hipHostFree(h_total);
+        if (!no_alloc) {
+            if (h_views) (void)hipHostFree(h_views);
+            if (h_all) (void)hipHostFree(h_all);
+            if (h_total) (void)hipHostFree(h_total);
+        }
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     }
 };
@@ -548,7 +579,16 @@ gsc_status ensure_common(gsc_ctx* ctx, const float* means, const float* scales,
         return GSC_OK;
     }
     ctx->bin = ctx->opt.bin_size;
-    if (ctx->bin == 0) {
+    if (ctx->bin == 0 && ctx->no_alloc) {  // no remembered choice (that would allocate)
+        double* d_stats = reinterpret_cast<double*>(ctx->misc.as<char>() + 32);
+        launch_geometry_stats(means, scales, N, d_stats, s);
+        GSC_LAUNCHED("geometry stats");
+        GSC_HIP(hipMemcpyAsync(ctx->h_total, d_stats, 32, hipMemcpyDeviceToHost, s));
+        GSC_HIP(hipStreamSynchronize(s));
+        double st[4];
+        memcpy(st, ctx->h_total, sizeof(st));
+        ctx->bin = choose_bin(st, N, cams, n_cams);
+    } else if (ctx->bin == 0) {
         BinKey key;
         key.means = means;
         key.scales = scales;
@@ -924,6 +964,49 @@ gsc_status colorize_core(gsc_ctx* ctx, const float* means, const float* scales,
                       dc_scratch, d_ill, s);
     GSC_LAUNCHED("fold/solve");
     ctx->stats_pending = true;
+    ctx->stats_dev = nullptr;
+    return GSC_OK;
+}
+
+}  // namespace
+
+// The scratch of the allocation-free colorize: one fixed array per GPU.  Host
+// code must not use the name as an address; kernels receive the device
+// address that hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kNoallocScratchBytes];
+
+namespace {
+
+// ---- allocation-free colorize ---------------------------------------------
+//
+// Every scratch buffer of gsc_colorize_noalloc is carved from `scratch`, a
+// fixed array in device memory that each GPU holds once the library is loaded
+// (its address is looked up once per device); the host staging of the view
+// tables lives in static arrays.  Calls share both: they are serialised on the
+// host by a mutex, and calls on one GPU from different processes race.
+constexpr int kNoallocMaxViews = 1024;
+constexpr int kNoallocMaxDevices = 64;
+
+std::mutex g_noalloc_mu;
+void* g_scratch_ptr[kNoallocMaxDevices];  // device address of `scratch` per device
+ViewInfo g_noalloc_table[kNoallocMaxViews];
+ViewInfo g_noalloc_batch[kNoallocMaxViews];
+ViewInfo g_noalloc_upload[kNoallocMaxViews];
+uint32_t g_noalloc_total[16];
+
+// Device address of `scratch` on the current device (under g_noalloc_mu).
+gsc_status noalloc_scratch(void** out) {
+    int dev = 0;
+    GSC_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoallocMaxDevices) return fail(GSC_ERR_UNSUPPORTED, "device %d out of range", dev);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        GSC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(GSC_ERR_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
     return GSC_OK;
 }
 
@@ -951,6 +1034,72 @@ gsc_status gsc_colorize_ex(gsc_ctx* ctx, const float* means, const float* scales
     std::vector<ViewInfo> all(std::max(n_cams, 1));
     return colorize_core(ctx, means, scales, quats, opacities, N, cams, n_cams, targets, tdtype, C,
                          sh_deg, lam, coeffs, status, extras, s, &key, reuse, all.data());
+}
+
+gsc_status gsc_colorize_noalloc(gsc_ctx* ctx, const float* means, const float* scales,
+                                const float* quats, const float* opacities, int64_t N,
+                                const gsc_camera* cams, int32_t n_cams, const void* targets,
+                                int32_t tdtype, int32_t C, int32_t sh_deg, const float* lambda,
+                                int32_t n_lambda, float* coeffs, uint8_t* status,
+                                gsc_stream_t stream) {
+    if (!ctx) return fail(GSC_ERR_INVALID_ARG, "null ctx");
+    double lam[kMaxNb];
+    gsc_status st = validate_colorize(means, scales, quats, opacities, N, cams, n_cams, targets,
+                                      tdtype, C, sh_deg, lambda, n_lambda, coeffs, lam);
+    if (st != GSC_OK) return st;
+    if (n_cams > kNoallocMaxViews)
+        return fail(GSC_ERR_CAPACITY, "gsc_colorize_noalloc takes at most %d cameras (got %d)",
+                    kNoallocMaxViews, n_cams);
+    // what is known before binning: view tables, geometry records, per-item
+    // keys, counts and records, and the per-view sums
+    const uint64_t items = (uint64_t)N * (uint64_t)n_cams;
+    const uint64_t vs_words = (uint64_t)(sh_deg > 0 ? std::max(n_cams, 1) : 1) * (uint64_t)N * (uint64_t)(C + 1);
+    const uint64_t known = 2 * sizeof(ViewInfo) * (uint64_t)n_cams + 4ull * kGeoStride * (uint64_t)N +
+                           64ull * items + 4 * vs_words;
+    if (known > kNoallocScratchBytes)
+        return fail(GSC_ERR_CAPACITY,
+                    "gsc_colorize_noalloc: %llu Gaussians x %d views x %d channels need at least %llu "
+                    "bytes of scratch before binning; the static scratch holds %llu",
+                    (unsigned long long)N, n_cams, C, (unsigned long long)known,
+                    (unsigned long long)kNoallocScratchBytes);
+    if (ctx->opt.flags & GSC_FLAG_VALIDATE_ONLY) return GSC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    memset(&ctx->stats, 0, sizeof(ctx->stats));
+    ctx->stats_pending = false;
+    if (N == 0) return GSC_OK;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    void* base = nullptr;
+    if ((st = noalloc_scratch(&base)) != GSC_OK) return st;
+    // a working context whose buffers are all carved from the scratch
+    Arena arena;
+    arena.base = static_cast<char*>(base);
+    arena.cap = kNoallocScratchBytes;
+    gsc_ctx w;
+    for (DevBuf* b : w.bufs()) b->arena = &arena;
+    w.no_alloc = true;
+    w.h_views = g_noalloc_batch;
+    w.h_views_cap = kNoallocMaxViews;
+    w.h_all = g_noalloc_upload;
+    w.h_all_cap = kNoallocMaxViews;
+    w.h_total = g_noalloc_total;
+    w.opt = ctx->opt;
+    w.opt.flags &= ~(GSC_FLAG_PROFILE | GSC_FLAG_REUSE_BINNING);
+    memset(&w.stats, 0, sizeof(w.stats));
+    st = colorize_core(&w, means, scales, quats, opacities, N, cams, n_cams, targets, tdtype, C,
+                       sh_deg, lam, coeffs, status, nullptr, s, nullptr, false, g_noalloc_table);
+    if (st != GSC_OK) {
+        if (arena.need > 0)
+            return fail(GSC_ERR_CAPACITY,
+                        "gsc_colorize_noalloc: the call needs more than the %llu-byte static scratch "
+                        "(a buffer would have ended at byte %llu)",
+                        (unsigned long long)kNoallocScratchBytes, (unsigned long long)arena.need);
+        return st;
+    }
+    ctx->stats = w.stats;
+    ctx->bin = w.bin;
+    ctx->stats_pending = true;
+    ctx->stats_dev = w.misc.p;  // inside the scratch: valid until the next call on this GPU
+    return GSC_OK;
 }
 
 gsc_status gsc_colorize(gsc_ctx* ctx, const float* means, const float* scales, const float* quats,
@@ -1004,6 +1153,7 @@ gsc_status gsc_render(gsc_ctx* ctx, const float* means, const float* scales, con
     });
     if (st != GSC_OK) return st;
     ctx->stats_pending = true;
+    ctx->stats_dev = nullptr;
     return GSC_OK;
 }
 
@@ -1103,6 +1253,7 @@ gsc_status gsc_colorize_backward(gsc_ctx* ctx, const float* means, const float* 
     ctx->stats.items = pass1.items;
     ctx->stats.view_batches = pass1.view_batches;
     ctx->stats_pending = true;
+    ctx->stats_dev = nullptr;
     return GSC_OK;
 }
 
@@ -1181,6 +1332,7 @@ gsc_status gsc_render_backward(gsc_ctx* ctx, const float* means, const float* sc
         GSC_LAUNCHED("fold");
     }
     ctx->stats_pending = true;
+    ctx->stats_dev = nullptr;
     return GSC_OK;
 }
 
@@ -1456,10 +1608,10 @@ gsc_status gsc_plan_get_info(gsc_plan* plan, gsc_plan_info* out) {
 
 gsc_status gsc_get_stats(gsc_ctx* ctx, gsc_stats* out) {
     if (!ctx || !out) return fail(GSC_ERR_INVALID_ARG, "null ctx or output");
-    if (ctx->stats_pending && ctx->misc.p) {
+    if (ctx->stats_pending && (ctx->stats_dev || ctx->misc.p)) {
         uint64_t buf[2] = {0, 0};
         GSC_HIP(hipDeviceSynchronize());
-        GSC_HIP(hipMemcpy(buf, ctx->misc.p, 16, hipMemcpyDeviceToHost));
+        GSC_HIP(hipMemcpy(buf, ctx->stats_dev ? ctx->stats_dev : ctx->misc.p, 16, hipMemcpyDeviceToHost));
         ctx->stats.contributions = buf[0];
         ctx->stats.ill_conditioned = (uint32_t)(buf[1] >> 32);
         ctx->stats_pending = false;

@@ -111,6 +111,8 @@ def load(path: Optional[str] = None):
     lib.gsc_colorize_ex.argtypes = [P, P, P, P, P, i64, P, i32, P, i32, i32, i32, P, i32, P, P,
                                     ct.POINTER(GscExtras), P]
     lib.gsc_colorize_ex.restype = ct.c_int
+    lib.gsc_colorize_noalloc.argtypes = [P, P, P, P, P, i64, P, i32, P, i32, i32, i32, P, i32, P, P, P]
+    lib.gsc_colorize_noalloc.restype = ct.c_int
     lib.gsc_render.argtypes = [P, P, P, P, P, i64, P, i32, P, i32, i32, P, P]
     lib.gsc_render.restype = ct.c_int
     lib.gsc_colorize_backward.argtypes = [P, P, P, P, P, i64, P, i32, P, i32, i32, i32, P, i32, P, P,
@@ -290,6 +292,22 @@ class Context:
         _check(self.lib, st)
         if xd is not None:
             return coeffs, status, xd
+        return coeffs, status
+
+    def colorize_noalloc(self, means, scales, quats, opacities, cams, targets, sh_deg: int, lam,
+                         coeffs, status=None, offsets=None, stream=None):
+        """gsc_colorize_noalloc: colorize with the library's fixed scratch
+        (no allocation inside the call).  coeffs [N,(L+1)^2,C] float32 and
+        status [N] uint8 (optional) are caller-allocated outputs."""
+        N = int(means.shape[0])
+        C = int(targets.shape[1])
+        lam_a = (ct.c_float * len(lam))(*[float(v) for v in lam])
+        cam_arr = make_cameras(cams, offsets)
+        st = self.lib.gsc_colorize_noalloc(self.handle, _ptr(means), _ptr(scales), _ptr(quats),
+                                           _ptr(opacities), N, cam_arr, len(cams), _ptr(targets),
+                                           _tdtype(targets), C, sh_deg, lam_a, len(lam),
+                                           _ptr(coeffs), _ptr(status), _stream_ptr(stream))
+        _check(self.lib, st)
         return coeffs, status
 
     def render(self, means, scales, quats, opacities, cams, coeffs, images=None, offsets=None,

@@ -206,6 +206,29 @@ def test_plan_validation(lib):
     assert lib.gsc_colorize_batched(None, FAKE, 0, None, 1, FAKE, None, None) == gsc.GSC_ERR_INVALID_ARG
 
 
+def _call_noalloc(ctx, N=10, n_cams=2, C=3, sh_deg=0, lam=(1e-4,), res=16):
+    cams = syn.circle_cams(n_cams, 3.0, res, res) if n_cams <= 64 else syn.hemisphere_cams(n_cams, 3.0, res, res)
+    arr = gsc.make_cameras(cams)
+    lam_a = (ct.c_float * max(1, len(lam)))(*lam)
+    return ctx.lib.gsc_colorize_noalloc(ctx.handle, FAKE, FAKE, FAKE, FAKE, N, arr, len(cams), FAKE,
+                                        0, C, sh_deg, lam_a, len(lam), FAKE, None, None)
+
+
+def test_noalloc_validation(lib):
+    """The allocation-free colorize validates like gsc_colorize and rejects,
+    before any device work, calls whose known sizes exceed its fixed scratch."""
+    ctx = _vctx()
+    assert _call_noalloc(ctx) == gsc.GSC_OK
+    assert _call_noalloc(ctx, N=2000, n_cams=8, res=64) == gsc.GSC_OK
+    assert _call_noalloc(ctx, C=0) == gsc.GSC_ERR_INVALID_ARG
+    st = _call_noalloc(ctx, N=300_000, n_cams=100, sh_deg=3, lam=(1e-4,))
+    assert st == gsc.GSC_ERR_CAPACITY
+    assert "static scratch" in lib.gsc_last_error().decode()
+    st = _call_noalloc(ctx, N=10, n_cams=1025)
+    assert st == gsc.GSC_ERR_CAPACITY
+    assert "1024 cameras" in lib.gsc_last_error().decode()
+
+
 def test_batch_limit_options(lib):
     o = gsc.default_options()
     assert o.batch_items == 0 and o.batch_pairs == 0
