@@ -1,30 +1,35 @@
 #!/usr/bin/env python3
 """Throughput of colorization (Algorithm 1, steps 1-6) on MI355X.
 
-Default workload (`--workload relight`): the view-dependent relighting scene
--- 100k anisotropic Gaussians (20 blobs, log-scales N(-4, 0.5), random
-rotations, opacity Beta(2,2)), 50 hemisphere cameras at 512x512, SH degree 3,
-C = 3 FP32 channels, per-band Lambda (1e-5, 1e-4, 1e-3, 1e-2).  Targets are
-the render of random ground-truth SH coefficients plus N(0, 0.01^2) noise,
-resident in HBM before timing.  One step = one gsc_colorize call (project,
-depth sort, binning, tile sort, fused blend + accumulate, FP64 fold +
-Cholesky solve).
+Default workload (`--workload batched`), the largest one-GPU configuration:
+32 segmentation scenes of uneven size (5k-400k isotropic Gaussians,
+log-uniform; 20-200 hemisphere cameras each at 640x480 .. 1280x720), SH
+degree 0, C = 16 one-hot label channels rendered from per-Gaussian labels
+(nearest of 16 random seeds) to BF16 targets, lambda = 1e-4.  All scenes are
+one plan (gsc_plan_create), autotuned once and captured into a graph; one
+step is one graph replay that projects, bins, blends, accumulates and solves
+every scene.  Targets (63 GB of BF16) are resident in HBM before timing.
+The line also carries the relighting workload (100k anisotropic Gaussians,
+50 cameras 512x512, L=3, C=3 FP32; one gsc_colorize per step) as a
+secondary figure.
 
-Other workloads (one JSON line each, same fields):
+Other workloads (`--workload`, one JSON line each, same fields):
+  relight   the relighting workload above as the headline.
   features  500k isotropic Gaussians, 100 cameras 960x540, L=0, C=64 BF16
             feature targets (feature distillation).
-  batched   32 segmentation scenes of uneven size (5k-400k Gaussians, 20-200
-            cameras, 640x480 .. 1280x720), L=0, C=16 BF16 one-hot labels, as
-            one plan captured into a graph; a step is one graph replay.
   diff      300k anisotropic Gaussians, 100 cameras 800x800, L=3, C=3: a step
             is colorize + render of the loss mean((render(colorize(y1)) - y2)^2)
             and its backward through both adjoints (targets and opacities).
+  plain     2k Gaussians, 8 cameras 64x64, L=0, C=3, a one-scene plan replayed
+            as a graph (scenes/s).
 
-`value` is accepted Gaussian-pixel contributions per second of the colorize
-pass(es) in a step; `roofline` rates the dominant kernel (fused blend +
-accumulate) by its algorithmic FP32 work against the MI355X vector peak,
-timed with HIP events on the stream it runs on; `cpu_baseline` times the FP64
-oracle on the host on a bounded sample of the same workload.
+`value` is accepted Gaussian-pixel contributions per second; `roofline`
+rates the dominant kernel (the fused blend + accumulate) against its roof,
+with its launch times taken by HIP events on its own stream over the timed
+steps; `cpu_baseline` times the FP64 oracle on the host on a bounded sample
+of the same workload, and for the batched workload the same leg checks the
+timed plan against the oracle on sampled Gaussians of the smallest, the
+largest and two random scenes: the line is printed only if they pass.
 """
 import argparse
 import json
@@ -45,6 +50,11 @@ def algorithmic_flops_per_contribution(C: int) -> float:
     # weight: offsets, quadratic form, alpha, transmittance (12 FLOP) + 1 exp;
     # accumulation of V and S: 2 (C + 1) FLOP
     return 12.0 + 1.0 + 2.0 * (C + 1)
+
+
+def progress(msg: str):
+    """One line per finished stage on stderr (the result line alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def host_threads() -> int:
@@ -209,6 +219,21 @@ def workload_relight(args, gsc):
     return out
 
 
+def secondary_relight(args, gsc):
+    """The relighting workload (one gsc_colorize per step) as a secondary
+    figure of the default line."""
+    from paper_2604_17155_amd import synthetic as syn
+    sc = syn.make_relight()
+    targets = gpu_targets(gsc, sc)
+    label = (f"relighting: {sc.N} anisotropic Gaussians, {len(sc.cams)} hemisphere cameras "
+             f"{sc.cams[0].width}x{sc.cams[0].height}, SH degree {sc.sh_deg}, C={sc.C}, FP32 targets")
+    r = run_single(args, gsc, sc, targets, label, "f32", "relight")
+    progress(f"secondary relighting figure: {r['ms_per_step']:.3f} ms per step")
+    return {"workload": label, "value": r["value"], "unit": r["unit"], "ms_per_step": r["ms_per_step"],
+            "dtype": r["dtype"], "stage_ms_per_step": r["config"]["stage_ms_per_step"],
+            "roofline": r["roofline"]}
+
+
 def workload_features(args, gsc):
     from paper_2604_17155_amd import synthetic as syn
     sc = syn.make_features(n=args.n or 500_000, n_cams=args.views or 100)
@@ -223,16 +248,171 @@ def workload_features(args, gsc):
     return out
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line_ in fh:
+                if line_.startswith("model name"):
+                    return line_.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def roofline_hbm(kernel, bytes_per_step, kernel_ms_per_step, launches, traffic=None):
+    """The accumulate's algorithmic HBM traffic (each target read once per
+    step) over its launch time, against the MI355X HBM peak."""
+    gbs = bytes_per_step / (kernel_ms_per_step * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+            "frac": gbs * 1e9 / PEAK_HBM, "traffic": traffic, "kernel": kernel,
+            "kernel_ms": kernel_ms_per_step / max(1, launches), "launches_per_step": launches,
+            "bytes_per_launch": bytes_per_step / max(1, launches)}
+
+
+def accumulate_kernel_name(variant: int, C: int) -> str:
+    if variant & 128:
+        return "k_accumulate_mfma"
+    return "k_accumulate"
+
+
+def segment_subset(scenes, seed=20260417):
+    """The scenes the oracle checks and times: the smallest and the largest
+    (by Gaussian count) and two others drawn with a fixed seed."""
+    import numpy as np
+    order = sorted(range(len(scenes)), key=lambda k: scenes[k].N)
+    rest = order[1:-1]
+    rng = np.random.default_rng(seed)
+    pick = [int(k) for k in rng.choice(rest, size=min(2, len(rest)), replace=False)]
+    return [order[0], order[-1]] + pick
+
+
+def cpu_baseline_leg(args, gsc, scenes, table, row0, targets, graph, coeffs, status):
+    """The oracle leg of the batched workload (the only place bench.py runs
+    the oracle).  Two parts:
+      check  -- on the smallest, the largest and two random scenes, sample
+                Gaussians, render the target rows they read with the oracle,
+                write those rows into the device targets, replay the timed
+                graph once and compare the sampled Gaussians' coefficients
+                with the oracle's (e_g <= 1e-4 + the bound of near-threshold
+                decisions, as in tests/parity.py);
+      timing -- the oracle's full colorize on a bounded sample of the same
+                scenes (their first views), on all host threads and on one.
+    Returns (accuracy, cpu_baseline)."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_2604_17155_amd import synthetic as syn
+    threads = host_threads()
+    subset = segment_subset(scenes)
+    rng = np.random.default_rng(7)
+    checks = []
+    for k in subset:
+        sc = scenes[k]
+        # sampled among the top twentieth by height (the cameras look down from
+        # the upper hemisphere, so these are rarely hidden) and, of those, the
+        # smaller-scale half; as many as keep the target rows they read within
+        # about two million
+        top = np.argsort(-sc.means[:, 2], kind="stable")[:max(1, sc.N // 20)]
+        small = top[np.argsort(sc.scales[top, 0], kind="stable")[:max(1, top.size // 2)]]
+        n_want = 64
+        while True:
+            want = np.zeros(sc.N, np.uint8)
+            want[rng.choice(small, min(n_want, small.size), replace=False)] = 1
+            rows = oracle.wanted_rows(sc, want)
+            if rows.size <= 2_000_000 or n_want <= 2:
+                break
+            n_want //= 2
+        ysp, vals = oracle.sparse_targets(sc, rows, threads=threads)
+        progress(f"check: scene {k}, {int(want.sum())} sampled Gaussians reading {rows.size} target rows")
+        idx = torch.from_numpy(rows + row0[k]).cuda()
+        targets[idx] = torch.from_numpy(vals.view(np.int16)).cuda().view(torch.bfloat16)
+        checks.append((k, want, ysp))
+    torch.cuda.synchronize()
+    graph.replay()
+    torch.cuda.synchronize()
+    c_all, s_all = coeffs.cpu().numpy(), status.cpu().numpy()
+    per_scene, ok = [], True
+    t_check = time.perf_counter()
+    for k, want, ysp in checks:
+        sc = scenes[k]
+        g0 = table[k][0]
+        ref = oracle.colorize(sc, ysp, want=want, threads=threads)
+        sel = want.astype(bool)
+        c, st = c_all[g0:g0 + sc.N], s_all[g0:g0 + sc.N]
+        nrm = np.linalg.norm(ref["coeffs"].reshape(sc.N, -1), axis=1)
+        obs = sel & ((ref["status"] & 1) == 0)
+        tau = 1e-3 * np.median(nrm[obs]) if obs.any() else 1.0
+        scale = np.maximum(nrm, tau)
+        e = np.linalg.norm((c.astype(np.float64) - ref["coeffs"]).reshape(sc.N, -1), axis=1) / scale
+        b = ref["flip"] / scale
+        inside = bool(np.all(e[obs] <= 1e-4 + b[obs]))
+        sure = sel & (ref["ndec"] == 0)
+        same_obs = bool(np.array_equal(st[sure] & 1, ref["status"][sure] & 1))
+        fl = obs & (b > 0.5e-4)
+        ok = ok and inside and same_obs
+        per_scene.append({"scene": k, "gaussians": sc.N, "views": len(sc.cams), "sampled": int(sel.sum()),
+                          "observed": int(obs.sum()), "flagged": int(fl.sum()),
+                          "max_rel_err": float(e[obs & ~fl].max()) if (obs & ~fl).any() else 0.0,
+                          "max_rel_err_flagged": float(e[fl].max()) if fl.any() else 0.0,
+                          "within_bounds": inside, "unobserved_agree": same_obs})
+        progress(f"check: scene {k} compared, within bounds: {inside}")
+    t_check = time.perf_counter() - t_check
+    observed = sum(p["observed"] for p in per_scene)
+    accuracy = {"gate": "e_g <= 1e-4 + near-threshold bound on every sampled observed Gaussian",
+                "passed": ok, "observed_compared": observed,
+                "flagged_fraction": sum(p["flagged"] for p in per_scene) / max(1, observed),
+                "max_rel_err": max(p["max_rel_err"] for p in per_scene),
+                "scenes": per_scene}
+    # timing: full oracle colorize of each subset scene's first views (about
+    # 3 M pixels per scene), on every host thread, and the smallest of these
+    # samples on one thread
+    samples = []
+    for k in subset:
+        sc = scenes[k]
+        px = sc.cams[0].width * sc.cams[0].height
+        sub = syn.make_segment_scene(k)
+        sub.cams = sub.cams[:max(1, min(len(sub.cams), 3_000_000 // px))]
+        samples.append((k, sub, oracle.make_targets(sub, threads=threads)))
+        progress(f"baseline sample of scene {k}: {len(sub.cams)} views")
+    count, dt = 0, 0.0
+    for k, sub, y in samples:
+        t0 = time.perf_counter()
+        r = oracle.colorize(sub, y, threads=threads)
+        dt += time.perf_counter() - t0
+        count += r["count"]
+    desc = "; ".join(f"scene {k} ({sub.N} Gaussians, first {len(sub.cams)} of {len(scenes[k].cams)} views "
+                     f"{sub.cams[0].width}x{sub.cams[0].height})" for k, sub, _ in samples)
+    # one thread: the smallest scene's sample, a third of its views
+    k1, sub, y = min(samples, key=lambda t: t[1].N)
+    sub1 = syn.make_segment_scene(k1)
+    sub1.cams = sub.cams[:max(1, len(sub.cams) // 3)]
+    y1 = y[:sub1.n_pixels]
+    t0 = time.perf_counter()
+    r1 = oracle.colorize(sub1, y1, threads=1)
+    dt1 = time.perf_counter() - t0
+    baseline = {"value": count / dt, "unit": "contributions/s", "cores": threads, "kind": "oracle",
+                "sample": f"full FP64 oracle colorize of the first views of the smallest, the largest "
+                          f"and two random scenes: {desc}; {count} contributions in {dt:.3g} s "
+                          f"(oracle-rendered targets)",
+                "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+                "single_thread": {"value": r1["count"] / dt1, "unit": "contributions/s",
+                                  "sample": f"scene {k1}, first {len(sub1.cams)} views, "
+                                            f"{r1['count']} contributions in {dt1:.3g} s"},
+                "check_seconds": t_check}
+    return accuracy, baseline
+
+
 def workload_batched(args, gsc):
     import numpy as np
     import torch
     from paper_2604_17155_amd import synthetic as syn
     n_scenes = args.scenes
     scenes = [syn.make_segment_scene(k) for k in range(n_scenes)]
-    table, cams = [], []
+    table, cams, row0 = [], [], []
     g0 = c0 = r0 = 0
     for sc in scenes:
         table.append((g0, sc.N, c0, len(sc.cams)))
+        row0.append(r0)
         g0, c0, r0 = g0 + sc.N, c0 + len(sc.cams), r0 + sc.n_pixels
         cams += list(sc.cams)
     C = scenes[0].C
@@ -241,18 +421,21 @@ def workload_batched(args, gsc):
     for sc in scenes:  # one scene at a time: its FP32 render is the only temporary
         targets[r:r + sc.n_pixels] = gpu_targets(gsc, sc, bf16=True)
         r += sc.n_pixels
+    progress(f"targets of {n_scenes} scenes rendered ({r0} pixels)")
     cat = lambda f: torch.from_numpy(np.ascontiguousarray(np.concatenate([getattr(sc, f) for sc in scenes]))).cuda()
     geo = [cat(f) for f in ("means", "scales", "quats", "opacities")]
-    ctx = gsc.Context(bin_size=args.bin)
+    blend_bit = 1 << 5  # GSC_STAGE_BLEND: events around each batch's accumulate
+    ctx = gsc.Context(bin_size=args.bin, flags=gsc.GSC_FLAG_PROFILE, profile_stages=blend_bit)
     plan = gsc.Plan(ctx, table, *geo, cams, C, 0)
     lam = list(scenes[0].lam)
     coeffs, status = plan.autotune(targets, lam)
     info = plan.info()
     contrib = int(info.contributions)
     variant = int(info.accumulate_variant)
+    progress(f"plan created and autotuned: {int(info.batches)} view batches, {variant_name(variant)}")
     tuned = {variant_name(v): float(info.tuned_ms[i]) for i, v in enumerate(info.tuned_variant) if v}
-    acc_ms = [float(info.tuned_ms[i]) for i, v in enumerate(info.tuned_variant) if v == variant][0]
-    # capture one run and replay it
+    # warm up on the capture stream, then capture one run (its stage events
+    # become graph nodes, re-recorded by every replay) and replay it
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
@@ -260,6 +443,7 @@ def workload_batched(args, gsc):
             plan.run(targets, lam, coeffs, status)
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
+    ctx.stats()  # drain the eager runs' events
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         plan.run(targets, lam, coeffs, status)
@@ -270,23 +454,34 @@ def workload_batched(args, gsc):
         graph.replay()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    progress(f"{args.steps} graph replays timed: {1e3 * elapsed / args.steps:.1f} ms each")
+    st = ctx.stats()  # the accumulate events of the last timed replay
+    acc_ms = float(st.stage_dict()["blend"])
     info2 = plan.info()
-    assert int(info2.dropped_pairs) == 0
+    assert int(info2.dropped_pairs) == 0 and int(info2.contributions) == contrib
     launches = variant_launches(C, variant) * int(info.batches)
+    target_bytes = float(r0) * C * 2
     config = {"workload": f"multi-scene segmentation: {n_scenes} scenes, {g0} Gaussians in total "
                           f"(5k-400k per scene), {c0} cameras 640x480..1280x720, SH degree 0, "
                           f"C={C}, BF16 targets, one plan replayed as a graph",
+              "arithmetic": "BF16 targets decoded exactly; blend weights FP32, split into BF16 high "
+                            "and low parts for the matrix-core product (FP32 accumulation); "
+                            "per-Gaussian sums FP32; fold and solve FP64",
               "contributions_per_step": contrib, "scenes_per_sec": n_scenes * args.steps / elapsed,
-              "pixels": r0, "tile_pairs_per_step": int(info.pair_capacity),
+              "pixels": r0, "target_bytes": target_bytes, "tile_pairs_per_step": int(info.pair_capacity),
               "view_batches": int(info.batches), "bin_size": int(info.bin_size),
               "autotune_accumulate_ms": tuned,
               "accumulate_variant": variant_name(variant),
-              "accumulate_hbm": hbm_view(float(r0) * C * 2, acc_ms)}
+              "accumulate_ms_per_step": acc_ms,
+              "accumulate_ms_source": "HIP event nodes around each batch's accumulate in the "
+                                      "captured graph, read after the last timed replay"}
     out = line(args, contrib * args.steps / elapsed, 1e3 * elapsed / args.steps, "bf16", config,
-               roofline(C, contrib, acc_ms, launches))
+               roofline_hbm(accumulate_kernel_name(variant, C), target_bytes, acc_ms, launches))
+    out["roofline_valu"] = roofline(C, contrib, acc_ms, launches)
     if not args.no_cpu_baseline:
-        small = min(scenes, key=lambda sc: sc.N * len(sc.cams))
-        out["cpu_baseline"] = cpu_baseline(small, host_threads(), "the smallest scene of the batch")
+        acc, base = cpu_baseline_leg(args, gsc, scenes, table, row0, targets, graph, coeffs, status)
+        out["accuracy"] = acc
+        out["cpu_baseline"] = base
     return out
 
 
@@ -400,8 +595,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="relight",
+    ap.add_argument("--workload", default="batched",
                     choices=["relight", "features", "batched", "diff", "plain"])
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="batched workload: skip the relighting figure carried as a secondary field")
     ap.add_argument("--n", type=int, default=0, help="Gaussians (0: the workload's size)")
     ap.add_argument("--views", type=int, default=0, help="cameras (0: the workload's count)")
     ap.add_argument("--res", type=int, default=0, help="square resolution (0: the workload's)")
@@ -434,7 +631,15 @@ def main():
     fn = {"relight": workload_relight, "features": workload_features, "batched": workload_batched,
           "plain": workload_plain,
           "diff": workload_diff}[args.workload]
-    print(json.dumps(fn(args, gsc)), flush=True)
+    out = fn(args, gsc)
+    if args.workload == "batched" and not args.no_secondary:
+        out["config"]["secondary"] = secondary_relight(args, gsc)
+    acc = out.get("accuracy")
+    if acc is not None and not acc["passed"]:
+        print("accuracy check against the oracle failed; no result line:\n" + json.dumps(acc),
+              file=sys.stderr)
+        sys.exit(1)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

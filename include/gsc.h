@@ -19,7 +19,8 @@
  *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream).
  *     Calls that size their scratch from data (colorize, render and their
  *     adjoints) read one 4-byte count back from the device and therefore
- *     synchronise `stream` once per call.
+ *     synchronise `stream` once per call; on a stream under graph capture
+ *     they return GSC_ERR_NOT_CAPTURABLE without enqueueing anything.
  *   - Return value: GSC_OK or a negative gsc_status.  On failure
  *     gsc_last_error() returns a message for the calling thread.  Invalid
  *     arguments are rejected before any device work is enqueued.
@@ -71,7 +72,11 @@ typedef enum {
     GSC_ERR_INVALID_ARG = -1,
     GSC_ERR_HIP = -2,
     GSC_ERR_CAPACITY = -3,
-    GSC_ERR_UNSUPPORTED = -4
+    GSC_ERR_UNSUPPORTED = -4,
+    GSC_ERR_NOT_CAPTURABLE = -5 /* called on a stream under graph capture by an entry
+                                   point that must read a count back (colorize, render
+                                   and their adjoints); nothing was enqueued.  Plans
+                                   (gsc_colorize_batched) are capturable. */
 } gsc_status;
 
 typedef enum { GSC_F32 = 0, GSC_BF16 = 1 } gsc_dtype;

@@ -133,6 +133,9 @@ def load():
     lib.oc_project.argtypes = [P, P, P, P, i64, P, P, P]
     lib.oc_contributions.argtypes = [P, P, P, P, i64, P, i32, P, P, P, i64]
     lib.oc_contributions.restype = ct.c_int64
+    lib.oc_wanted_rows.argtypes = [P, P, P, P, i64, P, i32, P, P, P, i64]
+    lib.oc_wanted_rows.restype = ct.c_int64
+    lib.oc_render_rows.argtypes = [P, P, P, P, i64, P, i32, P, i32, i32, P, P, i64, P, i32]
     lib.oc_solve.argtypes = [i32, i32, P, P, P]
     lib.oc_cond.argtypes = [i32, P]
     lib.oc_cond.restype = ct.c_double
@@ -307,6 +310,61 @@ def contributions(scene, opts: Optional[Options] = None, cap: int = 5_000_000):
     if n > cap:
         raise ValueError("contribution buffer too small")
     return idx[:n].copy(), w[:n].copy()
+
+
+def wanted_rows(scene, want: np.ndarray, opts: Optional[Options] = None) -> np.ndarray:
+    """Target rows a colorize restricted to the Gaussians with want[g] != 0
+    reads (their pixel ranges in every view), ascending."""
+    lib = load()
+    opts = opts or Options()
+    m, s, q, o = _geom(scene)
+    cams = cameras(scene.cams)
+    w = np.ascontiguousarray(want, np.uint8)
+    oo = opts.c()
+    n = lib.oc_wanted_rows(_f(m), _f(s), _f(q), _f(o), scene.N, ct.cast(cams, ct.c_void_p),
+                           len(scene.cams), ct.byref(oo), _f(w), None, 0)
+    rows = np.zeros(max(1, n), np.int64)
+    lib.oc_wanted_rows(_f(m), _f(s), _f(q), _f(o), scene.N, ct.cast(cams, ct.c_void_p),
+                       len(scene.cams), ct.byref(oo), _f(w), _f(rows), n)
+    return np.sort(rows[:n])
+
+
+def render_rows(scene, coeffs, rows: np.ndarray, opts: Optional[Options] = None, threads=None):
+    """Oracle render (eqs. 1-3) of the listed target rows only -> [len(rows), C]."""
+    lib = load()
+    opts = opts or Options()
+    m, s, q, o = _geom(scene)
+    coeffs = np.ascontiguousarray(coeffs, np.float64)
+    C = coeffs.shape[2]
+    L = int(round(np.sqrt(coeffs.shape[1]))) - 1
+    rows = np.ascontiguousarray(rows, np.int64)
+    out = np.zeros((rows.size, C), np.float64)
+    cams = cameras(scene.cams)
+    oo = opts.c()
+    rc = lib.oc_render_rows(_f(m), _f(s), _f(q), _f(o), scene.N, ct.cast(cams, ct.c_void_p),
+                            len(scene.cams), _f(coeffs), C, L, ct.byref(oo), _f(rows), rows.size,
+                            _f(out), _threads(threads))
+    if rc != 0:
+        raise ValueError("oracle render_rows rejected its arguments")
+    return out
+
+
+def sparse_targets(scene, rows: np.ndarray, which: int = 0, opts: Optional[Options] = None,
+                   threads=None):
+    """Targets of a synthetic workload at the listed rows only (the oracle's
+    render of ground-truth set `which` plus the seeded noise, cast to the
+    workload's target dtype), returned as (full-size array that holds them at
+    those rows and zeros elsewhere, the values at the rows).  The full array
+    is allocated lazily, so only the pages of the listed rows use memory."""
+    vals = render_rows(scene, scene.gt[which], rows, opts, threads)
+    if scene.noise_std:
+        vals = vals + syn.target_noise(scene, which)[rows]
+    vals = vals.astype(np.float32)
+    if scene.target_dtype == "bf16":
+        vals = syn.round_bf16(vals)
+    full = np.zeros((scene.n_pixels, scene.C), vals.dtype)
+    full[rows] = vals
+    return full, vals
 
 
 def sh_basis(L: int, dirs: np.ndarray) -> np.ndarray:

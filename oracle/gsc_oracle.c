@@ -1274,6 +1274,124 @@ int64_t oc_contributions(const float* means, const float* scales, const float* q
     return n;
 }
 
+/* The target rows (camera pixel_offset + y W + x) inside the pixel ranges of
+ * the wanted Gaussians, view by view in ascending order: the only target
+ * values a colorize restricted to those Gaussians reads.  Returns the number
+ * of rows (rows_out receives at most cap of them). */
+int64_t oc_wanted_rows(const float* means, const float* scales, const float* quats,
+                       const float* opac, int64_t N, const oc_camera* cams, int n_cams,
+                       const oc_options* o, const uint8_t* want, int64_t* rows_out, int64_t cap) {
+    scene_t sc;
+    build_scene(&sc, means, scales, quats, opac, N);
+    uint8_t** masks = (uint8_t**)calloc((size_t)(n_cams > 0 ? n_cams : 1), sizeof(uint8_t*));
+    int64_t* cnt = (int64_t*)calloc((size_t)(n_cams > 0 ? n_cams : 1) + 1, sizeof(int64_t));
+#pragma omp parallel
+    {
+        proj_t* P = (proj_t*)malloc(sizeof(proj_t) * (size_t)(N > 0 ? N : 1));
+#pragma omp for schedule(dynamic, 1)
+        for (int j = 0; j < n_cams; ++j) {
+            masks[j] = wanted_mask(&sc, &cams[j], o, want, P);
+            int64_t npx = (int64_t)cams[j].width * cams[j].height, c = 0;
+            for (int64_t i = 0; i < npx; ++i) c += masks[j][i] != 0;
+            cnt[j + 1] = c;
+        }
+        free(P);
+    }
+    for (int j = 0; j < n_cams; ++j) cnt[j + 1] += cnt[j];
+    int64_t n = cnt[n_cams > 0 ? n_cams : 0];
+    for (int j = 0; j < n_cams; ++j) {
+        int64_t npx = (int64_t)cams[j].width * cams[j].height, k = cnt[j];
+        for (int64_t i = 0; i < npx; ++i) {
+            if (!masks[j][i]) continue;
+            if (k < cap) rows_out[k] = cams[j].pixel_offset + i;
+            ++k;
+        }
+        free(masks[j]);
+    }
+    free(masks); free(cnt); free(sc.cov3); free(sc.rot);
+    return n;
+}
+
+/* Render (eqs. 1-3) of the listed target rows only (ascending, each inside
+ * one camera): out[k][c] = sum_g w_g phi_g^T c_g at row rows[k]. */
+int oc_render_rows(const float* means, const float* scales, const float* quats, const float* opac,
+                   int64_t N, const oc_camera* cams, int n_cams, const double* coeffs, int C, int L,
+                   const oc_options* o, const int64_t* rows, int64_t n_rows, double* out,
+                   int n_threads) {
+    if (check_common(N, n_cams, C, L)) return -1;
+    int nb = (L + 1) * (L + 1);
+    scene_t sc;
+    build_scene(&sc, means, scales, quats, opac, N);
+    memset(out, 0, sizeof(double) * (size_t)n_rows * C);
+    if (n_threads > 0) {
+#ifdef _OPENMP
+        omp_set_num_threads(n_threads);
+#endif
+    }
+#pragma omp parallel
+    {
+        proj_t* P = (proj_t*)malloc(sizeof(proj_t) * (size_t)(N > 0 ? N : 1));
+        double* gam = (double*)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1) * C);
+        elist_t lst = {0, 0, 0};
+#pragma omp for schedule(dynamic, 1)
+        for (int j = 0; j < n_cams; ++j) {
+            const oc_camera* cam = &cams[j];
+            int64_t npx = (int64_t)cam->width * cam->height;
+            /* the listed rows of this camera: [k0, k1) */
+            int64_t lo = 0, hi = n_rows;
+            while (lo < hi) {
+                int64_t mid = (lo + hi) / 2;
+                if (rows[mid] < cam->pixel_offset) lo = mid + 1; else hi = mid;
+            }
+            int64_t k0 = lo;
+            hi = n_rows;
+            while (lo < hi) {
+                int64_t mid = (lo + hi) / 2;
+                if (rows[mid] < cam->pixel_offset + npx) lo = mid + 1; else hi = mid;
+            }
+            int64_t k1 = lo;
+            if (k0 == k1) continue;
+            int64_t* slot = (int64_t*)malloc(sizeof(int64_t) * (size_t)npx);
+            uint8_t* mask = (uint8_t*)calloc((size_t)npx, 1);
+            for (int64_t i = 0; i < npx; ++i) slot[i] = -1;
+            for (int64_t k = k0; k < k1; ++k) {
+                slot[rows[k] - cam->pixel_offset] = k;
+                mask[rows[k] - cam->pixel_offset] = 1;
+            }
+            double phi[OC_MAX_NB];
+            for (int64_t g = 0; g < N; ++g) {
+                double d[3];
+                view_dir(cam, means + 3 * g, d);
+                sh_basis(L, d, phi);
+                for (int c = 0; c < C; ++c) {
+                    double a = 0.0;
+                    for (int m = 0; m < nb; ++m) a += coeffs[((size_t)g * nb + m) * C + c] * phi[m];
+                    gam[g * C + c] = a;
+                }
+            }
+            lst.n = 0;
+            vstats_t st = {0, 0};
+            blend_view(&sc, cam, o, mask, P, &lst, NULL, &st);
+            int64_t row_start = 0;
+            for (int64_t i = 0; i < lst.n; ++i) {
+                if (lst.e[i].g >= 0) continue;
+                int y = lst.e[i].x;
+                for (int64_t r = row_start; r < i; ++r) {
+                    const entry_t* en = &lst.e[r];
+                    int64_t k = slot[(int64_t)y * cam->width + en->x];
+                    if (k < 0) continue;
+                    for (int c = 0; c < C; ++c) out[k * C + c] += en->w * gam[(size_t)en->g * C + c];
+                }
+                row_start = i + 1;
+            }
+            free(slot); free(mask);
+        }
+        free(P); free(gam); free(lst.e);
+    }
+    free(sc.cov3); free(sc.rot);
+    return 0;
+}
+
 /* Regularised solve of given normal equations (for checking the solver). */
 int oc_solve(int nb, int C, const double* A, const double* B, double* X) {
     double Lm[OC_MAX_NB * OC_MAX_NB];

@@ -181,18 +181,43 @@ struct gsc_ctx {
 namespace {
 constexpr size_t kMaxEvents = 1 << 14;
 // Records an event pair around a stage when profiling is on.  Pairs pile up
-// until gsc_get_stats() sums them.
+// until gsc_get_stats() sums them.  Under stream capture each event becomes an
+// event-record node of the graph, added after the capture's current nodes
+// (which it then replaces), so every replay re-records it and gsc_get_stats()
+// reads the last replay's times.  (The runtime torch loads rejects
+// hipEventRecordExternal under capture, so the node is added directly.)  If
+// that fails the stage is not timed and the error is cleared: profiling never
+// breaks a capture.
 struct StageTimer {
     gsc_ctx* ctx;
     hipStream_t s;
     int stage;
     uint32_t launches;
     hipEvent_t a = nullptr;
+    bool capturing = false;
     StageTimer(gsc_ctx* c, hipStream_t st, int stg, uint32_t n = 1) : ctx(c), s(st), stage(stg), launches(n) {
         if (!(ctx->opt.flags & GSC_FLAG_PROFILE)) return;
         if (ctx->opt.profile_stages != 0u && !((ctx->opt.profile_stages >> (stg & 31)) & 1u)) return;
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        capturing = hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive;
         a = take();
-        if (a) (void)hipEventRecord(a, s);
+        if (a && record(a) != hipSuccess) {
+            (void)hipGetLastError();
+            a = nullptr;
+        }
+    }
+    hipError_t record(hipEvent_t e) {
+        if (!capturing) return hipEventRecord(e, s);
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        unsigned long long id = 0;
+        hipGraph_t g = nullptr;
+        const hipGraphNode_t* deps = nullptr;
+        size_t nd = 0;
+        hipError_t err = hipStreamGetCaptureInfo_v2(s, &cs, &id, &g, &deps, &nd);
+        if (err != hipSuccess) return err;
+        hipGraphNode_t node = nullptr;
+        if ((err = hipGraphAddEventRecordNode(&node, g, deps, nd, e)) != hipSuccess) return err;
+        return hipStreamUpdateCaptureDependencies(s, &node, 1, hipStreamSetCaptureDependencies);
     }
     hipEvent_t take() {
         if (ctx->ev_used >= kMaxEvents) return nullptr;  // stats not drained: stop recording
@@ -207,7 +232,10 @@ struct StageTimer {
         if (!a) return;
         hipEvent_t b = take();
         if (!b) return;
-        (void)hipEventRecord(b, s);
+        if (record(b) != hipSuccess) {
+            (void)hipGetLastError();
+            return;
+        }
         ctx->marks.push_back({stage, a, b, launches});
     }
 };
@@ -219,6 +247,16 @@ namespace {
 constexpr size_t kMiscBytes = 64;  // [32..63]: geometry statistics (4 doubles)
 // bin_views result asking the caller to retry with fewer views per batch
 constexpr gsc_status kSplit = (gsc_status)1;
+
+// Entry points that read a count back cannot run under stream capture.
+gsc_status refuse_capture(hipStream_t s, const char* what) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+        return fail(GSC_ERR_NOT_CAPTURABLE,
+                    "%s reads the tile-pair count back and cannot be captured into a graph; "
+                    "create a plan (gsc_plan_create) and capture gsc_colorize_batched", what);
+    return GSC_OK;
+}
 
 gsc_status validate_options(const gsc_options* o) {
     if (!(o->alpha_min >= 0.0f && o->alpha_min < 1.0f)) return fail(GSC_ERR_INVALID_ARG, "alpha_min must be in [0,1)");
@@ -1027,6 +1065,7 @@ gsc_status gsc_colorize_ex(gsc_ctx* ctx, const float* means, const float* scales
     if (st != GSC_OK) return st;
     if (ctx->opt.flags & GSC_FLAG_VALIDATE_ONLY) return GSC_OK;
     hipStream_t s = (hipStream_t)stream;
+    if ((st = refuse_capture(s, "gsc_colorize")) != GSC_OK) return st;
     memset(&ctx->stats, 0, sizeof(ctx->stats));
     if (N == 0) return GSC_OK;
     const BinKey key = make_key(ctx, means, scales, quats, opacities, N, cams, n_cams, blend_params(ctx->opt));
@@ -1064,6 +1103,7 @@ gsc_status gsc_colorize_noalloc(gsc_ctx* ctx, const float* means, const float* s
                     (unsigned long long)kNoallocScratchBytes);
     if (ctx->opt.flags & GSC_FLAG_VALIDATE_ONLY) return GSC_OK;
     hipStream_t s = (hipStream_t)stream;
+    if ((st = refuse_capture(s, "gsc_colorize_noalloc")) != GSC_OK) return st;
     memset(&ctx->stats, 0, sizeof(ctx->stats));
     ctx->stats_pending = false;
     if (N == 0) return GSC_OK;
@@ -1124,6 +1164,7 @@ gsc_status gsc_render(gsc_ctx* ctx, const float* means, const float* scales, con
     if (N > 0 && !coeffs) return fail(GSC_ERR_INVALID_ARG, "coeffs is null");
     if (ctx->opt.flags & GSC_FLAG_VALIDATE_ONLY) return GSC_OK;
     hipStream_t s = (hipStream_t)stream;
+    if ((st = refuse_capture(s, "gsc_render")) != GSC_OK) return st;
     memset(&ctx->stats, 0, sizeof(ctx->stats));
     if (n_cams == 0) return GSC_OK;
     BlendParams bp = blend_params(ctx->opt);
@@ -1176,6 +1217,7 @@ gsc_status gsc_colorize_backward(gsc_ctx* ctx, const float* means, const float* 
     if (ctx->opt.flags & GSC_FLAG_VALIDATE_ONLY) return GSC_OK;
 
     hipStream_t s = (hipStream_t)stream;
+    if ((st = refuse_capture(s, "gsc_colorize_backward")) != GSC_OK) return st;
     memset(&ctx->stats, 0, sizeof(ctx->stats));
     if (grad_targets && rows > 0) launch_fill_u32((uint32_t*)grad_targets, 0u, (uint64_t)rows * C, s);
     if (grad_opacities && N > 0) launch_fill_u32((uint32_t*)grad_opacities, 0u, (uint64_t)N, s);
@@ -1271,6 +1313,7 @@ gsc_status gsc_render_backward(gsc_ctx* ctx, const float* means, const float* sc
     if (N > 0 && !coeffs) return fail(GSC_ERR_INVALID_ARG, "coeffs is null");
     if (ctx->opt.flags & GSC_FLAG_VALIDATE_ONLY) return GSC_OK;
     hipStream_t s = (hipStream_t)stream;
+    if ((st = refuse_capture(s, "gsc_render_backward")) != GSC_OK) return st;
     memset(&ctx->stats, 0, sizeof(ctx->stats));
     const int nb = (sh_deg + 1) * (sh_deg + 1);
     if (grad_coeffs && N > 0) launch_fill_u32((uint32_t*)grad_coeffs, 0u, (uint64_t)N * nb * C, s);

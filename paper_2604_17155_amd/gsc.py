@@ -23,6 +23,7 @@ GSC_ERR_INVALID_ARG = -1
 GSC_ERR_HIP = -2
 GSC_ERR_CAPACITY = -3
 GSC_ERR_UNSUPPORTED = -4
+GSC_ERR_NOT_CAPTURABLE = -5
 GSC_F32 = 0
 GSC_BF16 = 1
 GSC_G_UNOBSERVED = 1

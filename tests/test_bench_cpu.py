@@ -31,3 +31,22 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr) or "1 GPU" in (r.stdout + r.stderr)
+
+
+def test_hbm_roofline():
+    r = bench.roofline_hbm("k_accumulate_mfma", 16e9, 4.0, 8)  # 16 GB in 4 ms over 8 launches
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s"
+    assert abs(r["achieved"] - 4000.0) < 1e-9 and abs(r["frac"] - 0.5) < 1e-12
+    assert abs(r["kernel_ms"] - 0.5) < 1e-12 and abs(r["bytes_per_launch"] - 2e9) < 1
+
+
+def test_segment_subset():
+    from paper_2604_17155_amd import synthetic as syn
+
+    class S:
+        def __init__(self, n):
+            self.N = n
+    scenes = [S(n) for n in (50, 10, 400, 30, 20, 70)]
+    sub = bench.segment_subset(scenes)
+    assert sub[0] == 1 and sub[1] == 2 and len(sub) == 4 and len(set(sub)) == 4
+    assert sub == bench.segment_subset(scenes)  # fixed seed

@@ -152,6 +152,73 @@ def test_batched_graph_capture_and_replay(ctx, gsc_mod):
         torch.cuda.synchronize()
 
 
+def test_profiled_plan_in_a_graph(gsc_mod):
+    """A plan run with stage profiling captured into a graph: its events are
+    graph nodes, so every replay re-times the stages, and the replays still
+    match the eager run."""
+    import torch
+    scenes = segment_scenes()[:3]
+    targets = [oracle.make_targets(sc) for sc in scenes]
+    pctx = gsc_mod.Context(flags=gsc_mod.GSC_FLAG_PROFILE, profile_stages=1 << 5)
+    plan, table, tens, cams, y = make_plan(gsc_mod, pctx, scenes, targets)
+    lam = list(scenes[0].lam)
+    ref_c, ref_s = plan.run(y, lam)
+    torch.cuda.synchronize()
+    ref_c = ref_c.clone()
+    pctx.stats()  # drain the eager run's events
+    coeffs = torch.zeros_like(ref_c)
+    status = torch.zeros_like(ref_s)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.run(y, lam, coeffs, status)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    pctx.stats()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.run(y, lam, coeffs, status)
+    for rep in range(3):
+        coeffs.fill_(float("nan"))
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.allclose(coeffs, ref_c, rtol=1e-5, atol=1e-6)
+    st = pctx.stats()
+    blend = st.stage_dict()["blend"]
+    print(f"profiled graph: blend {blend:.3f} ms over {plan.info().batches} batch(es), "
+          f"{int(st.stage_launches[5])} launches", flush=True)
+    assert blend > 0.0 and int(st.stage_launches[5]) >= 1
+
+
+def test_colorize_refuses_capture(gsc_mod):
+    """Entry points that read a count back return GSC_ERR_NOT_CAPTURABLE on a
+    capturing stream and enqueue nothing; the capture stays usable."""
+    import torch
+    sc = syn.make_plain(n=500, n_cams=2, res=32)
+    y = parity.to_device_targets(oracle.make_targets(sc))
+    m, s, q, o = gsc_mod.scene_tensors(sc)
+    ctx = gsc_mod.Context()
+    lam = list(sc.lam)
+    coeffs, status = ctx.colorize(m, s, q, o, sc.cams, y, 0, lam)
+    torch.cuda.synchronize()
+    buf = torch.zeros(4, device="cuda")
+    graph = torch.cuda.CUDAGraph()
+    errors = []
+    with torch.cuda.graph(graph):
+        for call in (lambda: ctx.colorize(m, s, q, o, sc.cams, y, 0, lam, coeffs=coeffs, status=status),
+                     lambda: ctx.colorize_noalloc(m, s, q, o, sc.cams, y, 0, lam, coeffs, status),
+                     lambda: ctx.render(m, s, q, o, sc.cams, coeffs)):
+            try:
+                call()
+            except gsc_mod.GscError as e:
+                errors.append(e.status)
+        buf.add_(1.0)
+    graph.replay()
+    torch.cuda.synchronize()
+    assert errors == [gsc_mod.GSC_ERR_NOT_CAPTURABLE] * 3, errors
+    assert torch.equal(buf, torch.ones(4, device="cuda"))
+
+
 def test_batched_autotune(ctx, gsc_mod):
     import torch
     scenes = segment_scenes()[1:4]
