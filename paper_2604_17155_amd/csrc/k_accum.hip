@@ -71,8 +71,10 @@ __device__ __forceinline__ uint32_t accumulate_tile(
     const int64_t slot_base = per_view ? V.vs_base : V.g_offset;
     const bool first_chunk = c_off == 0;
 
-    const float qlim = (float)(kExp2Scale * (double)bp.cut2);  // q <= cut2  <=>  q2 >= qlim
-    const float amax = bp.alpha_max, amin = bp.alpha_min, tmin = bp.t_min;
+    // loop constants in vector registers (see uniform_in_vgpr)
+    const float qlim = uniform_in_vgpr((float)(kExp2Scale * (double)bp.cut2));  // q <= cut2  <=>  q2 >= qlim
+    const float amax = uniform_in_vgpr(bp.alpha_max), amin = uniform_in_vgpr(bp.alpha_min),
+                tmin = uniform_in_vgpr(bp.t_min);
     // the lane's pixel column and rows within the tile
     const float lx = tile_offset_col(lane);
     float lyk[4];
@@ -469,8 +471,10 @@ __device__ __forceinline__ uint32_t accumulate_tile_mfma(
     const int64_t slot_base = per_view ? V.vs_base : V.g_offset;
     const int64_t g_off = V.g_offset;
     const bool first_chunk = c_off == 0;
-    const float qlim = (float)(kExp2Scale * (double)bp.cut2);
-    const float amax = bp.alpha_max, amin = bp.alpha_min, tmin = bp.t_min;
+    // loop constants in vector registers (see uniform_in_vgpr)
+    const float qlim = uniform_in_vgpr((float)(kExp2Scale * (double)bp.cut2));
+    const float amax = uniform_in_vgpr(bp.alpha_max), amin = uniform_in_vgpr(bp.alpha_min),
+                tmin = uniform_in_vgpr(bp.t_min);
     // the lane's pixel offsets from the tile's centre point; R0 below keeps,
     // per entry, the offset of that point from the projected centre
     const float lx = tile_offset_col(lane);

@@ -159,7 +159,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(adj_waves_p
     // dL/do of an entry goes to Gaussian g_offset + (item - item_base), the
     // item being named by the entry's record
     const int64_t g_shift = V.g_offset - (int64_t)V.item_base;
-    const float qlim = (float)(kExp2Scale * (double)bp.cut2);
+    // loop constants in vector registers (see uniform_in_vgpr)
+    const float qlim = uniform_in_vgpr((float)(kExp2Scale * (double)bp.cut2));
+    BlendParams bpv = bp;
+    bpv.alpha_max = uniform_in_vgpr(bp.alpha_max);
+    bpv.alpha_min = uniform_in_vgpr(bp.alpha_min);
+    bpv.t_min = uniform_in_vgpr(bp.t_min);
 
     bool inside[4];
     float yv[4][CC];  // pixel values (read only when dL/do is wanted)
@@ -259,7 +264,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(adj_waves_p
             if (!((bands >> k) & 1u)) continue;  // uniform
             const float dy = c0.y + lyk[k];
             const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
-            const Step st = blend_step(T[k], live[k], q2, c1.w, qlim, bp);
+            const Step st = blend_step(T[k], live[k], q2, c1.w, qlim, bpv);
             float u = -del;
 #pragma unroll
             for (int c = 0; c < CC; ++c) u = fmaf(bet[c], yv[k][c], u);
@@ -298,7 +303,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(adj_waves_p
             if (!((bands >> k) & 1u)) continue;  // uniform
             const float dy = c0.y + lyk[k];
             const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
-            const Step st = blend_step(T[k], live[k], q2, c1.w, qlim, bp);
+            const Step st = blend_step(T[k], live[k], q2, c1.w, qlim, bpv);
             float u = -del;
 #pragma unroll
             for (int c = 0; c < CC; ++c) u = fmaf(bet[c], yv[k][c], u);

@@ -115,8 +115,10 @@ __global__ __launch_bounds__(256) void k_render(
     rg.x = (uint32_t)__builtin_amdgcn_readfirstlane((int)rg.x);
     rg.y = (uint32_t)__builtin_amdgcn_readfirstlane((int)rg.y);
     uint32_t cnt = 0;
-    const float qlim = (float)(kExp2Scale * (double)bp.cut2);
-    const float amax = bp.alpha_max, amin = bp.alpha_min, tmin = bp.t_min;
+    // loop constants in vector registers (see uniform_in_vgpr)
+    const float qlim = uniform_in_vgpr((float)(kExp2Scale * (double)bp.cut2));
+    const float amax = uniform_in_vgpr(bp.alpha_max), amin = uniform_in_vgpr(bp.alpha_min),
+                tmin = uniform_in_vgpr(bp.t_min);
     // the lane's pixel offsets from the tile's centre point; R0 below keeps,
     // per entry, the offset of that point from the projected centre
     const float lx = tile_offset_col(lane);

@@ -230,6 +230,14 @@ __device__ __forceinline__ float tile_offset_row(uint32_t lane, int k) {
     return (float)((lane >> 4) + 4 * k) - 7.5f;
 }
 
+// A wave-uniform loop constant held in a vector register: the identity DPP
+// move makes the compiler treat it as a per-lane value, so it takes one VGPR
+// instead of a scalar register that the inner loops, short of scalar
+// registers, would otherwise spill to vector lanes and reload every iteration.
+__device__ __forceinline__ float uniform_in_vgpr(float x) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xE4, 0xF, 0xF, true));
+}
+
 __device__ __forceinline__ float pixel_step(float q2, float opac, float& T, float qlim, float amin,
                                             float amax, float tmin, uint64_t& taken) {
     const float al = __builtin_amdgcn_fmed3f(opac * __builtin_amdgcn_exp2f(q2), 0.0f, amax);
