@@ -168,6 +168,8 @@ def _targets(targets):
     t = np.ascontiguousarray(targets)
     if t.dtype == np.uint16:
         return t, 1
+    if t.dtype == np.float64:
+        return t, 2
     return np.ascontiguousarray(t, np.float32), 0
 
 
@@ -215,6 +217,57 @@ def colorize(scene, targets, want: Optional[np.ndarray] = None, opts: Optional[O
         raise ValueError("oracle colorize rejected its arguments")
     return dict(coeffs=coeffs, status=status, A=A, B=B, w=w, flip=flip, kappa=kappa, cnt=cnt,
                 ndec=ndec, count=int(stats[0]), events=int(stats[1]))
+
+
+def expand_lambda(lam, L: int) -> np.ndarray:
+    """Lambda per coefficient (l*l + l + m) from 1, L+1 or (L+1)^2 values."""
+    lam = np.asarray(lam, np.float64).reshape(-1)
+    nb = (L + 1) ** 2
+    if lam.size == 1:
+        return np.full(nb, lam[0])
+    if lam.size == L + 1:
+        return np.concatenate([np.full(2 * l + 1, lam[l]) for l in range(L + 1)])
+    return lam.copy()
+
+
+def refine_step(scene, targets, coeffs, first, opts: Optional[Options] = None, lam=None,
+                threads=None):
+    """One refinement pass (Algorithm 1, steps 8-10) from coefficients
+    `coeffs`: render them, take the residual targets (decoded targets minus
+    the render, FP64), accumulate the right-hand side B_g of the residual and
+    update c_g <- c_g + (A_g + w_g Lambda)^{-1} (B_g - w_g Lambda c_g) with
+    the regularised normal matrix A and visibilities w of the first pass
+    (`first`, an oracle colorize of the same scene).  Unobserved Gaussians and
+    failed factorisations keep their coefficients."""
+    lam = scene.lam if lam is None else lam
+    lam_full = expand_lambda(lam, scene.sh_deg)
+    y = decode_targets(targets).astype(np.float64)
+    c = np.array(coeffs, np.float64, copy=True)
+    img = render(scene, c, opts=opts, threads=threads)
+    res = colorize(scene, y - img, opts=opts, lam=lam, threads=threads)
+    for g in np.flatnonzero((first["status"] & 5) == 0):
+        rhs = res["B"][g] - first["w"][g] * lam_full[:, None] * c[g]
+        c[g] = c[g] + solve(first["A"][g], rhs)
+    return c
+
+
+def refine(scene, targets, n_steps: int, opts: Optional[Options] = None, lam=None, threads=None,
+           return_all: bool = False):
+    """Colorization with iterative refinement (Algorithm 1: steps 1-6, then
+    n_steps refinement passes, refine_step).  Returns the colorize dict of the
+    first pass with coeffs replaced by the refined ones (and, with return_all,
+    `history`: the coefficients after every pass, the first one included)."""
+    first = colorize(scene, targets, opts=opts, lam=lam, threads=threads)
+    c = first["coeffs"]
+    history = [c.copy()]
+    for _ in range(n_steps):
+        c = refine_step(scene, targets, c, first, opts=opts, lam=lam, threads=threads)
+        history.append(c.copy())
+    out = dict(first)
+    out["coeffs"] = c
+    if return_all:
+        out["history"] = history
+    return out
 
 
 def render(scene, coeffs, opts: Optional[Options] = None, threads=None, with_bound: bool = False):

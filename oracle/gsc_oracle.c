@@ -641,7 +641,9 @@ static double jacobi_cond(int n, const double* A) {
     return lo > 0.0 ? hi / lo : INFINITY;
 }
 
+/* tdtype 0: float32, 1: bfloat16 bits, 2: float64 */
 static double target_at(const void* targets, int tdtype, int64_t row, int C, int c) {
+    if (tdtype == 2) return ((const double*)targets)[row * C + c];
     if (tdtype == 1) {
         uint16_t b = ((const uint16_t*)targets)[row * C + c];
         uint32_t u = (uint32_t)b << 16;
@@ -687,7 +689,8 @@ static uint8_t* wanted_mask(const scene_t* sc, const oc_camera* cam, const oc_op
 /* Colorize: Algorithm 1 steps 1-6                                     */
 /* ------------------------------------------------------------------ */
 /*
- * targets: [sum_j H_j W_j, C] float32 (tdtype 0) or bfloat16 bits (tdtype 1),
+ * targets: [sum_j H_j W_j, C] float32 (tdtype 0), bfloat16 bits (tdtype 1) or float64
+ *          (tdtype 2),
  *          camera j's pixels start at cams[j].pixel_offset, row-major.
  * lam:     n_lambda in {1, L+1, (L+1)^2} (per coefficient / band / all).
  * want:    N bytes or NULL; only Gaussians with want[g] != 0 are solved.
