@@ -237,6 +237,34 @@ gsc_status gsc_colorize_ex(gsc_ctx* ctx, const float* means, const float* scales
                            const gsc_extras* extras, gsc_stream_t stream);
 
 /*
+ * Colorize with iterative refinement (Algorithm 1: steps 1-6, then n_refine
+ * passes of steps 8-10; Sec. 3 "Iterative Refinement").  After the first
+ * pass each refinement pass renders the current coefficients (eqs. 1-3),
+ * accumulates the right-hand side B_g of the residual targets (targets minus
+ * that render) and updates
+ *   c_g <- c_g + (A_g + w_g Lambda)^{-1} (B_g - w_g Lambda c_g)
+ * with the Cholesky factor of the first pass, kept on the device: the
+ * geometry, hence A_g and w_g, does not change.  The fixed point is the
+ * coupled regularised least-squares solution over all Gaussians, in which the
+ * colours of overlapping transparent splats mix.
+ *   Arguments as for gsc_colorize, plus n_refine in [0, 10000] (0: the same
+ *   as gsc_colorize).  coeffs receives the refined coefficients; status, the
+ *   first pass's bits (may be NULL).
+ * Unobserved Gaussians and failed factorisations keep zero coefficients.
+ * Scratch beyond gsc_colorize's: one FP32 image of the targets' size and,
+ * for L >= 1, ((L+1)^2 ((L+1)^2 + 1) / 2 + 1) doubles per Gaussian.  A call
+ * with one view batch bins once; otherwise every pass bins each batch again.
+ * gsc_get_stats reports the first pass's counts; its stage times cover every
+ * pass.
+ */
+gsc_status gsc_colorize_refine(gsc_ctx* ctx, const float* means, const float* scales,
+                               const float* quats, const float* opacities, int64_t N,
+                               const gsc_camera* cams, int32_t n_cams, const void* targets,
+                               int32_t tdtype, int32_t C, int32_t sh_deg, const float* lambda,
+                               int32_t n_lambda, int32_t n_refine, float* coeffs, uint8_t* status,
+                               gsc_stream_t stream);
+
+/*
  * gsc_colorize for callers that cannot allocate memory (code under graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * computation and arguments as gsc_colorize, with every scratch buffer taken

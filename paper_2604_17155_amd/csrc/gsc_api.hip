@@ -141,7 +141,7 @@ struct gsc_ctx {
     // device scratch
     DevBuf views, views_all, cov, keys, vals, keys_alt, vals_alt, counts, offsets, rec0, rec1, rec2,
         sort_scratch, pkeys, pvals, pkeys_alt, pvals_alt, ranges, vs, gamma, bbar, misc, order, queues,
-        coef_t;
+        coef_t, factor, img, stat, wbuf;
     bool order_valid = false;  // `order` holds the tile order of the current binning
     // host staging
     ViewInfo* h_views = nullptr;  // staging of one batch's table
@@ -162,10 +162,11 @@ struct gsc_ctx {
     size_t ev_used = 0;
     struct Mark { int stage; hipEvent_t a, b; uint32_t launches; };
     std::vector<Mark> marks;
-    std::array<DevBuf*, 25> bufs() {
+    std::array<DevBuf*, 29> bufs() {
         return {&views, &views_all, &cov, &keys, &vals, &keys_alt, &vals_alt, &counts,
                 &offsets, &rec0, &rec1, &rec2, &sort_scratch, &pkeys, &pvals, &pkeys_alt,
-                &pvals_alt, &ranges, &vs, &gamma, &bbar, &misc, &order, &queues, &coef_t};
+                &pvals_alt, &ranges, &vs, &gamma, &bbar, &misc, &order, &queues, &coef_t,
+                &factor, &img, &stat, &wbuf};
     }
     ~gsc_ctx() {
         for (DevBuf* b : bufs()) b->release();
@@ -949,7 +950,7 @@ gsc_status colorize_core(gsc_ctx* ctx, const float* means, const float* scales,
                          const gsc_camera* cams, int32_t n_cams, const void* targets,
                          int32_t tdtype, int32_t C, int32_t sh_deg, const double* lam,
                          float* coeffs, uint8_t* status, const gsc_extras* extras, hipStream_t s,
-                         const BinKey* key, bool reuse, ViewInfo* all) {
+                         const BinKey* key, bool reuse, ViewInfo* all, double* factor = nullptr) {
     gsc_status st;
     float* x_sums = extras ? extras->view_sums : nullptr;
     float* x_vis = extras ? extras->visibility : nullptr;
@@ -999,7 +1000,7 @@ gsc_status colorize_core(gsc_ctx* ctx, const float* means, const float* scales,
     StageTimer t_solve(ctx, s, GSC_STAGE_SOLVE);
     launch_fold_solve(ctx->views_all.as<ViewInfo>(), per_view ? n_cams : 0, means, ctx->vs.as<float>(),
                       per_view, N, C, sh_deg, lam, ctx->opt.kappa_max, coeffs, status, x_vis,
-                      dc_scratch, d_ill, s);
+                      dc_scratch, d_ill, s, factor);
     GSC_LAUNCHED("fold/solve");
     ctx->stats_pending = true;
     ctx->stats_dev = nullptr;
@@ -1149,6 +1150,108 @@ gsc_status gsc_colorize(gsc_ctx* ctx, const float* means, const float* scales, c
                         gsc_stream_t stream) {
     return gsc_colorize_ex(ctx, means, scales, quats, opacities, N, cams, n_cams, targets, tdtype,
                            C, sh_deg, lambda, n_lambda, coeffs, status, nullptr, stream);
+}
+
+gsc_status gsc_colorize_refine(gsc_ctx* ctx, const float* means, const float* scales,
+                               const float* quats, const float* opacities, int64_t N,
+                               const gsc_camera* cams, int32_t n_cams, const void* targets,
+                               int32_t tdtype, int32_t C, int32_t sh_deg, const float* lambda,
+                               int32_t n_lambda, int32_t n_refine, float* coeffs, uint8_t* status,
+                               gsc_stream_t stream) {
+    if (!ctx) return fail(GSC_ERR_INVALID_ARG, "null ctx");
+    double lam[kMaxNb];
+    gsc_status st = validate_colorize(means, scales, quats, opacities, N, cams, n_cams, targets,
+                                      tdtype, C, sh_deg, lambda, n_lambda, coeffs, lam);
+    if (st != GSC_OK) return st;
+    if (n_refine < 0 || n_refine > 10000) return fail(GSC_ERR_INVALID_ARG, "n_refine must be in [0, 10000] (got %d)", n_refine);
+    if (ctx->opt.flags & GSC_FLAG_VALIDATE_ONLY) return GSC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = refuse_capture(s, "gsc_colorize_refine")) != GSC_OK) return st;
+    memset(&ctx->stats, 0, sizeof(ctx->stats));
+    if (N == 0) return GSC_OK;
+    const BinKey key = make_key(ctx, means, scales, quats, opacities, N, cams, n_cams, blend_params(ctx->opt));
+    const bool reuse = can_reuse(ctx, key);
+    std::vector<ViewInfo> all(std::max(n_cams, 1));
+    // first pass (Algorithm 1, steps 1-6), keeping w_g, the statuses and the factor
+    GSC_HIP(ctx->wbuf.ensure(4 * (size_t)N));
+    if (!status) {
+        GSC_HIP(ctx->stat.ensure((size_t)N));
+        status = ctx->stat.as<uint8_t>();
+    }
+    double* factor = nullptr;
+    if (sh_deg > 0) {
+        GSC_HIP(ctx->factor.ensure(8 * (size_t)N * (size_t)refine_factor_words(sh_deg)));
+        factor = ctx->factor.as<double>();
+    }
+    gsc_extras ex;
+    ex.view_sums = nullptr;
+    ex.visibility = ctx->wbuf.as<float>();
+    ex.counts = nullptr;
+    st = colorize_core(ctx, means, scales, quats, opacities, N, cams, n_cams, targets, tdtype, C,
+                       sh_deg, lam, coeffs, status, &ex, s, &key, reuse, all.data(), factor);
+    if (st != GSC_OK || n_refine == 0 || n_cams == 0) return st;
+    // refinement passes (steps 8-10): render, residual, accumulate, update.
+    // The binning of a call with one view batch stays in place; otherwise each
+    // pass bins every batch again (once for its render and accumulate).
+    const bool single = ctx->cache_valid && ctx->cache_key.same(key);
+    const int nb = (sh_deg + 1) * (sh_deg + 1);
+    const int kc = nb * C;
+    const bool per_view = sh_deg > 0;
+    int64_t rows = 0;
+    for (int j = 0; j < n_cams; ++j) rows = std::max<int64_t>(rows, cams[j].pixel_offset + (int64_t)cams[j].width * cams[j].height);
+    GSC_HIP(ctx->coef_t.ensure(4 * (size_t)N * (size_t)kc));
+    GSC_HIP(ctx->img.ensure(4 * (size_t)rows * (size_t)C));
+    const uint64_t vs_words = (uint64_t)(per_view ? n_cams : 1) * (uint64_t)N * (uint64_t)(C + 1);
+    BlendParams bp = blend_params(ctx->opt);
+    // the passes count their contributions apart: the statistics stay the first pass's
+    unsigned long long* d_pass_counter = reinterpret_cast<unsigned long long*>(ctx->misc.as<char>() + 24);
+    const int chunk = resolve_chunk(ctx->opt.accumulate_variant, C, GSC_F32);
+    const gsc_stats first = ctx->stats;
+    for (int step = 0; step < n_refine; ++step) {
+        launch_transpose(coeffs, N, kc, ctx->coef_t.as<float>(), s);
+        launch_fill_u32(ctx->vs.as<uint32_t>(), 0u, vs_words, s);
+        GSC_LAUNCHED("refinement setup");
+        st = for_view_batches(ctx, all.data(), n_cams, means, opacities, N, bp, s,
+                              [&](int v0, int nv, const Binned& bn) -> gsc_status {
+            GSC_HIP(ctx->gamma.ensure(4 * (size_t)nv * (size_t)N * (size_t)C));
+            int max_px = 0;
+            for (int k = 0; k < nv; ++k) max_px = std::max(max_px, all[v0 + k].width * all[v0 + k].height);
+            const uint32_t* order = tile_order(ctx, bn.n_tiles);
+            StageTimer t(ctx, s, GSC_STAGE_BLEND);
+            launch_view_colors(ctx->views.as<ViewInfo>(), nv, (uint32_t)bn.n_items, means,
+                               ctx->coef_t.as<float>(), N, C, sh_deg, ctx->gamma.as<float>(), s);
+            launch_render(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
+                          ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(),
+                          ctx->rec2.as<uint2>(), ctx->bin, ctx->gamma.as<float>(), C, bp,
+                          ctx->img.as<float>(), d_pass_counter, s, order);
+            launch_residual(ctx->views.as<ViewInfo>(), nv, max_px, targets, tdtype, C, ctx->img.as<float>(), s);
+            uint32_t* queues = nullptr;
+            if (order != nullptr && (chunk & kChunkMfma)) {
+                GSC_HIP(ctx->queues.ensure(4 * (size_t)(kMaxC + 1)));
+                queues = ctx->queues.as<uint32_t>();
+            }
+            launch_accumulate_chunked(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
+                                      ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(),
+                                      ctx->rec1.as<float4>(), ctx->rec2.as<uint2>(), ctx->bin,
+                                      ctx->img.as<float>(), GSC_F32, C, per_view, bp, ctx->vs.as<float>(),
+                                      d_pass_counter, nullptr, chunk, s, queues, order);
+            GSC_LAUNCHED("refinement pass");
+            (void)v0;
+            return GSC_OK;
+        }, &key, single);
+        if (st != GSC_OK) return st;
+        StageTimer t(ctx, s, GSC_STAGE_SOLVE);
+        launch_refine_update(ctx->views_all.as<ViewInfo>(), n_cams, means, ctx->vs.as<float>(), N, C,
+                             sh_deg, lam, factor, ctx->wbuf.as<float>(), status, coeffs, s);
+        GSC_LAUNCHED("refinement update");
+    }
+    // statistics of the first pass (batches and pairs counted once)
+    const gsc_stats last = ctx->stats;
+    ctx->stats = first;
+    for (int i = 0; i < GSC_N_STAGES; ++i) ctx->stats.stage_ms[i] = last.stage_ms[i];
+    ctx->stats_pending = true;
+    ctx->stats_dev = nullptr;
+    return GSC_OK;
 }
 
 gsc_status gsc_render(gsc_ctx* ctx, const float* means, const float* scales, const float* quats,

@@ -200,10 +200,34 @@ void launch_render(const ViewInfo* views, int n_views, uint32_t n_tiles, const u
 // per_view: VS holds [n_views][N][C+1] (else [N][C+1] summed over views).
 // wout (optional): w_g = sum_j V_gj.  dc_scratch: N*(C+1) floats, used when
 // sh_deg == 0 and per_view.
+// factor (optional, sh_deg >= 1): per Gaussian the Cholesky factor of
+// A_g + w_g Lambda, packed by rows (row i at i (i + 1) / 2, 1/L_ii on the
+// diagonal), then w_g: refine_factor_words(sh_deg) doubles.
 void launch_fold_solve(const ViewInfo* views, int n_views, const float* means, const float* VS,
                        bool per_view, int64_t N, int C, int sh_deg, const double* lam_nb /*host, nb*/,
                        float kappa_max, float* coeffs, uint8_t* status, float* wout,
-                       float* dc_scratch, unsigned int* ill_count, hipStream_t s);
+                       float* dc_scratch, unsigned int* ill_count, hipStream_t s,
+                       double* factor = nullptr);
+inline int refine_factor_words(int sh_deg) {
+    const int nb = (sh_deg + 1) * (sh_deg + 1);
+    return nb * (nb + 1) / 2 + 1;
+}
+
+// One refinement update (Algorithm 1, step 10): with the per-view sums VS of
+// the residual targets (as for launch_fold_solve; per_view when sh_deg >= 1),
+//   c_g += (A_g + w_g Lambda)^{-1} (sum_j phi_gj S_gj^T - w_g Lambda c_g)
+// using the stored factor (sh_deg >= 1) or w (sh_deg == 0, where the matrix is
+// w_g (Y0^2 + lambda_0)).  Gaussians whose status has UNOBSERVED or FAILED
+// are left alone.
+void launch_refine_update(const ViewInfo* views, int n_views, const float* means, const float* VS,
+                          int64_t N, int C, int sh_deg, const double* lam_nb, const double* factor,
+                          const float* w, const uint8_t* status, float* coeffs, hipStream_t s);
+
+// Residual targets of the views of a batch, in place: img[row][c] =
+// y[row][c] - img[row][c] for every pixel of the n_views views (y float32
+// or bfloat16).
+void launch_residual(const ViewInfo* views, int n_views, int max_pixels, const void* y, int ydtype,
+                     int C, float* img, hipStream_t s);
 
 // Weights-only accumulate: V[slot] += sum_p w (stride 1; slots as in launch_accumulate).
 void launch_accumulate_weights(const ViewInfo* views, int n_views, uint32_t n_tiles,

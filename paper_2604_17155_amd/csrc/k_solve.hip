@@ -9,6 +9,8 @@
 // cooperative FP64 Cholesky and solves four right-hand-side columns at a
 // time, all in registers; the factor stays there for further channel chunks.
 // L = 0: A_g = w_g Y0^2 is a scalar and c_g = Y0 S_g / (w_g (Y0^2 + lambda_0)).
+#include <algorithm>
+
 #include "gsc_internal.h"
 #include "sh.h"
 
@@ -108,7 +110,8 @@ __global__ __launch_bounds__(256) void k_fold_solve(const ViewInfo* __restrict__
                                                     float* __restrict__ rho,
                                                     uint8_t* __restrict__ status,
                                                     float* __restrict__ wout,
-                                                    unsigned int* __restrict__ ill_count) {
+                                                    unsigned int* __restrict__ ill_count,
+                                                    double* __restrict__ factor) {
     constexpr int NB = (L + 1) * (L + 1);
     constexpr int RPL = (NB + 3) / 4;  // rows per lane
     const int r = threadIdx.x & 3;
@@ -267,6 +270,22 @@ __global__ __launch_bounds__(256) void k_fold_solve(const ViewInfo* __restrict__
                         }
                 }
             }
+            // keep the factor for refinement: row i at i (i + 1) / 2, 1/L_ii
+            // on the diagonal, then w_g
+            if constexpr (!ADJ) {
+                if (factor != nullptr && valid) {
+                    constexpr int NT = NB * (NB + 1) / 2;
+                    double* F = factor + g * (int64_t)(NT + 1);
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k) {
+                        const int i = 4 * k + r;
+#pragma unroll
+                        for (int j = 0; j < NB; ++j)
+                            if (j < 4 * k + 4 && j <= i && i < NB) F[i * (i + 1) / 2 + j] = accA[k][j];
+                    }
+                    if (r == 0) F[NT] = wsum;
+                }
+            }
         }
         if constexpr (ADJ) {
 #pragma unroll
@@ -384,7 +403,7 @@ __global__ __launch_bounds__(256) void k_fold_solve(const ViewInfo* __restrict__
 void launch_fold_solve(const ViewInfo* views, int n_views, const float* means, const float* VS,
                        bool per_view, int64_t N, int C, int sh_deg, const double* lam_nb,
                        float kappa_max, float* coeffs, uint8_t* status, float* wout,
-                       float* dc_scratch, unsigned int* ill_count, hipStream_t s) {
+                       float* dc_scratch, unsigned int* ill_count, hipStream_t s, double* factor) {
     if (N <= 0) return;
     if (sh_deg == 0) {
         const float* src = VS;
@@ -408,10 +427,151 @@ void launch_fold_solve(const ViewInfo* views, int n_views, const float* means, c
     const float* nf = nullptr;
     float* nw = nullptr;
     switch (sh_deg) {
-        case 1: hipLaunchKernelGGL((k_fold_solve<1, false>), grid, block, 0, s, views, n_views, means, VS, C + 1, N, C, lam, kappa_max, nf, nf, coeffs, nw, status, wout, ill_count); break;
-        case 2: hipLaunchKernelGGL((k_fold_solve<2, false>), grid, block, 0, s, views, n_views, means, VS, C + 1, N, C, lam, kappa_max, nf, nf, coeffs, nw, status, wout, ill_count); break;
-        default: hipLaunchKernelGGL((k_fold_solve<3, false>), grid, block, 0, s, views, n_views, means, VS, C + 1, N, C, lam, kappa_max, nf, nf, coeffs, nw, status, wout, ill_count); break;
+        case 1: hipLaunchKernelGGL((k_fold_solve<1, false>), grid, block, 0, s, views, n_views, means, VS, C + 1, N, C, lam, kappa_max, nf, nf, coeffs, nw, status, wout, ill_count, factor); break;
+        case 2: hipLaunchKernelGGL((k_fold_solve<2, false>), grid, block, 0, s, views, n_views, means, VS, C + 1, N, C, lam, kappa_max, nf, nf, coeffs, nw, status, wout, ill_count, factor); break;
+        default: hipLaunchKernelGGL((k_fold_solve<3, false>), grid, block, 0, s, views, n_views, means, VS, C + 1, N, C, lam, kappa_max, nf, nf, coeffs, nw, status, wout, ill_count, factor); break;
     }
+}
+
+// ---- refinement (Algorithm 1, steps 8-10) --------------------------------
+//
+// One thread per Gaussian: fold the residual's per-view sums into
+// B = sum_j phi_gj S_gj^T in FP64 (four channels at a time, the SH values of
+// each view evaluated as in the fold above), form B - w_g Lambda c_g and solve
+// with the factor stored by the first pass (forward substitution L y = rhs,
+// back substitution L^T x = y, 1/L_ii kept on the diagonal), then c_g += x.
+template <int L>
+__global__ __launch_bounds__(256) void k_refine_update(const ViewInfo* __restrict__ views, int n_views,
+                                                       const float* __restrict__ means,
+                                                       const float* __restrict__ VS, int64_t N, int C,
+                                                       LamNB lam, const double* __restrict__ factor,
+                                                       const uint8_t* __restrict__ status,
+                                                       float* __restrict__ coeffs) {
+    constexpr int NB = (L + 1) * (L + 1);
+    constexpr int NT = NB * (NB + 1) / 2;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= N) return;
+    if (status[g] & (GSC_G_UNOBSERVED | GSC_G_FAILED)) return;
+    const double* F = factor + g * (int64_t)(NT + 1);
+    const double wg = F[NT];
+    const float mx = means[3 * g], my = means[3 * g + 1], mz = means[3 * g + 2];
+    const int stride = C + 1;
+    const int64_t vstep = N * (int64_t)stride;
+    float* out = coeffs + g * NB * C;
+    for (int c0 = 0; c0 < C; c0 += 4) {
+        double b[NB][4];
+#pragma unroll
+        for (int m = 0; m < NB; ++m)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) b[m][c] = 0.0;
+        for (int v = 0; v < n_views; ++v) {
+            const float* p = VS + (int64_t)v * vstep + g * stride;
+            if (p[0] == 0.0f) continue;  // no contribution in this view
+            const float dx = mx - (float)views[v].centre[0];
+            const float dy = my - (float)views[v].centre[1];
+            const float dz = mz - (float)views[v].centre[2];
+            const float inv = rsqrtf(dx * dx + dy * dy + dz * dz);
+            double ph[NB];
+            sh_eval<double, L>((double)(dx * inv), (double)(dy * inv), (double)(dz * inv), ph);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double sc = c0 + c < C ? (double)p[1 + c0 + c] : 0.0;
+#pragma unroll
+                for (int m = 0; m < NB; ++m) b[m][c] = fma(ph[m], sc, b[m][c]);
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < NB; ++m)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (c0 + c < C) b[m][c] = fma(-wg * lam.v[m], (double)out[m * C + c0 + c], b[m][c]);
+        // L y = rhs
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                double t = b[i][c];
+#pragma unroll
+                for (int j = 0; j < i; ++j) t = fma(-F[i * (i + 1) / 2 + j], b[j][c], t);
+                b[i][c] = t * F[i * (i + 1) / 2 + i];
+            }
+        }
+        // L^T x = y
+#pragma unroll
+        for (int i = NB - 1; i >= 0; --i) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                double t = b[i][c];
+#pragma unroll
+                for (int k = i + 1; k < NB; ++k) t = fma(-F[k * (k + 1) / 2 + i], b[k][c], t);
+                b[i][c] = t * F[i * (i + 1) / 2 + i];
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < NB; ++m)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (c0 + c < C) out[m * C + c0 + c] = (float)((double)out[m * C + c0 + c] + b[m][c]);
+    }
+}
+
+// L = 0: the matrix is w_g (Y0^2 + lambda_0) and B = Y0 S_g (VS summed over views).
+__global__ void k_refine_update_dc(const float* __restrict__ VS, int64_t N, int C, double lam0,
+                                   const float* __restrict__ w, const uint8_t* __restrict__ status,
+                                   float* __restrict__ coeffs) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= N) return;
+    if (status[g] & (GSC_G_UNOBSERVED | GSC_G_FAILED)) return;
+    const double wg = w[g];
+    const float* sg = VS + g * (int64_t)(C + 1);
+    const double den = wg * (kY0 * kY0 + lam0);
+    for (int c = 0; c < C; ++c) {
+        const double cg = coeffs[g * C + c];
+        coeffs[g * C + c] = (float)(cg + (kY0 * (double)sg[1 + c] - wg * lam0 * cg) / den);
+    }
+}
+
+void launch_refine_update(const ViewInfo* views, int n_views, const float* means, const float* VS,
+                          int64_t N, int C, int sh_deg, const double* lam_nb, const double* factor,
+                          const float* w, const uint8_t* status, float* coeffs, hipStream_t s) {
+    if (N <= 0) return;
+    const dim3 grid((unsigned)((N + 255) / 256)), block(256);
+    if (sh_deg == 0) {
+        hipLaunchKernelGGL(k_refine_update_dc, grid, block, 0, s, VS, N, C, lam_nb[0], w, status, coeffs);
+        return;
+    }
+    LamNB lam;
+    for (int i = 0; i < kMaxNb; ++i) lam.v[i] = 0.0;
+    const int nb = (sh_deg + 1) * (sh_deg + 1);
+    for (int i = 0; i < nb; ++i) lam.v[i] = lam_nb[i];
+    switch (sh_deg) {
+        case 1: hipLaunchKernelGGL((k_refine_update<1>), grid, block, 0, s, views, n_views, means, VS, N, C, lam, factor, status, coeffs); break;
+        case 2: hipLaunchKernelGGL((k_refine_update<2>), grid, block, 0, s, views, n_views, means, VS, N, C, lam, factor, status, coeffs); break;
+        default: hipLaunchKernelGGL((k_refine_update<3>), grid, block, 0, s, views, n_views, means, VS, N, C, lam, factor, status, coeffs); break;
+    }
+}
+
+// Residual targets in place over the pixels of a batch's views (grid y: view).
+__global__ __launch_bounds__(256) void k_residual(const ViewInfo* __restrict__ views, const void* __restrict__ y,
+                                                  int ydtype, int C, float* __restrict__ img) {
+    const ViewInfo& V = views[blockIdx.y];
+    const int64_t n = (int64_t)V.width * V.height * C;
+    const int64_t base = V.pixel_offset * (int64_t)C;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = base + i;
+        const float yv = ydtype == GSC_BF16 ? __uint_as_float((uint32_t)((const uint16_t*)y)[e] << 16)
+                                            : ((const float*)y)[e];
+        img[e] = yv - img[e];
+    }
+}
+
+void launch_residual(const ViewInfo* views, int n_views, int max_pixels, const void* y, int ydtype,
+                     int C, float* img, hipStream_t s) {
+    if (n_views <= 0 || max_pixels <= 0) return;
+    const int64_t per = (int64_t)max_pixels * C;
+    const unsigned bx = (unsigned)std::min<int64_t>((per + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_residual, dim3(bx, (unsigned)n_views), dim3(256), 0, s, views, y, ydtype, C, img);
 }
 
 // L = 0 adjoint: A_g + w_g Lambda = w_g (Y0^2 + lambda_0).
@@ -457,9 +617,9 @@ void launch_adjoint_solve(const ViewInfo* views, int n_views, const float* means
     float* nw = nullptr;
     unsigned int* ni = nullptr;
     switch (sh_deg) {
-        case 1: hipLaunchKernelGGL((k_fold_solve<1, true>), grid, block, 0, s, views, n_views, means, V, 1, N, C, lam, 0.0f, grad_coeffs, coeffs, bbar, rho, ns, nw, ni); break;
-        case 2: hipLaunchKernelGGL((k_fold_solve<2, true>), grid, block, 0, s, views, n_views, means, V, 1, N, C, lam, 0.0f, grad_coeffs, coeffs, bbar, rho, ns, nw, ni); break;
-        default: hipLaunchKernelGGL((k_fold_solve<3, true>), grid, block, 0, s, views, n_views, means, V, 1, N, C, lam, 0.0f, grad_coeffs, coeffs, bbar, rho, ns, nw, ni); break;
+        case 1: hipLaunchKernelGGL((k_fold_solve<1, true>), grid, block, 0, s, views, n_views, means, V, 1, N, C, lam, 0.0f, grad_coeffs, coeffs, bbar, rho, ns, nw, ni, nullptr); break;
+        case 2: hipLaunchKernelGGL((k_fold_solve<2, true>), grid, block, 0, s, views, n_views, means, V, 1, N, C, lam, 0.0f, grad_coeffs, coeffs, bbar, rho, ns, nw, ni, nullptr); break;
+        default: hipLaunchKernelGGL((k_fold_solve<3, true>), grid, block, 0, s, views, n_views, means, V, 1, N, C, lam, 0.0f, grad_coeffs, coeffs, bbar, rho, ns, nw, ni, nullptr); break;
     }
 }
 

@@ -112,6 +112,8 @@ def load(path: Optional[str] = None):
     lib.gsc_colorize_ex.argtypes = [P, P, P, P, P, i64, P, i32, P, i32, i32, i32, P, i32, P, P,
                                     ct.POINTER(GscExtras), P]
     lib.gsc_colorize_ex.restype = ct.c_int
+    lib.gsc_colorize_refine.argtypes = [P, P, P, P, P, i64, P, i32, P, i32, i32, i32, P, i32, i32, P, P, P]
+    lib.gsc_colorize_refine.restype = ct.c_int
     lib.gsc_colorize_noalloc.argtypes = [P, P, P, P, P, i64, P, i32, P, i32, i32, i32, P, i32, P, P, P]
     lib.gsc_colorize_noalloc.restype = ct.c_int
     lib.gsc_render.argtypes = [P, P, P, P, P, i64, P, i32, P, i32, i32, P, P]
@@ -293,6 +295,27 @@ class Context:
         _check(self.lib, st)
         if xd is not None:
             return coeffs, status, xd
+        return coeffs, status
+
+    def colorize_refine(self, means, scales, quats, opacities, cams, targets, sh_deg: int, lam,
+                        n_refine: int, coeffs=None, status=None, offsets=None, stream=None):
+        """Colorize, then n_refine refinement passes (gsc_colorize_refine).
+        Returns (coeffs [N,(L+1)^2,C] float32, status [N] uint8)."""
+        import torch
+        N = int(means.shape[0])
+        C = int(targets.shape[1])
+        nb = (sh_deg + 1) ** 2
+        if coeffs is None:
+            coeffs = torch.empty((N, nb, C), dtype=torch.float32, device=means.device)
+        if status is None:
+            status = torch.empty((N,), dtype=torch.uint8, device=means.device)
+        lam_a = (ct.c_float * len(lam))(*[float(v) for v in lam])
+        cam_arr = make_cameras(cams, offsets)
+        st = self.lib.gsc_colorize_refine(self.handle, _ptr(means), _ptr(scales), _ptr(quats),
+                                          _ptr(opacities), N, cam_arr, len(cams), _ptr(targets),
+                                          _tdtype(targets), C, sh_deg, lam_a, len(lam), int(n_refine),
+                                          _ptr(coeffs), _ptr(status), _stream_ptr(stream))
+        _check(self.lib, st)
         return coeffs, status
 
     def colorize_noalloc(self, means, scales, quats, opacities, cams, targets, sh_deg: int, lam,

@@ -243,3 +243,17 @@ def test_batch_limit_options(lib):
         assert (st == gsc.GSC_OK) == ok, over
         if st == gsc.GSC_OK:
             lib.gsc_ctx_destroy(h)
+
+
+def test_refine_validation(lib):
+    ctx = _vctx()
+    cams = syn.circle_cams(2, 3.0, 16, 16)
+    arr = gsc.make_cameras(cams)
+    lam_a = (ct.c_float * 1)(1e-4)
+
+    def call(n_refine, C=3):
+        return lib.gsc_colorize_refine(ctx.handle, FAKE, FAKE, FAKE, FAKE, 10, arr, 2, FAKE, 0, C, 0,
+                                       lam_a, 1, n_refine, FAKE, None, None)
+    assert call(0) == gsc.GSC_OK and call(5) == gsc.GSC_OK
+    assert call(-1) == gsc.GSC_ERR_INVALID_ARG and "n_refine" in lib.gsc_last_error().decode()
+    assert call(3, C=0) == gsc.GSC_ERR_INVALID_ARG
