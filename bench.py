@@ -540,9 +540,9 @@ def workload_diff(args, gsc):
     o_p = o.clone().requires_grad_(True)
     y_p = y1.clone().requires_grad_(True)
 
-    def step():
-        c = ag.colorize(y_p, o_p, m, s, q, sc.cams, sc.sh_deg, lam, context=ctx)
-        img = ag.render(c, o_p, m, s, q, sc.cams, context=ctx)
+    def step():  # geometry and opacities stay fixed here, so the tile lists are reused
+        c = ag.colorize(y_p, o_p, m, s, q, sc.cams, sc.sh_deg, lam, context=ctx, reuse_binning=True)
+        img = ag.render(c, o_p, m, s, q, sc.cams, context=ctx, reuse_binning=True)
         loss = ((img - y2) ** 2).mean()
         y_p.grad = None
         o_p.grad = None

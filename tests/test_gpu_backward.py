@@ -270,6 +270,35 @@ def test_binning_reuse(gsc_mod):
     assert projected(ctx) > 0
 
 
+def test_autograd_sees_data_edits(gsc_mod):
+    """The autograd wrappers bin anew on every call unless asked not to, so an
+    opacity update written through `.data` (which leaves torch's version
+    counter alone) reaches the next call's coefficients."""
+    import torch
+    from paper_2604_17155_amd import autograd as ag
+    sc = syn.make_relight(seed_offset=37, n=5000, n_cams=6, res=128)
+    y = _dev(oracle.make_targets(sc))
+    m, s, q, o = gsc_mod.scene_tensors(sc)
+    lam = list(sc.lam)
+    ctx = gsc_mod.Context(flags=gsc_mod.GSC_FLAG_PROFILE)
+    fresh = gsc_mod.Context()
+    o_p = o.clone().requires_grad_(True)
+    ag.colorize(y, o_p, m, s, q, sc.cams, sc.sh_deg, lam, context=ctx)
+    v0 = o_p._version
+    o_p.data.mul_(0.7)
+    assert o_p._version == v0  # the write is invisible to the version guard
+    c2 = ag.colorize(y, o_p, m, s, q, sc.cams, sc.sh_deg, lam, context=ctx)
+    torch.cuda.synchronize()
+    assert int(ctx.stats().stage_launches[0]) > 0  # projected again
+    ref, _ = fresh.colorize(m, s, q, o_p.detach(), sc.cams, y, sc.sh_deg, lam)
+    torch.cuda.synchronize()
+    assert torch.allclose(c2.detach(), ref, rtol=1e-5, atol=1e-6)
+    # opting in reuses the lists when nothing changed
+    ag.colorize(y, o_p, m, s, q, sc.cams, sc.sh_deg, lam, context=ctx, reuse_binning=True)
+    torch.cuda.synchronize()
+    assert int(ctx.stats().stage_launches[0]) == 0
+
+
 def test_backward_degenerate(ctx_prod, gsc_mod):
     import torch
     from tests import tiny
