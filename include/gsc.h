@@ -92,13 +92,30 @@ enum {
 enum {
     GSC_FLAG_VALIDATE_ONLY = 1, /* check the arguments and return; enqueue nothing */
     GSC_FLAG_PROFILE = 2,       /* time each pipeline stage with events on the call's stream */
-    GSC_FLAG_REUSE_BINNING = 4  /* reuse the tile lists of the previous call on this context
+    GSC_FLAG_REUSE_BINNING = 4, /* reuse the tile lists of the previous call on this context
                                    when it had one view batch and this call passes the same
                                    means, scales, quats and opacities pointers, N, cameras
                                    and blend options: the caller guarantees that the
                                    contents of those arrays are unchanged since that call
                                    (e.g. colorize, render and their adjoints in one
                                    optimisation step); otherwise the call bins anew */
+    GSC_FLAG_DETERMINISTIC = 8, /* gsc_colorize / gsc_colorize_ex (and the first pass of
+                                   gsc_colorize_refine): bit-identical results from run to
+                                   run.  The per-view sums are added as 64-bit fixed-point
+                                   integers (exact, so independent of the order of the
+                                   tiles) at a power-of-two step of at most 2^-62 times the
+                                   largest sum a view's pixels can form (pixels, and pixels
+                                   * max|y|; the step is about 2^-42 for 1280x720 views and
+                                   |y| <= 1), then converted to binary32 before the FP64
+                                   fold.  Costs a scan of the targets (one read-back),
+                                   [n_cams, N, C+1] 64-bit words of scratch and the vector
+                                   blend (the matrix-core form is not used).  Ignored by
+                                   gsc_colorize_noalloc and by plans. */
+    GSC_FLAG_CHECK_FINITE = 16  /* gsc_colorize / gsc_colorize_ex / gsc_colorize_refine:
+                                   before any other work, scan the targets and the
+                                   Gaussian arrays (one read-back) and return
+                                   GSC_ERR_INVALID_ARG naming the first array that holds
+                                   a NaN or an infinity, and where */
 };
 
 /* Pipeline stages timed under GSC_FLAG_PROFILE (indices of gsc_stats.stage_ms). */
@@ -350,6 +367,48 @@ gsc_status gsc_render_backward(gsc_ctx* ctx, const float* means, const float* sc
                                const gsc_camera* cams, int32_t n_cams, const float* coeffs,
                                int32_t C, int32_t sh_deg, const float* grad_images,
                                float* grad_coeffs, float* grad_opacities, gsc_stream_t stream);
+
+/*
+ * Linear combination of coefficient sets (Sec. 4.1, qualitative results:
+ * light fields are linear, so solved coefficient sets can be summed and
+ * filtered into lightings that no capture contained).  Elementwise
+ *   out[g][m][c] = filter[c] * sum_k weights[k] * sets[k][g][m][c],
+ * the sum taken as one binary32 fma chain in k order, then the product with
+ * the filter.  Because colorize is linear in its targets, combining the
+ * coefficients of several target sets equals colorizing the same
+ * combination of the targets (up to rounding).
+ *   sets: host array of n_sets (1..4096) device pointers, each
+ *         [N, (L+1)^2, C] float32; weights: host [n_sets], finite;
+ *   filter: host [C] per-channel gains (a colour filter), or NULL for 1;
+ *   out: device output [N, (L+1)^2, C] float32.  It may be one of the sets
+ *        when n_sets <= 16 (each element is read before it is written);
+ *        otherwise it must not alias any set.
+ * No scratch, no synchronisation; capturable.
+ */
+gsc_status gsc_combine_coeffs(const float* const* sets, const float* weights, int32_t n_sets,
+                              const float* filter, int64_t N, int32_t sh_deg, int32_t C, float* out,
+                              gsc_stream_t stream);
+
+/*
+ * Segmentation filter (Sec. 4.3: after masks are colorized at L = 0 onto the
+ * splats, Gaussians whose mask value falls below a threshold, 0.6 there, are
+ * removed).  The mask value of Gaussian g in `channel` is its colour averaged
+ * over view directions, Y_0 * coeffs[g][0][channel] (the colour itself at
+ * L = 0).  Gaussian g is kept when that value, computed in binary32, is
+ * >= threshold and, when status is given, neither GSC_G_UNOBSERVED nor
+ * GSC_G_FAILED is set.
+ *   coeffs: device [N, (L+1)^2, C] float32; status: device [N] or NULL;
+ *   keep: device output [N] uint8 (1 kept, 0 dropped) or NULL;
+ *   indices: device output with room for N int64, receiving the kept
+ *            indices in increasing order (entries past the count untouched),
+ *            or NULL;
+ *   n_kept: device output, one int64 (the number kept), or NULL.
+ * At least one output must be given.  Scratch: 4 bytes per 1024 Gaussians in
+ * the context, grown on demand.  No synchronisation.
+ */
+gsc_status gsc_mask_filter(gsc_ctx* ctx, const float* coeffs, int64_t N, int32_t sh_deg, int32_t C,
+                           int32_t channel, float threshold, const uint8_t* status, uint8_t* keep,
+                           int64_t* indices, int64_t* n_kept, gsc_stream_t stream);
 
 /*
  * Batched colorize of many scenes (plans).

@@ -460,3 +460,43 @@ def decode_targets(t: np.ndarray) -> np.ndarray:
     if t.dtype == np.uint16:
         return syn.bf16_to_f32(t)
     return np.asarray(t, np.float32)
+
+
+# --- post-processing (Sec. 4.1 qualitative results; Sec. 4.3) ----------------
+# Plain definitions in numpy.
+
+UNOBSERVED, ILL_COND, FAILED = 1, 2, 4
+
+
+def combine(sets, weights, filt=None) -> np.ndarray:
+    """A new lighting from solved coefficient sets (Sec. 4.1, qualitative
+    results: light fields are linear, so colorizations can be combined and
+    filtered): filt[c] * sum_k weights[k] * sets[k], in FP64.  The weights and
+    the filter are taken as the binary32 values a caller hands over."""
+    acc = np.zeros(np.shape(sets[0]), np.float64)
+    for s, w in zip(sets, weights):
+        acc += float(np.float32(w)) * np.asarray(s, np.float64)
+    if filt is not None:
+        acc *= np.asarray(filt, np.float32).astype(np.float64)  # last axis: channels
+    return acc
+
+
+def mask_value(coeffs, channel: int) -> np.ndarray:
+    """Mask value of every Gaussian in one channel (Sec. 4.3): its colour
+    averaged over all view directions.  Only the l = 0 harmonic has a non-zero
+    mean over the sphere, so the average is Y_0 c[g][0][channel], with Y_0
+    taken from the basis routine; at L = 0 it is the colour itself.  Returned
+    in binary32, the precision the keep decision is taken in."""
+    y0 = np.float32(sh_basis(0, np.array([[0.0, 0.0, 1.0]]))[0, 0])
+    return y0 * np.asarray(coeffs, np.float32)[:, 0, channel]
+
+
+def mask_filter(coeffs, channel: int = 0, threshold: float = 0.6, status=None):
+    """Segmentation filter (Sec. 4.3): a Gaussian stays when its mask value
+    reaches the threshold (0.6 in the paper), and, when status bits are given,
+    it was observed and solved.  Returns (keep [N] bool, kept indices in
+    increasing order)."""
+    keep = mask_value(coeffs, channel) >= np.float32(threshold)
+    if status is not None:
+        keep &= (np.asarray(status) & (UNOBSERVED | FAILED)) == 0
+    return keep, np.nonzero(keep)[0].astype(np.int64)

@@ -10,7 +10,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgsc.so")
-SOURCES = ["gsc_api.hip", "k_project.hip", "k_sort.hip", "k_accum.hip", "k_render.hip", "k_solve.hip", "k_adjoint.hip"]
+SOURCES = ["gsc_api.hip", "k_project.hip", "k_sort.hip", "k_accum.hip", "k_render.hip", "k_solve.hip", "k_adjoint.hip", "k_post.hip", "k_scan.hip"]
 ARCH = os.environ.get("GSC_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -141,7 +141,7 @@ struct gsc_ctx {
     // device scratch
     DevBuf views, views_all, cov, keys, vals, keys_alt, vals_alt, counts, offsets, rec0, rec1, rec2,
         sort_scratch, pkeys, pvals, pkeys_alt, pvals_alt, ranges, vs, gamma, bbar, misc, order, queues,
-        coef_t, factor, img, stat, wbuf;
+        coef_t, factor, img, stat, wbuf, post, vsdet, chk;
     bool order_valid = false;  // `order` holds the tile order of the current binning
     // host staging
     ViewInfo* h_views = nullptr;  // staging of one batch's table
@@ -162,11 +162,11 @@ struct gsc_ctx {
     size_t ev_used = 0;
     struct Mark { int stage; hipEvent_t a, b; uint32_t launches; };
     std::vector<Mark> marks;
-    std::array<DevBuf*, 29> bufs() {
+    std::array<DevBuf*, 32> bufs() {
         return {&views, &views_all, &cov, &keys, &vals, &keys_alt, &vals_alt, &counts,
                 &offsets, &rec0, &rec1, &rec2, &sort_scratch, &pkeys, &pvals, &pkeys_alt,
                 &pvals_alt, &ranges, &vs, &gamma, &bbar, &misc, &order, &queues, &coef_t,
-                &factor, &img, &stat, &wbuf};
+                &factor, &img, &stat, &wbuf, &post, &vsdet, &chk};
     }
     ~gsc_ctx() {
         for (DevBuf* b : bufs()) b->release();
@@ -945,6 +945,63 @@ gsc_status validate_colorize(const float* means, const float* scales, const floa
 
 // The colorize pipeline on validated arguments (N > 0).  `all` holds n_cams
 // view slots, filled here.  key / reuse: binning reuse (key may be null).
+// One array to scan for non-finite values (GSC_FLAG_CHECK_FINITE) and for
+// its largest magnitude.
+struct ScanSeg {
+    const char* name;
+    const void* p;
+    int dtype;
+    int64_t n;
+    int per;  // values per entity (Gaussian or target row), for the message
+};
+
+// Scans the segments on `s`, reads the results back (synchronising `s`) and
+// fails with GSC_ERR_INVALID_ARG naming the first segment that holds a
+// non-finite value.  absmax (optional): the largest |value| of each segment.
+gsc_status scan_inputs(gsc_ctx* ctx, const ScanSeg* seg, int n_seg, hipStream_t s, float* absmax) {
+    constexpr int kMaxSeg = 8;
+    if (n_seg > kMaxSeg) return fail(GSC_ERR_INVALID_ARG, "too many arrays to scan");
+    GSC_HIP(ctx->chk.ensure(16 * kMaxSeg));
+    unsigned long long* bad = ctx->chk.as<unsigned long long>();
+    uint32_t* mx = reinterpret_cast<uint32_t*>(bad + kMaxSeg);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(bad), 0xffffffffu, 2 * kMaxSeg, s);
+    launch_fill_u32(mx, 0u, kMaxSeg, s);
+    for (int i = 0; i < n_seg; ++i) launch_scan_values(seg[i].p, seg[i].dtype, seg[i].n, bad + i, mx + i, s);
+    GSC_LAUNCHED("input scan");
+    unsigned long long h[kMaxSeg + kMaxSeg / 2];
+    GSC_HIP(hipMemcpyAsync(h, bad, 12 * kMaxSeg, hipMemcpyDeviceToHost, s));
+    GSC_HIP(hipStreamSynchronize(s));
+    const uint32_t* hm = reinterpret_cast<const uint32_t*>(h + kMaxSeg);
+    for (int i = 0; i < n_seg; ++i) {
+        if (h[i] != ~0ull)
+            return fail(GSC_ERR_INVALID_ARG, "%s holds a non-finite value at element %llu (entry %llu)",
+                        seg[i].name, h[i], h[i] / (unsigned long long)seg[i].per);
+        if (absmax) {
+            float f;
+            memcpy(&f, &hm[i], 4);
+            absmax[i] = f;
+        }
+    }
+    return GSC_OK;
+}
+
+// Fixed-point scales of the deterministic per-view sums: a power of two per
+// column kind such that no slot can exceed 2^62 in magnitude.  A slot sums
+// one view's pixels, each with weight <= 1: V <= pixels and |S| <= pixels *
+// max|y|.
+float2 det_scales(const gsc_camera* cams, int n_cams, float ymax) {
+    double P = 1.0;
+    for (int j = 0; j < n_cams; ++j) P = std::max(P, (double)cams[j].width * cams[j].height);
+    auto pow2_for = [](double bound) {
+        int e = 62 - (int)ceil(log2(std::max(bound, 1e-30)));
+        e = std::min(std::max(e, -126), 126);
+        return ldexpf(1.0f, e);
+    };
+    const float sv = pow2_for(P);
+    const float ss = ymax > 0.0f ? pow2_for(P * (double)ymax) : sv;
+    return make_float2(sv, ss);
+}
+
 gsc_status colorize_core(gsc_ctx* ctx, const float* means, const float* scales,
                          const float* quats, const float* opacities, int64_t N,
                          const gsc_camera* cams, int32_t n_cams, const void* targets,
@@ -956,12 +1013,37 @@ gsc_status colorize_core(gsc_ctx* ctx, const float* means, const float* scales,
     float* x_vis = extras ? extras->visibility : nullptr;
     uint32_t* x_cnt = extras ? extras->counts : nullptr;
     BlendParams bp = blend_params(ctx->opt);
+    const bool det = (ctx->opt.flags & GSC_FLAG_DETERMINISTIC) != 0;
+    float2 dsc = make_float2(0.f, 0.f);
+    if ((ctx->opt.flags & GSC_FLAG_CHECK_FINITE) || det) {
+        int64_t rows = 0;
+        for (int j = 0; j < n_cams; ++j)
+            rows = std::max<int64_t>(rows, cams[j].pixel_offset + (int64_t)cams[j].width * cams[j].height);
+        const ScanSeg all_segs[5] = {{"targets", targets, tdtype, rows * C, C},
+                                     {"means", means, GSC_F32, 3 * N, 3},
+                                     {"scales", scales, GSC_F32, 3 * N, 3},
+                                     {"quats", quats, GSC_F32, 4 * N, 4},
+                                     {"opacities", opacities, GSC_F32, N, 1}};
+        const int n_seg = (ctx->opt.flags & GSC_FLAG_CHECK_FINITE) ? 5 : 1;
+        float mx[5] = {0, 0, 0, 0, 0};
+        if ((st = scan_inputs(ctx, all_segs, n_seg, s, mx)) != GSC_OK) return st;
+        dsc = det_scales(cams, n_cams, mx[0]);
+    }
     if ((st = ensure_common(ctx, means, scales, quats, opacities, N, cams, n_cams, s, reuse)) != GSC_OK) return st;
     for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j], j, N, ctx->bin);
-    const bool per_view = sh_deg > 0 || x_sums != nullptr;
+    // the deterministic sums keep one slot per view (a slot summed over all
+    // views would need a coarser fixed-point step)
+    const bool per_view = sh_deg > 0 || x_sums != nullptr || det;
     const uint64_t vs_words = (uint64_t)(per_view ? std::max(n_cams, 1) : 1) * (uint64_t)N * (uint64_t)(C + 1);
     GSC_HIP(ctx->vs.ensure(4 * vs_words));
-    launch_fill_u32(ctx->vs.as<uint32_t>(), 0u, vs_words, s);
+    float* acc_vs = ctx->vs.as<float>();
+    if (det) {
+        GSC_HIP(ctx->vsdet.ensure(8 * vs_words));
+        launch_fill_u32(ctx->vsdet.as<uint32_t>(), 0u, 2 * vs_words, s);
+        acc_vs = ctx->vsdet.as<float>();  // 64-bit words, see launch_accumulate_chunked
+    } else {
+        launch_fill_u32(ctx->vs.as<uint32_t>(), 0u, vs_words, s);
+    }
     if (x_cnt) launch_fill_u32(x_cnt, 0u, (uint64_t)N, s);
     unsigned long long* d_counter = reinterpret_cast<unsigned long long*>(ctx->misc.p);
     st = for_view_batches_k(ctx, all, n_cams, means, opacities, N, bp, s, key, reuse,
@@ -982,11 +1064,16 @@ gsc_status colorize_core(gsc_ctx* ctx, const float* means, const float* scales,
         launch_accumulate_chunked(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
                                   ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(), ctx->rec1.as<float4>(),
                                   ctx->rec2.as<uint2>(), ctx->bin, targets, tdtype, C, per_view, bp,
-                                  ctx->vs.as<float>(), d_counter, x_cnt, chunk, s, queues, order);
+                                  acc_vs, d_counter, x_cnt, chunk, s, queues, order, det ? &dsc : nullptr);
         GSC_LAUNCHED("accumulate");
         return GSC_OK;
     });
     if (st != GSC_OK) return st;
+    if (det) {
+        launch_det_to_float(ctx->vsdet.as<unsigned long long>(), (int64_t)vs_words, C + 1, 1.0 / dsc.x,
+                            1.0 / dsc.y, ctx->vs.as<float>(), s);
+        GSC_LAUNCHED("deterministic sums");
+    }
     if (x_sums && n_cams > 0)
         GSC_HIP(hipMemcpyAsync(x_sums, ctx->vs.p, 4 * vs_words, hipMemcpyDeviceToDevice, s));
     // fold + solve needs the full camera table (only the camera centres are used)
@@ -1124,7 +1211,7 @@ gsc_status gsc_colorize_noalloc(gsc_ctx* ctx, const float* means, const float* s
     w.h_all_cap = kNoallocMaxViews;
     w.h_total = g_noalloc_total;
     w.opt = ctx->opt;
-    w.opt.flags &= ~(GSC_FLAG_PROFILE | GSC_FLAG_REUSE_BINNING);
+    w.opt.flags &= ~(GSC_FLAG_PROFILE | GSC_FLAG_REUSE_BINNING | GSC_FLAG_DETERMINISTIC);
     memset(&w.stats, 0, sizeof(w.stats));
     st = colorize_core(&w, means, scales, quats, opacities, N, cams, n_cams, targets, tdtype, C,
                        sh_deg, lam, coeffs, status, nullptr, s, nullptr, false, g_noalloc_table);
@@ -1749,6 +1836,67 @@ gsc_status gsc_plan_get_info(gsc_plan* plan, gsc_plan_info* out) {
         out->tuned_variant[i] = plan->tune_variant[i];
         out->tuned_ms[i] = plan->tune_ms[i];
     }
+    return GSC_OK;
+}
+
+gsc_status gsc_combine_coeffs(const float* const* sets, const float* weights, int32_t n_sets,
+                              const float* filter, int64_t N, int32_t sh_deg, int32_t C, float* out,
+                              gsc_stream_t stream) {
+    if (N < 0) return fail(GSC_ERR_INVALID_ARG, "N must be >= 0 (got %lld)", (long long)N);
+    gsc_status st = validate_channels(C, sh_deg);
+    if (st != GSC_OK) return st;
+    if (n_sets < 1 || n_sets > 4096) return fail(GSC_ERR_INVALID_ARG, "n_sets must be in [1,4096] (got %d)", n_sets);
+    if (!sets || !weights) return fail(GSC_ERR_INVALID_ARG, "sets or weights is null");
+    for (int k = 0; k < n_sets; ++k) {
+        if (!isfinite(weights[k])) return fail(GSC_ERR_INVALID_ARG, "weights[%d] is not finite", k);
+        if (N > 0 && !sets[k]) return fail(GSC_ERR_INVALID_ARG, "sets[%d] is null", k);
+        if (n_sets > kCombineSets && sets[k] == out)
+            return fail(GSC_ERR_INVALID_ARG, "out may alias a set only when n_sets <= %d", kCombineSets);
+    }
+    if (filter)
+        for (int c = 0; c < C; ++c)
+            if (!isfinite(filter[c])) return fail(GSC_ERR_INVALID_ARG, "filter[%d] is not finite", c);
+    if (N > 0 && !out) return fail(GSC_ERR_INVALID_ARG, "out is null");
+    const int64_t n = N * (int64_t)(sh_deg + 1) * (sh_deg + 1) * C;
+    if (n == 0) return GSC_OK;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    bool vec4 = n % 4 == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0;
+    for (int k = 0; k < n_sets; ++k) vec4 = vec4 && (reinterpret_cast<uintptr_t>(sets[k]) & 15) == 0;
+    for (int k0 = 0; k0 < n_sets; k0 += kCombineSets) {
+        CombineArgs a{};
+        a.n = std::min(kCombineSets, n_sets - k0);
+        for (int k = 0; k < a.n; ++k) {
+            a.p[k] = sets[k0 + k];
+            a.w[k] = weights[k0 + k];
+        }
+        a.accumulate = k0 > 0;
+        a.filter = filter && k0 + a.n == n_sets;
+        for (int c = 0; c < C; ++c) a.f[c] = filter ? filter[c] : 1.0f;
+        launch_combine(a, n, C, vec4, out, s);
+        GSC_LAUNCHED("combine");
+    }
+    return GSC_OK;
+}
+
+gsc_status gsc_mask_filter(gsc_ctx* ctx, const float* coeffs, int64_t N, int32_t sh_deg, int32_t C,
+                           int32_t channel, float threshold, const uint8_t* status, uint8_t* keep,
+                           int64_t* indices, int64_t* n_kept, gsc_stream_t stream) {
+    if (!ctx) return fail(GSC_ERR_INVALID_ARG, "null ctx");
+    if (N < 0) return fail(GSC_ERR_INVALID_ARG, "N must be >= 0 (got %lld)", (long long)N);
+    if (N > (int64_t)kItemMask) return fail(GSC_ERR_UNSUPPORTED, "N must be < 2^26 (got %lld)", (long long)N);
+    gsc_status st = validate_channels(C, sh_deg);
+    if (st != GSC_OK) return st;
+    if (channel < 0 || channel >= C) return fail(GSC_ERR_INVALID_ARG, "channel must be in [0,C) (got %d)", channel);
+    if (!isfinite(threshold)) return fail(GSC_ERR_INVALID_ARG, "threshold is not finite");
+    if (!keep && !indices && !n_kept) return fail(GSC_ERR_INVALID_ARG, "no output requested");
+    if (N > 0 && !coeffs) return fail(GSC_ERR_INVALID_ARG, "coeffs is null");
+    if (ctx->opt.flags & GSC_FLAG_VALIDATE_ONLY) return GSC_OK;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int nb = mask_blocks(N);
+    GSC_HIP(ctx->post.ensure((size_t)std::max(nb, 1) * sizeof(uint32_t)));
+    launch_mask_filter(coeffs, N, (int64_t)(sh_deg + 1) * (sh_deg + 1) * C, channel, threshold, status,
+                       keep, indices, n_kept, ctx->post.as<uint32_t>(), s);
+    GSC_LAUNCHED("mask filter");
     return GSC_OK;
 }
 

@@ -177,7 +177,11 @@ void launch_accumulate_chunked(const ViewInfo* views, int n_views, uint32_t n_ti
                                bool per_view, BlendParams bp, float* VS,
                                unsigned long long* counter, uint32_t* gcount, int chunk,
                                hipStream_t s, uint32_t* queues = nullptr,
-                               const uint32_t* order = nullptr);
+                               const uint32_t* order = nullptr, const float2* det = nullptr);
+// det (non-null): deterministic form.  VS holds 64-bit fixed-point words
+// (zero before the first launch); each tile's share is scaled by det->x
+// (visibility column) or det->y (channel columns), powers of two, and added
+// with integer atomics.  Vector form only (a matrix-core chunk falls back).
 
 // out[k][r] = in[r][k] (rows x K row-major in, K x rows row-major out).
 void launch_transpose(const float* in, int64_t rows, int K, float* out, hipStream_t s);
@@ -264,5 +268,40 @@ void launch_blend_adjoint(const ViewInfo* views, int n_views, uint32_t n_tiles, 
 // grad_coeffs[g][m][c] = sum_j phi_gj[m] S_gj[c] from per-view sums [n_views][N][C+1].
 void launch_fold_rhs(const ViewInfo* views, int n_views, const float* means, const float* VS,
                      bool per_view, int64_t N, int C, int sh_deg, float* out, hipStream_t s);
+
+// Input checks and the deterministic sums.
+// Over n values of dtype GSC_F32 or GSC_BF16 at p: the smallest index of a
+// non-finite value (atomicMin into *first_bad, which the caller sets to
+// UINT64_MAX) and the largest |value| as binary32 bits (atomicMax into
+// *absmax, set to 0 by the caller; NaN counts as larger than infinity).
+void launch_scan_values(const void* p, int dtype, int64_t n, unsigned long long* first_bad,
+                        uint32_t* absmax, hipStream_t s);
+// out[i] = in[i] / scale, scale = 1/inv_v for column 0 of every row of
+// `stride` words and 1/inv_s for the others (powers of two).
+void launch_det_to_float(const unsigned long long* in, int64_t n, int stride, double inv_v,
+                         double inv_s, float* out, hipStream_t s);
+
+// Post-processing.  Linear combination of up to kCombineSets coefficient sets
+// per launch: out = filter * sum_k w_k p_k elementwise (filter by channel,
+// i mod C, applied when `filter`); with `accumulate` the sum continues from
+// out.
+constexpr int kCombineSets = 16;
+struct CombineArgs {
+    const float* p[kCombineSets];
+    float w[kCombineSets];
+    float f[kMaxC];
+    int n;
+    int accumulate;
+    int filter;
+};
+void launch_combine(const CombineArgs& a, int64_t n, int C, bool vec4, float* out, hipStream_t s);
+
+// Segmentation filter over coeffs rows of `row` floats: keep[g] (optional),
+// the kept indices in increasing order (optional) and their number (device
+// int64, optional).  block_scratch: mask_blocks(N) words.
+int mask_blocks(int64_t N);
+void launch_mask_filter(const float* coeffs, int64_t N, int64_t row, int channel, float thr,
+                        const uint8_t* status, uint8_t* keep, int64_t* indices, int64_t* n_kept,
+                        uint32_t* block_scratch, hipStream_t s);
 
 }  // namespace gsc

@@ -16,6 +16,22 @@
 namespace gsc {
 
 
+// Adds a tile's share v to the per-view sum at p (an element of VS).  The
+// default adds binary32 with a float atomic, so the order of the tiles'
+// additions shows in the last bits.  DET: VS holds 64-bit fixed-point words
+// instead (element k of VS is word k); v is scaled by the power of two
+// `scale`, rounded to an integer and added with an integer atomic, which is
+// exact and therefore independent of the order.
+template <bool DET>
+__device__ __forceinline__ void vs_add(float* VS, float* p, float v, float scale) {
+    if constexpr (DET) {
+        unsigned long long* q = reinterpret_cast<unsigned long long*>(VS) + (p - VS);
+        atomicAdd(q, (unsigned long long)__float2ll_rn(v * scale));
+    } else {
+        unsafeAtomicAdd(p, v);
+    }
+}
+
 // One tile, by one wave: blend its pixels front to back and add each
 // Gaussian's tile share of V and S (channels [c_off, c_off + CC) of C) to its
 // slot.  Returns the wave's accepted contributions (uniform).
@@ -24,14 +40,14 @@ namespace gsc {
 // pixel rows are skipped when the Gaussian's footprint misses them (bits of
 // the pair value) or when none of their pixels is live; the wave ends when no
 // band is live.
-template <int CC, bool BF16, int BIN>
+template <int CC, bool BF16, int BIN, bool DET>
 __device__ __forceinline__ uint32_t accumulate_tile(
     uint32_t tile, uint32_t lane, const ViewInfo* __restrict__ views, int n_views,
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_vals,
     const float4* __restrict__ rec0, const float4* __restrict__ rec1,
     const uint2* __restrict__ rec2,
     const void* __restrict__ targets, int C, int c_off, int per_view, const BlendParams& bp,
-    float* __restrict__ VS, uint32_t* __restrict__ gcount) {
+    float* __restrict__ VS, float2 dsc, uint32_t* __restrict__ gcount) {
     constexpr int CCA = CC > 0 ? CC : 1;
     const TileGeom tg = tile_geom<BIN>(tile, views, n_views);
     const ViewInfo& V = views[tg.vloc];
@@ -183,7 +199,8 @@ __device__ __forceinline__ uint32_t accumulate_tile(
                     const bool he = e == 0 ? has[0] : (e == 1 ? has[1] : (e == 2 ? has[2] : has[3]));
                     const int64_t sl = e == 0 ? gslot[0] : (e == 1 ? gslot[1] : (e == 2 ? gslot[2] : gslot[3]));
                     const bool use = lane < 16u && he && (v == 0 ? first_chunk : (v <= CC && c_off + v - 1 < C));
-                    if (use) unsafeAtomicAdd(VS + sl * (int64_t)stride + (v == 0 ? 0 : c_off + v), t);
+                    if (use) vs_add<DET>(VS, VS + sl * (int64_t)stride + (v == 0 ? 0 : c_off + v), t,
+                                         v == 0 ? dsc.x : dsc.y);
                 }
             }
         } else {
@@ -228,7 +245,7 @@ __device__ __forceinline__ uint32_t accumulate_tile(
                     float* slot = VS + (slot_base + g) * (int64_t)stride;
                     if constexpr (CC == 0) {
                         const float tv = wave_sum(sv);
-                        if (lane == 0) unsafeAtomicAdd(slot, tv);
+                        if (lane == 0) vs_add<DET>(VS, slot, tv, dsc.x);
                     } else if constexpr (CC <= 3) {
                         const float v1 = CC > 1 ? ss[CC > 1 ? 1 : 0] : 0.0f;
                         const float v2 = CC > 2 ? ss[CC > 2 ? 2 : 0] : 0.0f;
@@ -236,18 +253,18 @@ __device__ __forceinline__ uint32_t accumulate_tile(
                         if (lane < 4u) {
                             const int idx = transposed_index<4>(lane);
                             if (idx == 0) {
-                                if (first_chunk) unsafeAtomicAdd(slot, t);
+                                if (first_chunk) vs_add<DET>(VS, slot, t, dsc.x);
                             } else if (idx <= CC && c_off + idx - 1 < C) {
-                                unsafeAtomicAdd(slot + c_off + idx, t);
+                                vs_add<DET>(VS, slot + c_off + idx, t, dsc.y);
                             }
                         }
                     } else {
                         const float tv = wave_sum(sv);
                         const float t = wave_sum_transposed<CC>(ss, lane);
-                        if (lane == 0 && first_chunk) unsafeAtomicAdd(slot, tv);
+                        if (lane == 0 && first_chunk) vs_add<DET>(VS, slot, tv, dsc.x);
                         if (lane < (uint32_t)CC) {
                             const int c = c_off + transposed_index<CC>(lane);
-                            if (c < C) unsafeAtomicAdd(slot + 1 + c, t);
+                            if (c < C) vs_add<DET>(VS, slot + 1 + c, t, dsc.y);
                         }
                     }
                 }
@@ -278,13 +295,13 @@ __device__ __forceinline__ uint32_t accumulate_tile(
 template <int CC>
 constexpr int acc_waves_per_simd() { return CC >= 1 && CC <= 3 ? 7 : 1; }
 
-template <int CC, bool BF16, int BIN>
+template <int CC, bool BF16, int BIN, bool DET>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(acc_waves_per_simd<CC>()))) void k_accumulate(
     const ViewInfo* __restrict__ views, int n_views, uint32_t n_tiles, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ pair_vals,
     const float4* __restrict__ rec0, const float4* __restrict__ rec1,
     const uint2* __restrict__ rec2, const void* __restrict__ targets, int C, int c_off,
-    int per_view, BlendParams bp, float* __restrict__ VS,
+    int per_view, BlendParams bp, float* __restrict__ VS, float2 dsc,
     unsigned long long* __restrict__ counter, uint32_t* __restrict__ gcount,
     uint32_t* __restrict__ queue, const uint32_t* __restrict__ order) {
     const uint32_t lane = threadIdx.x & 63;
@@ -293,9 +310,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(acc_waves_p
         const uint32_t wi = blockIdx.x * 4 + (threadIdx.x >> 6);
         if (wi >= n_tiles) return;  // whole wave
         const uint32_t tile = queued_tile<BIN>(wi, order);  // blocks start in index order
-        cnt = accumulate_tile<CC, BF16, BIN>(tile, lane, views, n_views, ranges, pair_vals,
-                                             rec0, rec1, rec2, targets, C, c_off, per_view, bp, VS,
-                                             gcount);
+        cnt = accumulate_tile<CC, BF16, BIN, DET>(tile, lane, views, n_views, ranges, pair_vals,
+                                                  rec0, rec1, rec2, targets, C, c_off, per_view, bp,
+                                                  VS, dsc, gcount);
     } else {
         for (;;) {
             uint32_t t = 0;
@@ -303,9 +320,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(acc_waves_p
             const uint32_t tq = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
             if (tq >= n_tiles) break;  // uniform: every wave ends here
             const uint32_t tile = queued_tile<BIN>(tq, order);
-            cnt += accumulate_tile<CC, BF16, BIN>(tile, lane, views, n_views, ranges, pair_vals,
-                                                  rec0, rec1, rec2, targets, C, c_off,
-                                                  per_view, bp, VS, gcount);
+            cnt += accumulate_tile<CC, BF16, BIN, DET>(tile, lane, views, n_views, ranges, pair_vals,
+                                                       rec0, rec1, rec2, targets, C, c_off,
+                                                       per_view, bp, VS, dsc, gcount);
         }
     }
     if (c_off == 0 && lane == 0 && cnt) atomicAdd(counter, (unsigned long long)cnt);
@@ -314,22 +331,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(acc_waves_p
 // Waves (16x16 tiles) of a launch over n_bins bins of `bin` pixels.
 static inline uint32_t wave_tiles(uint32_t n_bins, int bin) { return bin == 32 ? 4u * n_bins : n_bins; }
 
-template <int CC, bool BF16, int BIN>
+template <int CC, bool BF16, int BIN, bool DET = false>
 static void launch_acc_k(const ViewInfo* views, int n_views, uint32_t n_wt, const uint2* ranges,
                          const uint32_t* pair_vals, const float4* rec0,
                          const float4* rec1,
                          const uint2* rec2, const void* targets, int C, bool per_view,
                          BlendParams bp, float* VS, unsigned long long* counter, uint32_t* gcount,
-                         uint32_t* queues, const uint32_t* order, hipStream_t s) {
+                         uint32_t* queues, const uint32_t* order, hipStream_t s,
+                         float2 dsc = make_float2(0.f, 0.f)) {
     const uint32_t full = (n_wt + 3) / 4;
     dim3 grid(queues ? std::min(full, kPersistentBlocks) : full), block(256);
     int pass = 0;
     const int step = CC > 0 ? CC : C + 1;
     for (int c_off = 0; c_off < std::max(C, 1); c_off += step, ++pass) {
         uint32_t* q = queues ? queues + pass : nullptr;
-        hipLaunchKernelGGL((k_accumulate<CC, BF16, BIN>), grid, block, 0, s, views, n_views, n_wt,
+        hipLaunchKernelGGL((k_accumulate<CC, BF16, BIN, DET>), grid, block, 0, s, views, n_views, n_wt,
                            ranges, pair_vals, rec0, rec1, rec2, targets, C, c_off,
-                           (int)per_view, bp, VS, counter, gcount, q, order);
+                           (int)per_view, bp, VS, dsc, counter, gcount, q, order);
     }
 }
 
@@ -339,16 +357,24 @@ static void launch_acc_cc(const ViewInfo* views, int n_views, uint32_t n_bins, c
                           const float4* rec1,
                           const uint2* rec2, int bin, const void* targets, int tdtype, int C,
                           bool per_view, BlendParams bp, float* VS, unsigned long long* counter,
-                          uint32_t* gcount, uint32_t* queues, const uint32_t* order, hipStream_t s) {
+                          uint32_t* gcount, uint32_t* queues, const uint32_t* order, hipStream_t s,
+                          const float2* det) {
     const uint32_t n_wt = wave_tiles(n_bins, bin);
     const bool bf = tdtype == GSC_BF16;
-#define GSC_ACCK(BFV, BINV)                                                                        \
-    launch_acc_k<CC, BFV, BINV>(views, n_views, n_wt, ranges, pair_vals, rec0, rec1, rec2, targets, \
-                                C, per_view, bp, VS, counter, gcount, queues, order, s)
-    if (bin == 32) {
-        if (bf) GSC_ACCK(true, 32); else GSC_ACCK(false, 32);
+#define GSC_ACCK(BFV, BINV, DETV)                                                                  \
+    launch_acc_k<CC, BFV, BINV, DETV>(views, n_views, n_wt, ranges, pair_vals, rec0, rec1, rec2,    \
+                                      targets, C, per_view, bp, VS, counter, gcount, queues, order, s, \
+                                      det ? *det : make_float2(0.f, 0.f))
+    if (det) {
+        if (bin == 32) {
+            if (bf) GSC_ACCK(true, 32, true); else GSC_ACCK(false, 32, true);
+        } else {
+            if (bf) GSC_ACCK(true, 16, true); else GSC_ACCK(false, 16, true);
+        }
+    } else if (bin == 32) {
+        if (bf) GSC_ACCK(true, 32, false); else GSC_ACCK(false, 32, false);
     } else {
-        if (bf) GSC_ACCK(true, 16); else GSC_ACCK(false, 16);
+        if (bf) GSC_ACCK(true, 16, false); else GSC_ACCK(false, 16, false);
     }
 #undef GSC_ACCK
 }
@@ -734,7 +760,8 @@ void launch_accumulate(const ViewInfo* views, int n_views, uint32_t n_tiles, con
                        bool per_view, BlendParams bp, float* VS, unsigned long long* counter,
                        uint32_t* gcount, hipStream_t s, const uint32_t* order) {
     launch_accumulate_chunked(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, rec2, bin,
-                              targets, tdtype, C, per_view, bp, VS, counter, gcount, 0, s, nullptr, order);
+                              targets, tdtype, C, per_view, bp, VS, counter, gcount, 0, s, nullptr, order,
+                              nullptr);
 }
 
 void launch_accumulate_chunked(const ViewInfo* views, int n_views, uint32_t n_tiles,
@@ -744,9 +771,10 @@ void launch_accumulate_chunked(const ViewInfo* views, int n_views, uint32_t n_ti
                                const void* targets, int tdtype, int C, bool per_view,
                                BlendParams bp, float* VS, unsigned long long* counter,
                                uint32_t* gcount, int chunk, hipStream_t s, uint32_t* queues,
-                               const uint32_t* order) {
+                               const uint32_t* order, const float2* det) {
     if (n_tiles == 0) return;
     chunk = resolve_chunk(chunk, C, tdtype);
+    if (det && (chunk & kChunkMfma)) chunk = accumulate_chunk(C, GSC_F32);  // vector form only
     if (queues) launch_fill_u32(queues, 0u, (uint64_t)accumulate_launches(C, chunk), s);
     if (chunk & kChunkMfma) {
 #define GSC_ACCM(NB, YMV)                                                                          \
@@ -765,7 +793,7 @@ void launch_accumulate_chunked(const ViewInfo* views, int n_views, uint32_t n_ti
     }
 #define GSC_ACC(CCV)                                                                                \
     launch_acc_cc<CCV>(views, n_views, n_tiles, ranges, pair_vals, rec0, rec1, rec2, bin, targets, \
-                       tdtype, C, per_view, bp, VS, counter, gcount, queues, order, s)
+                       tdtype, C, per_view, bp, VS, counter, gcount, queues, order, s, det)
     switch (chunk) {
         case 1: GSC_ACC(1); break;
         case 2: GSC_ACC(2); break;

@@ -50,6 +50,8 @@ class GscOptions(ct.Structure):
 GSC_SCHEDULE_AUTO, GSC_SCHEDULE_GRID, GSC_SCHEDULE_LONGEST_FIRST = 0, 1, 2
 GSC_FLAG_PROFILE = 2
 GSC_FLAG_REUSE_BINNING = 4
+GSC_FLAG_DETERMINISTIC = 8
+GSC_FLAG_CHECK_FINITE = 16
 STAGES = ["project", "depth_sort", "scan", "emit", "tile_sort", "blend", "solve", "blend_adjoint"]
 
 
@@ -133,6 +135,10 @@ def load(path: Optional[str] = None):
     lib.gsc_plan_autotune.restype = ct.c_int
     lib.gsc_plan_get_info.argtypes = [P, ct.POINTER(GscPlanInfo)]
     lib.gsc_plan_get_info.restype = ct.c_int
+    lib.gsc_combine_coeffs.argtypes = [P, P, i32, P, i64, i32, i32, P, P]
+    lib.gsc_combine_coeffs.restype = ct.c_int
+    lib.gsc_mask_filter.argtypes = [P, P, i64, i32, i32, i32, ct.c_float, P, P, P, P, P]
+    lib.gsc_mask_filter.restype = ct.c_int
     lib.gsc_get_stats.argtypes = [P, ct.POINTER(GscStats)]
     lib.gsc_get_stats.restype = ct.c_int
     lib.gsc_last_error.argtypes = []
@@ -334,6 +340,24 @@ class Context:
         _check(self.lib, st)
         return coeffs, status
 
+    def mask_filter(self, coeffs, channel: int = 0, threshold: float = 0.6, status=None,
+                    want_keep: bool = True, stream=None):
+        """Segmentation filter (gsc_mask_filter) of coefficients [N,(L+1)^2,C].
+        Returns (keep [N] uint8 or None, kept indices [n_kept] int64); reads
+        the count back, so it synchronises."""
+        import torch
+        N, nb, C = (int(v) for v in coeffs.shape)
+        sh_deg = int(round(nb ** 0.5)) - 1
+        dev = coeffs.device
+        keep = torch.empty((N,), dtype=torch.uint8, device=dev) if want_keep else None
+        idx = torch.empty((max(N, 1),), dtype=torch.int64, device=dev)
+        cnt = torch.zeros((1,), dtype=torch.int64, device=dev)
+        st = self.lib.gsc_mask_filter(self.handle, _ptr(coeffs), N, sh_deg, C, int(channel),
+                                      float(threshold), _ptr(status), _ptr(keep), _ptr(idx),
+                                      _ptr(cnt), _stream_ptr(stream))
+        _check(self.lib, st)
+        return keep, idx[:int(cnt.item())]
+
     def render(self, means, scales, quats, opacities, cams, coeffs, images=None, offsets=None,
                stream=None, reuse_binning: bool = False):
         """Render coefficients [N,(L+1)^2,C] to images [sum HW, C] float32."""
@@ -477,6 +501,29 @@ class Plan:
         out = GscPlanInfo()
         _check(self.lib, self.lib.gsc_plan_get_info(self.handle, ct.byref(out)))
         return out
+
+
+def combine_coeffs(sets, weights, filt=None, out=None, stream=None):
+    """Linear combination of coefficient sets (gsc_combine_coeffs):
+    out = filt[c] * sum_k weights[k] * sets[k], each [N,(L+1)^2,C] float32."""
+    import torch
+    lib = load()
+    sets = list(sets)
+    N, nb, C = (int(v) for v in sets[0].shape)
+    for t in sets:
+        if tuple(t.shape) != (N, nb, C) or t.dtype != torch.float32 or not t.is_contiguous():
+            raise ValueError("every set must be a contiguous float32 tensor of one shape")
+    sh_deg = int(round(nb ** 0.5)) - 1
+    if out is None:
+        out = torch.empty_like(sets[0])
+    ptrs = (ct.c_void_p * len(sets))(*[_ptr(t) for t in sets])
+    w = (ct.c_float * len(sets))(*[float(v) for v in weights])
+    if len(weights) != len(sets):
+        raise ValueError("one weight per set")
+    f = None if filt is None else (ct.c_float * C)(*[float(v) for v in filt])
+    st = lib.gsc_combine_coeffs(ptrs, w, len(sets), f, N, sh_deg, C, _ptr(out), _stream_ptr(stream))
+    _check(lib, st)
+    return out
 
 
 def _rows(cams, offsets=None) -> int:

@@ -257,3 +257,41 @@ def test_refine_validation(lib):
     assert call(0) == gsc.GSC_OK and call(5) == gsc.GSC_OK
     assert call(-1) == gsc.GSC_ERR_INVALID_ARG and "n_refine" in lib.gsc_last_error().decode()
     assert call(3, C=0) == gsc.GSC_ERR_INVALID_ARG
+
+
+def test_post_processing_validation(lib):
+    """gsc_combine_coeffs and gsc_mask_filter reject bad arguments before any
+    device work."""
+    ptrs = (ct.c_void_p * 17)(*([FAKE] * 17))
+    w = (ct.c_float * 17)(*([1.0] * 17))
+    comb = lib.gsc_combine_coeffs
+    assert comb(ptrs, w, 0, None, 10, 0, 3, FAKE, None) == gsc.GSC_ERR_INVALID_ARG
+    assert "n_sets" in lib.gsc_last_error().decode()
+    assert comb(ptrs, w, 2, None, 10, 4, 3, FAKE, None) == gsc.GSC_ERR_INVALID_ARG
+    assert comb(ptrs, w, 2, None, 10, 0, 65, FAKE, None) == gsc.GSC_ERR_INVALID_ARG
+    assert comb(ptrs, w, 2, None, -1, 0, 3, FAKE, None) == gsc.GSC_ERR_INVALID_ARG
+    assert comb(ptrs, w, 2, None, 10, 0, 3, None, None) == gsc.GSC_ERR_INVALID_ARG
+    bad_w = (ct.c_float * 2)(1.0, float("nan"))
+    assert comb(ptrs, bad_w, 2, None, 10, 0, 3, FAKE, None) == gsc.GSC_ERR_INVALID_ARG
+    assert "weights[1]" in lib.gsc_last_error().decode()
+    bad_f = (ct.c_float * 3)(1.0, float("inf"), 1.0)
+    assert comb(ptrs, w, 2, bad_f, 10, 0, 3, FAKE, None) == gsc.GSC_ERR_INVALID_ARG
+    # out aliasing a set is allowed up to 16 sets only
+    assert comb(ptrs, w, 17, None, 10, 0, 3, FAKE, None) == gsc.GSC_ERR_INVALID_ARG
+    assert "alias" in lib.gsc_last_error().decode()
+    null_set = (ct.c_void_p * 2)(FAKE, None)
+    assert comb(null_set, w, 2, None, 10, 0, 3, FAKE, None) == gsc.GSC_ERR_INVALID_ARG
+    # nothing to do: no device work, success
+    assert comb(ptrs, w, 2, None, 0, 0, 3, FAKE, None) == gsc.GSC_OK
+
+    ctx = _vctx()
+    mf = lib.gsc_mask_filter
+    assert mf(ctx.handle, FAKE, 10, 0, 3, 0, 0.6, None, FAKE, None, None, None) == gsc.GSC_OK
+    assert mf(ctx.handle, FAKE, 10, 0, 3, 3, 0.6, None, FAKE, None, None, None) == gsc.GSC_ERR_INVALID_ARG
+    assert "channel" in lib.gsc_last_error().decode()
+    assert mf(ctx.handle, FAKE, 10, 0, 3, 0, float("nan"), None, FAKE, None, None, None) == gsc.GSC_ERR_INVALID_ARG
+    assert mf(ctx.handle, FAKE, 10, 0, 3, 0, 0.6, None, None, None, None, None) == gsc.GSC_ERR_INVALID_ARG
+    assert "no output" in lib.gsc_last_error().decode()
+    assert mf(ctx.handle, None, 10, 0, 3, 0, 0.6, None, FAKE, None, None, None) == gsc.GSC_ERR_INVALID_ARG
+    assert mf(None, FAKE, 10, 0, 3, 0, 0.6, None, FAKE, None, None, None) == gsc.GSC_ERR_INVALID_ARG
+    assert mf(ctx.handle, FAKE, 1 << 26, 0, 3, 0, 0.6, None, FAKE, None, None, None) == gsc.GSC_ERR_UNSUPPORTED
