@@ -331,7 +331,7 @@ def cpu_baseline_leg(args, gsc, scenes, table, row0, targets, graph, coeffs, sta
     graph.replay()
     torch.cuda.synchronize()
     c_all, s_all = coeffs.cpu().numpy(), status.cpu().numpy()
-    per_scene, ok = [], True
+    per_scene, ok, all_e = [], True, []
     t_check = time.perf_counter()
     for k, want, ysp in checks:
         sc = scenes[k]
@@ -350,6 +350,7 @@ def cpu_baseline_leg(args, gsc, scenes, table, row0, targets, graph, coeffs, sta
         same_obs = bool(np.array_equal(st[sure] & 1, ref["status"][sure] & 1))
         fl = obs & (b > 0.5e-4)
         ok = ok and inside and same_obs
+        all_e.append(e[obs])
         per_scene.append({"scene": k, "gaussians": sc.N, "views": len(sc.cams), "sampled": int(sel.sum()),
                           "observed": int(obs.sum()), "flagged": int(fl.sum()),
                           "max_rel_err": float(e[obs & ~fl].max()) if (obs & ~fl).any() else 0.0,
@@ -363,6 +364,9 @@ def cpu_baseline_leg(args, gsc, scenes, table, row0, targets, graph, coeffs, sta
                 "flagged_fraction": sum(p["flagged"] for p in per_scene) / max(1, observed),
                 "max_rel_err": max(p["max_rel_err"] for p in per_scene),
                 "scenes": per_scene}
+    ea = np.concatenate(all_e) if all_e else np.zeros(1)
+    accuracy["rel_err_all_compared"] = {"p50": float(np.median(ea)), "p99": float(np.percentile(ea, 99)),
+                                        "max": float(ea.max())}
     # timing: full oracle colorize of each subset scene's first views (about
     # 3 M pixels per scene), on every host thread, and the smallest of these
     # samples on one thread

@@ -125,7 +125,7 @@ def load():
     i64, i32 = ct.c_int64, ct.c_int
     lib.oc_sh_basis.argtypes = [i32, P, i64, P]
     lib.oc_colorize.argtypes = [P, P, P, P, i64, P, i32, P, i32, i32, i32, P, i32, P, P, P, P, P,
-                                P, P, P, P, P, P, P, i32]
+                                P, P, P, P, P, P, P, P, i32]
     lib.oc_render.argtypes = [P, P, P, P, i64, P, i32, P, i32, i32, P, P, P, P, i32]
     lib.oc_colorize_backward.argtypes = [P, P, P, P, i64, P, i32, P, i32, i32, i32, P, i32, P, P,
                                          P, P, P, i32]
@@ -185,8 +185,9 @@ def colorize(scene, targets, want: Optional[np.ndarray] = None, opts: Optional[O
     coeffs [N,nb,C], status, A (regularised), B, w, flip (bound on the
     coefficient change near-threshold decisions could cause), kappa, cnt
     (accepted contributions per Gaussian), ndec (near-threshold decisions on
-    each Gaussian's own acceptance), count (accepted contributions) and
-    events (near-threshold decisions)."""
+    each Gaussian's own acceptance), werr (bound on the relative error of
+    each Gaussian's per-view weight sums from binary32 weights), count
+    (accepted contributions) and events (near-threshold decisions)."""
     lib = load()
     opts = opts or Options()
     m, s, q, o = _geom(scene)
@@ -203,6 +204,7 @@ def colorize(scene, targets, want: Optional[np.ndarray] = None, opts: Optional[O
     kappa = np.zeros(N, np.float64) if with_kappa else None
     cnt = np.zeros(N, np.int64)
     ndec = np.zeros(N, np.int64)
+    werr = np.zeros(N, np.float64)
     stats = np.zeros(2, np.int64)
     wp = None
     if want is not None:
@@ -212,11 +214,11 @@ def colorize(scene, targets, want: Optional[np.ndarray] = None, opts: Optional[O
                          len(scene.cams), _f(t), td, C, scene.sh_deg, _f(lam), lam.size,
                          ct.byref(oo), None if wp is None else _f(wp), _f(coeffs), _f(status),
                          _f(A), _f(B), _f(w), _f(flip), None if kappa is None else _f(kappa),
-                         _f(cnt), _f(ndec), _f(stats), _threads(threads))
+                         _f(cnt), _f(ndec), _f(werr), _f(stats), _threads(threads))
     if rc != 0:
         raise ValueError("oracle colorize rejected its arguments")
     return dict(coeffs=coeffs, status=status, A=A, B=B, w=w, flip=flip, kappa=kappa, cnt=cnt,
-                ndec=ndec, count=int(stats[0]), events=int(stats[1]))
+                ndec=ndec, werr=werr, count=int(stats[0]), events=int(stats[1]))
 
 
 def expand_lambda(lam, L: int) -> np.ndarray:

@@ -277,6 +277,7 @@ typedef struct {
     int32_t x;
     int32_t g;
     double w, alpha, G; /* weight, alpha, exp(-q/2) */
+    double werr;        /* relative error bound of w evaluated in binary32 (margin model) */
     int clamped;        /* alpha hit alpha_max: d alpha / d o = 0 */
 } entry_t;
 
@@ -534,6 +535,7 @@ static void blend_view(const scene_t* sc, const oc_camera* cam, const oc_options
                 en.w = w;
                 en.alpha = alpha;
                 en.G = G;
+                en.werr = da + terr[x]; /* alpha's own error and that of T so far */
                 en.clamped = araw >= amax;
                 push(out, en);
                 st->count++;
@@ -708,6 +710,12 @@ static uint8_t* wanted_mask(const scene_t* sc, const oc_camera* cam, const oc_op
  *   ndec_out [N] near-threshold decisions on g's own acceptance: an
  *   implementation within the margins accepts g exactly cnt_out[g] times
  *   when ndec_out[g] = 0, and differs by at most ndec_out[g] otherwise;
+ *   werr_out [N]: the largest over views of the weight-averaged relative
+ *   error bound of g's pixel weights w = alpha T evaluated in binary32 under
+ *   the margin model (alpha's own margin unless it is surely clamped, plus
+ *   the accumulated bound of T), so that an implementation's per-view sum
+ *   V_gj lies within a factor 1 +- werr_out[g] of the exact one, before the
+ *   rounding of the summation itself;
  *   stats[0] total accepted contributions of the wanted Gaussians,
  *   stats[1] near-threshold decisions.
  */
@@ -716,7 +724,7 @@ int oc_colorize(const float* means, const float* scales, const float* quats, con
                 int C, int L, const float* lam, int n_lambda, const oc_options* o,
                 const uint8_t* want, double* coeffs, uint8_t* status, double* A_out, double* B_out,
                 double* w_out, double* flip_out, double* kappa_out, int64_t* cnt_out,
-                int64_t* ndec_out, int64_t* stats, int n_threads) {
+                int64_t* ndec_out, double* werr_out, int64_t* stats, int n_threads) {
     if (check_common(N, n_cams, C, L)) return -1;
     if (!(n_lambda == 1 || n_lambda == L + 1 || n_lambda == (L + 1) * (L + 1))) return -1;
     int nb = (L + 1) * (L + 1);
@@ -728,7 +736,7 @@ int oc_colorize(const float* means, const float* scales, const float* quats, con
     int64_t* kidx = (int64_t*)malloc(sizeof(int64_t) * (size_t)(N > 0 ? N : 1));
     int64_t K = 0;
     for (int64_t g = 0; g < N; ++g) kidx[g] = (!want || want[g]) ? K++ : -1;
-    int stride = C + 2; /* V, S[C], count */
+    int stride = C + 3; /* V, S[C], count, sum of w times its error bound */
     double* per_view = (double*)calloc((size_t)(K > 0 ? K : 1) * (size_t)(n_cams > 0 ? n_cams : 1) * stride, sizeof(double));
     evlist_t* evs = (evlist_t*)calloc((size_t)(n_cams > 0 ? n_cams : 1), sizeof(evlist_t));
     int64_t tot_events = 0;
@@ -764,6 +772,7 @@ int oc_colorize(const float* means, const float* scales, const float* quats, con
                     a[0] += en->w;
                     for (int c = 0; c < C; ++c) a[1 + c] += en->w * target_at(targets, tdtype, row, C, c);
                     a[C + 1] += 1.0;
+                    a[C + 2] += en->w * en->werr;
                 }
                 row_start = i + 1;
             }
@@ -803,12 +812,13 @@ int oc_colorize(const float* means, const float* scales, const float* quats, con
         double phi[OC_MAX_NB];
         memset(A, 0, sizeof(A));
         memset(B, 0, sizeof(B));
-        double w = 0.0;
+        double w = 0.0, werr = 0.0;
         int64_t cnt = 0;
         for (int j = 0; j < n_cams; ++j) {
             const double* a = per_view + ((size_t)j * (size_t)K + (size_t)k) * stride;
             cnt += (int64_t)a[C + 1];
             if (a[0] == 0.0) continue;
+            werr = fmax(werr, a[C + 2] / a[0]);
             double d[3];
             view_dir(&cams[j], means + 3 * g, d);
             sh_basis(L, d, phi);
@@ -823,6 +833,7 @@ int oc_colorize(const float* means, const float* scales, const float* quats, con
         if (A_out) memcpy(A_out + (size_t)g * nb * nb, A, sizeof(double) * (size_t)(nb * nb));
         if (B_out) memcpy(B_out + (size_t)g * nb * C, B, sizeof(double) * (size_t)(nb * C));
         if (w_out) w_out[g] = w;
+        if (werr_out) werr_out[g] = werr;
         if (cnt_out) cnt_out[g] = cnt;
         uint8_t stt = 0;
         double* cg = coeffs + (size_t)g * nb * C;
@@ -1029,7 +1040,7 @@ int oc_colorize_backward(const float* means, const float* scales, const float* q
     double* tmpc = (double*)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1) * nb * C);
     int rc = oc_colorize(means, scales, quats, opac, N, cams, n_cams, targets, tdtype, C, L, lam,
                          n_lambda, o, NULL, tmpc, NULL, A, NULL, w, NULL, NULL, NULL, NULL, NULL,
-                         n_threads);
+                         NULL, n_threads);
     if (rc) { free(A); free(w); free(tmpc); return rc; }
     double* Bbar = (double*)calloc((size_t)(N > 0 ? N : 1) * nb * C, sizeof(double));
     double* rho = (double*)calloc((size_t)(N > 0 ? N : 1), sizeof(double));

@@ -90,16 +90,17 @@ static int run(int L, int C, int tdtype, int threads) {
     uint8_t status[NG];
     double* A = calloc((size_t)NG * nb * nb, sizeof(double));
     double* B = calloc((size_t)NG * nb * C, sizeof(double));
-    double w[NG], flip[NG], kappa[NG];
+    double w[NG], flip[NG], kappa[NG], werr[NG];
     int64_t cnt[NG], ndec[NG], stats[2];
     uint8_t want[NG];
     for (int g = 0; g < NG; ++g) want[g] = (uint8_t)(g % 3 != 0);
     int bad = 0;
     bad |= oc_colorize(means, scales, quats, opac, NG, cams, NCAM, targets, tdtype, C, L, lam, nb, &o,
-                       NULL, coeffs, status, A, B, w, flip, kappa, cnt, ndec, stats, threads) != 0;
-    bad |= !all_finite(coeffs, (int64_t)NG * nb * C) || !all_finite(w, NG) || !all_finite(flip, NG);
+                       NULL, coeffs, status, A, B, w, flip, kappa, cnt, ndec, werr, stats, threads) != 0;
+    bad |= !all_finite(coeffs, (int64_t)NG * nb * C) || !all_finite(w, NG) || !all_finite(flip, NG) ||
+           !all_finite(werr, NG);
     bad |= oc_colorize(means, scales, quats, opac, NG, cams, NCAM, targets, tdtype, C, L, lam, 1, &o,
-                       want, coeffs, status, A, B, w, flip, NULL, cnt, ndec, stats, threads) != 0;
+                       want, coeffs, status, A, B, w, flip, NULL, cnt, ndec, NULL, stats, threads) != 0;
 
     double* img = calloc((size_t)rows * C, sizeof(double));
     double* pix = calloc((size_t)rows, sizeof(double));

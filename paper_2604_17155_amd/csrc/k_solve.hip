@@ -83,6 +83,43 @@ __device__ __forceinline__ double quad_max(double x) {
     return x;
 }
 
+// Unit direction from a camera centre (FP64) to a Gaussian mean, in FP64:
+// the normal equations are assembled in FP64, and a direction rounded to
+// binary32 would perturb A_g by an amount that weak regularisation does not
+// damp.  1/|d| from the hardware reciprocal square root refined by three
+// Newton steps y <- y (3/2 - n y^2 / 2), each of which squares the relative
+// error (full FP64 from any start better than 2^-12), at a fraction of the
+// cost of a square root and a division.
+__device__ __forceinline__ void view_direction(float mx, float my, float mz, const double* centre,
+                                               double* dir) {
+    const double dx = (double)mx - centre[0];
+    const double dy = (double)my - centre[1];
+    const double dz = (double)mz - centre[2];
+    const double n2 = dx * dx + dy * dy + dz * dz;
+    if (!(n2 > 0.0)) {  // a mean at the camera centre: culled there, any unit vector will do
+        dir[0] = 0.0;
+        dir[1] = 0.0;
+        dir[2] = 1.0;
+        return;
+    }
+    double inv = __builtin_amdgcn_rsq(n2);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) inv = inv * fma(-0.5 * n2 * inv, inv, 1.5);
+    dir[0] = dx * inv;
+    dir[1] = dy * inv;
+    dir[2] = dz * inv;
+}
+
+// Broadcast from quad lane j & 3.
+__device__ __forceinline__ double quad_from(double x, int j) {
+    switch (j & 3) {
+        case 0: return quad_bcast<0>(x);
+        case 1: return quad_bcast<1>(x);
+        case 2: return quad_bcast<2>(x);
+        default: return quad_bcast<3>(x);
+    }
+}
+
 // Fold + solve for L >= 1.  Four lanes (a quad) per Gaussian; lane r owns
 // the rows i = 4k + r of A (lower triangle) and of the right-hand sides,
 // four channels at a time, all in FP64 registers.  The views' sums are read
@@ -180,11 +217,9 @@ __global__ __launch_bounds__(256) void k_fold_solve(const ViewInfo* __restrict__
                     const int v = v0 + u + h;
                     const bool use = valid && v < nvw && cV[u + h] != 0.0f;
                     const int vv = v < nvw ? v : 0;
-                    const float dx = mx - (float)views[vv].centre[0];
-                    const float dy = my - (float)views[vv].centre[1];
-                    const float dz = mz - (float)views[vv].centre[2];
-                    const float inv = rsqrtf(dx * dx + dy * dy + dz * dz);
-                    sh_eval<double, L>((double)(dx * inv), (double)(dy * inv), (double)(dz * inv), phd[h]);
+                    double dir[3];
+                    view_direction(mx, my, mz, views[vv].centre, dir);
+                    sh_eval<double, L>(dir[0], dir[1], dir[2], phd[h]);
                     Vd[h] = use ? (double)cV[u + h] : 0.0;
                     // unused views add nothing to B (their sums read as 0)
 #pragma unroll
@@ -382,6 +417,100 @@ __global__ __launch_bounds__(256) void k_fold_solve(const ViewInfo* __restrict__
     }
     imax = quad_max(imax);
     imin = -quad_max(-imin);
+    // Extreme eigenvalues of M = L L^T: eight steps of power iteration give
+    // lambda_max >= x^T M x / x^T x = |L^T x|^2 / |x|^2 (and lambda_max >=
+    // max_i M_ii), eight of inverse iteration give 1/lambda_min >=
+    // |L^{-1} x|^2 / |x|^2.  Their product is a lower bound of kappa(M) that
+    // is close once the iterates align with the extreme eigenvectors (slowest
+    // when the largest eigenvalues cluster); with the pivot ratio above it is
+    // the estimate.  Vectors are distributed like the rows of L (row 4k + r
+    // on lane r); the starts are golden-ratio sequences, free of the
+    // symmetries of the SH basis that a regular start can share.
+    auto lval = [&](int k, int j) {  // L[4k + r][j] for j <= 4k + r
+        const int i = 4 * k + r;
+        return i == j ? 1.0 / accA[k][j] : accA[k][j];
+    };
+    auto norm2 = [&](const double (&x)[RPL]) {
+        double p = 0.0;
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) p = 4 * k + r < NB ? fma(x[k], x[k], p) : p;
+        return quad_sum(p);
+    };
+    auto lt_mul = [&](const double (&x)[RPL], double (&u)[RPL]) {  // u = L^T x
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            double p = 0.0;
+#pragma unroll
+            for (int k = 0; k < RPL; ++k)
+                if (4 * k + 3 >= j) p = (4 * k + r >= j && 4 * k + r < NB) ? fma(lval(k, j), x[k], p) : p;
+            p = quad_sum(p);
+            if (r == (j & 3)) u[j >> 2] = p;
+        }
+    };
+    auto l_mul = [&](const double (&u)[RPL], double (&z)[RPL]) {  // z = L u
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) z[k] = 0.0;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const double uj = quad_from(u[j >> 2], j);
+#pragma unroll
+            for (int k = 0; k < RPL; ++k)
+                if (4 * k + 3 >= j) z[k] = (4 * k + r >= j && 4 * k + r < NB) ? fma(lval(k, j), uj, z[k]) : z[k];
+        }
+    };
+    auto l_solve = [&](double (&x)[RPL]) {  // x <- L^{-1} x
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const double yj = quad_from(x[j >> 2] * accA[j >> 2][j], j);
+            if (r == (j & 3)) x[j >> 2] = yj;
+#pragma unroll
+            for (int k = 0; k < RPL; ++k)
+                if (4 * k + 3 > j) x[k] = (4 * k + r > j && 4 * k + r < NB) ? fma(-accA[k][j], yj, x[k]) : x[k];
+        }
+    };
+    auto lt_solve = [&](double (&x)[RPL]) {  // x <- L^{-T} x
+#pragma unroll
+        for (int i = NB - 1; i >= 0; --i) {
+            double p = 0.0;
+#pragma unroll
+            for (int k = 0; k < RPL; ++k)
+                if (4 * k + 3 > i) p = (4 * k + r > i && 4 * k + r < NB) ? fma(accA[k][i], x[k], p) : p;
+            p = quad_sum(p);
+            if (r == (i & 3)) x[i >> 2] = (x[i >> 2] - p) * accA[i >> 2][i];
+        }
+    };
+    double xp[RPL], xi[RPL], tmp[RPL];
+    double mdiag = 0.0;  // max_i M_ii = max_i sum_j L_ij^2
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) {
+        const int i = 4 * k + r;
+        const double fp = 0.6180339887498949 * i, fi = 0.7548776662466927 * i;
+        xp[k] = i < NB ? 2.0 * (fp - floor(fp)) - 0.9 : 0.0;
+        xi[k] = i < NB ? 2.0 * (fi - floor(fi)) - 0.9 : 0.0;
+        double rn = 0.0;
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+            if (j < 4 * k + 4) rn = (j <= i && i < NB) ? fma(lval(k, j), lval(k, j), rn) : rn;
+        mdiag = fmax(mdiag, rn);
+    }
+    mdiag = quad_max(mdiag);
+    double lmax_est = 0.0, sig = 0.0;
+#pragma unroll 1
+    for (int it = 0; it < 8; ++it) {
+        const double np = norm2(xp), ni = norm2(xi);
+        lt_mul(xp, tmp);
+        lmax_est = norm2(tmp) / np;
+        l_mul(tmp, xp);
+        l_solve(xi);
+        sig = norm2(xi) / ni;
+        lt_solve(xi);
+        const double sp = 1.0 / sqrt(norm2(xp)), si = 1.0 / sqrt(norm2(xi));
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+            xp[k] *= sp;
+            xi[k] *= si;
+        }
+    }
     if (valid && r == 0) {
         if (wout) wout[g] = (float)wsum;
         uint8_t st = 0;
@@ -390,7 +519,7 @@ __global__ __launch_bounds__(256) void k_fold_solve(const ViewInfo* __restrict__
         } else if (failed) {
             st = GSC_G_FAILED;
         } else {
-            const double kap = (imax / imin) * (imax / imin);
+            const double kap = fmax((imax / imin) * (imax / imin), fmax(lmax_est, mdiag) * sig);
             if (kap > (double)kappa_max) {
                 st = GSC_G_ILL_COND;
                 if (ill_count) atomicAdd(ill_count, 1u);
@@ -467,12 +596,10 @@ __global__ __launch_bounds__(256) void k_refine_update(const ViewInfo* __restric
         for (int v = 0; v < n_views; ++v) {
             const float* p = VS + (int64_t)v * vstep + g * stride;
             if (p[0] == 0.0f) continue;  // no contribution in this view
-            const float dx = mx - (float)views[v].centre[0];
-            const float dy = my - (float)views[v].centre[1];
-            const float dz = mz - (float)views[v].centre[2];
-            const float inv = rsqrtf(dx * dx + dy * dy + dz * dz);
+            double dir[3];
+            view_direction(mx, my, mz, views[v].centre, dir);
             double ph[NB];
-            sh_eval<double, L>((double)(dx * inv), (double)(dy * inv), (double)(dz * inv), ph);
+            sh_eval<double, L>(dir[0], dir[1], dir[2], ph);
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const double sc = c0 + c < C ? (double)p[1 + c0 + c] : 0.0;

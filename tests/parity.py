@@ -117,3 +117,43 @@ def check_render(img_gpu, img_ref, pix_bound, tol_abs=1e-5, label=""):
            f"{int((pix_bound > 0).sum())}, max err among them {err[pix_bound > 0].max() if (pix_bound > 0).any() else 0:.2e}")
     assert over.size == 0, msg + f" | outside: rows {over[:5]} err {err[over[:5]]} bound {pix_bound[over[:5]]}"
     return msg
+
+
+# Binary32 per-view sums.  The GPU forms each view's sums V_gj = sum_p w and
+# S_gj = sum_p w y_p in binary32 (binary32 pixel weights, each pixel's band
+# sum, the wave's reduction, then one addition per tile in any order) and
+# folds them in FP64.  If every V_gj carries a relative error of at most eps,
+# then every term V_gj (phi phi^T + Lambda) of M = A + w Lambda is scaled by a
+# factor in [1 - eps, 1 + eps], so the perturbed matrix satisfies
+#   (1 - eps) M <= M~ <= (1 + eps) M          (Loewner order),
+# and each S_gj[c] moves by at most eps V_gj Y_c (Y_c = max |y_c|).  With
+# X = [sqrt(V_gj) phi_gj] (X X^T = A <= M), |M^{-1/2} dB[:, c]| <=
+# eps Y_c sqrt(w_g).  Hence, in the norm |x|_M = sqrt(x^T M x) (summed over
+# channels),
+#   |c~ - c|_M <= eps (|c|_M + sqrt(w_g) |Y|) / (1 - eps),
+# and |x| <= |x|_M / sqrt(lambda_min(M)):  the error grows with sqrt(kappa),
+# not with kappa.
+#   eps = werr_g (the oracle's bound on the binary32 weights, margin model)
+#       + SUM_DEPTH * 2^-24 (the summation: 4 band terms, 6 reduction levels
+#         and up to 64 tile additions of one Gaussian in one view).
+SUM_DEPTH = 74
+
+
+def fp32_sum_bound(ref, Y, sum_depth=SUM_DEPTH):
+    """Per Gaussian, the bound above divided by max(|c_ref|, tau) (the e_g
+    scale); zero for unobserved Gaussians."""
+    A = ref["A"]
+    c = ref["coeffs"]
+    scale, obs = norms(ref)
+    N = c.shape[0]
+    out = np.zeros(N)
+    Yn = float(np.linalg.norm(np.asarray(Y, np.float64)))
+    for g in np.flatnonzero(obs):
+        eps = ref["werr"][g] + sum_depth * 2.0 ** -24
+        lmin = np.linalg.eigvalsh(A[g])[0]
+        if not lmin > 0:
+            out[g] = np.inf
+            continue
+        cM = np.sqrt(max(0.0, float(np.einsum("mc,mn,nc->", c[g], A[g], c[g]))))
+        out[g] = eps * (cM + np.sqrt(ref["w"][g]) * Yn) / ((1 - eps) * np.sqrt(lmin)) / scale[g]
+    return out
