@@ -141,7 +141,7 @@ struct gsc_ctx {
     // device scratch
     DevBuf views, views_all, cov, keys, vals, keys_alt, vals_alt, counts, offsets, rec0, rec1, rec2,
         sort_scratch, pkeys, pvals, pkeys_alt, pvals_alt, ranges, vs, gamma, bbar, misc, order, queues,
-        coef_t, factor, img, stat, wbuf, post, vsdet, chk;
+        coef_t, factor, img, stat, wbuf, post, vsdet, chk, obs;
     bool order_valid = false;  // `order` holds the tile order of the current binning
     // host staging
     ViewInfo* h_views = nullptr;  // staging of one batch's table
@@ -162,11 +162,11 @@ struct gsc_ctx {
     size_t ev_used = 0;
     struct Mark { int stage; hipEvent_t a, b; uint32_t launches; };
     std::vector<Mark> marks;
-    std::array<DevBuf*, 32> bufs() {
+    std::array<DevBuf*, 33> bufs() {
         return {&views, &views_all, &cov, &keys, &vals, &keys_alt, &vals_alt, &counts,
                 &offsets, &rec0, &rec1, &rec2, &sort_scratch, &pkeys, &pvals, &pkeys_alt,
                 &pvals_alt, &ranges, &vs, &gamma, &bbar, &misc, &order, &queues, &coef_t,
-                &factor, &img, &stat, &wbuf, &post, &vsdet, &chk};
+                &factor, &img, &stat, &wbuf, &post, &vsdet, &chk, &obs};
     }
     ~gsc_ctx() {
         for (DevBuf* b : bufs()) b->release();
@@ -706,11 +706,11 @@ struct gsc_plan {
     float tune_ms[8] = {};
     int tune_variant[8] = {};
     DevBuf d_views, cov, keys, vals, keys_alt, vals_alt, counts, offsets, rec0, rec1,
-        rec2, sort_scratch, pkeys, pvals, pkeys_alt, pvals_alt, ranges, vs, misc, queues, order;
+        rec2, sort_scratch, pkeys, pvals, pkeys_alt, pvals_alt, ranges, vs, misc, queues, order, obs;
     ~gsc_plan() {
         DevBuf* all[] = {&d_views, &cov, &keys, &vals, &keys_alt, &vals_alt, &counts,
                          &offsets, &rec0, &rec1, &rec2, &sort_scratch, &pkeys, &pvals, &pkeys_alt,
-                         &pvals_alt, &ranges, &vs, &misc, &queues, &order};
+                         &pvals_alt, &ranges, &vs, &misc, &queues, &order, &obs};
         for (DevBuf* b : all) b->release();
     }
 };
@@ -850,7 +850,8 @@ gsc_status plan_solve(gsc_plan* P, const double* lam, float* coeffs, uint8_t* st
                           P->vs.as<float>() + P->scene_vs0[k] * (P->C + 1), true, sc.n_gaussians,
                           P->C, P->sh_deg, lam, ctx->opt.kappa_max,
                           coeffs + sc.gaussian_offset * nb * P->C,
-                          status ? status + sc.gaussian_offset : nullptr, nullptr, nullptr, d_ill, s);
+                          status ? status + sc.gaussian_offset : nullptr, nullptr, nullptr, d_ill, s,
+                          nullptr, P->obs.as<uint32_t>());
         GSC_LAUNCHED("fold/solve");
     }
     return GSC_OK;
@@ -1084,10 +1085,15 @@ gsc_status colorize_core(gsc_ctx* ctx, const float* means, const float* scales,
         dc_scratch = ctx->gamma.as<float>();
     }
     unsigned int* d_ill = reinterpret_cast<unsigned int*>(ctx->misc.as<char>() + 12);
+    uint32_t* obs = nullptr;
+    if (sh_deg > 0) {
+        GSC_HIP(ctx->obs.ensure(4 * (size_t)fold_obs_words(N)));
+        obs = ctx->obs.as<uint32_t>();
+    }
     StageTimer t_solve(ctx, s, GSC_STAGE_SOLVE);
     launch_fold_solve(ctx->views_all.as<ViewInfo>(), per_view ? n_cams : 0, means, ctx->vs.as<float>(),
                       per_view, N, C, sh_deg, lam, ctx->opt.kappa_max, coeffs, status, x_vis,
-                      dc_scratch, d_ill, s, factor);
+                      dc_scratch, d_ill, s, factor, obs);
     GSC_LAUNCHED("fold/solve");
     ctx->stats_pending = true;
     ctx->stats_dev = nullptr;
@@ -1182,7 +1188,7 @@ gsc_status gsc_colorize_noalloc(gsc_ctx* ctx, const float* means, const float* s
     const uint64_t items = (uint64_t)N * (uint64_t)n_cams;
     const uint64_t vs_words = (uint64_t)(sh_deg > 0 ? std::max(n_cams, 1) : 1) * (uint64_t)N * (uint64_t)(C + 1);
     const uint64_t known = 2 * sizeof(ViewInfo) * (uint64_t)n_cams + 4ull * kGeoStride * (uint64_t)N +
-                           64ull * items + 4 * vs_words;
+                           64ull * items + 4 * vs_words + (sh_deg > 0 ? 4ull * fold_obs_words(N) : 0);
     if (known > kNoallocScratchBytes)
         return fail(GSC_ERR_CAPACITY,
                     "gsc_colorize_noalloc: %llu Gaussians x %d views x %d channels need at least %llu "
@@ -1715,6 +1721,11 @@ gsc_status gsc_plan_create(gsc_ctx* ctx, const gsc_scene* scenes, int32_t n_scen
     GSC_HIP(P->sort_scratch.ensure(4 * scr + 256));
     GSC_HIP(P->vs.ensure(4 * P->vs_slots * (size_t)(C + 1)));
     GSC_HIP(P->queues.ensure(4 * (size_t)kMaxC));
+    if (sh_deg > 0) {  // observed lists of the fold, one scene at a time
+        int64_t nmax = 1;
+        for (const gsc_scene& sc : P->scenes) nmax = std::max<int64_t>(nmax, sc.n_gaussians);
+        GSC_HIP(P->obs.ensure(4 * (size_t)fold_obs_words(nmax)));
+    }
     *out = guard.release();
     return GSC_OK;
 }

@@ -207,11 +207,17 @@ void launch_render(const ViewInfo* views, int n_views, uint32_t n_tiles, const u
 // factor (optional, sh_deg >= 1): per Gaussian the Cholesky factor of
 // A_g + w_g Lambda, packed by rows (row i at i (i + 1) / 2, 1/L_ii on the
 // diagonal), then w_g: refine_factor_words(sh_deg) doubles.
+// obs_scratch (optional, sh_deg >= 1): fold_obs_words(N) words; then the
+// unobserved Gaussians (no view saw them) are written directly and the fold
+// runs over an ordered list of the observed ones only.
 void launch_fold_solve(const ViewInfo* views, int n_views, const float* means, const float* VS,
                        bool per_view, int64_t N, int C, int sh_deg, const double* lam_nb /*host, nb*/,
                        float kappa_max, float* coeffs, uint8_t* status, float* wout,
                        float* dc_scratch, unsigned int* ill_count, hipStream_t s,
-                       double* factor = nullptr);
+                       double* factor = nullptr, uint32_t* obs_scratch = nullptr);
+inline int64_t fold_obs_words(int64_t N) {  // list, block counts, int64 total, flag bytes
+    return N + (N + 1023) / 1024 + 4 + (N + 3) / 4;
+}
 inline int refine_factor_words(int sh_deg) {
     const int nb = (sh_deg + 1) * (sh_deg + 1);
     return nb * (nb + 1) / 2 + 1;
@@ -300,6 +306,9 @@ void launch_combine(const CombineArgs& a, int64_t n, int C, bool vec4, float* ou
 // the kept indices in increasing order (optional) and their number (device
 // int64, optional).  block_scratch: mask_blocks(N) words.
 int mask_blocks(int64_t N);
+// Exclusive scan in place of n_blocks counts (one block of 1024 threads);
+// *total (if non-null) receives the sum.
+void launch_block_scan(uint32_t* counts, int n_blocks, int64_t* total, hipStream_t s);
 void launch_mask_filter(const float* coeffs, int64_t N, int64_t row, int channel, float thr,
                         const uint8_t* status, uint8_t* keep, int64_t* indices, int64_t* n_kept,
                         uint32_t* block_scratch, hipStream_t s);

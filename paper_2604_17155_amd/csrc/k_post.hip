@@ -158,6 +158,10 @@ __global__ __launch_bounds__(256) void k_mask_scatter(const float* __restrict__ 
 
 int mask_blocks(int64_t N) { return (int)((N + kMaskBlock - 1) / kMaskBlock); }
 
+void launch_block_scan(uint32_t* counts, int n_blocks, int64_t* total, hipStream_t s) {
+    hipLaunchKernelGGL(k_mask_scan, dim3(1), dim3(1024), 0, s, counts, n_blocks, total);
+}
+
 void launch_mask_filter(const float* coeffs, int64_t N, int64_t row, int channel, float thr,
                         const uint8_t* status, uint8_t* keep, int64_t* indices, int64_t* n_kept,
                         uint32_t* block_scratch, hipStream_t s) {

@@ -148,12 +148,18 @@ __global__ __launch_bounds__(256) void k_fold_solve(const ViewInfo* __restrict__
                                                     uint8_t* __restrict__ status,
                                                     float* __restrict__ wout,
                                                     unsigned int* __restrict__ ill_count,
-                                                    double* __restrict__ factor) {
+                                                    double* __restrict__ factor,
+                                                    const uint32_t* __restrict__ list,
+                                                    const int64_t* __restrict__ n_list) {
     constexpr int NB = (L + 1) * (L + 1);
     constexpr int RPL = (NB + 3) / 4;  // rows per lane
     const int r = threadIdx.x & 3;
-    const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 2;
-    const bool valid = g < N;
+    // with a list, quad q takes the q-th observed Gaussian; a wave past the
+    // end of the list has nothing to do (one wave per block: no barrier)
+    const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 2;
+    const bool valid = list ? q < *n_list : q < N;
+    if (list && __builtin_amdgcn_ballot_w64(valid) == 0) return;
+    const int64_t g = list ? (valid ? (int64_t)list[q] : 0) : q;
     const int stride = vs_stride;
     float mx = 0.f, my = 0.f, mz = 0.f;
     if (valid) {
@@ -188,7 +194,7 @@ __global__ __launch_bounds__(256) void k_fold_solve(const ViewInfo* __restrict__
         // without branches (an invalid lane reads its block's first slot, a
         // view past the end reads the last view) and masked where used.
         const int nvw = (!ADJ || firstc) ? n_views : 0;
-        const float* slot = VS + (valid ? g : (int64_t)blockIdx.x * (blockDim.x >> 2)) * (int64_t)stride;
+        const float* slot = VS + (valid ? g : (list ? 0 : (int64_t)blockIdx.x * (blockDim.x >> 2))) * (int64_t)stride;
         const int64_t vstep = N * (int64_t)stride;
         constexpr int kGroup = 4;
         float cV[kGroup], cS[kGroup][4], nV[kGroup], nS[kGroup][4];
@@ -529,10 +535,66 @@ __global__ __launch_bounds__(256) void k_fold_solve(const ViewInfo* __restrict__
     }
 }
 
+// Observed-list pre-pass (one Gaussian per thread, blocks of 1024): a
+// Gaussian is observed when some view gave it weight.  Its views' weights are
+// loaded eight at a time (independent loads in flight together).
+// Unobserved ones get their outputs here (zero coefficients,
+// GSC_G_UNOBSERVED, w = 0); the observed ones are flagged and counted per
+// block, then listed in index order.
+__global__ __launch_bounds__(1024) void k_obs_count(const float* __restrict__ VS, int n_views, int64_t N,
+                                                    int stride, int64_t row, float* __restrict__ coeffs,
+                                                    uint8_t* __restrict__ status, float* __restrict__ wout,
+                                                    uint8_t* __restrict__ flag,
+                                                    uint32_t* __restrict__ block_counts) {
+    __shared__ uint32_t wsum[16];
+    const int64_t g = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    bool seen = false;
+    if (g < N) {
+        for (int v0 = 0; v0 < n_views && !seen; v0 += 8) {
+            float x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) x[u] = v0 + u < n_views ? VS[((int64_t)(v0 + u) * N + g) * stride] : 0.0f;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) seen |= x[u] > 0.0f;
+        }
+        flag[g] = seen ? 1 : 0;
+        if (!seen) {
+            for (int64_t i = 0; i < row; ++i) coeffs[g * row + i] = 0.0f;
+            if (status) status[g] = GSC_G_UNOBSERVED;
+            if (wout) wout[g] = 0.0f;
+        }
+    }
+    const uint64_t bal = __builtin_amdgcn_ballot_w64(seen);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < 16; ++w) t += wsum[w];
+        block_counts[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_obs_scatter(const uint8_t* __restrict__ flag, int64_t N,
+                                                      const uint32_t* __restrict__ block_offsets,
+                                                      uint32_t* __restrict__ list) {
+    __shared__ uint32_t wcnt[16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t g = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    const bool o = g < N && flag[g] != 0;
+    const uint64_t bal = __builtin_amdgcn_ballot_w64(o);
+    if (lane == 0) wcnt[wave] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    uint32_t before = block_offsets[blockIdx.x];
+    for (int w = 0; w < wave; ++w) before += wcnt[w];
+    const uint64_t lt = lane ? (bal & (~0ull >> (64 - lane))) : 0ull;
+    if (o) list[before + (uint32_t)__popcll(lt)] = (uint32_t)g;
+}
+
 void launch_fold_solve(const ViewInfo* views, int n_views, const float* means, const float* VS,
                        bool per_view, int64_t N, int C, int sh_deg, const double* lam_nb,
                        float kappa_max, float* coeffs, uint8_t* status, float* wout,
-                       float* dc_scratch, unsigned int* ill_count, hipStream_t s, double* factor) {
+                       float* dc_scratch, unsigned int* ill_count, hipStream_t s, double* factor,
+                       uint32_t* obs_scratch) {
     if (N <= 0) return;
     if (sh_deg == 0) {
         const float* src = VS;
@@ -555,10 +617,27 @@ void launch_fold_solve(const ViewInfo* views, int n_views, const float* means, c
     dim3 grid((unsigned)((N + 15) / 16)), block(64);
     const float* nf = nullptr;
     float* nw = nullptr;
+    const uint32_t* list = nullptr;
+    const int64_t* n_list = nullptr;
+    if (obs_scratch && per_view && n_views > 0) {
+        // layout: list [N], block counts [nblk], int64 total (8-byte aligned), flags [N bytes]
+        const int nblk = (int)((N + 1023) / 1024);
+        uint32_t* lst = obs_scratch;
+        uint32_t* blocks = obs_scratch + N;
+        const int64_t t_word = (N + nblk + 1) & ~(int64_t)1;
+        int64_t* total = reinterpret_cast<int64_t*>(obs_scratch + t_word);
+        uint8_t* flag = reinterpret_cast<uint8_t*>(obs_scratch + t_word + 2);
+        hipLaunchKernelGGL(k_obs_count, dim3(nblk), dim3(1024), 0, s, VS, n_views, N, C + 1,
+                           (int64_t)nb * C, coeffs, status, wout, flag, blocks);
+        launch_block_scan(blocks, nblk, total, s);
+        hipLaunchKernelGGL(k_obs_scatter, dim3(nblk), dim3(1024), 0, s, flag, N, blocks, lst);
+        list = lst;
+        n_list = total;
+    }
     switch (sh_deg) {
-        case 1: hipLaunchKernelGGL((k_fold_solve<1, false>), grid, block, 0, s, views, n_views, means, VS, C + 1, N, C, lam, kappa_max, nf, nf, coeffs, nw, status, wout, ill_count, factor); break;
-        case 2: hipLaunchKernelGGL((k_fold_solve<2, false>), grid, block, 0, s, views, n_views, means, VS, C + 1, N, C, lam, kappa_max, nf, nf, coeffs, nw, status, wout, ill_count, factor); break;
-        default: hipLaunchKernelGGL((k_fold_solve<3, false>), grid, block, 0, s, views, n_views, means, VS, C + 1, N, C, lam, kappa_max, nf, nf, coeffs, nw, status, wout, ill_count, factor); break;
+        case 1: hipLaunchKernelGGL((k_fold_solve<1, false>), grid, block, 0, s, views, n_views, means, VS, C + 1, N, C, lam, kappa_max, nf, nf, coeffs, nw, status, wout, ill_count, factor, list, n_list); break;
+        case 2: hipLaunchKernelGGL((k_fold_solve<2, false>), grid, block, 0, s, views, n_views, means, VS, C + 1, N, C, lam, kappa_max, nf, nf, coeffs, nw, status, wout, ill_count, factor, list, n_list); break;
+        default: hipLaunchKernelGGL((k_fold_solve<3, false>), grid, block, 0, s, views, n_views, means, VS, C + 1, N, C, lam, kappa_max, nf, nf, coeffs, nw, status, wout, ill_count, factor, list, n_list); break;
     }
 }
 
@@ -744,9 +823,9 @@ void launch_adjoint_solve(const ViewInfo* views, int n_views, const float* means
     float* nw = nullptr;
     unsigned int* ni = nullptr;
     switch (sh_deg) {
-        case 1: hipLaunchKernelGGL((k_fold_solve<1, true>), grid, block, 0, s, views, n_views, means, V, 1, N, C, lam, 0.0f, grad_coeffs, coeffs, bbar, rho, ns, nw, ni, nullptr); break;
-        case 2: hipLaunchKernelGGL((k_fold_solve<2, true>), grid, block, 0, s, views, n_views, means, V, 1, N, C, lam, 0.0f, grad_coeffs, coeffs, bbar, rho, ns, nw, ni, nullptr); break;
-        default: hipLaunchKernelGGL((k_fold_solve<3, true>), grid, block, 0, s, views, n_views, means, V, 1, N, C, lam, 0.0f, grad_coeffs, coeffs, bbar, rho, ns, nw, ni, nullptr); break;
+        case 1: hipLaunchKernelGGL((k_fold_solve<1, true>), grid, block, 0, s, views, n_views, means, V, 1, N, C, lam, 0.0f, grad_coeffs, coeffs, bbar, rho, ns, nw, ni, nullptr, nullptr, nullptr); break;
+        case 2: hipLaunchKernelGGL((k_fold_solve<2, true>), grid, block, 0, s, views, n_views, means, V, 1, N, C, lam, 0.0f, grad_coeffs, coeffs, bbar, rho, ns, nw, ni, nullptr, nullptr, nullptr); break;
+        default: hipLaunchKernelGGL((k_fold_solve<3, true>), grid, block, 0, s, views, n_views, means, V, 1, N, C, lam, 0.0f, grad_coeffs, coeffs, bbar, rho, ns, nw, ni, nullptr, nullptr, nullptr); break;
     }
 }
 
