@@ -411,6 +411,30 @@ gsc_status gsc_mask_filter(gsc_ctx* ctx, const float* coeffs, int64_t N, int32_t
                            int64_t* indices, int64_t* n_kept, gsc_stream_t stream);
 
 /*
+ * View selection (Sec. 5: fewer camera images, chosen by visibility).  Picks
+ * k of the n_cams views greedily to maximise the coverage objective
+ *   sum_g min(number of chosen views that observe g, multiplicity),
+ * where view j observes Gaussian g when g receives weight at some pixel of j
+ * (V_gj > 0 under the context's blend options).  Each pick takes the view
+ * with the largest gain; ties go to the lower index.  The objective is
+ * monotone and submodular, so the greedy choice reaches at least (1 - 1/e) of
+ * the best k-view objective.  Colorize the chosen views by passing those
+ * cameras (with their pixel_offset unchanged, so the targets stay where they
+ * are).
+ *   cams: host [n_cams]; k in [0, n_cams]; multiplicity in [1, 64] (1:
+ *   cover every Gaussian once; L >= 1 solves profit from several views per
+ *   Gaussian).
+ *   chosen: host output [k], view indices in the order picked.
+ *   objective: host output (may be NULL), the objective of the chosen set.
+ * Runs one weights-only blend of every view, reads n_cams * ceil(N / 64)
+ * 64-bit words back (synchronises `stream`), then picks on the host.
+ */
+gsc_status gsc_select_views(gsc_ctx* ctx, const float* means, const float* scales, const float* quats,
+                            const float* opacities, int64_t N, const gsc_camera* cams, int32_t n_cams,
+                            int32_t k, int32_t multiplicity, int32_t* chosen, int64_t* objective,
+                            gsc_stream_t stream);
+
+/*
  * Batched colorize of many scenes (plans).
  *
  * Several scenes of uneven size are colorized in one pass: all their views

@@ -502,3 +502,39 @@ def mask_filter(coeffs, channel: int = 0, threshold: float = 0.6, status=None):
     if status is not None:
         keep &= (np.asarray(status) & (UNOBSERVED | FAILED)) == 0
     return keep, np.nonzero(keep)[0].astype(np.int64)
+
+
+# --- view selection (Sec. 5: fewer camera images) ----------------------------
+
+def observed_pairs(scene, opts: Optional[Options] = None) -> np.ndarray:
+    """[n_views, N] bool: view j observes Gaussian g (some pixel of j gives g
+    weight), from the oracle's contributions."""
+    idx, _ = contributions(scene, opts, cap=max(5_000_000, 4 * scene.n_pixels))
+    seen = np.zeros((len(scene.cams), scene.N), bool)
+    seen[idx[:, 0], idx[:, 2]] = True
+    return seen
+
+
+def coverage(seen: np.ndarray, views, multiplicity: int) -> int:
+    """sum_g min(number of the given views that observe g, multiplicity)."""
+    if len(views) == 0:
+        return 0
+    return int(np.minimum(seen[list(views)].sum(axis=0), multiplicity).sum())
+
+
+def select_views(seen: np.ndarray, k: int, multiplicity: int = 1):
+    """Greedy maximum coverage: k times, take the view whose addition raises
+    coverage() the most (lowest index on ties).  Returns (views in pick
+    order, objective)."""
+    chosen = []
+    for _ in range(k):
+        base = coverage(seen, chosen, multiplicity)
+        best, best_gain = -1, -1
+        for j in range(seen.shape[0]):
+            if j in chosen:
+                continue
+            gain = coverage(seen, chosen + [j], multiplicity) - base
+            if gain > best_gain:
+                best, best_gain = j, gain
+        chosen.append(best)
+    return chosen, coverage(seen, chosen, multiplicity)

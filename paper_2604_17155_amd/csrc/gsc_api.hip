@@ -1911,6 +1911,94 @@ gsc_status gsc_mask_filter(gsc_ctx* ctx, const float* coeffs, int64_t N, int32_t
     return GSC_OK;
 }
 
+gsc_status gsc_select_views(gsc_ctx* ctx, const float* means, const float* scales, const float* quats,
+                            const float* opacities, int64_t N, const gsc_camera* cams, int32_t n_cams,
+                            int32_t k, int32_t multiplicity, int32_t* chosen, int64_t* objective,
+                            gsc_stream_t stream) {
+    if (!ctx) return fail(GSC_ERR_INVALID_ARG, "null ctx");
+    int64_t rows = 0;
+    gsc_status st = validate_geometry(means, scales, quats, opacities, N, cams, n_cams, &rows);
+    if (st != GSC_OK) return st;
+    if (k < 0 || k > n_cams) return fail(GSC_ERR_INVALID_ARG, "k must be in [0, n_cams] (got %d)", k);
+    if (multiplicity < 1 || multiplicity > 64)
+        return fail(GSC_ERR_INVALID_ARG, "multiplicity must be in [1, 64] (got %d)", multiplicity);
+    if (k > 0 && !chosen) return fail(GSC_ERR_INVALID_ARG, "chosen is null");
+    if (ctx->opt.flags & GSC_FLAG_VALIDATE_ONLY) return GSC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = refuse_capture(s, "gsc_select_views")) != GSC_OK) return st;
+    memset(&ctx->stats, 0, sizeof(ctx->stats));
+    if (objective) *objective = 0;
+    if (k == 0) return GSC_OK;
+    const int64_t words = (N + 63) / 64;
+    std::vector<uint64_t> bits((size_t)n_cams * (size_t)words, 0);
+    if (N > 0) {
+        // 1. per-view visibilities V_gj from a weights-only blend of every view
+        BlendParams bp = blend_params(ctx->opt);
+        if ((st = ensure_common(ctx, means, scales, quats, opacities, N, cams, n_cams, s)) != GSC_OK) return st;
+        std::vector<ViewInfo> all(n_cams);
+        for (int j = 0; j < n_cams; ++j) all[j] = make_view(cams[j], j, N, ctx->bin);
+        const uint64_t v_words = (uint64_t)n_cams * (uint64_t)N;
+        GSC_HIP(ctx->vs.ensure(4 * v_words));
+        launch_fill_u32(ctx->vs.as<uint32_t>(), 0u, v_words, s);
+        unsigned long long* d_counter = reinterpret_cast<unsigned long long*>(ctx->misc.p);
+        st = for_view_batches_k(ctx, all.data(), n_cams, means, opacities, N, bp, s, nullptr, false,
+                                [&](int v0, int nv, const Binned& bn) -> gsc_status {
+            StageTimer t(ctx, s, GSC_STAGE_BLEND);
+            (void)v0;
+            launch_accumulate_weights(ctx->views.as<ViewInfo>(), nv, bn.n_tiles, ctx->ranges.as<uint2>(),
+                                      ctx->pvals.as<uint32_t>(), ctx->rec0.as<float4>(),
+                                      ctx->rec1.as<float4>(), ctx->rec2.as<uint2>(), ctx->bin, true, bp,
+                                      ctx->vs.as<float>(), d_counter, s, tile_order(ctx, bn.n_tiles));
+            GSC_LAUNCHED("accumulate weights");
+            return GSC_OK;
+        });
+        if (st != GSC_OK) return st;
+        // 2. one bitset per view of the Gaussians it observed, read back
+        GSC_HIP(ctx->post.ensure(8 * bits.size()));
+        launch_seen_bits(ctx->vs.as<float>(), n_cams, N, ctx->post.as<unsigned long long>(), s);
+        GSC_LAUNCHED("seen bits");
+        GSC_HIP(hipMemcpyAsync(bits.data(), ctx->post.p, 8 * bits.size(), hipMemcpyDeviceToHost, s));
+        GSC_HIP(hipStreamSynchronize(s));
+        ctx->stats_pending = true;
+        ctx->stats_dev = nullptr;
+    }
+    // 3. greedy maximum coverage of sum_g min(views seeing g, multiplicity):
+    // layer r holds the Gaussians seen by at least r + 1 chosen views; a new
+    // view raises each Gaussian it sees by one, so its gain is the number of
+    // them not yet in the top layer.  Ties go to the lower view index.
+    const int R = multiplicity;
+    std::vector<uint64_t> layer((size_t)R * (size_t)words, 0);
+    std::vector<char> used(n_cams, 0);
+    int64_t total = 0;
+    for (int pick = 0; pick < k; ++pick) {
+        int best = -1;
+        int64_t best_gain = -1;
+        for (int j = 0; j < n_cams; ++j) {
+            if (used[j]) continue;
+            const uint64_t* b = bits.data() + (size_t)j * words;
+            const uint64_t* top = layer.data() + (size_t)(R - 1) * words;
+            int64_t gain = 0;
+            for (int64_t w = 0; w < words; ++w) gain += __builtin_popcountll(b[w] & ~top[w]);
+            if (gain > best_gain) {
+                best_gain = gain;
+                best = j;
+            }
+        }
+        used[best] = 1;
+        chosen[pick] = best;
+        total += best_gain;
+        // a Gaussian seen by the new view moves up one layer
+        const uint64_t* b = bits.data() + (size_t)best * words;
+        for (int r = R - 1; r >= 0; --r) {
+            uint64_t* l = layer.data() + (size_t)r * words;
+            const uint64_t* below = r > 0 ? layer.data() + (size_t)(r - 1) * words : nullptr;
+            for (int64_t w = 0; w < words; ++w) l[w] |= b[w] & (below ? below[w] : ~0ull);
+        }
+    }
+    if (objective) *objective = total;
+    return GSC_OK;
+}
+
 gsc_status gsc_get_stats(gsc_ctx* ctx, gsc_stats* out) {
     if (!ctx || !out) return fail(GSC_ERR_INVALID_ARG, "null ctx or output");
     if (ctx->stats_pending && (ctx->stats_dev || ctx->misc.p)) {

@@ -287,6 +287,10 @@ void launch_scan_values(const void* p, int dtype, int64_t n, unsigned long long*
 void launch_det_to_float(const unsigned long long* in, int64_t n, int stride, double inv_v,
                          double inv_s, float* out, hipStream_t s);
 
+// View selection: one bitset per view of the Gaussians it observed
+// (bits[v][w], (N + 63) / 64 words per view) from per-view weights V [n_views][N].
+void launch_seen_bits(const float* V, int n_views, int64_t N, unsigned long long* bits, hipStream_t s);
+
 // Post-processing.  Linear combination of up to kCombineSets coefficient sets
 // per launch: out = filter * sum_k w_k p_k elementwise (filter by channel,
 // i mod C, applied when `filter`); with `accumulate` the sum continues from

@@ -179,4 +179,24 @@ void launch_mask_filter(const float* coeffs, int64_t N, int64_t row, int channel
                            status, block_scratch, indices);
 }
 
+// bits[v][w] bit b = (V[v][64 w + b] > 0): which Gaussians view v observed.
+__global__ __launch_bounds__(256) void k_seen_bits(const float* __restrict__ V, int n_views, int64_t N,
+                                                   int64_t words, unsigned long long* __restrict__ bits) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // one thread per bit
+    const int64_t total = (int64_t)n_views * words * 64;
+    if (i >= total) return;  // whole trailing waves only: words * 64 is a multiple of 64
+    const int64_t v = i / (words * 64), g = i % (words * 64);
+    const bool seen = g < N && V[v * N + g] > 0.0f;
+    const uint64_t bal = __builtin_amdgcn_ballot_w64(seen);
+    if ((threadIdx.x & 63) == 0) bits[v * words + g / 64] = bal;
+}
+
+void launch_seen_bits(const float* V, int n_views, int64_t N, unsigned long long* bits, hipStream_t s) {
+    const int64_t words = (N + 63) / 64;
+    const int64_t total = (int64_t)n_views * words * 64;
+    if (total == 0) return;
+    hipLaunchKernelGGL(k_seen_bits, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, V, n_views, N,
+                       words, bits);
+}
+
 }  // namespace gsc

@@ -139,6 +139,8 @@ def load(path: Optional[str] = None):
     lib.gsc_combine_coeffs.restype = ct.c_int
     lib.gsc_mask_filter.argtypes = [P, P, i64, i32, i32, i32, ct.c_float, P, P, P, P, P]
     lib.gsc_mask_filter.restype = ct.c_int
+    lib.gsc_select_views.argtypes = [P, P, P, P, P, i64, P, i32, i32, i32, P, P, P]
+    lib.gsc_select_views.restype = ct.c_int
     lib.gsc_get_stats.argtypes = [P, ct.POINTER(GscStats)]
     lib.gsc_get_stats.restype = ct.c_int
     lib.gsc_last_error.argtypes = []
@@ -339,6 +341,19 @@ class Context:
                                            _ptr(coeffs), _ptr(status), _stream_ptr(stream))
         _check(self.lib, st)
         return coeffs, status
+
+    def select_views(self, means, scales, quats, opacities, cams, k: int, multiplicity: int = 1,
+                     offsets=None, stream=None):
+        """gsc_select_views: k view indices picked greedily for coverage
+        (in pick order) and the coverage objective they reach."""
+        cam_arr = make_cameras(cams, offsets)
+        out = (ct.c_int32 * max(1, int(k)))()
+        obj = ct.c_int64(0)
+        st = self.lib.gsc_select_views(self.handle, _ptr(means), _ptr(scales), _ptr(quats),
+                                       _ptr(opacities), int(means.shape[0]), cam_arr, len(cams), int(k),
+                                       int(multiplicity), out, ct.byref(obj), _stream_ptr(stream))
+        _check(self.lib, st)
+        return [int(out[i]) for i in range(int(k))], int(obj.value)
 
     def mask_filter(self, coeffs, channel: int = 0, threshold: float = 0.6, status=None,
                     want_keep: bool = True, stream=None):
