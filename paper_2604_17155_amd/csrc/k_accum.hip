@@ -509,13 +509,17 @@ __device__ __forceinline__ uint32_t accumulate_tile_mfma(
     for (int k = 0; k < 4; ++k) lyk[k] = tile_offset_row(lane, k);
     const float ox = tile_centre(tg.x0), oy = tile_centre(tg.y0);
 
-    // W rows start (and are left) zero
-    {
-        uint4* wz = reinterpret_cast<uint4*>(&L.whi[0]);
-        constexpr int n4 = 2 * ROWS * kWRow * 2 / 16;  // both planes
-        for (int i = (int)lane; i < n4; i += 64) wz[i] = make_uint4(0u, 0u, 0u, 0u);
-        __builtin_amdgcn_wave_barrier();
-    }
+    // Rows are never cleared; rows past a group's count feed only output rows
+    // that the flush does not use.  Two ways keep a row's unreached bands out
+    // of the product (measured: each is the faster for its shape):
+    //  - one channel block (VALU-bound at four waves per SIMD): the entry
+    //    writes zeros in the bands its footprint misses;
+    //  - several blocks: the entry writes only the bands it reaches; lane m
+    //    keeps row m's band mask (rowmask), the flush zeroes a row's operand
+    //    where that mask lacks the band and skips the K-steps of a band that
+    //    no row of the group wrote.
+    constexpr bool kBandMask = NBLK > 1;
+    uint32_t rowmask = 0;
 
     // one matrix product over the group's `rows` entries, then the atomics
     auto flush = [&](uint32_t rows) {
@@ -528,14 +532,25 @@ __device__ __forceinline__ uint32_t accumulate_tile_mfma(
         const uint32_t arow = n16 < (uint32_t)ROWS ? n16 : 0u;
         const __bf16* ah_p = &L.whi[arow * kWRow + 8 * q4];
         const __bf16* al_p = &L.wlo[arow * kWRow + 8 * q4];
+        // the band mask of this lane's A row, and the bands any row wrote
+        uint32_t mrow = (ROWS < 16 && n16 >= (uint32_t)ROWS) ? 0u : 0xFu;
+        uint32_t anyb = 0xFu;
+        if constexpr (kBandMask) {
+            mrow &= (uint32_t)__shfl((int)rowmask, (int)arow, 64);
+            anyb = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                anyb |= (__builtin_amdgcn_ballot_w64(lane < rows && ((rowmask >> k) & 1u)) != 0 ? 1u : 0u) << k;
+        }
         bf16x8_t zero8;
 #pragma unroll
         for (int i = 0; i < 8; ++i) zero8[i] = (__bf16)0.0f;
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
+            if (!((anyb >> (s >> 1)) & 1u)) continue;  // uniform: no row wrote this band
             bf16x8_t ah = *reinterpret_cast<const bf16x8_t*>(ah_p + 32 * s);
             bf16x8_t al = *reinterpret_cast<const bf16x8_t*>(al_p + 32 * s);
-            if (ROWS < 16 && n16 >= (uint32_t)ROWS) {
+            if (!((mrow >> (s >> 1)) & 1u)) {
                 ah = zero8;
                 al = zero8;
             }
@@ -571,15 +586,7 @@ __device__ __forceinline__ uint32_t accumulate_tile_mfma(
                 else if ((int)n16 < C) unsafeAtomicAdd(slot + 1 + n16, D[0][i] + lo);
             }
         }
-        // clear the rows used
-        __builtin_amdgcn_wave_barrier();
-        uint4* wh = reinterpret_cast<uint4*>(&L.whi[0]);
-        uint4* wl = reinterpret_cast<uint4*>(&L.wlo[0]);
-        const uint32_t n4 = rows * kWRow * 2 / 16;
-        for (uint32_t i = lane; i < n4; i += 64) {
-            wh[i] = make_uint4(0u, 0u, 0u, 0u);
-            wl[i] = make_uint4(0u, 0u, 0u, 0u);
-        }
+        // the next group overwrites these rows
         __builtin_amdgcn_wave_barrier();
     };
 
@@ -633,9 +640,16 @@ __device__ __forceinline__ uint32_t accumulate_tile_mfma(
         uint32_t nh = 0;
         __bf16* wrow_h = &L.whi[rows * kWRow];
         __bf16* wrow_l = &L.wlo[rows * kWRow];
+        if constexpr (kBandMask) rowmask = lane == rows ? bands : rowmask;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            if (!((bands >> k) & 1u)) continue;  // uniform
+            if (!((bands >> k) & 1u)) {  // uniform: no weight in this band
+                if constexpr (!kBandMask) {
+                    wrow_h[lane + 64 * k] = (__bf16)0.0f;
+                    wrow_l[lane + 64 * k] = (__bf16)0.0f;
+                }
+                continue;
+            }
             const float dy = c0.y + lyk[k];
             const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
             uint64_t taken;
