@@ -226,13 +226,13 @@ __device__ __forceinline__ uint32_t accumulate_tile(
                     if (!((bands >> k) & 1u)) continue;  // uniform
                     const float dy = c0.y + lyk[k];
                     const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
-                    uint64_t taken;
-                    const float w = pixel_step(q2, c1.w, T[k], qlim, amin, amax, tmin, taken);
+                    uint64_t taken, kept;
+                    const float w = pixel_step(q2, c1.w, T[k], qlim, amin, amax, tmin, taken, kept);
                     sv += w;
     #pragma unroll
                     for (int c = 0; c < CC; ++c) ss[c] = fmaf(w, y[k][c], ss[c]);
                     nh += (uint32_t)__popcll(taken);
-                    if (__builtin_amdgcn_ballot_w64(T[k] > 0.0f) == 0) alive &= ~(1u << k);
+                    if (kept == 0) alive &= ~(1u << k);
                 }
                 // keep the band mask and the count in scalar registers
                 alive = (uint32_t)__builtin_amdgcn_readfirstlane((int)alive);
@@ -384,8 +384,8 @@ static void launch_acc_cc(const ViewInfo* views, int n_views, uint32_t n_bins, c
 // The channel sums S_g[c] = sum_p w_gp y_p[c] of a tile are a product
 // W (Gaussians x pixels) . Y (pixels x channels).  Here the blend runs as in
 // accumulate_tile, but each entry's weights go to LDS as a row of W, split
-// into a BF16 high part and a BF16 remainder (w = hi + lo to ~2^-17
-// relative).  Every 16 entries, v_mfma_f32_16x16x32_bf16 forms
+// into a BF16 high part (w's upper half) and a BF16 remainder (the exact
+// w - hi rounded; w = hi + lo to 2^-16 relative).  Every 16 entries, v_mfma_f32_16x16x32_bf16 forms
 // (W_hi + W_lo) . [Y | 1] over the tile's 256 pixels (eight K-steps of 32
 // pixels): the targets, held as B operands in registers for the whole tile,
 // give S, and a block of ones gives V = sum_p w from the same split weights.
@@ -480,12 +480,18 @@ __device__ __forceinline__ uint32_t accumulate_tile_mfma(
 #pragma unroll
     for (int i = 0; i < 8; ++i) ones[i] = (__bf16)1.0f;
 
-    float T[4];
+    // transmittance of the lane's pixel in each band: four scalars (as an
+    // array the compiler rebuilt it in new registers on every band update)
+    float T0, T1, T2, T3;
     uint32_t alive = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const bool inside = (ix < vw) & (iy0 + 4 * k < vh);
-        T[k] = inside ? 1.0f : 0.0f;
+        const float t = inside ? 1.0f : 0.0f;
+        if (k == 0) T0 = t;
+        if (k == 1) T1 = t;
+        if (k == 2) T2 = t;
+        if (k == 3) T3 = t;
         alive |= (__builtin_amdgcn_ballot_w64(inside) != 0 ? 1u : 0u) << k;
     }
     alive = (uint32_t)__builtin_amdgcn_readfirstlane((int)alive);
@@ -641,26 +647,32 @@ __device__ __forceinline__ uint32_t accumulate_tile_mfma(
         __bf16* wrow_h = &L.whi[rows * kWRow];
         __bf16* wrow_l = &L.wlo[rows * kWRow];
         if constexpr (kBandMask) rowmask = lane == rows ? bands : rowmask;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        auto band = [&](const int k, float& Tk) {
             if (!((bands >> k) & 1u)) {  // uniform: no weight in this band
                 if constexpr (!kBandMask) {
                     wrow_h[lane + 64 * k] = (__bf16)0.0f;
                     wrow_l[lane + 64 * k] = (__bf16)0.0f;
                 }
-                continue;
+                return;
             }
             const float dy = c0.y + lyk[k];
             const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
-            uint64_t taken;
-            const float w = pixel_step(q2, c1.w, T[k], qlim, amin, amax, tmin, taken);
-            const __bf16 hi = (__bf16)w;
-            const __bf16 lo = (__bf16)(w - (float)hi);
+            uint64_t taken, kept;
+            const float w = pixel_step(q2, c1.w, Tk, qlim, amin, amax, tmin, taken, kept);
+            // hi: w's upper half (truncated), lo: the exact remainder rounded
+            // to BF16; |w - hi - lo| <= 2^-16 |w|
+            const uint32_t wb = __float_as_uint(w);
+            const __bf16 hi = __builtin_bit_cast(__bf16, (uint16_t)(wb >> 16));
+            const __bf16 lo = (__bf16)(w - __uint_as_float(wb & 0xffff0000u));
             wrow_h[lane + 64 * k] = hi;
             wrow_l[lane + 64 * k] = lo;
             nh += (uint32_t)__popcll(taken);
-            if (__builtin_amdgcn_ballot_w64(T[k] > 0.0f) == 0) alive &= ~(1u << k);
-        }
+            if (kept == 0) alive &= ~(1u << k);
+        };
+        band(0, T0);
+        band(1, T1);
+        band(2, T2);
+        band(3, T3);
         alive = (uint32_t)__builtin_amdgcn_readfirstlane((int)alive);
         nh = (uint32_t)__builtin_amdgcn_readfirstlane((int)nh);
         cnt += nh;

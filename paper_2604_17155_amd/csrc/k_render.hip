@@ -165,12 +165,12 @@ __global__ __launch_bounds__(256) void k_render(
                 if (!((bands >> k) & 1u)) continue;
                 const float dy = c0.y + lyk[k];
                 const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
-                uint64_t taken;
-                const float w = pixel_step(q2, c1.w, T[k], qlim, amin, amax, tmin, taken);
+                uint64_t taken, kept;
+                const float w = pixel_step(q2, c1.w, T[k], qlim, amin, amax, tmin, taken, kept);
 #pragma unroll
                 for (int c = 0; c < CC; ++c) img[k][c] = fmaf(w, col[c], img[k][c]);
                 nh += (uint32_t)__popcll(taken);
-                if (__builtin_amdgcn_ballot_w64(T[k] > 0.0f) == 0) alive &= ~(1u << k);
+                if (kept == 0) alive &= ~(1u << k);
             }
             alive = (uint32_t)__builtin_amdgcn_readfirstlane((int)alive);
             cnt += (uint32_t)__builtin_amdgcn_readfirstlane((int)nh);
