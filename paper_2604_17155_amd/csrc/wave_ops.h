@@ -238,21 +238,24 @@ __device__ __forceinline__ float uniform_in_vgpr(float x) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xE4, 0xF, 0xF, true));
 }
 
-// kept: the lanes whose T stays above zero after the step.  When it is
-// empty, every pixel of the band has stopped (T = 0 is only ever set by a
-// stop), so the band can be retired without a separate test of T.
+// T of a pixel that has stopped, or lies outside the image, is kStoppedT
+// (negative): its test T (1 - alpha) is then negative and fails the stop
+// test for any t_min >= 0, so such a pixel takes no weight without a
+// separate test.  kept: the lanes still live after the step; when it is
+// empty every pixel of the band has stopped and the band can be retired.
+constexpr float kStoppedT = -1.0f;
+
 __device__ __forceinline__ float pixel_step(float q2, float opac, float& T, float qlim, float amin,
                                             float amax, float tmin, uint64_t& taken, uint64_t& kept) {
     const float al = __builtin_amdgcn_fmed3f(opac * __builtin_amdgcn_exp2f(q2), 0.0f, amax);
     const bool inq = q2 >= qlim, ina = al >= amin;
     const float ae = (inq & ina) ? al : 0.0f;
     const float test = fmaf(-T, ae, T);
-    const bool keep = test >= tmin, live = T > 0.0f;
+    const bool keep = test >= tmin;
     kept = __builtin_amdgcn_ballot_w64(keep);
-    taken = __builtin_amdgcn_ballot_w64(inq) & __builtin_amdgcn_ballot_w64(ina) & kept &
-            __builtin_amdgcn_ballot_w64(live);
+    taken = __builtin_amdgcn_ballot_w64(inq) & __builtin_amdgcn_ballot_w64(ina) & kept;
     const float w = keep ? T * ae : 0.0f;
-    T = keep ? test : 0.0f;
+    T = keep ? test : kStoppedT;
     return w;
 }
 
