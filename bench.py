@@ -286,23 +286,17 @@ def segment_subset(scenes, seed=20260417):
     return [order[0], order[-1]] + pick
 
 
-def cpu_baseline_leg(args, gsc, scenes, table, row0, targets, graph, coeffs, status):
-    """The oracle leg of the batched workload (the only place bench.py runs
-    the oracle).  Two parts:
-      check  -- on the smallest, the largest and two random scenes, sample
-                Gaussians, render the target rows they read with the oracle,
-                write those rows into the device targets, replay the timed
-                graph once and compare the sampled Gaussians' coefficients
-                with the oracle's (e_g <= 1e-4 + the bound of near-threshold
-                decisions, as in tests/parity.py);
-      timing -- the oracle's full colorize on a bounded sample of the same
-                scenes (their first views), on all host threads and on one.
-    Returns (accuracy, cpu_baseline)."""
+def segment_check(scenes, table, row0, targets, rerun, coeffs, status, threads):
+    """Accuracy of the batched plan against the oracle on the smallest, the
+    largest and two random scenes: sample Gaussians, render the target rows
+    they read with the oracle, write those rows into the device targets, run
+    the plan again (`rerun`) and compare the sampled Gaussians' coefficients
+    with the oracle's (e_g <= 1e-4 + the bound of near-threshold decisions,
+    as in tests/parity.py; the unobserved sets agree where no decision is in
+    doubt).  Returns the accuracy record."""
     import numpy as np
     import torch
     import oracle
-    from paper_2604_17155_amd import synthetic as syn
-    threads = host_threads()
     subset = segment_subset(scenes)
     rng = np.random.default_rng(7)
     checks = []
@@ -328,7 +322,7 @@ def cpu_baseline_leg(args, gsc, scenes, table, row0, targets, graph, coeffs, sta
         targets[idx] = torch.from_numpy(vals.view(np.int16)).cuda().view(torch.bfloat16)
         checks.append((k, want, ysp))
     torch.cuda.synchronize()
-    graph.replay()
+    rerun()
     torch.cuda.synchronize()
     c_all, s_all = coeffs.cpu().numpy(), status.cpu().numpy()
     per_scene, ok, all_e = [], True, []
@@ -349,7 +343,7 @@ def cpu_baseline_leg(args, gsc, scenes, table, row0, targets, graph, coeffs, sta
         sure = sel & (ref["ndec"] == 0)
         same_obs = bool(np.array_equal(st[sure] & 1, ref["status"][sure] & 1))
         fl = obs & (b > 0.5e-4)
-        ok = ok and inside and same_obs
+        ok = ok and inside and same_obs and bool(obs.any())
         all_e.append(e[obs])
         per_scene.append({"scene": k, "gaussians": sc.N, "views": len(sc.cams), "sampled": int(sel.sum()),
                           "observed": int(obs.sum()), "flagged": int(fl.sum()),
@@ -357,16 +351,30 @@ def cpu_baseline_leg(args, gsc, scenes, table, row0, targets, graph, coeffs, sta
                           "max_rel_err_flagged": float(e[fl].max()) if fl.any() else 0.0,
                           "within_bounds": inside, "unobserved_agree": same_obs})
         progress(f"check: scene {k} compared, within bounds: {inside}")
-    t_check = time.perf_counter() - t_check
     observed = sum(p["observed"] for p in per_scene)
     accuracy = {"gate": "e_g <= 1e-4 + near-threshold bound on every sampled observed Gaussian",
                 "passed": ok, "observed_compared": observed,
                 "flagged_fraction": sum(p["flagged"] for p in per_scene) / max(1, observed),
                 "max_rel_err": max(p["max_rel_err"] for p in per_scene),
-                "scenes": per_scene}
+                "scenes": per_scene, "check_seconds": time.perf_counter() - t_check}
     ea = np.concatenate(all_e) if all_e else np.zeros(1)
     accuracy["rel_err_all_compared"] = {"p50": float(np.median(ea)), "p99": float(np.percentile(ea, 99)),
                                         "max": float(ea.max())}
+    return accuracy
+
+
+def cpu_baseline_leg(args, gsc, scenes, table, row0, targets, graph, coeffs, status):
+    """The oracle leg of the batched workload (the only place bench.py runs
+    the oracle).  Two parts:
+      check  -- segment_check() on the timed graph;
+      timing -- the oracle's full colorize on a bounded sample of the same
+                scenes (their first views), on all host threads and on one.
+    Returns (accuracy, cpu_baseline)."""
+    import oracle
+    from paper_2604_17155_amd import synthetic as syn
+    threads = host_threads()
+    subset = segment_subset(scenes)
+    accuracy = segment_check(scenes, table, row0, targets, graph.replay, coeffs, status, threads)
     # timing: full oracle colorize of each subset scene's first views (about
     # 3 M pixels per scene), on every host thread, and the smallest of these
     # samples on one thread
@@ -402,15 +410,18 @@ def cpu_baseline_leg(args, gsc, scenes, table, row0, targets, graph, coeffs, sta
                 "single_thread": {"value": r1["count"] / dt1, "unit": "contributions/s",
                                   "sample": f"scene {k1}, first {len(sub1.cams)} views, "
                                             f"{r1['count']} contributions in {dt1:.3g} s"},
-                "check_seconds": t_check}
+                "check_seconds": accuracy["check_seconds"]}
     return accuracy, baseline
 
 
-def workload_batched(args, gsc):
+def build_segment_workload(gsc, n_scenes):
+    """The multi-scene segmentation workload: scenes, the plan's scene table
+    (Gaussian offset, count, camera offset, count), each scene's first target
+    row, all cameras, the concatenated geometry on the device and the BF16
+    targets (each scene's GPU render of its ground truth)."""
     import numpy as np
     import torch
     from paper_2604_17155_amd import synthetic as syn
-    n_scenes = args.scenes
     scenes = [syn.make_segment_scene(k) for k in range(n_scenes)]
     table, cams, row0 = [], [], []
     g0 = c0 = r0 = 0
@@ -428,6 +439,17 @@ def workload_batched(args, gsc):
     progress(f"targets of {n_scenes} scenes rendered ({r0} pixels)")
     cat = lambda f: torch.from_numpy(np.ascontiguousarray(np.concatenate([getattr(sc, f) for sc in scenes]))).cuda()
     geo = [cat(f) for f in ("means", "scales", "quats", "opacities")]
+    return scenes, table, row0, cams, geo, targets
+
+
+def workload_batched(args, gsc):
+    import torch
+    n_scenes = args.scenes
+    scenes, table, row0, cams, geo, targets = build_segment_workload(gsc, n_scenes)
+    C = scenes[0].C
+    g0 = sum(sc.N for sc in scenes)
+    c0 = len(cams)
+    r0 = sum(sc.n_pixels for sc in scenes)
     blend_bit = 1 << 5  # GSC_STAGE_BLEND: events around each batch's accumulate
     ctx = gsc.Context(bin_size=args.bin, flags=gsc.GSC_FLAG_PROFILE, profile_stages=blend_bit)
     plan = gsc.Plan(ctx, table, *geo, cams, C, 0)
