@@ -133,6 +133,8 @@ def load():
     lib.oc_project.argtypes = [P, P, P, P, i64, P, P, P]
     lib.oc_contributions.argtypes = [P, P, P, P, i64, P, i32, P, P, P, i64]
     lib.oc_contributions.restype = ct.c_int64
+    lib.oc_contributions_rows.argtypes = [P, P, P, P, i64, P, i32, P, P, i64, P, P, i64, i32]
+    lib.oc_contributions_rows.restype = ct.c_int64
     lib.oc_wanted_rows.argtypes = [P, P, P, P, i64, P, i32, P, P, P, i64]
     lib.oc_wanted_rows.restype = ct.c_int64
     lib.oc_render_rows.argtypes = [P, P, P, P, i64, P, i32, P, i32, i32, P, P, i64, P, i32]
@@ -365,6 +367,27 @@ def contributions(scene, opts: Optional[Options] = None, cap: int = 5_000_000):
     if n > cap:
         raise ValueError("contribution buffer too small")
     return idx[:n].copy(), w[:n].copy()
+
+
+def contributions_rows(scene, rows: np.ndarray, opts: Optional[Options] = None, threads=None):
+    """Accepted contributions at the given target rows only (each pixel's full
+    front-to-back walk): (view, row, g) int64 [n,3] and w [n], in view order."""
+    lib = load()
+    opts = opts or Options()
+    m, s, q, o = _geom(scene)
+    cams = cameras(scene.cams)
+    r = np.ascontiguousarray(np.unique(np.asarray(rows, np.int64)))
+    cap = max(1024, 64 * r.size)
+    while True:
+        idx = np.zeros((cap, 3), np.int64)
+        w = np.zeros(cap, np.float64)
+        oo = opts.c()
+        n = lib.oc_contributions_rows(_f(m), _f(s), _f(q), _f(o), scene.N, ct.cast(cams, ct.c_void_p),
+                                      len(scene.cams), ct.byref(oo), _f(r), r.size, _f(idx), _f(w), cap,
+                                      _threads(threads))
+        if n <= cap:
+            return idx[:n].copy(), w[:n].copy()
+        cap = int(n)
 
 
 def wanted_rows(scene, want: np.ndarray, opts: Optional[Options] = None) -> np.ndarray:

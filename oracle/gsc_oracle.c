@@ -42,6 +42,7 @@
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
+#include <stdio.h>
 #include <string.h>
 #ifdef _OPENMP
 #include <omp.h>
@@ -78,6 +79,23 @@ typedef struct {
 } oc_options;
 
 #define OC_MAX_NB 16
+
+/* Progress for long runs: with GSC_ORACLE_PROGRESS set in the environment,
+ * the view loops print a line to stderr as every tenth of their views starts
+ * (test infrastructure; the arithmetic is unaffected). */
+static int oc_progress_on(void) { return getenv("GSC_ORACLE_PROGRESS") != NULL; }
+
+static void oc_progress(const char* what, int* started, int n_views, int on) {
+    if (!on) return;
+    int d;
+#pragma omp atomic capture
+    d = ++(*started);
+    const int step = n_views >= 10 ? n_views / 10 : 1;
+    if (d % step == 0 || d == n_views) {
+        fprintf(stderr, "[oracle] %s: view %d of %d\n", what, d, n_views);
+        fflush(stderr);
+    }
+}
 
 /* ------------------------------------------------------------------ */
 /* Real spherical harmonics (eq. 3), from the definition:              */
@@ -745,12 +763,15 @@ int oc_colorize(const float* means, const float* scales, const float* quats, con
         omp_set_num_threads(n_threads);
 #endif
     }
+    int prog_started = 0;
+    const int prog_on = oc_progress_on();
 #pragma omp parallel reduction(+ : tot_events)
     {
         proj_t* P = (proj_t*)malloc(sizeof(proj_t) * (size_t)(N > 0 ? N : 1));
         elist_t lst = {0, 0, 0};
 #pragma omp for schedule(dynamic, 1)
         for (int j = 0; j < n_cams; ++j) {
+            oc_progress("colorize", &prog_started, n_cams, prog_on);
             const oc_camera* cam = &cams[j];
             uint8_t* mask = want ? wanted_mask(&sc, cam, o, want, P) : NULL;
             lst.n = 0;
@@ -934,6 +955,8 @@ int oc_render(const float* means, const float* scales, const float* quats, const
         omp_set_num_threads(n_threads);
 #endif
     }
+    int prog_started = 0;
+    const int prog_on = oc_progress_on();
 #pragma omp parallel reduction(+ : tot)
     {
         proj_t* P = (proj_t*)malloc(sizeof(proj_t) * (size_t)(N > 0 ? N : 1));
@@ -941,6 +964,7 @@ int oc_render(const float* means, const float* scales, const float* quats, const
         elist_t lst = {0, 0, 0};
 #pragma omp for schedule(dynamic, 1)
         for (int j = 0; j < n_cams; ++j) {
+            oc_progress("render", &prog_started, n_cams, prog_on);
             const oc_camera* cam = &cams[j];
             double phi[OC_MAX_NB];
             for (int64_t g = 0; g < N; ++g) {
@@ -1044,6 +1068,8 @@ int oc_colorize_backward(const float* means, const float* scales, const float* q
     if (rc) { free(A); free(w); free(tmpc); return rc; }
     double* Bbar = (double*)calloc((size_t)(N > 0 ? N : 1) * nb * C, sizeof(double));
     double* rho = (double*)calloc((size_t)(N > 0 ? N : 1), sizeof(double));
+    int prog_started = 0;
+    const int prog_on = oc_progress_on();
 #pragma omp parallel for schedule(static)
     for (int64_t g = 0; g < N; ++g) {
         if (w[g] == 0.0) continue;
@@ -1071,6 +1097,7 @@ int oc_colorize_backward(const float* means, const float* scales, const float* q
         double* acc = NULL;
 #pragma omp for schedule(dynamic, 1)
         for (int j = 0; j < n_cams; ++j) {
+            oc_progress("colorize adjoint", &prog_started, n_cams, prog_on);
             const oc_camera* cam = &cams[j];
             double phi[OC_MAX_NB];
             for (int64_t g = 0; g < N; ++g) {
@@ -1150,6 +1177,8 @@ int oc_render_backward(const float* means, const float* scales, const float* qua
     double* go_view = (double*)calloc((size_t)(N > 0 ? N : 1) * (size_t)(n_cams > 0 ? n_cams : 1), sizeof(double));
     /* per-view dL/dc contributions: V-style [view][g][C] sums of w*Ibar, folded with phi after */
     double* gs_view = (double*)calloc((size_t)(N > 0 ? N : 1) * (size_t)(n_cams > 0 ? n_cams : 1) * C, sizeof(double));
+    int prog_started = 0;
+    const int prog_on = oc_progress_on();
 #pragma omp parallel
     {
         proj_t* P = (proj_t*)malloc(sizeof(proj_t) * (size_t)(N > 0 ? N : 1));
@@ -1160,6 +1189,7 @@ int oc_render_backward(const float* means, const float* scales, const float* qua
         double* acc = NULL;
 #pragma omp for schedule(dynamic, 1)
         for (int j = 0; j < n_cams; ++j) {
+            oc_progress("render adjoint", &prog_started, n_cams, prog_on);
             const oc_camera* cam = &cams[j];
             double phi[OC_MAX_NB];
             for (int64_t g = 0; g < N; ++g) {
@@ -1292,6 +1322,70 @@ int64_t oc_contributions(const float* means, const float* scales, const float* q
  * the wanted Gaussians, view by view in ascending order: the only target
  * values a colorize restricted to those Gaussians reads.  Returns the number
  * of rows (rows_out receives at most cap of them). */
+/* Every accepted contribution at the given pixels only: rows (sorted
+ * ascending global target rows) select pixels of every camera; the blend runs
+ * over those pixels (a pixel's full front-to-back walk) and writes rows of
+ * (view, pixel row, g, w) in view order.  Returns the number of contributions
+ * (<= cap written), or -1. */
+int64_t oc_contributions_rows(const float* means, const float* scales, const float* quats,
+                              const float* opac, int64_t N, const oc_camera* cams, int n_cams,
+                              const oc_options* o, const int64_t* rows, int64_t n_rows,
+                              int64_t* out_idx /* [cap][3] */, double* out_w, int64_t cap,
+                              int n_threads) {
+    scene_t sc;
+    build_scene(&sc, means, scales, quats, opac, N);
+    elist_t* lists = (elist_t*)calloc((size_t)(n_cams > 0 ? n_cams : 1), sizeof(elist_t));
+    if (n_threads > 0) {
+#ifdef _OPENMP
+        omp_set_num_threads(n_threads);
+#endif
+    }
+#pragma omp parallel
+    {
+        proj_t* P = (proj_t*)malloc(sizeof(proj_t) * (size_t)(N > 0 ? N : 1));
+#pragma omp for schedule(dynamic, 1)
+        for (int j = 0; j < n_cams; ++j) {
+            const oc_camera* cam = &cams[j];
+            const int64_t lo = cam->pixel_offset, hi = lo + (int64_t)cam->width * cam->height;
+            /* first requested row of this camera (rows are sorted) */
+            int64_t a = 0, b = n_rows;
+            while (a < b) {
+                int64_t m = (a + b) / 2;
+                if (rows[m] < lo) a = m + 1; else b = m;
+            }
+            if (a >= n_rows || rows[a] >= hi) continue;
+            uint8_t* mask = (uint8_t*)calloc((size_t)cam->width * (size_t)cam->height, 1);
+            for (int64_t k = a; k < n_rows && rows[k] < hi; ++k) mask[rows[k] - lo] = 1;
+            vstats_t st = {0, 0};
+            blend_view(&sc, cam, o, mask, P, &lists[j], NULL, &st);
+            free(mask);
+        }
+        free(P);
+    }
+    int64_t n = 0;
+    for (int j = 0; j < n_cams; ++j) {
+        const elist_t* L = &lists[j];
+        int64_t row_start = 0;
+        for (int64_t i = 0; i < L->n; ++i) {
+            if (L->e[i].g >= 0) continue;
+            int y = L->e[i].x;
+            for (int64_t r = row_start; r < i; ++r) {
+                if (n < cap) {
+                    out_idx[3 * n] = j;
+                    out_idx[3 * n + 1] = cams[j].pixel_offset + (int64_t)y * cams[j].width + L->e[r].x;
+                    out_idx[3 * n + 2] = L->e[r].g;
+                    out_w[n] = L->e[r].w;
+                }
+                ++n;
+            }
+            row_start = i + 1;
+        }
+        free(L->e);
+    }
+    free(lists); free(sc.cov3); free(sc.rot);
+    return n;
+}
+
 int64_t oc_wanted_rows(const float* means, const float* scales, const float* quats,
                        const float* opac, int64_t N, const oc_camera* cams, int n_cams,
                        const oc_options* o, const uint8_t* want, int64_t* rows_out, int64_t cap) {
@@ -1342,6 +1436,8 @@ int oc_render_rows(const float* means, const float* scales, const float* quats, 
         omp_set_num_threads(n_threads);
 #endif
     }
+    int prog_started = 0;
+    const int prog_on = oc_progress_on();
 #pragma omp parallel
     {
         proj_t* P = (proj_t*)malloc(sizeof(proj_t) * (size_t)(N > 0 ? N : 1));
@@ -1349,6 +1445,7 @@ int oc_render_rows(const float* means, const float* scales, const float* quats, 
         elist_t lst = {0, 0, 0};
 #pragma omp for schedule(dynamic, 1)
         for (int j = 0; j < n_cams; ++j) {
+            oc_progress("render rows", &prog_started, n_cams, prog_on);
             const oc_camera* cam = &cams[j];
             int64_t npx = (int64_t)cam->width * cam->height;
             /* the listed rows of this camera: [k0, k1) */
