@@ -512,10 +512,15 @@ gsc_status bin_views(gsc_ctx* ctx, const ViewInfo* all, int v0, int nv,
     GSC_HIP(ctx->sort_scratch.ensure(4 * std::max(pscr, scr) + 256));
     {
         StageTimer t(ctx, s, GSC_STAGE_TILE_SORT);
+        bool in_alt = false;
         radix_sort(ctx->pkeys.as<uint32_t>(), ctx->pvals.as<uint32_t>(), ctx->pkeys_alt.as<uint32_t>(),
                    ctx->pvals_alt.as<uint32_t>(), (uint32_t)pairs, bits_for(tiles + 1),
-                   ctx->sort_scratch.as<uint32_t>(), s);
+                   ctx->sort_scratch.as<uint32_t>(), s, nullptr, &in_alt);
         GSC_LAUNCHED("tile sort");
+        if (in_alt) {  // the sorted pairs are in the alternate buffers: swap roles, no copy
+            std::swap(ctx->pkeys, ctx->pkeys_alt);
+            std::swap(ctx->pvals, ctx->pvals_alt);
+        }
         launch_fill_u32(ctx->ranges.as<uint32_t>(), 0u, (uint64_t)2 * tiles, s);
         launch_tile_ranges(ctx->pkeys.as<uint32_t>(), (uint32_t)pairs, (uint32_t)tiles,
                            ctx->ranges.as<uint2>(), s);
@@ -819,9 +824,14 @@ gsc_status plan_bin_batch(gsc_plan* P, const gsc_plan::Batch& b, hipStream_t s) 
     }
     {
         StageTimer t(ctx, s, GSC_STAGE_TILE_SORT);
+        bool in_alt = false;
         radix_sort(P->pkeys.as<uint32_t>(), P->pvals.as<uint32_t>(), P->pkeys_alt.as<uint32_t>(),
                    P->pvals_alt.as<uint32_t>(), b.pair_cap, b.tile_bits,
-                   P->sort_scratch.as<uint32_t>(), s, d_live);
+                   P->sort_scratch.as<uint32_t>(), s, d_live, &in_alt);
+        if (in_alt) {  // swap roles instead of copying; every run swaps alike
+            std::swap(P->pkeys, P->pkeys_alt);
+            std::swap(P->pvals, P->pvals_alt);
+        }
         launch_fill_u32(P->ranges.as<uint32_t>(), 0u, (uint64_t)2 * b.n_tiles, s);
         launch_tile_ranges(P->pkeys.as<uint32_t>(), b.pair_cap, b.n_tiles, P->ranges.as<uint2>(), s,
                            d_live);

@@ -131,9 +131,13 @@ size_t radix_scratch_words(uint32_t n);
 // work + n_bins.  work holds tile_order_words(n_bins) words.
 size_t tile_order_words(uint32_t n_bins);
 const uint32_t* launch_tile_order(const uint2* ranges, uint32_t n_bins, uint32_t* work, hipStream_t s);
+// Stable LSD radix sort of (key, value) by the low `bits` key bits, 8 per
+// pass.  The result lands in keys/vals, except with result_in_alt: then an odd
+// pass count leaves it in keys_alt/vals_alt (*result_in_alt = true) instead of
+// copying it back.
 void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                 uint32_t n, int bits, uint32_t* scratch, hipStream_t s,
-                const uint32_t* n_dev = nullptr);
+                const uint32_t* n_dev = nullptr, bool* result_in_alt = nullptr);
 
 // Accumulate variants ("chunks"): the channels per launch (launches =
 // ceil(C / channels)), plus kChunkMfma for the matrix-core forms: BF16

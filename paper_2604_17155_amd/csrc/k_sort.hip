@@ -281,7 +281,8 @@ __global__ void k_copy_pairs(const uint32_t* __restrict__ ka, const uint32_t* __
 }
 
 void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, uint32_t n,
-                int bits, uint32_t* scratch, hipStream_t s, const uint32_t* n_dev) {
+                int bits, uint32_t* scratch, hipStream_t s, const uint32_t* n_dev, bool* result_in_alt) {
+    if (result_in_alt) *result_in_alt = false;
     if (n <= 1 || bits <= 0) return;
     uint32_t nb = (n + kRsTile - 1) / kRsTile;
     uint32_t* hist = scratch;
@@ -298,7 +299,9 @@ void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* va
         t = sk; sk = dk; dk = t;
         t = sv; sv = dv; dv = t;
     }
-    if (sk != keys) {
+    if (sk != keys && result_in_alt) {
+        *result_in_alt = true;  // the caller takes the result from the alternate buffers
+    } else if (sk != keys) {
         // odd pass count: copy back with a kernel (plain kernel nodes under graph capture)
         const uint32_t blocks = std::min<uint32_t>((n + 255) / 256, 8192u);
         hipLaunchKernelGGL(k_copy_pairs, dim3(blocks), dim3(256), 0, s, sk, sv, keys, vals, n, n_dev);
