@@ -93,7 +93,12 @@ def gpu_targets(gsc, sc, which=0, bf16=False):
 # runs (profiles/accumulate_*.md), valid only for the kernel sources they were
 # taken on: the digest of those sources is kept beside each figure.
 MEASURED_TRAFFIC = {
-    "relight": {"bytes": 2.599e9, "sources": "32621809bd307686"},
+    # HBM bytes per accumulate launch: FETCH_SIZE x 2 + WRITE_SIZE x 1 (the
+    # factors a plain 256 MiB device copy gives), averaged over the launches
+    # of one step; valid while the accumulate's sources hash to "sources"
+    "relight": {"bytes": 2.620e9, "sources": "991d67580df756f3"},
+    "features": {"bytes": 2.464e10, "sources": "991d67580df756f3"},
+    "batched": {"bytes": 4.651e10, "sources": "991d67580df756f3"},
 }
 ACCUMULATE_SOURCES = ("paper_2604_17155_amd/csrc/k_accum.hip", "paper_2604_17155_amd/csrc/wave_ops.h",
                       "paper_2604_17155_amd/csrc/k_sort.hip",    # the tile order
@@ -240,7 +245,8 @@ def workload_features(args, gsc):
     targets = gpu_targets(gsc, sc, bf16=True)
     label = (f"feature distillation: {sc.N} isotropic Gaussians, {len(sc.cams)} hemisphere cameras "
              f"{sc.cams[0].width}x{sc.cams[0].height}, SH degree 0, C={sc.C}, BF16 targets")
-    out = run_single(args, gsc, sc, targets, label, "bf16")
+    default_size = not (args.n or args.views or args.res or args.bin or args.variant or args.schedule)
+    out = run_single(args, gsc, sc, targets, label, "bf16", "features" if default_size else None)
     if not args.no_cpu_baseline:
         sub = syn.make_features(n=sc.N, n_cams=len(sc.cams))
         sub.cams = sub.cams[:4]
@@ -487,6 +493,10 @@ def workload_batched(args, gsc):
     assert int(info2.dropped_pairs) == 0 and int(info2.contributions) == contrib
     launches = variant_launches(C, variant) * int(info.batches)
     target_bytes = float(r0) * C * 2
+    # the counters were read on the 32-scene plan, 32-pixel bins, 8 view
+    # batches, the persistent 16-channel matrix-core accumulate
+    measured_shape = (n_scenes == 32 and int(info.bin_size) == 32 and int(info.batches) == 8
+                      and variant_name(variant) == "mfma16/persistent")
     config = {"workload": f"multi-scene segmentation: {n_scenes} scenes, {g0} Gaussians in total "
                           f"(5k-400k per scene), {c0} cameras 640x480..1280x720, SH degree 0, "
                           f"C={C}, BF16 targets, one plan replayed as a graph",
@@ -502,7 +512,8 @@ def workload_batched(args, gsc):
               "accumulate_ms_source": "HIP event nodes around each batch's accumulate in the "
                                       "captured graph, read after the last timed replay"}
     out = line(args, contrib * args.steps / elapsed, 1e3 * elapsed / args.steps, "bf16", config,
-               roofline_hbm(accumulate_kernel_name(variant, C), target_bytes, acc_ms, launches))
+               roofline_hbm(accumulate_kernel_name(variant, C), target_bytes, acc_ms, launches,
+                            measured_traffic("batched") if measured_shape else None))
     out["roofline_valu"] = roofline(C, contrib, acc_ms, launches)
     if not args.no_cpu_baseline:
         acc, base = cpu_baseline_leg(args, gsc, scenes, table, row0, targets, graph, coeffs, status)
