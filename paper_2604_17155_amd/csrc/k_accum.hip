@@ -385,11 +385,12 @@ static void launch_acc_cc(const ViewInfo* views, int n_views, uint32_t n_bins, c
 // W (Gaussians x pixels) . Y (pixels x channels).  Here the blend runs as in
 // accumulate_tile, but each entry's weights go to LDS as a row of W, split
 // into a BF16 high part (w's upper half) and a BF16 remainder (the exact
-// w - hi rounded; w = hi + lo to 2^-16 relative).  Every 16 entries, v_mfma_f32_16x16x32_bf16 forms
-// (W_hi + W_lo) . [Y | 1] over the tile's 256 pixels (eight K-steps of 32
-// pixels): the targets, held as B operands in registers for the whole tile,
-// give S, and a block of ones gives V = sum_p w from the same split weights.
-// (With one channel block, groups of 8 entries fill rows 0..7 only.)
+// w - hi rounded; w = hi + lo to 2^-16 relative).  Every 8 or 16 entries,
+// v_mfma_f32_16x16x32_bf16 forms (W_hi + W_lo) . [Y | 1] over the tile's 256
+// pixels (eight K-steps of 32 pixels): the targets, held as B operands in
+// registers for the whole tile, give S, and a block of ones gives
+// V = sum_p w from the same split weights.  (Groups of 8 entries put W_hi in
+// rows 0..7 of the A operand and W_lo in rows 8..15: one product per K-step.)
 // K index k = 32 s + 8 (lane / 16) + i of K-step s is tile pixel k (row k/16,
 // column k%16); the blend's lane l owns pixels l + 64 j, j = 0..3.
 
@@ -400,8 +401,8 @@ constexpr int kWRow = 264;       // LDS row of W in BF16 elements (256 + padding
 constexpr int kMfmaWaves = 2;    // waves per block
 
 // W rows of one wave: ROWS list entries per matrix product (8 or 16; with 8,
-// rows 8..15 of the A operand are zero and less LDS per wave leaves room for
-// more waves).
+// the A operand holds the high parts in rows 0..7 and the remainders in rows
+// 8..15, and less LDS per wave leaves room for more waves).
 template <int ROWS>
 struct alignas(16) MfmaLds {
     __bf16 whi[ROWS * kWRow];
@@ -476,9 +477,15 @@ __device__ __forceinline__ uint32_t accumulate_tile_mfma(
             }
         }
     }
+    // the ones operand, each register made through an identity DPP move so
+    // that the compiler holds it instead of rebuilding it before every product
     bf16x8_t ones;
+    {
+        uint32_t o4[4];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) ones[i] = (__bf16)1.0f;
+        for (int i = 0; i < 4; ++i) o4[i] = (uint32_t)__builtin_amdgcn_mov_dpp(0x3F803F80, 0xE4, 0xF, 0xF, true);
+        ones = __builtin_bit_cast(bf16x8_t, o4);
+    }
 
     // transmittance of the lane's pixel in each band: four scalars (as an
     // array the compiler rebuilt it in new registers on every band update)
@@ -527,7 +534,13 @@ __device__ __forceinline__ uint32_t accumulate_tile_mfma(
     constexpr bool kBandMask = NBLK > 1;
     uint32_t rowmask = 0;
 
-    // one matrix product over the group's `rows` entries, then the atomics
+    // one matrix product over the group's `rows` entries, then the atomics.
+    // With 8 rows per group the A operand's rows 0..7 take the weights' high
+    // parts and rows 8..15 their remainders, so one product per K-step forms
+    // both halves; each output row then adds its two halves (lanes l and
+    // l + 32).  With 16 rows the high parts and the remainders take a
+    // product each.
+    constexpr bool kSplitRows = ROWS == 8;
     auto flush = [&](uint32_t rows) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -535,14 +548,14 @@ __device__ __forceinline__ uint32_t accumulate_tile_mfma(
 #pragma unroll
         for (int b = 0; b < NBLK; ++b) D[b] = floatx4_t{0.f, 0.f, 0.f, 0.f};
         DV = floatx4_t{0.f, 0.f, 0.f, 0.f};
-        const uint32_t arow = n16 < (uint32_t)ROWS ? n16 : 0u;
-        const __bf16* ah_p = &L.whi[arow * kWRow + 8 * q4];
+        const uint32_t arow = kSplitRows ? (n16 & 7u) : n16;
+        const __bf16* ah_p = &((kSplitRows && n16 >= 8u) ? L.wlo : L.whi)[arow * kWRow + 8 * q4];
         const __bf16* al_p = &L.wlo[arow * kWRow + 8 * q4];
         // the band mask of this lane's A row, and the bands any row wrote
-        uint32_t mrow = (ROWS < 16 && n16 >= (uint32_t)ROWS) ? 0u : 0xFu;
+        uint32_t mrow = 0xFu;
         uint32_t anyb = 0xFu;
         if constexpr (kBandMask) {
-            mrow &= (uint32_t)__shfl((int)rowmask, (int)arow, 64);
+            mrow = (uint32_t)__shfl((int)rowmask, (int)arow, 64);
             anyb = 0;
 #pragma unroll
             for (int k = 0; k < 4; ++k)
@@ -554,20 +567,27 @@ __device__ __forceinline__ uint32_t accumulate_tile_mfma(
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
             if (!((anyb >> (s >> 1)) & 1u)) continue;  // uniform: no row wrote this band
+            const bool masked = kBandMask && !((mrow >> (s >> 1)) & 1u);
             bf16x8_t ah = *reinterpret_cast<const bf16x8_t*>(ah_p + 32 * s);
-            bf16x8_t al = *reinterpret_cast<const bf16x8_t*>(al_p + 32 * s);
-            if (!((mrow >> (s >> 1)) & 1u)) {
-                ah = zero8;
-                al = zero8;
-            }
-            if (YM == 0 && first_chunk) {
-                DV = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, ones, DV, 0, 0, 0);
-                DV = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, ones, DV, 0, 0, 0);
-            }
+            if (masked) ah = zero8;
+            if (YM == 0 && first_chunk) DV = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, ones, DV, 0, 0, 0);
 #pragma unroll
-            for (int b = 0; b < NBLK; ++b) {
-                D[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, Y[s][b], D[b], 0, 0, 0);
-                D[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, Y[s][b], D[b], 0, 0, 0);
+            for (int b = 0; b < NBLK; ++b) D[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, Y[s][b], D[b], 0, 0, 0);
+            if constexpr (!kSplitRows) {
+                bf16x8_t al = *reinterpret_cast<const bf16x8_t*>(al_p + 32 * s);
+                if (masked) al = zero8;
+                if (YM == 0 && first_chunk) DV = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, ones, DV, 0, 0, 0);
+#pragma unroll
+                for (int b = 0; b < NBLK; ++b)
+                    D[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, Y[s][b], D[b], 0, 0, 0);
+            }
+        }
+        if constexpr (kSplitRows) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (YM == 0 && first_chunk) DV[i] += __shfl_xor(DV[i], 32, 64);
+#pragma unroll
+                for (int b = 0; b < NBLK; ++b) D[b][i] += __shfl_xor(D[b][i], 32, 64);
             }
         }
         // lane holds rows 4 q4 + i, column n16
@@ -596,92 +616,74 @@ __device__ __forceinline__ uint32_t accumulate_tile_mfma(
         __builtin_amdgcn_wave_barrier();
     };
 
-    // list walk: chunks of 64 entries gathered one per lane; the entries whose
-    // footprint can reach a live band of this tile are taken in order
-    auto load_pv = [&](uint32_t b) -> uint32_t { return b + lane < rg.y ? pair_vals[b + lane] : 0u; };
-    uint32_t b = rg.x;
-    uint32_t pv = load_pv(b);
-    float2 R0 = make_float2(0.f, 0.f);
-    float4 R1 = make_float4(0.f, 0.f, 0.f, 0.f);
-    uint2 R2 = make_uint2(0u, 0u);
-    auto gather = [&](uint32_t p, uint32_t base) {
-        const uint32_t it = p & kItemMask;
-        const bool own = base + lane < rg.y && pair_reaches<BIN>(p, tg.quad, alive);
-        const float4 r = own ? rec0[it] : make_float4(0.f, 0.f, 0.f, 0.f);
-        R0 = make_float2((ox - r.x) - r.z, (oy - r.y) - r.w);
-        R1 = own ? rec1[it] : make_float4(0.f, 0.f, 0.f, 0.f);
-        R2 = own ? rec2[it] : make_uint2(0u, 0u);
-    };
-    uint64_t sm = 0;  // entries of the chunk still to take
-    auto survivors = [&]() -> uint64_t {
-        const bool own = b + lane < rg.y && pair_reaches<BIN>(pv, tg.quad, alive);
-        const uint32_t bl = entry_bands<BIN>(pv, tg.quad, R2.x, tg.y0) & alive;
-        return __builtin_amdgcn_ballot_w64(own && bl != 0u);
-    };
-    if (b < rg.y) {
-        gather(pv, b);
-        sm = survivors();
-    }
+    // list walk: chunks of 64 entries gathered one per lane; each lane also
+    // forms its entry's band mask (the live bands its footprint rows reach),
+    // so taking an entry costs one broadcast of that mask; the entries that
+    // reach a live band are taken in order
     uint32_t rows = 0;
-    while (alive != 0u) {
-        if (sm == 0) {
-            b += 64;
-            if (b >= rg.y) break;
-            pv = load_pv(b);
-            gather(pv, b);
-            sm = survivors();
-            continue;
-        }
-        const uint32_t j = (uint32_t)__builtin_ctzll(sm);
-        sm &= sm - 1;
-        const uint32_t pc = bcast_u(pv, j);
-        const uint2 e2 = make_uint2(bcast_u(R2.x, j), bcast_u(R2.y, j));
-        const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2.x, tg.y0) & alive;
-        if (bands == 0u) continue;
-        const float2 c0 = make_float2(bcast(R0.x, j), bcast(R0.y, j));
-        const float4 c1 = make_float4(bcast(R1.x, j), bcast(R1.y, j), bcast(R1.z, j), bcast(R1.w, j));
-        const float dx = c0.x + lx;
-        const float a0 = c1.x * dx * dx;
-        const float b0 = c1.y * dx;
-        uint32_t nh = 0;
-        __bf16* wrow_h = &L.whi[rows * kWRow];
-        __bf16* wrow_l = &L.wlo[rows * kWRow];
-        if constexpr (kBandMask) rowmask = lane == rows ? bands : rowmask;
-        auto band = [&](const int k, float& Tk) {
-            if (!((bands >> k) & 1u)) {  // uniform: no weight in this band
-                if constexpr (!kBandMask) {
-                    wrow_h[lane + 64 * k] = (__bf16)0.0f;
-                    wrow_l[lane + 64 * k] = (__bf16)0.0f;
+    for (uint32_t b = rg.x; b < rg.y && alive != 0u; b += 64) {
+        const bool in_list = b + lane < rg.y;
+        const uint32_t pv = in_list ? pair_vals[b + lane] : 0u;
+        const uint32_t it = pv & kItemMask;
+        const bool own = in_list && pair_reaches<BIN>(pv, tg.quad, alive);
+        const float4 r = own ? rec0[it] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float2 R0 = make_float2((ox - r.x) - r.z, (oy - r.y) - r.w);
+        const float4 R1 = own ? rec1[it] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const uint2 r2 = own ? rec2[it] : make_uint2(0u, 0u);
+        const uint32_t gid = r2.y;  // the entry's item (geometry slot) index
+        const uint32_t BL = own ? (entry_bands<BIN>(pv, tg.quad, r2.x, tg.y0) & alive) : 0u;
+        uint64_t sm = __builtin_amdgcn_ballot_w64(BL != 0u);  // entries still to take
+        while (sm != 0u) {
+            const uint32_t j = (uint32_t)__builtin_ctzll(sm);
+            sm &= sm - 1;
+            const uint32_t bands = bcast_u(BL, j) & alive;
+            if (bands == 0u) continue;
+            const float2 c0 = make_float2(bcast(R0.x, j), bcast(R0.y, j));
+            const float4 c1 = make_float4(bcast(R1.x, j), bcast(R1.y, j), bcast(R1.z, j), bcast(R1.w, j));
+            const float dx = c0.x + lx;
+            const float a0 = c1.x * dx * dx;
+            const float b0 = c1.y * dx;
+            uint32_t nh = 0;
+            __bf16* wrow_h = &L.whi[rows * kWRow];
+            __bf16* wrow_l = &L.wlo[rows * kWRow];
+            if constexpr (kBandMask) rowmask = lane == rows ? bands : rowmask;
+            auto band = [&](const int k, float& Tk) {
+                if (!((bands >> k) & 1u)) {  // uniform: no weight in this band
+                    if constexpr (!kBandMask) {
+                        wrow_h[lane + 64 * k] = (__bf16)0.0f;
+                        wrow_l[lane + 64 * k] = (__bf16)0.0f;
+                    }
+                    return;
                 }
-                return;
+                const float dy = c0.y + lyk[k];
+                const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
+                uint64_t taken, kept;
+                const float w = pixel_step(q2, c1.w, Tk, qlim, amin, amax, tmin, taken, kept);
+                // hi: w's upper half (truncated), lo: the exact remainder rounded
+                // to BF16; |w - hi - lo| <= 2^-16 |w|
+                const uint32_t wb = __float_as_uint(w);
+                const __bf16 hi = __builtin_bit_cast(__bf16, (uint16_t)(wb >> 16));
+                const __bf16 lo = (__bf16)(w - __uint_as_float(wb & 0xffff0000u));
+                wrow_h[lane + 64 * k] = hi;
+                wrow_l[lane + 64 * k] = lo;
+                nh += (uint32_t)__popcll(taken);
+                if (kept == 0) alive &= ~(1u << k);
+            };
+            band(0, T0);
+            band(1, T1);
+            band(2, T2);
+            band(3, T3);
+            alive = (uint32_t)__builtin_amdgcn_readfirstlane((int)alive);
+            nh = (uint32_t)__builtin_amdgcn_readfirstlane((int)nh);
+            cnt += nh;
+            const uint32_t gl = (uint32_t)((int64_t)bcast_u(gid, j) - item_base);
+            if (lane == 0) L.gslot[rows] = nh != 0u ? gl : 0xFFFFFFFFu;
+            if (nh != 0u && gcount != nullptr && first_chunk && lane == 0) atomicAdd(gcount + g_off + gl, nh);
+            if (++rows == (uint32_t)ROWS) {
+                flush(rows);
+                rows = 0;
             }
-            const float dy = c0.y + lyk[k];
-            const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
-            uint64_t taken, kept;
-            const float w = pixel_step(q2, c1.w, Tk, qlim, amin, amax, tmin, taken, kept);
-            // hi: w's upper half (truncated), lo: the exact remainder rounded
-            // to BF16; |w - hi - lo| <= 2^-16 |w|
-            const uint32_t wb = __float_as_uint(w);
-            const __bf16 hi = __builtin_bit_cast(__bf16, (uint16_t)(wb >> 16));
-            const __bf16 lo = (__bf16)(w - __uint_as_float(wb & 0xffff0000u));
-            wrow_h[lane + 64 * k] = hi;
-            wrow_l[lane + 64 * k] = lo;
-            nh += (uint32_t)__popcll(taken);
-            if (kept == 0) alive &= ~(1u << k);
-        };
-        band(0, T0);
-        band(1, T1);
-        band(2, T2);
-        band(3, T3);
-        alive = (uint32_t)__builtin_amdgcn_readfirstlane((int)alive);
-        nh = (uint32_t)__builtin_amdgcn_readfirstlane((int)nh);
-        cnt += nh;
-        const uint32_t gl = (uint32_t)((int64_t)e2.y - item_base);
-        if (lane == 0) L.gslot[rows] = nh != 0u ? gl : 0xFFFFFFFFu;
-        if (nh != 0u && gcount != nullptr && first_chunk && lane == 0) atomicAdd(gcount + g_off + gl, nh);
-        if (++rows == (uint32_t)ROWS) {
-            flush(rows);
-            rows = 0;
+            if (alive == 0u) break;
         }
     }
     if (rows != 0u) flush(rows);
