@@ -156,9 +156,13 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint32_t* __restri
                                                         int shift, uint32_t* __restrict__ hist,
                                                         uint32_t nblocks) {
     if (n_dev) n = min(n, *n_dev);
-    __shared__ uint32_t h[kRsWaves][256];
-    int w = threadIdx.x >> 6;
-    for (int k = threadIdx.x; k < kRsWaves * 256; k += kRsThreads) (&h[0][0])[k] = 0;
+    // four counter sets per wave (lane % 4): keys that share a digit, as in
+    // the last pass of a sort whose top digit takes few values, spread their
+    // LDS atomics over four addresses
+    constexpr int kSets = 4;
+    __shared__ uint32_t h[kRsWaves * kSets][256];
+    const int w = (int)(threadIdx.x >> 6) * kSets + (int)(threadIdx.x & (kSets - 1));
+    for (int k = threadIdx.x; k < kRsWaves * kSets * 256; k += kRsThreads) (&h[0][0])[k] = 0;
     __syncthreads();
     uint64_t base = (uint64_t)blockIdx.x * kRsTile;
 #pragma unroll 4
@@ -171,7 +175,7 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint32_t* __restri
     if (d >= 256u) return;
     uint32_t sum = 0;
 #pragma unroll
-    for (int k = 0; k < kRsWaves; ++k) sum += h[k][d];
+    for (int k = 0; k < kRsWaves * kSets; ++k) sum += h[k][d];
     hist[(uint64_t)d * nblocks + blockIdx.x] = sum;
 }
 
