@@ -96,9 +96,9 @@ MEASURED_TRAFFIC = {
     # HBM bytes per accumulate launch: FETCH_SIZE x 2 + WRITE_SIZE x 1 (the
     # factors a plain 256 MiB device copy gives), averaged over the launches
     # of one step; valid while the accumulate's sources hash to "sources"
-    "relight": {"bytes": 2.620e9, "sources": "991d67580df756f3"},
-    "features": {"bytes": 2.464e10, "sources": "991d67580df756f3"},
-    "batched": {"bytes": 4.651e10, "sources": "991d67580df756f3"},
+    "relight": {"bytes": 2.620e9, "sources": "18277db2ccc86ddd"},
+    "features": {"bytes": 2.363e10, "sources": "18277db2ccc86ddd"},
+    "batched": {"bytes": 4.605e10, "sources": "18277db2ccc86ddd"},
 }
 ACCUMULATE_SOURCES = ("paper_2604_17155_amd/csrc/k_accum.hip", "paper_2604_17155_amd/csrc/wave_ops.h",
                       "paper_2604_17155_amd/csrc/k_sort.hip",    # the tile order
