@@ -182,9 +182,10 @@ typedef struct {
                                 batch.  Views are binned and blended in batches
                                 of consecutive views whose items stay within
                                 this bound (a view with more items forms a batch
-                                of its own); 0 = 2^26.  Smaller batches need less
-                                scratch and take more launches.  The result does
-                                not depend on it. */
+                                of its own); 0 = 2^26 for single calls and 2^24
+                                for plans.  Smaller batches need less scratch and
+                                take more launches.  The result does not depend
+                                on it. */
     uint32_t batch_pairs;    /* 0, or at most 2^31 - 1: (bin, item) pairs per view
                                 batch.  A batch of several views whose pairs
                                 exceed it is split in halves until they fit or

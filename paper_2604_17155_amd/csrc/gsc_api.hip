@@ -101,6 +101,15 @@ constexpr uint64_t kMaxPairsPerBatch = 1ull << 31;
 inline uint64_t batch_item_limit(const gsc_options& o) {
     return o.batch_items ? (uint64_t)o.batch_items : kMaxItemsPerBatch;
 }
+// A plan's default batch: 2^24 items, whose depth-sort keys, values and
+// their alternates (16 bytes per item) about fill the 256 MB last-level
+// cache.  Measured on the 32-scene plan (8 to 49 batches): 2^24 items per
+// batch 281 ms per run, 2^26 296 ms; the accumulate itself is 3% slower in
+// the smaller batches, the sorts gain more.
+constexpr uint64_t kPlanItemsPerBatch = 1ull << 24;
+inline uint64_t plan_item_limit(const gsc_options& o) {
+    return o.batch_items ? (uint64_t)o.batch_items : kPlanItemsPerBatch;
+}
 inline uint64_t batch_pair_limit(const gsc_options& o) {
     return o.batch_pairs ? (uint64_t)o.batch_pairs : kMaxPairsPerBatch - 1;
 }
@@ -1664,7 +1673,7 @@ gsc_status gsc_plan_create(gsc_ctx* ctx, const gsc_scene* scenes, int32_t n_scen
         int v0 = 0;
         for (int v = 0; v < (int)P->views.size(); ++v) {
             const uint64_t ni = P->views[v].n_gauss, nt = (uint64_t)P->views[v].tiles_x * P->views[v].tiles_y;
-            if (v > v0 && (items + ni > batch_item_limit(ctx->opt) || tiles + nt >= (1ull << 31))) {
+            if (v > v0 && (items + ni > plan_item_limit(ctx->opt) || tiles + nt >= (1ull << 31))) {
                 P->batches.push_back({v0, v - v0, 0, 0, 0, 0});
                 v0 = v;
                 items = tiles = 0;
