@@ -96,9 +96,9 @@ MEASURED_TRAFFIC = {
     # HBM bytes per accumulate launch: FETCH_SIZE x 2 + WRITE_SIZE x 1 (the
     # factors a plain 256 MiB device copy gives), averaged over the launches
     # of one step; valid while the accumulate's sources hash to "sources"
-    "relight": {"bytes": 2.620e9, "sources": "18277db2ccc86ddd"},
-    "features": {"bytes": 2.363e10, "sources": "18277db2ccc86ddd"},
-    "batched": {"bytes": 4.605e10, "sources": "18277db2ccc86ddd"},
+    "relight": {"bytes": 2.620e9, "sources": "851c6cf0a7e3c0c9"},
+    "features": {"bytes": 2.363e10, "sources": "851c6cf0a7e3c0c9"},
+    "batched": {"bytes": 1.136e10, "sources": "851c6cf0a7e3c0c9"},
 }
 ACCUMULATE_SOURCES = ("paper_2604_17155_amd/csrc/k_accum.hip", "paper_2604_17155_amd/csrc/wave_ops.h",
                       "paper_2604_17155_amd/csrc/k_sort.hip",    # the tile order
@@ -493,10 +493,10 @@ def workload_batched(args, gsc):
     assert int(info2.dropped_pairs) == 0 and int(info2.contributions) == contrib
     launches = variant_launches(C, variant) * int(info.batches)
     target_bytes = float(r0) * C * 2
-    # the counters were read on the 32-scene plan, 32-pixel bins, 8 view
-    # batches, the persistent 16-channel matrix-core accumulate
-    measured_shape = (n_scenes == 32 and int(info.bin_size) == 32 and int(info.batches) == 8
-                      and variant_name(variant) == "mfma16/persistent")
+    # the counters were read on the 32-scene plan, 32-pixel bins, 29 view
+    # batches, the 16-channel matrix-core accumulate as a grid
+    measured_shape = (n_scenes == 32 and int(info.bin_size) == 32 and int(info.batches) == 29
+                      and variant_name(variant) == "mfma16")
     config = {"workload": f"multi-scene segmentation: {n_scenes} scenes, {g0} Gaussians in total "
                           f"(5k-400k per scene), {c0} cameras 640x480..1280x720, SH degree 0, "
                           f"C={C}, BF16 targets, one plan replayed as a graph",
