@@ -658,7 +658,7 @@ __device__ __forceinline__ uint32_t accumulate_tile_mfma(
                 const float dy = c0.y + lyk[k];
                 const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
                 uint64_t taken, kept;
-                const float w = pixel_step(q2, c1.w, Tk, qlim, amin, amax, tmin, taken, kept);
+                const float w = pixel_step_open(q2, c1.w, Tk, qlim, amin, amax, tmin, taken, kept);
                 // hi: w's upper half (truncated), lo: the exact remainder rounded
                 // to BF16; |w - hi - lo| <= 2^-16 |w|
                 const uint32_t wb = __float_as_uint(w);

@@ -259,6 +259,24 @@ __device__ __forceinline__ float pixel_step(float q2, float opac, float& T, floa
     return w;
 }
 
+// The same step where T takes the tested value whether or not the pixel
+// stops, for a walk that reads T only through this step: a pixel that fails
+// the stop test keeps T < t_min, every later test fails as well (the tested
+// value never exceeds T for T >= 0, and stays negative for T < 0), so it
+// takes no more weight, exactly as with the stopped value.  One select fewer.
+__device__ __forceinline__ float pixel_step_open(float q2, float opac, float& T, float qlim, float amin,
+                                                 float amax, float tmin, uint64_t& taken, uint64_t& kept) {
+    const float al = __builtin_amdgcn_fmed3f(opac * __builtin_amdgcn_exp2f(q2), 0.0f, amax);
+    const bool inq = q2 >= qlim, ina = al >= amin;
+    const float ae = (inq & ina) ? al : 0.0f;
+    const float wt = T * ae;
+    T = fmaf(-T, ae, T);
+    const bool keep = T >= tmin;
+    kept = __builtin_amdgcn_ballot_w64(keep);
+    taken = __builtin_amdgcn_ballot_w64(inq) & __builtin_amdgcn_ballot_w64(ina) & kept;
+    return keep ? wt : 0.0f;
+}
+
 __device__ __forceinline__ float pixel_step(float q2, float opac, float& T, float qlim, float amin,
                                             float amax, float tmin, uint64_t& taken) {
     uint64_t kept;
