@@ -36,10 +36,10 @@ __device__ __forceinline__ void vs_add(float* VS, float* p, float v, float scale
 // Gaussian's tile share of V and S (channels [c_off, c_off + CC) of C) to its
 // slot.  Returns the wave's accepted contributions (uniform).
 //
-// A pixel that stopped (or lies outside the image) has T = kStoppedT.  Bands of four
-// pixel rows are skipped when the Gaussian's footprint misses them (bits of
-// the pair value) or when none of their pixels is live; the wave ends when no
-// band is live.
+// A pixel that stopped has T < t_min (outside the image: kStoppedT).  Bands of
+// four pixel rows are skipped when the Gaussian's footprint misses them (bits
+// of the pair value) or when none of their pixels is live; the wave ends when
+// no band is live.
 template <int CC, bool BF16, int BIN, bool DET>
 __device__ __forceinline__ uint32_t accumulate_tile(
     uint32_t tile, uint32_t lane, const ViewInfo* __restrict__ views, int n_views,
@@ -141,7 +141,7 @@ __device__ __forceinline__ uint32_t accumulate_tile(
             // a fixed register slot, and one wave reduction of the group's 16
             // values (lane e*4+v, bit-reversed) feeds one atomic per value.
             // Tile liveness is refreshed once per group: entries after the
-            // last live pixel stopped meet T = 0 everywhere and add nothing.
+            // last live pixel stopped meet T < t_min everywhere and add nothing.
             while (todo != 0u && alive != 0u) {
                 float pend[16];
                 int64_t gslot[4];
@@ -167,8 +167,8 @@ __device__ __forceinline__ uint32_t accumulate_tile(
                             if (!((bands >> k) & 1u)) continue;  // uniform
                             const float dy = c0.y + lyk[k];
                             const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
-                            uint64_t taken;
-                            const float w = pixel_step(q2, c1.w, T[k], qlim, amin, amax, tmin, taken);
+                            uint64_t taken, kept;
+                            const float w = pixel_step(q2, c1.w, T[k], qlim, amin, amax, tmin, taken, kept);
                             sv += w;
                             s0 = fmaf(w, y[k][0], s0);
                             if constexpr (CC > 1) s1 = fmaf(w, y[k][CC > 1 ? 1 : 0], s1);
@@ -190,7 +190,7 @@ __device__ __forceinline__ uint32_t accumulate_tile(
                 }
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
-                    if (((alive >> k) & 1u) && __builtin_amdgcn_ballot_w64(T[k] > 0.0f) == 0) alive &= ~(1u << k);
+                    if (((alive >> k) & 1u) && __builtin_amdgcn_ballot_w64(T[k] >= tmin) == 0) alive &= ~(1u << k);
                 alive = (uint32_t)__builtin_amdgcn_readfirstlane((int)alive);
                 if (has[0] || has[1] || has[2] || has[3]) {
                     const float t = wave_sum_transposed<16>(pend, lane);
@@ -658,7 +658,7 @@ __device__ __forceinline__ uint32_t accumulate_tile_mfma(
                 const float dy = c0.y + lyk[k];
                 const float q2 = fmaf(dy, fmaf(c1.z, dy, b0), a0);
                 uint64_t taken, kept;
-                const float w = pixel_step_open(q2, c1.w, Tk, qlim, amin, amax, tmin, taken, kept);
+                const float w = pixel_step(q2, c1.w, Tk, qlim, amin, amax, tmin, taken, kept);
                 // hi: w's upper half (truncated), lo: the exact remainder rounded
                 // to BF16; |w - hi - lo| <= 2^-16 |w|
                 const uint32_t wb = __float_as_uint(w);

@@ -208,14 +208,6 @@ __device__ __forceinline__ bool pair_reaches(uint32_t pc, uint32_t quad, uint32_
     else return ((m >> quad) & 1u) != 0u;
 }
 
-// One front-to-back step of one pixel (eq. 2).  alpha = min(alpha_max, o 2^q2)
-// is used when the pixel lies inside the cut-off ellipse (q2 >= qlim) and
-// alpha >= alpha_min; a used alpha that would take T below t_min stops the
-// pixel (T = 0) and contributes nothing.  A live pixel has T >= t_min, so an
-// unused Gaussian (effective alpha 0) leaves T as it is through the same
-// test, and a stopped pixel (T = 0) stays at 0.  Returns the weight alpha T
-// (0 unless used); `taken` gets the wave's lanes that contributed, built
-// from one ballot per condition (each a compare the step makes anyway).
 // Pixel offsets d = pixel centre - projected centre within a 16x16 tile are
 // formed against the tile's centre point x0 + 8 (between its two middle pixel
 // columns): an entry's offset of that point, (x0 + 8 - u_hi) - u_lo, is
@@ -238,11 +230,20 @@ __device__ __forceinline__ float uniform_in_vgpr(float x) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xE4, 0xF, 0xF, true));
 }
 
-// T of a pixel that has stopped, or lies outside the image, is kStoppedT
-// (negative): its test T (1 - alpha) is then negative and fails the stop
-// test for any t_min >= 0, so such a pixel takes no weight without a
-// separate test.  kept: the lanes still live after the step; when it is
-// empty every pixel of the band has stopped and the band can be retired.
+// One front-to-back step of one pixel (eq. 2).  alpha = min(alpha_max, o 2^q2)
+// is used when the pixel lies inside the cut-off ellipse (q2 >= qlim) and
+// alpha >= alpha_min (effective alpha 0 otherwise).  T takes T (1 - alpha)
+// (one fma); when that falls below t_min the pixel stops: this Gaussian
+// contributes nothing, and since T keeps the value below t_min, every later
+// step fails the same test (T (1 - alpha) never exceeds T for T >= 0), so
+// the pixel takes no more weight.  A live pixel has T >= t_min, so an unused
+// Gaussian leaves T as it is through the same test.  Returns the weight
+// alpha T (0 unless used); `taken` gets the wave's lanes that contributed,
+// built from one ballot per condition (each a compare the step makes
+// anyway); `kept` the lanes still live after the step (empty: every pixel of
+// the band has stopped and the band can be retired).
+// Pixels outside the image start at kStoppedT (negative): T (1 - alpha)
+// stays negative and fails the test for any t_min >= 0.
 constexpr float kStoppedT = -1.0f;
 
 __device__ __forceinline__ float pixel_step(float q2, float opac, float& T, float qlim, float amin,
@@ -250,37 +251,12 @@ __device__ __forceinline__ float pixel_step(float q2, float opac, float& T, floa
     const float al = __builtin_amdgcn_fmed3f(opac * __builtin_amdgcn_exp2f(q2), 0.0f, amax);
     const bool inq = q2 >= qlim, ina = al >= amin;
     const float ae = (inq & ina) ? al : 0.0f;
-    const float test = fmaf(-T, ae, T);
-    const bool keep = test >= tmin;
-    kept = __builtin_amdgcn_ballot_w64(keep);
-    taken = __builtin_amdgcn_ballot_w64(inq) & __builtin_amdgcn_ballot_w64(ina) & kept;
-    const float w = keep ? T * ae : 0.0f;
-    T = keep ? test : kStoppedT;
-    return w;
-}
-
-// The same step where T takes the tested value whether or not the pixel
-// stops, for a walk that reads T only through this step: a pixel that fails
-// the stop test keeps T < t_min, every later test fails as well (the tested
-// value never exceeds T for T >= 0, and stays negative for T < 0), so it
-// takes no more weight, exactly as with the stopped value.  One select fewer.
-__device__ __forceinline__ float pixel_step_open(float q2, float opac, float& T, float qlim, float amin,
-                                                 float amax, float tmin, uint64_t& taken, uint64_t& kept) {
-    const float al = __builtin_amdgcn_fmed3f(opac * __builtin_amdgcn_exp2f(q2), 0.0f, amax);
-    const bool inq = q2 >= qlim, ina = al >= amin;
-    const float ae = (inq & ina) ? al : 0.0f;
     const float wt = T * ae;
-    T = fmaf(-T, ae, T);
+    T = fmaf(-T, ae, T);  // in place: the product above is the last read of the old T
     const bool keep = T >= tmin;
     kept = __builtin_amdgcn_ballot_w64(keep);
     taken = __builtin_amdgcn_ballot_w64(inq) & __builtin_amdgcn_ballot_w64(ina) & kept;
     return keep ? wt : 0.0f;
-}
-
-__device__ __forceinline__ float pixel_step(float q2, float opac, float& T, float qlim, float amin,
-                                            float amax, float tmin, uint64_t& taken) {
-    uint64_t kept;
-    return pixel_step(q2, opac, T, qlim, amin, amax, tmin, taken, kept);
 }
 
 template <bool BF16>
