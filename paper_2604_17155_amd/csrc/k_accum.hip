@@ -522,17 +522,10 @@ __device__ __forceinline__ uint32_t accumulate_tile_mfma(
     for (int k = 0; k < 4; ++k) lyk[k] = tile_offset_row(lane, k);
     const float ox = tile_centre(tg.x0), oy = tile_centre(tg.y0);
 
-    // Rows are never cleared; rows past a group's count feed only output rows
-    // that the flush does not use.  Two ways keep a row's unreached bands out
-    // of the product (measured: each is the faster for its shape):
-    //  - one channel block (VALU-bound at four waves per SIMD): the entry
-    //    writes zeros in the bands its footprint misses;
-    //  - several blocks: the entry writes only the bands it reaches; lane m
-    //    keeps row m's band mask (rowmask), the flush zeroes a row's operand
-    //    where that mask lacks the band and skips the K-steps of a band that
-    //    no row of the group wrote.
-    constexpr bool kBandMask = NBLK > 1;
-    uint32_t rowmask = 0;
+    // Rows are never cleared: rows past a group's count feed only output rows
+    // that the flush does not use, and an entry writes zeros in the bands its
+    // footprint misses (measured faster than per-row band masks that zero
+    // the operand in the flush, for one and for two channel blocks).
 
     // one matrix product over the group's `rows` entries, then the atomics.
     // With 8 rows per group the A operand's rows 0..7 take the weights' high
@@ -551,31 +544,14 @@ __device__ __forceinline__ uint32_t accumulate_tile_mfma(
         const uint32_t arow = kSplitRows ? (n16 & 7u) : n16;
         const __bf16* ah_p = &((kSplitRows && n16 >= 8u) ? L.wlo : L.whi)[arow * kWRow + 8 * q4];
         const __bf16* al_p = &L.wlo[arow * kWRow + 8 * q4];
-        // the band mask of this lane's A row, and the bands any row wrote
-        uint32_t mrow = 0xFu;
-        uint32_t anyb = 0xFu;
-        if constexpr (kBandMask) {
-            mrow = (uint32_t)__shfl((int)rowmask, (int)arow, 64);
-            anyb = 0;
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                anyb |= (__builtin_amdgcn_ballot_w64(lane < rows && ((rowmask >> k) & 1u)) != 0 ? 1u : 0u) << k;
-        }
-        bf16x8_t zero8;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) zero8[i] = (__bf16)0.0f;
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
-            if (!((anyb >> (s >> 1)) & 1u)) continue;  // uniform: no row wrote this band
-            const bool masked = kBandMask && !((mrow >> (s >> 1)) & 1u);
-            bf16x8_t ah = *reinterpret_cast<const bf16x8_t*>(ah_p + 32 * s);
-            if (masked) ah = zero8;
+            const bf16x8_t ah = *reinterpret_cast<const bf16x8_t*>(ah_p + 32 * s);
             if (YM == 0 && first_chunk) DV = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, ones, DV, 0, 0, 0);
 #pragma unroll
             for (int b = 0; b < NBLK; ++b) D[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, Y[s][b], D[b], 0, 0, 0);
             if constexpr (!kSplitRows) {
-                bf16x8_t al = *reinterpret_cast<const bf16x8_t*>(al_p + 32 * s);
-                if (masked) al = zero8;
+                const bf16x8_t al = *reinterpret_cast<const bf16x8_t*>(al_p + 32 * s);
                 if (YM == 0 && first_chunk) DV = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, ones, DV, 0, 0, 0);
 #pragma unroll
                 for (int b = 0; b < NBLK; ++b)
@@ -646,13 +622,10 @@ __device__ __forceinline__ uint32_t accumulate_tile_mfma(
             uint32_t nh = 0;
             __bf16* wrow_h = &L.whi[rows * kWRow];
             __bf16* wrow_l = &L.wlo[rows * kWRow];
-            if constexpr (kBandMask) rowmask = lane == rows ? bands : rowmask;
             auto band = [&](const int k, float& Tk) {
                 if (!((bands >> k) & 1u)) {  // uniform: no weight in this band
-                    if constexpr (!kBandMask) {
-                        wrow_h[lane + 64 * k] = (__bf16)0.0f;
-                        wrow_l[lane + 64 * k] = (__bf16)0.0f;
-                    }
+                    wrow_h[lane + 64 * k] = (__bf16)0.0f;
+                    wrow_l[lane + 64 * k] = (__bf16)0.0f;
                     return;
                 }
                 const float dy = c0.y + lyk[k];
