@@ -96,9 +96,9 @@ MEASURED_TRAFFIC = {
     # HBM bytes per accumulate launch: FETCH_SIZE x 2 + WRITE_SIZE x 1 (the
     # factors a plain 256 MiB device copy gives), averaged over the launches
     # of one step; valid while the accumulate's sources hash to "sources"
-    "relight": {"bytes": 2.620e9, "sources": "87bd0e1039cd0a17"},
-    "features": {"bytes": 2.363e10, "sources": "87bd0e1039cd0a17"},
-    "batched": {"bytes": 1.135e10, "sources": "87bd0e1039cd0a17"},
+    "relight": {"bytes": 2.620e9, "sources": "aa42ecc10386c6c1"},
+    "features": {"bytes": 2.363e10, "sources": "aa42ecc10386c6c1"},
+    "batched": {"bytes": 1.135e10, "sources": "aa42ecc10386c6c1"},
 }
 ACCUMULATE_SOURCES = ("paper_2604_17155_amd/csrc/k_accum.hip", "paper_2604_17155_amd/csrc/wave_ops.h",
                       "paper_2604_17155_amd/csrc/k_sort.hip",    # the tile order

@@ -36,7 +36,7 @@ __device__ __forceinline__ void vs_add(float* VS, float* p, float v, float scale
 // Gaussian's tile share of V and S (channels [c_off, c_off + CC) of C) to its
 // slot.  Returns the wave's accepted contributions (uniform).
 //
-// A pixel that stopped has T < t_min (outside the image: kStoppedT).  Bands of
+// A pixel that stopped has T < t_min (outside the image it starts at kOutsideT).  Bands of
 // four pixel rows are skipped when the Gaussian's footprint misses them (bits
 // of the pair value) or when none of their pixels is live; the wave ends when
 // no band is live.
@@ -65,7 +65,7 @@ __device__ __forceinline__ uint32_t accumulate_tile(
     for (int k = 0; k < 4; ++k) {
         const int iy = iy0 + 4 * k;
         const bool inside = (ix < vw) & (iy < vh);
-        T[k] = inside ? 1.0f : kStoppedT;
+        T[k] = inside ? 1.0f : kOutsideT;
         alive |= (__builtin_amdgcn_ballot_w64(inside) != 0 ? 1u : 0u) << k;
         const int64_t row = poff + (int64_t)iy * vw + ix;
         // unconditional loads (element 0 stands in for pixels outside the
@@ -494,7 +494,7 @@ __device__ __forceinline__ uint32_t accumulate_tile_mfma(
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const bool inside = (ix < vw) & (iy0 + 4 * k < vh);
-        const float t = inside ? 1.0f : kStoppedT;
+        const float t = inside ? 1.0f : kOutsideT;
         if (k == 0) T0 = t;
         if (k == 1) T1 = t;
         if (k == 2) T2 = t;

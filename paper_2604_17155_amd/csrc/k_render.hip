@@ -105,7 +105,7 @@ __global__ __launch_bounds__(256) void k_render(
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         inside[k] = ix < V.width && iy0 + 4 * k < V.height;
-        T[k] = inside[k] ? 1.0f : kStoppedT;
+        T[k] = inside[k] ? 1.0f : kOutsideT;
         alive |= (__builtin_amdgcn_ballot_w64(inside[k]) != 0 ? 1u : 0u) << k;
 #pragma unroll
         for (int c = 0; c < CC; ++c) img[k][c] = 0.0f;

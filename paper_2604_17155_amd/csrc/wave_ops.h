@@ -242,9 +242,9 @@ __device__ __forceinline__ float uniform_in_vgpr(float x) {
 // built from one ballot per condition (each a compare the step makes
 // anyway); `kept` the lanes still live after the step (empty: every pixel of
 // the band has stopped and the band can be retired).
-// Pixels outside the image start at kStoppedT (negative): T (1 - alpha)
+// Pixels outside the image start at kOutsideT (negative): T (1 - alpha)
 // stays negative and fails the test for any t_min >= 0.
-constexpr float kStoppedT = -1.0f;
+constexpr float kOutsideT = -1.0f;
 
 __device__ __forceinline__ float pixel_step(float q2, float opac, float& T, float qlim, float amin,
                                             float amax, float tmin, uint64_t& taken, uint64_t& kept) {
