@@ -307,7 +307,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(acc_waves_p
     const uint32_t lane = threadIdx.x & 63;
     uint32_t cnt = 0;
     if (queue == nullptr) {
-        const uint32_t wi = blockIdx.x * 4 + (threadIdx.x >> 6);
+        const uint32_t wi = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
         if (wi >= n_tiles) return;  // whole wave
         const uint32_t tile = queued_tile<BIN>(wi, order);  // blocks start in index order
         cnt = accumulate_tile<CC, BF16, BIN, DET>(tile, lane, views, n_views, ranges, pair_vals,
@@ -676,7 +676,7 @@ __attribute__((amdgpu_waves_per_eu(mfma_waves_per_simd<NBLK>()))) void k_accumul
     const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint32_t cnt = 0;
     if (queue == nullptr) {
-        const uint32_t wi = blockIdx.x * kMfmaWaves + w;
+        const uint32_t wi = xcd_block(blockIdx.x, gridDim.x) * kMfmaWaves + w;
         if (wi >= n_tiles) return;  // whole wave
         const uint32_t tile = queued_tile<BIN>(wi, order);  // blocks start in index order
         cnt = accumulate_tile_mfma<NBLK, BIN, YM>(tile, lane, lds[w], views, n_views, ranges, pair_vals,

@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(adj_waves_p
     const float* __restrict__ beta, BlendParams bp, float* __restrict__ grad_y,
     float* __restrict__ grad_o, const uint32_t* __restrict__ order) {
     const uint32_t lane = threadIdx.x & 63;
-    const uint32_t wi = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const uint32_t wi = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
     if (wi >= n_wt) return;  // whole wave
     const uint32_t wt = queued_tile<BIN>(wi, order);  // blocks start in index order
     const TileGeom tg = tile_geom<BIN>(wt, views, n_views);

@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void k_render(
     const float* __restrict__ gamma, int C, int c_off, BlendParams bp, float* __restrict__ images,
     unsigned long long* __restrict__ counter, const uint32_t* __restrict__ order) {
     const uint32_t lane = threadIdx.x & 63;
-    const uint32_t wi = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const uint32_t wi = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
     if (wi >= n_wt) return;
     const uint32_t wt = queued_tile<BIN>(wi, order);  // blocks start in index order
     const TileGeom tg = tile_geom<BIN>(wt, views, n_views);

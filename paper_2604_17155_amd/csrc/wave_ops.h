@@ -169,6 +169,22 @@ __device__ __forceinline__ TileGeom tile_geom(uint32_t vt, const ViewInfo* __res
     return t;
 }
 
+// Logical block of a grid block.  The dispatcher deals a grid's blocks to
+// the 8 XCDs in turn (block b runs on XCD b % 8), and each XCD has an L2 of
+// its own.  The grid is cut into groups of 8 kXcdRun blocks; within a group,
+// XCD x takes the logical blocks x kXcdRun .. x kXcdRun + kXcdRun - 1, so
+// that consecutive logical blocks (neighbouring tiles of the launch order,
+// which read the same Gaussian records, and the quadrant waves of one
+// 32-pixel bin) share an L2, while the groups still start in order.  Blocks
+// of a last, incomplete group keep their index.  A bijection on [0, G).
+constexpr uint32_t kXcds = 8, kXcdRun = 32;
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t G) {
+    constexpr uint32_t group = kXcds * kXcdRun;
+    if (b >= G - G % group) return b;
+    const uint32_t x = b % kXcds, r = b / kXcds;
+    return (r / kXcdRun) * group + x * kXcdRun + r % kXcdRun;
+}
+
 // The wave tile taken t-th from a persistent launch's queue.  With `order`
 // (bins by decreasing octave of list length) the longest lists start first,
 // so that no long tile is left to run alone at the end of the launch.
