@@ -47,7 +47,8 @@ __device__ __forceinline__ uint32_t accumulate_tile(
     const float4* __restrict__ rec0, const float4* __restrict__ rec1,
     const uint2* __restrict__ rec2,
     const void* __restrict__ targets, int C, int c_off, int per_view, const BlendParams& bp,
-    float* __restrict__ VS, float2 dsc, uint32_t* __restrict__ gcount) {
+    float* __restrict__ VS, float2 dsc, uint32_t* __restrict__ gcount, float4* __restrict__ lrec1,
+    float2* __restrict__ lrec0) {
     constexpr int CCA = CC > 0 ? CC : 1;
     const TileGeom tg = tile_geom<BIN>(tile, views, n_views);
     const ViewInfo& V = views[tg.vloc];
@@ -136,6 +137,12 @@ __device__ __forceinline__ uint32_t accumulate_tile(
         // list order: the walk visits only these
         uint64_t todo = __builtin_amdgcn_ballot_w64(
             lane < nb && (entry_bands<BIN>(pv, tg.quad, R2.x, tg.y0) & alive) != 0u);
+        // the chunk's records go through LDS (this wave's 64 slots): an entry
+        // reads them back with two broadcast loads instead of six readlanes
+        lrec1[lane] = R1;
+        lrec0[lane] = R0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
         if constexpr (CC >= 1 && CC <= 3) {
             // Entries in groups of four: each entry's tile sums (V, S) stay in
             // a fixed register slot, and one wave reduction of the group's 16
@@ -157,8 +164,8 @@ __device__ __forceinline__ uint32_t accumulate_tile(
                     float sv = 0.0f, s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
                     uint32_t nh = 0;
                     if (bands != 0u) {
-                        const float2 c0 = make_float2(bcast(R0.x, j), bcast(R0.y, j));
-                        const float4 c1 = make_float4(bcast(R1.x, j), bcast(R1.y, j), bcast(R1.z, j), bcast(R1.w, j));
+                        const float2 c0 = lrec0[j];
+                        const float4 c1 = lrec1[j];
                         const float dx = c0.x + lx;
                         const float a0 = c1.x * dx * dx;
                         const float b0 = c1.y * dx;
@@ -211,8 +218,8 @@ __device__ __forceinline__ uint32_t accumulate_tile(
                 const uint2 e2 = make_uint2(bcast_u(R2.x, j), bcast_u(R2.y, j));
                 const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2.x, tg.y0) & alive;
                 if (bands == 0u) continue;
-                const float2 c0 = make_float2(bcast(R0.x, j), bcast(R0.y, j));
-                const float4 c1 = make_float4(bcast(R1.x, j), bcast(R1.y, j), bcast(R1.z, j), bcast(R1.w, j));
+                const float2 c0 = lrec0[j];
+                const float4 c1 = lrec1[j];
                 const float dx = c0.x + lx;
                 const float a0 = c1.x * dx * dx;
                 const float b0 = c1.y * dx;
@@ -271,6 +278,7 @@ __device__ __forceinline__ uint32_t accumulate_tile(
                 if (alive == 0u) break;
             }
         }
+        __builtin_amdgcn_wave_barrier();  // the next chunk's records overwrite these
         if constexpr (kDouble) {
             R0 = Q0;
             R1 = Q1;
@@ -304,15 +312,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(acc_waves_p
     int per_view, BlendParams bp, float* __restrict__ VS, float2 dsc,
     unsigned long long* __restrict__ counter, uint32_t* __restrict__ gcount,
     uint32_t* __restrict__ queue, const uint32_t* __restrict__ order) {
-    const uint32_t lane = threadIdx.x & 63;
+    __shared__ float4 srec1[4][64];
+    __shared__ float2 srec0[4][64];
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint32_t cnt = 0;
     if (queue == nullptr) {
-        const uint32_t wi = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+        const uint32_t wi = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
         if (wi >= n_tiles) return;  // whole wave
         const uint32_t tile = queued_tile<BIN>(wi, order);  // blocks start in index order
         cnt = accumulate_tile<CC, BF16, BIN, DET>(tile, lane, views, n_views, ranges, pair_vals,
                                                   rec0, rec1, rec2, targets, C, c_off, per_view, bp,
-                                                  VS, dsc, gcount);
+                                                  VS, dsc, gcount, srec1[w], srec0[w]);
     } else {
         for (;;) {
             uint32_t t = 0;
@@ -322,7 +332,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(acc_waves_p
             const uint32_t tile = queued_tile<BIN>(tq, order);
             cnt += accumulate_tile<CC, BF16, BIN, DET>(tile, lane, views, n_views, ranges, pair_vals,
                                                        rec0, rec1, rec2, targets, C, c_off,
-                                                       per_view, bp, VS, dsc, gcount);
+                                                       per_view, bp, VS, dsc, gcount, srec1[w], srec0[w]);
         }
     }
     if (c_off == 0 && lane == 0 && cnt) atomicAdd(counter, (unsigned long long)cnt);
