@@ -146,8 +146,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(adj_waves_p
     const uint2* __restrict__ rec2, const void* __restrict__ ypix, int C, int c_off,
     const float* __restrict__ beta, BlendParams bp, float* __restrict__ grad_y,
     float* __restrict__ grad_o, const uint32_t* __restrict__ order) {
-    const uint32_t lane = threadIdx.x & 63;
-    const uint32_t wi = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    // the chunk's records and, for up to three channels, the entry's adjoint
+    // colours and offset, read back by every lane as broadcasts
+    constexpr bool kLdsB = CC <= 3;
+    __shared__ float4 srec1[4][64];
+    __shared__ float4 sbet[4][kLdsB ? 64 : 1];
+    __shared__ float2 srec0[4][64];
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t wi = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
     if (wi >= n_wt) return;  // whole wave
     const uint32_t wt = queued_tile<BIN>(wi, order);  // blocks start in index order
     const TileGeom tg = tile_geom<BIN>(wt, views, n_views);
@@ -189,8 +195,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(adj_waves_p
 
     // Both passes walk the list the same way, so that they take the same
     // decisions.  A chunk of 64 entries is gathered at once, one entry per
-    // lane (records and the entry's adjoint colours), and broadcast entry by
-    // entry; only entries reaching a band with a live pixel are visited.  A
+    // lane (records and the entry's adjoint colours), and staged in LDS, from
+    // which an entry reads them back with broadcast loads (adjoint colours of
+    // wider chunks by readlane); each lane forms its entry's band mask, and
+    // only entries reaching a band with a live pixel are visited.  A
     // pixel that stopped adds nothing in either pass, so the skipped entries
     // and bands change no sum.
     uint32_t alive0 = 0;  // bands holding a pixel of the image
@@ -220,21 +228,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(adj_waves_p
 #pragma unroll
             for (int c = 0; c < CC; ++c) RB[c] = (own && c_off + c < C) ? bl[c_off + c] : 0.0f;
             const float RD = (own && first_chunk) ? bl[C] : 0.0f;
-            uint64_t todo = __builtin_amdgcn_ballot_w64(
-                own && (entry_bands<BIN>(pv, tg.quad, R2.x, tg.y0) & alive) != 0u);
+            const uint32_t BL = own ? (entry_bands<BIN>(pv, tg.quad, R2.x, tg.y0) & alive) : 0u;
+            uint64_t todo = __builtin_amdgcn_ballot_w64(BL != 0u);
+            srec1[w][lane] = R1;
+            srec0[w][lane] = R0;
+            if constexpr (kLdsB)
+                sbet[w][lane] = make_float4(RB[0], CC > 1 ? RB[CC > 1 ? 1 : 0] : 0.0f,
+                                            CC > 2 ? RB[CC > 2 ? 2 : 0] : 0.0f, RD);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
             while (todo != 0u) {
                 const uint32_t j = (uint32_t)__builtin_ctzll(todo);
                 todo &= todo - 1u;
-                const uint32_t pc = bcast_u(pv, j);
-                const uint2 e2 = make_uint2(bcast_u(R2.x, j), bcast_u(R2.y, j));
-                const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2.x, tg.y0) & alive;
+                const uint32_t bands = bcast_u(BL, j) & alive;
                 if (bands == 0u) continue;
-                const float2 c0 = make_float2(bcast(R0.x, j), bcast(R0.y, j));
-                const float4 c1 = make_float4(bcast(R1.x, j), bcast(R1.y, j), bcast(R1.z, j), bcast(R1.w, j));
+                const uint2 e2 = make_uint2(0u, bcast_u(R2.y, j));  // the item
+                const float2 c0 = srec0[w][j];
+                const float4 c1 = srec1[w][j];
                 float bet[CC];
+                float del;
+                if constexpr (kLdsB) {
+                    const float4 b4 = sbet[w][kLdsB ? j : 0];
+                    const float bb[3] = {b4.x, b4.y, b4.z};
 #pragma unroll
-                for (int c = 0; c < CC; ++c) bet[c] = bcast(RB[c], j);
-                const float del = bcast(RD, j);
+                    for (int c = 0; c < CC; ++c) bet[c] = bb[c < 3 ? c : 0];
+                    del = b4.w;
+                } else {
+#pragma unroll
+                    for (int c = 0; c < CC; ++c) bet[c] = bcast(RB[c], j);
+                    del = bcast(RD, j);
+                }
                 body(bands, c0, c1, e2, bet, del);
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
@@ -242,6 +265,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(adj_waves_p
                 alive = (uint32_t)__builtin_amdgcn_readfirstlane((int)alive);
                 if (alive == 0u) break;
             }
+            __builtin_amdgcn_wave_barrier();  // the next chunk overwrites the records
         }
     };
 

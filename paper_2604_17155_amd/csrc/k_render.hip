@@ -90,8 +90,13 @@ __global__ __launch_bounds__(256) void k_render(
     const float4* __restrict__ rec1, const uint2* __restrict__ rec2,
     const float* __restrict__ gamma, int C, int c_off, BlendParams bp, float* __restrict__ images,
     unsigned long long* __restrict__ counter, const uint32_t* __restrict__ order) {
-    const uint32_t lane = threadIdx.x & 63;
-    const uint32_t wi = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    static_assert(CC <= 4, "one float4 of colours per entry");
+    // the chunk's records and colours, read back by every lane as broadcasts
+    __shared__ float4 srec1[4][64];
+    __shared__ float4 scol[4][64];
+    __shared__ float2 srec0[4][64];
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t wi = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
     if (wi >= n_wt) return;
     const uint32_t wt = queued_tile<BIN>(wi, order);  // blocks start in index order
     const TileGeom tg = tile_geom<BIN>(wt, views, n_views);
@@ -127,8 +132,9 @@ __global__ __launch_bounds__(256) void k_render(
     for (int k = 0; k < 4; ++k) lyk[k] = tile_offset_row(lane, k);
     const float ox = tile_centre(tg.x0), oy = tile_centre(tg.y0);
     // A chunk of 64 entries is gathered at once, one entry per lane (records
-    // and the item's colours), and broadcast entry by entry; only entries
-    // reaching a band with a live pixel are visited.
+    // and the item's colours), and staged in LDS, from which an entry reads
+    // them back with broadcast loads; each lane forms its entry's band mask,
+    // and only entries reaching a band with a live pixel are visited.
     for (uint32_t b = rg.x; b < rg.y && alive != 0u; b += 64) {
         const uint32_t nb = min(64u, rg.y - b);
         const bool own = lane < nb;
@@ -142,20 +148,23 @@ __global__ __launch_bounds__(256) void k_render(
         float RC[CC];
 #pragma unroll
         for (int c = 0; c < CC; ++c) RC[c] = (own && c_off + c < C) ? gl[c] : 0.0f;
-        uint64_t todo = __builtin_amdgcn_ballot_w64(
-            own && (entry_bands<BIN>(pv, tg.quad, R2.x, tg.y0) & alive) != 0u);
+        const uint32_t BL = own ? (entry_bands<BIN>(pv, tg.quad, R2.x, tg.y0) & alive) : 0u;
+        uint64_t todo = __builtin_amdgcn_ballot_w64(BL != 0u);
+        srec1[w][lane] = R1;
+        srec0[w][lane] = R0;
+        scol[w][lane] = make_float4(RC[0], CC > 1 ? RC[CC > 1 ? 1 : 0] : 0.0f, CC > 2 ? RC[CC > 2 ? 2 : 0] : 0.0f,
+                                    CC > 3 ? RC[CC > 3 ? 3 : 0] : 0.0f);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
         while (todo != 0u) {
             const uint32_t j = (uint32_t)__builtin_ctzll(todo);
             todo &= todo - 1u;
-            const uint32_t pc = bcast_u(pv, j);
-            const uint32_t ext = bcast_u(R2.x, j);
-            const uint32_t bands = entry_bands<BIN>(pc, tg.quad, ext, tg.y0) & alive;
+            const uint32_t bands = bcast_u(BL, j) & alive;
             if (bands == 0u) continue;
-            const float2 c0 = make_float2(bcast(R0.x, j), bcast(R0.y, j));
-            const float4 c1 = make_float4(bcast(R1.x, j), bcast(R1.y, j), bcast(R1.z, j), bcast(R1.w, j));
-            float col[CC];
-#pragma unroll
-            for (int c = 0; c < CC; ++c) col[c] = bcast(RC[c], j);
+            const float2 c0 = srec0[w][j];
+            const float4 c1 = srec1[w][j];
+            const float4 c4 = scol[w][j];
+            const float col[4] = {c4.x, c4.y, c4.z, c4.w};
             const float dx = c0.x + lx;
             const float a0 = c1.x * dx * dx;
             const float b0 = c1.y * dx;
@@ -176,6 +185,7 @@ __global__ __launch_bounds__(256) void k_render(
             cnt += (uint32_t)__builtin_amdgcn_readfirstlane((int)nh);
             if (alive == 0u) break;
         }
+        __builtin_amdgcn_wave_barrier();  // the next chunk overwrites the records
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
