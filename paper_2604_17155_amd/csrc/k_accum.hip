@@ -135,8 +135,10 @@ __device__ __forceinline__ uint32_t accumulate_tile(
         const uint32_t pvnn = load_pv(b + 128);
         // the chunk's entries that can reach a live band, one bit per lane in
         // list order: the walk visits only these
-        uint64_t todo = __builtin_amdgcn_ballot_w64(
-            lane < nb && (entry_bands<BIN>(pv, tg.quad, R2.x, tg.y0) & alive) != 0u);
+        // each lane forms its entry's band mask: taking an entry then costs
+        // one broadcast of it
+        const uint32_t BL = lane < nb ? entry_bands<BIN>(pv, tg.quad, R2.x, tg.y0) : 0u;
+        uint64_t todo = __builtin_amdgcn_ballot_w64((BL & alive) != 0u);
         // the chunk's records go through LDS (this wave's 64 slots): an entry
         // reads them back with two broadcast loads instead of six readlanes
         lrec1[lane] = R1;
@@ -158,9 +160,8 @@ __device__ __forceinline__ uint32_t accumulate_tile(
                     const bool any = todo != 0u;
                     const uint32_t j = any ? (uint32_t)__builtin_ctzll(todo) : 0u;
                     todo &= todo - 1u;
-                    const uint32_t pc = bcast_u(pv, j);
-                    const uint2 e2 = make_uint2(bcast_u(R2.x, j), bcast_u(R2.y, j));
-                    const uint32_t bands = any ? entry_bands<BIN>(pc, tg.quad, e2.x, tg.y0) & alive : 0u;
+                    const uint32_t gid = bcast_u(R2.y, j);  // the entry's item
+                    const uint32_t bands = any ? bcast_u(BL, j) & alive : 0u;
                     float sv = 0.0f, s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
                     uint32_t nh = 0;
                     if (bands != 0u) {
@@ -185,7 +186,7 @@ __device__ __forceinline__ uint32_t accumulate_tile(
                     }
                     nh = (uint32_t)__builtin_amdgcn_readfirstlane((int)nh);
                     cnt += nh;
-                    const int64_t g = (int64_t)e2.y - item_base;
+                    const int64_t g = (int64_t)gid - item_base;
                     if (nh != 0u && gcount != nullptr && first_chunk && lane == 0)
                         atomicAdd(gcount + V.g_offset + g, nh);
                     has[u] = nh != 0u;
@@ -214,10 +215,9 @@ __device__ __forceinline__ uint32_t accumulate_tile(
             while (todo != 0u) {
                 const uint32_t j = (uint32_t)__builtin_ctzll(todo);
                 todo &= todo - 1u;
-                const uint32_t pc = bcast_u(pv, j);
-                const uint2 e2 = make_uint2(bcast_u(R2.x, j), bcast_u(R2.y, j));
-                const uint32_t bands = entry_bands<BIN>(pc, tg.quad, e2.x, tg.y0) & alive;
+                const uint32_t bands = bcast_u(BL, j) & alive;
                 if (bands == 0u) continue;
+                const uint32_t gid = bcast_u(R2.y, j);  // the entry's item
                 const float2 c0 = lrec0[j];
                 const float4 c1 = lrec1[j];
                 const float dx = c0.x + lx;
@@ -247,7 +247,7 @@ __device__ __forceinline__ uint32_t accumulate_tile(
                 cnt += nh;
                 if (nh != 0u) {
                     // the pair carries the depth rank; the record names the item
-                    const int64_t g = (int64_t)e2.y - item_base;
+                    const int64_t g = (int64_t)gid - item_base;
                     if (gcount != nullptr && first_chunk && lane == 0) atomicAdd(gcount + V.g_offset + g, nh);
                     float* slot = VS + (slot_base + g) * (int64_t)stride;
                     if constexpr (CC == 0) {
