@@ -512,8 +512,11 @@ gsc_status gsc_colorize_batched(gsc_plan* plan, const void* targets, int32_t tdt
  * arithmetic (vector lanes, or for BF16 targets matrix cores on blocks of 16
  * channels) and the grid form (one block per few tiles, or a persistent grid
  * whose waves take tiles from a queue).  Times each candidate over all view batches, keeps the
- * fastest, then runs the plan once more so that coeffs/status hold a clean
- * result.  Synchronises `stream`.  Not capturable.
+ * fastest (the plain grid over the persistent form of the same arithmetic
+ * when it is within 3% of it: its tiles map to the XCDs so that neighbours
+ * share an L2, which moves less HBM traffic), then runs the plan once more so
+ * that coeffs/status hold a clean result.  Synchronises `stream`.  Not
+ * capturable.
  */
 gsc_status gsc_plan_autotune(gsc_plan* plan, const void* targets, int32_t tdtype,
                              const float* lambda, int32_t n_lambda, float* coeffs,

@@ -238,6 +238,12 @@ def test_batched_autotune(ctx, gsc_mod):
     assert len(cands) >= 4 and info.accumulate_variant in cands
     assert any(v >> 8 for v in cands)  # persistent shapes were timed
     assert all(t > 0 for t in times)
+    # the fastest, or the plain grid within 3% of the persistent form
+    chosen = times[cands.index(info.accumulate_variant)]
+    assert chosen <= 1.03 * min(times) * (1 + 1e-6)
+    if info.accumulate_variant >> 8:
+        grid = info.accumulate_variant & 255
+        assert grid not in cands or times[cands.index(grid)] > 1.03 * chosen
     e, _ = parity.rel_errors(c.cpu().numpy(), dict(coeffs=ref_c.cpu().numpy().astype(np.float64),
                                                    status=np.zeros(len(c), np.uint8)))
     assert e.max() < 1e-5
