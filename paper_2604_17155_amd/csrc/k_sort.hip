@@ -47,18 +47,31 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* wsum, uint
     __syncthreads();
     return off + inc - v;
 }
+// The kScanItems = 8 consecutive elements at base: two 16-byte loads when
+// they all lie below n and the array is 16-byte aligned, else one guarded
+// load each (zero past the end).
+__device__ inline void scan_load8(const uint32_t* in, uint64_t base, uint32_t n, uint32_t* x) {
+    if (base + kScanItems <= n && (reinterpret_cast<uintptr_t>(in) & 15u) == 0) {
+        const uint4 a = *reinterpret_cast<const uint4*>(in + base);
+        const uint4 b = *reinterpret_cast<const uint4*>(in + base + 4);
+        x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+        x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < kScanItems; ++j) x[j] = base + j < n ? in[base + j] : 0u;
+    }
+}
 }  // namespace
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __restrict__ in,
                                                               uint32_t n, uint32_t* __restrict__ bsums) {
     __shared__ uint32_t wsum[kScanThreads / 64];
     uint64_t base = (uint64_t)blockIdx.x * kScanBlock + (uint64_t)threadIdx.x * kScanItems;
+    uint32_t x[kScanItems];
+    scan_load8(in, base, n, x);
     uint32_t s = 0;
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        uint64_t idx = base + j;
-        if (idx < n) s += in[idx];
-    }
+    for (int j = 0; j < kScanItems; ++j) s += x[j];
     uint32_t tot;
     block_exclusive_scan(s, wsum, &tot);
     if (threadIdx.x == 0) bsums[blockIdx.x] = tot;
@@ -82,21 +95,29 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* in, 
     }
     uint64_t base = (uint64_t)blockIdx.x * kScanBlock + (uint64_t)threadIdx.x * kScanItems;
     uint32_t x[kScanItems];
+    scan_load8(in, base, n, x);
     uint32_t s = 0;
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        uint64_t idx = base + j;
-        x[j] = idx < n ? in[idx] : 0u;
-        s += x[j];
-    }
+    for (int j = 0; j < kScanItems; ++j) s += x[j];
     uint32_t tot;
     uint32_t pre = block_exclusive_scan(s, wsum, &tot);
     pre += off;
+    if (base + kScanItems <= n && (reinterpret_cast<uintptr_t>(out) & 15u) == 0) {
+        uint32_t y[kScanItems];
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        uint64_t idx = base + j;
-        if (idx < n) out[idx] = pre;
-        pre += x[j];
+        for (int j = 0; j < kScanItems; ++j) {
+            y[j] = pre;
+            pre += x[j];
+        }
+        *reinterpret_cast<uint4*>(out + base) = make_uint4(y[0], y[1], y[2], y[3]);
+        *reinterpret_cast<uint4*>(out + base + 4) = make_uint4(y[4], y[5], y[6], y[7]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < kScanItems; ++j) {
+            uint64_t idx = base + j;
+            if (idx < n) out[idx] = pre;
+            pre += x[j];
+        }
     }
     if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = off + tot;
 }
@@ -162,13 +183,23 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint32_t* __restri
     constexpr int kSets = 4;
     __shared__ uint32_t h[kRsWaves * kSets][256];
     const int w = (int)(threadIdx.x >> 6) * kSets + (int)(threadIdx.x & (kSets - 1));
+    const uint64_t base = (uint64_t)blockIdx.x * kRsTile;
+    // All sixteen loads of a thread are issued before the counters are
+    // cleared (sixteen coalesced loads in flight per wave, not one); an index
+    // past the end reads the last key and is not counted.
+    uint32_t kk[kRsItems];
+    if (base < n) {
+#pragma unroll
+        for (int it = 0; it < kRsItems; ++it)
+            kk[it] = keys[min(base + (uint64_t)it * kRsThreads + threadIdx.x, (uint64_t)n - 1)];
+    }
     for (int k = threadIdx.x; k < kRsWaves * kSets * 256; k += kRsThreads) (&h[0][0])[k] = 0;
     __syncthreads();
-    uint64_t base = (uint64_t)blockIdx.x * kRsTile;
-#pragma unroll 4
-    for (int it = 0; it < kRsItems; ++it) {
-        uint64_t idx = base + (uint64_t)it * kRsThreads + threadIdx.x;
-        if (idx < n) atomicAdd(&h[w][(keys[idx] >> shift) & 255u], 1u);
+    if (base < n) {
+#pragma unroll
+        for (int it = 0; it < kRsItems; ++it)
+            if (base + (uint64_t)it * kRsThreads + threadIdx.x < n)
+                atomicAdd(&h[w][(kk[it] >> shift) & 255u], 1u);
     }
     __syncthreads();
     uint32_t d = threadIdx.x;
@@ -207,12 +238,20 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* __res
     const uint64_t tile0 = (uint64_t)blockIdx.x * kRsTile;
     const uint64_t base = tile0 + (uint64_t)w * (kRsTile / kRsWaves);
     uint32_t kk[kRsItems], vv[kRsItems], rk[kRsItems];
+    // The wave's 32 loads are all issued before the ranking, whose wave
+    // barriers would otherwise hold each round's loads until the round
+    // before has been ranked; an index past the end reads the last pair.
+#pragma unroll
+    for (int it = 0; it < kRsItems; ++it) {
+        const uint64_t idx = min(base + (uint64_t)it * 64 + lane, (uint64_t)n - 1);
+        kk[it] = keys_in[idx];
+        vv[it] = vals_in[idx];
+    }
 #pragma unroll
     for (int it = 0; it < kRsItems; ++it) {
         const uint64_t idx = base + (uint64_t)it * 64 + lane;
         const bool valid = idx < n;
-        const uint32_t key = valid ? keys_in[idx] : 0u;
-        const uint32_t val = valid ? vals_in[idx] : 0u;
+        const uint32_t key = kk[it];
         const uint32_t d = (key >> shift) & 255u;
         uint64_t m = __ballot(valid);
 #pragma unroll
@@ -226,8 +265,6 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* __res
         __builtin_amdgcn_wave_barrier();
         if (valid && pre == 0) wcnt[w][d] = c + (uint32_t)__popcll(m);
         __builtin_amdgcn_wave_barrier();
-        kk[it] = key;
-        vv[it] = val;
         rk[it] = valid ? c + pre : 0xFFFFFFFFu;
     }
     __syncthreads();
