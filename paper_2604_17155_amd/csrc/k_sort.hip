@@ -1,4 +1,4 @@
-// Device-wide exclusive scan and stable LSD radix sort (8-bit digits).
+// Device-wide exclusive scan and stable LSD radix sort (digits of up to 8 bits).
 //
 // The sort orders the (view, Gaussian) items by depth and then the emitted
 // (tile, item) pairs by tile.  Stability of every pass is what carries the
@@ -169,19 +169,21 @@ void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
 
 // ---- radix sort ----------------------------------------------------------
 
-// Digit histogram of one 8192-key tile, written digit-major: hist[d * nblocks + b].
+// Digit histogram of one 8192-key tile, written digit-major: hist[d * nblocks + b]
+// for the digits d <= mask of the pass ((key >> shift) & mask).
 // n_dev (optional): the live key count, read on the device and clamped to n;
 // the grid is sized for n.
 __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint32_t* __restrict__ keys, uint32_t n,
                                                         const uint32_t* __restrict__ n_dev,
-                                                        int shift, uint32_t* __restrict__ hist,
+                                                        int shift, uint32_t mask, uint32_t* __restrict__ hist,
                                                         uint32_t nblocks) {
     if (n_dev) n = min(n, *n_dev);
     // four counter sets per wave (lane % 4): keys that share a digit, as in
     // the last pass of a sort whose top digit takes few values, spread their
-    // LDS atomics over four addresses
-    constexpr int kSets = 4;
-    __shared__ uint32_t h[kRsWaves * kSets][256];
+    // LDS atomics over four addresses, which the padded rows (264 words: a
+    // shift of 8 banks from one set to the next) put in different banks
+    constexpr int kSets = 4, kRow = 264;
+    __shared__ uint32_t h[kRsWaves * kSets][kRow];
     const int w = (int)(threadIdx.x >> 6) * kSets + (int)(threadIdx.x & (kSets - 1));
     const uint64_t base = (uint64_t)blockIdx.x * kRsTile;
     // All sixteen loads of a thread are issued before the counters are
@@ -193,17 +195,17 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint32_t* __restri
         for (int it = 0; it < kRsItems; ++it)
             kk[it] = keys[min(base + (uint64_t)it * kRsThreads + threadIdx.x, (uint64_t)n - 1)];
     }
-    for (int k = threadIdx.x; k < kRsWaves * kSets * 256; k += kRsThreads) (&h[0][0])[k] = 0;
+    for (int k = threadIdx.x; k < kRsWaves * kSets * kRow; k += kRsThreads) (&h[0][0])[k] = 0;
     __syncthreads();
     if (base < n) {
 #pragma unroll
         for (int it = 0; it < kRsItems; ++it)
             if (base + (uint64_t)it * kRsThreads + threadIdx.x < n)
-                atomicAdd(&h[w][(kk[it] >> shift) & 255u], 1u);
+                atomicAdd(&h[w][(kk[it] >> shift) & mask], 1u);
     }
     __syncthreads();
     uint32_t d = threadIdx.x;
-    if (d >= 256u) return;
+    if (d > mask) return;
     uint32_t sum = 0;
 #pragma unroll
     for (int k = 0; k < kRsWaves * kSets; ++k) sum += h[k][d];
@@ -221,7 +223,7 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* __res
                                                            const uint32_t* __restrict__ vals_in,
                                                            uint32_t* __restrict__ keys_out,
                                                            uint32_t* __restrict__ vals_out,
-                                                           uint32_t n, const uint32_t* __restrict__ n_dev, int shift,
+                                                           uint32_t n, const uint32_t* __restrict__ n_dev, int shift, uint32_t mask,
                                                            const uint32_t* __restrict__ offs,
                                                            uint32_t nblocks) {
     if (n_dev) n = min(n, *n_dev);
@@ -234,7 +236,7 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* __res
     __shared__ uint32_t sval[kRsTile];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int k = lane; k < 256; k += 64) wcnt[w][k] = 0u;
-    if (threadIdx.x < 256) gbase[threadIdx.x] = offs[(uint64_t)threadIdx.x * nblocks + blockIdx.x];
+    if (threadIdx.x <= mask) gbase[threadIdx.x] = offs[(uint64_t)threadIdx.x * nblocks + blockIdx.x];
     const uint64_t tile0 = (uint64_t)blockIdx.x * kRsTile;
     const uint64_t base = tile0 + (uint64_t)w * (kRsTile / kRsWaves);
     uint32_t kk[kRsItems], vv[kRsItems], rk[kRsItems];
@@ -252,7 +254,7 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* __res
         const uint64_t idx = base + (uint64_t)it * 64 + lane;
         const bool valid = idx < n;
         const uint32_t key = kk[it];
-        const uint32_t d = (key >> shift) & 255u;
+        const uint32_t d = (key >> shift) & mask;
         uint64_t m = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -288,7 +290,7 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* __res
 #pragma unroll
     for (int it = 0; it < kRsItems; ++it) {
         if (rk[it] != 0xFFFFFFFFu) {
-            const uint32_t d = (kk[it] >> shift) & 255u;
+            const uint32_t d = (kk[it] >> shift) & mask;
             const uint32_t lp = dstart[d] + wcnt[w][d] + rk[it];
             skey[lp] = kk[it];
             sval[lp] = vv[it];
@@ -298,7 +300,7 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* __res
     const uint32_t cnt = (uint32_t)min((uint64_t)kRsTile, (uint64_t)n - tile0);
     for (uint32_t i = threadIdx.x; i < cnt; i += kRsThreads) {
         const uint32_t key = skey[i];
-        const uint32_t d = (key >> shift) & 255u;
+        const uint32_t d = (key >> shift) & mask;
         const uint32_t gp = gbase[d] + (i - dstart[d]);
         keys_out[gp] = key;
         vals_out[gp] = sval[i];
@@ -328,14 +330,20 @@ void radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* va
     uint32_t nb = (n + kRsTile - 1) / kRsTile;
     uint32_t* hist = scratch;
     uint32_t* sscr = scratch + ((256ull * nb + 63) / 64) * 64;
-    int passes = (bits + 7) / 8;
+    // as many passes as 8-bit digits need, with the bits spread evenly over
+    // them (19 bits: 7 + 6 + 6): narrower digits leave longer runs of equal
+    // digits in each tile, so the scattered writes come in fuller lines
+    const int passes = (bits + 7) / 8;
     uint32_t *sk = keys, *sv = vals, *dk = keys_alt, *dv = vals_alt;
+    int shift = 0;
     for (int p = 0; p < passes; ++p) {
-        int shift = 8 * p;
-        hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kRsThreads), 0, s, sk, n, n_dev, shift, hist, nb);
-        launch_scan(hist, hist, 256u * nb, nullptr, sscr, s);
+        const int width = bits / passes + (p < bits % passes ? 1 : 0);
+        const uint32_t mask = (1u << width) - 1u;
+        hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kRsThreads), 0, s, sk, n, n_dev, shift, mask, hist, nb);
+        launch_scan(hist, hist, (mask + 1u) * nb, nullptr, sscr, s);
         hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kRsThreads), 0, s, sk, sv, dk, dv, n, n_dev, shift,
-                           hist, nb);
+                           mask, hist, nb);
+        shift += width;
         uint32_t* t;
         t = sk; sk = dk; dk = t;
         t = sv; sv = dv; dv = t;
