@@ -172,9 +172,10 @@ __device__ inline void footprint_rows(float4 r0, float4 r1, float qmax, int W, i
 // Footprint per bin row.  BIN = 16: the bin is the 16x16 tile and its 4-bit
 // mask marks the bands (rows 4k..4k+3) the footprint reaches.  BIN = 32: the
 // bin is a 32x32 block of four 16x16 tiles and bit 2h + c marks the tile in
-// row half h and column half c.  visit(bin_row, t0, t1, mask_of) is called
-// per bin row with the bin columns [t0, t1] and a function giving a bin
-// column's mask (0: not reached).
+// row half h and column half c.  visit(bin_row, t0, t1, mask_of, n) is called
+// per bin row with the bin columns [t0, t1], a function giving a bin
+// column's mask (0: not reached) and n, the number of columns in [t0, t1]
+// whose mask is not 0.
 template <int BIN, typename Visit>
 __device__ inline void footprint_bins(float4 r0, float4 r1, float qmax, int W, int H,
                                       Visit&& visit, int* rows = nullptr) {
@@ -185,11 +186,14 @@ __device__ inline void footprint_bins(float4 r0, float4 r1, float qmax, int W, i
                 t0 = min(t0, lo[k]);
                 t1 = max(t1, hi[k]);
             }
-            visit(ty, t0, t1, [&](int t) {
+            auto mask_of = [&](int t) {
                 uint32_t m = 0;
                 for (int k = 0; k < 4; ++k) m |= (lo[k] <= t && t <= hi[k]) ? (1u << k) : 0u;
                 return m;
-            });
+            };
+            int n = 0;
+            for (int t = t0; t <= t1; ++t) n += mask_of(t) != 0u;
+            visit(ty, t0, t1, mask_of, n);
         }, rows);
     } else {
         static_assert(BIN == 32, "bins are 16 or 32 pixels");
@@ -198,14 +202,22 @@ __device__ inline void footprint_bins(float4 r0, float4 r1, float qmax, int W, i
         auto flush = [&]() {
             if (cur < 0) return;
             const int b0 = min(lo[0], lo[1]), b1 = max(hi[0], hi[1]);
-            if (b0 <= b1)
+            if (b0 <= b1) {
+                // a bin column t has a tile of row half h reached exactly when
+                // lo[h] >> 1 <= t <= hi[h] >> 1 (tile columns are >= 0; an
+                // unreached half has lo > hi and gives an empty range), so the
+                // reached columns are the union of two ranges
+                const int a0 = lo[0] >> 1, a1 = hi[0] >> 1, c0 = lo[1] >> 1, c1 = hi[1] >> 1;
+                const int na = max(a1 - a0 + 1, 0), nc = max(c1 - c0 + 1, 0);
+                const int nboth = max(min(a1, c1) - max(a0, c0) + 1, 0);
                 visit(cur, b0 >> 1, b1 >> 1, [&](int t) {
                     uint32_t m = 0;
                     for (int h = 0; h < 2; ++h)
                         for (int c = 0; c < 2; ++c)
                             m |= (lo[h] <= 2 * t + c && 2 * t + c <= hi[h]) ? (1u << (2 * h + c)) : 0u;
                     return m;
-                });
+                }, na + nc - nboth);
+            }
         };
         footprint_rows<16>(r0, r1, qmax, W, H, [&](int ty, const int* l4, const int* h4) {
             const int br = ty >> 1, h = ty & 1;
@@ -322,8 +334,8 @@ __global__ __launch_bounds__(256) void k_project(const ViewInfo* __restrict__ vi
             r0 = make_float4(uh, vh, (float)(u - (double)uh), (float)(vv - (double)vh));
             r1 = make_float4((float)(kExp2Scale * syy * inv), (float)(-2.0 * kExp2Scale * sxy * inv),
                              (float)(kExp2Scale * sxx * inv), og);
-            footprint_bins<BIN>(r0, r1, qmax, V.width, V.height, [&](int, int t0, int t1, auto&& mask_of) {
-                for (int t = t0; t <= t1; ++t) cnt += mask_of(t) != 0u;
+            footprint_bins<BIN>(r0, r1, qmax, V.width, V.height, [&](int, int, int, auto&&, int n) {
+                cnt += (uint32_t)n;
             }, rows);
         }
     }
@@ -393,7 +405,7 @@ __global__ __launch_bounds__(256) void k_emit(const ViewInfo* __restrict__ views
                 }
             };
             footprint_bins<BIN>(r0, r1, reach_q(r1.w, bp), V.width, V.height,
-                                [&](int ty, int t0, int t1, auto&& mask_of) {
+                                [&](int ty, int t0, int t1, auto&& mask_of, int) {
                 for (int t = t0; t <= t1; ++t) {
                     const uint32_t m = mask_of(t);
                     if (m == 0u || off >= end) continue;
