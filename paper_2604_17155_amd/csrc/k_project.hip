@@ -172,10 +172,11 @@ __device__ inline void footprint_rows(float4 r0, float4 r1, float qmax, int W, i
 // Footprint per bin row.  BIN = 16: the bin is the 16x16 tile and its 4-bit
 // mask marks the bands (rows 4k..4k+3) the footprint reaches.  BIN = 32: the
 // bin is a 32x32 block of four 16x16 tiles and bit 2h + c marks the tile in
-// row half h and column half c.  visit(bin_row, t0, t1, mask_of, n) is called
-// per bin row with the bin columns [t0, t1], a function giving a bin
-// column's mask (0: not reached) and n, the number of columns in [t0, t1]
-// whose mask is not 0.
+// row half h and column half c.  visit(bin_row, t0, t1, mask_of, n, h) is
+// called per bin row with the bin columns [t0, t1], a function giving a bin
+// column's mask (0: not reached), n, the number of columns in [t0, t1] whose
+// mask is not 0, and (BIN = 32) h = the first and last 16-pixel tile column
+// reached in each row half (lo0, hi0, lo1, hi1; lo > hi: none).
 template <int BIN, typename Visit>
 __device__ inline void footprint_bins(float4 r0, float4 r1, float qmax, int W, int H,
                                       Visit&& visit, int* rows = nullptr) {
@@ -193,7 +194,7 @@ __device__ inline void footprint_bins(float4 r0, float4 r1, float qmax, int W, i
             };
             int n = 0;
             for (int t = t0; t <= t1; ++t) n += mask_of(t) != 0u;
-            visit(ty, t0, t1, mask_of, n);
+            visit(ty, t0, t1, mask_of, n, make_int4(0, -1, 0, -1));
         }, rows);
     } else {
         static_assert(BIN == 32, "bins are 16 or 32 pixels");
@@ -216,7 +217,7 @@ __device__ inline void footprint_bins(float4 r0, float4 r1, float qmax, int W, i
                         for (int c = 0; c < 2; ++c)
                             m |= (lo[h] <= 2 * t + c && 2 * t + c <= hi[h]) ? (1u << (2 * h + c)) : 0u;
                     return m;
-                }, na + nc - nboth);
+                }, na + nc - nboth, make_int4(lo[0], hi[0], lo[1], hi[1]));
             }
         };
         footprint_rows<16>(r0, r1, qmax, W, H, [&](int ty, const int* l4, const int* h4) {
@@ -334,7 +335,7 @@ __global__ __launch_bounds__(256) void k_project(const ViewInfo* __restrict__ vi
             r0 = make_float4(uh, vh, (float)(u - (double)uh), (float)(vv - (double)vh));
             r1 = make_float4((float)(kExp2Scale * syy * inv), (float)(-2.0 * kExp2Scale * sxy * inv),
                              (float)(kExp2Scale * sxx * inv), og);
-            footprint_bins<BIN>(r0, r1, qmax, V.width, V.height, [&](int, int, int, auto&&, int n) {
+            footprint_bins<BIN>(r0, r1, qmax, V.width, V.height, [&](int, int, int, auto&&, int n, int4) {
                 cnt += (uint32_t)n;
             }, rows);
         }
@@ -405,7 +406,7 @@ __global__ __launch_bounds__(256) void k_emit(const ViewInfo* __restrict__ views
                 }
             };
             footprint_bins<BIN>(r0, r1, reach_q(r1.w, bp), V.width, V.height,
-                                [&](int ty, int t0, int t1, auto&& mask_of, int) {
+                                [&](int ty, int t0, int t1, auto&& mask_of, int, int4) {
                 for (int t = t0; t <= t1; ++t) {
                     const uint32_t m = mask_of(t);
                     if (m == 0u || off >= end) continue;
@@ -430,6 +431,179 @@ __global__ __launch_bounds__(256) void k_emit(const ViewInfo* __restrict__ views
     }
 }
 
+// 32-pixel bins, emitted by the block together.  Each lane walks its item's
+// footprint as above, but records every bin row it reaches as one segment
+// in LDS (the row's first output slot, the lane, and the two tile-row
+// halves' column ranges, whose union is the row's reached bin columns);
+// the first slot of each segment is marked.  A max-scan over the block's
+// output slots then names each slot's segment, and every thread writes one
+// pair per step: the pair's bin column is found by rank within its segment,
+// so an item's pair count no longer holds the other 63 lanes of its wave,
+// and the stores are coalesced.  Pairs come out in the order the per-lane
+// walk writes them.  Blocks whose range exceeds kEmitStage slots, or whose
+// rows exceed kEmitSegs segments, fall back to that walk.
+constexpr uint32_t kEmitSegs = 1024;  // bin-row segments a block collects (16 KB)
+
+// A tile-column range packed as lo | hi << 16; no columns: (0x7FFF, 0).
+__device__ inline uint32_t pack_cols(int lo, int hi) {
+    return lo <= hi ? ((uint32_t)lo | ((uint32_t)hi << 16)) : 0x7FFFu;
+}
+
+__global__ __launch_bounds__(256) void k_emit32(const ViewInfo* __restrict__ views, int n_views,
+                                                const uint32_t* __restrict__ sorted_vals,
+                                                const uint32_t* __restrict__ offsets,
+                                                const uint32_t* __restrict__ counts,
+                                                const float4* __restrict__ rec0,
+                                                const float4* __restrict__ rec1, BlendParams bp,
+                                                uint32_t n_items, uint32_t sentinel, uint32_t cap,
+                                                uint32_t* __restrict__ overflow,
+                                                uint32_t* __restrict__ pair_keys,
+                                                uint32_t* __restrict__ pair_vals) {
+    __shared__ uint4 sseg[kEmitSegs];        // (first slot | lane << 16 | sentinel << 31, bin row, half 0, half 1)
+    __shared__ uint16_t sslot[kEmitStage];   // segment marks, then each slot's segment
+    __shared__ uint32_t sitem[256], stbase[256], stx[256];
+    __shared__ uint32_t wtop[4];
+    __shared__ uint32_t nseg;
+    static_assert(kEmitStage == 8 * 256, "eight slots per thread");
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint32_t k0 = blockIdx.x * blockDim.x;
+    const uint32_t klast = min(k0 + blockDim.x, n_items) - 1;
+    const uint32_t base = offsets[k0];
+    const uint32_t end_all = offsets[klast] + counts[klast];
+    const bool staged = end_all - base <= kEmitStage;  // uniform over the block
+    const uint32_t k = k0 + tid;
+    uint32_t cnt = 0, off = 0, end = 0;
+    const ViewInfo* V = nullptr;
+    float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
+    if (k < n_items) {
+        cnt = counts[k];
+        if (cnt != 0) {
+            V = &views[find_view_item(views, n_views, sorted_vals[k])];
+            r0 = rec0[k];
+            r1 = rec1[k];
+            off = offsets[k];
+            end = off + cnt;
+            if (end > cap || end < off) {  // capacity exceeded: keep what fits, report the rest
+                if (overflow) atomicAdd(overflow, 1u);
+                end = off < cap ? cap : off;
+            }
+        }
+    }
+    if (staged) {
+        reinterpret_cast<uint4*>(sslot)[tid] = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+        if (tid == 0) nseg = 0u;
+        __syncthreads();
+        if (cnt != 0) {
+            sitem[tid] = k;
+            stbase[tid] = V->tile_base;
+            stx[tid] = V->tiles_x;
+            uint32_t o = off;
+            auto add_seg = [&](uint32_t x, uint32_t y, uint32_t z, uint32_t ww) {
+                const uint32_t si = atomicAdd(&nseg, 1u);
+                if (si < kEmitSegs) {
+                    sseg[si] = make_uint4(x, y, z, ww);
+                    sslot[o - base] = (uint16_t)si;
+                }
+            };
+            footprint_bins<32>(r0, r1, reach_q(r1.w, bp), V->width, V->height,
+                               [&](int ty, int, int, auto&&, int n, int4 h) {
+                if (n <= 0) return;
+                if (o < end)
+                    add_seg((o - base) | (tid << 16), (uint32_t)ty, pack_cols(h.x, h.y), pack_cols(h.z, h.w));
+                o += (uint32_t)n;
+            });
+            // The walk above and the one that counted are the same code on the
+            // same record; should they ever disagree, unused slots get a tile
+            // id past the last tile, which sorts last and is ignored by the
+            // range kernel.
+            if (o < end) add_seg((o - base) | (tid << 16) | 0x80000000u, 0u, 0x7FFFu, 0x7FFFu);
+        }
+        __syncthreads();
+        if (nseg <= kEmitSegs) {  // uniform over the block
+            // each slot's segment: the last mark at or before it, by a max-scan
+            // of (slot + 1) << 16 | segment over the marked slots
+            const uint4 raw = reinterpret_cast<const uint4*>(sslot)[tid];
+            const uint32_t words[4] = {raw.x, raw.y, raw.z, raw.w};
+            uint32_t inc[8], run = 0u;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const uint32_t mk = (words[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+                if (mk != 0xFFFFu) run = ((8u * tid + (uint32_t)j + 1u) << 16) | mk;
+                inc[j] = run;
+            }
+            uint32_t sc = run;  // wave inclusive max-scan of the threads' last marks
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t o2 = __shfl_up(sc, d, 64);
+                if ((int)lane >= d) sc = max(sc, o2);
+            }
+            if (lane == 63) wtop[w] = sc;
+            uint32_t carry = __shfl_up(sc, 1, 64);
+            if (lane == 0) carry = 0u;
+            __syncthreads();
+            for (uint32_t q = 0; q < w; ++q) carry = max(carry, wtop[q]);
+            uint32_t outw[4];
+#pragma unroll
+            for (int j = 0; j < 8; j += 2)
+                outw[j >> 1] = (max(carry, inc[j]) & 0xFFFFu) | ((max(carry, inc[j + 1]) & 0xFFFFu) << 16);
+            reinterpret_cast<uint4*>(sslot)[tid] = make_uint4(outw[0], outw[1], outw[2], outw[3]);
+            __syncthreads();
+            const uint32_t lim = min(end_all, max(cap, base));
+            for (uint32_t i = tid; base + i < lim; i += blockDim.x) {
+                const uint4 sg = sseg[sslot[i]];
+                uint32_t key = sentinel, val = 0u;
+                if (!(sg.x & 0x80000000u)) {
+                    const uint32_t l = (sg.x >> 16) & 0xFFu;
+                    const int r = (int)(i - (sg.x & 0xFFFFu));
+                    const int lo0 = (int)(sg.z & 0xFFFFu), hi0 = (int)(sg.z >> 16);
+                    const int lo1 = (int)(sg.w & 0xFFFFu), hi1 = (int)(sg.w >> 16);
+                    // the row's reached bin columns, [a0, a1] u [c0, c1], in
+                    // increasing order
+                    const int a0 = lo0 >> 1, a1 = hi0 >> 1, c0 = lo1 >> 1, c1 = hi1 >> 1;
+                    int t;
+                    if (a1 < a0) {
+                        t = c0 + r;
+                    } else if (c1 < c0) {
+                        t = a0 + r;
+                    } else {
+                        const bool af = a0 <= c0;
+                        const int f0 = af ? a0 : c0, f1 = af ? a1 : c1, s0 = af ? c0 : a0;
+                        const int nf = f1 - f0 + 1;
+                        t = (s0 <= f1 + 1 || r < nf) ? f0 + r : s0 + (r - nf);
+                    }
+                    uint32_t m = 0u;
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        m |= (lo0 <= 2 * t + c && 2 * t + c <= hi0) ? (1u << c) : 0u;
+                        m |= (lo1 <= 2 * t + c && 2 * t + c <= hi1) ? (1u << (2 + c)) : 0u;
+                    }
+                    key = stbase[l] + sg.y * stx[l] + (uint32_t)t;
+                    val = sitem[l] | (m << kItemBits);
+                }
+                pair_keys[base + i] = key;
+                pair_vals[base + i] = val;
+            }
+            return;
+        }
+    }
+    // each lane writes its own pairs
+    if (cnt == 0) return;
+    footprint_bins<32>(r0, r1, reach_q(r1.w, bp), V->width, V->height,
+                       [&](int ty, int t0, int t1, auto&& mask_of, int, int4) {
+        for (int t = t0; t <= t1; ++t) {
+            const uint32_t m = mask_of(t);
+            if (m == 0u || off >= end) continue;
+            pair_keys[off] = V->tile_base + (uint32_t)ty * (uint32_t)V->tiles_x + (uint32_t)t;
+            pair_vals[off] = k | (m << kItemBits);
+            ++off;
+        }
+    });
+    for (; off < end; ++off) {
+        pair_keys[off] = sentinel;
+        pair_vals[off] = 0u;
+    }
+}
+
 void launch_emit(const ViewInfo* views, int n_views, const uint32_t* sorted_vals,
                  const uint32_t* offsets, const uint32_t* counts, const float4* rec0,
                  const float4* rec1, BlendParams bp, uint32_t n_items, uint32_t n_tiles,
@@ -437,7 +611,7 @@ void launch_emit(const ViewInfo* views, int n_views, const uint32_t* sorted_vals
                  uint32_t* overflow) {
     if (n_items == 0) return;
     if (bin == 32)
-        hipLaunchKernelGGL(k_emit<32>, dim3((n_items + 255) / 256), dim3(256), 0, s, views, n_views,
+        hipLaunchKernelGGL(k_emit32, dim3((n_items + 255) / 256), dim3(256), 0, s, views, n_views,
                            sorted_vals, offsets, counts, rec0, rec1, bp, n_items, n_tiles, cap,
                            overflow, pair_keys, pair_vals);
     else

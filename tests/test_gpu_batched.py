@@ -291,3 +291,50 @@ def test_batched_bins_of_32_pixels(gsc_mod):
     coeffs, status = plan.run(y, list(scenes[0].lam))
     torch.cuda.synchronize()
     check_scenes(scenes, targets, table, coeffs.cpu().numpy(), status.cpu().numpy(), "batched bin32")
+
+
+def test_batched_bins_of_32_pixels_wide_splats(gsc_mod):
+    """32-pixel bins with the splats of two scenes grown eight- and
+    three-fold: blocks of items whose pairs exceed what the block-wide
+    emission collects (2048 per 256 items) fall back to each item writing its
+    own pairs, beside blocks that take the block-wide path; every scene still
+    matches the oracle."""
+    import torch
+    ctx = gsc_mod.Context(bin_size=32)
+    scenes = segment_scenes()[:3]
+    for sc, f in zip(scenes[:2], (8.0, 3.0)):
+        sc.scales = np.ascontiguousarray(sc.scales * np.float32(f))
+    targets = [oracle.make_targets(sc) for sc in scenes]
+    plan, table, tens, cams, y = make_plan(gsc_mod, ctx, scenes, targets)
+    coeffs, status = plan.run(y, list(scenes[0].lam))
+    torch.cuda.synchronize()
+    info = plan.info()
+    print(f"wide splats, bins of 32: pair capacity {info.pair_capacity} for {info.items} items", flush=True)
+    check_scenes(scenes, targets, table, coeffs.cpu().numpy(), status.cpu().numpy(), "bin32 wide")
+
+
+def test_batched_bins_of_32_pixels_capacity_guard(gsc_mod):
+    """The capacity guard with 32-pixel bins: pairs past the plan's capacity
+    are dropped and reported by the block-wide emission as well."""
+    import torch
+    ctx = gsc_mod.Context(bin_size=32)
+    scenes = segment_scenes()[:2]
+    targets = [oracle.make_targets(sc) for sc in scenes]
+    plan, table, tens, cams, y = make_plan(gsc_mod, ctx, scenes, targets)
+    lam = list(scenes[0].lam)
+    ref_c, _ = plan.run(y, lam)
+    torch.cuda.synchronize()
+    ref_c = ref_c.clone()
+    scales = tens[1]
+    saved = scales.clone()
+    scales.mul_(2.0)
+    plan.run(y, lam)
+    info = plan.info()
+    print(f"bins of 32, grown geometry: dropped {info.dropped_pairs} items' pairs", flush=True)
+    assert info.dropped_pairs > 0
+    scales.copy_(saved)
+    c, _ = plan.run(y, lam)
+    assert plan.info().dropped_pairs == 0
+    e, _ = parity.rel_errors(c.cpu().numpy(), dict(coeffs=ref_c.cpu().numpy().astype(np.float64),
+                                                   status=np.zeros(len(c), np.uint8)))
+    assert e.max() < 1e-5
