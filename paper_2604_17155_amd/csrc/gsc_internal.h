@@ -52,6 +52,30 @@ __device__ inline int find_view_item(const ViewInfo* __restrict__ views, int n_v
     return lo;
 }
 
+// The same lookup on the views' first items staged in LDS by the block:
+// stage_view_bases fills sbase (kViewLds words) when the batch's views differ
+// in size and fit, and ends with a block barrier (every thread must call it);
+// view_of then searches LDS instead of the view records in global memory.
+constexpr int kViewLds = 512;
+__device__ inline bool stage_view_bases(const ViewInfo* __restrict__ views, int n_views, uint32_t* sbase) {
+    const bool use = views[0].uniform_n == 0u && n_views <= kViewLds;
+    if (use)
+        for (int v = (int)threadIdx.x; v < n_views; v += (int)blockDim.x) sbase[v] = views[v].item_base;
+    __syncthreads();
+    return use;
+}
+__device__ inline int view_of(const ViewInfo* __restrict__ views, int n_views, const uint32_t* sbase,
+                              bool staged, uint32_t item) {
+    if (!staged) return find_view_item(views, n_views, item);
+    int lo = 0, hi = n_views - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sbase[mid] <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // Blend constants in the form the kernels use.
 struct BlendParams {
     float alpha_min, alpha_max, t_min, cut2, dilation, znear;

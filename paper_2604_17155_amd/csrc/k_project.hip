@@ -284,10 +284,12 @@ __global__ __launch_bounds__(256) void k_project(const ViewInfo* __restrict__ vi
                                                  BlendParams bp, uint32_t* __restrict__ counts,
                                                  float4* __restrict__ rec0, float4* __restrict__ rec1,
                                                  uint2* __restrict__ rec2) {
+    __shared__ uint32_t sbase[kViewLds];
+    const bool vlds = stage_view_bases(views, n_views, sbase);
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_items) return;
     const uint32_t i = order ? order[k] : k;
-    const ViewInfo& V = views[find_view_item(views, n_views, i)];
+    const ViewInfo& V = views[view_of(views, n_views, sbase, vlds, i)];
     const int64_t g = V.g_offset + (int64_t)(i - V.item_base);
     // one 64-byte record per Gaussian: a single cache line per random gather
     const float4* gr = reinterpret_cast<const float4*>(geo + kGeoStride * g);
@@ -464,7 +466,9 @@ __global__ __launch_bounds__(256) void k_emit32(const ViewInfo* __restrict__ vie
     __shared__ uint32_t sitem[256], stbase[256], stx[256];
     __shared__ uint32_t wtop[4];
     __shared__ uint32_t nseg;
+    __shared__ uint32_t sbase[kViewLds];
     static_assert(kEmitStage == 8 * 256, "eight slots per thread");
+    const bool vlds = stage_view_bases(views, n_views, sbase);
     const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint32_t k0 = blockIdx.x * blockDim.x;
     const uint32_t klast = min(k0 + blockDim.x, n_items) - 1;
@@ -478,7 +482,7 @@ __global__ __launch_bounds__(256) void k_emit32(const ViewInfo* __restrict__ vie
     if (k < n_items) {
         cnt = counts[k];
         if (cnt != 0) {
-            V = &views[find_view_item(views, n_views, sorted_vals[k])];
+            V = &views[view_of(views, n_views, sbase, vlds, sorted_vals[k])];
             r0 = rec0[k];
             r1 = rec1[k];
             off = offsets[k];
