@@ -294,7 +294,7 @@ def test_batched_bins_of_32_pixels(gsc_mod):
 
 
 def test_batched_bins_of_32_pixels_wide_splats(gsc_mod):
-    """32-pixel bins with the splats of two scenes grown eight- and
+    """32-pixel bins with the splats of two scenes grown sixteen- and
     three-fold: blocks of items whose pairs exceed what the block-wide
     emission collects (2048 per 256 items) fall back to each item writing its
     own pairs, beside blocks that take the block-wide path; every scene still
@@ -302,7 +302,7 @@ def test_batched_bins_of_32_pixels_wide_splats(gsc_mod):
     import torch
     ctx = gsc_mod.Context(bin_size=32)
     scenes = segment_scenes()[:3]
-    for sc, f in zip(scenes[:2], (8.0, 3.0)):
+    for sc, f in zip(scenes[:2], (16.0, 3.0)):
         sc.scales = np.ascontiguousarray(sc.scales * np.float32(f))
     targets = [oracle.make_targets(sc) for sc in scenes]
     plan, table, tens, cams, y = make_plan(gsc_mod, ctx, scenes, targets)
