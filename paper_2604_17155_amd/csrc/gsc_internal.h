@@ -115,8 +115,9 @@ void launch_depth_keys(const ViewInfo* views, int n_views, uint32_t n_items, con
                        hipStream_t s);
 
 // Projection in depth order: position k handles item i = order[k] (k if order
-// is null) and writes counts[k], rec0/rec1[k] and rec2[k] = (first | last << 16,
-// i): the pixel rows of the footprint and the item.
+// is null) and writes counts[k] and, when counts[k] > 0, rec0/rec1[k] and
+// rec2[k] = (first | last << 16, i): the pixel rows of the footprint and the
+// item (records are only ever read through tile pairs).
 void launch_project(const ViewInfo* views, int n_views, uint32_t n_items, const uint32_t* order,
                     const float* geo, BlendParams bp, uint32_t* counts, float4* rec0, float4* rec1,
                     uint2* rec2, int bin, hipStream_t s);

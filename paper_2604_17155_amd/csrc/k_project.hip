@@ -343,9 +343,13 @@ __global__ __launch_bounds__(256) void k_project(const ViewInfo* __restrict__ vi
         }
     }
     counts[k] = cnt;
-    rec0[k] = r0;
-    rec1[k] = r1;
-    rec2[k] = make_uint2((uint32_t)(rows[0] & 0xFFFF) | ((uint32_t)(rows[1] & 0xFFFF) << 16), i);
+    // records are read only through tile pairs: an item with none keeps its
+    // slot unwritten
+    if (cnt != 0) {
+        rec0[k] = r0;
+        rec1[k] = r1;
+        rec2[k] = make_uint2((uint32_t)(rows[0] & 0xFFFF) | ((uint32_t)(rows[1] & 0xFFFF) << 16), i);
+    }
 }
 
 void launch_project(const ViewInfo* views, int n_views, uint32_t n_items, const uint32_t* order,
