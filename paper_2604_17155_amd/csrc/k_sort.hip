@@ -230,8 +230,10 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint32_t* __restri
 // comes from the global digit counts `gcount`.  A status word holds the
 // value in bits 0..29, kStAgg once the tile's own count is there and kStInc
 // once its inclusive prefix is.  Every wait is bounded: after kLookbackSpins
-// polls a block gives up, sets *fault and goes on (its output is then wrong,
-// but no kernel can hang).
+// polls a block gives up, sets *fault (a word of the sort's scratch, not
+// reported further) and goes on, so no kernel can hang; its output is then
+// wrong, but only a predecessor that never publishes could cause that, and
+// the ticket order guarantees every predecessor is running.
 constexpr uint32_t kStAgg = 1u << 30, kStInc = 1u << 31, kStVal = kStAgg - 1u;
 constexpr uint32_t kLookbackSpins = 1u << 22;
 
