@@ -293,14 +293,16 @@ def test_batched_bins_of_32_pixels(gsc_mod):
     check_scenes(scenes, targets, table, coeffs.cpu().numpy(), status.cpu().numpy(), "batched bin32")
 
 
-def test_batched_bins_of_32_pixels_wide_splats(gsc_mod):
-    """32-pixel bins with the splats of two scenes grown sixteen- and
-    three-fold: blocks of items whose pairs exceed what the block-wide
-    emission collects (2048 per 256 items) fall back to each item writing its
-    own pairs, beside blocks that take the block-wide path; every scene still
-    matches the oracle."""
+@pytest.mark.parametrize("bin_size", [32, 16])
+def test_batched_bins_of_32_pixels_wide_splats(gsc_mod, bin_size):
+    """Splats of two scenes grown sixteen- and three-fold.  With 32-pixel
+    bins, blocks of items whose pairs exceed what the block-wide emission
+    collects (2048 per 256 items) fall back to each item writing its own
+    pairs, beside blocks that take the block-wide path; with 16-pixel bins
+    the per-item emission's unstaged path runs beside its staged one.  Every
+    scene still matches the oracle."""
     import torch
-    ctx = gsc_mod.Context(bin_size=32)
+    ctx = gsc_mod.Context(bin_size=bin_size)
     scenes = segment_scenes()[:3]
     for sc, f in zip(scenes[:2], (16.0, 3.0)):
         sc.scales = np.ascontiguousarray(sc.scales * np.float32(f))
@@ -309,8 +311,9 @@ def test_batched_bins_of_32_pixels_wide_splats(gsc_mod):
     coeffs, status = plan.run(y, list(scenes[0].lam))
     torch.cuda.synchronize()
     info = plan.info()
-    print(f"wide splats, bins of 32: pair capacity {info.pair_capacity} for {info.items} items", flush=True)
-    check_scenes(scenes, targets, table, coeffs.cpu().numpy(), status.cpu().numpy(), "bin32 wide")
+    print(f"wide splats, bins of {bin_size}: pair capacity {info.pair_capacity} for {info.items} items",
+          flush=True)
+    check_scenes(scenes, targets, table, coeffs.cpu().numpy(), status.cpu().numpy(), f"bin{bin_size} wide")
 
 
 def test_batched_bins_of_32_pixels_capacity_guard(gsc_mod):
