@@ -96,9 +96,9 @@ MEASURED_TRAFFIC = {
     # HBM bytes per accumulate launch: FETCH_SIZE x 2 + WRITE_SIZE x 1 (the
     # factors a plain 256 MiB device copy gives), averaged over the launches
     # of one step; valid while the accumulate's sources hash to "sources"
-    "relight": {"bytes": 2.205e9, "sources": "63f70ed1699cbfed"},
-    "features": {"bytes": 2.361e10, "sources": "63f70ed1699cbfed"},
-    "batched": {"bytes": 7.677e9, "sources": "63f70ed1699cbfed"},
+    "relight": {"bytes": 2.207e9, "sources": "4a382471bd57137b"},
+    "features": {"bytes": 2.362e10, "sources": "4a382471bd57137b"},
+    "batched": {"bytes": 7.689e9, "sources": "4a382471bd57137b"},
 }
 ACCUMULATE_SOURCES = ("paper_2604_17155_amd/csrc/k_accum.hip", "paper_2604_17155_amd/csrc/wave_ops.h",
                       "paper_2604_17155_amd/csrc/k_sort.hip",    # the tile order

@@ -8,6 +8,8 @@
 // atomic per value adds the tile's share to the (view, Gaussian) slot.
 // Splat records for the next 64 list entries are loaded one per lane and
 // broadcast with v_readlane, so the loop needs no LDS and no barriers.
+#include <type_traits>
+
 #include "gsc_internal.h"
 #include "wave_ops.h"
 
@@ -225,10 +227,10 @@ __device__ __forceinline__ uint32_t accumulate_tile(
                 const float b0 = c1.y * dx;
                 float sv = 0.0f;
                 float ss[CCA];
-    #pragma unroll
+#pragma unroll
                 for (int c = 0; c < CCA; ++c) ss[c] = 0.0f;
                 uint32_t nh = 0;    // contributions of this entry (wave total)
-    #pragma unroll
+#pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     if (!((bands >> k) & 1u)) continue;  // uniform
                     const float dy = c0.y + lyk[k];
@@ -236,7 +238,7 @@ __device__ __forceinline__ uint32_t accumulate_tile(
                     uint64_t taken, kept;
                     const float w = pixel_step(q2, c1.w, T[k], qlim, amin, amax, tmin, taken, kept);
                     sv += w;
-    #pragma unroll
+#pragma unroll
                     for (int c = 0; c < CC; ++c) ss[c] = fmaf(w, y[k][c], ss[c]);
                     nh += (uint32_t)__popcll(taken);
                     if (kept == 0) alive &= ~(1u << k);
@@ -462,29 +464,77 @@ __device__ __forceinline__ uint32_t accumulate_tile_mfma(
     const int pc = YM == 2 ? ((int)n16 < C ? (int)n16 : (int)n16 - C) : (int)n16;
     const bool pcol = YM == 2 ? (int)n16 < 2 * C : (int)n16 < C;   // a target column
     const bool pone = YM == 2 ? (int)n16 == 2 * C : (int)n16 == C;  // the ones column
+    if constexpr (NBLK == 1) {
+        // One 64-bit offset per row of eight pixels, then a uniform step of C
+        // elements per pixel; element 0 of the view stands in outside (no branch).
+        // All loads are issued before any is used (one channel block: 5.37 ->
+        // 5.31-5.34 ms per launch on the 32-scene plan; with two blocks the
+        // loaded values spill, 8.0 -> 8.2 ms, and the form below is kept).
+        using TY = std::conditional_t<YM == 2, float, uint16_t>;
+        const TY* vt = (const TY*)targets + poff * C;
+        TY xv[8][NBLK][8];
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-        const int gy = tg.y0 + 2 * s + (int)(q4 >> 1);
-        const int gx0 = tg.x0 + 8 * (int)(q4 & 1u);
+        for (int s = 0; s < 8; ++s) {
+            const int gy = tg.y0 + 2 * s + (int)(q4 >> 1);
+            const int gx0 = tg.x0 + 8 * (int)(q4 & 1u);
 #pragma unroll
-        for (int b = 0; b < NBLK; ++b) {
-            const int c = YM == 0 ? c_off + 16 * b + (int)n16 : pc;
+            for (int b = 0; b < NBLK; ++b) {
+                const int c = YM == 0 ? c_off + 16 * b + (int)n16 : pc;
+                const bool rowin = (gy < vh) & (YM == 0 ? c < C : pcol);
+                const TY* rp = vt + (rowin ? ((int64_t)gy * vw + gx0) * C + c : (int64_t)0);
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int gx = gx0 + i;
-                const bool in = (gx < vw) & (gy < vh) & (YM == 0 ? c < C : pcol);
-                const int64_t row = poff + (int64_t)gy * vw + gx;
-                // unconditional load (element 0 stands in outside): no branch
-                const int64_t e = in ? row * C + c : 0;
-                if constexpr (YM == 2) {
-                    const float f = ((const float*)targets)[e];
-                    const __bf16 hi = (__bf16)f;
-                    const __bf16 v = (int)n16 < C ? hi : (__bf16)(f - (float)hi);
-                    Y[s][b][i] = in ? v : (pone ? (__bf16)1.0f : (__bf16)0.0f);
-                } else {
-                    const uint16_t u = ((const uint16_t*)targets)[e];
-                    const __bf16 v = __builtin_bit_cast(__bf16, u);
-                    Y[s][b][i] = in ? v : ((YM == 1 && pone) ? (__bf16)1.0f : (__bf16)0.0f);
+                for (int i = 0; i < 8; ++i) xv[s][b][i] = *((rowin & (gx0 + i < vw)) ? rp + i * C : vt);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const int gy = tg.y0 + 2 * s + (int)(q4 >> 1);
+            const int gx0 = tg.x0 + 8 * (int)(q4 & 1u);
+#pragma unroll
+            for (int b = 0; b < NBLK; ++b) {
+                const int c = YM == 0 ? c_off + 16 * b + (int)n16 : pc;
+                const bool rowin = (gy < vh) & (YM == 0 ? c < C : pcol);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const bool in = rowin & (gx0 + i < vw);
+                    const TY x = xv[s][b][i];
+                    if constexpr (YM == 2) {
+                        const __bf16 hi = (__bf16)x;
+                        const __bf16 v = (int)n16 < C ? hi : (__bf16)(x - (float)hi);
+                        Y[s][b][i] = in ? v : (pone ? (__bf16)1.0f : (__bf16)0.0f);
+                    } else {
+                        const __bf16 v = __builtin_bit_cast(__bf16, x);
+                        Y[s][b][i] = in ? v : ((YM == 1 && pone) ? (__bf16)1.0f : (__bf16)0.0f);
+                    }
+                }
+            }
+        }
+    } else {
+        // a 64-bit element index per load
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const int gy = tg.y0 + 2 * s + (int)(q4 >> 1);
+            const int gx0 = tg.x0 + 8 * (int)(q4 & 1u);
+#pragma unroll
+            for (int b = 0; b < NBLK; ++b) {
+                const int c = YM == 0 ? c_off + 16 * b + (int)n16 : pc;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int gx = gx0 + i;
+                    const bool in = (gx < vw) & (gy < vh) & (YM == 0 ? c < C : pcol);
+                    const int64_t row = poff + (int64_t)gy * vw + gx;
+                    // unconditional load (element 0 stands in outside): no branch
+                    const int64_t e = in ? row * C + c : 0;
+                    if constexpr (YM == 2) {
+                        const float f = ((const float*)targets)[e];
+                        const __bf16 hi = (__bf16)f;
+                        const __bf16 v = (int)n16 < C ? hi : (__bf16)(f - (float)hi);
+                        Y[s][b][i] = in ? v : (pone ? (__bf16)1.0f : (__bf16)0.0f);
+                    } else {
+                        const uint16_t u = ((const uint16_t*)targets)[e];
+                        const __bf16 v = __builtin_bit_cast(__bf16, u);
+                        Y[s][b][i] = in ? v : ((YM == 1 && pone) ? (__bf16)1.0f : (__bf16)0.0f);
+                    }
                 }
             }
         }
