@@ -246,9 +246,11 @@ __global__ __launch_bounds__(256) void k_depth_keys(const ViewInfo* __restrict__
                                                     const float* __restrict__ opac, BlendParams bp,
                                                     uint32_t* __restrict__ keys,
                                                     uint32_t* __restrict__ vals) {
+    __shared__ uint32_t sbase[kViewLds];
+    const bool vlds = stage_view_bases(views, n_views, sbase);
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_items) return;
-    const ViewInfo& V = views[find_view_item(views, n_views, i)];
+    const ViewInfo& V = views[view_of(views, n_views, sbase, vlds, i)];
     const int64_t g = V.g_offset + (int64_t)(i - V.item_base);
     const float key = __fmaf_rn(V.R[6], means[3 * g],
                                 __fmaf_rn(V.R[7], means[3 * g + 1], __fmaf_rn(V.R[8], means[3 * g + 2], V.t[2])));
